@@ -1,0 +1,211 @@
+"""CPU FP64 oracle for the VCT-SPH(2) operators (test infrastructure only).
+
+Only the tests, the smoke check and the CPU-baseline leg of the benchmark may
+import this package.  The product path (the HIP library and its binding) never
+imports, links or calls it, and the oracle never calls the product path.
+
+The arithmetic lives in plain C (orc.c, FP64, OpenMP over particles); this
+module only builds that file with gcc and marshals numpy arrays into it.
+Record layout of sph2() outputs: see ORC_REC in orc.h (indices below).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liborc.so")
+
+# record indices (orc.h)
+REC = 32
+I_GRAD = slice(0, 3)
+I_LAP = 3
+I_CROSS = slice(4, 7)
+I_HESS = slice(7, 13)
+I_G1 = slice(13, 16)
+I_G2 = slice(16, 19)
+I_D = slice(19, 25)
+I_DHAT = slice(25, 31)
+I_LAP_TRACE = 31
+
+F_FEW, F_SINGULAR_A, F_SINGULAR_M, F_NONFINITE, F_DUPLICATE = 1, 2, 4, 8, 16
+
+
+def build(verbose=False):
+    """Compile orc.c into liborc.so (plain gcc, no fused multiply-add)."""
+    src = os.path.join(HERE, "orc.c")
+    cmd = ["gcc", "-O2", "-std=gnu11", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+           "-fPIC", "-shared", "-Wall", "-Wno-unused-function", src, "-o", LIB_PATH, "-lm"]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.run(cmd, check=True)
+    global _lib
+    _lib = None
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        L = C.CDLL(LIB_PATH)
+        dp, ip64, ip32, u8p = (C.POINTER(C.c_double), C.POINTER(C.c_int64),
+                               C.POINTER(C.c_int32), C.POINTER(C.c_uint8))
+        L.orc_neighbors.restype = C.c_int64
+        L.orc_neighbors.argtypes = [C.c_int, C.c_int64, dp, C.c_double, C.c_int64, ip64, C.c_int,
+                                    ip64, ip32, C.c_int64]
+        L.orc_sph2.restype = C.c_int
+        L.orc_sph2.argtypes = [C.c_int, C.c_int64, dp, dp, C.c_int, dp, C.c_int, C.c_double,
+                               C.c_int, C.c_double, C.c_double, C.c_double, C.c_double, C.c_int, dp,
+                               C.c_int, C.c_int64, ip64, ip64, ip32, dp, u8p]
+        L.orc_adjoint_dphi.restype = C.c_int
+        L.orc_adjoint_dphi.argtypes = [C.c_int, C.c_int64, dp, dp, C.c_int, C.c_double, C.c_int,
+                                       C.c_double, C.c_double, C.c_double, C.c_double, C.c_int, dp,
+                                       C.c_int, ip64, ip32, dp, C.c_int64, ip64, dp]
+        L.orc_dtheta.restype = C.c_int
+        L.orc_dtheta.argtypes = [C.c_int, C.c_int64, dp, C.c_int, C.c_double, C.c_double, C.c_double,
+                                 C.c_double, C.c_int, dp, dp, dp, C.c_int, ip32, dp]
+        L.orc_map_eval.restype = C.c_int
+        L.orc_map_eval.argtypes = [C.c_int, C.c_int64, dp, dp, dp, C.c_int, C.c_double, C.c_double,
+                                   C.c_double, C.c_double, C.c_int, dp, C.c_int, dp]
+        L.orc_alpha_beta.restype = C.c_int
+        L.orc_alpha_beta.argtypes = [C.c_int, C.c_int64, dp, dp, C.c_int, C.c_double, C.c_double,
+                                     C.c_double, C.c_double, C.c_int, dp, dp]
+        L.orc_kernel_eval.restype = None
+        L.orc_kernel_eval.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, dp, dp]
+        L.orc_threads.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _p(a, t=C.c_double):
+    return None if a is None else a.ctypes.data_as(C.POINTER(t))
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _map_args(ms):
+    terms = _f64(ms.as_array())
+    return (int(ms.kind), float(ms.Hhat), float(ms.H), float(ms.dmin), float(ms.eps),
+            int(terms.shape[0]), terms)
+
+
+def threads():
+    return lib().orc_threads()
+
+
+def kernel_eval(kernel, dim, R, r):
+    w, dw = C.c_double(), C.c_double()
+    lib().orc_kernel_eval(int(kernel), int(dim), float(R), float(r), C.byref(w), C.byref(dw))
+    return w.value, dw.value
+
+
+def neighbors(pos, R, rows=None, brute=False):
+    """CSR neighbour lists (original indices, ascending) of the given rows."""
+    pos = _f64(pos)
+    dim, n = pos.shape
+    rows_a = None if rows is None else np.ascontiguousarray(rows, dtype=np.int64)
+    nr = n if rows_a is None else rows_a.shape[0]
+    row_ptr = np.zeros(nr + 1, dtype=np.int64)
+    nnz = lib().orc_neighbors(dim, n, _p(pos), float(R), nr, _p(rows_a, C.c_int64), int(brute),
+                              _p(row_ptr, C.c_int64), None, 0)
+    if nnz < 0:
+        raise RuntimeError(f"orc_neighbors failed ({nnz})")
+    col = np.zeros(max(nnz, 1), dtype=np.int32)
+    nnz2 = lib().orc_neighbors(dim, n, _p(pos), float(R), nr, _p(rows_a, C.c_int64), int(brute),
+                               _p(row_ptr, C.c_int64), _p(col, C.c_int32), col.shape[0])
+    assert nnz2 == nnz
+    return row_ptr, col[:nnz]
+
+
+def sph2(pos, vol, phi, kernel, R, mapspec, rows=None, csr=None, grad_order=2):
+    """Per-particle SPH(2) records (nrows, nf, REC) and flags (nrows,)."""
+    pos = _f64(pos)
+    vol = _f64(vol)
+    phi = _f64(np.atleast_2d(phi))
+    dim, n = pos.shape
+    nf = phi.shape[0]
+    rows_a = None if rows is None else np.ascontiguousarray(rows, dtype=np.int64)
+    if csr is None:
+        csr = neighbors(pos, R, rows=rows_a)
+    row_ptr, col = csr
+    row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    nr = n if rows_a is None else rows_a.shape[0]
+    out = np.zeros((nr, nf, REC), dtype=np.float64)
+    flags = np.zeros(nr, dtype=np.uint8)
+    kind, Hh, H, dmin, eps, nt, terms = _map_args(mapspec)
+    st = lib().orc_sph2(dim, n, _p(pos), _p(vol), nf, _p(phi), int(kernel), float(R), kind, Hh, H,
+                        dmin, eps, nt, _p(terms), int(grad_order), nr, _p(rows_a, C.c_int64),
+                        _p(row_ptr, C.c_int64), _p(col if col.size else np.zeros(1, np.int32), C.c_int32),
+                        _p(out), _p(flags, C.c_uint8))
+    if st != 0:
+        raise RuntimeError(f"orc_sph2 failed ({st})")
+    return out, flags
+
+
+def adjoint_dphi(pos, vol, kernel, R, mapspec, u, ks=None, csr=None, grad_order=2):
+    """dphi_k = sum_i u_i d(lap_i)/d(phi_k) at sampled k (all if ks is None)."""
+    pos = _f64(pos)
+    vol = _f64(vol)
+    u = _f64(u)
+    dim, n = pos.shape
+    if csr is None:
+        csr = neighbors(pos, R)
+    row_ptr, col = csr
+    ks_a = None if ks is None else np.ascontiguousarray(ks, dtype=np.int64)
+    nk = n if ks_a is None else ks_a.shape[0]
+    out = np.zeros(nk, dtype=np.float64)
+    kind, Hh, H, dmin, eps, nt, terms = _map_args(mapspec)
+    st = lib().orc_adjoint_dphi(dim, n, _p(pos), _p(vol), int(kernel), float(R), kind, Hh, H, dmin,
+                                eps, nt, _p(terms), int(grad_order),
+                                _p(np.ascontiguousarray(row_ptr, dtype=np.int64), C.c_int64),
+                                _p(np.ascontiguousarray(col, dtype=np.int32), C.c_int32), _p(u), nk,
+                                _p(ks_a, C.c_int64), _p(out))
+    if st != 0:
+        raise RuntimeError("orc_adjoint_dphi failed")
+    return out
+
+
+def dtheta(pos, mapspec, u, dhat, tlist):
+    """sum_i u_i d(c_trans_i)/d(coef_t) . Dhat_i for each term index t."""
+    pos = _f64(pos)
+    dim, n = pos.shape
+    u = _f64(u)
+    dhat = _f64(dhat).reshape(n, 6)
+    tl = np.ascontiguousarray(tlist, dtype=np.int32)
+    out = np.zeros(tl.shape[0], dtype=np.float64)
+    kind, Hh, H, dmin, eps, nt, terms = _map_args(mapspec)
+    lib().orc_dtheta(dim, n, _p(pos), kind, Hh, H, dmin, eps, nt, _p(terms), _p(u), _p(dhat),
+                     tl.shape[0], _p(tl, C.c_int32), _p(out))
+    return out
+
+
+def map_eval(dim, x, y, zh, mapspec, t=-1):
+    """(np, 24): J (9), c_trans (6), second derivatives of z^ (9); or their
+    complex-step derivative with respect to term t."""
+    x = _f64(x)
+    zh = _f64(zh)
+    y = None if y is None else _f64(y)
+    out = np.zeros((x.shape[0], 24))
+    kind, Hh, H, dmin, eps, nt, terms = _map_args(mapspec)
+    lib().orc_map_eval(dim, x.shape[0], _p(x), _p(y), _p(zh), kind, Hh, H, dmin, eps, nt, _p(terms),
+                       int(t), _p(out))
+    return out
+
+
+def alpha_beta(dim, x, y, mapspec):
+    x = _f64(x)
+    y = None if y is None else _f64(y)
+    out = np.zeros((x.shape[0], 12))
+    kind, Hh, H, dmin, eps, nt, terms = _map_args(mapspec)
+    lib().orc_alpha_beta(dim, x.shape[0], _p(x), _p(y), kind, Hh, H, dmin, eps, nt, _p(terms), _p(out))
+    return out
