@@ -1,0 +1,272 @@
+/* vct.h -- C ABI of the VCT-SPH(2) operator library for AMD MI355X (gfx950).
+ *
+ * The library evaluates second-order-accurate SPH derivative operators
+ * (gradient, Laplacian, cross derivatives) of particle fields, computed in the
+ * projected space of a vertical coordinate transformation (VCT) and mapped back
+ * to physical space:
+ *   - VCT:  x^ = x, y^ = y, z^ = alpha(x,y) (z + beta(x,y))        paper Sec. 2.1, Eq. VCT
+ *   - gradient  grad phi = J grad^ phi                              Eq. grad_VCT
+ *   - Laplacian lap phi = c_trans . D^ phi                          Eq. lap_VCT
+ *   - alpha/beta for E-, BF-, BFE- and sigma-SPH                     Sec. 2.2
+ *   - neighbour set S_i = { j != i : |r^_ij| < R }                   Sec. 3.1, Eq. SPH_neighbor_set
+ *   - first-order corrected gradient (L_i)                          Sec. 3.1, Eq. gra_1st
+ *   - SPH(2) second derivatives (M_i, F_ij, p_ij, q_ij)             Sec. 3.1, Eq. sec_SPH2
+ *
+ * Conventions for every entry point
+ *   - Pointers are DEVICE pointers unless marked (host).  The library never
+ *     allocates device memory: the caller owns inputs, outputs and scratch
+ *     ("workspace", sized by the matching *_workspace_size query).
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *     Calls are stream-ordered and asynchronous unless marked SYNC, in which
+ *     case they wait for their own work on `stream` before returning.
+ *   - Per-particle arrays are in the cell-sorted order produced by
+ *     vct_build_cells unless stated otherwise; perm maps sorted -> original.
+ *   - Layouts: positions SoA [dim][n] (2-D sets use the vertical plane (x, z));
+ *     fields [nf][n]; outputs [nf][n][n_out]; CSR row_ptr int64 [n+1], col int32
+ *     (sorted indices, ascending within a row); state SoA [stride][n].
+ *   - Return value: VCT_OK (0); a positive warning (outputs written); or a
+ *     negative error, in which case nothing was launched unless stated.
+ *     Argument errors are detected on the host before any HIP call.  Nothing
+ *     aborts or throws across the ABI.  Calls that share a workspace or outputs
+ *     must not overlap.
+ */
+#ifndef VCT_H
+#define VCT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- status */
+enum {
+    VCT_OK = 0,
+    VCT_W_FLAGGED = 1,      /* some particles were flagged; their outputs are NaN */
+    VCT_E_ARG = -1,         /* invalid argument (null pointer, size, enum, range) */
+    VCT_E_HIP = -2,         /* a HIP runtime call or kernel launch failed */
+    VCT_E_CAPACITY = -3,    /* an output array is too small; the required size is reported */
+    VCT_E_NONFINITE = -4,   /* a non-finite input position */
+    VCT_E_WORKSPACE = -5    /* workspace missing or smaller than the size query returns */
+};
+
+/* ---------------------------------------------------------------- enums */
+enum { VCT_KERNEL_WENDLAND_C2 = 0, VCT_KERNEL_CUBIC_SPLINE = 1 };
+
+/* arithmetic of vct_apply_ops */
+enum {
+    VCT_FP64 = 0,           /* FP64 pair terms and sums, FP64 state */
+    VCT_MIXED = 1,          /* FP32 pair terms and FP32 sums, FP32 copy of the FP64-solved state */
+    VCT_MIXED_S64 = 2       /* FP32 pair terms and FP32 sums, FP64 state */
+};
+
+/* mapping kinds (paper Sec. 2.2) */
+enum { VCT_MAP_IDENTITY = 0, VCT_MAP_E = 1, VCT_MAP_BF = 2, VCT_MAP_BFE = 3, VCT_MAP_SIGMA = 4 };
+
+/* one separable factor B(s) of a bathymetry term */
+enum { VCT_BASIS_ONE = 0, VCT_BASIS_LIN = 1, VCT_BASIS_COS = 2, VCT_BASIS_SIN = 3 };
+
+#define VCT_MAX_TERMS 32
+
+/* Output selection.  Rows of one particle's output record are the selected
+ * groups concatenated in this bit order:
+ *   GRAD   physical gradient            2-D: x, z         3-D: x, y, z
+ *   LAP    physical Laplacian           1
+ *   CROSS  physical cross derivatives   2-D: xz           3-D: xy, xz, yz
+ *   HESS   physical Hessian             2-D: xx, zz, xz   3-D: xx, yy, zz, xy, xz, yz
+ *   PGRAD  projected gradient           2-D: x^, z^       3-D: x^, y^, z^
+ *   PHESS  projected second derivatives (same component order as HESS)
+ * VCT_OPT_GRAD1 makes every gradient (and the dz^ entering LAP, CROSS and HESS)
+ * the first-order corrected one (Eq. gra_1st) instead of the second-order
+ * gradient SPH(2) provides.                                                    */
+enum {
+    VCT_OUT_GRAD = 1u << 0,
+    VCT_OUT_LAP = 1u << 1,
+    VCT_OUT_CROSS = 1u << 2,
+    VCT_OUT_HESS = 1u << 3,
+    VCT_OUT_PGRAD = 1u << 4,
+    VCT_OUT_PHESS = 1u << 5,
+    VCT_OPT_GRAD1 = 1u << 8
+};
+#define VCT_OUT_DEFAULT (VCT_OUT_GRAD | VCT_OUT_LAP | VCT_OUT_CROSS)
+
+/* per-particle flag bits written by vct_moments */
+enum {
+    VCT_FLAG_FEW = 1,        /* fewer than d + m neighbours (d + m = 5 in 2-D, 9 in 3-D) */
+    VCT_FLAG_SINGULAR_A = 2, /* first-order correction matrix numerically singular */
+    VCT_FLAG_SINGULAR_M = 4, /* SPH(2) moment matrix numerically singular */
+    VCT_FLAG_NONFINITE = 8,  /* non-finite position or volume at the particle or a neighbour */
+    VCT_FLAG_DUPLICATE = 16  /* a neighbour at zero distance */
+};
+
+/* Bottom elevation term: h(x, y) += coef * Bx(x) * By(y) with
+ * B = 1, s, cos(2 pi f s) or sin(2 pi f s) (basis kind, frequency f).
+ * In 2-D only the x factor varies (By is evaluated at y = 0, derivatives 0). */
+typedef struct {
+    double coef;
+    int32_t bx, by;
+    double fx, fy;
+} vct_term;
+
+/* Vertical coordinate transformation (paper Sec. 2.2):
+ *   IDENTITY  alpha = 1,            beta = 0
+ *   E         alpha = Hhat / H,     beta = 0
+ *   BF        alpha = 1,            beta = -h
+ *   BFE       alpha = Hhat / H,     beta = -h
+ *   SIGMA     alpha = Hhat / D_eff, beta = D_eff - H,  D = H - h,
+ *             D_eff = (D + dmin + sqrt((D - dmin)^2 + eps^2)) / 2 when dmin > 0 or
+ *             eps > 0 (the paper asks for a constant alpha outside an unstated
+ *             applicable range; this smooth limiter is the reading used), else D.
+ * `terms` is a HOST pointer to nterms (<= VCT_MAX_TERMS) entries; it is read
+ * during the call only.                                                        */
+typedef struct {
+    int32_t kind;
+    int32_t nterms;
+    double Hhat, H, dmin, eps;
+    const vct_term* terms;
+} vct_map;
+
+/* ---------------------------------------------------------------- queries */
+
+/* Status name (static string; never NULL). */
+const char* vct_status_string(int status);
+
+/* Text of the last HIP error seen by this thread (static storage). */
+const char* vct_last_error(void);
+
+/* Background-cell grid over the projected box [lo, hi) for support radius R:
+ * per axis nc = max(1, floor((hi - lo) / (R (1 + 2^-20)))) cells of size
+ * (hi - lo) / nc >= R.  Positions outside the box are clamped to the boundary
+ * cells, which keeps the search correct (clamping never separates two points
+ * closer than one cell).  Writes dims (host, 3 entries; unused axes = 1) and
+ * returns the number of cells, or a negative status.  Host only.              */
+int64_t vct_grid_dims(int dim, const double* lo, const double* hi, double R, int64_t* dims);
+
+/* Rows of one particle's output record for `out_mask` (0 if invalid). */
+int vct_n_out(int dim, uint32_t out_mask);
+
+/* Values per particle in the state written by vct_moments:
+ * nL + n_out * (d + m) + n_out * d, nL = 3 (2-D) or 6 (3-D).  0 if invalid. */
+int vct_state_stride(int dim, uint32_t out_mask);
+
+/* ---------------------------------------------------------------- cells */
+
+size_t vct_build_cells_workspace_size(int dim, int64_t n, int64_t ncell);
+
+/* Background-cell sort (paper Sec. 3.4 performs neighbour searches with
+ * background cells).  Buckets the n particles (positions `pos`, SoA [dim][n],
+ * ORIGINAL order, projected space) into the grid of vct_grid_dims and sorts
+ * them by (cell, original index): cells in lexicographic order of (x, y, z)
+ * cell coordinates with z fastest.
+ *   perm       [n]          sorted index -> original index
+ *   pos_sorted [dim][n]     positions in sorted order
+ *   cell_start [ncell + 1]  first sorted index of every cell; cell c holds
+ *                           [cell_start[c], cell_start[c+1])
+ * SYNC.  Returns VCT_E_NONFINITE (outputs undefined) if any coordinate is not
+ * finite.  n == 0 is valid (cell_start is zero-filled).                        */
+int vct_build_cells(int dim, int64_t n, const double* pos, const double* lo, const double* hi,
+                    double R, int32_t* perm, double* pos_sorted, int64_t* cell_start,
+                    int64_t ncell, void* ws, size_t ws_bytes, void* stream);
+
+/* Gather per-particle arrays into sorted order: dst[c][s] = src[c][perm[s]] for
+ * ncomp components of n values each.  vct_scatter_sorted is the inverse
+ * (dst[c][perm[s]] = src[c][s]).                                               */
+int vct_gather_sorted(int64_t n, int ncomp, const int32_t* perm, const double* src, double* dst,
+                      void* stream);
+int vct_scatter_sorted(int64_t n, int ncomp, const int32_t* perm, const double* src, double* dst,
+                       void* stream);
+
+/* ---------------------------------------------------------------- neighbours */
+
+size_t vct_neighbors_workspace_size(int64_t n);
+
+/* Neighbour lists S_i = { j != i : d2(i,j) < R*R } (Eq. SPH_neighbor_set) of
+ * the cell-sorted particles, as CSR over sorted indices with ascending columns.
+ * d2 is evaluated in FP64 as ((dx*dx + dy*dy) + dz*dz) with dx = x_j - x_i and
+ * no fused multiply-add, so lists are reproducible bit for bit.
+ * lo, hi, R, cell_start must be those given to vct_build_cells.
+ * Protocol: row_ptr [n+1] is always written and *nnz_out (host) receives the
+ * total.  If col is NULL the call stops there (VCT_OK).  If col_cap < nnz it
+ * returns VCT_E_CAPACITY.  Otherwise col [nnz] is filled.  With
+ * reuse_row_ptr != 0 the counts are not recomputed: row_ptr must hold the
+ * result of an earlier call on the same inputs.  SYNC (reads nnz).             */
+int vct_neighbors(int dim, int64_t n, const double* pos_sorted, const double* lo, const double* hi,
+                  double R, const int64_t* cell_start, int64_t ncell, int64_t* row_ptr, int32_t* col,
+                  int64_t col_cap, int64_t* nnz_out, int reuse_row_ptr, void* ws, size_t ws_bytes,
+                  void* stream);
+
+/* ---------------------------------------------------------------- moments */
+
+/* Per-particle moment assembly and solve, always in FP64 (Eqs. gra_1st and
+ * sec_SPH2).  For every particle i it forms the first-order correction matrix
+ * and the SPH(2) system, equivalently the (d+m) x (d+m) block system of the
+ * Taylor moments (m = 3 in 2-D, 6 in 3-D), solves it with partial pivoting, and
+ * folds the solution with the VCT coefficients of `map` at the particle into
+ * the state consumed by vct_apply_ops:
+ *   state[k][i], k < nL               dimensionless first-order correction
+ *                                     matrix (symmetric, upper triangle) in
+ *                                     units of R
+ *   state[nL + o*(d+m) + c][i]         coefficient of neighbour sum c in output
+ *                                     row o of `out_mask`
+ *   state[nL + n_out*(d+m) + o*d + a][i]  response of output row o to a unit
+ *                                     projected gradient along axis a (the
+ *                                     operator applied to a linear field)
+ * state64 [stride][n] (FP64) is required; state32 (FP32 copy, same layout) may
+ * be NULL.  flags [n] (may be NULL) receives VCT_FLAG_* bits; flagged particles
+ * get NaN state rows, hence NaN outputs.  If n_flagged (host) is not NULL the
+ * call is SYNC and returns VCT_W_FLAGGED when the count is non-zero.          */
+int vct_moments(int dim, int64_t n, const double* pos_sorted, const double* vol_sorted,
+                const int64_t* row_ptr, const int32_t* col, int kernel, double R,
+                const vct_map* map /* host */, uint32_t out_mask, double* state64, float* state32,
+                uint8_t* flags, int64_t* n_flagged, void* ws, size_t ws_bytes, void* stream);
+
+size_t vct_moments_workspace_size(int dim, int64_t n);
+
+/* ---------------------------------------------------------------- apply */
+
+/* Apply the operators to nf fields (Eqs. grad_VCT, lap_VCT, sec_SPH2):
+ *   a_i = sum_j V_j phi_ij grad w_ij,   s_i = sum_j V_j F_ij q_ij phi_ij
+ * (phi_ij = phi_j - phi_i), then out_i = P_i [a_i; s_i] with the state of
+ * vct_moments (same out_mask).  The sums are taken in two passes over the row:
+ * the first gives the first-order gradient G_i = L_i a_i, the second sums the
+ * residual psi_ij = phi_ij - r_ij . G_i (formed in FP64), and
+ * out_i = P_i [a_i(psi); s_i(psi)] + W_i G_i.  This equals the one-pass result
+ * exactly (the operator reproduces linear fields) while keeping the summed
+ * terms second-order small, so rounding in the sums is not amplified by the
+ * cancellation of the first-order parts.  `state` is FP64 for VCT_FP64 and
+ * VCT_MIXED_S64, FP32 (state32) for VCT_MIXED.  phi_sorted [nf][n] FP64,
+ * out [nf][n][n_out] FP64.  In the mixed forms r_ij, phi_ij and psi_ij are
+ * formed in FP64 and rounded once to FP32; the pair terms and sums are FP32;
+ * the final product with the state is FP32 and stored as FP64.                */
+int vct_apply_ops(int dim, int64_t n, int nf, const double* phi_sorted, const double* pos_sorted,
+                  const double* vol_sorted, const int64_t* row_ptr, const int32_t* col, int kernel,
+                  double R, const void* state, uint32_t out_mask, int precision, double* out,
+                  void* stream);
+
+/* ---------------------------------------------------------------- adjoint */
+
+size_t vct_adjoint_workspace_size(int dim, int64_t n, int nterms);
+
+/* Adjoint of the physical Laplacian (not in the paper; built on Eqs. lap_VCT
+ * and sec_SPH2).  With lap_i = sum_j W_ij phi_ij the linear operator of
+ * vct_apply_ops (FP64), and u [n] the cotangent of lap:
+ *   dphi_k   = sum_{i in S_k} u_i W_ik - u_k sum_{j in S_k} W_kj
+ *              (transposed operator, evaluated as a gather: no atomics)
+ *   dtheta_t = sum_i u_i (d c_trans_i / d coef_t) . D^ phi_i
+ *              for every bathymetry term t of `map` (projected positions held
+ *              fixed; the sum is reduced in a fixed order).
+ * `state64` must come from vct_moments with out_mask containing
+ * VCT_OUT_LAP | VCT_OUT_PGRAD | VCT_OUT_PHESS (pass the same mask).
+ * phi_sorted [n] is needed only when dtheta is not NULL.  dphi [n] and
+ * dtheta [map->nterms] are device outputs; either may be NULL.                 */
+int vct_apply_ops_adjoint(int dim, int64_t n, const double* pos_sorted, const double* vol_sorted,
+                          const int64_t* row_ptr, const int32_t* col, int kernel, double R,
+                          const double* state64, uint32_t out_mask, const vct_map* map /* host */,
+                          const double* phi_sorted, const double* u, double* dphi, double* dtheta,
+                          void* ws, size_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VCT_H */

@@ -1,0 +1,162 @@
+// Vertical coordinate transformation on the device: bottom elevation terms,
+// alpha/beta for the mapping kinds, and the coefficients that carry projected
+// derivatives to physical ones (paper Sec. 2.1, Eqs. VCT, jacobi, grad_VCT,
+// lap_VCT; Sec. 2.2 for alpha and beta).
+//
+// The same template serves plain FP64 and a forward-mode dual number whose
+// tangents are the derivatives with respect to the six bottom-elevation
+// quantities (h, h_x, h_y, h_xx, h_xy, h_yy); the adjoint uses the latter for
+// the sensitivity to bathymetry coefficients.
+#pragma once
+
+#include "common.h"
+
+namespace vct {
+
+struct MapParams {
+    int32_t kind;
+    int32_t nterms;
+    int32_t dim;
+    int32_t limiter;          // sigma: smooth depth limiter on
+    double Hhat, H, dmin, eps;
+    double coef[VCT_MAX_TERMS];
+    int32_t bx[VCT_MAX_TERMS], by[VCT_MAX_TERMS];
+    double fx[VCT_MAX_TERMS], fy[VCT_MAX_TERMS];
+};
+
+int map_params_from(const vct_map* m, int dim, MapParams& p);  // host, returns status
+
+// B(s), B'(s), B''(s) of one separable factor
+__device__ __forceinline__ void basis3(int kind, double f, double s, double b[3]) {
+    if (kind == VCT_BASIS_ONE) { b[0] = 1.0; b[1] = 0.0; b[2] = 0.0; return; }
+    if (kind == VCT_BASIS_LIN) { b[0] = s; b[1] = 1.0; b[2] = 0.0; return; }
+    double sn, cs;
+    sincospi(2.0 * f * s, &sn, &cs);
+    const double w = 2.0 * M_PI * f;
+    if (kind == VCT_BASIS_COS) { b[0] = cs; b[1] = -w * sn; b[2] = -w * w * cs; }
+    else { b[0] = sn; b[1] = w * cs; b[2] = -w * w * sn; }
+}
+
+// the six products [B B, B' B, B B', B'' B, B' B', B B''] of term t at (x, y)
+__device__ __forceinline__ void term_derivs(const MapParams& mp, int t, double x, double y, double o[6]) {
+    double bx[3], by[3];
+    basis3(mp.bx[t], mp.fx[t], x, bx);
+    basis3(mp.by[t], mp.fy[t], y, by);
+    if (mp.dim == 2) { by[1] = 0.0; by[2] = 0.0; }
+    o[0] = bx[0] * by[0];
+    o[1] = bx[1] * by[0];
+    o[2] = bx[0] * by[1];
+    o[3] = bx[2] * by[0];
+    o[4] = bx[1] * by[1];
+    o[5] = bx[0] * by[2];
+}
+
+// h, h_x, h_y, h_xx, h_xy, h_yy at (x, y)
+__device__ __forceinline__ void bottom6(const MapParams& mp, double x, double y, double h[6]) {
+    for (int k = 0; k < 6; ++k) h[k] = 0.0;
+    for (int t = 0; t < mp.nterms; ++t) {
+        double o[6];
+        term_derivs(mp, t, x, y, o);
+        for (int k = 0; k < 6; ++k) h[k] += mp.coef[t] * o[k];
+    }
+}
+
+// ------------------------------------------------------------------ dual numbers
+
+struct Dual6 {
+    double v;
+    double d[6];
+    __device__ Dual6() {}
+    __device__ Dual6(double c) : v(c) { for (int k = 0; k < 6; ++k) d[k] = 0.0; }
+};
+__device__ __forceinline__ Dual6 operator+(const Dual6& a, const Dual6& b) {
+    Dual6 r; r.v = a.v + b.v; for (int k = 0; k < 6; ++k) r.d[k] = a.d[k] + b.d[k]; return r;
+}
+__device__ __forceinline__ Dual6 operator-(const Dual6& a, const Dual6& b) {
+    Dual6 r; r.v = a.v - b.v; for (int k = 0; k < 6; ++k) r.d[k] = a.d[k] - b.d[k]; return r;
+}
+__device__ __forceinline__ Dual6 operator-(const Dual6& a) {
+    Dual6 r; r.v = -a.v; for (int k = 0; k < 6; ++k) r.d[k] = -a.d[k]; return r;
+}
+__device__ __forceinline__ Dual6 operator*(const Dual6& a, const Dual6& b) {
+    Dual6 r; r.v = a.v * b.v; for (int k = 0; k < 6; ++k) r.d[k] = a.d[k] * b.v + a.v * b.d[k]; return r;
+}
+__device__ __forceinline__ Dual6 operator/(const Dual6& a, const Dual6& b) {
+    Dual6 r; r.v = a.v / b.v;
+    double ib = 1.0 / b.v;
+    for (int k = 0; k < 6; ++k) r.d[k] = (a.d[k] - r.v * b.d[k]) * ib;
+    return r;
+}
+__device__ __forceinline__ Dual6 dsqrt(const Dual6& a) {
+    Dual6 r; r.v = sqrt(a.v);
+    double h = 0.5 / r.v;
+    for (int k = 0; k < 6; ++k) r.d[k] = a.d[k] * h;
+    return r;
+}
+__device__ __forceinline__ double dsqrt(double a) { return sqrt(a); }
+__device__ __forceinline__ double value(double a) { return a; }
+__device__ __forceinline__ double value(const Dual6& a) { return a.v; }
+
+// ------------------------------------------------------------------ mapping coefficients
+
+// Coefficients of the physical derivatives at one particle:
+//   gx = dz^/dx, gy = dz^/dy, alpha = dz^/dz (Jacobian column of z^, Eq. jacobi)
+//   c0, c3, c4, c5: the non-constant entries of c_trans (Eq. lap_VCT)
+//   second derivatives of z^ with respect to (x, y, z): zxx, zyy, zxy, zxz, zyz (zzz = 0)
+template <class T> struct MapCoef {
+    T alpha, gx, gy, c0, c3, c4, c5, zxx, zyy, zxy, zxz, zyz;
+};
+
+// From h (and derivatives) and the projected height zh; z + beta = zh / alpha.
+template <class T>
+__device__ __forceinline__ MapCoef<T> map_coef(const MapParams& mp, const T h[6], double zh) {
+    T a(1.0), ax(0.0), ay(0.0), axx(0.0), axy(0.0), ayy(0.0);
+    T bx(0.0), by(0.0), bxx(0.0), bxy(0.0), byy(0.0);
+    if (mp.kind == VCT_MAP_E || mp.kind == VCT_MAP_BFE) a = T(mp.Hhat / mp.H);
+    if (mp.kind == VCT_MAP_BF || mp.kind == VCT_MAP_BFE) {
+        bx = -h[1]; by = -h[2]; bxx = -h[3]; bxy = -h[4]; byy = -h[5];
+    }
+    if (mp.kind == VCT_MAP_SIGMA) {
+        // depth D = H - h, smoothly limited from below: E = smax(D, dmin; eps)
+        T D = T(mp.H) - h[0];
+        T Dx = -h[1], Dy = -h[2], Dxx = -h[3], Dxy = -h[4], Dyy = -h[5];
+        T E = D, s1(1.0), s2(0.0);
+        if (mp.limiter) {
+            T dd = D - T(mp.dmin);
+            T S = dsqrt(dd * dd + T(mp.eps * mp.eps));
+            E = T(0.5) * (D + T(mp.dmin) + S);
+            s1 = T(0.5) * (T(1.0) + dd / S);
+            s2 = T(0.5 * mp.eps * mp.eps) / (S * S * S);
+        }
+        T Ex = s1 * Dx, Ey = s1 * Dy;
+        T Exx = s2 * Dx * Dx + s1 * Dxx;
+        T Exy = s2 * Dx * Dy + s1 * Dxy;
+        T Eyy = s2 * Dy * Dy + s1 * Dyy;
+        T iE = T(1.0) / E;
+        T Hh(mp.Hhat);
+        a = Hh * iE;
+        ax = -a * Ex * iE;
+        ay = -a * Ey * iE;
+        axx = a * iE * (T(2.0) * Ex * Ex * iE - Exx);
+        axy = a * iE * (T(2.0) * Ex * Ey * iE - Exy);
+        ayy = a * iE * (T(2.0) * Ey * Ey * iE - Eyy);
+        bx = Ex; by = Ey; bxx = Exx; bxy = Exy; byy = Eyy;
+    }
+    T zb = T(zh) / a;  // z + beta
+    MapCoef<T> c;
+    c.alpha = a;
+    c.gx = ax * zb + a * bx;
+    c.gy = ay * zb + a * by;
+    c.zxx = axx * zb + T(2.0) * ax * bx + a * bxx;
+    c.zyy = ayy * zb + T(2.0) * ay * by + a * byy;
+    c.zxy = axy * zb + ax * by + ay * bx + a * bxy;
+    c.zxz = ax;
+    c.zyz = ay;
+    c.c0 = c.zxx + c.zyy;                         // Laplacian of z^
+    c.c3 = a * a + c.gx * c.gx + c.gy * c.gy;
+    c.c4 = T(2.0) * c.gx;
+    c.c5 = T(2.0) * c.gy;
+    return c;
+}
+
+}  // namespace vct

@@ -1,0 +1,482 @@
+// Moment assembly and per-particle solve, FP64 (paper Sec. 3.1, Eqs. gra_1st
+// and sec_SPH2), folded with the VCT coefficients (Sec. 2.1).
+//
+// Formulation.  With r~ = r_ij / R, c~ the kernel shape (grad w = K c~ r~) and
+// q~ the quadratic monomials of r~, expanding phi_ij to second order and taking
+// moments against V c~ r~ (d rows) and V F~ q~ (m rows) gives the block system
+//     [ A  B ] [ R grad phi ]   [ a ]    A = sum V c~ r~ r~^T   B = sum V c~ r~ q~^T
+//     [ C  E ] [ R^2 D / 2  ] = [ s ]    C = sum V F~ q~ r~^T   E = sum V F~ q~ q~^T
+// with F~ = c~ (r~^T L r~) / |r~|^4, L = A^-1 (the paper's first-order
+// correction, F_ij of Eq. sec_SPH2 up to constant factors), a = sum V c~ phi_ij r~,
+// s = sum V F~ q~ phi_ij.  Eliminating the first block row reproduces Eq.
+// sec_SPH2: M = E - C L B and D/2 = M^-1 (s - C L a), and the second-order
+// gradient is L a - (L B) D/2.  Only the distinct monomials are accumulated
+// (3rd and 4th order: 10 and 15 in 3-D); the two sweeps differ because F~
+// needs L from the first.
+//
+// Kernel 1 (one group of G lanes per particle) runs the sweeps and writes the
+// monomial sums.  Kernel 2 (one thread per particle) solves the Schur system
+// with partial pivoting and writes, per output row o and neighbour sum c, the
+// coefficient P_i[o][c] of the physical output in terms of [a; s].
+#include "common.h"
+#include "map_dev.h"
+
+namespace vct {
+
+template <int D> struct MomLayout {
+    static constexpr int nL = Dims<D>::nL, n3 = Dims<D>::n3, n4 = Dims<D>::n4;
+    static constexpr int oL = 0, oB = nL, oC = nL + n3, oE = nL + 2 * n3;
+    static constexpr int total = nL + 2 * n3 + n4;
+};
+
+constexpr double kPivotTol = 1e-12;
+
+// inverse of a symmetric d x d matrix (pairs order), false if singular
+template <int D>
+__device__ __forceinline__ bool sym_inverse(const double (&A)[Dims<D>::nL], double (&L)[Dims<D>::nL]) {
+    if (D == 2) {
+        // pairs [xx, zz, xz]
+        double a = A[0], c = A[1], b = A[2];
+        double det = a * c - b * b;
+        double sc = fmax(fabs(a), fmax(fabs(b), fabs(c)));
+        bool bad = !(fabs(det) > kPivotTol * sc * sc) || !isfinite(det);
+        double id = 1.0 / det;
+        L[0] = c * id; L[1] = a * id; L[2] = -b * id;
+        return !bad;
+    } else {
+        // pairs [xx, yy, zz, xy, xz, yz]
+        double a00 = A[0], a11 = A[1], a22 = A[2], a01 = A[3], a02 = A[4], a12 = A[5];
+        double c00 = a11 * a22 - a12 * a12;
+        double c01 = a02 * a12 - a01 * a22;
+        double c02 = a01 * a12 - a02 * a11;
+        double c11 = a00 * a22 - a02 * a02;
+        double c12 = a01 * a02 - a00 * a12;
+        double c22 = a00 * a11 - a01 * a01;
+        double det = a00 * c00 + a01 * c01 + a02 * c02;
+        double sc = 0.0;
+        for (int k = 0; k < 6; ++k) sc = fmax(sc, fabs(A[k]));
+        bool bad = !(fabs(det) > kPivotTol * sc * sc * sc) || !isfinite(det);
+        double id = 1.0 / det;
+        L[0] = c00 * id; L[1] = c11 * id; L[2] = c22 * id;
+        L[3] = c01 * id; L[4] = c02 * id; L[5] = c12 * id;
+        return !bad;
+    }
+}
+
+template <int D>
+__device__ __forceinline__ double sym_at(const double (&S)[Dims<D>::nL], int a, int b) {
+    // element (a, b) of a symmetric matrix stored in pairs order
+    if (D == 2) return (a == b) ? S[a] : S[2];
+    if (a == b) return S[a];
+    int lo = a < b ? a : b, hi = a < b ? b : a;
+    return (lo == 0 && hi == 1) ? S[3] : (lo == 0 ? S[4] : S[5]);
+}
+
+// ------------------------------------------------------------------ kernel 1: sweeps
+
+template <int D, int G, int KERNEL>
+__global__ __launch_bounds__(256) void k_moment_sweeps(int64_t n, const double* __restrict__ pos,
+                                                       const double* __restrict__ vol,
+                                                       const int64_t* __restrict__ row_ptr,
+                                                       const int32_t* __restrict__ col, double invR,
+                                                       double* __restrict__ mom, uint8_t* __restrict__ mflags) {
+    using Dm = Dims<D>;
+    using ML = MomLayout<D>;
+    constexpr int PER_BLOCK = 256 / G;
+    const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int lane = threadIdx.x % G;
+    const int64_t i = (int64_t)tile * PER_BLOCK + threadIdx.x / G;
+    if (i >= n) return;
+    double xi[D];
+    for (int a = 0; a < D; ++a) xi[a] = pos[a * n + i];
+    const int64_t rb = row_ptr[i], re = row_ptr[i + 1];
+    int fl = 0;
+    if (re - rb < D + Dm::m) fl |= VCT_FLAG_FEW;
+    bool fin = isfinite(vol[i]);
+    for (int a = 0; a < D; ++a) fin = fin && isfinite(xi[a]);
+    if (!fin) fl |= VCT_FLAG_NONFINITE;
+
+    // sweep 1: A (pairs) and B (3rd-order monomials), weights V c~
+    double A[Dm::nL], B[Dm::n3];
+    for (int p = 0; p < Dm::nL; ++p) A[p] = 0.0;
+    for (int t = 0; t < Dm::n3; ++t) B[t] = 0.0;
+    for (int64_t k = rb + lane; k < re; k += G) {
+        const int64_t j = col[k];
+        double r[D], q2 = 0.0;
+        for (int a = 0; a < D; ++a) { r[a] = (pos[a * n + j] - xi[a]) * invR; q2 += r[a] * r[a]; }
+        const double V = vol[j];
+        if (q2 == 0.0) fl |= VCT_FLAG_DUPLICATE;
+        if (!isfinite(q2) || !isfinite(V)) fl |= VCT_FLAG_NONFINITE;
+        const double w = V * kernel_shape<KERNEL>(sqrt(q2));
+#pragma unroll
+        for (int p = 0; p < Dm::nL; ++p) A[p] += w * r[pair_a<D>(p)] * r[pair_b<D>(p)];
+#pragma unroll
+        for (int t = 0; t < Dm::n3; ++t)
+            B[t] += w * r[mono_comp<D, 3>(t, 0)] * r[mono_comp<D, 3>(t, 1)] * r[mono_comp<D, 3>(t, 2)];
+    }
+#pragma unroll
+    for (int p = 0; p < Dm::nL; ++p) A[p] = group_sum(A[p], G);
+#pragma unroll
+    for (int t = 0; t < Dm::n3; ++t) B[t] = group_sum(B[t], G);
+    for (int m_ = G >> 1; m_ >= 1; m_ >>= 1) fl |= __shfl_xor(fl, m_, kWave);
+
+    double L[Dm::nL];
+    if (!sym_inverse<D>(A, L)) fl |= VCT_FLAG_SINGULAR_A;
+
+    // sweep 2: C (3rd order) and E (4th order), weights V F~
+    double Cm[Dm::n3], E[Dm::n4];
+    for (int t = 0; t < Dm::n3; ++t) Cm[t] = 0.0;
+    for (int t = 0; t < Dm::n4; ++t) E[t] = 0.0;
+    if (!fl) {
+        for (int64_t k = rb + lane; k < re; k += G) {
+            const int64_t j = col[k];
+            double r[D], q2 = 0.0;
+            for (int a = 0; a < D; ++a) { r[a] = (pos[a * n + j] - xi[a]) * invR; q2 += r[a] * r[a]; }
+            double rLr = 0.0;
+#pragma unroll
+            for (int p = 0; p < Dm::nL; ++p)
+                rLr += (pair_a<D>(p) == pair_b<D>(p) ? 1.0 : 2.0) * L[p] * r[pair_a<D>(p)] * r[pair_b<D>(p)];
+            const double F = kernel_shape<KERNEL>(sqrt(q2)) * rLr / (q2 * q2);
+            const double w = vol[j] * F;
+#pragma unroll
+            for (int t = 0; t < Dm::n3; ++t)
+                Cm[t] += w * r[mono_comp<D, 3>(t, 0)] * r[mono_comp<D, 3>(t, 1)] * r[mono_comp<D, 3>(t, 2)];
+#pragma unroll
+            for (int t = 0; t < Dm::n4; ++t)
+                E[t] += w * r[mono_comp<D, 4>(t, 0)] * r[mono_comp<D, 4>(t, 1)] * r[mono_comp<D, 4>(t, 2)] *
+                        r[mono_comp<D, 4>(t, 3)];
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < Dm::n3; ++t) Cm[t] = group_sum(Cm[t], G);
+#pragma unroll
+    for (int t = 0; t < Dm::n4; ++t) E[t] = group_sum(E[t], G);
+
+    // each lane stores a share of the sums (all lanes hold all of them)
+#pragma unroll
+    for (int v = 0; v < ML::total; ++v) {
+        if (v % G != lane) continue;
+        double x = v < ML::oB ? L[v] : v < ML::oC ? B[v - ML::oB] : v < ML::oE ? Cm[v - ML::oC] : E[v - ML::oE];
+        mom[(int64_t)v * n + i] = x;
+    }
+    if (lane == 0) mflags[i] = (uint8_t)fl;
+}
+
+// ------------------------------------------------------------------ kernel 2: solve + fold
+
+template <int M>
+__device__ __forceinline__ bool lu_factor(double (&A)[M][M], int (&piv)[M]) {
+    double scale = 0.0;
+#pragma unroll
+    for (int r = 0; r < M; ++r)
+#pragma unroll
+        for (int c = 0; c < M; ++c) scale = fmax(scale, fabs(A[r][c]));
+    bool bad = !(scale > 0.0) || !isfinite(scale);
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+        int p = c;
+        double best = fabs(A[c][c]);
+#pragma unroll
+        for (int r = c + 1; r < M; ++r) {
+            double v = fabs(A[r][c]);
+            if (v > best) { best = v; p = r; }
+        }
+        piv[c] = p;
+        if (!(best > kPivotTol * scale)) bad = true;
+#pragma unroll
+        for (int r = c + 1; r < M; ++r) {
+            if (r == p) {
+#pragma unroll
+                for (int k = 0; k < M; ++k) { double t = A[c][k]; A[c][k] = A[r][k]; A[r][k] = t; }
+            }
+        }
+        const double inv = 1.0 / A[c][c];
+#pragma unroll
+        for (int r = c + 1; r < M; ++r) {
+            const double f = A[r][c] * inv;
+            A[r][c] = f;
+#pragma unroll
+            for (int k = c + 1; k < M; ++k) A[r][k] -= f * A[c][k];
+        }
+    }
+    return !bad;
+}
+
+template <int M>
+__device__ __forceinline__ void lu_solve(const double (&A)[M][M], const int (&piv)[M], double (&b)[M]) {
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+#pragma unroll
+        for (int r = c + 1; r < M; ++r) {
+            if (r == piv[c]) { double t = b[c]; b[c] = b[r]; b[r] = t; }
+        }
+    }
+#pragma unroll
+    for (int r = 1; r < M; ++r)
+#pragma unroll
+        for (int k = 0; k < r; ++k) b[r] -= A[r][k] * b[k];
+#pragma unroll
+    for (int r = M - 1; r >= 0; --r) {
+#pragma unroll
+        for (int k = r + 1; k < M; ++k) b[r] -= A[r][k] * b[k];
+        b[r] /= A[r][r];
+    }
+}
+
+// Physical (and projected) outputs from a projected gradient pg and projected
+// second derivatives ph (pairs order), in the row order of the output mask.
+// Linear in (pg, ph): applied to one column of the solved system it yields
+// that column of P.  Eq. grad_VCT, Eq. lap_VCT, and the chain rule
+// Hess = J H^ J^T + dz^phi (d2 z^) for the cross and full Hessian rows.
+template <int D, class Put>
+__device__ __forceinline__ int emit_rows(uint32_t mask, const MapCoef<double>& c, const double* pg,
+                                         const double* ph, Put&& out) {
+    int o = 0;
+    if (D == 3) {
+        const double gz = pg[2];
+        const double Hxx = ph[0], Hyy = ph[1], Hzz = ph[2], Hxy = ph[3], Hxz = ph[4], Hyz = ph[5];
+        const double xy = Hxy + c.gy * Hxz + c.gx * Hyz + c.gx * c.gy * Hzz + c.zxy * gz;
+        const double xz = c.alpha * (Hxz + c.gx * Hzz) + c.zxz * gz;
+        const double yz = c.alpha * (Hyz + c.gy * Hzz) + c.zyz * gz;
+        if (mask & VCT_OUT_GRAD) {
+            out(o++, pg[0] + c.gx * gz);
+            out(o++, pg[1] + c.gy * gz);
+            out(o++, c.alpha * gz);
+        }
+        if (mask & VCT_OUT_LAP) out(o++, c.c0 * gz + Hxx + Hyy + c.c3 * Hzz + c.c4 * Hxz + c.c5 * Hyz);
+        if (mask & VCT_OUT_CROSS) { out(o++, xy); out(o++, xz); out(o++, yz); }
+        if (mask & VCT_OUT_HESS) {
+            out(o++, Hxx + 2.0 * c.gx * Hxz + c.gx * c.gx * Hzz + c.zxx * gz);
+            out(o++, Hyy + 2.0 * c.gy * Hyz + c.gy * c.gy * Hzz + c.zyy * gz);
+            out(o++, c.alpha * c.alpha * Hzz);
+            out(o++, xy); out(o++, xz); out(o++, yz);
+        }
+        if (mask & VCT_OUT_PGRAD) { out(o++, pg[0]); out(o++, pg[1]); out(o++, pg[2]); }
+        if (mask & VCT_OUT_PHESS) for (int p = 0; p < 6; ++p) out(o++, ph[p]);
+    } else {
+        const double gz = pg[1];
+        const double Hxx = ph[0], Hzz = ph[1], Hxz = ph[2];
+        const double xz = c.alpha * (Hxz + c.gx * Hzz) + c.zxz * gz;
+        if (mask & VCT_OUT_GRAD) { out(o++, pg[0] + c.gx * gz); out(o++, c.alpha * gz); }
+        if (mask & VCT_OUT_LAP) out(o++, c.c0 * gz + Hxx + c.c3 * Hzz + c.c4 * Hxz);
+        if (mask & VCT_OUT_CROSS) out(o++, xz);
+        if (mask & VCT_OUT_HESS) {
+            out(o++, Hxx + 2.0 * c.gx * Hxz + c.gx * c.gx * Hzz + c.zxx * gz);
+            out(o++, c.alpha * c.alpha * Hzz);
+            out(o++, xz);
+        }
+        if (mask & VCT_OUT_PGRAD) { out(o++, pg[0]); out(o++, pg[1]); }
+        if (mask & VCT_OUT_PHESS) for (int p = 0; p < 3; ++p) out(o++, ph[p]);
+    }
+    return o;
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_moment_solve(int64_t n, const double* __restrict__ pos,
+                                                      const double* __restrict__ mom,
+                                                      const uint8_t* __restrict__ mflags, double invR,
+                                                      MapParams mp, uint32_t mask, int nrows,
+                                                      double* __restrict__ state64, float* __restrict__ state32,
+                                                      uint8_t* __restrict__ flags_out,
+                                                      unsigned long long* __restrict__ nflag) {
+    using Dm = Dims<D>;
+    using ML = MomLayout<D>;
+    constexpr int d = D, m = Dm::m, nL = Dm::nL, nk = Dm::nk;
+    const int64_t i = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int fl = mflags[i];
+    double L[nL];
+    for (int p = 0; p < nL; ++p) L[p] = mom[(int64_t)(ML::oL + p) * n + i];
+
+    // B~ (d x m), C~ (m x d), E~ (m x m) from the distinct monomial sums
+    double Bt[d][m], Ct[m][d], M[m][m];
+#pragma unroll
+    for (int a = 0; a < d; ++a)
+#pragma unroll
+        for (int p = 0; p < m; ++p) {
+            Bt[a][p] = mom[(int64_t)(ML::oB + mono3_index<D>(a, pair_a<D>(p), pair_b<D>(p))) * n + i];
+            Ct[p][a] = mom[(int64_t)(ML::oC + mono3_index<D>(pair_a<D>(p), pair_b<D>(p), a)) * n + i];
+        }
+#pragma unroll
+    for (int p = 0; p < m; ++p)
+#pragma unroll
+        for (int q = 0; q < m; ++q)
+            M[p][q] = mom[(int64_t)(ML::oE + mono4_index<D>(pair_a<D>(p), pair_b<D>(p), pair_a<D>(q), pair_b<D>(q))) * n + i];
+
+    // Q^T = L B (d x m);  M = E - C Q^T;  CL = C L (m x d)
+    double Qt[d][m], CL[m][d];
+#pragma unroll
+    for (int a = 0; a < d; ++a)
+#pragma unroll
+        for (int p = 0; p < m; ++p) {
+            double t = 0.0;
+#pragma unroll
+            for (int b = 0; b < d; ++b) t += sym_at<D>(L, a, b) * Bt[b][p];
+            Qt[a][p] = t;
+        }
+#pragma unroll
+    for (int p = 0; p < m; ++p) {
+#pragma unroll
+        for (int q = 0; q < m; ++q) {
+            double t = 0.0;
+#pragma unroll
+            for (int a = 0; a < d; ++a) t += Ct[p][a] * Qt[a][q];
+            M[p][q] -= t;
+        }
+#pragma unroll
+        for (int a = 0; a < d; ++a) {
+            double t = 0.0;
+#pragma unroll
+            for (int b = 0; b < d; ++b) t += Ct[p][b] * sym_at<D>(L, b, a);
+            CL[p][a] = t;
+        }
+    }
+    int piv[m];
+    if (!fl && !lu_factor<m>(M, piv)) fl |= VCT_FLAG_SINGULAR_M;
+
+    // VCT coefficients at the particle
+    const double x = pos[i], y = (D == 3) ? pos[n + i] : 0.0, zh = pos[(int64_t)(D - 1) * n + i];
+    double h[6];
+    bottom6(mp, x, y, h);
+    const MapCoef<double> mc = map_coef<double>(mp, h, zh);
+    const bool grad1 = (mask & VCT_OPT_GRAD1) != 0;
+    const double invR2 = invR * invR;
+    const double nanv = __builtin_nan("");
+
+#pragma unroll
+    for (int k = 0; k < nk; ++k) {
+        double z[m];
+#pragma unroll
+        for (int p = 0; p < m; ++p) z[p] = (k < d) ? CL[p][k] : (p == k - d ? 1.0 : 0.0);
+        lu_solve<m>(M, piv, z);
+        double pg[d], ph[m];
+#pragma unroll
+        for (int a = 0; a < d; ++a) {
+            double t = 0.0;
+#pragma unroll
+            for (int p = 0; p < m; ++p) t += Qt[a][p] * z[p];
+            double g;
+            if (k < d) g = sym_at<D>(L, a, k) + (grad1 ? 0.0 : t);
+            else g = grad1 ? 0.0 : -t;
+            pg[a] = g * invR;
+        }
+#pragma unroll
+        for (int p = 0; p < m; ++p) {
+            const double hv = (k < d) ? -z[p] : z[p];
+            ph[p] = hv * ((p < d) ? 2.0 * invR2 : invR2);
+        }
+        emit_rows<D>(mask, mc, pg, ph, [&](int o, double v) {
+            v = fl ? nanv : v;
+            const int64_t idx = (int64_t)(nL + o * nk + k) * n + i;
+            state64[idx] = v;
+            if (state32) state32[idx] = (float)v;
+        });
+    }
+    // W: response of every output row to a unit projected gradient (a linear
+    // field), used by the apply kernels to add back the linear part removed
+    // from the field before the neighbour sums
+    const int wbase = nL + nrows * nk;
+#pragma unroll
+    for (int a = 0; a < d; ++a) {
+        double pg[d], ph[m];
+#pragma unroll
+        for (int b = 0; b < d; ++b) pg[b] = (a == b) ? 1.0 : 0.0;
+#pragma unroll
+        for (int p = 0; p < m; ++p) ph[p] = 0.0;
+        emit_rows<D>(mask, mc, pg, ph, [&](int o, double v) {
+            v = fl ? nanv : v;
+            const int64_t idx = (int64_t)(wbase + o * d + a) * n + i;
+            state64[idx] = v;
+            if (state32) state32[idx] = (float)v;
+        });
+    }
+#pragma unroll
+    for (int p = 0; p < nL; ++p) {
+        const double v = fl ? nanv : L[p];
+        state64[(int64_t)p * n + i] = v;
+        if (state32) state32[(int64_t)p * n + i] = (float)v;
+    }
+    if (flags_out) flags_out[i] = (uint8_t)fl;
+    if (fl && nflag) atomicAdd(nflag, 1ull);
+}
+
+template <int D, int KERNEL>
+static int launch_moments(int64_t n, const double* pos, const double* vol, const int64_t* row_ptr,
+                          const int32_t* col, double invR, const MapParams& mp, uint32_t mask, int nrows,
+                          double* mom, uint8_t* mflags, double* s64, float* s32, uint8_t* flags,
+                          unsigned long long* nflag, hipStream_t s) {
+    constexpr int G = (D == 3) ? 16 : 8;
+    constexpr int PER_BLOCK = 256 / G;
+    int64_t nb1 = (n + PER_BLOCK - 1) / PER_BLOCK;
+    hipLaunchKernelGGL((k_moment_sweeps<D, G, KERNEL>), dim3((unsigned)nb1), dim3(256), 0, s, n, pos, vol,
+                       row_ptr, col, invR, mom, mflags);
+    VCT_LAUNCH_CHECK();
+    int64_t nb2 = (n + 127) / 128;
+    hipLaunchKernelGGL((k_moment_solve<D>), dim3((unsigned)nb2), dim3(128), 0, s, n, pos, mom, mflags, invR, mp,
+                       mask, nrows, s64, s32, flags, nflag);
+    VCT_LAUNCH_CHECK();
+    return VCT_OK;
+}
+
+}  // namespace vct
+
+using namespace vct;
+
+extern "C" size_t vct_moments_workspace_size(int dim, int64_t n) {
+    if ((dim != 2 && dim != 3) || n < 0) return 0;
+    int total = dim == 2 ? MomLayout<2>::total : MomLayout<3>::total;
+    return aligned_sum({(size_t)n * total * sizeof(double), (size_t)n, 64});
+}
+
+__global__ void k_zero_u64(unsigned long long* p) { *p = 0ull; }
+
+extern "C" int vct_moments(int dim, int64_t n, const double* pos_sorted, const double* vol_sorted,
+                           const int64_t* row_ptr, const int32_t* col, int kernel, double R, const vct_map* map,
+                           uint32_t out_mask, double* state64, float* state32, uint8_t* flags,
+                           int64_t* n_flagged, void* ws, size_t ws_bytes, void* stream) {
+    if ((dim != 2 && dim != 3) || n < 0 || n > INT32_MAX || !(R > 0.0) || !isfinite(R) || !map ||
+        !mask_valid(out_mask) || (kernel != VCT_KERNEL_WENDLAND_C2 && kernel != VCT_KERNEL_CUBIC_SPLINE))
+        return VCT_E_ARG;
+    MapParams mp;
+    int st = map_params_from(map, dim, mp);
+    if (st) return st;
+    if (n > 0 && (!pos_sorted || !vol_sorted || !row_ptr || !col || !state64)) return VCT_E_ARG;
+    if (!ws || ws_bytes < vct_moments_workspace_size(dim, n)) return VCT_E_WORKSPACE;
+    hipStream_t s = as_stream(stream);
+    Carver cv(ws, ws_bytes);
+    const int total = dim == 2 ? MomLayout<2>::total : MomLayout<3>::total;
+    double* mom = cv.take<double>((size_t)n * total);
+    uint8_t* mflags = cv.take<uint8_t>((size_t)n);
+    unsigned long long* cnt = cv.take<unsigned long long>(8);
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, s, cnt);
+    VCT_LAUNCH_CHECK();
+    if (n > 0) {
+        const double invR = 1.0 / R;
+        const int nrows = n_out_rows(dim, out_mask);
+        if (dim == 2)
+            st = (kernel == VCT_KERNEL_WENDLAND_C2)
+                     ? launch_moments<2, VCT_KERNEL_WENDLAND_C2>(n, pos_sorted, vol_sorted, row_ptr, col, invR, mp,
+                                                                 out_mask, nrows, mom, mflags, state64, state32,
+                                                                 flags, cnt, s)
+                     : launch_moments<2, VCT_KERNEL_CUBIC_SPLINE>(n, pos_sorted, vol_sorted, row_ptr, col, invR, mp,
+                                                                  out_mask, nrows, mom, mflags, state64, state32,
+                                                                  flags, cnt, s);
+        else
+            st = (kernel == VCT_KERNEL_WENDLAND_C2)
+                     ? launch_moments<3, VCT_KERNEL_WENDLAND_C2>(n, pos_sorted, vol_sorted, row_ptr, col, invR, mp,
+                                                                 out_mask, nrows, mom, mflags, state64, state32,
+                                                                 flags, cnt, s)
+                     : launch_moments<3, VCT_KERNEL_CUBIC_SPLINE>(n, pos_sorted, vol_sorted, row_ptr, col, invR, mp,
+                                                                  out_mask, nrows, mom, mflags, state64, state32,
+                                                                  flags, cnt, s);
+        if (st) return st;
+    }
+    if (n_flagged) {
+        unsigned long long h = 0;
+        VCT_HIP_CHECK(hipMemcpyAsync(&h, cnt, sizeof(h), hipMemcpyDeviceToHost, s));
+        VCT_HIP_CHECK(hipStreamSynchronize(s));
+        *n_flagged = (int64_t)h;
+        return h ? VCT_W_FLAGGED : VCT_OK;
+    }
+    return VCT_OK;
+}

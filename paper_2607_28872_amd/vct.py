@@ -1,0 +1,326 @@
+"""Python binding of libvct (ctypes): argument marshalling only.
+
+Every computation runs in the HIP kernels of libvct.so.  PyTorch supplies
+device memory and the current stream.  If the shared library has not been
+built, every call raises (there is no CPU fallback).
+
+Functions named like the C ABI (vct_*) take torch tensors (device) and plain
+Python numbers, pass raw pointers and the current HIP stream, and raise
+VctError on negative status.  `Geometry` strings the calls together for one
+particle set: cell sort, neighbour lists, moments, and repeated applies.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libvct.so")
+
+VCT_OK, VCT_W_FLAGGED = 0, 1
+VCT_E_ARG, VCT_E_HIP, VCT_E_CAPACITY, VCT_E_NONFINITE, VCT_E_WORKSPACE = -1, -2, -3, -4, -5
+VCT_KERNEL_WENDLAND_C2, VCT_KERNEL_CUBIC_SPLINE = 0, 1
+VCT_FP64, VCT_MIXED, VCT_MIXED_S64 = 0, 1, 2
+VCT_OUT_GRAD, VCT_OUT_LAP, VCT_OUT_CROSS, VCT_OUT_HESS, VCT_OUT_PGRAD, VCT_OUT_PHESS = 1, 2, 4, 8, 16, 32
+VCT_OPT_GRAD1 = 256
+VCT_OUT_DEFAULT = VCT_OUT_GRAD | VCT_OUT_LAP | VCT_OUT_CROSS
+VCT_MAX_TERMS = 32
+FLAG_FEW, FLAG_SINGULAR_A, FLAG_SINGULAR_M, FLAG_NONFINITE, FLAG_DUPLICATE = 1, 2, 4, 8, 16
+
+
+class VctError(RuntimeError):
+    def __init__(self, name, status, detail=""):
+        self.status = status
+        super().__init__(f"{name}: {status_string(status)}" + (f" ({detail})" if detail else ""))
+
+
+class vct_term(C.Structure):
+    _fields_ = [("coef", C.c_double), ("bx", C.c_int32), ("by", C.c_int32), ("fx", C.c_double),
+                ("fy", C.c_double)]
+
+
+class vct_map(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("nterms", C.c_int32), ("Hhat", C.c_double), ("H", C.c_double),
+                ("dmin", C.c_double), ("eps", C.c_double), ("terms", C.POINTER(vct_term))]
+
+
+_lib = None
+_vp, _i64, _sz, _dp = C.c_void_p, C.c_int64, C.c_size_t, C.POINTER(C.c_double)
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                               "(the operators have no CPU fallback)")
+        L = C.CDLL(LIB_PATH)
+        L.vct_status_string.restype = C.c_char_p
+        L.vct_status_string.argtypes = [C.c_int]
+        L.vct_last_error.restype = C.c_char_p
+        L.vct_last_error.argtypes = []
+        L.vct_grid_dims.restype = _i64
+        L.vct_grid_dims.argtypes = [C.c_int, _dp, _dp, C.c_double, C.POINTER(_i64)]
+        L.vct_n_out.restype = C.c_int
+        L.vct_n_out.argtypes = [C.c_int, C.c_uint32]
+        L.vct_state_stride.restype = C.c_int
+        L.vct_state_stride.argtypes = [C.c_int, C.c_uint32]
+        L.vct_build_cells_workspace_size.restype = _sz
+        L.vct_build_cells_workspace_size.argtypes = [C.c_int, _i64, _i64]
+        L.vct_build_cells.restype = C.c_int
+        L.vct_build_cells.argtypes = [C.c_int, _i64, _vp, _dp, _dp, C.c_double, _vp, _vp, _vp, _i64, _vp, _sz,
+                                      _vp]
+        L.vct_gather_sorted.restype = C.c_int
+        L.vct_gather_sorted.argtypes = [_i64, C.c_int, _vp, _vp, _vp, _vp]
+        L.vct_scatter_sorted.restype = C.c_int
+        L.vct_scatter_sorted.argtypes = [_i64, C.c_int, _vp, _vp, _vp, _vp]
+        L.vct_neighbors_workspace_size.restype = _sz
+        L.vct_neighbors_workspace_size.argtypes = [_i64]
+        L.vct_neighbors.restype = C.c_int
+        L.vct_neighbors.argtypes = [C.c_int, _i64, _vp, _dp, _dp, C.c_double, _vp, _i64, _vp, _vp, _i64,
+                                    C.POINTER(_i64), C.c_int, _vp, _sz, _vp]
+        L.vct_moments_workspace_size.restype = _sz
+        L.vct_moments_workspace_size.argtypes = [C.c_int, _i64]
+        L.vct_moments.restype = C.c_int
+        L.vct_moments.argtypes = [C.c_int, _i64, _vp, _vp, _vp, _vp, C.c_int, C.c_double, C.POINTER(vct_map),
+                                  C.c_uint32, _vp, _vp, _vp, C.POINTER(_i64), _vp, _sz, _vp]
+        L.vct_apply_ops.restype = C.c_int
+        L.vct_apply_ops.argtypes = [C.c_int, _i64, C.c_int, _vp, _vp, _vp, _vp, _vp, C.c_int, C.c_double, _vp,
+                                    C.c_uint32, C.c_int, _vp, _vp]
+        L.vct_adjoint_workspace_size.restype = _sz
+        L.vct_adjoint_workspace_size.argtypes = [C.c_int, _i64, C.c_int]
+        L.vct_apply_ops_adjoint.restype = C.c_int
+        L.vct_apply_ops_adjoint.argtypes = [C.c_int, _i64, _vp, _vp, _vp, _vp, C.c_int, C.c_double, _vp,
+                                            C.c_uint32, C.POINTER(vct_map), _vp, _vp, _vp, _vp, _vp, _sz, _vp]
+        _lib = L
+    return _lib
+
+
+def status_string(st):
+    return lib().vct_status_string(int(st)).decode()
+
+
+def _check(name, st):
+    if st < 0:
+        detail = lib().vct_last_error().decode() if st == VCT_E_HIP else ""
+        raise VctError(name, st, detail)
+    return st
+
+
+def _p(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _d3(v):
+    a = (C.c_double * 3)()
+    for k, x in enumerate(list(v)[:3]):
+        a[k] = float(x)
+    return a
+
+
+def make_map(mapspec):
+    """vct_map (plus the term array it points to) from an inputs.MapSpec."""
+    terms = mapspec.as_array()
+    nt = terms.shape[0]
+    if nt > VCT_MAX_TERMS:
+        raise ValueError(f"at most {VCT_MAX_TERMS} bathymetry terms")
+    arr = (vct_term * max(nt, 1))()
+    for t in range(nt):
+        arr[t] = vct_term(float(terms[t, 0]), int(terms[t, 1]), int(terms[t, 3]), float(terms[t, 2]),
+                          float(terms[t, 4]))
+    m = vct_map(int(mapspec.kind), nt, float(mapspec.Hhat), float(mapspec.H), float(mapspec.dmin),
+                float(mapspec.eps), C.cast(arr, C.POINTER(vct_term)))
+    m._keep = arr
+    return m
+
+
+# ---------------------------------------------------------------- thin wrappers
+
+def vct_grid_dims(dim, lo, hi, R):
+    dims = (_i64 * 3)()
+    nc = lib().vct_grid_dims(dim, _d3(lo), _d3(hi), float(R), dims)
+    _check("vct_grid_dims", nc if nc < 0 else 0)
+    return int(nc), tuple(dims)
+
+
+def vct_n_out(dim, mask):
+    return lib().vct_n_out(dim, mask)
+
+
+def vct_state_stride(dim, mask):
+    return lib().vct_state_stride(dim, mask)
+
+
+def vct_build_cells(dim, n, pos, lo, hi, R, perm, pos_sorted, cell_start, ncell, ws, stream=None):
+    return _check("vct_build_cells", lib().vct_build_cells(
+        dim, n, _p(pos), _d3(lo), _d3(hi), float(R), _p(perm), _p(pos_sorted), _p(cell_start), ncell, _p(ws),
+        0 if ws is None else ws.numel() * ws.element_size(), _stream(stream)))
+
+
+def vct_gather_sorted(n, ncomp, perm, src, dst, stream=None):
+    return _check("vct_gather_sorted", lib().vct_gather_sorted(n, ncomp, _p(perm), _p(src), _p(dst),
+                                                                _stream(stream)))
+
+
+def vct_scatter_sorted(n, ncomp, perm, src, dst, stream=None):
+    return _check("vct_scatter_sorted", lib().vct_scatter_sorted(n, ncomp, _p(perm), _p(src), _p(dst),
+                                                                  _stream(stream)))
+
+
+def vct_neighbors(dim, n, pos_sorted, lo, hi, R, cell_start, ncell, row_ptr, col, col_cap, reuse, ws,
+                  stream=None):
+    nnz = _i64(0)
+    st = lib().vct_neighbors(dim, n, _p(pos_sorted), _d3(lo), _d3(hi), float(R), _p(cell_start), ncell,
+                             _p(row_ptr), _p(col), int(col_cap), C.byref(nnz), int(reuse), _p(ws),
+                             0 if ws is None else ws.numel() * ws.element_size(), _stream(stream))
+    if st == VCT_E_CAPACITY:
+        return st, nnz.value
+    _check("vct_neighbors", st)
+    return st, nnz.value
+
+
+def vct_moments(dim, n, pos_sorted, vol_sorted, row_ptr, col, kernel, R, cmap, mask, state64, state32, flags,
+                count_flagged, ws, stream=None):
+    cnt = _i64(0)
+    st = lib().vct_moments(dim, n, _p(pos_sorted), _p(vol_sorted), _p(row_ptr), _p(col), kernel, float(R),
+                           C.byref(cmap), mask, _p(state64), _p(state32), _p(flags),
+                           C.byref(cnt) if count_flagged else None, _p(ws),
+                           0 if ws is None else ws.numel() * ws.element_size(), _stream(stream))
+    _check("vct_moments", st)
+    return st, cnt.value
+
+
+def vct_apply_ops(dim, n, nf, phi_sorted, pos_sorted, vol_sorted, row_ptr, col, kernel, R, state, mask,
+                  precision, out, stream=None):
+    return _check("vct_apply_ops", lib().vct_apply_ops(
+        dim, n, nf, _p(phi_sorted), _p(pos_sorted), _p(vol_sorted), _p(row_ptr), _p(col), kernel, float(R),
+        _p(state), mask, precision, _p(out), _stream(stream)))
+
+
+def vct_apply_ops_adjoint(dim, n, pos_sorted, vol_sorted, row_ptr, col, kernel, R, state64, mask, cmap,
+                          phi_sorted, u, dphi, dtheta, ws, stream=None):
+    return _check("vct_apply_ops_adjoint", lib().vct_apply_ops_adjoint(
+        dim, n, _p(pos_sorted), _p(vol_sorted), _p(row_ptr), _p(col), kernel, float(R), _p(state64), mask,
+        C.byref(cmap), _p(phi_sorted), _p(u), _p(dphi), _p(dtheta), _p(ws),
+        0 if ws is None else ws.numel() * ws.element_size(), _stream(stream)))
+
+
+# ---------------------------------------------------------------- orchestration
+
+def _bytes(nbytes, device):
+    import torch
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+class Geometry:
+    """One particle set on the GPU: cell sort, neighbour lists, per-particle
+    state.  Positions are projected coordinates (dim, n) in the caller's order;
+    `perm` maps sorted -> original."""
+
+    def __init__(self, pos, vol, lo, hi, R, kernel=VCT_KERNEL_WENDLAND_C2, device="cuda"):
+        import torch
+        pos = torch.as_tensor(pos, dtype=torch.float64, device=device).contiguous()
+        vol = torch.as_tensor(vol, dtype=torch.float64, device=device).contiguous()
+        self.dim, self.n = int(pos.shape[0]), int(pos.shape[1])
+        self.lo, self.hi, self.R, self.kernel, self.device = tuple(lo), tuple(hi), float(R), int(kernel), device
+        self.ncell, self.dims = vct_grid_dims(self.dim, lo, hi, R)
+        n = self.n
+        self.perm = torch.empty(max(n, 1), dtype=torch.int32, device=device)
+        self.pos = torch.empty((self.dim, max(n, 1)), dtype=torch.float64, device=device)
+        self.cell_start = torch.empty(self.ncell + 1, dtype=torch.int64, device=device)
+        ws = _bytes(lib().vct_build_cells_workspace_size(self.dim, n, self.ncell), device)
+        vct_build_cells(self.dim, n, pos, lo, hi, R, self.perm, self.pos, self.cell_start, self.ncell, ws)
+        self.vol = torch.empty(max(n, 1), dtype=torch.float64, device=device)
+        if n:
+            vct_gather_sorted(n, 1, self.perm, vol, self.vol)
+        self.row_ptr = torch.empty(n + 1, dtype=torch.int64, device=device)
+        self._nws = _bytes(lib().vct_neighbors_workspace_size(n), device)
+        _, nnz = vct_neighbors(self.dim, n, self.pos, lo, hi, R, self.cell_start, self.ncell, self.row_ptr,
+                               None, 0, 0, self._nws)
+        self.nnz = nnz
+        self.col = torch.empty(max(nnz, 1), dtype=torch.int32, device=device)
+        vct_neighbors(self.dim, n, self.pos, lo, hi, R, self.cell_start, self.ncell, self.row_ptr, self.col,
+                      self.col.numel(), 1, self._nws)
+        self.state64 = self.state32 = self.flags = None
+        self.mask = None
+
+    def sorted_field(self, phi):
+        """(nf, n) field in the caller's order -> sorted order (device)."""
+        import torch
+        phi = torch.as_tensor(phi, dtype=torch.float64, device=self.device)
+        phi = phi.reshape(-1, self.n).contiguous()
+        out = torch.empty_like(phi)
+        if self.n:
+            vct_gather_sorted(self.n, phi.shape[0], self.perm, phi, out)
+        return out
+
+    def unsort(self, x):
+        """Rows over sorted particles -> caller's order; x is (..., n, k) or (n,)."""
+        import torch
+        idx = self.perm.long()[: self.n]
+        out = torch.empty_like(x)
+        if x.dim() == 1:
+            out[idx] = x
+        else:
+            out[..., idx, :] = x
+        return out
+
+    def moments(self, mapspec, mask=VCT_OUT_DEFAULT, fp32_copy=False, count_flagged=True):
+        import torch
+        n, dim = self.n, self.dim
+        stride = vct_state_stride(dim, mask)
+        self.cmap = make_map(mapspec)
+        self.mask = mask
+        self.state64 = torch.empty((stride, max(n, 1)), dtype=torch.float64, device=self.device)
+        self.state32 = torch.empty((stride, max(n, 1)), dtype=torch.float32, device=self.device) if fp32_copy else None
+        self.flags = torch.empty(max(n, 1), dtype=torch.uint8, device=self.device)
+        ws = _bytes(lib().vct_moments_workspace_size(dim, n), self.device)
+        st, nflag = vct_moments(dim, n, self.pos, self.vol, self.row_ptr, self.col, self.kernel, self.R, self.cmap,
+                                mask, self.state64, self.state32, self.flags, count_flagged, ws)
+        self.n_flagged = nflag
+        return st
+
+    def apply(self, phi_sorted, precision=VCT_FP64, out=None):
+        import torch
+        nf = int(phi_sorted.shape[0])
+        nout = vct_n_out(self.dim, self.mask)
+        if out is None:
+            out = torch.empty((nf, max(self.n, 1), nout), dtype=torch.float64, device=self.device)
+        state = self.state32 if precision == VCT_MIXED else self.state64
+        if state is None:
+            raise ValueError("VCT_MIXED needs moments(..., fp32_copy=True)")
+        vct_apply_ops(self.dim, self.n, nf, phi_sorted, self.pos, self.vol, self.row_ptr, self.col, self.kernel,
+                      self.R, state, self.mask, precision, out)
+        return out
+
+    def adjoint(self, u_sorted, phi_sorted=None, want_dtheta=True):
+        import torch
+        nt = self.cmap.nterms
+        dphi = torch.empty(max(self.n, 1), dtype=torch.float64, device=self.device)
+        dth = torch.empty(max(nt, 1), dtype=torch.float64, device=self.device) if want_dtheta else None
+        ws = _bytes(lib().vct_adjoint_workspace_size(self.dim, self.n, nt), self.device)
+        vct_apply_ops_adjoint(self.dim, self.n, self.pos, self.vol, self.row_ptr, self.col, self.kernel, self.R,
+                              self.state64, self.mask, self.cmap, phi_sorted, u_sorted, dphi, dth, ws)
+        return dphi[: self.n], (dth[:nt] if dth is not None else None)
+
+    def csr_original(self):
+        """Neighbour lists in original indices, rows in original order, columns
+        ascending (host numpy) -- for comparisons."""
+        perm = self.perm[: self.n].cpu().numpy().astype(np.int64)
+        rp = self.row_ptr.cpu().numpy()
+        col = self.col[: self.nnz].cpu().numpy().astype(np.int64)
+        deg = np.diff(rp)
+        orig_row = np.repeat(perm, deg)
+        orig_col = perm[col]
+        order = np.lexsort((orig_col, orig_row))
+        new_rp = np.zeros(self.n + 1, dtype=np.int64)
+        new_rp[1:] = np.cumsum(np.bincount(orig_row, minlength=self.n))
+        return new_rp, orig_col[order]

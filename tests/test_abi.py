@@ -1,0 +1,113 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol the
+public header declares, and rejects bad arguments on the host."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2607_28872_amd import vct
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    text = open(os.path.join(ROOT, "include", "vct.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(vct_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(vct.LIB_PATH):
+        pytest.fail("libvct.so is not built (run __graft_entry__.build())")
+    return vct.lib()
+
+
+def test_exports_every_declared_symbol(L):
+    syms = _declared_symbols()
+    assert len(syms) >= 14
+    for s in syms:
+        assert hasattr(L, s), s
+
+
+def test_status_strings(L):
+    for st in (0, 1, -1, -2, -3, -4, -5):
+        assert vct.status_string(st).startswith("VCT_")
+    assert vct.status_string(99) == "unknown status"
+
+
+def test_layout_queries(L):
+    assert vct.vct_n_out(3, vct.VCT_OUT_DEFAULT) == 7
+    assert vct.vct_n_out(2, vct.VCT_OUT_DEFAULT) == 4
+    assert vct.vct_state_stride(3, vct.VCT_OUT_DEFAULT) == 6 + 7 * (9 + 3)
+    assert vct.vct_state_stride(2, vct.VCT_OUT_DEFAULT) == 3 + 4 * (5 + 2)
+    full = 63
+    assert vct.vct_n_out(3, full) == 3 + 1 + 3 + 6 + 3 + 6
+    assert vct.vct_n_out(3, 0) == 0 and vct.vct_n_out(4, 1) == 0
+    assert vct.vct_n_out(3, 1 << 12) == 0
+
+
+def test_grid_dims(L):
+    nc, dims = vct.vct_grid_dims(3, (0, 0, 0), (1, 1, 0.125), 3 / 256)
+    assert dims == (85, 85, 10) and nc == 85 * 85 * 10
+    nc, dims = vct.vct_grid_dims(2, (0, 0), (1, 0.25), 3 / 2048)
+    assert dims[2] == 1 and nc == dims[0] * dims[1]
+    # cell size never below R even when the extent is an exact multiple of R
+    nc, dims = vct.vct_grid_dims(2, (0, 0), (1, 1), 0.25)
+    assert dims[:2] == (3, 3)
+    with pytest.raises(vct.VctError):
+        vct.vct_grid_dims(3, (0, 0, 0), (1, 1, 1), 0.0)
+    with pytest.raises(vct.VctError):
+        vct.vct_grid_dims(3, (0, 0, 0), (0, 1, 1), 0.1)
+
+
+def _dp3(v):
+    a = (C.c_double * 3)(*v)
+    return a
+
+
+def test_argument_errors_are_caught_on_the_host(L):
+    lo, hi = _dp3((0, 0, 0)), _dp3((1, 1, 1))
+    E = vct.VCT_E_ARG
+    assert L.vct_build_cells(4, 10, None, lo, hi, 0.1, None, None, None, 1000, None, 0, None) == E
+    assert L.vct_build_cells(3, -1, None, lo, hi, 0.1, None, None, None, 1000, None, 0, None) == E
+    assert L.vct_build_cells(3, 10, None, lo, hi, 0.1, None, None, None, 999, None, 0, None) == E  # wrong ncell
+    nnz = C.c_int64(0)
+    assert L.vct_neighbors(3, 10, None, lo, hi, 0.1, None, 1000, None, None, 0, C.byref(nnz), 0, None, 0,
+                           None) == E
+    m = vct.make_map(__import__("paper_2607_28872_amd.inputs", fromlist=["MapSpec"]).MapSpec())
+    assert L.vct_moments(3, 10, None, None, None, None, 0, 0.1, C.byref(m), 0, None, None, None, None, None, 0,
+                         None) == E              # empty output mask
+    assert L.vct_moments(3, 10, None, None, None, None, 7, 0.1, C.byref(m), 3, None, None, None, None, None, 0,
+                         None) == E              # unknown kernel
+    bad = vct.vct_map(9, 0, 1.0, 1.0, 0.0, 0.0, None)
+    assert L.vct_moments(3, 10, None, None, None, None, 0, 0.1, C.byref(bad), 3, None, None, None, None, None,
+                         0, None) == E           # unknown map kind
+    sig = vct.vct_map(4, 0, -1.0, 0.0, 0.0, 0.0, None)
+    assert L.vct_moments(3, 10, None, None, None, None, 0, 0.1, C.byref(sig), 3, None, None, None, None, None,
+                         0, None) == E           # sigma with Hhat <= 0
+    assert L.vct_apply_ops(3, 10, 0, None, None, None, None, None, 0, 0.1, None, 3, 0, None, None) == E  # nf
+    assert L.vct_apply_ops(3, 10, 1, None, None, None, None, None, 0, 0.1, None, 3, 5, None, None) == E  # prec
+    assert L.vct_apply_ops(3, 10, 1, None, None, None, None, None, 0, 0.1, None, 3, 0, None, None) == E  # nulls
+    # adjoint needs LAP | PGRAD | PHESS rows in the state
+    assert L.vct_apply_ops_adjoint(3, 10, None, None, None, None, 0, 0.1, None, vct.VCT_OUT_DEFAULT, C.byref(m),
+                                   None, None, None, None, None, 0, None) == E
+
+
+def test_workspace_errors(L):
+    # valid arguments but no workspace: rejected before any launch
+    lo, hi = _dp3((0, 0, 0)), _dp3((1, 1, 1))
+    nc, _ = vct.vct_grid_dims(3, (0, 0, 0), (1, 1, 1), 0.25)
+    assert L.vct_build_cells(3, 0, None, lo, hi, 0.25, None, None, C.c_void_p(16), nc, None, 0,
+                             None) == vct.VCT_E_WORKSPACE
+    assert L.vct_build_cells_workspace_size(3, 100, nc) > 100 * 4
+    assert L.vct_moments_workspace_size(3, 100) >= 100 * 41 * 8
+    assert L.vct_adjoint_workspace_size(3, 100, 16) >= 100 * 6 * 8
+
+
+def test_binding_fails_loudly_without_library(monkeypatch):
+    monkeypatch.setattr(vct, "_lib", None)
+    monkeypatch.setattr(vct, "LIB_PATH", "/nonexistent/libvct.so")
+    with pytest.raises(RuntimeError, match="not built"):
+        vct.lib()

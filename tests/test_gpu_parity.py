@@ -1,0 +1,183 @@
+"""GPU parity of the HIP path against the CPU oracle, on the same seeded inputs.
+
+Bars (per output row, normwise: max|gpu - oracle| / max|oracle|):
+  * neighbour lists: bit-exact (as sets in original indices, ascending);
+  * FP64 path: FP64_TOL (see the design doc for the derivation from conditioning);
+  * mixed path: gradient 1e-5, Laplacian / cross / Hessian 1e-4 relative to
+    the largest reference value of that output.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2607_28872_amd import inputs as I
+from paper_2607_28872_amd import vct
+
+from _parity import ALL_OUT, normwise, oracle_rows, row_names
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-12
+DEV = "cuda:0"
+
+
+def _geom(w, kernel=None, R=None):
+    return vct.Geometry(w.pos, w.vol, w.lo, w.hi, R or w.R, w.kernel if kernel is None else kernel, device=DEV)
+
+
+def _gpu_out(g, phi, precision):
+    out = g.apply(g.sorted_field(phi), precision)[:, : g.n]
+    return g.unsort(out).cpu().numpy()
+
+
+FAMILIES = ["bf2d", "bfe2d", "sigma3d"]
+
+
+@pytest.mark.parametrize("family", ["c0"] + FAMILIES)
+def test_neighbor_lists_bit_exact(family):
+    w = I.config("c0") if family == "c0" else I.small(family)
+    g = _geom(w)
+    rp, col = g.csr_original()
+    orp, ocol = O.neighbors(w.pos, w.R, brute=(family == "c0"))
+    assert np.array_equal(rp, orp)
+    assert np.array_equal(col, ocol)
+
+
+@pytest.mark.parametrize("family", FAMILIES)
+@pytest.mark.parametrize("kernel", [I.KERNEL_WENDLAND_C2, I.KERNEL_CUBIC_SPLINE])
+def test_fp64_parity_all_outputs(family, kernel):
+    w = I.small(family)
+    R = w.R if kernel == I.KERNEL_WENDLAND_C2 else 2.4 * w.dx
+    g = _geom(w, kernel, R)
+    st = g.moments(w.mapspec, ALL_OUT)
+    assert st == vct.VCT_OK and g.n_flagged == 0
+    got = _gpu_out(g, w.phi, vct.VCT_FP64)
+    rec, fl = O.sph2(w.pos, w.vol, w.phi, kernel, R, w.mapspec)
+    assert not fl.any()
+    ref = oracle_rows(rec, w.dim, ALL_OUT)
+    err = normwise(got, ref)
+    names = row_names(w.dim, ALL_OUT)
+    print(f"\n{family} k={kernel} FP64 normwise errors:",
+          {f"f{f}.{nm}": float(f"{err[f, o]:.2e}") for f in range(err.shape[0]) for o, nm in enumerate(names)})
+    assert err.max() <= FP64_TOL
+
+
+@pytest.mark.parametrize("family", FAMILIES)
+def test_first_order_gradient_option(family):
+    w = I.small(family)
+    g = _geom(w)
+    mask = vct.VCT_OUT_DEFAULT | vct.VCT_OUT_PGRAD | vct.VCT_OPT_GRAD1
+    g.moments(w.mapspec, mask)
+    got = _gpu_out(g, w.phi, vct.VCT_FP64)
+    rec, _ = O.sph2(w.pos, w.vol, w.phi, w.kernel, w.R, w.mapspec, grad_order=1)
+    assert normwise(got, oracle_rows(rec, w.dim, mask)).max() <= FP64_TOL
+
+
+@pytest.mark.parametrize("family", FAMILIES)
+@pytest.mark.parametrize("precision", [vct.VCT_MIXED, vct.VCT_MIXED_S64])
+def test_mixed_parity(family, precision):
+    w = I.small(family)
+    g = _geom(w)
+    mask = vct.VCT_OUT_DEFAULT | vct.VCT_OUT_HESS
+    g.moments(w.mapspec, mask, fp32_copy=True)
+    got = _gpu_out(g, w.phi, precision)
+    rec, _ = O.sph2(w.pos, w.vol, w.phi, w.kernel, w.R, w.mapspec)
+    ref = oracle_rows(rec, w.dim, mask)
+    err = normwise(got, ref)
+    names = row_names(w.dim, mask)
+    print(f"\n{family} p={precision} mixed errors:",
+          {f"f{f}.{nm}": float(f"{err[f, o]:.2e}") for f in range(err.shape[0]) for o, nm in enumerate(names)})
+    d = w.dim
+    assert err[:, :d].max() <= 1e-5
+    assert err[:, d:].max() <= 1e-4
+
+
+@pytest.mark.parametrize("family", FAMILIES)
+def test_projected_quadratics_exact_on_gpu(family):
+    w = I.small(family)
+    g = _geom(w)
+    mask = vct.VCT_OUT_PGRAD | vct.VCT_OUT_PHESS
+    g.moments(w.mapspec, mask)
+    c = w.extra["pquad"]
+    phi = I.eval_quadratic(c, w.pos)[None]
+    got = _gpu_out(g, phi, vct.VCT_FP64)[0]
+    d = w.dim
+    if d == 2:
+        x, z = w.pos
+        ex = np.stack([c[1] + 2 * c[3] * x + c[4] * z, c[2] + c[4] * x + 2 * c[5] * z,
+                       np.full_like(x, 2 * c[3]), np.full_like(x, 2 * c[5]), np.full_like(x, c[4])], 1)
+    else:
+        x, y, z = w.pos
+        ex = np.stack([c[1] + 2 * c[4] * x + c[5] * y + c[6] * z, c[2] + c[5] * x + 2 * c[7] * y + c[8] * z,
+                       c[3] + c[6] * x + c[8] * y + 2 * c[9] * z] + [np.full_like(x, v) for v in
+                      (2 * c[4], 2 * c[7], 2 * c[9], c[5], c[6], c[8])], 1)
+    assert np.abs(got - ex).max() <= 1e-8 * np.abs(ex).max()
+
+
+def test_determinism_bitwise():
+    w = I.small("sigma3d")
+    outs = []
+    for _ in range(2):
+        g = _geom(w)
+        g.moments(w.mapspec, ALL_OUT, fp32_copy=True)
+        phi = g.sorted_field(w.phi)
+        outs.append((g.col.cpu().numpy(), g.state64.cpu().numpy(), g.apply(phi, vct.VCT_FP64).cpu().numpy(),
+                     g.apply(phi, vct.VCT_MIXED).cpu().numpy()))
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
+
+
+def test_adjoint_against_oracle():
+    w = I.small("sigma3d-adj")
+    mask = vct.VCT_OUT_LAP | vct.VCT_OUT_PGRAD | vct.VCT_OUT_PHESS
+    g = _geom(w)
+    g.moments(w.mapspec, mask)
+    phi = g.sorted_field(w.phi[0])
+    lap = g.unsort(g.apply(phi, vct.VCT_FP64)[0, : g.n, 0]).cpu().numpy()
+    u = 2.0 * (lap - w.extra["target"])
+    dphi, dth = g.adjoint(g.sorted_field(u)[0], phi[0])
+    dphi = g.unsort(dphi).cpu().numpy()
+    csr = O.neighbors(w.pos, w.R)
+    ref = O.adjoint_dphi(w.pos, w.vol, w.kernel, w.R, w.mapspec, u, csr=csr)
+    assert np.abs(dphi - ref).max() <= 1e-10 * np.abs(ref).max()
+    rec, _ = O.sph2(w.pos, w.vol, w.phi[0], w.kernel, w.R, w.mapspec, csr=csr)
+    nt = w.mapspec.as_array().shape[0]
+    dref = O.dtheta(w.pos, w.mapspec, u, rec[:, 0, O.I_DHAT], np.arange(nt))
+    dth = dth.cpu().numpy()
+    assert np.abs(dth - dref).max() <= 1e-9 * np.abs(dref).max()
+
+
+def test_degenerate_particles_flagged():
+    # an isolated particle (outside the box: clamped into a boundary cell, no
+    # neighbours) and an exact duplicate of particle 0
+    w = I.small("bf2d")
+    pos = np.concatenate([w.pos, [[0.5], [10.0]], w.pos[:, :1]], axis=1)
+    vol = np.concatenate([w.vol, [w.vol[0], w.vol[0]]])
+    g = vct.Geometry(pos, vol, w.lo, w.hi, w.R, w.kernel, device=DEV)
+    st = g.moments(w.mapspec, vct.VCT_OUT_DEFAULT)
+    assert st == vct.VCT_W_FLAGGED
+    flags = g.unsort(g.flags[: g.n]).cpu().numpy()
+    assert flags[w.n] & vct.FLAG_FEW
+    assert flags[w.n + 1] & vct.FLAG_DUPLICATE and flags[0] & vct.FLAG_DUPLICATE
+    out = _gpu_out(g, np.zeros((1, g.n)), vct.VCT_FP64)
+    assert np.isnan(out[0, w.n]).all() and np.isnan(out[0, w.n + 1]).all()
+    ok = flags == 0
+    assert ok.sum() > w.n - 40 and np.isfinite(out[0, ok]).all()
+
+
+def test_nonfinite_position_rejected():
+    w = I.small("bf2d")
+    pos = w.pos.copy()
+    pos[0, 3] = np.nan
+    with pytest.raises(vct.VctError) as e:
+        vct.Geometry(pos, w.vol, w.lo, w.hi, w.R, w.kernel, device=DEV)
+    assert e.value.status == vct.VCT_E_NONFINITE
+
+
+def test_empty_set():
+    g = vct.Geometry(np.zeros((3, 0)), np.zeros(0), (0, 0, 0), (1, 1, 1), 0.1, device=DEV)
+    assert g.nnz == 0
+    assert g.moments(I.MapSpec(), vct.VCT_OUT_DEFAULT) == vct.VCT_OK
+    out = g.apply(torch.zeros((1, 1), dtype=torch.float64, device=DEV))
+    assert out.shape[0] == 1
