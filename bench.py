@@ -1,0 +1,320 @@
+"""Benchmark of the VCT-SPH(2) operator path on one MI355X.
+
+One step = one pass of the whole hot path over the 3-D sigma-SPH particle set
+(512 x 512 x 32 = 8,388,608 particles, sloped-beach bathymetry, 5% jitter):
+  cell sort -> neighbour lists (count + fill) -> FP64 moments + solve (with the
+  FP32 copy of the state) -> mixed-precision operator apply (grad + lap +
+  cross) -> FP64 moments recomputed for the adjoint -> adjoint (d/dphi and
+  d/d bathymetry coefficients).
+Inputs are resident in HBM before the timed region.  `value` is particle-
+operator evaluations (particles x fields) per second of the whole step.
+
+The JSON line also carries per-stage times, the apply-only rates of the FP64
+and mixed paths, the roofline of the dominant kernel and of the apply kernel
+(algorithmic bytes or flops per launch / launch time), and the
+CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+
+# Algorithmic floating-point operations per neighbour pair (multiply-add = 2)
+# and per particle of the FP64 moments (both sweeps and the solve); counted
+# from the formulation in the design doc.
+MOMENT_FLOP_PER_PAIR_3D = 2 * (3 + 3 + 3 + 1 + 3 + 6 + 10) + 2 * (3 + 3 + 3 + 1 + 3 + 7 + 10 + 15 + 15)
+MOMENT_FLOP_SOLVE_3D = 3200
+ADJOINT_FLOP_PER_PAIR_3D = 2 * (3 + 3 + 6 + 1 + 6 + 6 + 2 + 3 + 6 + 2 + 3 + 6 + 1) + 2 * (3 + 3 + 6 + 6 + 2 + 9 + 1)
+NB_FLOP_PER_CANDIDATE = 9            # FP32 offset difference, squared distance, two compares
+FP32_PEAK_TFLOPS = 157.3
+STAGE_KERNELS = {"cells": "k_cell_keys + k_cell_scatter + k_cell_sort + k_gather",
+                 "nb_count": "k_nb_chunk (count)", "nb_fill": "k_nb_chunk (fill)",
+                 "moments": "k_moment_sweeps + k_moment_solve", "moments_adj": "k_moment_sweeps + k_moment_solve",
+                 "apply": "k_apply (mixed)", "adjoint": "k_apply (lap) + k_adjoint_dphi + k_adjoint_xi"}
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=5)
+    p.add_argument("--warmup", type=int, default=2)
+    p.add_argument("--config", default="c3")
+    p.add_argument("--nf", type=int, default=1)
+    p.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    return p.parse_args()
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(os.path.join(ROOT, "paper_2607_28872_amd", "csrc"))):
+        h.update(open(os.path.join(ROOT, "paper_2607_28872_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel_name, launches_bytes):
+    """HBM bytes per launch from committed rocprofv3 counter summaries, or None
+    if absent or taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        d = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_hash") != kernel_hash():
+        return None
+    k = d.get("kernels", {}).get(kernel_name)
+    if not k:
+        return None
+    return (k["fetch_kib"] * d["fetch_scale"] + k["write_kib"] * d["write_scale"]) * 1024.0
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
+              "the multi-GPU sharding is a design note in DESIGN.md, not an implemented path.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2607_28872_amd import inputs as I
+    from paper_2607_28872_amd import vct
+
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    w = I.config(args.config)
+    n, dim = w.n, w.dim
+    nf = args.nf
+    phis = np.concatenate([w.phi] * ((nf + w.phi.shape[0] - 1) // w.phi.shape[0]))[:nf]
+    theta = I.theta0()
+    ms = w.mapspec.with_terms(I.theta_terms(theta))
+    cmap = vct.make_map(ms)
+    target = I.target_field(w.pos, ms.Hhat)
+    L = vct.lib()
+
+    # ---------------------------------------------------------------- resident inputs + buffers
+    pos = torch.as_tensor(w.pos, device=dev).contiguous()
+    vol = torch.as_tensor(w.vol, device=dev).contiguous()
+    phi_in = torch.as_tensor(phis, device=dev).contiguous()
+    g_in = torch.as_tensor(target, device=dev).contiguous()
+    ncell, _ = vct.vct_grid_dims(dim, w.lo, w.hi, w.R)
+    perm = torch.empty(n, dtype=torch.int32, device=dev)
+    pos_s = torch.empty((dim, n), dtype=torch.float64, device=dev)
+    vol_s = torch.empty(n, dtype=torch.float64, device=dev)
+    phi_s = torch.empty((nf, n), dtype=torch.float64, device=dev)
+    g_s = torch.empty(n, dtype=torch.float64, device=dev)
+    cell_start = torch.empty(ncell + 1, dtype=torch.int64, device=dev)
+    row_ptr = torch.empty(n + 1, dtype=torch.int64, device=dev)
+    _, dims = vct.vct_grid_dims(dim, w.lo, w.hi, w.R)
+    ncols = dims[0] * dims[1] if dim == 3 else dims[0]
+    cap = L.vct_chunk_capacity(dim, n, ncell)
+    chunk_off = torch.empty(ncols + 1, dtype=torch.int64, device=dev)
+    chunk_start = torch.empty(cap + 1, dtype=torch.int32, device=dev)
+    chunk_info = torch.empty((cap, 4), dtype=torch.int32, device=dev)
+    ws_cells = torch.empty(L.vct_build_cells_workspace_size(dim, n, ncell), dtype=torch.uint8, device=dev)
+    ws_nb = torch.empty(L.vct_neighbors_workspace_size(n, ncell), dtype=torch.uint8, device=dev)
+    ws_mom = torch.empty(L.vct_moments_workspace_size(dim, n), dtype=torch.uint8, device=dev)
+    nterms = cmap.nterms
+    ws_adj = torch.empty(L.vct_adjoint_workspace_size(dim, n, nterms), dtype=torch.uint8, device=dev)
+    fwd_mask = vct.VCT_OUT_DEFAULT
+    adj_mask = vct.VCT_OUT_LAP | vct.VCT_OUT_PGRAD | vct.VCT_OUT_PHESS
+    n_out = vct.vct_n_out(dim, fwd_mask)
+    stride_f = vct.vct_state_stride(dim, fwd_mask)
+    stride_a = vct.vct_state_stride(dim, adj_mask)
+    st64 = torch.empty((stride_f, n), dtype=torch.float64, device=dev)
+    st32 = torch.empty((stride_f, n), dtype=torch.float32, device=dev)
+    sta = torch.empty((stride_a, n), dtype=torch.float64, device=dev)
+    flags = torch.empty(n, dtype=torch.uint8, device=dev)
+    out = torch.empty((nf, n, n_out), dtype=torch.float64, device=dev)
+    lap = torch.empty((1, n, 1), dtype=torch.float64, device=dev)
+    u = torch.empty(n, dtype=torch.float64, device=dev)
+    dphi = torch.empty(n, dtype=torch.float64, device=dev)
+    dth = torch.empty(nterms, dtype=torch.float64, device=dev)
+
+    # size the column array once (the geometry does not change between steps)
+    vct.vct_build_cells(dim, n, pos, w.lo, w.hi, w.R, perm, pos_s, cell_start, ncell, ws_cells)
+    nl0 = vct.make_nlist(dim, n, ncell, w.lo, w.hi, w.R, cell_start, chunk_off, chunk_start, chunk_info, row_ptr)
+    _, nnz = vct.vct_neighbors(nl0, pos_s, 0, 0, ws_nb)
+    col16 = torch.empty(nnz, dtype=torch.uint16, device=dev)
+    nl = vct.make_nlist(dim, n, ncell, w.lo, w.hi, w.R, cell_start, chunk_off, chunk_start, chunk_info, row_ptr,
+                        None, col16)
+    torch.cuda.synchronize()
+
+    stream = torch.cuda.current_stream()
+    stage_names = ["cells", "nb_count", "nb_fill", "moments", "apply", "moments_adj", "adjoint"]
+
+    def ev():
+        e = torch.cuda.Event(enable_timing=True)
+        e.record(stream)
+        return e
+
+    def step(record):
+        marks = [ev()] if record else None
+
+        def mark():
+            if record:
+                marks.append(ev())
+
+        vct.vct_build_cells(dim, n, pos, w.lo, w.hi, w.R, perm, pos_s, cell_start, ncell, ws_cells)
+        vct.vct_gather_sorted(n, 1, perm, vol, vol_s)
+        vct.vct_gather_sorted(n, nf, perm, phi_in, phi_s)
+        vct.vct_gather_sorted(n, 1, perm, g_in, g_s)
+        mark()
+        vct.vct_neighbors(nl0, pos_s, 0, 0, ws_nb)
+        mark()
+        vct.vct_neighbors(nl, pos_s, nnz, 1, ws_nb)
+        mark()
+        vct.vct_moments(nl, pos_s, vol_s, w.kernel, cmap, fwd_mask, st64, st32, flags, False, ws_mom)
+        mark()
+        vct.vct_apply_ops(nl, nf, phi_s, pos_s, vol_s, w.kernel, st32, fwd_mask, vct.VCT_MIXED, out)
+        mark()
+        # backward of loss = sum (lap f - g)^2 with the state recomputed
+        vct.vct_moments(nl, pos_s, vol_s, w.kernel, cmap, adj_mask, sta, None, flags, False, ws_mom)
+        mark()
+        vct.vct_apply_ops(nl, 1, phi_s, pos_s, vol_s, w.kernel, sta, vct.VCT_OUT_LAP, vct.VCT_FP64, lap)
+        torch.sub(lap.view(n), g_s, out=u)
+        u.mul_(2.0)
+        vct.vct_apply_ops_adjoint(nl, pos_s, vol_s, w.kernel, sta, adj_mask, cmap, phi_s, u, dphi, dth, ws_adj)
+        mark()
+        return marks
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    stage_ms = {k: [] for k in stage_names}
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        marks = step(True)
+        torch.cuda.synchronize()
+        for k, nm in enumerate(stage_names):
+            stage_ms[nm].append(marks[k].elapsed_time(marks[k + 1]))
+    torch.cuda.synchronize()
+    t_step = (time.perf_counter() - t0) / args.steps
+    stage = {k: float(np.mean(v)) for k, v in stage_ms.items()}
+
+    # apply-only rates of both precisions (same launch configuration)
+    def time_apply(prec, state, reps=10):
+        vct.vct_apply_ops(nl, nf, phi_s, pos_s, vol_s, w.kernel, state, fwd_mask, prec, out)
+        torch.cuda.synchronize()
+        e0 = ev()
+        for _ in range(reps):
+            vct.vct_apply_ops(nl, nf, phi_s, pos_s, vol_s, w.kernel, state, fwd_mask, prec, out)
+        e1 = ev()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    t_apply_mixed = time_apply(vct.VCT_MIXED, st32)
+    t_apply_fp64 = time_apply(vct.VCT_FP64, st64)
+
+    deg = nnz / n
+    # algorithmic bytes of one apply launch: row_ptr, 16-bit columns, one read
+    # of every particle's position/volume/field, the state, the outputs
+    def apply_bytes(state_elem):
+        per_particle = 8 + 2 * deg + (dim * 8 + 8 + 8 * nf) + stride_f * state_elem + 8 * n_out * nf
+        return per_particle * n
+
+    b_mixed, b_fp64 = apply_bytes(4), apply_bytes(8)
+    apply_gbs = b_mixed / (t_apply_mixed * 1e-3) / 1e9
+    roof_apply = {"kernel": "k_apply (mixed)", "bound": "hbm", "achieved": round(apply_gbs, 1),
+                  "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(apply_gbs / HBM_PEAK_GBS, 4),
+                  "traffic": measured_traffic("k_apply_mixed", b_mixed), "ms": round(t_apply_mixed, 4),
+                  "algorithmic_bytes": int(b_mixed)}
+    # dominant stage of the step and its roofline model
+    pairs = float(nnz)
+    flop_models = {
+        # FP64 flops per neighbour pair (multiply-add counted as 2), see the design doc
+        "moments": pairs * MOMENT_FLOP_PER_PAIR_3D + n * MOMENT_FLOP_SOLVE_3D,
+        "moments_adj": pairs * MOMENT_FLOP_PER_PAIR_3D + n * MOMENT_FLOP_SOLVE_3D,
+        "adjoint": pairs * ADJOINT_FLOP_PER_PAIR_3D,
+        "nb_count": pairs * 0 + n * 27.0 * (n / ncell) * NB_FLOP_PER_CANDIDATE,
+        "nb_fill": pairs * 0 + n * 27.0 * (n / ncell) * NB_FLOP_PER_CANDIDATE,
+    }
+    dom = max(stage, key=stage.get)
+    if dom == "apply":
+        roofline = dict(roof_apply)
+    elif dom in flop_models:
+        ach = flop_models[dom] / (stage[dom] * 1e-3) / 1e12
+        peak = FP32_PEAK_TFLOPS if dom.startswith("nb_") else FP64_PEAK_TFLOPS
+        roofline = {"kernel": STAGE_KERNELS[dom], "bound": "alu", "achieved": round(ach, 3), "peak": peak,
+                    "unit": "TFLOP/s", "frac": round(ach / peak, 4), "traffic": measured_traffic(dom, None),
+                    "ms": round(stage[dom], 4)}
+    else:
+        cells_bytes = n * (dim * 8 * 3 + 4 * 4 + 8 * (2 + nf))
+        ach = cells_bytes / (stage[dom] * 1e-3) / 1e9
+        roofline = {"kernel": STAGE_KERNELS[dom], "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                    "ms": round(stage[dom], 4)}
+    roofline["stage"] = dom
+
+    value = n * nf / t_step
+    res = {
+        "metric": "particle-operator evals/s (grad+lap+cross), mixed vs FP64 GPU; HBM GB/s",
+        "value": value,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t_step * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32-sums/f64-moments",
+        "data": "synthetic",
+        "config": {"workload": f"3-D sigma-SPH sloped beach {w.counts[0]}x{w.counts[1]}x{w.counts[2]} "
+                               f"({n} particles), Wendland C2 R=3dx, 5% jitter, {nf} field(s), mixed apply, "
+                               f"adjoint with recomputed moments",
+                   "particles": n, "fields": nf, "neighbours_per_particle": round(deg, 2),
+                   "parallelism": "single GPU"},
+        "stage_ms": {k: round(v, 4) for k, v in stage.items()},
+        "apply_only": {"mixed_ms": round(t_apply_mixed, 4), "fp64_ms": round(t_apply_fp64, 4),
+                       "mixed_evals_per_s": n * nf / (t_apply_mixed * 1e-3),
+                       "fp64_evals_per_s": n * nf / (t_apply_fp64 * 1e-3),
+                       "speedup_mixed_vs_fp64": round(t_apply_fp64 / t_apply_mixed, 3),
+                       "fp64_alg_GBs": round(b_fp64 / (t_apply_fp64 * 1e-3) / 1e9, 1)},
+        "roofline": roofline,
+        "roofline_apply": roof_apply,
+    }
+
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(w, nf, args.cpu_seconds)
+    print(json.dumps(res), flush=True)
+
+
+def cpu_baseline(w, nf, target_s):
+    """The CPU oracle (neighbour search + SPH(2) operators, FP64, OpenMP) timed
+    on a bounded sample of particles of the same set; reported in evals/s."""
+    import numpy as np
+    import oracle
+
+    oracle.lib()
+    rng = np.random.default_rng(123)
+    phis = np.concatenate([w.phi] * nf)[:nf] if nf > w.phi.shape[0] else w.phi[:nf]
+    size = 2000
+    t = 0.0
+    while True:
+        rows = np.sort(rng.choice(w.n, size=min(size, w.n), replace=False))
+        t0 = time.perf_counter()
+        csr = oracle.neighbors(w.pos, w.R, rows=rows)
+        oracle.sph2(w.pos, w.vol, phis, w.kernel, w.R, w.mapspec, rows=rows, csr=csr)
+        t = time.perf_counter() - t0
+        if t >= target_s / 4 or size >= w.n:
+            break
+        size = int(min(w.n, size * max(2.0, 0.5 * target_s / max(t, 1e-3))))
+    return {"value": size * nf / t, "unit": "evals/s", "cores": oracle.threads(), "kind": "oracle",
+            "sample": f"{size} random particles of the {w.n}-particle set (neighbour grid over all particles "
+                      f"+ SPH(2) at the sampled rows), {t:.1f} s"}
+
+
+if __name__ == "__main__":
+    main()

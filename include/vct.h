@@ -22,8 +22,8 @@
  *   - Per-particle arrays are in the cell-sorted order produced by
  *     vct_build_cells unless stated otherwise; perm maps sorted -> original.
  *   - Layouts: positions SoA [dim][n] (2-D sets use the vertical plane (x, z));
- *     fields [nf][n]; outputs [nf][n][n_out]; CSR row_ptr int64 [n+1], col int32
- *     (sorted indices, ascending within a row); state SoA [stride][n].
+ *     fields [nf][n]; outputs [nf][n][n_out]; state SoA [stride][n];
+ *     neighbour lists in CSR form (vct_nlist).
  *   - Return value: VCT_OK (0); a positive warning (outputs written); or a
  *     negative error, in which case nothing was launched unless stated.
  *     Argument errors are detected on the host before any HIP call.  Nothing
@@ -48,7 +48,8 @@ enum {
     VCT_E_HIP = -2,         /* a HIP runtime call or kernel launch failed */
     VCT_E_CAPACITY = -3,    /* an output array is too small; the required size is reported */
     VCT_E_NONFINITE = -4,   /* a non-finite input position */
-    VCT_E_WORKSPACE = -5    /* workspace missing or smaller than the size query returns */
+    VCT_E_WORKSPACE = -5,   /* workspace missing or smaller than the size query returns */
+    VCT_E_WINDOW = -6       /* a chunk's neighbour window exceeds 65535 particles (16-bit offsets) */
 };
 
 /* ---------------------------------------------------------------- enums */
@@ -179,22 +180,58 @@ int vct_scatter_sorted(int64_t n, int ncomp, const int32_t* perm, const double* 
 
 /* ---------------------------------------------------------------- neighbours */
 
-size_t vct_neighbors_workspace_size(int64_t n);
+/* Neighbour structure of one cell-sorted particle set.  A host struct of
+ * device pointers that the caller allocates; vct_neighbors fills the chunk
+ * table, row_ptr and the columns.
+ *
+ * Chunks: the particles of each background-cell column ((x, y) column in 3-D,
+ * x column in 2-D) are split into runs of at most 64 consecutive sorted
+ * particles.  A chunk's window is the concatenation, in increasing order, of
+ * the sorted-index ranges of the 3^(d-1) columns around its own, restricted
+ * to the z cells the chunk spans plus one on each side; every neighbour of a
+ * chunk's particles lies in it.  Kernels stage the window in LDS.
+ *
+ * Columns of row i are ascending; `col` holds sorted particle indices and
+ * `col16` the same neighbours as offsets into the window of i's chunk.  At
+ * least one of them must be given to vct_neighbors; vct_moments,
+ * vct_apply_ops and vct_apply_ops_adjoint read col16, which must be 16-byte
+ * aligned (VCT_E_ARG otherwise).                                             */
+typedef struct {
+    int32_t dim;            /* 2 or 3 */
+    int32_t reserved;
+    int64_t n;              /* particles */
+    int64_t ncell;          /* cells (vct_grid_dims) */
+    int64_t chunk_cap;      /* capacity of the chunk arrays, >= vct_chunk_capacity() */
+    double lo[3], hi[3];    /* projected box given to vct_build_cells (unused entries ignored) */
+    double R;               /* support radius */
+    const int64_t* cell_start;  /* [ncell + 1], from vct_build_cells */
+    int64_t* chunk_off;     /* [ncols + 1]: first chunk of every column; chunk_off[ncols] = chunks */
+    int32_t* chunk_start;   /* [chunk_cap + 1]: first sorted particle of every chunk */
+    int32_t* chunk_info;    /* [chunk_cap][4]: column, first z cell, last z cell, 0 */
+    int64_t* row_ptr;       /* [n + 1] */
+    int32_t* col;           /* [nnz] or NULL */
+    uint16_t* col16;        /* [nnz] or NULL; 16-byte aligned */
+} vct_nlist;
+
+/* Entries needed in the chunk arrays of a set of n particles on ncell cells. */
+int64_t vct_chunk_capacity(int dim, int64_t n, int64_t ncell);
+
+size_t vct_neighbors_workspace_size(int64_t n, int64_t ncell);
 
 /* Neighbour lists S_i = { j != i : d2(i,j) < R*R } (Eq. SPH_neighbor_set) of
- * the cell-sorted particles, as CSR over sorted indices with ascending columns.
- * d2 is evaluated in FP64 as ((dx*dx + dy*dy) + dz*dz) with dx = x_j - x_i and
- * no fused multiply-add, so lists are reproducible bit for bit.
- * lo, hi, R, cell_start must be those given to vct_build_cells.
- * Protocol: row_ptr [n+1] is always written and *nnz_out (host) receives the
- * total.  If col is NULL the call stops there (VCT_OK).  If col_cap < nnz it
- * returns VCT_E_CAPACITY.  Otherwise col [nnz] is filled.  With
- * reuse_row_ptr != 0 the counts are not recomputed: row_ptr must hold the
- * result of an earlier call on the same inputs.  SYNC (reads nnz).             */
-int vct_neighbors(int dim, int64_t n, const double* pos_sorted, const double* lo, const double* hi,
-                  double R, const int64_t* cell_start, int64_t ncell, int64_t* row_ptr, int32_t* col,
-                  int64_t col_cap, int64_t* nnz_out, int reuse_row_ptr, void* ws, size_t ws_bytes,
-                  void* stream);
+ * the cell-sorted particles pos_sorted (SoA [dim][n]).  d2 is defined in FP64
+ * as ((dx*dx + dy*dy) + dz*dz) with dx = x_j - x_i and no fused multiply-add,
+ * so lists are reproducible bit for bit (a conservative FP32 pre-test decides
+ * the clear cases; the rest use that exact FP64 expression).
+ * Protocol: the chunk table and row_ptr are always written and *nnz_out (host)
+ * receives the total.  If both col and col16 are NULL the call stops there
+ * (VCT_OK).  If col_cap < nnz it returns VCT_E_CAPACITY.  Otherwise the
+ * columns are written.  With reuse_row_ptr != 0 the chunk table and counts are
+ * not recomputed: they must hold the result of an earlier call on the same
+ * inputs.  Returns VCT_E_WINDOW if some window exceeds 65535 particles (col16
+ * cannot address it).  SYNC (reads nnz).                                       */
+int vct_neighbors(vct_nlist* nl, const double* pos_sorted, int64_t col_cap, int64_t* nnz_out, int reuse_row_ptr,
+                  void* ws, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------- moments */
 
@@ -216,10 +253,9 @@ int vct_neighbors(int dim, int64_t n, const double* pos_sorted, const double* lo
  * be NULL.  flags [n] (may be NULL) receives VCT_FLAG_* bits; flagged particles
  * get NaN state rows, hence NaN outputs.  If n_flagged (host) is not NULL the
  * call is SYNC and returns VCT_W_FLAGGED when the count is non-zero.          */
-int vct_moments(int dim, int64_t n, const double* pos_sorted, const double* vol_sorted,
-                const int64_t* row_ptr, const int32_t* col, int kernel, double R,
-                const vct_map* map /* host */, uint32_t out_mask, double* state64, float* state32,
-                uint8_t* flags, int64_t* n_flagged, void* ws, size_t ws_bytes, void* stream);
+int vct_moments(const vct_nlist* nl, const double* pos_sorted, const double* vol_sorted, int kernel,
+                const vct_map* map /* host */, uint32_t out_mask, double* state64, float* state32, uint8_t* flags,
+                int64_t* n_flagged, void* ws, size_t ws_bytes, void* stream);
 
 size_t vct_moments_workspace_size(int dim, int64_t n);
 
@@ -239,10 +275,9 @@ size_t vct_moments_workspace_size(int dim, int64_t n);
  * out [nf][n][n_out] FP64.  In the mixed forms r_ij, phi_ij and psi_ij are
  * formed in FP64 and rounded once to FP32; the pair terms and sums are FP32;
  * the final product with the state is FP32 and stored as FP64.                */
-int vct_apply_ops(int dim, int64_t n, int nf, const double* phi_sorted, const double* pos_sorted,
-                  const double* vol_sorted, const int64_t* row_ptr, const int32_t* col, int kernel,
-                  double R, const void* state, uint32_t out_mask, int precision, double* out,
-                  void* stream);
+int vct_apply_ops(const vct_nlist* nl, int nf, const double* phi_sorted, const double* pos_sorted,
+                  const double* vol_sorted, int kernel, const void* state, uint32_t out_mask, int precision,
+                  double* out, void* stream);
 
 /* ---------------------------------------------------------------- adjoint */
 
@@ -260,11 +295,10 @@ size_t vct_adjoint_workspace_size(int dim, int64_t n, int nterms);
  * VCT_OUT_LAP | VCT_OUT_PGRAD | VCT_OUT_PHESS (pass the same mask).
  * phi_sorted [n] is needed only when dtheta is not NULL.  dphi [n] and
  * dtheta [map->nterms] are device outputs; either may be NULL.                 */
-int vct_apply_ops_adjoint(int dim, int64_t n, const double* pos_sorted, const double* vol_sorted,
-                          const int64_t* row_ptr, const int32_t* col, int kernel, double R,
+int vct_apply_ops_adjoint(const vct_nlist* nl, const double* pos_sorted, const double* vol_sorted, int kernel,
                           const double* state64, uint32_t out_mask, const vct_map* map /* host */,
-                          const double* phi_sorted, const double* u, double* dphi, double* dtheta,
-                          void* ws, size_t ws_bytes, void* stream);
+                          const double* phi_sorted, const double* u, double* dphi, double* dtheta, void* ws,
+                          size_t ws_bytes, void* stream);
 
 #ifdef __cplusplus
 }

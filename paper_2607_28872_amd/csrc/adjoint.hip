@@ -17,119 +17,237 @@
 // fixed order.
 #include "common.h"
 #include "map_dev.h"
-#include "pairs.h"
+#include "tiles.h"
 
 namespace vct {
 
-template <int D, int G, int KERNEL>
-__global__ __launch_bounds__(256) void k_adjoint_dphi(int64_t n, const double* __restrict__ pos,
-                                                      const double* __restrict__ vol,
-                                                      const int64_t* __restrict__ row_ptr,
-                                                      const int32_t* __restrict__ col, double invR,
-                                                      const double* __restrict__ state, int lap_row,
-                                                      const double* __restrict__ u, double* __restrict__ dphi) {
+int nlist_check(const vct_nlist* nl, Grid& g);
+
+constexpr int kALanes = 4;                     // lanes per particle
+constexpr int kAThreads = kChunk * kALanes;    // one chunk per work-group
+constexpr int kAWin = 1280;                    // LDS window capacity (records)
+constexpr int kCoef = 16;                      // packed per-particle adjoint record
+
+// Per particle: [L~ (nL), P_lap (d + m), u], one 128-byte record, so the
+// gather of a neighbour's coefficients touches a single cache line.
+template <int D>
+__global__ void k_adjoint_pack(int64_t n, const double* __restrict__ state, int lap_row,
+                               const double* __restrict__ u, double* __restrict__ coef) {
+    using Dm = Dims<D>;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double* c = coef + i * kCoef;
+#pragma unroll
+    for (int p = 0; p < Dm::nL; ++p) c[p] = state[(int64_t)p * n + i];
+#pragma unroll
+    for (int k = 0; k < Dm::nk; ++k) c[Dm::nL + k] = state[(int64_t)(Dm::nL + lap_row * Dm::nk + k) * n + i];
+    c[Dm::nL + Dm::nk] = u[i];
+}
+
+struct AdjArgs {
+    int64_t n;
+    double invR;
+    Grid g;
+    const double* pos;
+    const double* vol;
+    const double* phi;
+    const double* state;
+    const double* u;
+    const double* coef;
+    const int64_t* row_ptr;
+    const uint16_t* col16;
+    const int64_t* cs;
+    const int32_t* cstart;
+    const int4* cinfo;
+    const int64_t* nchunks;
+    int pg_row, ph_row;
+    double* dphi;
+    double* xi;
+};
+
+template <int D, int KERNEL>
+__global__ __launch_bounds__(kAThreads) void k_adjoint_dphi(AdjArgs A) {
     using Dm = Dims<D>;
     constexpr int nL = Dm::nL, nk = Dm::nk, m = Dm::m;
-    constexpr int PER_BLOCK = 256 / G;
-    const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
-    const int lane = threadIdx.x % G;
-    const int64_t k = (int64_t)tile * PER_BLOCK + threadIdx.x / G;
-    if (k >= n) return;
+    __shared__ double sx[D][kAWin];
+    __shared__ double sv[kAWin];
+    __shared__ int32_t sj[kAWin];
+    const uint32_t b = xcd_tile(blockIdx.x, gridDim.x);
+    if (b >= *A.nchunks) return;
+    const int64_t n = A.n;
+    const int64_t p0 = A.cstart[b], p1 = A.cstart[b + 1];
+    __shared__ WindowT<D> w;   // one copy per work-group: runtime-indexed, so kept in LDS
+    if (threadIdx.x == 0) chunk_window<D>(A.g, A.cs, A.cinfo[b], w);
+    __syncthreads();
+    const int W = w.off[w.nr];
+    const bool in_lds = W <= kAWin;
+    if (in_lds) {
+        for (int t = threadIdx.x; t < W; t += kAThreads) {
+            const int64_t j = window_global<D>(w, t);
+#pragma unroll
+            for (int a = 0; a < D; ++a) sx[a][t] = A.pos[a * n + j];
+            sv[t] = A.vol[j];
+            sj[t] = (int32_t)j;
+        }
+    }
+    __syncthreads();
+    const int lane = threadIdx.x % kALanes;
+    const int64_t k = p0 + threadIdx.x / kALanes;
+    if (k >= p1) return;   // whole groups leave together; no barrier follows
     double xk[D];
 #pragma unroll
-    for (int a = 0; a < D; ++a) xk[a] = pos[a * n + k];
-    double Lk[nL];
+    for (int a = 0; a < D; ++a) xk[a] = A.pos[a * n + k];
+    const double* ck = A.coef + k * kCoef;
+    double Lk2[nL];
 #pragma unroll
-    for (int p = 0; p < nL; ++p) Lk[p] = state[(int64_t)p * n + k];
-    const double* Plap = state + (int64_t)(nL + lap_row * nk) * n;
-    const double Vk = vol[k];
+    for (int p = 0; p < nL; ++p) Lk2[p] = (pair_a<D>(p) == pair_b<D>(p) ? 1.0 : 2.0) * ck[p];
+    const double Vk = A.vol[k];
     double acc1 = 0.0, acc2[nk];
 #pragma unroll
     for (int c = 0; c < nk; ++c) acc2[c] = 0.0;
-    const int64_t rb = row_ptr[k], re = row_ptr[k + 1];
-    for (int64_t e = rb + lane; e < re; e += G) {
-        const int64_t i = col[e];
-        double r[D], q2 = 0.0;
+    const int64_t rb = A.row_ptr[k], re = A.row_ptr[k + 1];
+    for (int64_t e = rb + lane; e < re; e += kALanes) {
+        const int t = A.col16[e];
+        double r[D], q2 = 0.0, Vi;
+        int64_t i;
+        if (in_lds) {
 #pragma unroll
-        for (int a = 0; a < D; ++a) { r[a] = (pos[a * n + i] - xk[a]) * invR; q2 += r[a] * r[a]; }
+            for (int a = 0; a < D; ++a) r[a] = (sx[a][t] - xk[a]) * A.invR;
+            Vi = sv[t];
+            i = sj[t];
+        } else {
+            i = window_global<D>(w, t);
+#pragma unroll
+            for (int a = 0; a < D; ++a) r[a] = (A.pos[a * n + i] - xk[a]) * A.invR;
+            Vi = A.vol[i];
+        }
+#pragma unroll
+        for (int a = 0; a < D; ++a) q2 += r[a] * r[a];
         double qv[m];
 #pragma unroll
         for (int p = 0; p < m; ++p) qv[p] = r[pair_a<D>(p)] * r[pair_b<D>(p)];
         const double c = kernel_shape<KERNEL>(sqrt(q2));
         const double iq4 = 1.0 / (q2 * q2);
-        // k's own row: v_ki with the correction matrix of k
+        const double* ci = A.coef + i * kCoef;
         double rLk = 0.0, rLi = 0.0;
 #pragma unroll
         for (int p = 0; p < nL; ++p) {
-            const double wgt = (pair_a<D>(p) == pair_b<D>(p) ? 1.0 : 2.0) * qv[p];
-            rLk += wgt * Lk[p];
-            rLi += wgt * state[(int64_t)p * n + i];
+            rLk += Lk2[p] * qv[p];
+            rLi += (pair_a<D>(p) == pair_b<D>(p) ? 1.0 : 2.0) * ci[p] * qv[p];
         }
-        const double Vi = vol[i];
+        // k's own row: v_ki with the correction matrix of k
         const double wa = Vi * c, wsk = Vi * c * rLk * iq4;
 #pragma unroll
         for (int a = 0; a < D; ++a) acc2[a] += wa * r[a];
 #pragma unroll
         for (int p = 0; p < m; ++p) acc2[D + p] += wsk * qv[p];
-        // W_ik from row i: r~_ik = -r~_ki, V_k, correction matrix of i
+        // W_ik from row i: r~_ik = -r~_ki, volume V_k, correction matrix of i
         const double ca = Vk * c, csi = Vk * c * rLi * iq4;
-        double W = 0.0;
+        double Wik = 0.0;
 #pragma unroll
-        for (int a = 0; a < D; ++a) W -= Plap[(int64_t)a * n + i] * ca * r[a];
+        for (int a = 0; a < D; ++a) Wik -= ci[nL + a] * ca * r[a];
 #pragma unroll
-        for (int p = 0; p < m; ++p) W += Plap[(int64_t)(D + p) * n + i] * csi * qv[p];
-        acc1 += u[i] * W;
+        for (int p = 0; p < m; ++p) Wik += ci[nL + D + p] * csi * qv[p];
+        acc1 += ci[nL + nk] * Wik;
     }
-    acc1 = group_sum(acc1, G);
+    acc1 = group_sum(acc1, kALanes);
 #pragma unroll
-    for (int c = 0; c < nk; ++c) acc2[c] = group_sum(acc2[c], G);
+    for (int c = 0; c < nk; ++c) acc2[c] = group_sum(acc2[c], kALanes);
     if (lane == 0) {
         double self = 0.0;
 #pragma unroll
-        for (int c = 0; c < nk; ++c) self += Plap[(int64_t)c * n + k] * acc2[c];
-        dphi[k] = acc1 - u[k] * self;
+        for (int c = 0; c < nk; ++c) self += ck[nL + c] * acc2[c];
+        A.dphi[k] = acc1 - ck[nL + nk] * self;
     }
 }
 
 // Per particle: D^ phi from the PGRAD / PHESS rows, then
 // xi_k = u_i * d(c_trans . D^)/d h^(k) for the six bottom quantities.
-template <int D, int G, int KERNEL>
-__global__ __launch_bounds__(256) void k_adjoint_xi(int64_t n, const double* __restrict__ pos,
-                                                    const double* __restrict__ vol,
-                                                    const int64_t* __restrict__ row_ptr,
-                                                    const int32_t* __restrict__ col, double invR,
-                                                    const double* __restrict__ state, int pg_row, int ph_row,
-                                                    MapParams mp, const double* __restrict__ phi,
-                                                    const double* __restrict__ u, double* __restrict__ xi_out) {
+template <int D, int KERNEL>
+__global__ __launch_bounds__(kAThreads) void k_adjoint_xi(AdjArgs A, MapParams mp) {
     using Dm = Dims<D>;
-    constexpr int nL = Dm::nL, nk = Dm::nk;
-    constexpr int PER_BLOCK = 256 / G;
-    const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
-    const int lane = threadIdx.x % G;
-    const int64_t i = (int64_t)tile * PER_BLOCK + threadIdx.x / G;
-    if (i >= n) return;
+    constexpr int nL = Dm::nL, nk = Dm::nk, m = Dm::m;
+    __shared__ double sx[D][kAWin];
+    __shared__ double sv[kAWin];
+    __shared__ double sp[kAWin];
+    const uint32_t b = xcd_tile(blockIdx.x, gridDim.x);
+    if (b >= *A.nchunks) return;
+    const int64_t n = A.n;
+    const int64_t p0 = A.cstart[b], p1 = A.cstart[b + 1];
+    __shared__ WindowT<D> w;   // one copy per work-group: runtime-indexed, so kept in LDS
+    if (threadIdx.x == 0) chunk_window<D>(A.g, A.cs, A.cinfo[b], w);
+    __syncthreads();
+    const int W = w.off[w.nr];
+    const bool in_lds = W <= kAWin;
+    if (in_lds) {
+        for (int t = threadIdx.x; t < W; t += kAThreads) {
+            const int64_t j = window_global<D>(w, t);
+#pragma unroll
+            for (int a = 0; a < D; ++a) sx[a][t] = A.pos[a * n + j];
+            sv[t] = A.vol[j];
+            sp[t] = A.phi[j];
+        }
+    }
+    __syncthreads();
+    const int lane = threadIdx.x % kALanes;
+    const int64_t i = p0 + threadIdx.x / kALanes;
+    if (i >= p1) return;   // whole groups leave together; no barrier follows
     double x[D];
 #pragma unroll
-    for (int a = 0; a < D; ++a) x[a] = pos[a * n + i];
-    double L[nL];
+    for (int a = 0; a < D; ++a) x[a] = A.pos[a * n + i];
+    double L2[nL];
 #pragma unroll
-    for (int p = 0; p < nL; ++p) L[p] = state[(int64_t)p * n + i];
+    for (int p = 0; p < nL; ++p) L2[p] = (pair_a<D>(p) == pair_b<D>(p) ? 1.0 : 2.0) * A.state[(int64_t)p * n + i];
+    const double phi_i = A.phi[i];
     double acc[nk];
-    row_sums<D, G, KERNEL, double>(pos, vol, col, n, row_ptr[i], row_ptr[i + 1], lane, x, invR, phi, phi[i], L,
-                                   acc);
-    // projected derivatives needed by c_trans: dz^, zz, xz, (yz)
+#pragma unroll
+    for (int c = 0; c < nk; ++c) acc[c] = 0.0;
+    const int64_t rb = A.row_ptr[i], re = A.row_ptr[i + 1];
+    for (int64_t e = rb + lane; e < re; e += kALanes) {
+        const int t = A.col16[e];
+        double r[D], q2 = 0.0, V, pj;
+        if (in_lds) {
+#pragma unroll
+            for (int a = 0; a < D; ++a) r[a] = (sx[a][t] - x[a]) * A.invR;
+            V = sv[t];
+            pj = sp[t];
+        } else {
+            const int64_t j = window_global<D>(w, t);
+#pragma unroll
+            for (int a = 0; a < D; ++a) r[a] = (A.pos[a * n + j] - x[a]) * A.invR;
+            V = A.vol[j];
+            pj = A.phi[j];
+        }
+#pragma unroll
+        for (int a = 0; a < D; ++a) q2 += r[a] * r[a];
+        double qv[m];
+#pragma unroll
+        for (int p = 0; p < m; ++p) qv[p] = r[pair_a<D>(p)] * r[pair_b<D>(p)];
+        double rLr = 0.0;
+#pragma unroll
+        for (int p = 0; p < nL; ++p) rLr += L2[p] * qv[p];
+        const double wa = V * kernel_shape<KERNEL>(sqrt(q2)) * (pj - phi_i);
+        const double ws = wa * rLr / (q2 * q2);
+#pragma unroll
+        for (int a = 0; a < D; ++a) acc[a] += wa * r[a];
+#pragma unroll
+        for (int p = 0; p < m; ++p) acc[D + p] += ws * qv[p];
+    }
+#pragma unroll
+    for (int c = 0; c < nk; ++c) acc[c] = group_sum(acc[c], kALanes);
+    if (lane != 0) return;
     auto row = [&](int o) {
-        const double* P = state + (int64_t)(nL + o * nk) * n + i;
+        const double* P = A.state + (int64_t)(nL + o * nk) * n + i;
         double v = 0.0;
 #pragma unroll
         for (int c = 0; c < nk; ++c) v += P[(int64_t)c * n] * acc[c];
         return v;
     };
-    const double gz = row(pg_row + D - 1);
-    const double Hzz = (D == 3) ? row(ph_row + 2) : row(ph_row + 1);
-    const double Hxz = (D == 3) ? row(ph_row + 4) : row(ph_row + 2);
-    const double Hyz = (D == 3) ? row(ph_row + 5) : 0.0;
-    if (lane != 0) return;
+    // projected derivatives needed by c_trans: dz^, zz, xz, (yz)
+    const double gz = row(A.pg_row + D - 1);
+    const double Hzz = (D == 3) ? row(A.ph_row + 2) : row(A.ph_row + 1);
+    const double Hxz = (D == 3) ? row(A.ph_row + 4) : row(A.ph_row + 2);
+    const double Hyz = (D == 3) ? row(A.ph_row + 5) : 0.0;
     double h[6];
     bottom6(mp, x[0], D == 3 ? x[1] : 0.0, h);
     Dual6 hd[6];
@@ -139,10 +257,10 @@ __global__ __launch_bounds__(256) void k_adjoint_xi(int64_t n, const double* __r
         hd[q].d[q] = 1.0;
     }
     const MapCoef<Dual6> mc = map_coef<Dual6>(mp, hd, x[D - 1]);
-    const double ui = u[i];
+    const double ui = A.u[i];
 #pragma unroll
     for (int q = 0; q < 6; ++q)
-        xi_out[(int64_t)q * n + i] = ui * (mc.c0.d[q] * gz + mc.c3.d[q] * Hzz + mc.c4.d[q] * Hxz + mc.c5.d[q] * Hyz);
+        A.xi[(int64_t)q * n + i] = ui * (mc.c0.d[q] * gz + mc.c3.d[q] * Hzz + mc.c4.d[q] * Hxz + mc.c5.d[q] * Hyz);
 }
 
 constexpr int kRedThreads = 256;
@@ -195,24 +313,21 @@ __global__ __launch_bounds__(kRedThreads) void k_dtheta_final(int64_t nblocks, i
 }
 
 template <int D, int KERNEL>
-static int launch_adjoint(int64_t n, const double* pos, const double* vol, const int64_t* row_ptr,
-                          const int32_t* col, double invR, const double* state, int lap_row, int pg_row,
-                          int ph_row, const MapParams& mp, const double* phi, const double* u, double* dphi,
-                          double* dtheta, double* xi, double* partials, hipStream_t s) {
-    constexpr int G = (D == 3) ? 8 : 4;
-    constexpr int PER_BLOCK = 256 / G;
-    const int64_t nb = (n + PER_BLOCK - 1) / PER_BLOCK;
-    if (dphi) {
-        hipLaunchKernelGGL((k_adjoint_dphi<D, G, KERNEL>), dim3((unsigned)nb), dim3(256), 0, s, n, pos, vol,
-                           row_ptr, col, invR, state, lap_row, u, dphi);
+static int launch_adjoint(AdjArgs a, int64_t cap, const MapParams& mp, int lap_row, double* dtheta,
+                          double* partials, hipStream_t s) {
+    const int64_t n = a.n;
+    if (a.dphi) {
+        hipLaunchKernelGGL((k_adjoint_pack<D>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, a.state,
+                           lap_row, a.u, const_cast<double*>(a.coef));
+        VCT_LAUNCH_CHECK();
+        hipLaunchKernelGGL((k_adjoint_dphi<D, KERNEL>), dim3((unsigned)cap), dim3(kAThreads), 0, s, a);
         VCT_LAUNCH_CHECK();
     }
     if (dtheta && mp.nterms > 0) {
-        hipLaunchKernelGGL((k_adjoint_xi<D, G, KERNEL>), dim3((unsigned)nb), dim3(256), 0, s, n, pos, vol, row_ptr,
-                           col, invR, state, pg_row, ph_row, mp, phi, u, xi);
+        hipLaunchKernelGGL((k_adjoint_xi<D, KERNEL>), dim3((unsigned)cap), dim3(kAThreads), 0, s, a, mp);
         VCT_LAUNCH_CHECK();
         const int64_t nred = (n + kRedThreads - 1) / kRedThreads;
-        hipLaunchKernelGGL(k_dtheta_partials, dim3((unsigned)nred), dim3(kRedThreads), 0, s, n, pos, D, mp, xi,
+        hipLaunchKernelGGL(k_dtheta_partials, dim3((unsigned)nred), dim3(kRedThreads), 0, s, n, a.pos, D, mp, a.xi,
                            partials);
         VCT_LAUNCH_CHECK();
         hipLaunchKernelGGL(k_dtheta_final, dim3((unsigned)mp.nterms), dim3(kRedThreads), 0, s, nred, mp.nterms,
@@ -234,21 +349,25 @@ using namespace vct;
 extern "C" size_t vct_adjoint_workspace_size(int dim, int64_t n, int nterms) {
     if ((dim != 2 && dim != 3) || n < 0 || nterms < 0) return 0;
     const int64_t nred = (n + kRedThreads - 1) / kRedThreads;
-    return aligned_sum({(size_t)n * 6 * sizeof(double), (size_t)(nred > 0 ? nred : 1) * (nterms > 0 ? nterms : 1) * 8});
+    return aligned_sum({(size_t)n * 6 * sizeof(double), (size_t)(nred > 0 ? nred : 1) * (nterms > 0 ? nterms : 1) * 8,
+                        (size_t)n * kCoef * sizeof(double)});
 }
 
-extern "C" int vct_apply_ops_adjoint(int dim, int64_t n, const double* pos_sorted, const double* vol_sorted,
-                                     const int64_t* row_ptr, const int32_t* col, int kernel, double R,
-                                     const double* state64, uint32_t out_mask, const vct_map* map,
+extern "C" int vct_apply_ops_adjoint(const vct_nlist* nl, const double* pos_sorted, const double* vol_sorted,
+                                     int kernel, const double* state64, uint32_t out_mask, const vct_map* map,
                                      const double* phi_sorted, const double* u, double* dphi, double* dtheta,
                                      void* ws, size_t ws_bytes, void* stream) {
     const uint32_t need = VCT_OUT_LAP | VCT_OUT_PGRAD | VCT_OUT_PHESS;
-    if ((dim != 2 && dim != 3) || n < 0 || n > INT32_MAX || !(R > 0.0) || !isfinite(R) || !map ||
-        !mask_valid(out_mask) || (out_mask & need) != need ||
+    Grid g;
+    int st = nlist_check(nl, g);
+    if (st) return st;
+    const int dim = nl->dim;
+    const int64_t n = nl->n;
+    if (!map || !mask_valid(out_mask) || (out_mask & need) != need ||
         (kernel != VCT_KERNEL_WENDLAND_C2 && kernel != VCT_KERNEL_CUBIC_SPLINE))
         return VCT_E_ARG;
     MapParams mp;
-    int st = map_params_from(map, dim, mp);
+    st = map_params_from(map, dim, mp);
     if (st) return st;
     hipStream_t s = as_stream(stream);
     if (n == 0) {
@@ -258,32 +377,32 @@ extern "C" int vct_apply_ops_adjoint(int dim, int64_t n, const double* pos_sorte
         }
         return VCT_OK;
     }
-    if (!pos_sorted || !vol_sorted || !row_ptr || !col || !state64 || !u) return VCT_E_ARG;
+    if (!pos_sorted || !vol_sorted || !nl->col16 || !state64 || !u) return VCT_E_ARG;
     if (dtheta && !phi_sorted) return VCT_E_ARG;
     if (!ws || ws_bytes < vct_adjoint_workspace_size(dim, n, mp.nterms)) return VCT_E_WORKSPACE;
     Carver cv(ws, ws_bytes);
     double* xi = cv.take<double>((size_t)n * 6);
     const int64_t nred = (n + kRedThreads - 1) / kRedThreads;
     double* partials = cv.take<double>((size_t)nred * (mp.nterms > 0 ? mp.nterms : 1));
+    double* coef = cv.take<double>((size_t)n * kCoef);
+    const int64_t ncols = dim == 3 ? g.nc[0] * g.nc[1] : g.nc[0];
+    AdjArgs a;
+    a.n = n; a.invR = 1.0 / nl->R; a.g = g; a.pos = pos_sorted; a.vol = vol_sorted; a.phi = phi_sorted;
+    a.state = state64; a.u = u; a.coef = coef; a.row_ptr = nl->row_ptr; a.col16 = nl->col16; a.cs = nl->cell_start;
+    a.cstart = nl->chunk_start; a.cinfo = reinterpret_cast<const int4*>(nl->chunk_info);
+    a.nchunks = nl->chunk_off + ncols;
+    a.pg_row = group_row(dim, out_mask, VCT_OUT_PGRAD);
+    a.ph_row = group_row(dim, out_mask, VCT_OUT_PHESS);
+    a.dphi = dphi; a.xi = xi;
     const int lap_row = group_row(dim, out_mask, VCT_OUT_LAP);
-    const int pg_row = group_row(dim, out_mask, VCT_OUT_PGRAD);
-    const int ph_row = group_row(dim, out_mask, VCT_OUT_PHESS);
-    const double invR = 1.0 / R;
+    const int64_t cap = ncols + n / kChunk + 1;
     if (dim == 2)
         st = (kernel == VCT_KERNEL_WENDLAND_C2)
-                 ? launch_adjoint<2, VCT_KERNEL_WENDLAND_C2>(n, pos_sorted, vol_sorted, row_ptr, col, invR, state64,
-                                                             lap_row, pg_row, ph_row, mp, phi_sorted, u, dphi,
-                                                             dtheta, xi, partials, s)
-                 : launch_adjoint<2, VCT_KERNEL_CUBIC_SPLINE>(n, pos_sorted, vol_sorted, row_ptr, col, invR, state64,
-                                                              lap_row, pg_row, ph_row, mp, phi_sorted, u, dphi,
-                                                              dtheta, xi, partials, s);
+                 ? launch_adjoint<2, VCT_KERNEL_WENDLAND_C2>(a, cap, mp, lap_row, dtheta, partials, s)
+                 : launch_adjoint<2, VCT_KERNEL_CUBIC_SPLINE>(a, cap, mp, lap_row, dtheta, partials, s);
     else
         st = (kernel == VCT_KERNEL_WENDLAND_C2)
-                 ? launch_adjoint<3, VCT_KERNEL_WENDLAND_C2>(n, pos_sorted, vol_sorted, row_ptr, col, invR, state64,
-                                                             lap_row, pg_row, ph_row, mp, phi_sorted, u, dphi,
-                                                             dtheta, xi, partials, s)
-                 : launch_adjoint<3, VCT_KERNEL_CUBIC_SPLINE>(n, pos_sorted, vol_sorted, row_ptr, col, invR, state64,
-                                                              lap_row, pg_row, ph_row, mp, phi_sorted, u, dphi,
-                                                              dtheta, xi, partials, s);
+                 ? launch_adjoint<3, VCT_KERNEL_WENDLAND_C2>(a, cap, mp, lap_row, dtheta, partials, s)
+                 : launch_adjoint<3, VCT_KERNEL_CUBIC_SPLINE>(a, cap, mp, lap_row, dtheta, partials, s);
     return st;
 }

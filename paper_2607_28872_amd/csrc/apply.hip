@@ -5,158 +5,495 @@
 // Numerics.  phi_ij is dominated by its first-order part r_ij . grad phi,
 // which cancels across a (nearly) symmetric neighbourhood in s_i; rounding the
 // individual terms is then amplified by |grad phi| / (R |Hess phi|).  The
-// kernel therefore sums in two passes: pass 1 forms the first-order gradient
-// G = L a (only d sums), pass 2 sums the residual psi_ij = phi_ij - r_ij . G,
-// formed in FP64 and second-order small, and the output adds back W G, the
-// exact response of the operator to the linear field r . G.  The result is the
-// same linear operator; only the rounding changes.
+// operator is linear and reproduces linear fields exactly, so for any vector
+// G, out(phi) = P [a; s](psi) + W G with psi_ij = phi_ij - (x_j - x_i) . G and
+// W the response of the output rows to a unit projected gradient (stored by
+// vct_moments).  The kernel sums in two passes: pass 1 forms the particle's
+// first-order gradient G = L a (d sums), pass 2 sums the residual psi, which
+// is second-order small and has a(psi) = 0 up to rounding.  psi is formed in
+// FP64 from the FP64 positions and field values; the pair geometry, kernel and
+// sums run in the arithmetic type T (FP64, or FP32 for the mixed form).  The
+// result is the same linear operator; only the rounding changes.
 //
-// One group of G lanes per particle walks its CSR row (coalesced column reads,
-// neighbours of consecutive cell-sorted particles shared in L1/L2), the group
-// reduces its sums with cross-lane shuffles, and lane o of the group produces
-// output row o.  Work-groups are remapped so each XCD covers a contiguous
-// range of particles; the second pass re-reads the row from cache.
+// Work decomposition.  One work-group per chunk (at most 64 consecutive
+// particles of one cell column).  The chunk's neighbour window (positions,
+// field values, volumes) and its block of 16-bit row entries are staged once
+// in LDS with coalesced loads; each particle is served by kLanes lanes that
+// hold their share of the row entries in registers and read the pair records
+// from LDS, software-pipelined one record ahead.  The group reduces its sums
+// with cross-lane shuffles; the products with the state are done with one
+// thread per (row, particle) so that the state is read with unit stride.
+// Work-groups are remapped so each XCD covers a contiguous range of chunks.
+#include <type_traits>
+
 #include "common.h"
-#include "pairs.h"
+#include "tiles.h"
 
 namespace vct {
 
-template <int D, int G, int KERNEL, class T, class S>
-__global__ __launch_bounds__(256) void k_apply(int64_t n, int nf, const double* __restrict__ phi,
-                                               const double* __restrict__ pos, const double* __restrict__ vol,
-                                               const int64_t* __restrict__ row_ptr,
-                                               const int32_t* __restrict__ col, double invR,
-                                               const S* __restrict__ state, int nrows,
-                                               double* __restrict__ out) {
+int nlist_check(const vct_nlist* nl, Grid& g);
+
+constexpr int kLanes = 8;                    // lanes per particle
+constexpr int kThreads = kChunk * kLanes;    // one chunk per work-group
+constexpr int kColCap = 7168;                // row entries of a chunk staged in LDS
+constexpr int kColBlocks = (kColCap / 8 + kThreads - 1) / kThreads;   // 16-byte blocks per thread
+
+// Register slots per lane, occupancy target and LDS window capacity (records)
+// of each arithmetic type.
+template <class T> struct ApplyCfg;
+template <> struct ApplyCfg<float> {
+    static constexpr int slots = 14;
+    static constexpr int waves = 4;
+    static constexpr int win = 1664;
+};
+template <> struct ApplyCfg<double> {
+    static constexpr int slots = 14;
+    static constexpr int waves = 2;
+    static constexpr int win = 1600;
+};
+
+template <class S> struct ApplyArgs {
+    int64_t n;
+    int nf;
+    int nrows;
+    double invR;
+    Grid g;
+    const double* phi;
+    const double* pos;
+    const double* vol;
+    const int64_t* row_ptr;
+    const uint16_t* col16;
+    const int64_t* cs;
+    const int32_t* cstart;
+    const int4* cinfo;
+    const int64_t* nchunks;
+    const S* state;
+    double* out;
+};
+
+// Pair geometry: FP64 offset dx = x_j - x_i, r~ = dx / R, q^2 = |r~|^2 and
+// V_j c~(q) in the arithmetic type T.
+template <int D, int KERNEL, class T>
+__device__ __forceinline__ void pair_geom(const double4& q, T vj, const double (&xi)[3], T invR,
+                                          double (&dx)[D], T (&r)[D], T& q2, T& vc) {
+    dx[0] = q.x - xi[0];
+    dx[1] = q.y - xi[1];
+    if (D == 3) dx[D - 1] = q.z - xi[2];
+    q2 = T(0);
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        r[a] = T(dx[a]) * invR;
+        q2 += r[a] * r[a];
+    }
+    vc = vj * kernel_shape<KERNEL>(vsqrt(q2));
+}
+
+// Sums of one pair with residual psi: a~ += V c~ psi r~ and
+// s~ += V c~ psi (r~' L~ r~) / |r~|^4 r~ r~'  (L2 holds L~ with doubled
+// off-diagonal entries).
+template <int D, class T>
+__device__ __forceinline__ void pair_sums(const T (&r)[D], T q2, T vc, T psi, const T (&L2)[Dims<D>::nL],
+                                          T (&acc)[Dims<D>::nk]) {
+    using Dm = Dims<D>;
+    T qv[Dm::m];
+#pragma unroll
+    for (int p = 0; p < Dm::m; ++p) qv[p] = r[pair_a<D>(p)] * r[pair_b<D>(p)];
+    T rLr = T(0);
+#pragma unroll
+    for (int p = 0; p < Dm::nL; ++p) rLr += L2[p] * qv[p];
+    const T wa = vc * psi, ws = wa * rLr * vrcp(q2 * q2);
+#pragma unroll
+    for (int a = 0; a < D; ++a) acc[a] += wa * r[a];
+#pragma unroll
+    for (int p = 0; p < Dm::m; ++p) acc[D + p] += ws * qv[p];
+}
+
+// G~ = L~ a~ after the group reduction of a~ (dimensionless).
+template <int D, class T>
+__device__ __forceinline__ void group_gradient(const T (&L2)[Dims<D>::nL], T (&a1)[D], T (&Gt)[D]) {
+#pragma unroll
+    for (int a = 0; a < D; ++a) a1[a] = group_sum(a1[a], kLanes);
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        T t = T(0);
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            const int p = sym_index<D>(a, c);
+            t += (a == c ? L2[p] : T(0.5) * L2[p]) * a1[c];
+        }
+        Gt[a] = t;
+    }
+}
+
+template <int D, class T, class S>
+__device__ __forceinline__ void load_L(const ApplyArgs<S>& A, int64_t ii, T (&L2)[Dims<D>::nL]) {
+#pragma unroll
+    for (int p = 0; p < Dims<D>::nL; ++p) {
+        const T v = T(A.state[(int64_t)p * A.n + ii]);
+        L2[p] = (pair_a<D>(p) == pair_b<D>(p)) ? v : T(2) * v;
+    }
+}
+
+// out row o of particle i: P_o [a~; s~] + W_o G~ / R.
+template <int D, class T, class S>
+__device__ __forceinline__ double out_row(const ApplyArgs<S>& A, int64_t i, int o, const T* acc, const T* Gt) {
     using Dm = Dims<D>;
     constexpr int nL = Dm::nL, nk = Dm::nk;
-    constexpr int PER_BLOCK = 256 / G;
-    const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
-    const int lane = threadIdx.x % G;
-    const int64_t i = (int64_t)tile * PER_BLOCK + threadIdx.x / G;
-    if (i >= n) return;
-    double xi[D];
+    const int64_t n = A.n;
+    const S* P = A.state + (int64_t)(nL + o * nk) * n + i;
+    const S* Wr = A.state + (int64_t)(nL + A.nrows * nk + o * D) * n + i;
+    T v = T(0);
 #pragma unroll
-    for (int a = 0; a < D; ++a) xi[a] = pos[a * n + i];
-    T L[nL];
+    for (int c = 0; c < nk; ++c) v += T(P[(int64_t)c * n]) * acc[c];
+    T lin = T(0);
 #pragma unroll
-    for (int p = 0; p < nL; ++p) L[p] = T(state[(int64_t)p * n + i]);
-    const int64_t rb = row_ptr[i], re = row_ptr[i + 1];
-    const S* Wst = state + (int64_t)(nL + nrows * nk) * n + i;
-    for (int f = 0; f < nf; ++f) {
-        const double* ph = phi + (int64_t)f * n;
+    for (int a = 0; a < D; ++a) lin += T(Wr[(int64_t)a * n]) * Gt[a];
+    return (double)v + (double)lin * A.invR;
+}
+
+// A chunk whose window exceeds the LDS capacity: the same two passes with
+// every record read from the memory hierarchy.
+template <int D, int KERNEL, class T, class S>
+__device__ __forceinline__ void apply_chunk_global(const ApplyArgs<S>& A, const WindowT<D>& w, int64_t p0,
+                                                int64_t p1) {
+    constexpr int nk = Dims<D>::nk;
+    const int64_t n = A.n;
+    const int lane = threadIdx.x % kLanes;
+    const int64_t i = p0 + threadIdx.x / kLanes;
+    if (i >= p1) return;   // whole groups leave together
+    const T invR = T(A.invR);
+    double xi[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) xi[a] = a < D ? A.pos[a * n + i] : 0.0;
+    T L2[Dims<D>::nL];
+    load_L<D, T, S>(A, i, L2);
+    const int64_t rb = A.row_ptr[i], re = A.row_ptr[i + 1];
+    for (int f = 0; f < A.nf; ++f) {
+        const double* ph = A.phi + (int64_t)f * n;
         const double phi_i = ph[i];
-        // pass 1: first-order sums a_i and the gradient G~ = L~ a~ (units of 1/R)
-        T a1[D];
+        auto fetch = [&](int t, double4& q, T& v) {
+            const int64_t j = window_global<D>(w, t);
+            q = make_double4(A.pos[j], A.pos[n + j], D == 3 ? A.pos[2 * n + j] : 0.0, ph[j]);
+            v = T(A.vol[j]);
+        };
+        T a1[D], Gt[D];
 #pragma unroll
         for (int a = 0; a < D; ++a) a1[a] = T(0);
-        for (int64_t k = rb + lane; k < re; k += G) {
-            const int64_t j = col[k];
-            T r[D], q2 = T(0);
+        for (int64_t e = rb + lane; e < re; e += kLanes) {
+            double4 q;
+            T vj, r[D], q2, vc;
+            double dx[D];
+            fetch(A.col16[e], q, vj);
+            pair_geom<D, KERNEL, T>(q, vj, xi, invR, dx, r, q2, vc);
+            const T wgt = vc * T(q.w - phi_i);
 #pragma unroll
-            for (int a = 0; a < D; ++a) {
-                r[a] = T((pos[a * n + j] - xi[a]) * invR);
-                q2 += r[a] * r[a];
-            }
-            const T w = T(vol[j]) * kernel_shape<KERNEL>(vsqrt(q2)) * T(ph[j] - phi_i);
-#pragma unroll
-            for (int a = 0; a < D; ++a) a1[a] += w * r[a];
+            for (int a = 0; a < D; ++a) a1[a] += wgt * r[a];
         }
+        group_gradient<D, T>(L2, a1, Gt);
+        double Gp[D];
 #pragma unroll
-        for (int a = 0; a < D; ++a) a1[a] = group_sum(a1[a], G);
-        double Gt[D];
-#pragma unroll
-        for (int a = 0; a < D; ++a) {
-            T t = T(0);
-#pragma unroll
-            for (int b = 0; b < D; ++b) t += L[sym_index<D>(a, b)] * a1[b];
-            Gt[a] = (double)t;
-        }
-        // pass 2: sums of the residual psi_ij = phi_ij - r~_ij . G~ (formed in FP64)
+        for (int a = 0; a < D; ++a) Gp[a] = (double)Gt[a] * A.invR;
         T acc[nk];
 #pragma unroll
         for (int c = 0; c < nk; ++c) acc[c] = T(0);
-        for (int64_t k = rb + lane; k < re; k += G) {
-            const int64_t j = col[k];
-            double psi = ph[j] - phi_i;
+        for (int64_t e = rb + lane; e < re; e += kLanes) {
+            double4 q;
+            T vj, r[D], q2, vc;
+            double dx[D];
+            fetch(A.col16[e], q, vj);
+            pair_geom<D, KERNEL, T>(q, vj, xi, invR, dx, r, q2, vc);
+            double psi = q.w - phi_i;
 #pragma unroll
-            for (int a = 0; a < D; ++a) psi -= (pos[a * n + j] - xi[a]) * invR * Gt[a];
-            pair_terms<D, KERNEL, T>(pos, vol, n, j, xi, invR, L, T(psi), acc);
+            for (int a = 0; a < D; ++a) psi -= dx[a] * Gp[a];
+            pair_sums<D, T>(r, q2, vc, T(psi), L2, acc);
         }
 #pragma unroll
-        for (int c = 0; c < nk; ++c) acc[c] = group_sum(acc[c], G);
-        for (int o = lane; o < nrows; o += G) {
-            const S* P = state + (int64_t)(nL + o * nk) * n + i;
-            T v = T(0);
+        for (int c = 0; c < nk; ++c) acc[c] = group_sum(acc[c], kLanes);
+        for (int o = lane; o < A.nrows; o += kLanes)
+            A.out[((int64_t)f * n + i) * A.nrows + o] = out_row<D, T, S>(A, i, o, acc, Gt);
+    }
+}
+
+template <int D, int KERNEL, class T, class S>
+__global__ __launch_bounds__(kThreads, ApplyCfg<T>::waves) void k_apply(ApplyArgs<S> A) {
+    using Dm = Dims<D>;
+    constexpr int nk = Dm::nk, kS = ApplyCfg<T>::slots, kW = ApplyCfg<T>::win;
+    __shared__ double4 sd[kW];
+    __shared__ T sv[kW];
+    __shared__ uint4 scol4[kColCap / 8];
+    __shared__ T sacc[kChunk][nk + D];
+    __shared__ WindowT<D> w;
+    const uint32_t b = xcd_tile(blockIdx.x, gridDim.x);
+    if (b >= *A.nchunks) return;   // uniform over the work-group
+    const int64_t n = A.n;
+    const int64_t p0 = A.cstart[b], p1 = A.cstart[b + 1];
+    if (threadIdx.x < kWave) chunk_window_wave<D>(A.g, A.cs, A.cinfo[b], w);
+    // per-particle data, requested while the window is formed
+    const int lane = threadIdx.x % kLanes;
+    const int pl = threadIdx.x / kLanes;
+    const int64_t i = p0 + pl;
+    const bool valid = i < p1;
+    const int64_t ii = valid ? i : p0;
+    double xi[3];
 #pragma unroll
-            for (int c = 0; c < nk; ++c) v += T(P[(int64_t)c * n]) * acc[c];
-            T lin = T(0);
+    for (int a = 0; a < 3; ++a) xi[a] = a < D ? A.pos[a * n + ii] : 0.0;
+    T L2[Dm::nL];
+    load_L<D, T, S>(A, ii, L2);
+    const int64_t rb = valid ? A.row_ptr[ii] : 0, re = valid ? A.row_ptr[ii + 1] : 0;
+    // the chunk's row entries [cb, ce), staged from the 16-byte aligned cb8
+    const int64_t cb = A.row_ptr[p0], ce = A.row_ptr[p1], nnz = A.row_ptr[n];
+    const int64_t cb8 = cb & ~int64_t(7);
+    const bool col_lds = ce - cb8 <= kColCap;
+    __syncthreads();
+    const int W = __builtin_amdgcn_readfirstlane(w.off[w.nr]);
+    if (W > kW) {
+        apply_chunk_global<D, KERNEL, T, S>(A, w, p0, p1);
+        return;
+    }
+    // stage the window records and the chunk's row entries; every load of a
+    // thread is issued before its first LDS store
+    {
+        constexpr int kRep = (kW + kThreads - 1) / kThreads;
+        const double* ph = A.phi;
+        double4 q[kRep];
+        T v[kRep];
 #pragma unroll
-            for (int a = 0; a < D; ++a) lin += T(Wst[(int64_t)(o * D + a) * n]) * T(Gt[a]);
-            out[((int64_t)f * n + i) * nrows + o] = (double)v + (double)lin * invR;
+        for (int k = 0; k < kRep; ++k) {
+            const int t = threadIdx.x + k * kThreads;
+            const int64_t j = window_global<D>(w, t < W ? t : 0);
+            q[k] = make_double4(A.pos[j], A.pos[n + j], D == 3 ? A.pos[2 * n + j] : 0.0, ph[j]);
+            v[k] = T(A.vol[j]);
+        }
+        uint4 cv[kColBlocks];
+        if (col_lds) {
+#pragma unroll
+            for (int k = 0; k < kColBlocks; ++k) {
+                const int blk = threadIdx.x + k * kThreads;
+                const int64_t base = cb8 + 8 * (int64_t)blk;
+                if (base < ce) {
+                    if (base + 8 <= nnz) {
+                        cv[k] = *reinterpret_cast<const uint4*>(A.col16 + base);
+                    } else {   // the last block of the array: entry by entry
+                        uint32_t h[4] = {0u, 0u, 0u, 0u};
+                        for (int u = 0; u < 8 && base + u < nnz; ++u)
+                            h[u / 2] |= (uint32_t)A.col16[base + u] << (16 * (u % 2));
+                        cv[k] = make_uint4(h[0], h[1], h[2], h[3]);
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kRep; ++k) {
+            const int t = threadIdx.x + k * kThreads;
+            if (t < W) {
+                sd[t] = q[k];
+                sv[t] = v[k];
+            }
+        }
+        if (col_lds) {
+#pragma unroll
+            for (int k = 0; k < kColBlocks; ++k) {
+                const int blk = threadIdx.x + k * kThreads;
+                if (cb8 + 8 * (int64_t)blk < ce) scol4[blk] = cv[k];
+            }
+        }
+    }
+    __syncthreads();
+    // register slots: entry rb + lane + kLanes s; an empty slot repeats the
+    // row's first entry (offset 0 for an empty row) and is masked out
+    const uint16_t* scol = reinterpret_cast<const uint16_t*>(scol4);
+    auto col_at = [&](int64_t e) -> int { return col_lds ? (int)scol[e - cb8] : (int)A.col16[e]; };
+    // (two 16-bit offsets per register)
+    uint32_t cpk[(kS + 1) / 2];
+    int nslot = 0;
+    {
+        const uint32_t first = re > rb ? (uint32_t)col_at(rb) : 0u;
+#pragma unroll
+        for (int s = 0; s < kS; ++s) {
+            const int64_t e = rb + lane + (int64_t)kLanes * s;
+            const uint32_t c = e < re ? (uint32_t)col_at(e) : first;
+            nslot += e < re ? 1 : 0;
+            if (s % 2 == 0) cpk[s / 2] = c;
+            else cpk[s / 2] |= c << 16;
+        }
+    }
+    auto cols = [&](int s) -> int { return (int)((cpk[s / 2] >> (16 * (s % 2))) & 0xffffu); };
+    const int64_t tail = rb + (int64_t)kLanes * kS;
+    const T invR = T(A.invR);
+    for (int f = 0; f < A.nf; ++f) {
+        const double* ph = A.phi + (int64_t)f * n;
+        if (f > 0) {
+            // every read of sd happened before the epilogue's barrier
+            for (int t = threadIdx.x; t < W; t += kThreads) sd[t].w = ph[window_global<D>(w, t)];
+            __syncthreads();
+        }
+        const double phi_i = ph[ii];
+        // pass 1: first-order sums and G~ = L~ a~
+        T a1[D], Gt[D];
+#pragma unroll
+        for (int a = 0; a < D; ++a) a1[a] = T(0);
+        auto term1 = [&](const double4& q, T vj, bool use) {
+            double dx[D];
+            T r[D], q2, vc;
+            pair_geom<D, KERNEL, T>(q, vj, xi, invR, dx, r, q2, vc);
+            const T wgt = use ? vc * T(q.w - phi_i) : T(0);
+#pragma unroll
+            for (int a = 0; a < D; ++a) a1[a] += wgt * r[a];
+        };
+        // software pipeline: the record of slot s + 1 is read while slot s is
+        // summed (the scheduling barriers keep the compiler from hoisting
+        // every slot's read, which would exhaust the registers)
+        double4 qn = sd[cols(0)];
+        T vn = sv[cols(0)];
+#pragma unroll
+        for (int s = 0; s < kS; ++s) {
+            const double4 q = qn;
+            const T vj = vn;
+            if (s + 1 < kS) {
+                qn = sd[cols(s + 1)];
+                vn = sv[cols(s + 1)];
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            term1(q, vj, s < nslot);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        for (int64_t e = tail + lane; e < re; e += kLanes) {
+            const int t = col_at(e);
+            term1(sd[t], sv[t], true);
+        }
+        group_gradient<D, T>(L2, a1, Gt);
+        double Gp[D];
+#pragma unroll
+        for (int a = 0; a < D; ++a) Gp[a] = (double)Gt[a] * A.invR;
+        // pass 2: sums of the residual psi_ij = phi_ij - (x_j - x_i) . G
+        T acc[nk];
+#pragma unroll
+        for (int c = 0; c < nk; ++c) acc[c] = T(0);
+        auto term2 = [&](const double4& q, T vj, bool use) {
+            double dx[D];
+            T r[D], q2, vc;
+            pair_geom<D, KERNEL, T>(q, vj, xi, invR, dx, r, q2, vc);
+            double psi = q.w - phi_i;
+#pragma unroll
+            for (int a = 0; a < D; ++a) psi -= dx[a] * Gp[a];
+            pair_sums<D, T>(r, use ? q2 : T(1), use ? vc : T(0), T(psi), L2, acc);
+        };
+        qn = sd[cols(0)];
+        vn = sv[cols(0)];
+#pragma unroll
+        for (int s = 0; s < kS; ++s) {
+            const double4 q = qn;
+            const T vj = vn;
+            if (s + 1 < kS) {
+                qn = sd[cols(s + 1)];
+                vn = sv[cols(s + 1)];
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            term2(q, vj, s < nslot);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        for (int64_t e = tail + lane; e < re; e += kLanes) {
+            const int t = col_at(e);
+            term2(sd[t], sv[t], true);
+        }
+        // epilogue: the group's sums to LDS, then one thread per (row, particle)
+#pragma unroll
+        for (int c = 0; c < nk; ++c) acc[c] = group_sum(acc[c], kLanes);
+        if (lane == 0) {
+#pragma unroll
+            for (int c = 0; c < nk; ++c) sacc[pl][c] = acc[c];
+#pragma unroll
+            for (int a = 0; a < D; ++a) sacc[pl][nk + a] = Gt[a];
+        }
+        __syncthreads();
+        {
+            const int q = threadIdx.x % kChunk;
+            const int64_t iq = p0 + q;
+            if (iq < p1)
+                for (int o = threadIdx.x / kChunk; o < A.nrows; o += kThreads / kChunk)
+                    A.out[((int64_t)f * n + iq) * A.nrows + o] =
+                        out_row<D, T, S>(A, iq, o, &sacc[q][0], &sacc[q][nk]);
         }
     }
 }
 
 template <int D, int KERNEL, class T, class S>
-static int launch_apply(int64_t n, int nf, const double* phi, const double* pos, const double* vol,
-                        const int64_t* row_ptr, const int32_t* col, double invR, const S* state, int nrows,
-                        double* out, hipStream_t s) {
-    constexpr int G = (D == 3) ? 8 : 4;
-    constexpr int PER_BLOCK = 256 / G;
-    int64_t nb = (n + PER_BLOCK - 1) / PER_BLOCK;
-    hipLaunchKernelGGL((k_apply<D, G, KERNEL, T, S>), dim3((unsigned)nb), dim3(256), 0, s, n, nf, phi, pos, vol,
-                       row_ptr, col, invR, state, nrows, out);
+static int launch_apply(const ApplyArgs<S>& a, int64_t cap, hipStream_t s) {
+    hipLaunchKernelGGL((k_apply<D, KERNEL, T, S>), dim3((unsigned)cap), dim3(kThreads), 0, s, a);
     VCT_LAUNCH_CHECK();
     return VCT_OK;
 }
 
-template <int D, class T, class S>
-static int dispatch_kernel(int kernel, int64_t n, int nf, const double* phi, const double* pos, const double* vol,
-                           const int64_t* row_ptr, const int32_t* col, double invR, const S* state, int nrows,
-                           double* out, hipStream_t s) {
-    if (kernel == VCT_KERNEL_WENDLAND_C2)
-        return launch_apply<D, VCT_KERNEL_WENDLAND_C2, T, S>(n, nf, phi, pos, vol, row_ptr, col, invR, state,
-                                                             nrows, out, s);
-    return launch_apply<D, VCT_KERNEL_CUBIC_SPLINE, T, S>(n, nf, phi, pos, vol, row_ptr, col, invR, state, nrows,
-                                                          out, s);
+template <class T, class S>
+static int dispatch(int dim, int kernel, const ApplyArgs<S>& a, int64_t cap, hipStream_t s) {
+    if (dim == 2)
+        return kernel == VCT_KERNEL_WENDLAND_C2 ? launch_apply<2, VCT_KERNEL_WENDLAND_C2, T, S>(a, cap, s)
+                                                : launch_apply<2, VCT_KERNEL_CUBIC_SPLINE, T, S>(a, cap, s);
+    return kernel == VCT_KERNEL_WENDLAND_C2 ? launch_apply<3, VCT_KERNEL_WENDLAND_C2, T, S>(a, cap, s)
+                                            : launch_apply<3, VCT_KERNEL_CUBIC_SPLINE, T, S>(a, cap, s);
 }
 
-template <class T, class S>
-static int dispatch_dim(int dim, int kernel, int64_t n, int nf, const double* phi, const double* pos,
-                        const double* vol, const int64_t* row_ptr, const int32_t* col, double invR, const S* state,
-                        int nrows, double* out, hipStream_t s) {
-    if (dim == 2)
-        return dispatch_kernel<2, T, S>(kernel, n, nf, phi, pos, vol, row_ptr, col, invR, state, nrows, out, s);
-    return dispatch_kernel<3, T, S>(kernel, n, nf, phi, pos, vol, row_ptr, col, invR, state, nrows, out, s);
+template <class S>
+static ApplyArgs<S> make_args(const vct_nlist* nl, const Grid& g, int nf, const double* phi, const double* pos,
+                              const double* vol, const S* state, uint32_t mask, double* out) {
+    const int dim = nl->dim;
+    const int64_t ncols = dim == 3 ? g.nc[0] * g.nc[1] : g.nc[0];
+    ApplyArgs<S> a;
+    a.n = nl->n;
+    a.nf = nf;
+    a.nrows = n_out_rows(dim, mask);
+    a.invR = 1.0 / nl->R;
+    a.g = g;
+    a.phi = phi;
+    a.pos = pos;
+    a.vol = vol;
+    a.row_ptr = nl->row_ptr;
+    a.col16 = nl->col16;
+    a.cs = nl->cell_start;
+    a.cstart = nl->chunk_start;
+    a.cinfo = reinterpret_cast<const int4*>(nl->chunk_info);
+    a.nchunks = nl->chunk_off + ncols;
+    a.state = state;
+    a.out = out;
+    return a;
 }
 
 }  // namespace vct
 
 using namespace vct;
 
-extern "C" int vct_apply_ops(int dim, int64_t n, int nf, const double* phi_sorted, const double* pos_sorted,
-                             const double* vol_sorted, const int64_t* row_ptr, const int32_t* col, int kernel,
-                             double R, const void* state, uint32_t out_mask, int precision, double* out,
-                             void* stream) {
-    if ((dim != 2 && dim != 3) || n < 0 || n > INT32_MAX || nf < 1 || !(R > 0.0) || !isfinite(R) ||
-        !mask_valid(out_mask) || (kernel != VCT_KERNEL_WENDLAND_C2 && kernel != VCT_KERNEL_CUBIC_SPLINE) ||
+extern "C" int vct_apply_ops(const vct_nlist* nl, int nf, const double* phi_sorted, const double* pos_sorted,
+                             const double* vol_sorted, int kernel, const void* state, uint32_t out_mask,
+                             int precision, double* out, void* stream) {
+    Grid g;
+    int st = nlist_check(nl, g);
+    if (st) return st;
+    if (nf < 1 || !mask_valid(out_mask) ||
+        (kernel != VCT_KERNEL_WENDLAND_C2 && kernel != VCT_KERNEL_CUBIC_SPLINE) ||
         (precision != VCT_FP64 && precision != VCT_MIXED && precision != VCT_MIXED_S64))
         return VCT_E_ARG;
+    const int64_t n = nl->n;
     if (n == 0) return VCT_OK;
-    if (!phi_sorted || !pos_sorted || !vol_sorted || !row_ptr || !col || !state || !out) return VCT_E_ARG;
-    const int nrows = n_out_rows(dim, out_mask);
-    const double invR = 1.0 / R;
+    if (!phi_sorted || !pos_sorted || !vol_sorted || !nl->col16 || !state || !out) return VCT_E_ARG;
+    const int dim = nl->dim;
+    const int64_t ncols = dim == 3 ? g.nc[0] * g.nc[1] : g.nc[0];
+    const int64_t cap = ncols + n / kChunk + 1;   // upper bound of the chunk count
     hipStream_t s = as_stream(stream);
     switch (precision) {
     case VCT_FP64:
-        return dispatch_dim<double, double>(dim, kernel, n, nf, phi_sorted, pos_sorted, vol_sorted, row_ptr, col,
-                                            invR, static_cast<const double*>(state), nrows, out, s);
+        return dispatch<double, double>(
+            dim, kernel,
+            make_args(nl, g, nf, phi_sorted, pos_sorted, vol_sorted, static_cast<const double*>(state), out_mask, out),
+            cap, s);
     case VCT_MIXED:
-        return dispatch_dim<float, float>(dim, kernel, n, nf, phi_sorted, pos_sorted, vol_sorted, row_ptr, col,
-                                          invR, static_cast<const float*>(state), nrows, out, s);
+        return dispatch<float, float>(
+            dim, kernel,
+            make_args(nl, g, nf, phi_sorted, pos_sorted, vol_sorted, static_cast<const float*>(state), out_mask, out),
+            cap, s);
     default:
-        return dispatch_dim<float, double>(dim, kernel, n, nf, phi_sorted, pos_sorted, vol_sorted, row_ptr, col,
-                                           invR, static_cast<const double*>(state), nrows, out, s);
+        return dispatch<float, double>(
+            dim, kernel,
+            make_args(nl, g, nf, phi_sorted, pos_sorted, vol_sorted, static_cast<const double*>(state), out_mask, out),
+            cap, s);
     }
 }

@@ -7,6 +7,7 @@
 // cells of one (x, y) column are contiguous in memory and each particle's
 // candidates form 3^(d-1) contiguous ranges, visited in increasing order.
 #include "common.h"
+#include "tiles.h"
 
 namespace vct {
 
@@ -187,85 +188,182 @@ __global__ void k_scatter(int64_t n, int ncomp, const int32_t* __restrict__ perm
     for (int c = 0; c < ncomp; ++c) dst[c * n + o] = src[c * n + s];
 }
 
+// ------------------------------------------------------------------ chunk table
+
+// Chunks of one column: ceil(count / kChunk) pieces of consecutive particles.
+template <int D>
+__global__ void k_chunk_count(Grid g, const int64_t* __restrict__ cs, int32_t* __restrict__ nch) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= grid_ncols<D>(g)) return;
+    const int64_t nz = grid_nz<D>(g);
+    const int64_t cnt = cs[col_key<D>(g, c, nz - 1) + 1] - cs[col_key<D>(g, c, 0)];
+    nch[c] = (int32_t)((cnt + kChunk - 1) / kChunk);
+}
+
+// z cell of sorted particle p inside column c (largest z with cs[key(c, z)] <= p)
+template <int D>
+__device__ int64_t z_of(const Grid& g, const int64_t* __restrict__ cs, int64_t c, int64_t p) {
+    int64_t lo = 0, hi = grid_nz<D>(g) - 1;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) / 2;
+        if (cs[col_key<D>(g, c, mid)] <= p) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <int D>
+__global__ void k_chunk_fill(Grid g, int64_t n, const int64_t* __restrict__ cs, const int64_t* __restrict__ off,
+                             int32_t* __restrict__ cstart, int4* __restrict__ cinfo) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t ncols = grid_ncols<D>(g);
+    if (c >= ncols) {
+        if (c == ncols) cstart[off[ncols]] = (int32_t)n;
+        return;
+    }
+    const int64_t nz = grid_nz<D>(g);
+    const int64_t a = cs[col_key<D>(g, c, 0)], e = cs[col_key<D>(g, c, nz - 1) + 1];
+    int64_t b = off[c];
+    for (int64_t p = a; p < e; p += kChunk, ++b) {
+        const int64_t q = (p + kChunk < e ? p + kChunk : e) - 1;
+        cstart[b] = (int32_t)p;
+        cinfo[b] = make_int4((int)c, (int)z_of<D>(g, cs, c, p), (int)z_of<D>(g, cs, c, q), 0);
+    }
+}
+
 // ------------------------------------------------------------------ neighbours
 
 // The neighbour test of Eq. SPH_neighbor_set: d2 summed left to right in FP64
 // with no fused multiply-add (so the sets are reproducible bit for bit).
-template <int D>
-__device__ __forceinline__ bool within(const double* __restrict__ pos, int64_t n, int64_t i, int64_t j,
-                                       double xi0, double xi1, double xi2, double R2) {
+__device__ __forceinline__ bool within_exact(double dx, double dy, double dz, double R2) {
 #pragma clang fp contract(off)
-    double dx = pos[j] - xi0;
-    double dy = pos[n + j] - xi1;
     double d2 = dx * dx;
     d2 = d2 + dy * dy;
-    if (D == 3) {
-        double dz = pos[2 * n + j] - xi2;
-        d2 = d2 + dz * dz;
-    }
-    return d2 < R2 && j != i;
+    d2 = d2 + dz * dz;
+    return d2 < R2;
 }
 
-// One group of G lanes per particle.  FILL = false counts, FILL = true writes
-// the columns in ascending order (ballot compaction within the group).
-template <int D, int G, bool FILL>
-__global__ __launch_bounds__(256) void k_neighbors(int64_t n, const double* __restrict__ pos, Grid g,
-                                                   double R2, const int64_t* __restrict__ cell_start,
-                                                   int32_t* __restrict__ counts,
-                                                   const int64_t* __restrict__ row_ptr,
-                                                   int32_t* __restrict__ col) {
-    constexpr int PER_BLOCK = 256 / G;
-    const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
-    const int lane = threadIdx.x % G;
-    const int64_t i = (int64_t)tile * PER_BLOCK + threadIdx.x / G;
-    const int gshift = (threadIdx.x % kWave) / G * G;
-    const uint64_t gmask = (G == 64) ? ~0ull : (((1ull << G) - 1ull) << gshift);
+constexpr int kNbLanes = 4;                    // lanes per particle
+constexpr int kNbThreads = kChunk * kNbLanes;  // one chunk per work-group
+constexpr int kNbWindow = 2048;                // LDS window capacity (records)
+
+// One chunk per work-group, kNbLanes lanes per particle.  The window positions
+// are staged in LDS as FP32 offsets from the chunk's first particle; a
+// candidate whose FP32 squared distance is inside or outside R^2 by more than
+// a bound on its rounding error is decided by it, and only the few near the
+// support edge are re-tested with the exact FP64 predicate on the stored
+// positions.  FILL = false writes the counts, FILL = true writes the columns
+// (ascending) as sorted indices and/or 16-bit window offsets.
+template <int D, bool FILL>
+__global__ __launch_bounds__(kNbThreads) void k_nb_chunk(int64_t n, const double* __restrict__ pos, Grid g,
+                                                         double R2, const int64_t* __restrict__ cs,
+                                                         const int32_t* __restrict__ cstart,
+                                                         const int4* __restrict__ cinfo,
+                                                         const int64_t* __restrict__ nchunks,
+                                                         int32_t* __restrict__ counts,
+                                                         const int64_t* __restrict__ row_ptr,
+                                                         int32_t* __restrict__ col, uint16_t* __restrict__ col16,
+                                                         int32_t* __restrict__ overflow) {
+    __shared__ float4 win[kNbWindow];
+    __shared__ unsigned int maxoff_bits;
+    const uint32_t b = xcd_tile(blockIdx.x, gridDim.x);
+    if (b >= *nchunks) return;
+    const int64_t p0 = cstart[b], p1 = cstart[b + 1];
+    const int4 info = cinfo[b];
+    __shared__ WindowT<D> w;   // one copy per work-group: runtime-indexed, so kept in LDS
+    if (threadIdx.x == 0) chunk_window<D>(g, cs, info, w);
+    __syncthreads();
+    const int W = w.off[w.nr];
+    const bool in_lds = W <= kNbWindow;
+    const double o0 = pos[p0], o1 = pos[n + p0], o2 = (D == 3) ? pos[2 * n + p0] : 0.0;
+    if (threadIdx.x == 0) maxoff_bits = 0u;
+    __syncthreads();
+    if (in_lds) {
+        float mo = 0.0f;
+        for (int t = threadIdx.x; t < W; t += kNbThreads) {
+            const int64_t j = window_global<D>(w, t);
+            const float4 q = make_float4((float)(pos[j] - o0), (float)(pos[n + j] - o1),
+                                         D == 3 ? (float)(pos[2 * n + j] - o2) : 0.0f, 0.0f);
+            win[t] = q;
+            mo = fmaxf(mo, fmaxf(fabsf(q.x), fmaxf(fabsf(q.y), fabsf(q.z))));
+        }
+        atomicMax(&maxoff_bits, __float_as_uint(mo));   // non-negative floats order as their bits
+    }
+    if (FILL && threadIdx.x == 0 && W > 65535) atomicOr(overflow, 1);
+    __syncthreads();
+    const int lane = threadIdx.x % kNbLanes;
+    const int64_t i = p0 + threadIdx.x / kNbLanes;
+    if (i >= p1) return;   // whole 4-lane groups leave together
+    const int gshift = (threadIdx.x % kWave) / kNbLanes * kNbLanes;
+    const uint64_t gmask = 0xFull << gshift;
     const uint64_t below = (1ull << (threadIdx.x % kWave)) - 1ull;
-    if (i >= n) return;   // whole groups exit together
     const double xi0 = pos[i], xi1 = pos[n + i], xi2 = (D == 3) ? pos[2 * n + i] : 0.0;
-    int64_t c0 = cell_coord(xi0, g.lo[0], g.inv_cs[0], g.nc[0]);
-    int64_t c1 = cell_coord(xi1, g.lo[1], g.inv_cs[1], g.nc[1]);
-    int64_t c2 = (D == 3) ? cell_coord(xi2, g.lo[2], g.inv_cs[2], g.nc[2]) : 0;
+    // LDS path: offsets from the chunk origin; global path: offsets from the particle
+    const float f0 = in_lds ? (float)(xi0 - o0) : 0.0f, f1 = in_lds ? (float)(xi1 - o1) : 0.0f,
+                f2 = in_lds ? (float)(xi2 - o2) : 0.0f;
+    // Absolute bound on the FP32 error of d2: the two rounded offsets of each
+    // component (magnitude at most the window's largest offset), the rounding
+    // of R^2, and of the FP32 products and sums.
+    const double maxoff = in_lds ? (double)__uint_as_float(maxoff_bits) : 0.0;
+    const double R = sqrt(R2);
+    const double margin = 4.0 * (2.0 * R) * (maxoff * 0x1p-23) + R2 * 0x1p-19;
+    const float in_lim = (float)(R2 - margin), out_lim = (float)(R2 + margin);
+    const int64_t nz = grid_nz<D>(g);
+    const int64_t cz = cell_coord(D == 3 ? xi2 : xi1, g.lo[D - 1], g.inv_cs[D - 1], nz);
+    const int64_t zl = cz > 0 ? cz - 1 : 0, zh = cz + 1 < nz ? cz + 1 : nz - 1;
+    int self_t = -1;
     int64_t written = 0;
-    const int64_t out0 = FILL ? row_ptr[i] : 0;
-    const int64_t out1 = FILL ? row_ptr[i + 1] : 0;   // writes never pass the row end
-    // 2-D: axes (x, z) -> cells (c0, c1), z fastest; 3-D: (c0, c1, c2), z fastest
-    const int64_t a_lo = c0 > 0 ? c0 - 1 : 0, a_hi = c0 + 1 < g.nc[0] ? c0 + 1 : g.nc[0] - 1;
-    const int64_t b_lo = (D == 3) ? (c1 > 0 ? c1 - 1 : 0) : 0;
-    const int64_t b_hi = (D == 3) ? (c1 + 1 < g.nc[1] ? c1 + 1 : g.nc[1] - 1) : 0;
-    const int64_t zc = (D == 3) ? c2 : c1;
-    const int64_t nz = (D == 3) ? g.nc[2] : g.nc[1];
-    const int64_t z_lo = zc > 0 ? zc - 1 : 0, z_hi = zc + 1 < nz ? zc + 1 : nz - 1;
-    for (int64_t a = a_lo; a <= a_hi; ++a) {
-        for (int64_t b = b_lo; b <= b_hi; ++b) {
-            int64_t k_lo = (D == 3) ? cell_key(a, b, z_lo, g) : cell_key(a, z_lo, 0, g);
-            int64_t k_hi = (D == 3) ? cell_key(a, b, z_hi, g) : cell_key(a, z_hi, 0, g);
-            const int64_t jb = cell_start[k_lo], je = cell_start[k_hi + 1];
-            for (int64_t base = jb; base < je; base += G) {
-                const int64_t j = base + lane;
-                const bool hit = (j < je) && within<D>(pos, n, i, j, xi0, xi1, xi2, R2);
+    const int64_t out0 = FILL ? row_ptr[i] : 0, out1 = FILL ? row_ptr[i + 1] : 0;
+    // window ranges are the chunk's columns in order; the particle's candidate
+    // cells are the same columns restricted to its z cell +- 1
+    int64_t cx, cy = 0;
+    if (D == 3) { cx = info.x / g.nc[1]; cy = info.x % g.nc[1]; } else cx = info.x;
+    int r = 0;
+    for (int dx = -1; dx <= 1; ++dx) {
+        const int64_t x = cx + dx;
+        if (x < 0 || x >= g.nc[0]) continue;
+        for (int dy = (D == 3 ? -1 : 0); dy <= (D == 3 ? 1 : 0); ++dy) {
+            int64_t colid;
+            if (D == 3) {
+                const int64_t y = cy + dy;
+                if (y < 0 || y >= g.nc[1]) continue;
+                colid = x * g.nc[1] + y;
+            } else {
+                colid = x;
+            }
+            const int64_t ga = cs[col_key<D>(g, colid, zl)], gb = cs[col_key<D>(g, colid, zh) + 1];
+            const int64_t base = (int64_t)w.off[r] - w.gstart[r];   // window offset = sorted index + base
+            if (dx == 0 && dy == 0) self_t = (int)(i + base);
+            const int ta = (int)(ga + base), tb = (int)(gb + base);
+            for (int t0 = ta; t0 < tb; t0 += kNbLanes) {
+                const int t = t0 + lane;
+                bool hit = false;
+                if (t < tb && t != self_t) {
+                    const int64_t j = t - base;
+                    float4 q;
+                    if (in_lds) q = win[t];
+                    else q = make_float4((float)(pos[j] - xi0), (float)(pos[n + j] - xi1),
+                                         D == 3 ? (float)(pos[2 * n + j] - xi2) : 0.0f, 0.0f);
+                    const float ex = q.x - f0, ey = q.y - f1, ez = q.z - f2;
+                    const float d2f = ex * ex + ey * ey + ez * ez;
+                    if (d2f < in_lim) hit = true;
+                    else if (d2f <= out_lim)
+                        hit = within_exact(pos[j] - xi0, pos[n + j] - xi1, D == 3 ? pos[2 * n + j] - xi2 : 0.0, R2);
+                }
                 const uint64_t m = (uint64_t)__ballot(hit) & gmask;
                 if (FILL && hit) {
                     const int64_t at = out0 + written + __popcll(m & below);
-                    if (at < out1) col[at] = (int32_t)j;
+                    if (at < out1) {
+                        if (col) col[at] = (int32_t)(t - base);
+                        if (col16) col16[at] = (uint16_t)t;
+                    }
                 }
                 written += __popcll(m);
             }
+            ++r;
         }
     }
     if (!FILL && lane == 0) counts[i] = (int32_t)written;
-}
-
-template <int D, int G, bool FILL>
-static int launch_neighbors(int64_t n, const double* pos, const Grid& g, double R2,
-                            const int64_t* cell_start, int32_t* counts, const int64_t* row_ptr,
-                            int32_t* col, hipStream_t s) {
-    constexpr int PER_BLOCK = 256 / G;
-    int64_t nb = (n + PER_BLOCK - 1) / PER_BLOCK;
-    hipLaunchKernelGGL((k_neighbors<D, G, FILL>), dim3((unsigned)nb), dim3(256), 0, s, n, pos, g, R2,
-                       cell_start, counts, row_ptr, col);
-    VCT_LAUNCH_CHECK();
-    return VCT_OK;
 }
 
 }  // namespace vct
@@ -355,51 +453,96 @@ extern "C" int vct_scatter_sorted(int64_t n, int ncomp, const int32_t* perm, con
     return VCT_OK;
 }
 
-extern "C" size_t vct_neighbors_workspace_size(int64_t n) {
-    if (n < 0) return 0;
-    return aligned_sum({(size_t)n * 4, scan_ws_bytes(n), 64});
+extern "C" int64_t vct_chunk_capacity(int dim, int64_t n, int64_t ncell) {
+    if ((dim != 2 && dim != 3) || n < 0 || ncell < 1) return 0;
+    return n / kChunk + ncell + 1;
 }
 
-extern "C" int vct_neighbors(int dim, int64_t n, const double* pos_sorted, const double* lo, const double* hi,
-                             double R, const int64_t* cell_start, int64_t ncell, int64_t* row_ptr,
-                             int32_t* col, int64_t col_cap, int64_t* nnz_out, int reuse_row_ptr, void* ws,
-                             size_t ws_bytes, void* stream) {
-    if ((dim != 2 && dim != 3) || n < 0 || n > INT32_MAX || !lo || !hi || !(R > 0.0) || !isfinite(R) ||
-        !row_ptr || !nnz_out || !cell_start)
+extern "C" size_t vct_neighbors_workspace_size(int64_t n, int64_t ncell) {
+    if (n < 0 || ncell < 1) return 0;
+    const int64_t m = n > ncell ? n : ncell;
+    return aligned_sum({(size_t)m * 4, scan_ws_bytes(m), 64});
+}
+
+namespace vct {
+int nlist_check(const vct_nlist* nl, Grid& g) {
+    if (!nl || (nl->dim != 2 && nl->dim != 3) || nl->n < 0 || nl->n > INT32_MAX || !(nl->R > 0.0) ||
+        !isfinite(nl->R) || !nl->cell_start || !nl->row_ptr || !nl->chunk_off || !nl->chunk_start ||
+        !nl->chunk_info || (reinterpret_cast<uintptr_t>(nl->col16) & 15u) != 0)
         return VCT_E_ARG;
-    Grid g;
-    int64_t total = grid_setup(dim, lo, hi, R, g);
+    const int64_t total = grid_setup(nl->dim, nl->lo, nl->hi, nl->R, g);
     if (total < 0) return (int)total;
-    if (ncell != total) return VCT_E_ARG;
-    if (n > 0 && !pos_sorted) return VCT_E_ARG;
-    if (!ws || ws_bytes < vct_neighbors_workspace_size(n)) return VCT_E_WORKSPACE;
+    if (total != nl->ncell || nl->chunk_cap < vct_chunk_capacity(nl->dim, nl->n, nl->ncell)) return VCT_E_ARG;
+    return VCT_OK;
+}
+}  // namespace vct
+
+template <int D>
+static int build_chunks(const vct_nlist* nl, const Grid& g, int32_t* tmp, int64_t* tiles, hipStream_t s) {
+    const int64_t ncols = D == 3 ? g.nc[0] * g.nc[1] : g.nc[0];
+    const unsigned nb = (unsigned)((ncols + 1 + 255) / 256);
+    hipLaunchKernelGGL((k_chunk_count<D>), dim3(nb), dim3(256), 0, s, g, nl->cell_start, tmp);
+    VCT_LAUNCH_CHECK();
+    int st = exclusive_scan(tmp, ncols, nl->chunk_off, tiles, s);
+    if (st) return st;
+    hipLaunchKernelGGL((k_chunk_fill<D>), dim3(nb), dim3(256), 0, s, g, nl->n, nl->cell_start, nl->chunk_off,
+                       nl->chunk_start, reinterpret_cast<int4*>(nl->chunk_info));
+    VCT_LAUNCH_CHECK();
+    return VCT_OK;
+}
+
+template <int D, bool FILL>
+static int launch_nb(const vct_nlist* nl, const double* pos, const Grid& g, int32_t* counts, int32_t* overflow,
+                     hipStream_t s) {
+    const int64_t ncols = D == 3 ? g.nc[0] * g.nc[1] : g.nc[0];
+    const int64_t cap = ncols + nl->n / kChunk + 1;   // upper bound of the chunk count
+    hipLaunchKernelGGL((k_nb_chunk<D, FILL>), dim3((unsigned)cap), dim3(kNbThreads), 0, s, nl->n, pos, g,
+                       nl->R * nl->R, nl->cell_start, nl->chunk_start,
+                       reinterpret_cast<const int4*>(nl->chunk_info), nl->chunk_off + ncols, counts, nl->row_ptr,
+                       nl->col, nl->col16, overflow);
+    VCT_LAUNCH_CHECK();
+    return VCT_OK;
+}
+
+extern "C" int vct_neighbors(vct_nlist* nl, const double* pos_sorted, int64_t col_cap, int64_t* nnz_out,
+                             int reuse_row_ptr, void* ws, size_t ws_bytes, void* stream) {
+    Grid g;
+    int st = nlist_check(nl, g);
+    if (st) return st;
+    if (!nnz_out || (nl->n > 0 && !pos_sorted)) return VCT_E_ARG;
+    const int64_t n = nl->n;
+    if (!ws || ws_bytes < vct_neighbors_workspace_size(n, nl->ncell)) return VCT_E_WORKSPACE;
     hipStream_t s = as_stream(stream);
     Carver cv(ws, ws_bytes);
-    int32_t* counts = cv.take<int32_t>((size_t)n);
-    int64_t* tiles = cv.take<int64_t>(scan_ws_bytes(n) / 8);
-    const double R2 = R * R;
-    int st;
+    const int64_t m = n > nl->ncell ? n : nl->ncell;
+    int32_t* counts = cv.take<int32_t>((size_t)m);
+    int64_t* tiles = cv.take<int64_t>(scan_ws_bytes(m) / 8);
+    int32_t* flag = cv.take<int32_t>(16);
+    const int D = nl->dim;
     if (!reuse_row_ptr) {
+        st = (D == 2) ? build_chunks<2>(nl, g, counts, tiles, s) : build_chunks<3>(nl, g, counts, tiles, s);
+        if (st) return st;
         if (n > 0) {
-            st = (dim == 2) ? launch_neighbors<2, 16, false>(n, pos_sorted, g, R2, cell_start, counts, nullptr,
-                                                             nullptr, s)
-                            : launch_neighbors<3, 64, false>(n, pos_sorted, g, R2, cell_start, counts, nullptr,
-                                                             nullptr, s);
+            st = (D == 2) ? launch_nb<2, false>(nl, pos_sorted, g, counts, flag, s)
+                          : launch_nb<3, false>(nl, pos_sorted, g, counts, flag, s);
             if (st) return st;
         }
-        if ((st = exclusive_scan(counts, n, row_ptr, tiles, s))) return st;
+        if ((st = exclusive_scan(counts, n, nl->row_ptr, tiles, s))) return st;
     }
     int64_t nnz = 0;
-    VCT_HIP_CHECK(hipMemcpyAsync(&nnz, row_ptr + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    VCT_HIP_CHECK(hipMemcpyAsync(&nnz, nl->row_ptr + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     VCT_HIP_CHECK(hipStreamSynchronize(s));
     *nnz_out = nnz;
-    if (!col) return VCT_OK;
+    if (!nl->col && !nl->col16) return VCT_OK;
     if (col_cap < nnz) return VCT_E_CAPACITY;
-    if (nnz > INT32_MAX * 8LL) return VCT_E_CAPACITY;
+    if ((st = fill_i32(flag, 1, 0, s))) return st;
     if (n > 0) {
-        st = (dim == 2) ? launch_neighbors<2, 16, true>(n, pos_sorted, g, R2, cell_start, nullptr, row_ptr, col, s)
-                        : launch_neighbors<3, 64, true>(n, pos_sorted, g, R2, cell_start, nullptr, row_ptr, col, s);
+        st = (D == 2) ? launch_nb<2, true>(nl, pos_sorted, g, nullptr, flag, s)
+                      : launch_nb<3, true>(nl, pos_sorted, g, nullptr, flag, s);
         if (st) return st;
     }
-    return VCT_OK;
+    int32_t hflag = 0;
+    VCT_HIP_CHECK(hipMemcpyAsync(&hflag, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    VCT_HIP_CHECK(hipStreamSynchronize(s));
+    return hflag ? VCT_E_WINDOW : VCT_OK;
 }

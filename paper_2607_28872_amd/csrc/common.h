@@ -200,17 +200,19 @@ __device__ __forceinline__ T kernel_shape(T q) {
         t = t > T(0) ? t : T(0);
         return t * t * t;
     } else {
-        T s = T(2) * q;
-        if (s <= T(1)) return T(3) - T(2.25) * s;
+        // both branches evaluated and one selected (no divergence)
+        const T s = T(2) * q;
+        const T inner = T(3) - T(2.25) * s;
         T t = T(2) - s;
         t = t > T(0) ? t : T(0);
-        return T(0.75) * t * t / s;
+        const T outer = T(0.75) * t * t / s;
+        return s <= T(1) ? inner : outer;
     }
 }
 
 template <class T> __device__ __forceinline__ T vsqrt(T x);
 template <> __device__ __forceinline__ double vsqrt<double>(double x) { return sqrt(x); }
-template <> __device__ __forceinline__ float vsqrt<float>(float x) { return __builtin_sqrtf(x); }
+template <> __device__ __forceinline__ float vsqrt<float>(float x) { return __builtin_amdgcn_sqrtf(x); }
 
 template <class T> __device__ __forceinline__ T vrcp(T x);
 template <> __device__ __forceinline__ double vrcp<double>(double x) { return 1.0 / x; }

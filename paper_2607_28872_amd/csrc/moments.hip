@@ -20,6 +20,7 @@
 // coefficient P_i[o][c] of the physical output in terms of [a; s].
 #include "common.h"
 #include "map_dev.h"
+#include "tiles.h"
 
 namespace vct {
 
@@ -74,92 +75,148 @@ __device__ __forceinline__ double sym_at(const double (&S)[Dims<D>::nL], int a, 
 
 // ------------------------------------------------------------------ kernel 1: sweeps
 
-template <int D, int G, int KERNEL>
-__global__ __launch_bounds__(256) void k_moment_sweeps(int64_t n, const double* __restrict__ pos,
-                                                       const double* __restrict__ vol,
-                                                       const int64_t* __restrict__ row_ptr,
-                                                       const int32_t* __restrict__ col, double invR,
-                                                       double* __restrict__ mom, uint8_t* __restrict__ mflags) {
+constexpr int kMLanes = 4;                    // lanes per particle
+constexpr int kMThreads = kChunk * kMLanes;   // one chunk per work-group
+constexpr int kMWin = 1280;                   // LDS window capacity (records)
+
+struct SweepArgs {
+    int64_t n;
+    double invR;
+    Grid g;
+    const double* pos;
+    const double* vol;
+    const int64_t* row_ptr;
+    const uint16_t* col16;
+    const int64_t* cs;
+    const int32_t* cstart;
+    const int4* cinfo;
+    const int64_t* nchunks;
+    double* mom;
+    uint8_t* mflags;
+};
+
+// One chunk per work-group: the window's positions and volumes are staged in
+// LDS, kMLanes lanes per particle walk its row of window offsets for both
+// sweeps, and the sums are reduced across the group.
+template <int D, int KERNEL>
+__global__ __launch_bounds__(kMThreads) void k_moment_sweeps(SweepArgs A) {
     using Dm = Dims<D>;
     using ML = MomLayout<D>;
-    constexpr int PER_BLOCK = 256 / G;
-    const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
-    const int lane = threadIdx.x % G;
-    const int64_t i = (int64_t)tile * PER_BLOCK + threadIdx.x / G;
-    if (i >= n) return;
+    __shared__ double sx[D][kMWin];
+    __shared__ double sv[kMWin];
+    const uint32_t b = xcd_tile(blockIdx.x, gridDim.x);
+    if (b >= *A.nchunks) return;   // uniform over the work-group
+    const int64_t n = A.n;
+    const int64_t p0 = A.cstart[b], p1 = A.cstart[b + 1];
+    __shared__ WindowT<D> w;   // one copy per work-group: runtime-indexed, so kept in LDS
+    if (threadIdx.x == 0) chunk_window<D>(A.g, A.cs, A.cinfo[b], w);
+    __syncthreads();
+    const int W = w.off[w.nr];
+    const bool in_lds = W <= kMWin;
+    if (in_lds) {
+        for (int t = threadIdx.x; t < W; t += kMThreads) {
+            const int64_t j = window_global<D>(w, t);
+#pragma unroll
+            for (int a = 0; a < D; ++a) sx[a][t] = A.pos[a * n + j];
+            sv[t] = A.vol[j];
+        }
+    }
+    __syncthreads();
+    const int lane = threadIdx.x % kMLanes;
+    const int64_t i = p0 + threadIdx.x / kMLanes;
+    if (i >= p1) return;   // whole groups leave together; no barrier follows
+    auto rec = [&](int t, double (&r)[D], double& q2, double& V) {
+        q2 = 0.0;
+        if (in_lds) {
+#pragma unroll
+            for (int a = 0; a < D; ++a) r[a] = (sx[a][t] - A.pos[a * n + i]) * A.invR;
+            V = sv[t];
+        } else {
+            const int64_t j = window_global<D>(w, t);
+#pragma unroll
+            for (int a = 0; a < D; ++a) r[a] = (A.pos[a * n + j] - A.pos[a * n + i]) * A.invR;
+            V = A.vol[j];
+        }
+#pragma unroll
+        for (int a = 0; a < D; ++a) q2 += r[a] * r[a];
+    };
     double xi[D];
-    for (int a = 0; a < D; ++a) xi[a] = pos[a * n + i];
-    const int64_t rb = row_ptr[i], re = row_ptr[i + 1];
+#pragma unroll
+    for (int a = 0; a < D; ++a) xi[a] = A.pos[a * n + i];
+    const int64_t rb = A.row_ptr[i], re = A.row_ptr[i + 1];
     int fl = 0;
     if (re - rb < D + Dm::m) fl |= VCT_FLAG_FEW;
-    bool fin = isfinite(vol[i]);
+    bool fin = isfinite(A.vol[i]);
+#pragma unroll
     for (int a = 0; a < D; ++a) fin = fin && isfinite(xi[a]);
     if (!fin) fl |= VCT_FLAG_NONFINITE;
 
     // sweep 1: A (pairs) and B (3rd-order monomials), weights V c~
-    double A[Dm::nL], B[Dm::n3];
-    for (int p = 0; p < Dm::nL; ++p) A[p] = 0.0;
+    double Am[Dm::nL], B[Dm::n3];
+#pragma unroll
+    for (int p = 0; p < Dm::nL; ++p) Am[p] = 0.0;
+#pragma unroll
     for (int t = 0; t < Dm::n3; ++t) B[t] = 0.0;
-    for (int64_t k = rb + lane; k < re; k += G) {
-        const int64_t j = col[k];
-        double r[D], q2 = 0.0;
-        for (int a = 0; a < D; ++a) { r[a] = (pos[a * n + j] - xi[a]) * invR; q2 += r[a] * r[a]; }
-        const double V = vol[j];
+    for (int64_t k = rb + lane; k < re; k += kMLanes) {
+        double r[D], q2, V;
+        rec(A.col16[k], r, q2, V);
         if (q2 == 0.0) fl |= VCT_FLAG_DUPLICATE;
         if (!isfinite(q2) || !isfinite(V)) fl |= VCT_FLAG_NONFINITE;
-        const double w = V * kernel_shape<KERNEL>(sqrt(q2));
+        const double wgt = V * kernel_shape<KERNEL>(sqrt(q2));
 #pragma unroll
-        for (int p = 0; p < Dm::nL; ++p) A[p] += w * r[pair_a<D>(p)] * r[pair_b<D>(p)];
+        for (int p = 0; p < Dm::nL; ++p) Am[p] += wgt * r[pair_a<D>(p)] * r[pair_b<D>(p)];
 #pragma unroll
         for (int t = 0; t < Dm::n3; ++t)
-            B[t] += w * r[mono_comp<D, 3>(t, 0)] * r[mono_comp<D, 3>(t, 1)] * r[mono_comp<D, 3>(t, 2)];
+            B[t] += wgt * r[mono_comp<D, 3>(t, 0)] * r[mono_comp<D, 3>(t, 1)] * r[mono_comp<D, 3>(t, 2)];
     }
 #pragma unroll
-    for (int p = 0; p < Dm::nL; ++p) A[p] = group_sum(A[p], G);
+    for (int p = 0; p < Dm::nL; ++p) Am[p] = group_sum(Am[p], kMLanes);
 #pragma unroll
-    for (int t = 0; t < Dm::n3; ++t) B[t] = group_sum(B[t], G);
-    for (int m_ = G >> 1; m_ >= 1; m_ >>= 1) fl |= __shfl_xor(fl, m_, kWave);
+    for (int t = 0; t < Dm::n3; ++t) B[t] = group_sum(B[t], kMLanes);
+    for (int m_ = kMLanes >> 1; m_ >= 1; m_ >>= 1) fl |= __shfl_xor(fl, m_, kWave);
 
     double L[Dm::nL];
-    if (!sym_inverse<D>(A, L)) fl |= VCT_FLAG_SINGULAR_A;
+    if (!sym_inverse<D>(Am, L)) fl |= VCT_FLAG_SINGULAR_A;
+    double L2[Dm::nL];
+#pragma unroll
+    for (int p = 0; p < Dm::nL; ++p) L2[p] = (pair_a<D>(p) == pair_b<D>(p) ? 1.0 : 2.0) * L[p];
 
     // sweep 2: C (3rd order) and E (4th order), weights V F~
     double Cm[Dm::n3], E[Dm::n4];
+#pragma unroll
     for (int t = 0; t < Dm::n3; ++t) Cm[t] = 0.0;
+#pragma unroll
     for (int t = 0; t < Dm::n4; ++t) E[t] = 0.0;
     if (!fl) {
-        for (int64_t k = rb + lane; k < re; k += G) {
-            const int64_t j = col[k];
-            double r[D], q2 = 0.0;
-            for (int a = 0; a < D; ++a) { r[a] = (pos[a * n + j] - xi[a]) * invR; q2 += r[a] * r[a]; }
+        for (int64_t k = rb + lane; k < re; k += kMLanes) {
+            double r[D], q2, V;
+            rec(A.col16[k], r, q2, V);
             double rLr = 0.0;
 #pragma unroll
-            for (int p = 0; p < Dm::nL; ++p)
-                rLr += (pair_a<D>(p) == pair_b<D>(p) ? 1.0 : 2.0) * L[p] * r[pair_a<D>(p)] * r[pair_b<D>(p)];
-            const double F = kernel_shape<KERNEL>(sqrt(q2)) * rLr / (q2 * q2);
-            const double w = vol[j] * F;
+            for (int p = 0; p < Dm::nL; ++p) rLr += L2[p] * r[pair_a<D>(p)] * r[pair_b<D>(p)];
+            const double wgt = V * kernel_shape<KERNEL>(sqrt(q2)) * rLr / (q2 * q2);
 #pragma unroll
             for (int t = 0; t < Dm::n3; ++t)
-                Cm[t] += w * r[mono_comp<D, 3>(t, 0)] * r[mono_comp<D, 3>(t, 1)] * r[mono_comp<D, 3>(t, 2)];
+                Cm[t] += wgt * r[mono_comp<D, 3>(t, 0)] * r[mono_comp<D, 3>(t, 1)] * r[mono_comp<D, 3>(t, 2)];
 #pragma unroll
             for (int t = 0; t < Dm::n4; ++t)
-                E[t] += w * r[mono_comp<D, 4>(t, 0)] * r[mono_comp<D, 4>(t, 1)] * r[mono_comp<D, 4>(t, 2)] *
+                E[t] += wgt * r[mono_comp<D, 4>(t, 0)] * r[mono_comp<D, 4>(t, 1)] * r[mono_comp<D, 4>(t, 2)] *
                         r[mono_comp<D, 4>(t, 3)];
         }
     }
 #pragma unroll
-    for (int t = 0; t < Dm::n3; ++t) Cm[t] = group_sum(Cm[t], G);
+    for (int t = 0; t < Dm::n3; ++t) Cm[t] = group_sum(Cm[t], kMLanes);
 #pragma unroll
-    for (int t = 0; t < Dm::n4; ++t) E[t] = group_sum(E[t], G);
+    for (int t = 0; t < Dm::n4; ++t) E[t] = group_sum(E[t], kMLanes);
 
     // each lane stores a share of the sums (all lanes hold all of them)
 #pragma unroll
     for (int v = 0; v < ML::total; ++v) {
-        if (v % G != lane) continue;
-        double x = v < ML::oB ? L[v] : v < ML::oC ? B[v - ML::oB] : v < ML::oE ? Cm[v - ML::oC] : E[v - ML::oE];
-        mom[(int64_t)v * n + i] = x;
+        if (v % kMLanes != lane) continue;
+        const double x = v < ML::oB ? L[v] : v < ML::oC ? B[v - ML::oB] : v < ML::oE ? Cm[v - ML::oC] : E[v - ML::oE];
+        A.mom[(int64_t)v * n + i] = x;
     }
-    if (lane == 0) mflags[i] = (uint8_t)fl;
+    if (lane == 0) A.mflags[i] = (uint8_t)fl;
 }
 
 // ------------------------------------------------------------------ kernel 2: solve + fold
@@ -400,16 +457,20 @@ __global__ __launch_bounds__(256) void k_moment_solve(int64_t n, const double* _
     if (fl && nflag) atomicAdd(nflag, 1ull);
 }
 
+int nlist_check(const vct_nlist* nl, Grid& g);
+
 template <int D, int KERNEL>
-static int launch_moments(int64_t n, const double* pos, const double* vol, const int64_t* row_ptr,
-                          const int32_t* col, double invR, const MapParams& mp, uint32_t mask, int nrows,
-                          double* mom, uint8_t* mflags, double* s64, float* s32, uint8_t* flags,
-                          unsigned long long* nflag, hipStream_t s) {
-    constexpr int G = (D == 3) ? 16 : 8;
-    constexpr int PER_BLOCK = 256 / G;
-    int64_t nb1 = (n + PER_BLOCK - 1) / PER_BLOCK;
-    hipLaunchKernelGGL((k_moment_sweeps<D, G, KERNEL>), dim3((unsigned)nb1), dim3(256), 0, s, n, pos, vol,
-                       row_ptr, col, invR, mom, mflags);
+static int launch_moments(const vct_nlist* nl, const Grid& g, const double* pos, const double* vol, double invR,
+                          const MapParams& mp, uint32_t mask, int nrows, double* mom, uint8_t* mflags, double* s64,
+                          float* s32, uint8_t* flags, unsigned long long* nflag, hipStream_t s) {
+    const int64_t n = nl->n;
+    const int64_t ncols = D == 3 ? g.nc[0] * g.nc[1] : g.nc[0];
+    SweepArgs a;
+    a.n = n; a.invR = invR; a.g = g; a.pos = pos; a.vol = vol; a.row_ptr = nl->row_ptr; a.col16 = nl->col16;
+    a.cs = nl->cell_start; a.cstart = nl->chunk_start; a.cinfo = reinterpret_cast<const int4*>(nl->chunk_info);
+    a.nchunks = nl->chunk_off + ncols; a.mom = mom; a.mflags = mflags;
+    const int64_t cap = ncols + n / kChunk + 1;
+    hipLaunchKernelGGL((k_moment_sweeps<D, KERNEL>), dim3((unsigned)cap), dim3(kMThreads), 0, s, a);
     VCT_LAUNCH_CHECK();
     int64_t nb2 = (n + 127) / 128;
     hipLaunchKernelGGL((k_moment_solve<D>), dim3((unsigned)nb2), dim3(128), 0, s, n, pos, mom, mflags, invR, mp,
@@ -430,17 +491,20 @@ extern "C" size_t vct_moments_workspace_size(int dim, int64_t n) {
 
 __global__ void k_zero_u64(unsigned long long* p) { *p = 0ull; }
 
-extern "C" int vct_moments(int dim, int64_t n, const double* pos_sorted, const double* vol_sorted,
-                           const int64_t* row_ptr, const int32_t* col, int kernel, double R, const vct_map* map,
-                           uint32_t out_mask, double* state64, float* state32, uint8_t* flags,
+extern "C" int vct_moments(const vct_nlist* nl, const double* pos_sorted, const double* vol_sorted, int kernel,
+                           const vct_map* map, uint32_t out_mask, double* state64, float* state32, uint8_t* flags,
                            int64_t* n_flagged, void* ws, size_t ws_bytes, void* stream) {
-    if ((dim != 2 && dim != 3) || n < 0 || n > INT32_MAX || !(R > 0.0) || !isfinite(R) || !map ||
-        !mask_valid(out_mask) || (kernel != VCT_KERNEL_WENDLAND_C2 && kernel != VCT_KERNEL_CUBIC_SPLINE))
+    Grid g;
+    int st = nlist_check(nl, g);
+    if (st) return st;
+    const int dim = nl->dim;
+    const int64_t n = nl->n;
+    if (!map || !mask_valid(out_mask) || (kernel != VCT_KERNEL_WENDLAND_C2 && kernel != VCT_KERNEL_CUBIC_SPLINE))
         return VCT_E_ARG;
     MapParams mp;
-    int st = map_params_from(map, dim, mp);
+    st = map_params_from(map, dim, mp);
     if (st) return st;
-    if (n > 0 && (!pos_sorted || !vol_sorted || !row_ptr || !col || !state64)) return VCT_E_ARG;
+    if (n > 0 && (!pos_sorted || !vol_sorted || !nl->col16 || !state64)) return VCT_E_ARG;
     if (!ws || ws_bytes < vct_moments_workspace_size(dim, n)) return VCT_E_WORKSPACE;
     hipStream_t s = as_stream(stream);
     Carver cv(ws, ws_bytes);
@@ -451,24 +515,20 @@ extern "C" int vct_moments(int dim, int64_t n, const double* pos_sorted, const d
     hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, s, cnt);
     VCT_LAUNCH_CHECK();
     if (n > 0) {
-        const double invR = 1.0 / R;
+        const double invR = 1.0 / nl->R;
         const int nrows = n_out_rows(dim, out_mask);
         if (dim == 2)
             st = (kernel == VCT_KERNEL_WENDLAND_C2)
-                     ? launch_moments<2, VCT_KERNEL_WENDLAND_C2>(n, pos_sorted, vol_sorted, row_ptr, col, invR, mp,
-                                                                 out_mask, nrows, mom, mflags, state64, state32,
-                                                                 flags, cnt, s)
-                     : launch_moments<2, VCT_KERNEL_CUBIC_SPLINE>(n, pos_sorted, vol_sorted, row_ptr, col, invR, mp,
-                                                                  out_mask, nrows, mom, mflags, state64, state32,
-                                                                  flags, cnt, s);
+                     ? launch_moments<2, VCT_KERNEL_WENDLAND_C2>(nl, g, pos_sorted, vol_sorted, invR, mp, out_mask,
+                                                                 nrows, mom, mflags, state64, state32, flags, cnt, s)
+                     : launch_moments<2, VCT_KERNEL_CUBIC_SPLINE>(nl, g, pos_sorted, vol_sorted, invR, mp, out_mask,
+                                                                  nrows, mom, mflags, state64, state32, flags, cnt, s);
         else
             st = (kernel == VCT_KERNEL_WENDLAND_C2)
-                     ? launch_moments<3, VCT_KERNEL_WENDLAND_C2>(n, pos_sorted, vol_sorted, row_ptr, col, invR, mp,
-                                                                 out_mask, nrows, mom, mflags, state64, state32,
-                                                                 flags, cnt, s)
-                     : launch_moments<3, VCT_KERNEL_CUBIC_SPLINE>(n, pos_sorted, vol_sorted, row_ptr, col, invR, mp,
-                                                                  out_mask, nrows, mom, mflags, state64, state32,
-                                                                  flags, cnt, s);
+                     ? launch_moments<3, VCT_KERNEL_WENDLAND_C2>(nl, g, pos_sorted, vol_sorted, invR, mp, out_mask,
+                                                                 nrows, mom, mflags, state64, state32, flags, cnt, s)
+                     : launch_moments<3, VCT_KERNEL_CUBIC_SPLINE>(nl, g, pos_sorted, vol_sorted, invR, mp, out_mask,
+                                                                  nrows, mom, mflags, state64, state32, flags, cnt, s);
         if (st) return st;
     }
     if (n_flagged) {

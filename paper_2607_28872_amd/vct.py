@@ -20,7 +20,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libvct.so")
 
 VCT_OK, VCT_W_FLAGGED = 0, 1
-VCT_E_ARG, VCT_E_HIP, VCT_E_CAPACITY, VCT_E_NONFINITE, VCT_E_WORKSPACE = -1, -2, -3, -4, -5
+VCT_E_ARG, VCT_E_HIP, VCT_E_CAPACITY, VCT_E_NONFINITE, VCT_E_WORKSPACE, VCT_E_WINDOW = -1, -2, -3, -4, -5, -6
 VCT_KERNEL_WENDLAND_C2, VCT_KERNEL_CUBIC_SPLINE = 0, 1
 VCT_FP64, VCT_MIXED, VCT_MIXED_S64 = 0, 1, 2
 VCT_OUT_GRAD, VCT_OUT_LAP, VCT_OUT_CROSS, VCT_OUT_HESS, VCT_OUT_PGRAD, VCT_OUT_PHESS = 1, 2, 4, 8, 16, 32
@@ -46,8 +46,16 @@ class vct_map(C.Structure):
                 ("dmin", C.c_double), ("eps", C.c_double), ("terms", C.POINTER(vct_term))]
 
 
+class vct_nlist(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("reserved", C.c_int32), ("n", C.c_int64), ("ncell", C.c_int64),
+                ("chunk_cap", C.c_int64), ("lo", C.c_double * 3), ("hi", C.c_double * 3), ("R", C.c_double),
+                ("cell_start", C.c_void_p), ("chunk_off", C.c_void_p), ("chunk_start", C.c_void_p),
+                ("chunk_info", C.c_void_p), ("row_ptr", C.c_void_p), ("col", C.c_void_p), ("col16", C.c_void_p)]
+
+
 _lib = None
 _vp, _i64, _sz, _dp = C.c_void_p, C.c_int64, C.c_size_t, C.POINTER(C.c_double)
+_nlp = C.POINTER(vct_nlist)
 
 
 def lib():
@@ -76,24 +84,24 @@ def lib():
         L.vct_gather_sorted.argtypes = [_i64, C.c_int, _vp, _vp, _vp, _vp]
         L.vct_scatter_sorted.restype = C.c_int
         L.vct_scatter_sorted.argtypes = [_i64, C.c_int, _vp, _vp, _vp, _vp]
+        L.vct_chunk_capacity.restype = _i64
+        L.vct_chunk_capacity.argtypes = [C.c_int, _i64, _i64]
         L.vct_neighbors_workspace_size.restype = _sz
-        L.vct_neighbors_workspace_size.argtypes = [_i64]
+        L.vct_neighbors_workspace_size.argtypes = [_i64, _i64]
         L.vct_neighbors.restype = C.c_int
-        L.vct_neighbors.argtypes = [C.c_int, _i64, _vp, _dp, _dp, C.c_double, _vp, _i64, _vp, _vp, _i64,
-                                    C.POINTER(_i64), C.c_int, _vp, _sz, _vp]
+        L.vct_neighbors.argtypes = [_nlp, _vp, _i64, C.POINTER(_i64), C.c_int, _vp, _sz, _vp]
         L.vct_moments_workspace_size.restype = _sz
         L.vct_moments_workspace_size.argtypes = [C.c_int, _i64]
         L.vct_moments.restype = C.c_int
-        L.vct_moments.argtypes = [C.c_int, _i64, _vp, _vp, _vp, _vp, C.c_int, C.c_double, C.POINTER(vct_map),
-                                  C.c_uint32, _vp, _vp, _vp, C.POINTER(_i64), _vp, _sz, _vp]
+        L.vct_moments.argtypes = [_nlp, _vp, _vp, C.c_int, C.POINTER(vct_map), C.c_uint32, _vp, _vp, _vp,
+                                  C.POINTER(_i64), _vp, _sz, _vp]
         L.vct_apply_ops.restype = C.c_int
-        L.vct_apply_ops.argtypes = [C.c_int, _i64, C.c_int, _vp, _vp, _vp, _vp, _vp, C.c_int, C.c_double, _vp,
-                                    C.c_uint32, C.c_int, _vp, _vp]
+        L.vct_apply_ops.argtypes = [_nlp, C.c_int, _vp, _vp, _vp, C.c_int, _vp, C.c_uint32, C.c_int, _vp, _vp]
         L.vct_adjoint_workspace_size.restype = _sz
         L.vct_adjoint_workspace_size.argtypes = [C.c_int, _i64, C.c_int]
         L.vct_apply_ops_adjoint.restype = C.c_int
-        L.vct_apply_ops_adjoint.argtypes = [C.c_int, _i64, _vp, _vp, _vp, _vp, C.c_int, C.c_double, _vp,
-                                            C.c_uint32, C.POINTER(vct_map), _vp, _vp, _vp, _vp, _vp, _sz, _vp]
+        L.vct_apply_ops_adjoint.argtypes = [_nlp, _vp, _vp, C.c_int, _vp, C.c_uint32, C.POINTER(vct_map), _vp, _vp,
+                                            _vp, _vp, _vp, _sz, _vp]
         _lib = L
     return _lib
 
@@ -162,7 +170,7 @@ def vct_state_stride(dim, mask):
 def vct_build_cells(dim, n, pos, lo, hi, R, perm, pos_sorted, cell_start, ncell, ws, stream=None):
     return _check("vct_build_cells", lib().vct_build_cells(
         dim, n, _p(pos), _d3(lo), _d3(hi), float(R), _p(perm), _p(pos_sorted), _p(cell_start), ncell, _p(ws),
-        0 if ws is None else ws.numel() * ws.element_size(), _stream(stream)))
+        _nbytes(ws), _stream(stream)))
 
 
 def vct_gather_sorted(n, ncomp, perm, src, dst, stream=None):
@@ -175,42 +183,58 @@ def vct_scatter_sorted(n, ncomp, perm, src, dst, stream=None):
                                                                   _stream(stream)))
 
 
-def vct_neighbors(dim, n, pos_sorted, lo, hi, R, cell_start, ncell, row_ptr, col, col_cap, reuse, ws,
-                  stream=None):
+def _nbytes(t):
+    return 0 if t is None else t.numel() * t.element_size()
+
+
+def make_nlist(dim, n, ncell, lo, hi, R, cell_start, chunk_off, chunk_start, chunk_info, row_ptr, col=None,
+               col16=None, chunk_cap=None):
+    """vct_nlist over torch tensors (device)."""
+    nl = vct_nlist()
+    nl.dim, nl.n, nl.ncell = int(dim), int(n), int(ncell)
+    nl.chunk_cap = int(chunk_cap if chunk_cap is not None else chunk_start.numel() - 1)
+    for k in range(3):
+        nl.lo[k] = float(lo[k]) if k < len(lo) else 0.0
+        nl.hi[k] = float(hi[k]) if k < len(hi) else 0.0
+    nl.R = float(R)
+    nl.cell_start, nl.chunk_off, nl.chunk_start = cell_start.data_ptr(), chunk_off.data_ptr(), chunk_start.data_ptr()
+    nl.chunk_info, nl.row_ptr = chunk_info.data_ptr(), row_ptr.data_ptr()
+    nl.col = col.data_ptr() if col is not None else None
+    nl.col16 = col16.data_ptr() if col16 is not None else None
+    return nl
+
+
+def vct_neighbors(nl, pos_sorted, col_cap, reuse, ws, stream=None):
     nnz = _i64(0)
-    st = lib().vct_neighbors(dim, n, _p(pos_sorted), _d3(lo), _d3(hi), float(R), _p(cell_start), ncell,
-                             _p(row_ptr), _p(col), int(col_cap), C.byref(nnz), int(reuse), _p(ws),
-                             0 if ws is None else ws.numel() * ws.element_size(), _stream(stream))
+    st = lib().vct_neighbors(C.byref(nl), _p(pos_sorted), int(col_cap), C.byref(nnz), int(reuse), _p(ws),
+                             _nbytes(ws), _stream(stream))
     if st == VCT_E_CAPACITY:
         return st, nnz.value
     _check("vct_neighbors", st)
     return st, nnz.value
 
 
-def vct_moments(dim, n, pos_sorted, vol_sorted, row_ptr, col, kernel, R, cmap, mask, state64, state32, flags,
-                count_flagged, ws, stream=None):
+def vct_moments(nl, pos_sorted, vol_sorted, kernel, cmap, mask, state64, state32, flags, count_flagged, ws,
+                stream=None):
     cnt = _i64(0)
-    st = lib().vct_moments(dim, n, _p(pos_sorted), _p(vol_sorted), _p(row_ptr), _p(col), kernel, float(R),
-                           C.byref(cmap), mask, _p(state64), _p(state32), _p(flags),
-                           C.byref(cnt) if count_flagged else None, _p(ws),
-                           0 if ws is None else ws.numel() * ws.element_size(), _stream(stream))
+    st = lib().vct_moments(C.byref(nl), _p(pos_sorted), _p(vol_sorted), kernel, C.byref(cmap), mask, _p(state64),
+                           _p(state32), _p(flags), C.byref(cnt) if count_flagged else None, _p(ws), _nbytes(ws),
+                           _stream(stream))
     _check("vct_moments", st)
     return st, cnt.value
 
 
-def vct_apply_ops(dim, n, nf, phi_sorted, pos_sorted, vol_sorted, row_ptr, col, kernel, R, state, mask,
-                  precision, out, stream=None):
+def vct_apply_ops(nl, nf, phi_sorted, pos_sorted, vol_sorted, kernel, state, mask, precision, out, stream=None):
     return _check("vct_apply_ops", lib().vct_apply_ops(
-        dim, n, nf, _p(phi_sorted), _p(pos_sorted), _p(vol_sorted), _p(row_ptr), _p(col), kernel, float(R),
-        _p(state), mask, precision, _p(out), _stream(stream)))
+        C.byref(nl), nf, _p(phi_sorted), _p(pos_sorted), _p(vol_sorted), kernel, _p(state), mask, precision, _p(out),
+        _stream(stream)))
 
 
-def vct_apply_ops_adjoint(dim, n, pos_sorted, vol_sorted, row_ptr, col, kernel, R, state64, mask, cmap,
-                          phi_sorted, u, dphi, dtheta, ws, stream=None):
+def vct_apply_ops_adjoint(nl, pos_sorted, vol_sorted, kernel, state64, mask, cmap, phi_sorted, u, dphi, dtheta, ws,
+                          stream=None):
     return _check("vct_apply_ops_adjoint", lib().vct_apply_ops_adjoint(
-        dim, n, _p(pos_sorted), _p(vol_sorted), _p(row_ptr), _p(col), kernel, float(R), _p(state64), mask,
-        C.byref(cmap), _p(phi_sorted), _p(u), _p(dphi), _p(dtheta), _p(ws),
-        0 if ws is None else ws.numel() * ws.element_size(), _stream(stream)))
+        C.byref(nl), _p(pos_sorted), _p(vol_sorted), kernel, _p(state64), mask, C.byref(cmap), _p(phi_sorted), _p(u),
+        _p(dphi), _p(dtheta), _p(ws), _nbytes(ws), _stream(stream)))
 
 
 # ---------------------------------------------------------------- orchestration
@@ -225,7 +249,7 @@ class Geometry:
     state.  Positions are projected coordinates (dim, n) in the caller's order;
     `perm` maps sorted -> original."""
 
-    def __init__(self, pos, vol, lo, hi, R, kernel=VCT_KERNEL_WENDLAND_C2, device="cuda"):
+    def __init__(self, pos, vol, lo, hi, R, kernel=VCT_KERNEL_WENDLAND_C2, device="cuda", keep_col=True):
         import torch
         pos = torch.as_tensor(pos, dtype=torch.float64, device=device).contiguous()
         vol = torch.as_tensor(vol, dtype=torch.float64, device=device).contiguous()
@@ -242,13 +266,21 @@ class Geometry:
         if n:
             vct_gather_sorted(n, 1, self.perm, vol, self.vol)
         self.row_ptr = torch.empty(n + 1, dtype=torch.int64, device=device)
-        self._nws = _bytes(lib().vct_neighbors_workspace_size(n), device)
-        _, nnz = vct_neighbors(self.dim, n, self.pos, lo, hi, R, self.cell_start, self.ncell, self.row_ptr,
-                               None, 0, 0, self._nws)
+        ncols = self.dims[0] * self.dims[1] if self.dim == 3 else self.dims[0]
+        cap = lib().vct_chunk_capacity(self.dim, n, self.ncell)
+        self.chunk_off = torch.empty(ncols + 1, dtype=torch.int64, device=device)
+        self.chunk_start = torch.empty(cap + 1, dtype=torch.int32, device=device)
+        self.chunk_info = torch.empty((cap, 4), dtype=torch.int32, device=device)
+        self._nws = _bytes(lib().vct_neighbors_workspace_size(n, self.ncell), device)
+        nl = make_nlist(self.dim, n, self.ncell, lo, hi, R, self.cell_start, self.chunk_off, self.chunk_start,
+                        self.chunk_info, self.row_ptr, chunk_cap=cap)
+        _, nnz = vct_neighbors(nl, self.pos, 0, 0, self._nws)
         self.nnz = nnz
-        self.col = torch.empty(max(nnz, 1), dtype=torch.int32, device=device)
-        vct_neighbors(self.dim, n, self.pos, lo, hi, R, self.cell_start, self.ncell, self.row_ptr, self.col,
-                      self.col.numel(), 1, self._nws)
+        self.col = torch.empty(max(nnz, 1), dtype=torch.int32, device=device) if keep_col else None
+        self.col16 = torch.empty(max(nnz, 1), dtype=torch.uint16, device=device)
+        self.nl = make_nlist(self.dim, n, self.ncell, lo, hi, R, self.cell_start, self.chunk_off, self.chunk_start,
+                             self.chunk_info, self.row_ptr, self.col, self.col16, chunk_cap=cap)
+        vct_neighbors(self.nl, self.pos, max(nnz, 1), 1, self._nws)
         self.state64 = self.state32 = self.flags = None
         self.mask = None
 
@@ -283,8 +315,8 @@ class Geometry:
         self.state32 = torch.empty((stride, max(n, 1)), dtype=torch.float32, device=self.device) if fp32_copy else None
         self.flags = torch.empty(max(n, 1), dtype=torch.uint8, device=self.device)
         ws = _bytes(lib().vct_moments_workspace_size(dim, n), self.device)
-        st, nflag = vct_moments(dim, n, self.pos, self.vol, self.row_ptr, self.col, self.kernel, self.R, self.cmap,
-                                mask, self.state64, self.state32, self.flags, count_flagged, ws)
+        st, nflag = vct_moments(self.nl, self.pos, self.vol, self.kernel, self.cmap, mask, self.state64, self.state32,
+                                self.flags, count_flagged, ws)
         self.n_flagged = nflag
         return st
 
@@ -297,8 +329,7 @@ class Geometry:
         state = self.state32 if precision == VCT_MIXED else self.state64
         if state is None:
             raise ValueError("VCT_MIXED needs moments(..., fp32_copy=True)")
-        vct_apply_ops(self.dim, self.n, nf, phi_sorted, self.pos, self.vol, self.row_ptr, self.col, self.kernel,
-                      self.R, state, self.mask, precision, out)
+        vct_apply_ops(self.nl, nf, phi_sorted, self.pos, self.vol, self.kernel, state, self.mask, precision, out)
         return out
 
     def adjoint(self, u_sorted, phi_sorted=None, want_dtheta=True):
@@ -307,8 +338,8 @@ class Geometry:
         dphi = torch.empty(max(self.n, 1), dtype=torch.float64, device=self.device)
         dth = torch.empty(max(nt, 1), dtype=torch.float64, device=self.device) if want_dtheta else None
         ws = _bytes(lib().vct_adjoint_workspace_size(self.dim, self.n, nt), self.device)
-        vct_apply_ops_adjoint(self.dim, self.n, self.pos, self.vol, self.row_ptr, self.col, self.kernel, self.R,
-                              self.state64, self.mask, self.cmap, phi_sorted, u_sorted, dphi, dth, ws)
+        vct_apply_ops_adjoint(self.nl, self.pos, self.vol, self.kernel, self.state64, self.mask, self.cmap, phi_sorted,
+                              u_sorted, dphi, dth, ws)
         return dphi[: self.n], (dth[:nt] if dth is not None else None)
 
     def csr_original(self):

@@ -67,6 +67,20 @@ def _dp3(v):
     return a
 
 
+def _nlist(dim=3, n=10, ncell=None, R=0.25, cap=None):
+    lo, hi = (0.0, 0.0, 0.0), (1.0, 1.0, 1.0)
+    nc = ncell if ncell is not None else vct.vct_grid_dims(dim, lo, hi, R)[0]
+    nl = vct.vct_nlist()
+    nl.dim, nl.n, nl.ncell, nl.R = dim, n, nc, R
+    nl.chunk_cap = cap if cap is not None else vct.lib().vct_chunk_capacity(dim, n, nc)
+    for k in range(3):
+        nl.lo[k], nl.hi[k] = lo[k], hi[k]
+    # non-null placeholders: only argument checks run, nothing is dereferenced
+    for f in ("cell_start", "chunk_off", "chunk_start", "chunk_info", "row_ptr"):
+        setattr(nl, f, 256)
+    return nl
+
+
 def test_argument_errors_are_caught_on_the_host(L):
     lo, hi = _dp3((0, 0, 0)), _dp3((1, 1, 1))
     E = vct.VCT_E_ARG
@@ -74,25 +88,37 @@ def test_argument_errors_are_caught_on_the_host(L):
     assert L.vct_build_cells(3, -1, None, lo, hi, 0.1, None, None, None, 1000, None, 0, None) == E
     assert L.vct_build_cells(3, 10, None, lo, hi, 0.1, None, None, None, 999, None, 0, None) == E  # wrong ncell
     nnz = C.c_int64(0)
-    assert L.vct_neighbors(3, 10, None, lo, hi, 0.1, None, 1000, None, None, 0, C.byref(nnz), 0, None, 0,
-                           None) == E
+    assert L.vct_neighbors(None, None, 0, C.byref(nnz), 0, None, 0, None) == E
+    bad = _nlist()
+    bad.dim = 4
+    assert L.vct_neighbors(C.byref(bad), None, 0, C.byref(nnz), 0, None, 0, None) == E
+    short = _nlist()
+    short.chunk_cap = 1                               # chunk arrays too small
+    assert L.vct_neighbors(C.byref(short), None, 0, C.byref(nnz), 0, None, 0, None) == E
+    wrong = _nlist(ncell=7)                           # cell count inconsistent with the box and R
+    assert L.vct_neighbors(C.byref(wrong), None, 0, C.byref(nnz), 0, None, 0, None) == E
+    odd = _nlist()
+    odd.col16 = 258                                   # col16 must be 16-byte aligned
+    assert L.vct_neighbors(C.byref(odd), None, 0, C.byref(nnz), 0, None, 0, None) == E
+    nl = _nlist()
+    assert L.vct_neighbors(C.byref(nl), None, 0, C.byref(nnz), 0, None, 0, None) == E   # no positions
     m = vct.make_map(__import__("paper_2607_28872_amd.inputs", fromlist=["MapSpec"]).MapSpec())
-    assert L.vct_moments(3, 10, None, None, None, None, 0, 0.1, C.byref(m), 0, None, None, None, None, None, 0,
+    assert L.vct_moments(C.byref(nl), None, None, 0, C.byref(m), 0, None, None, None, None, None, 0,
                          None) == E              # empty output mask
-    assert L.vct_moments(3, 10, None, None, None, None, 7, 0.1, C.byref(m), 3, None, None, None, None, None, 0,
+    assert L.vct_moments(C.byref(nl), None, None, 7, C.byref(m), 3, None, None, None, None, None, 0,
                          None) == E              # unknown kernel
-    bad = vct.vct_map(9, 0, 1.0, 1.0, 0.0, 0.0, None)
-    assert L.vct_moments(3, 10, None, None, None, None, 0, 0.1, C.byref(bad), 3, None, None, None, None, None,
-                         0, None) == E           # unknown map kind
+    badm = vct.vct_map(9, 0, 1.0, 1.0, 0.0, 0.0, None)
+    assert L.vct_moments(C.byref(nl), None, None, 0, C.byref(badm), 3, None, None, None, None, None, 0,
+                         None) == E              # unknown map kind
     sig = vct.vct_map(4, 0, -1.0, 0.0, 0.0, 0.0, None)
-    assert L.vct_moments(3, 10, None, None, None, None, 0, 0.1, C.byref(sig), 3, None, None, None, None, None,
-                         0, None) == E           # sigma with Hhat <= 0
-    assert L.vct_apply_ops(3, 10, 0, None, None, None, None, None, 0, 0.1, None, 3, 0, None, None) == E  # nf
-    assert L.vct_apply_ops(3, 10, 1, None, None, None, None, None, 0, 0.1, None, 3, 5, None, None) == E  # prec
-    assert L.vct_apply_ops(3, 10, 1, None, None, None, None, None, 0, 0.1, None, 3, 0, None, None) == E  # nulls
-    # adjoint needs LAP | PGRAD | PHESS rows in the state
-    assert L.vct_apply_ops_adjoint(3, 10, None, None, None, None, 0, 0.1, None, vct.VCT_OUT_DEFAULT, C.byref(m),
-                                   None, None, None, None, None, 0, None) == E
+    assert L.vct_moments(C.byref(nl), None, None, 0, C.byref(sig), 3, None, None, None, None, None, 0,
+                         None) == E              # sigma with Hhat <= 0
+    assert L.vct_apply_ops(C.byref(nl), 0, None, None, None, 0, None, 3, 0, None, None) == E   # nf
+    assert L.vct_apply_ops(C.byref(nl), 1, None, None, None, 0, None, 3, 5, None, None) == E   # precision
+    assert L.vct_apply_ops(C.byref(nl), 1, None, None, None, 0, None, 3, 0, None, None) == E   # null arrays
+    # the adjoint needs LAP | PGRAD | PHESS rows in the state
+    assert L.vct_apply_ops_adjoint(C.byref(nl), None, None, 0, None, vct.VCT_OUT_DEFAULT, C.byref(m), None, None,
+                                   None, None, None, 0, None) == E
 
 
 def test_workspace_errors(L):
@@ -101,9 +127,14 @@ def test_workspace_errors(L):
     nc, _ = vct.vct_grid_dims(3, (0, 0, 0), (1, 1, 1), 0.25)
     assert L.vct_build_cells(3, 0, None, lo, hi, 0.25, None, None, C.c_void_p(16), nc, None, 0,
                              None) == vct.VCT_E_WORKSPACE
+    nl = _nlist()
+    nnz = C.c_int64(0)
+    assert L.vct_neighbors(C.byref(nl), C.c_void_p(256), 0, C.byref(nnz), 0, None, 0,
+                           None) == vct.VCT_E_WORKSPACE
     assert L.vct_build_cells_workspace_size(3, 100, nc) > 100 * 4
     assert L.vct_moments_workspace_size(3, 100) >= 100 * 41 * 8
     assert L.vct_adjoint_workspace_size(3, 100, 16) >= 100 * 6 * 8
+    assert L.vct_chunk_capacity(3, 6400, nc) >= 6400 // 64 + nc
 
 
 def test_binding_fails_loudly_without_library(monkeypatch):
