@@ -6,6 +6,9 @@ imports, links or calls it, and the oracle never calls the product path.
 
 The arithmetic lives in plain C (orc.c, FP64, OpenMP over particles); this
 module only builds that file with gcc and marshals numpy arrays into it.
+extended.py evaluates the same operators for selected particles in x87
+extended precision, to separate the FP64 oracle's own rounding from that of
+the code under test.
 Record layout of sph2() outputs: see ORC_REC in orc.h (indices below).
 """
 from __future__ import annotations

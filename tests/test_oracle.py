@@ -11,6 +11,7 @@ import pytest
 
 from paper_2607_28872_amd import inputs as I
 from oracle import brute
+from oracle import extended as OX
 
 import oracle as O
 
@@ -141,6 +142,36 @@ def test_sph2_reproduces_projected_quadratics(orc, family, kernel):
     glin, _ = _proj_quadratic_derivs(lin, w.pos)
     assert np.abs(out1[:, 0, O.I_G1] - glin).max() <= 1e-11 * np.abs(glin).max()
     assert np.abs(out1[:, 0, O.I_D]).max() <= 1e-8 * np.abs(glin).max() / w.dx
+
+
+@pytest.mark.skipif(not OX.available(), reason="long double is not wider than double here")
+@pytest.mark.parametrize("family", ["bfe2d", "sigma3d"])
+@pytest.mark.parametrize("kernel", [I.KERNEL_WENDLAND_C2, I.KERNEL_CUBIC_SPLINE])
+def test_extended_reproduces_projected_quadratics(orc, family, kernel):
+    """The extended-precision evaluation is exact on quadratics to far below
+    the FP64 oracle's 1e-8 (its sums round about 2000 times more finely)."""
+    w = I.small(family)
+    R = w.R if kernel == I.KERNEL_WENDLAND_C2 else 2.4 * w.dx
+    c = w.extra["pquad"]
+    phi = I.eval_quadratic(c.astype(np.longdouble), w.pos.astype(np.longdouble))   # exact field values
+    rows = np.random.default_rng(5).choice(w.n, 24, replace=False)
+    out = OX.sph2_extended(w.pos, w.vol, phi, kernel, R, w.mapspec, rows)
+    gex, Dex = _proj_quadratic_derivs(c, w.pos[:, rows])
+    assert np.abs(out[:, 0, O.I_D] - Dex).max() <= 1e-11 * np.abs(Dex).max()
+    assert np.abs(out[:, 0, O.I_G2] - gex).max() <= 1e-13 * np.abs(gex).max()
+
+
+@pytest.mark.skipif(not OX.available(), reason="long double is not wider than double here")
+@pytest.mark.parametrize("family", ["bf2d", "bfe2d", "sigma3d"])
+def test_extended_agrees_with_fp64_oracle(orc, family):
+    """Same operators, same steps: the two evaluations differ only by the FP64
+    oracle's rounding, every record slot included."""
+    w = I.small(family)
+    rows = np.random.default_rng(6).choice(w.n, 24, replace=False)
+    ext = OX.sph2_extended(w.pos, w.vol, w.phi, w.kernel, w.R, w.mapspec, rows)
+    rec, _ = orc.sph2(w.pos, w.vol, w.phi, w.kernel, w.R, w.mapspec, rows=rows)
+    scale = np.abs(rec).max(axis=0, keepdims=True)
+    assert np.all(np.abs(ext - rec) <= 1e-10 * scale + 1e-300)
 
 
 @pytest.mark.parametrize("family", ["bf2d", "sigma3d"])
