@@ -182,23 +182,37 @@ def sph2_extended(pos, vol, phi, kernel, R, mapspec, rows, grad_order=2, with_co
     return (out, conds) if with_cond else out
 
 
-def moment_condition(pos, vol, kernel, R, csr=None):
-    """2-norm condition number of M_i for every particle (FP64, vectorised over
-    the neighbour pairs; a diagnostic for error bounds, not an operator)."""
+def moment_condition(pos, vol, kernel, R, rows=None, block=200000):
+    """2-norm condition number of M_i for the given particles (all if rows is
+    None): FP64, vectorised over the neighbour pairs in blocks of rows; a
+    diagnostic for error bounds, not an operator."""
     pos = np.ascontiguousarray(pos, dtype=np.float64)
     vol = np.asarray(vol, dtype=np.float64)
     dim, n = pos.shape
-    rp, col = csr if csr is not None else neighbors(pos, R)
-    rows = np.repeat(np.arange(n), np.diff(rp))
-    r = (pos[:, col] - pos[:, rows]).T                         # (nnz, d)
+    rows = np.arange(n) if rows is None else np.asarray(rows, dtype=np.int64)
+    out = np.empty(rows.shape[0])
+    for b0 in range(0, rows.shape[0], block):
+        rb = rows[b0:b0 + block]
+        rp, col = neighbors(pos, R, rows=rb)
+        out[b0:b0 + block] = _cond_block(pos, vol, kernel, R, rb, rp, col)
+    return out
+
+
+def _cond_block(pos, vol, kernel, R, rb, rp, col):
+    dim = pos.shape[0]
+    owner = np.repeat(np.arange(rb.shape[0]), np.diff(rp))
+    r = (pos[:, col] - pos[:, rb[owner]]).T                     # (nnz, d)
     rr = np.sqrt(np.sum(r * r, axis=1))
-    dw = np.array([float(_kernel(kernel, dim, LD(R), LD(v))[1]) for v in rr])
+    dw = _dwdr64(kernel, dim, R, rr)
     gw = -(dw / rr)[:, None] * r
     V = vol[col]
-    seg = lambda x: np.add.reduceat(x, rp[:-1], axis=0) if x.shape[0] else x
+
+    def seg(x):
+        return np.add.reduceat(x, rp[:-1], axis=0)
+
     A = seg(V[:, None, None] * gw[:, :, None] * r[:, None, :])
     L = np.linalg.inv(A)
-    gt = np.einsum("kab,kb->ka", L[rows], gw)
+    gt = np.einsum("kab,kb->ka", L[owner], gw)
     if dim == 2:
         q = np.stack([r[:, 0] ** 2, r[:, 1] ** 2, r[:, 0] * r[:, 1]], axis=1)
     else:
@@ -206,6 +220,20 @@ def moment_condition(pos, vol, kernel, R, csr=None):
                       r[:, 1] * r[:, 2]], axis=1)
     Q = seg(V[:, None, None] * q[:, :, None] * gt[:, None, :])
     F = np.sum(r * gt, axis=1) / rr ** 4
-    p = q - np.einsum("kma,ka->km", Q[rows], r)
+    p = q - np.einsum("kma,ka->km", Q[owner], r)
     M = seg((V * F)[:, None, None] * q[:, :, None] * p[:, None, :])
     return np.linalg.cond(M)
+
+
+def _dwdr64(kernel, dim, R, r):
+    """dw/dr in FP64, vectorised (same formulas as _kernel)."""
+    if kernel == 0:
+        C = 7.0 / (np.pi * R * R) if dim == 2 else 21.0 / (2 * np.pi * R ** 3)
+        q = r / R
+        return np.where(q < 1.0, C * (-20.0 * q * (1.0 - q) ** 3) / R, 0.0)
+    l = 0.5 * R
+    ad = 10.0 / (7 * np.pi * l * l) if dim == 2 else 1.0 / (np.pi * l ** 3)
+    s = r / l
+    inner = ad * (-3.0 * s + 2.25 * s * s) / l
+    outer = ad * (-0.75 * (2.0 - s) ** 2) / l
+    return np.where(s <= 1.0, inner, np.where(s < 2.0, outer, 0.0))

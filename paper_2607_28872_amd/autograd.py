@@ -1,0 +1,78 @@
+"""torch.autograd bridge for the physical Laplacian and its hand-written adjoint.
+
+`VctLaplacian.apply(phi, theta, geom, base_map, recompute)` returns the
+physical Laplacian (paper Sec. 2.1, Eq. lap_VCT, with the SPH(2) operators of
+Sec. 3.1) of the field `phi` (sorted order, FP64, on the geometry's device)
+under the vertical transformation `base_map` whose bottom elevation is
+perturbed by sum_{m,n<4} theta[m, n] c_m(x) c_n(y), with
+c in {1, cos 2 pi s, sin 2 pi s, cos 4 pi s}.  Its backward calls the adjoint
+kernels (vct_apply_ops_adjoint) for d/dphi and d/dtheta; projected positions
+are held fixed, so theta enters only through the mapping coefficients.
+
+With recompute=True the per-particle state (moment matrices, folded
+operators) is dropped after the forward and recomputed by vct_moments in the
+backward, which runs the same kernels on the same inputs and so gives the
+same bits as keeping it.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import vct
+
+ADJ_MASK = vct.VCT_OUT_LAP | vct.VCT_OUT_PGRAD | vct.VCT_OUT_PHESS
+
+# perturbation basis of the bathymetry: (basis kind, frequency)
+_B_ONE, _B_COS, _B_SIN = 0, 2, 3
+PERTURBATION_BASIS = [(_B_ONE, 0.0), (_B_COS, 1.0), (_B_SIN, 1.0), (_B_COS, 2.0)]
+
+
+def perturbation_terms(theta):
+    """16 bottom terms theta[m, n] c_m(x) c_n(y) as (coef, bx, fx, by, fy)."""
+    th = np.asarray(theta, dtype=np.float64).reshape(4, 4)
+    return [(float(th[m, k]), bx, fx, by, fy)
+            for m, (bx, fx) in enumerate(PERTURBATION_BASIS)
+            for k, (by, fy) in enumerate(PERTURBATION_BASIS)]
+
+
+class VctLaplacian(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, phi, theta, geom, base_map, recompute=True):
+        spec = base_map.with_terms(perturbation_terms(theta.detach().cpu().numpy()))
+        st = geom.moments(spec, ADJ_MASK)
+        if st < 0:
+            raise vct.VctError("vct_moments", st)
+        lap = geom.apply(phi.reshape(1, -1).contiguous(), vct.VCT_FP64)[0, : geom.n, 0].clone()
+        ctx.geom, ctx.spec, ctx.recompute = geom, spec, recompute
+        ctx.nbase = len(base_map.terms)
+        ctx.theta_meta = (theta.dtype, theta.device)
+        ctx.state = None if recompute else geom.state64
+        if recompute:
+            geom.state64 = None
+        ctx.save_for_backward(phi)
+        return lap
+
+    @staticmethod
+    def backward(ctx, grad_lap):
+        (phi,) = ctx.saved_tensors
+        g = ctx.geom
+        if ctx.recompute:
+            st = g.moments(ctx.spec, ADJ_MASK)
+            if st < 0:
+                raise vct.VctError("vct_moments", st)
+        else:
+            g.state64, g.mask, g.cmap = ctx.state, ADJ_MASK, vct.make_map(ctx.spec)
+        u = grad_lap.to(torch.float64).contiguous()
+        dphi, dth = g.adjoint(u, phi.reshape(1, -1).contiguous(), want_dtheta=ctx.needs_input_grad[1])
+        dtheta = None
+        if dth is not None:
+            dtype, dev = ctx.theta_meta
+            dtheta = dth[ctx.nbase:].to(device=dev, dtype=dtype).reshape(4, 4)
+        return dphi.reshape(phi.shape), dtheta, None, None, None
+
+
+def laplacian_loss(geom, phi, theta, base_map, target, recompute=True):
+    """sum_i (lap_i - target_i)^2 on sorted particles, differentiable in phi and theta."""
+    lap = VctLaplacian.apply(phi, theta, geom, base_map, recompute)
+    return ((lap - target) ** 2).sum()

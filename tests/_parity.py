@@ -3,7 +3,13 @@ oracle's record slots and measure normwise errors."""
 import numpy as np
 
 import oracle as O
+from oracle import extended as OX
 from paper_2607_28872_amd import vct
+
+FP64_TOL = 1e-12
+FP64_ORACLE_TOL = 1e-11
+EXT_KAPPA = 1e-13        # GPU vs extended precision, per unit of kappa_i
+ORC_KAPPA = 1e-11        # GPU vs FP64 oracle (the oracle's own rounding dominates)
 
 ALL_OUT = (vct.VCT_OUT_GRAD | vct.VCT_OUT_LAP | vct.VCT_OUT_CROSS | vct.VCT_OUT_HESS | vct.VCT_OUT_PGRAD
            | vct.VCT_OUT_PHESS)
@@ -63,3 +69,37 @@ def normwise(got, ref):
     err = np.abs(got - ref).max(axis=1)
     sc = np.abs(ref).max(axis=1)
     return np.where(sc > 0, err / np.where(sc > 0, sc, 1.0), err)
+
+
+def per_particle(got, ref, scale):
+    """max over fields and rows of |got - ref| / (largest |value| of the row)."""
+    return (np.abs(got - ref) / scale).max(axis=(0, 2))
+
+
+def fp64_check(w, kernel, R, got, ref, mask, grad_order=2, worst=48, extra=16, idx=None, scale=None):
+    """Asserts the FP64 bounds (see the GPU parity tests); got and ref are
+    (nf, m, rows) for the particles idx (all if None).  Returns (GPU vs
+    oracle, GPU vs extended, oracle vs extended) maxima for the report."""
+    idx = np.arange(w.n) if idx is None else np.asarray(idx)
+    if scale is None:
+        scale = np.abs(ref).max(axis=1, keepdims=True)
+        scale = np.where(scale > 0, scale, 1.0)
+    e_orc_all = per_particle(got, ref, scale)
+    loose = np.nonzero(e_orc_all > FP64_ORACLE_TOL)[0]
+    if loose.size:
+        kap = OX.moment_condition(w.pos, w.vol, kernel, R, rows=idx[loose])
+        bad = e_orc_all[loose] > ORC_KAPPA * kap
+        assert not bad.any(), f"GPU vs FP64 oracle: {e_orc_all[loose][bad].max():.2e} at kappa {kap[bad].min():.2e}"
+    if not OX.available():
+        return e_orc_all.max(), None, None
+    rng = np.random.default_rng(11)
+    sel = np.unique(np.concatenate([np.argsort(e_orc_all)[-worst:],
+                                    rng.choice(idx.shape[0], min(extra, idx.shape[0]), replace=False)]))
+    rows = idx[sel]
+    ext = oracle_rows(OX.sph2_extended(w.pos, w.vol, w.phi, kernel, R, w.mapspec, rows, grad_order), w.dim, mask)
+    kap = OX.moment_condition(w.pos, w.vol, kernel, R, rows=rows)
+    e_gpu = per_particle(got[:, sel], ext, scale)
+    e_ref = per_particle(ref[:, sel], ext, scale)
+    assert np.all(e_gpu <= np.maximum(FP64_TOL, EXT_KAPPA * kap)), \
+        f"GPU vs extended: worst {e_gpu.max():.2e} at kappa {kap[np.argmax(e_gpu)]:.2e}"
+    return e_orc_all.max(), e_gpu.max(), e_ref.max()

@@ -142,3 +142,13 @@ def test_binding_fails_loudly_without_library(monkeypatch):
     monkeypatch.setattr(vct, "LIB_PATH", "/nonexistent/libvct.so")
     with pytest.raises(RuntimeError, match="not built"):
         vct.lib()
+
+
+def test_autograd_perturbation_basis_matches_the_workload_generator():
+    # the bridge builds the 16 bottom terms itself; they must be the ones the
+    # synthetic c4 workload adds to the sigma bottom
+    pytest.importorskip("torch")
+    from paper_2607_28872_amd import autograd as AG
+    from paper_2607_28872_amd import inputs as I
+    th = I.theta0()
+    assert AG.perturbation_terms(th) == I.theta_terms(th)

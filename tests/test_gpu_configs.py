@@ -1,0 +1,89 @@
+"""Parity on the named workloads at their full sizes, in the launch
+configuration the benchmark times (one vct_apply_ops call over all particles).
+
+  c0  (4,096, 2-D BF):       neighbours bit-exact elsewhere; FP64 on every
+                             particle against the oracle and, where they
+                             differ most, against the extended-precision values;
+  c1  (1,048,576, 2-D BFE):  FP64 on every particle; mixed within 1e-5
+                             (gradient) and 1e-4 (Laplacian, cross) of the
+                             largest reference value of the row;
+  c2  (2,097,152, 3-D sigma): FP64 on 20,000 sampled particles;
+  c3  (8,388,608, 3-D sigma): mixed on 20,000 sampled particles.
+Sampled comparisons scale by the largest reference value over the sample.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2607_28872_amd import inputs as I
+from paper_2607_28872_amd import vct
+
+from _parity import fp64_check, normwise, oracle_rows, row_names
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+MASK = vct.VCT_OUT_DEFAULT
+
+
+def _run(w, precision, mask=MASK):
+    g = vct.Geometry(w.pos, w.vol, w.lo, w.hi, w.R, w.kernel, device=DEV, keep_col=False)
+    st = g.moments(w.mapspec, mask, fp32_copy=(precision == vct.VCT_MIXED))
+    assert st == vct.VCT_OK and g.n_flagged == 0
+    out = g.apply(g.sorted_field(w.phi), precision)[:, : g.n]
+    got = g.unsort(out).cpu().numpy()
+    del g, out
+    torch.cuda.empty_cache()
+    return got
+
+
+def _mixed_bars(w, got, ref, label):
+    err = normwise(got, ref)
+    names = row_names(w.dim, MASK)
+    print(f"\n{label} mixed errors:", {f"f{f}.{nm}": float(f"{err[f, o]:.2e}")
+                                      for f in range(err.shape[0]) for o, nm in enumerate(names)})
+    assert err[:, : w.dim].max() <= 1e-5
+    assert err[:, w.dim:].max() <= 1e-4
+
+
+@pytest.mark.parametrize("name", ["c0", "c1"])
+def test_fp64_full_set(name):
+    w = I.config(name)
+    got = _run(w, vct.VCT_FP64)
+    rec, fl = O.sph2(w.pos, w.vol, w.phi, w.kernel, w.R, w.mapspec)
+    assert not fl.any()
+    ref = oracle_rows(rec, w.dim, MASK)
+    e_all, e_gpu, e_ref = fp64_check(w, w.kernel, w.R, got, ref, MASK)
+    print(f"\n{name} FP64: GPU vs oracle {e_all:.2e}; vs extended: GPU {e_gpu}, oracle {e_ref}")
+
+
+def test_mixed_c1_full_set():
+    w = I.config("c1")
+    got = _run(w, vct.VCT_MIXED)
+    rec, _ = O.sph2(w.pos, w.vol, w.phi, w.kernel, w.R, w.mapspec)
+    _mixed_bars(w, got, oracle_rows(rec, w.dim, MASK), "c1")
+
+
+def _sample(w, k=20000, seed=31):
+    return np.sort(np.random.default_rng(seed).choice(w.n, k, replace=False))
+
+
+def test_fp64_c2_sampled():
+    w = I.config("c2")
+    got = _run(w, vct.VCT_FP64)
+    rows = _sample(w)
+    rec, fl = O.sph2(w.pos, w.vol, w.phi, w.kernel, w.R, w.mapspec, rows=rows)
+    assert not fl.any()
+    ref = oracle_rows(rec, w.dim, MASK)
+    e_all, e_gpu, e_ref = fp64_check(w, w.kernel, w.R, got[:, rows], ref, MASK, idx=rows)
+    print(f"\nc2 FP64 (20k sampled): GPU vs oracle {e_all:.2e}; vs extended: GPU {e_gpu}, oracle {e_ref}")
+
+
+def test_mixed_c3_sampled():
+    w = I.config("c3")
+    got = _run(w, vct.VCT_MIXED)
+    rows = _sample(w)
+    rec, fl = O.sph2(w.pos, w.vol, w.phi, w.kernel, w.R, w.mapspec, rows=rows)
+    assert not fl.any()
+    _mixed_bars(w, got[:, rows], oracle_rows(rec, w.dim, MASK), "c3 (20k sampled)")
