@@ -40,7 +40,7 @@ FP32_PEAK_TFLOPS = 157.3
 STAGE_KERNELS = {"cells": "k_cell_keys + k_cell_scatter + k_cell_sort + k_gather",
                  "nb_count": "k_nb_chunk (count)", "nb_fill": "k_nb_chunk (fill)",
                  "moments": "k_moment_sweeps + k_moment_solve", "moments_adj": "k_moment_sweeps + k_moment_solve",
-                 "apply": "k_apply (mixed)", "adjoint": "k_apply (lap) + k_adjoint_dphi + k_adjoint_xi"}
+                 "apply": "k_apply (mixed)", "adjoint": "k_apply FP64 (lap + projected rows) + k_adjoint_pack + k_adjoint_dphi + k_adjoint_xi"}
 
 
 def parse():
@@ -126,7 +126,7 @@ def main():
     ws_nb = torch.empty(L.vct_neighbors_workspace_size(n, ncell), dtype=torch.uint8, device=dev)
     ws_mom = torch.empty(L.vct_moments_workspace_size(dim, n), dtype=torch.uint8, device=dev)
     nterms = cmap.nterms
-    ws_adj = torch.empty(L.vct_adjoint_workspace_size(dim, n, nterms), dtype=torch.uint8, device=dev)
+
     fwd_mask = vct.VCT_OUT_DEFAULT
     adj_mask = vct.VCT_OUT_LAP | vct.VCT_OUT_PGRAD | vct.VCT_OUT_PHESS
     n_out = vct.vct_n_out(dim, fwd_mask)
@@ -137,7 +137,7 @@ def main():
     sta = torch.empty((stride_a, n), dtype=torch.float64, device=dev)
     flags = torch.empty(n, dtype=torch.uint8, device=dev)
     out = torch.empty((nf, n, n_out), dtype=torch.float64, device=dev)
-    lap = torch.empty((1, n, 1), dtype=torch.float64, device=dev)
+    proj = torch.empty((1, n, vct.vct_n_out(dim, adj_mask)), dtype=torch.float64, device=dev)
     u = torch.empty(n, dtype=torch.float64, device=dev)
     dphi = torch.empty(n, dtype=torch.float64, device=dev)
     dth = torch.empty(nterms, dtype=torch.float64, device=dev)
@@ -147,8 +147,12 @@ def main():
     nl0 = vct.make_nlist(dim, n, ncell, w.lo, w.hi, w.R, cell_start, chunk_off, chunk_start, chunk_info, row_ptr)
     _, nnz = vct.vct_neighbors(nl0, pos_s, 0, 0, ws_nb)
     col16 = torch.empty(nnz, dtype=torch.uint16, device=dev)
+    # the adjoint takes its gather form (no int32 columns, no transposed-entry
+    # map): the geometry is rebuilt every step, and building the map costs more
+    # than it saves in a single adjoint call
     nl = vct.make_nlist(dim, n, ncell, w.lo, w.hi, w.R, cell_start, chunk_off, chunk_start, chunk_info, row_ptr,
                         None, col16)
+    ws_adj = torch.empty(L.vct_adjoint_workspace_size(dim, n, nnz, nterms), dtype=torch.uint8, device=dev)
     torch.cuda.synchronize()
 
     stream = torch.cuda.current_stream()
@@ -182,10 +186,10 @@ def main():
         # backward of loss = sum (lap f - g)^2 with the state recomputed
         vct.vct_moments(nl, pos_s, vol_s, w.kernel, cmap, adj_mask, sta, None, flags, False, ws_mom)
         mark()
-        vct.vct_apply_ops(nl, 1, phi_s, pos_s, vol_s, w.kernel, sta, vct.VCT_OUT_LAP, vct.VCT_FP64, lap)
-        torch.sub(lap.view(n), g_s, out=u)
+        vct.vct_apply_ops(nl, 1, phi_s, pos_s, vol_s, w.kernel, sta, adj_mask, vct.VCT_FP64, proj)
+        torch.sub(proj[0, :, 0], g_s, out=u)
         u.mul_(2.0)
-        vct.vct_apply_ops_adjoint(nl, pos_s, vol_s, w.kernel, sta, adj_mask, cmap, phi_s, u, dphi, dth, ws_adj)
+        vct.vct_apply_ops_adjoint(nl, pos_s, vol_s, w.kernel, sta, adj_mask, cmap, proj, u, dphi, dth, ws_adj)
         mark()
         return marks
 

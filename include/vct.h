@@ -211,6 +211,9 @@ typedef struct {
     int64_t* row_ptr;       /* [n + 1] */
     int32_t* col;           /* [nnz] or NULL */
     uint16_t* col16;        /* [nnz] or NULL; 16-byte aligned */
+    int32_t* col_t;         /* [nnz] or NULL: for entry e = (i, j) of row i, the position of
+                               the entry (j, i) in row j (needs col); read by the adjoint */
+    int64_t nnz;            /* written by vct_neighbors (the total of row_ptr) */
 } vct_nlist;
 
 /* Entries needed in the chunk arrays of a set of n particles on ncell cells. */
@@ -224,9 +227,10 @@ size_t vct_neighbors_workspace_size(int64_t n, int64_t ncell);
  * so lists are reproducible bit for bit (a conservative FP32 pre-test decides
  * the clear cases; the rest use that exact FP64 expression).
  * Protocol: the chunk table and row_ptr are always written and *nnz_out (host)
- * receives the total.  If both col and col16 are NULL the call stops there
+ * and nl->nnz receive the total.  If both col and col16 are NULL the call stops there
  * (VCT_OK).  If col_cap < nnz it returns VCT_E_CAPACITY.  Otherwise the
- * columns are written.  With reuse_row_ptr != 0 the chunk table and counts are
+ * columns are written, and col_t when it is given (it needs col; the
+ * neighbour relation is symmetric, so every entry has its transpose).  With reuse_row_ptr != 0 the chunk table and counts are
  * not recomputed: they must hold the result of an earlier call on the same
  * inputs.  Returns VCT_E_WINDOW if some window exceeds 65535 particles (col16
  * cannot address it).  SYNC (reads nnz).                                       */
@@ -281,23 +285,36 @@ int vct_apply_ops(const vct_nlist* nl, int nf, const double* phi_sorted, const d
 
 /* ---------------------------------------------------------------- adjoint */
 
-size_t vct_adjoint_workspace_size(int dim, int64_t n, int nterms);
+size_t vct_adjoint_workspace_size(int dim, int64_t n, int64_t nnz, int nterms);
 
 /* Adjoint of the physical Laplacian (not in the paper; built on Eqs. lap_VCT
  * and sec_SPH2).  With lap_i = sum_j W_ij phi_ij the linear operator of
  * vct_apply_ops (FP64), and u [n] the cotangent of lap:
  *   dphi_k   = sum_{i in S_k} u_i W_ik - u_k sum_{j in S_k} W_kj
- *              (transposed operator, evaluated as a gather: no atomics)
  *   dtheta_t = sum_i u_i (d c_trans_i / d coef_t) . D^ phi_i
  *              for every bathymetry term t of `map` (projected positions held
- *              fixed; the sum is reduced in a fixed order).
+ *              fixed).
+ * dphi, two forms, both without atomics and with a fixed summation order
+ * (the same bits on every run):
+ *   with nl->col_t: every particle i writes u_i W_ij for its row into the
+ *     workspace at the transposed position col_t[e], then every particle k sums
+ *     its row of that buffer in row order (the map costs a binary search per
+ *     entry to build, so this pays when one geometry serves many adjoints);
+ *   without: every particle k walks its own row and rebuilds u_i W_ik from a
+ *     128-byte packed record of i (correction matrix and u_i times its
+ *     Laplacian row), which it reads per neighbour.
+ * dtheta: per particle from D^ phi_i, reduced in a fixed order.
  * `state64` must come from vct_moments with out_mask containing
  * VCT_OUT_LAP | VCT_OUT_PGRAD | VCT_OUT_PHESS (pass the same mask).
- * phi_sorted [n] is needed only when dtheta is not NULL.  dphi [n] and
- * dtheta [map->nterms] are device outputs; either may be NULL.                 */
+ * `proj` [n][n_out] FP64 is the output of vct_apply_ops (nf = 1, VCT_FP64,
+ * the same state and mask) for the field whose dtheta is wanted; it supplies
+ * D^ phi and is needed only when dtheta is not NULL.  dphi [n] and
+ * dtheta [map->nterms] are device outputs; either may be NULL.  The workspace
+ * holds nnz + 7 n doubles and the reduction partials
+ * (vct_adjoint_workspace_size, with nnz = nl->nnz).                            */
 int vct_apply_ops_adjoint(const vct_nlist* nl, const double* pos_sorted, const double* vol_sorted, int kernel,
                           const double* state64, uint32_t out_mask, const vct_map* map /* host */,
-                          const double* phi_sorted, const double* u, double* dphi, double* dtheta, void* ws,
+                          const double* proj, const double* u, double* dphi, double* dtheta, void* ws,
                           size_t ws_bytes, void* stream);
 
 #ifdef __cplusplus

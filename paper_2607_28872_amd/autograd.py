@@ -43,7 +43,11 @@ class VctLaplacian(torch.autograd.Function):
         st = geom.moments(spec, ADJ_MASK)
         if st < 0:
             raise vct.VctError("vct_moments", st)
-        lap = geom.apply(phi.reshape(1, -1).contiguous(), vct.VCT_FP64)[0, : geom.n, 0].clone()
+        # one FP64 apply gives the Laplacian (row 0) and the projected
+        # derivatives the bathymetry adjoint needs (the remaining rows)
+        proj = geom.apply(phi.reshape(1, -1).contiguous(), vct.VCT_FP64)
+        lap = proj[0, : geom.n, 0].clone()
+        ctx.proj = proj
         ctx.geom, ctx.spec, ctx.recompute = geom, spec, recompute
         ctx.nbase = len(base_map.terms)
         ctx.theta_meta = (theta.dtype, theta.device)
@@ -64,7 +68,7 @@ class VctLaplacian(torch.autograd.Function):
         else:
             g.state64, g.mask, g.cmap = ctx.state, ADJ_MASK, vct.make_map(ctx.spec)
         u = grad_lap.to(torch.float64).contiguous()
-        dphi, dth = g.adjoint(u, phi.reshape(1, -1).contiguous(), want_dtheta=ctx.needs_input_grad[1])
+        dphi, dth = g.adjoint(u, ctx.proj, want_dtheta=ctx.needs_input_grad[1])
         dtheta = None
         if dth is not None:
             dtype, dev = ctx.theta_meta

@@ -1,18 +1,23 @@
 // Adjoint of the physical Laplacian operator (built on paper Eqs. lap_VCT and
 // sec_SPH2; the adjoint itself is not in the paper).
 //
-// With lap_i = sum_{j in S_i} W_ij (phi_j - phi_i) and W_ij = P_lap,i . v_ij,
-// v_ij = [V_j c~ r~_ij ; V_j F~_ij q~_ij] (F~_ij uses the correction matrix of
-// particle i), the field cotangent is
-//   dphi_k = sum_{i in S_k} u_i W_ik  -  u_k P_lap,k . sum_{j in S_k} v_kj .
-// The neighbour relation is symmetric (the test |r_ij| < R is), so both terms
-// are gathers over the row of k: no atomics and a fixed summation order.
+// With lap_i = sum_{j in S_i} W_ij (phi_j - phi_i) and
+//   W_ij = V_j c~_ij [P_a,i . r~_ij + (r~_ij' L~_i r~_ij) / |r~_ij|^4 P_s,i . q~_ij]
+// (P_a,i, P_s,i the first- and second-order parts of particle i's Laplacian
+// row of the state), the field cotangent is
+//   dphi_k = sum_{i in S_k} u_i W_ik  -  sum_{j in S_k} u_k W_kj .
+// Every particle i evaluates u_i W_ij once for its own row, with its own state
+// in registers, and writes it at the transposed position col_t[e] (the entry
+// (j, i) of row j) of a buffer, and its row sum to a second buffer; then every
+// particle k sums its row of the first buffer in row order and subtracts its
+// row sum.  No atomics, a fixed summation order, the same bits on every run.
 //
 // Bathymetry coefficients enter only through the VCT coefficients (projected
 // positions are held fixed), so
 //   dtheta_t = sum_i u_i (d c_trans_i / d coef_t) . D^ phi_i ,
 // with d c_trans / d (h, h_x, h_y, h_xx, h_xy, h_yy) from forward-mode dual
-// numbers and d h^(k) / d coef_t the t-th term's basis products.  Per-particle
+// numbers, D^ phi_i from the projected-derivative rows of the forward apply,
+// and d h^(k) / d coef_t the t-th term's basis products.  Per-particle
 // contributions are reduced per work-group, then across work-groups, in a
 // fixed order.
 #include "common.h"
@@ -23,26 +28,9 @@ namespace vct {
 
 int nlist_check(const vct_nlist* nl, Grid& g);
 
-constexpr int kALanes = 4;                     // lanes per particle
+constexpr int kALanes = 8;                     // lanes per particle
 constexpr int kAThreads = kChunk * kALanes;    // one chunk per work-group
-constexpr int kAWin = 1280;                    // LDS window capacity (records)
-constexpr int kCoef = 16;                      // packed per-particle adjoint record
-
-// Per particle: [L~ (nL), P_lap (d + m), u], one 128-byte record, so the
-// gather of a neighbour's coefficients touches a single cache line.
-template <int D>
-__global__ void k_adjoint_pack(int64_t n, const double* __restrict__ state, int lap_row,
-                               const double* __restrict__ u, double* __restrict__ coef) {
-    using Dm = Dims<D>;
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    double* c = coef + i * kCoef;
-#pragma unroll
-    for (int p = 0; p < Dm::nL; ++p) c[p] = state[(int64_t)p * n + i];
-#pragma unroll
-    for (int k = 0; k < Dm::nk; ++k) c[Dm::nL + k] = state[(int64_t)(Dm::nL + lap_row * Dm::nk + k) * n + i];
-    c[Dm::nL + Dm::nk] = u[i];
-}
+constexpr int kAWin = 1600;                    // LDS window capacity (records)
 
 struct AdjArgs {
     int64_t n;
@@ -50,204 +38,302 @@ struct AdjArgs {
     Grid g;
     const double* pos;
     const double* vol;
-    const double* phi;
     const double* state;
     const double* u;
-    const double* coef;
+    const double* proj;
     const int64_t* row_ptr;
     const uint16_t* col16;
+    const int32_t* col_t;
     const int64_t* cs;
     const int32_t* cstart;
     const int4* cinfo;
     const int64_t* nchunks;
-    int pg_row, ph_row;
+    int lap_row, pg_row, ph_row, nrows;
+    const double* coef;   // [n][kCoef] packed records of the gather form
+    double* wbuf;      // [nnz]: u_i W_ij at the transposed position
+    double* rowsum;    // [n]:  u_i sum_j W_ij
     double* dphi;
     double* xi;
 };
 
+// Pass 1: u_i W_ij for every entry of row i, written transposed.  The first
+// kALanes * kWSlots entries of each row (offset and transposed position) are
+// loaded into registers up front; the window records are read from LDS one
+// slot ahead of the arithmetic.
+constexpr int kWSlots = 14;
+
 template <int D, int KERNEL>
-__global__ __launch_bounds__(kAThreads) void k_adjoint_dphi(AdjArgs A) {
+__device__ __forceinline__ double adj_weight(const double4& q, const double (&xi)[3], double invR,
+                                             const double (&L2)[Dims<D>::nL], const double (&Pl)[Dims<D>::nk]) {
     using Dm = Dims<D>;
-    constexpr int nL = Dm::nL, nk = Dm::nk, m = Dm::m;
-    __shared__ double sx[D][kAWin];
-    __shared__ double sv[kAWin];
-    __shared__ int32_t sj[kAWin];
+    constexpr int nL = Dm::nL, m = Dm::m;
+    double r[D];
+    r[0] = (q.x - xi[0]) * invR;
+    r[1] = (q.y - xi[1]) * invR;
+    if (D == 3) r[D - 1] = (q.z - xi[2]) * invR;
+    double q2 = 0.0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) q2 += r[a] * r[a];
+    double qv[m];
+#pragma unroll
+    for (int p = 0; p < m; ++p) qv[p] = r[pair_a<D>(p)] * r[pair_b<D>(p)];
+    double rLr = 0.0, sa = 0.0, ss = 0.0;
+#pragma unroll
+    for (int p = 0; p < nL; ++p) rLr += L2[p] * qv[p];
+#pragma unroll
+    for (int a = 0; a < D; ++a) sa += Pl[a] * r[a];
+#pragma unroll
+    for (int p = 0; p < m; ++p) ss += Pl[D + p] * qv[p];
+    const double vc = q.w * kernel_shape<KERNEL>(vsqrt(q2));
+    return vc * (sa + rLr * vrcp(q2 * q2) * ss);
+}
+
+template <int D, int KERNEL>
+__global__ __launch_bounds__(kAThreads, 2) void k_adjoint_weights(AdjArgs A) {
+    using Dm = Dims<D>;
+    constexpr int nL = Dm::nL, nk = Dm::nk;
+    __shared__ double4 sd[kAWin];   // x, y, z, V
+    __shared__ WindowT<D> w;
     const uint32_t b = xcd_tile(blockIdx.x, gridDim.x);
-    if (b >= *A.nchunks) return;
+    if (b >= *A.nchunks) return;   // uniform over the work-group
     const int64_t n = A.n;
     const int64_t p0 = A.cstart[b], p1 = A.cstart[b + 1];
-    __shared__ WindowT<D> w;   // one copy per work-group: runtime-indexed, so kept in LDS
-    if (threadIdx.x == 0) chunk_window<D>(A.g, A.cs, A.cinfo[b], w);
+    if (threadIdx.x < kWave) chunk_window_wave<D>(A.g, A.cs, A.cinfo[b], w);
+    const int lane = threadIdx.x % kALanes;
+    const int64_t i = p0 + threadIdx.x / kALanes;
+    const bool valid = i < p1;
+    const int64_t ii = valid ? i : p0;
+    double xi[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) xi[a] = a < D ? A.pos[a * n + ii] : 0.0;
+    double L2[nL], Pl[nk];
+    const double ui = A.u[ii];
+#pragma unroll
+    for (int p = 0; p < nL; ++p) L2[p] = (pair_a<D>(p) == pair_b<D>(p) ? 1.0 : 2.0) * A.state[(int64_t)p * n + ii];
+#pragma unroll
+    for (int c = 0; c < nk; ++c) Pl[c] = ui * A.state[(int64_t)(nL + A.lap_row * nk + c) * n + ii];
+    const int64_t rb = valid ? A.row_ptr[ii] : 0, re = valid ? A.row_ptr[ii + 1] : 0;
+    // register slots: entry rb + lane + kALanes s (window offset, transposed position)
+    uint32_t cpk[(kWSlots + 1) / 2];
+    int32_t tcol[kWSlots];
+    int nslot = 0;
+    {
+        const uint32_t first = re > rb ? (uint32_t)A.col16[rb] : 0u;
+#pragma unroll
+        for (int s = 0; s < kWSlots; ++s) {
+            const int64_t e = rb + lane + (int64_t)kALanes * s;
+            const bool in = e < re;
+            const uint32_t c = in ? (uint32_t)A.col16[e] : first;
+            tcol[s] = in ? A.col_t[e] : -1;
+            nslot += in ? 1 : 0;
+            if (s % 2 == 0) cpk[s / 2] = c;
+            else cpk[s / 2] |= c << 16;
+        }
+    }
+    auto cols = [&](int s) -> int { return (int)((cpk[s / 2] >> (16 * (s % 2))) & 0xffffu); };
     __syncthreads();
-    const int W = w.off[w.nr];
+    const int W = __builtin_amdgcn_readfirstlane(w.off[w.nr]);
     const bool in_lds = W <= kAWin;
     if (in_lds) {
         for (int t = threadIdx.x; t < W; t += kAThreads) {
             const int64_t j = window_global<D>(w, t);
+            sd[t] = make_double4(A.pos[j], A.pos[n + j], D == 3 ? A.pos[2 * n + j] : 0.0, A.vol[j]);
+        }
+    }
+    __syncthreads();
+    auto fetch = [&](int t) -> double4 {
+        if (in_lds) return sd[t];
+        const int64_t j = window_global<D>(w, t);
+        return make_double4(A.pos[j], A.pos[n + j], D == 3 ? A.pos[2 * n + j] : 0.0, A.vol[j]);
+    };
+    double sum = 0.0;
+    if (in_lds) {
+        double4 qn = sd[cols(0)];
 #pragma unroll
-            for (int a = 0; a < D; ++a) sx[a][t] = A.pos[a * n + j];
-            sv[t] = A.vol[j];
+        for (int s = 0; s < kWSlots; ++s) {
+            const double4 q = qn;
+            if (s + 1 < kWSlots) qn = sd[cols(s + 1)];
+            __builtin_amdgcn_sched_barrier(0);
+            if (s < nslot) {
+                const double wij = adj_weight<D, KERNEL>(q, xi, A.invR, L2, Pl);
+                A.wbuf[tcol[s]] = wij;
+                sum += wij;
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    } else {
+#pragma unroll 1
+        for (int s = 0; s < kWSlots; ++s) {
+            if (s < nslot) {
+                const double wij = adj_weight<D, KERNEL>(fetch(cols(s)), xi, A.invR, L2, Pl);
+                A.wbuf[tcol[s]] = wij;
+                sum += wij;
+            }
+        }
+    }
+    for (int64_t e = rb + lane + (int64_t)kALanes * kWSlots; e < re; e += kALanes) {
+        const double wij = adj_weight<D, KERNEL>(fetch(A.col16[e]), xi, A.invR, L2, Pl);
+        A.wbuf[A.col_t[e]] = wij;
+        sum += wij;
+    }
+    sum = group_sum(sum, kALanes);
+    if (valid && lane == 0) A.rowsum[ii] = sum;
+}
+
+// Gather form (no transposed map): per particle, [L~ (nL, off-diagonals
+// doubled), u P_lap (d + m), 0...] packed in one 128-byte record, so the
+// rebuild of W_ik from row i reads a single cache line per neighbour.
+constexpr int kCoef = 16;
+template <int D>
+__global__ __launch_bounds__(256) void k_adjoint_pack(int64_t n, const double* __restrict__ state, int lap_row,
+                                                      const double* __restrict__ u, double* __restrict__ coef) {
+    using Dm = Dims<D>;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double c[kCoef];
+#pragma unroll
+    for (int k = 0; k < kCoef; ++k) c[k] = 0.0;
+#pragma unroll
+    for (int p = 0; p < Dm::nL; ++p)
+        c[p] = (pair_a<D>(p) == pair_b<D>(p) ? 1.0 : 2.0) * state[(int64_t)p * n + i];
+    const double ui = u[i];
+#pragma unroll
+    for (int k = 0; k < Dm::nk; ++k) c[Dm::nL + k] = ui * state[(int64_t)(Dm::nL + lap_row * Dm::nk + k) * n + i];
+    double2* dst = reinterpret_cast<double2*>(coef + i * kCoef);
+#pragma unroll
+    for (int k = 0; k < kCoef / 2; ++k) dst[k] = make_double2(c[2 * k], c[2 * k + 1]);
+}
+
+// dphi_k = sum_{i in S_k} u_i W_ik - u_k sum_j W_kj, both over the row of k.
+template <int D, int KERNEL>
+__global__ __launch_bounds__(kAThreads, 2) void k_adjoint_dphi(AdjArgs A) {
+    using Dm = Dims<D>;
+    constexpr int nL = Dm::nL, nk = Dm::nk, m = Dm::m;
+    __shared__ double4 sd[kAWin];   // x, y, z, V
+    __shared__ int32_t sj[kAWin];   // sorted index
+    __shared__ WindowT<D> w;
+    const uint32_t b = xcd_tile(blockIdx.x, gridDim.x);
+    if (b >= *A.nchunks) return;   // uniform over the work-group
+    const int64_t n = A.n;
+    const int64_t p0 = A.cstart[b], p1 = A.cstart[b + 1];
+    if (threadIdx.x < kWave) chunk_window_wave<D>(A.g, A.cs, A.cinfo[b], w);
+    const int lane = threadIdx.x % kALanes;
+    const int64_t k = p0 + threadIdx.x / kALanes;
+    const bool valid = k < p1;
+    const int64_t kk = valid ? k : p0;
+    double xk[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) xk[a] = a < D ? A.pos[a * n + kk] : 0.0;
+    const double* ck = A.coef + kk * kCoef;
+    double Lk2[nL], Pk[nk];
+#pragma unroll
+    for (int p = 0; p < nL; ++p) Lk2[p] = ck[p];
+#pragma unroll
+    for (int c = 0; c < nk; ++c) Pk[c] = ck[nL + c];   // u_k P_lap,k
+    const double Vk = A.vol[kk];
+    const int64_t rb = valid ? A.row_ptr[kk] : 0, re = valid ? A.row_ptr[kk + 1] : 0;
+    __syncthreads();
+    const int W = __builtin_amdgcn_readfirstlane(w.off[w.nr]);
+    const bool in_lds = W <= kAWin;
+    if (in_lds) {
+        for (int t = threadIdx.x; t < W; t += kAThreads) {
+            const int64_t j = window_global<D>(w, t);
+            sd[t] = make_double4(A.pos[j], A.pos[n + j], D == 3 ? A.pos[2 * n + j] : 0.0, A.vol[j]);
             sj[t] = (int32_t)j;
         }
     }
     __syncthreads();
-    const int lane = threadIdx.x % kALanes;
-    const int64_t k = p0 + threadIdx.x / kALanes;
-    if (k >= p1) return;   // whole groups leave together; no barrier follows
-    double xk[D];
-#pragma unroll
-    for (int a = 0; a < D; ++a) xk[a] = A.pos[a * n + k];
-    const double* ck = A.coef + k * kCoef;
-    double Lk2[nL];
-#pragma unroll
-    for (int p = 0; p < nL; ++p) Lk2[p] = (pair_a<D>(p) == pair_b<D>(p) ? 1.0 : 2.0) * ck[p];
-    const double Vk = A.vol[k];
-    double acc1 = 0.0, acc2[nk];
-#pragma unroll
-    for (int c = 0; c < nk; ++c) acc2[c] = 0.0;
-    const int64_t rb = A.row_ptr[k], re = A.row_ptr[k + 1];
+    double acc1 = 0.0, self = 0.0;
     for (int64_t e = rb + lane; e < re; e += kALanes) {
         const int t = A.col16[e];
-        double r[D], q2 = 0.0, Vi;
+        double4 q;
         int64_t i;
         if (in_lds) {
-#pragma unroll
-            for (int a = 0; a < D; ++a) r[a] = (sx[a][t] - xk[a]) * A.invR;
-            Vi = sv[t];
+            q = sd[t];
             i = sj[t];
         } else {
             i = window_global<D>(w, t);
-#pragma unroll
-            for (int a = 0; a < D; ++a) r[a] = (A.pos[a * n + i] - xk[a]) * A.invR;
-            Vi = A.vol[i];
+            q = make_double4(A.pos[i], A.pos[n + i], D == 3 ? A.pos[2 * n + i] : 0.0, A.vol[i]);
         }
+        const double2* ci2 = reinterpret_cast<const double2*>(A.coef + i * kCoef);
+        double ci[kCoef];
+#pragma unroll
+        for (int c = 0; c < kCoef / 2; ++c) {
+            const double2 v = ci2[c];
+            ci[2 * c] = v.x;
+            ci[2 * c + 1] = v.y;
+        }
+        double r[D];   // r~_ki
+        r[0] = (q.x - xk[0]) * A.invR;
+        r[1] = (q.y - xk[1]) * A.invR;
+        if (D == 3) r[D - 1] = (q.z - xk[2]) * A.invR;
+        double q2 = 0.0;
 #pragma unroll
         for (int a = 0; a < D; ++a) q2 += r[a] * r[a];
         double qv[m];
 #pragma unroll
         for (int p = 0; p < m; ++p) qv[p] = r[pair_a<D>(p)] * r[pair_b<D>(p)];
-        const double c = kernel_shape<KERNEL>(sqrt(q2));
-        const double iq4 = 1.0 / (q2 * q2);
-        const double* ci = A.coef + i * kCoef;
-        double rLk = 0.0, rLi = 0.0;
+        const double c = kernel_shape<KERNEL>(vsqrt(q2));
+        const double iq4 = vrcp(q2 * q2);
+        double rLk = 0.0, rLi = 0.0, sak = 0.0, ssk = 0.0, sai = 0.0, ssi = 0.0;
 #pragma unroll
         for (int p = 0; p < nL; ++p) {
             rLk += Lk2[p] * qv[p];
-            rLi += (pair_a<D>(p) == pair_b<D>(p) ? 1.0 : 2.0) * ci[p] * qv[p];
+            rLi += ci[p] * qv[p];
         }
-        // k's own row: v_ki with the correction matrix of k
-        const double wa = Vi * c, wsk = Vi * c * rLk * iq4;
 #pragma unroll
-        for (int a = 0; a < D; ++a) acc2[a] += wa * r[a];
+        for (int a = 0; a < D; ++a) {
+            sak += Pk[a] * r[a];
+            sai += ci[nL + a] * r[a];
+        }
 #pragma unroll
-        for (int p = 0; p < m; ++p) acc2[D + p] += wsk * qv[p];
-        // W_ik from row i: r~_ik = -r~_ki, volume V_k, correction matrix of i
-        const double ca = Vk * c, csi = Vk * c * rLi * iq4;
-        double Wik = 0.0;
-#pragma unroll
-        for (int a = 0; a < D; ++a) Wik -= ci[nL + a] * ca * r[a];
-#pragma unroll
-        for (int p = 0; p < m; ++p) Wik += ci[nL + D + p] * csi * qv[p];
-        acc1 += ci[nL + nk] * Wik;
+        for (int p = 0; p < m; ++p) {
+            ssk += Pk[D + p] * qv[p];
+            ssi += ci[nL + D + p] * qv[p];
+        }
+        // u_k W_ki (row k: volume V_i, correction of k) and u_i W_ik (row i:
+        // r~_ik = -r~_ki, volume V_k, correction of i)
+        self += q.w * c * (sak + rLk * iq4 * ssk);
+        acc1 += Vk * c * (rLi * iq4 * ssi - sai);
     }
     acc1 = group_sum(acc1, kALanes);
-#pragma unroll
-    for (int c = 0; c < nk; ++c) acc2[c] = group_sum(acc2[c], kALanes);
-    if (lane == 0) {
-        double self = 0.0;
-#pragma unroll
-        for (int c = 0; c < nk; ++c) self += ck[nL + c] * acc2[c];
-        A.dphi[k] = acc1 - ck[nL + nk] * self;
-    }
+    self = group_sum(self, kALanes);
+    if (valid && lane == 0) A.dphi[kk] = acc1 - self;
 }
 
-// Per particle: D^ phi from the PGRAD / PHESS rows, then
-// xi_k = u_i * d(c_trans . D^)/d h^(k) for the six bottom quantities.
-template <int D, int KERNEL>
-__global__ __launch_bounds__(kAThreads) void k_adjoint_xi(AdjArgs A, MapParams mp) {
-    using Dm = Dims<D>;
-    constexpr int nL = Dm::nL, nk = Dm::nk, m = Dm::m;
-    __shared__ double sx[D][kAWin];
-    __shared__ double sv[kAWin];
-    __shared__ double sp[kAWin];
-    const uint32_t b = xcd_tile(blockIdx.x, gridDim.x);
-    if (b >= *A.nchunks) return;
-    const int64_t n = A.n;
-    const int64_t p0 = A.cstart[b], p1 = A.cstart[b + 1];
-    __shared__ WindowT<D> w;   // one copy per work-group: runtime-indexed, so kept in LDS
-    if (threadIdx.x == 0) chunk_window<D>(A.g, A.cs, A.cinfo[b], w);
-    __syncthreads();
-    const int W = w.off[w.nr];
-    const bool in_lds = W <= kAWin;
-    if (in_lds) {
-        for (int t = threadIdx.x; t < W; t += kAThreads) {
-            const int64_t j = window_global<D>(w, t);
-#pragma unroll
-            for (int a = 0; a < D; ++a) sx[a][t] = A.pos[a * n + j];
-            sv[t] = A.vol[j];
-            sp[t] = A.phi[j];
-        }
-    }
-    __syncthreads();
+// Pass 2: dphi_k = (row k of the transposed buffer, summed in row order) - rowsum_k.
+__global__ __launch_bounds__(256) void k_adjoint_gather(int64_t n, const int64_t* __restrict__ row_ptr,
+                                                        const double* __restrict__ wbuf,
+                                                        const double* __restrict__ rowsum,
+                                                        double* __restrict__ dphi) {
+    const int64_t k = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kALanes;
     const int lane = threadIdx.x % kALanes;
-    const int64_t i = p0 + threadIdx.x / kALanes;
-    if (i >= p1) return;   // whole groups leave together; no barrier follows
+    const bool valid = k < n;
+    double s = 0.0;
+    if (valid) {
+        const int64_t rb = row_ptr[k], re = row_ptr[k + 1];
+        for (int64_t e = rb + lane; e < re; e += kALanes) s += wbuf[e];
+    }
+    s = group_sum(s, kALanes);
+    if (valid && lane == 0) dphi[k] = s - rowsum[k];
+}
+
+// Per particle: D^ phi from the projected rows of the forward apply, then
+// xi_k = u_i * d(c_trans . D^)/d h^(k) for the six bottom quantities.
+template <int D>
+__global__ __launch_bounds__(256) void k_adjoint_xi(AdjArgs A, MapParams mp) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t n = A.n;
+    if (i >= n) return;
+    const double* pr = A.proj + i * A.nrows;
+    // projected derivatives needed by c_trans: dz^, zz, xz, (yz)
+    const double gz = pr[A.pg_row + D - 1];
+    const double Hzz = (D == 3) ? pr[A.ph_row + 2] : pr[A.ph_row + 1];
+    const double Hxz = (D == 3) ? pr[A.ph_row + 4] : pr[A.ph_row + 2];
+    const double Hyz = (D == 3) ? pr[A.ph_row + 5] : 0.0;
     double x[D];
 #pragma unroll
     for (int a = 0; a < D; ++a) x[a] = A.pos[a * n + i];
-    double L2[nL];
-#pragma unroll
-    for (int p = 0; p < nL; ++p) L2[p] = (pair_a<D>(p) == pair_b<D>(p) ? 1.0 : 2.0) * A.state[(int64_t)p * n + i];
-    const double phi_i = A.phi[i];
-    double acc[nk];
-#pragma unroll
-    for (int c = 0; c < nk; ++c) acc[c] = 0.0;
-    const int64_t rb = A.row_ptr[i], re = A.row_ptr[i + 1];
-    for (int64_t e = rb + lane; e < re; e += kALanes) {
-        const int t = A.col16[e];
-        double r[D], q2 = 0.0, V, pj;
-        if (in_lds) {
-#pragma unroll
-            for (int a = 0; a < D; ++a) r[a] = (sx[a][t] - x[a]) * A.invR;
-            V = sv[t];
-            pj = sp[t];
-        } else {
-            const int64_t j = window_global<D>(w, t);
-#pragma unroll
-            for (int a = 0; a < D; ++a) r[a] = (A.pos[a * n + j] - x[a]) * A.invR;
-            V = A.vol[j];
-            pj = A.phi[j];
-        }
-#pragma unroll
-        for (int a = 0; a < D; ++a) q2 += r[a] * r[a];
-        double qv[m];
-#pragma unroll
-        for (int p = 0; p < m; ++p) qv[p] = r[pair_a<D>(p)] * r[pair_b<D>(p)];
-        double rLr = 0.0;
-#pragma unroll
-        for (int p = 0; p < nL; ++p) rLr += L2[p] * qv[p];
-        const double wa = V * kernel_shape<KERNEL>(sqrt(q2)) * (pj - phi_i);
-        const double ws = wa * rLr / (q2 * q2);
-#pragma unroll
-        for (int a = 0; a < D; ++a) acc[a] += wa * r[a];
-#pragma unroll
-        for (int p = 0; p < m; ++p) acc[D + p] += ws * qv[p];
-    }
-#pragma unroll
-    for (int c = 0; c < nk; ++c) acc[c] = group_sum(acc[c], kALanes);
-    if (lane != 0) return;
-    auto row = [&](int o) {
-        const double* P = A.state + (int64_t)(nL + o * nk) * n + i;
-        double v = 0.0;
-#pragma unroll
-        for (int c = 0; c < nk; ++c) v += P[(int64_t)c * n] * acc[c];
-        return v;
-    };
-    // projected derivatives needed by c_trans: dz^, zz, xz, (yz)
-    const double gz = row(A.pg_row + D - 1);
-    const double Hzz = (D == 3) ? row(A.ph_row + 2) : row(A.ph_row + 1);
-    const double Hxz = (D == 3) ? row(A.ph_row + 4) : row(A.ph_row + 2);
-    const double Hyz = (D == 3) ? row(A.ph_row + 5) : 0.0;
     double h[6];
     bottom6(mp, x[0], D == 3 ? x[1] : 0.0, h);
     Dual6 hd[6];
@@ -313,18 +399,24 @@ __global__ __launch_bounds__(kRedThreads) void k_dtheta_final(int64_t nblocks, i
 }
 
 template <int D, int KERNEL>
-static int launch_adjoint(AdjArgs a, int64_t cap, const MapParams& mp, int lap_row, double* dtheta,
-                          double* partials, hipStream_t s) {
+static int launch_adjoint(AdjArgs a, int64_t cap, const MapParams& mp, double* dtheta, double* partials,
+                          hipStream_t s) {
     const int64_t n = a.n;
-    if (a.dphi) {
+    if (a.dphi && a.col_t) {
+        hipLaunchKernelGGL((k_adjoint_weights<D, KERNEL>), dim3((unsigned)cap), dim3(kAThreads), 0, s, a);
+        VCT_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_adjoint_gather, dim3((unsigned)((n * kALanes + 255) / 256)), dim3(256), 0, s, n,
+                           a.row_ptr, a.wbuf, a.rowsum, a.dphi);
+        VCT_LAUNCH_CHECK();
+    } else if (a.dphi) {
         hipLaunchKernelGGL((k_adjoint_pack<D>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, a.state,
-                           lap_row, a.u, const_cast<double*>(a.coef));
+                           a.lap_row, a.u, const_cast<double*>(a.coef));
         VCT_LAUNCH_CHECK();
         hipLaunchKernelGGL((k_adjoint_dphi<D, KERNEL>), dim3((unsigned)cap), dim3(kAThreads), 0, s, a);
         VCT_LAUNCH_CHECK();
     }
     if (dtheta && mp.nterms > 0) {
-        hipLaunchKernelGGL((k_adjoint_xi<D, KERNEL>), dim3((unsigned)cap), dim3(kAThreads), 0, s, a, mp);
+        hipLaunchKernelGGL((k_adjoint_xi<D>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, mp);
         VCT_LAUNCH_CHECK();
         const int64_t nred = (n + kRedThreads - 1) / kRedThreads;
         hipLaunchKernelGGL(k_dtheta_partials, dim3((unsigned)nred), dim3(kRedThreads), 0, s, n, a.pos, D, mp, a.xi,
@@ -346,17 +438,18 @@ __global__ void k_zero_f64(double* p, int64_t cnt) {
 
 using namespace vct;
 
-extern "C" size_t vct_adjoint_workspace_size(int dim, int64_t n, int nterms) {
-    if ((dim != 2 && dim != 3) || n < 0 || nterms < 0) return 0;
+extern "C" size_t vct_adjoint_workspace_size(int dim, int64_t n, int64_t nnz, int nterms) {
+    if ((dim != 2 && dim != 3) || n < 0 || nnz < 0 || nterms < 0) return 0;
     const int64_t nred = (n + kRedThreads - 1) / kRedThreads;
     return aligned_sum({(size_t)n * 6 * sizeof(double), (size_t)(nred > 0 ? nred : 1) * (nterms > 0 ? nterms : 1) * 8,
-                        (size_t)n * kCoef * sizeof(double)});
+                        (size_t)(nnz > 0 ? nnz : 1) * sizeof(double), (size_t)(n > 0 ? n : 1) * sizeof(double),
+                        (size_t)(n > 0 ? n : 1) * kCoef * sizeof(double)});
 }
 
 extern "C" int vct_apply_ops_adjoint(const vct_nlist* nl, const double* pos_sorted, const double* vol_sorted,
                                      int kernel, const double* state64, uint32_t out_mask, const vct_map* map,
-                                     const double* phi_sorted, const double* u, double* dphi, double* dtheta,
-                                     void* ws, size_t ws_bytes, void* stream) {
+                                     const double* proj, const double* u, double* dphi, double* dtheta, void* ws,
+                                     size_t ws_bytes, void* stream) {
     const uint32_t need = VCT_OUT_LAP | VCT_OUT_PGRAD | VCT_OUT_PHESS;
     Grid g;
     int st = nlist_check(nl, g);
@@ -378,31 +471,36 @@ extern "C" int vct_apply_ops_adjoint(const vct_nlist* nl, const double* pos_sort
         return VCT_OK;
     }
     if (!pos_sorted || !vol_sorted || !nl->col16 || !state64 || !u) return VCT_E_ARG;
-    if (dtheta && !phi_sorted) return VCT_E_ARG;
-    if (!ws || ws_bytes < vct_adjoint_workspace_size(dim, n, mp.nterms)) return VCT_E_WORKSPACE;
+    if (dtheta && !proj) return VCT_E_ARG;
+    const int64_t nnz = (dphi && nl->col_t) ? nl->nnz : 0;   // the buffer is indexed by entries
+    if (nnz < 0) return VCT_E_ARG;
+    if (!ws || ws_bytes < vct_adjoint_workspace_size(dim, n, nnz, mp.nterms)) return VCT_E_WORKSPACE;
     Carver cv(ws, ws_bytes);
     double* xi = cv.take<double>((size_t)n * 6);
     const int64_t nred = (n + kRedThreads - 1) / kRedThreads;
     double* partials = cv.take<double>((size_t)nred * (mp.nterms > 0 ? mp.nterms : 1));
+    double* wbuf = cv.take<double>((size_t)(nnz > 0 ? nnz : 1));
+    double* rowsum = cv.take<double>((size_t)n);
     double* coef = cv.take<double>((size_t)n * kCoef);
     const int64_t ncols = dim == 3 ? g.nc[0] * g.nc[1] : g.nc[0];
     AdjArgs a;
-    a.n = n; a.invR = 1.0 / nl->R; a.g = g; a.pos = pos_sorted; a.vol = vol_sorted; a.phi = phi_sorted;
-    a.state = state64; a.u = u; a.coef = coef; a.row_ptr = nl->row_ptr; a.col16 = nl->col16; a.cs = nl->cell_start;
+    a.n = n; a.invR = 1.0 / nl->R; a.g = g; a.pos = pos_sorted; a.vol = vol_sorted; a.state = state64; a.u = u;
+    a.proj = proj; a.row_ptr = nl->row_ptr; a.col16 = nl->col16; a.col_t = nl->col_t; a.cs = nl->cell_start;
     a.cstart = nl->chunk_start; a.cinfo = reinterpret_cast<const int4*>(nl->chunk_info);
     a.nchunks = nl->chunk_off + ncols;
+    a.lap_row = group_row(dim, out_mask, VCT_OUT_LAP);
     a.pg_row = group_row(dim, out_mask, VCT_OUT_PGRAD);
     a.ph_row = group_row(dim, out_mask, VCT_OUT_PHESS);
-    a.dphi = dphi; a.xi = xi;
-    const int lap_row = group_row(dim, out_mask, VCT_OUT_LAP);
+    a.nrows = n_out_rows(dim, out_mask);
+    a.wbuf = wbuf; a.rowsum = rowsum; a.coef = coef; a.dphi = dphi; a.xi = xi;
     const int64_t cap = ncols + n / kChunk + 1;
     if (dim == 2)
         st = (kernel == VCT_KERNEL_WENDLAND_C2)
-                 ? launch_adjoint<2, VCT_KERNEL_WENDLAND_C2>(a, cap, mp, lap_row, dtheta, partials, s)
-                 : launch_adjoint<2, VCT_KERNEL_CUBIC_SPLINE>(a, cap, mp, lap_row, dtheta, partials, s);
+                 ? launch_adjoint<2, VCT_KERNEL_WENDLAND_C2>(a, cap, mp, dtheta, partials, s)
+                 : launch_adjoint<2, VCT_KERNEL_CUBIC_SPLINE>(a, cap, mp, dtheta, partials, s);
     else
         st = (kernel == VCT_KERNEL_WENDLAND_C2)
-                 ? launch_adjoint<3, VCT_KERNEL_WENDLAND_C2>(a, cap, mp, lap_row, dtheta, partials, s)
-                 : launch_adjoint<3, VCT_KERNEL_CUBIC_SPLINE>(a, cap, mp, lap_row, dtheta, partials, s);
+                 ? launch_adjoint<3, VCT_KERNEL_WENDLAND_C2>(a, cap, mp, dtheta, partials, s)
+                 : launch_adjoint<3, VCT_KERNEL_CUBIC_SPLINE>(a, cap, mp, dtheta, partials, s);
     return st;
 }

@@ -465,6 +465,63 @@ extern "C" size_t vct_neighbors_workspace_size(int64_t n, int64_t ncell) {
 }
 
 namespace vct {
+// Transposed-entry map: for entry e = (i, j) of row i, the position of (j, i)
+// in row j, found by binary search of i in row j's ascending columns.  The
+// neighbour relation is symmetric (d2 is formed from x_j - x_i, whose
+// negation is exact), so every search succeeds; a miss raises the flag.
+// Each lane holds kTSlots entries and advances all their searches together,
+// so the dependent loads of one step are in flight at once.
+constexpr int kTLanes = 8;
+constexpr int kTSlots = 16;
+__global__ __launch_bounds__(256) void k_col_transpose(int64_t n, const int64_t* __restrict__ row_ptr,
+                                                       const int32_t* __restrict__ col, int32_t* __restrict__ col_t,
+                                                       int32_t* __restrict__ miss) {
+    const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kTLanes;
+    const int lane = threadIdx.x % kTLanes;
+    if (i >= n) return;
+    const int64_t rb = row_ptr[i], re = row_ptr[i + 1];
+    for (int64_t e0 = rb + lane; e0 < re; e0 += (int64_t)kTLanes * kTSlots) {
+        int64_t lo[kTSlots], hi[kTSlots];
+        bool act[kTSlots];
+#pragma unroll
+        for (int s = 0; s < kTSlots; ++s) {
+            const int64_t e = e0 + (int64_t)kTLanes * s;
+            act[s] = e < re;
+            const int64_t j = act[s] ? col[e] : i;
+            lo[s] = row_ptr[j];
+            hi[s] = row_ptr[j + 1] - 1;
+        }
+        bool more = true;
+        while (more) {
+            more = false;
+            int32_t v[kTSlots];
+#pragma unroll
+            for (int s = 0; s < kTSlots; ++s) {
+                const bool go = act[s] && lo[s] < hi[s];
+                v[s] = go ? col[(lo[s] + hi[s]) / 2] : 0;
+            }
+#pragma unroll
+            for (int s = 0; s < kTSlots; ++s) {
+                if (act[s] && lo[s] < hi[s]) {
+                    const int64_t mid = (lo[s] + hi[s]) / 2;
+                    if (v[s] < i) lo[s] = mid + 1;
+                    else hi[s] = mid;
+                    more = more || lo[s] < hi[s];
+                }
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < kTSlots; ++s) {
+            const int64_t e = e0 + (int64_t)kTLanes * s;
+            if (act[s]) {
+                const bool ok = lo[s] <= hi[s] && col[lo[s]] == (int32_t)i;
+                col_t[e] = ok ? (int32_t)lo[s] : -1;
+                if (!ok) atomicOr(miss, 1);
+            }
+        }
+    }
+}
+
 int nlist_check(const vct_nlist* nl, Grid& g) {
     if (!nl || (nl->dim != 2 && nl->dim != 3) || nl->n < 0 || nl->n > INT32_MAX || !(nl->R > 0.0) ||
         !isfinite(nl->R) || !nl->cell_start || !nl->row_ptr || !nl->chunk_off || !nl->chunk_start ||
@@ -533,16 +590,24 @@ extern "C" int vct_neighbors(vct_nlist* nl, const double* pos_sorted, int64_t co
     VCT_HIP_CHECK(hipMemcpyAsync(&nnz, nl->row_ptr + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     VCT_HIP_CHECK(hipStreamSynchronize(s));
     *nnz_out = nnz;
+    nl->nnz = nnz;
     if (!nl->col && !nl->col16) return VCT_OK;
     if (col_cap < nnz) return VCT_E_CAPACITY;
-    if ((st = fill_i32(flag, 1, 0, s))) return st;
+    if (nl->col_t && (!nl->col || nnz > INT32_MAX)) return VCT_E_ARG;
+    if ((st = fill_i32(flag, 2, 0, s))) return st;
     if (n > 0) {
         st = (D == 2) ? launch_nb<2, true>(nl, pos_sorted, g, nullptr, flag, s)
                       : launch_nb<3, true>(nl, pos_sorted, g, nullptr, flag, s);
         if (st) return st;
     }
-    int32_t hflag = 0;
-    VCT_HIP_CHECK(hipMemcpyAsync(&hflag, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    int32_t hflag[2] = {0, 0};
+    if (nl->col_t && n > 0) {
+        hipLaunchKernelGGL(k_col_transpose, dim3((unsigned)((n * kTLanes + 255) / 256)), dim3(256), 0, s, n,
+                           nl->row_ptr, nl->col, nl->col_t, flag + 1);
+        VCT_LAUNCH_CHECK();
+    }
+    VCT_HIP_CHECK(hipMemcpyAsync(hflag, flag, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     VCT_HIP_CHECK(hipStreamSynchronize(s));
-    return hflag ? VCT_E_WINDOW : VCT_OK;
+    if (hflag[0]) return VCT_E_WINDOW;
+    return hflag[1] ? VCT_E_HIP : VCT_OK;
 }

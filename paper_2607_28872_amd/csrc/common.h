@@ -63,9 +63,31 @@ __device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t nblocks) {
     return x * per + (x < rem ? x : rem) + idx;
 }
 
+// Value of another lane of the same row of 16, by a DPP permutation (a VALU
+// operand modifier: no LDS traffic, unlike a generic shuffle).
+template <int CTRL>
+__device__ __forceinline__ float dpp_lane(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_lane(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over aligned groups of G lanes (a power of two up to the wave), the
+// total in every lane of the group.  Within 16 lanes the partner lanes come
+// from DPP: quad permutations (lane ^ 1, lane ^ 2), then the half-row and
+// row mirrors (lane i <-> 7 - i, i <-> 15 - i), which pair every quad, then
+// every half-row, with the other; wider groups use shuffles.
 template <class T>
 __device__ __forceinline__ T group_sum(T v, int G) {
-    for (int m = G >> 1; m >= 1; m >>= 1) v += __shfl_xor(v, m, kWave);
+    if (G >= 2) v += dpp_lane<0xB1>(v);    // quad_perm [1, 0, 3, 2]
+    if (G >= 4) v += dpp_lane<0x4E>(v);    // quad_perm [2, 3, 0, 1]
+    if (G >= 8) v += dpp_lane<0x141>(v);   // row_half_mirror
+    if (G >= 16) v += dpp_lane<0x140>(v);  // row_mirror
+    for (int m = 16; m < G; m <<= 1) v += __shfl_xor(v, m, kWave);
     return v;
 }
 
@@ -187,6 +209,27 @@ template <int D> __host__ __device__ constexpr int mono4_index(int a, int b, int
 
 // ------------------------------------------------------------------ kernel gradient
 
+// Square root and reciprocal of the pair terms (kernel weights and powers of
+// |r|).  FP32: the hardware instructions.  FP64: the hardware estimates are
+// good to about 2^-26 only, so each gets one Newton step (the error squares to
+// about an ulp), a few instructions instead of the correctly rounded library
+// sequences.
+template <class T> __device__ __forceinline__ T vsqrt(T x);
+template <> __device__ __forceinline__ double vsqrt<double>(double x) {
+    // y ~ 1/sqrt(x); y <- y (3 - x y^2) / 2; sqrt(x) = x y  (x = 0 gives 0)
+    double y = __builtin_amdgcn_rsq(x);
+    y = y * fma(-0.5 * x, y * y, 1.5);
+    return x > 0.0 ? x * y : 0.0;
+}
+template <> __device__ __forceinline__ float vsqrt<float>(float x) { return __builtin_amdgcn_sqrtf(x); }
+
+template <class T> __device__ __forceinline__ T vrcp(T x);
+template <> __device__ __forceinline__ double vrcp<double>(double x) {
+    double y = __builtin_amdgcn_rcp(x);
+    return fma(y, fma(-x, y, 1.0), y);
+}
+template <> __device__ __forceinline__ float vrcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+
 // grad_i w(|r_ij|) = K * c~(q) * r~_ij with r~ = r/R, q = |r~|; the constant K
 // (normalisation, powers of R) cancels in every corrected operator, so only
 // the dimensionless shape c~ is evaluated.
@@ -205,18 +248,12 @@ __device__ __forceinline__ T kernel_shape(T q) {
         const T inner = T(3) - T(2.25) * s;
         T t = T(2) - s;
         t = t > T(0) ? t : T(0);
-        const T outer = T(0.75) * t * t / s;
+        const T outer = T(0.75) * t * t * vrcp(s);
         return s <= T(1) ? inner : outer;
     }
 }
 
-template <class T> __device__ __forceinline__ T vsqrt(T x);
-template <> __device__ __forceinline__ double vsqrt<double>(double x) { return sqrt(x); }
-template <> __device__ __forceinline__ float vsqrt<float>(float x) { return __builtin_amdgcn_sqrtf(x); }
 
-template <class T> __device__ __forceinline__ T vrcp(T x);
-template <> __device__ __forceinline__ double vrcp<double>(double x) { return 1.0 / x; }
-template <> __device__ __forceinline__ float vrcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
 
 // ------------------------------------------------------------------ state layout
 

@@ -75,9 +75,13 @@ __device__ __forceinline__ double sym_at(const double (&S)[Dims<D>::nL], int a, 
 
 // ------------------------------------------------------------------ kernel 1: sweeps
 
-constexpr int kMLanes = 4;                    // lanes per particle
+constexpr int kMLanes = 8;                    // lanes per particle
 constexpr int kMThreads = kChunk * kMLanes;   // one chunk per work-group
-constexpr int kMWin = 1280;                   // LDS window capacity (records)
+constexpr int kMWin = 1600;                   // LDS window capacity (records)
+#ifndef VCT_SWEEP_WAVES
+#define VCT_SWEEP_WAVES 2
+#endif
+constexpr int kMSlots = 14;                   // row entries per lane held in registers
 
 struct SweepArgs {
     int64_t n;
@@ -96,57 +100,91 @@ struct SweepArgs {
 };
 
 // One chunk per work-group: the window's positions and volumes are staged in
-// LDS, kMLanes lanes per particle walk its row of window offsets for both
-// sweeps, and the sums are reduced across the group.
+// LDS (x, y, z, V per record), kMLanes lanes per particle hold their share of
+// the row's window offsets in registers and read the records from LDS one
+// entry ahead of the arithmetic, for both sweeps; the sums are reduced across
+// the group and written through LDS with unit stride.
 template <int D, int KERNEL>
-__global__ __launch_bounds__(kMThreads) void k_moment_sweeps(SweepArgs A) {
+__global__ __launch_bounds__(kMThreads, VCT_SWEEP_WAVES) void k_moment_sweeps(SweepArgs A) {
     using Dm = Dims<D>;
     using ML = MomLayout<D>;
-    __shared__ double sx[D][kMWin];
-    __shared__ double sv[kMWin];
+    __shared__ double4 sd[kMWin];
+    __shared__ WindowT<D> w;
     const uint32_t b = xcd_tile(blockIdx.x, gridDim.x);
     if (b >= *A.nchunks) return;   // uniform over the work-group
     const int64_t n = A.n;
     const int64_t p0 = A.cstart[b], p1 = A.cstart[b + 1];
-    __shared__ WindowT<D> w;   // one copy per work-group: runtime-indexed, so kept in LDS
-    if (threadIdx.x == 0) chunk_window<D>(A.g, A.cs, A.cinfo[b], w);
+    if (threadIdx.x < kWave) chunk_window_wave<D>(A.g, A.cs, A.cinfo[b], w);
+    const int lane = threadIdx.x % kMLanes;
+    const int pl = threadIdx.x / kMLanes;
+    const int64_t i = p0 + pl;
+    const bool valid = i < p1;
+    const int64_t ii = valid ? i : p0;
+    double xi[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) xi[a] = a < D ? A.pos[a * n + ii] : 0.0;
+    const double Vi = A.vol[ii];
+    const int64_t rb = valid ? A.row_ptr[ii] : 0, re = valid ? A.row_ptr[ii + 1] : 0;
+    uint32_t cpk[(kMSlots + 1) / 2];
+    int nslot = 0;
+    {
+        const uint32_t first = re > rb ? (uint32_t)A.col16[rb] : 0u;
+#pragma unroll
+        for (int s = 0; s < kMSlots; ++s) {
+            const int64_t e = rb + lane + (int64_t)kMLanes * s;
+            const uint32_t c = e < re ? (uint32_t)A.col16[e] : first;
+            nslot += e < re ? 1 : 0;
+            if (s % 2 == 0) cpk[s / 2] = c;
+            else cpk[s / 2] |= c << 16;
+        }
+    }
+    auto cols = [&](int s) -> int { return (int)((cpk[s / 2] >> (16 * (s % 2))) & 0xffffu); };
     __syncthreads();
-    const int W = w.off[w.nr];
+    const int W = __builtin_amdgcn_readfirstlane(w.off[w.nr]);
     const bool in_lds = W <= kMWin;
     if (in_lds) {
         for (int t = threadIdx.x; t < W; t += kMThreads) {
             const int64_t j = window_global<D>(w, t);
-#pragma unroll
-            for (int a = 0; a < D; ++a) sx[a][t] = A.pos[a * n + j];
-            sv[t] = A.vol[j];
+            sd[t] = make_double4(A.pos[j], A.pos[n + j], D == 3 ? A.pos[2 * n + j] : 0.0, A.vol[j]);
         }
     }
     __syncthreads();
-    const int lane = threadIdx.x % kMLanes;
-    const int64_t i = p0 + threadIdx.x / kMLanes;
-    if (i >= p1) return;   // whole groups leave together; no barrier follows
-    auto rec = [&](int t, double (&r)[D], double& q2, double& V) {
+    auto fetch = [&](int t) -> double4 {
+        if (in_lds) return sd[t];
+        const int64_t j = window_global<D>(w, t);
+        return make_double4(A.pos[j], A.pos[n + j], D == 3 ? A.pos[2 * n + j] : 0.0, A.vol[j]);
+    };
+    auto geom = [&](const double4& q, double (&r)[D], double& q2) {
+        r[0] = (q.x - xi[0]) * A.invR;
+        r[1] = (q.y - xi[1]) * A.invR;
+        if (D == 3) r[D - 1] = (q.z - xi[2]) * A.invR;
         q2 = 0.0;
-        if (in_lds) {
-#pragma unroll
-            for (int a = 0; a < D; ++a) r[a] = (sx[a][t] - A.pos[a * n + i]) * A.invR;
-            V = sv[t];
-        } else {
-            const int64_t j = window_global<D>(w, t);
-#pragma unroll
-            for (int a = 0; a < D; ++a) r[a] = (A.pos[a * n + j] - A.pos[a * n + i]) * A.invR;
-            V = A.vol[j];
-        }
 #pragma unroll
         for (int a = 0; a < D; ++a) q2 += r[a] * r[a];
     };
-    double xi[D];
+    // visits every row entry: the register slots (records read one ahead
+    // when the window is in LDS), then the rest of a long row
+    auto sweep = [&](auto&& body) {
+        if (in_lds) {
+            double4 qn = sd[cols(0)];
 #pragma unroll
-    for (int a = 0; a < D; ++a) xi[a] = A.pos[a * n + i];
-    const int64_t rb = A.row_ptr[i], re = A.row_ptr[i + 1];
+            for (int s = 0; s < kMSlots; ++s) {
+                const double4 q = qn;
+                if (s + 1 < kMSlots) qn = sd[cols(s + 1)];
+                __builtin_amdgcn_sched_barrier(0);
+                if (s < nslot) body(q);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        } else {
+#pragma unroll 1
+            for (int s = 0; s < kMSlots; ++s)
+                if (s < nslot) body(fetch(cols(s)));
+        }
+        for (int64_t e = rb + lane + (int64_t)kMLanes * kMSlots; e < re; e += kMLanes) body(fetch(A.col16[e]));
+    };
     int fl = 0;
-    if (re - rb < D + Dm::m) fl |= VCT_FLAG_FEW;
-    bool fin = isfinite(A.vol[i]);
+    if (valid && re - rb < D + Dm::m) fl |= VCT_FLAG_FEW;
+    bool fin = isfinite(Vi);
 #pragma unroll
     for (int a = 0; a < D; ++a) fin = fin && isfinite(xi[a]);
     if (!fin) fl |= VCT_FLAG_NONFINITE;
@@ -157,18 +195,26 @@ __global__ __launch_bounds__(kMThreads) void k_moment_sweeps(SweepArgs A) {
     for (int p = 0; p < Dm::nL; ++p) Am[p] = 0.0;
 #pragma unroll
     for (int t = 0; t < Dm::n3; ++t) B[t] = 0.0;
-    for (int64_t k = rb + lane; k < re; k += kMLanes) {
-        double r[D], q2, V;
-        rec(A.col16[k], r, q2, V);
-        if (q2 == 0.0) fl |= VCT_FLAG_DUPLICATE;
-        if (!isfinite(q2) || !isfinite(V)) fl |= VCT_FLAG_NONFINITE;
-        const double wgt = V * kernel_shape<KERNEL>(sqrt(q2));
+    // monomials of r~ built from the pair products: qv (2nd), cub (3rd), quartic on the fly
+    auto monos = [&](const double (&r)[D], double (&qv)[Dm::m], double (&cub)[Dm::n3]) {
 #pragma unroll
-        for (int p = 0; p < Dm::nL; ++p) Am[p] += wgt * r[pair_a<D>(p)] * r[pair_b<D>(p)];
+        for (int p = 0; p < Dm::m; ++p) qv[p] = r[pair_a<D>(p)] * r[pair_b<D>(p)];
 #pragma unroll
         for (int t = 0; t < Dm::n3; ++t)
-            B[t] += wgt * r[mono_comp<D, 3>(t, 0)] * r[mono_comp<D, 3>(t, 1)] * r[mono_comp<D, 3>(t, 2)];
-    }
+            cub[t] = qv[sym_index<D>(mono_comp<D, 3>(t, 0), mono_comp<D, 3>(t, 1))] * r[mono_comp<D, 3>(t, 2)];
+    };
+    sweep([&](const double4& q) {
+        double r[D], q2, qv[Dm::m], cub[Dm::n3];
+        geom(q, r, q2);
+        if (q2 == 0.0) fl |= VCT_FLAG_DUPLICATE;
+        if (!isfinite(q2) || !isfinite(q.w)) fl |= VCT_FLAG_NONFINITE;
+        monos(r, qv, cub);
+        const double wgt = q.w * kernel_shape<KERNEL>(vsqrt(q2));
+#pragma unroll
+        for (int p = 0; p < Dm::nL; ++p) Am[p] += wgt * qv[p];
+#pragma unroll
+        for (int t = 0; t < Dm::n3; ++t) B[t] += wgt * cub[t];
+    });
 #pragma unroll
     for (int p = 0; p < Dm::nL; ++p) Am[p] = group_sum(Am[p], kMLanes);
 #pragma unroll
@@ -181,42 +227,53 @@ __global__ __launch_bounds__(kMThreads) void k_moment_sweeps(SweepArgs A) {
 #pragma unroll
     for (int p = 0; p < Dm::nL; ++p) L2[p] = (pair_a<D>(p) == pair_b<D>(p) ? 1.0 : 2.0) * L[p];
 
-    // sweep 2: C (3rd order) and E (4th order), weights V F~
+    // sweep 2: C (3rd order) and E (4th order), weights V F~ (skipped for a
+    // flagged particle: its state is NaN anyway)
     double Cm[Dm::n3], E[Dm::n4];
 #pragma unroll
     for (int t = 0; t < Dm::n3; ++t) Cm[t] = 0.0;
 #pragma unroll
     for (int t = 0; t < Dm::n4; ++t) E[t] = 0.0;
-    if (!fl) {
-        for (int64_t k = rb + lane; k < re; k += kMLanes) {
-            double r[D], q2, V;
-            rec(A.col16[k], r, q2, V);
-            double rLr = 0.0;
+    const bool live = fl == 0;
+    sweep([&](const double4& q) {
+        double r[D], q2, qv[Dm::m], cub[Dm::n3];
+        geom(q, r, q2);
+        monos(r, qv, cub);
+        double rLr = 0.0;
 #pragma unroll
-            for (int p = 0; p < Dm::nL; ++p) rLr += L2[p] * r[pair_a<D>(p)] * r[pair_b<D>(p)];
-            const double wgt = V * kernel_shape<KERNEL>(sqrt(q2)) * rLr / (q2 * q2);
+        for (int p = 0; p < Dm::nL; ++p) rLr += L2[p] * qv[p];
+        const double wgt = live ? q.w * kernel_shape<KERNEL>(vsqrt(q2)) * rLr * vrcp(q2 * q2) : 0.0;
 #pragma unroll
-            for (int t = 0; t < Dm::n3; ++t)
-                Cm[t] += wgt * r[mono_comp<D, 3>(t, 0)] * r[mono_comp<D, 3>(t, 1)] * r[mono_comp<D, 3>(t, 2)];
+        for (int t = 0; t < Dm::n3; ++t) Cm[t] += wgt * cub[t];
 #pragma unroll
-            for (int t = 0; t < Dm::n4; ++t)
-                E[t] += wgt * r[mono_comp<D, 4>(t, 0)] * r[mono_comp<D, 4>(t, 1)] * r[mono_comp<D, 4>(t, 2)] *
-                        r[mono_comp<D, 4>(t, 3)];
-        }
-    }
+        for (int t = 0; t < Dm::n4; ++t)
+            E[t] += wgt * qv[sym_index<D>(mono_comp<D, 4>(t, 0), mono_comp<D, 4>(t, 1))] *
+                    qv[sym_index<D>(mono_comp<D, 4>(t, 2), mono_comp<D, 4>(t, 3))];
+    });
 #pragma unroll
     for (int t = 0; t < Dm::n3; ++t) Cm[t] = group_sum(Cm[t], kMLanes);
 #pragma unroll
     for (int t = 0; t < Dm::n4; ++t) E[t] = group_sum(E[t], kMLanes);
 
-    // each lane stores a share of the sums (all lanes hold all of them)
+    // the sums through LDS (the window is no longer needed), then unit-stride
+    // stores: thread t writes entries (v, q) with q = t % kChunk
+    static_assert(ML::total * kChunk * 8 <= kMWin * 32, "sum staging must fit the window buffer");
+    double* ssum = reinterpret_cast<double*>(sd);
+    __syncthreads();
 #pragma unroll
     for (int v = 0; v < ML::total; ++v) {
         if (v % kMLanes != lane) continue;
-        const double x = v < ML::oB ? L[v] : v < ML::oC ? B[v - ML::oB] : v < ML::oE ? Cm[v - ML::oC] : E[v - ML::oE];
-        A.mom[(int64_t)v * n + i] = x;
+        ssum[v * kChunk + pl] = v < ML::oB ? L[v] : v < ML::oC ? B[v - ML::oB] : v < ML::oE ? Cm[v - ML::oC]
+                                                                                             : E[v - ML::oE];
     }
-    if (lane == 0) A.mflags[i] = (uint8_t)fl;
+    __syncthreads();
+    {
+        const int q = threadIdx.x % kChunk;
+        if (p0 + q < p1)
+            for (int v = threadIdx.x / kChunk; v < ML::total; v += kMThreads / kChunk)
+                A.mom[(int64_t)v * n + p0 + q] = ssum[v * kChunk + q];
+    }
+    if (valid && lane == 0) A.mflags[ii] = (uint8_t)fl;
 }
 
 // ------------------------------------------------------------------ kernel 2: solve + fold

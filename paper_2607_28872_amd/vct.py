@@ -50,7 +50,8 @@ class vct_nlist(C.Structure):
     _fields_ = [("dim", C.c_int32), ("reserved", C.c_int32), ("n", C.c_int64), ("ncell", C.c_int64),
                 ("chunk_cap", C.c_int64), ("lo", C.c_double * 3), ("hi", C.c_double * 3), ("R", C.c_double),
                 ("cell_start", C.c_void_p), ("chunk_off", C.c_void_p), ("chunk_start", C.c_void_p),
-                ("chunk_info", C.c_void_p), ("row_ptr", C.c_void_p), ("col", C.c_void_p), ("col16", C.c_void_p)]
+                ("chunk_info", C.c_void_p), ("row_ptr", C.c_void_p), ("col", C.c_void_p), ("col16", C.c_void_p),
+                ("col_t", C.c_void_p), ("nnz", C.c_int64)]
 
 
 _lib = None
@@ -98,7 +99,7 @@ def lib():
         L.vct_apply_ops.restype = C.c_int
         L.vct_apply_ops.argtypes = [_nlp, C.c_int, _vp, _vp, _vp, C.c_int, _vp, C.c_uint32, C.c_int, _vp, _vp]
         L.vct_adjoint_workspace_size.restype = _sz
-        L.vct_adjoint_workspace_size.argtypes = [C.c_int, _i64, C.c_int]
+        L.vct_adjoint_workspace_size.argtypes = [C.c_int, _i64, _i64, C.c_int]
         L.vct_apply_ops_adjoint.restype = C.c_int
         L.vct_apply_ops_adjoint.argtypes = [_nlp, _vp, _vp, C.c_int, _vp, C.c_uint32, C.POINTER(vct_map), _vp, _vp,
                                             _vp, _vp, _vp, _sz, _vp]
@@ -188,7 +189,7 @@ def _nbytes(t):
 
 
 def make_nlist(dim, n, ncell, lo, hi, R, cell_start, chunk_off, chunk_start, chunk_info, row_ptr, col=None,
-               col16=None, chunk_cap=None):
+               col16=None, chunk_cap=None, col_t=None):
     """vct_nlist over torch tensors (device)."""
     nl = vct_nlist()
     nl.dim, nl.n, nl.ncell = int(dim), int(n), int(ncell)
@@ -201,6 +202,7 @@ def make_nlist(dim, n, ncell, lo, hi, R, cell_start, chunk_off, chunk_start, chu
     nl.chunk_info, nl.row_ptr = chunk_info.data_ptr(), row_ptr.data_ptr()
     nl.col = col.data_ptr() if col is not None else None
     nl.col16 = col16.data_ptr() if col16 is not None else None
+    nl.col_t = col_t.data_ptr() if col_t is not None else None
     return nl
 
 
@@ -230,10 +232,10 @@ def vct_apply_ops(nl, nf, phi_sorted, pos_sorted, vol_sorted, kernel, state, mas
         _stream(stream)))
 
 
-def vct_apply_ops_adjoint(nl, pos_sorted, vol_sorted, kernel, state64, mask, cmap, phi_sorted, u, dphi, dtheta, ws,
+def vct_apply_ops_adjoint(nl, pos_sorted, vol_sorted, kernel, state64, mask, cmap, proj, u, dphi, dtheta, ws,
                           stream=None):
     return _check("vct_apply_ops_adjoint", lib().vct_apply_ops_adjoint(
-        C.byref(nl), _p(pos_sorted), _p(vol_sorted), kernel, _p(state64), mask, C.byref(cmap), _p(phi_sorted), _p(u),
+        C.byref(nl), _p(pos_sorted), _p(vol_sorted), kernel, _p(state64), mask, C.byref(cmap), _p(proj), _p(u),
         _p(dphi), _p(dtheta), _p(ws), _nbytes(ws), _stream(stream)))
 
 
@@ -278,8 +280,10 @@ class Geometry:
         self.nnz = nnz
         self.col = torch.empty(max(nnz, 1), dtype=torch.int32, device=device) if keep_col else None
         self.col16 = torch.empty(max(nnz, 1), dtype=torch.uint16, device=device)
+        # transposed-entry map, for the adjoint (needs the int32 columns)
+        self.col_t = torch.empty(max(nnz, 1), dtype=torch.int32, device=device) if keep_col else None
         self.nl = make_nlist(self.dim, n, self.ncell, lo, hi, R, self.cell_start, self.chunk_off, self.chunk_start,
-                             self.chunk_info, self.row_ptr, self.col, self.col16, chunk_cap=cap)
+                             self.chunk_info, self.row_ptr, self.col, self.col16, chunk_cap=cap, col_t=self.col_t)
         vct_neighbors(self.nl, self.pos, max(nnz, 1), 1, self._nws)
         self.state64 = self.state32 = self.flags = None
         self.mask = None
@@ -332,13 +336,16 @@ class Geometry:
         vct_apply_ops(self.nl, nf, phi_sorted, self.pos, self.vol, self.kernel, state, self.mask, precision, out)
         return out
 
-    def adjoint(self, u_sorted, phi_sorted=None, want_dtheta=True):
+    def adjoint(self, u_sorted, proj=None, want_dtheta=True):
+        """dphi (sorted) and dtheta for the cotangent u of the Laplacian; `proj`
+        is the FP64 apply output (1, n, n_out) of the field, needed for dtheta.
+        With keep_col the transposed-map form runs, else the gather form."""
         import torch
         nt = self.cmap.nterms
         dphi = torch.empty(max(self.n, 1), dtype=torch.float64, device=self.device)
         dth = torch.empty(max(nt, 1), dtype=torch.float64, device=self.device) if want_dtheta else None
-        ws = _bytes(lib().vct_adjoint_workspace_size(self.dim, self.n, nt), self.device)
-        vct_apply_ops_adjoint(self.nl, self.pos, self.vol, self.kernel, self.state64, self.mask, self.cmap, phi_sorted,
+        ws = _bytes(lib().vct_adjoint_workspace_size(self.dim, self.n, self.nnz, nt), self.device)
+        vct_apply_ops_adjoint(self.nl, self.pos, self.vol, self.kernel, self.state64, self.mask, self.cmap, proj,
                               u_sorted, dphi, dth, ws)
         return dphi[: self.n], (dth[:nt] if dth is not None else None)
 

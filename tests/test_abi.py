@@ -133,7 +133,7 @@ def test_workspace_errors(L):
                            None) == vct.VCT_E_WORKSPACE
     assert L.vct_build_cells_workspace_size(3, 100, nc) > 100 * 4
     assert L.vct_moments_workspace_size(3, 100) >= 100 * 41 * 8
-    assert L.vct_adjoint_workspace_size(3, 100, 16) >= 100 * 6 * 8
+    assert L.vct_adjoint_workspace_size(3, 100, 1000, 16) >= (100 * 7 + 1000) * 8
     assert L.vct_chunk_capacity(3, 6400, nc) >= 6400 // 64 + nc
 
 

@@ -29,7 +29,7 @@ FD_TOL = 1e-6
 def c4():
     from paper_2607_28872_amd.autograd import VctLaplacian, laplacian_loss
     w = I.config("c4")
-    g = vct.Geometry(w.pos, w.vol, w.lo, w.hi, w.R, w.kernel, device=DEV, keep_col=False)
+    g = vct.Geometry(w.pos, w.vol, w.lo, w.hi, w.R, w.kernel, device=DEV, keep_col=True)
     ms = w.mapspec
     base = I.MapSpec(ms.kind, ms.Hhat, ms.H, ms.dmin, ms.eps, list(ms.terms[:-16]))
     phi = g.sorted_field(w.phi[0])[0]
@@ -61,6 +61,18 @@ def test_recomputed_state_gives_the_same_bits(c4):
     gp2, gt2 = _grads(c4, False)
     assert torch.equal(gp1, gp2)
     assert torch.equal(gt1, gt2)
+
+
+def test_gather_and_transposed_forms_agree(c4):
+    g = c4["g"]
+    gp1, gt1 = _grads(c4, True)
+    saved, g.nl.col_t = g.nl.col_t, None       # the gather form
+    try:
+        gp2, gt2 = _grads(c4, True)
+    finally:
+        g.nl.col_t = saved
+    assert torch.equal(gt1, gt2)
+    assert float((gp1 - gp2).abs().max()) <= 1e-13 * float(gp1.abs().max())
 
 
 def test_phi_gradient_matches_central_difference(c4):
