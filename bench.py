@@ -2,17 +2,19 @@
 
 One step = one pass of the whole hot path over the 3-D sigma-SPH particle set
 (512 x 512 x 32 = 8,388,608 particles, sloped-beach bathymetry, 5% jitter):
-  cell sort -> neighbour lists (count + fill) -> FP64 moments + solve (with the
+  cell sort -> neighbour lists (one staged search) -> FP64 moments + solve (with the
   FP32 copy of the state) -> mixed-precision operator apply (grad + lap +
   cross) -> FP64 moments recomputed for the adjoint -> adjoint (d/dphi and
   d/d bathymetry coefficients).
 Inputs are resident in HBM before the timed region.  `value` is particle-
 operator evaluations (particles x fields) per second of the whole step.
 
-The JSON line also carries per-stage times, the apply-only rates of the FP64
-and mixed paths, the roofline of the dominant kernel and of the apply kernel
-(algorithmic bytes or flops per launch / launch time), and the
-CPU oracle timed on a bounded sample of the same workload.
+The JSON line also carries per-stage times, per-kernel launch times (HIP
+events on the launch stream, recorded by the library over the timed steps),
+the apply-only rates of the FP64 and mixed paths, the roofline of the step's
+dominant kernel and of the mixed apply kernel (algorithmic bytes or flops per
+launch / average launch time), and the CPU oracle timed on a bounded sample of
+the same workload.
 """
 from __future__ import annotations
 
@@ -29,18 +31,24 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 
-# Algorithmic floating-point operations per neighbour pair (multiply-add = 2)
-# and per particle of the FP64 moments (both sweeps and the solve); counted
-# from the formulation in the design doc.
-MOMENT_FLOP_PER_PAIR_3D = 2 * (3 + 3 + 3 + 1 + 3 + 6 + 10) + 2 * (3 + 3 + 3 + 1 + 3 + 7 + 10 + 15 + 15)
+# Algorithmic floating-point operations (a fused multiply-add counts 2, a
+# square root or reciprocal 1) of the 3-D kernels, counted from the per-pair
+# arithmetic they perform:
+#   moment sweeps, per pair: pass 1 = offsets and q^2 (11), the 6 pair and 10
+#   cubic monomials (16), kernel value times volume (8), A and B sums (32);
+#   pass 2 = offsets and q^2 (11), monomials (16), r~.L~.r~ (12), weight (12),
+#   C sums (20), E sums of the 15 quartic monomials (45);
+#   moment solve, per particle: the Schur LU and folds (about 3200);
+#   adjoint d/dphi, per pair: offsets and q^2 (11), pair monomials (6), kernel
+#   value and 1/q^4 (10), r~.L~.r~ for both particles (24), the Laplacian row
+#   contractions for both particles (36), the combination (10);
+#   neighbour search, per candidate: offset difference, squared distance and
+#   the two comparisons in FP32 (9).
+MOMENT_FLOP_PER_PAIR_3D = (11 + 16 + 8 + 32) + (11 + 16 + 12 + 12 + 20 + 45)
 MOMENT_FLOP_SOLVE_3D = 3200
-ADJOINT_FLOP_PER_PAIR_3D = 2 * (3 + 3 + 6 + 1 + 6 + 6 + 2 + 3 + 6 + 2 + 3 + 6 + 1) + 2 * (3 + 3 + 6 + 6 + 2 + 9 + 1)
-NB_FLOP_PER_CANDIDATE = 9            # FP32 offset difference, squared distance, two compares
-FP32_PEAK_TFLOPS = 157.3
-STAGE_KERNELS = {"cells": "k_cell_keys + k_cell_scatter + k_cell_sort + k_gather",
-                 "nb_count": "k_nb_chunk (count)", "nb_fill": "k_nb_chunk (fill)",
-                 "moments": "k_moment_sweeps + k_moment_solve", "moments_adj": "k_moment_sweeps + k_moment_solve",
-                 "apply": "k_apply (mixed)", "adjoint": "k_apply FP64 (lap + projected rows) + k_adjoint_pack + k_adjoint_dphi + k_adjoint_xi"}
+ADJOINT_DPHI_FLOP_PER_PAIR_3D = 11 + 6 + 10 + 24 + 36 + 10
+NB_FLOP_PER_CANDIDATE = 9
+FP32_VALU_PEAK_TFLOPS = 157.3        # published FP32 vector peak (packed instructions)
 
 
 def parse():
@@ -146,7 +154,7 @@ def main():
     vct.vct_build_cells(dim, n, pos, w.lo, w.hi, w.R, perm, pos_s, cell_start, ncell, ws_cells)
     nl0 = vct.make_nlist(dim, n, ncell, w.lo, w.hi, w.R, cell_start, chunk_off, chunk_start, chunk_info, row_ptr)
     _, nnz = vct.vct_neighbors(nl0, pos_s, 0, 0, ws_nb)
-    col16 = torch.empty(nnz, dtype=torch.uint16, device=dev)
+    col16 = torch.empty(max(nnz, 8), dtype=torch.uint16, device=dev)
     # the adjoint takes its gather form (no int32 columns, no transposed-entry
     # map): the geometry is rebuilt every step, and building the map costs more
     # than it saves in a single adjoint call
@@ -156,7 +164,7 @@ def main():
     torch.cuda.synchronize()
 
     stream = torch.cuda.current_stream()
-    stage_names = ["cells", "nb_count", "nb_fill", "moments", "apply", "moments_adj", "adjoint"]
+    stage_names = ["cells", "nb", "moments", "apply", "moments_adj", "adjoint"]
 
     def ev():
         e = torch.cuda.Event(enable_timing=True)
@@ -175,9 +183,7 @@ def main():
         vct.vct_gather_sorted(n, nf, perm, phi_in, phi_s)
         vct.vct_gather_sorted(n, 1, perm, g_in, g_s)
         mark()
-        vct.vct_neighbors(nl0, pos_s, 0, 0, ws_nb)
-        mark()
-        vct.vct_neighbors(nl, pos_s, nnz, 1, ws_nb)
+        vct.vct_neighbors(nl, pos_s, nnz, 0, ws_nb)
         mark()
         vct.vct_moments(nl, pos_s, vol_s, w.kernel, cmap, fwd_mask, st64, st32, flags, False, ws_mom)
         mark()
@@ -195,8 +201,15 @@ def main():
 
     for _ in range(args.warmup):
         step(False)
+    # one more untimed step with launch timing on, so that the events the
+    # timed steps record are already created
+    vct.vct_timing_enable(True)
+    step(False)
     torch.cuda.synchronize()
+    vct.vct_timing_enable(False)
+    vct.vct_timing_reset()
     stage_ms = {k: [] for k in stage_names}
+    vct.vct_timing_enable(True)
     t0 = time.perf_counter()
     for _ in range(args.steps):
         marks = step(True)
@@ -205,6 +218,8 @@ def main():
             stage_ms[nm].append(marks[k].elapsed_time(marks[k + 1]))
     torch.cuda.synchronize()
     t_step = (time.perf_counter() - t0) / args.steps
+    vct.vct_timing_enable(False)
+    ktimes = vct.vct_timing_read()
     stage = {k: float(np.mean(v)) for k, v in stage_ms.items()}
 
     # apply-only rates of both precisions (same launch configuration)
@@ -229,37 +244,41 @@ def main():
         return per_particle * n
 
     b_mixed, b_fp64 = apply_bytes(4), apply_bytes(8)
-    apply_gbs = b_mixed / (t_apply_mixed * 1e-3) / 1e9
-    roof_apply = {"kernel": "k_apply (mixed)", "bound": "hbm", "achieved": round(apply_gbs, 1),
-                  "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(apply_gbs / HBM_PEAK_GBS, 4),
-                  "traffic": measured_traffic("k_apply_mixed", b_mixed), "ms": round(t_apply_mixed, 4),
-                  "algorithmic_bytes": int(b_mixed)}
-    # dominant stage of the step and its roofline model
+    # per-kernel launch times over the timed steps, and the roofline of the
+    # kernel that takes the most time per step
+    n_out_a = vct.vct_n_out(dim, adj_mask)
     pairs = float(nnz)
-    flop_models = {
-        # FP64 flops per neighbour pair (multiply-add counted as 2), see the design doc
-        "moments": pairs * MOMENT_FLOP_PER_PAIR_3D + n * MOMENT_FLOP_SOLVE_3D,
-        "moments_adj": pairs * MOMENT_FLOP_PER_PAIR_3D + n * MOMENT_FLOP_SOLVE_3D,
-        "adjoint": pairs * ADJOINT_FLOP_PER_PAIR_3D,
-        "nb_count": pairs * 0 + n * 27.0 * (n / ncell) * NB_FLOP_PER_CANDIDATE,
-        "nb_fill": pairs * 0 + n * 27.0 * (n / ncell) * NB_FLOP_PER_CANDIDATE,
+    b_fp64_adj = n * (8 + 2 * deg + (dim * 8 + 8 + 8) + stride_a * 8 + 8 * n_out_a)
+    candidates = n * 27.0 * (n / ncell)
+    models = {   # kernel -> (bound, algorithmic bytes or flops per launch, peak)
+        "k_apply (mixed)": ("hbm", b_mixed, HBM_PEAK_GBS),
+        "k_apply (fp64)": ("hbm", b_fp64_adj, HBM_PEAK_GBS),
+        "k_moment_sweeps": ("alu", pairs * MOMENT_FLOP_PER_PAIR_3D, FP64_PEAK_TFLOPS),
+        "k_moment_solve": ("alu", n * MOMENT_FLOP_SOLVE_3D, FP64_PEAK_TFLOPS),
+        "k_adjoint_dphi": ("alu", pairs * ADJOINT_DPHI_FLOP_PER_PAIR_3D, FP64_PEAK_TFLOPS),
+        "k_nb_chunk (stage)": ("alu", candidates * NB_FLOP_PER_CANDIDATE, FP32_VALU_PEAK_TFLOPS),
     }
-    dom = max(stage, key=stage.get)
-    if dom == "apply":
-        roofline = dict(roof_apply)
-    elif dom in flop_models:
-        ach = flop_models[dom] / (stage[dom] * 1e-3) / 1e12
-        peak = FP32_PEAK_TFLOPS if dom.startswith("nb_") else FP64_PEAK_TFLOPS
-        roofline = {"kernel": STAGE_KERNELS[dom], "bound": "alu", "achieved": round(ach, 3), "peak": peak,
-                    "unit": "TFLOP/s", "frac": round(ach / peak, 4), "traffic": measured_traffic(dom, None),
-                    "ms": round(stage[dom], 4)}
-    else:
-        cells_bytes = n * (dim * 8 * 3 + 4 * 4 + 8 * (2 + nf))
-        ach = cells_bytes / (stage[dom] * 1e-3) / 1e9
-        roofline = {"kernel": STAGE_KERNELS[dom], "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
-                    "ms": round(stage[dom], 4)}
-    roofline["stage"] = dom
+    kernels = {k: {"launches_per_step": c / args.steps, "ms_per_step": round(t / args.steps, 4),
+                   "avg_launch_ms": round(t / c, 4)} for k, (c, t) in sorted(ktimes.items())}
+
+    def kernel_roofline(name):
+        c, t = ktimes[name]
+        avg = t / c
+        bound, work, peak = models[name]
+        if bound == "hbm":
+            ach = work / (avg * 1e-3) / 1e9
+            unit = "GB/s"
+        else:
+            ach = work / (avg * 1e-3) / 1e12
+            unit = "TFLOP/s"
+        return {"kernel": name, "bound": bound, "achieved": round(ach, 3), "peak": peak, "unit": unit,
+                "frac": round(ach / peak, 4), "traffic": measured_traffic(name, work), "avg_launch_ms": round(avg, 4),
+                "launches_per_step": c / args.steps, "work_per_launch": work}
+
+    dom = max(ktimes, key=lambda k: ktimes[k][1])
+    roofline = kernel_roofline(dom) if dom in models else {"kernel": dom, "bound": None, "traffic": None}
+    roof_apply = kernel_roofline("k_apply (mixed)")
+    roof_apply["apply_only_ms"] = round(t_apply_mixed, 4)
 
     value = n * nf / t_step
     res = {
@@ -288,6 +307,7 @@ def main():
                        "fp64_alg_GBs": round(b_fp64 / (t_apply_fp64 * 1e-3) / 1e9, 1)},
         "roofline": roofline,
         "roofline_apply": roof_apply,
+        "kernels": kernels,
     }
 
     if not args.no_cpu_baseline:

@@ -151,6 +151,26 @@ int vct_n_out(int dim, uint32_t out_mask);
  * nL + n_out * (d + m) + n_out * d, nL = 3 (2-D) or 6 (3-D).  0 if invalid. */
 int vct_state_stride(int dim, uint32_t out_mask);
 
+/* ---------------------------------------------------------------- launch timing */
+
+/* Per-kernel launch timing, for measurement.  While enabled, every kernel
+ * launch made by this library is bracketed by two HIP events recorded on the
+ * stream the kernel is launched on.  vct_timing_count and vct_timing_get wait
+ * for the recorded events (SYNC on them) and fold them, per kernel name, into
+ * a launch count and a summed duration in milliseconds.  Off by default; when
+ * off a launch pays one atomic load.  Do not enable while a stream of this
+ * library is being captured into a graph.  Host only, thread-safe.
+ * vct_timing_enable returns the previous state (0/1); disabling folds the
+ * pending records.  vct_timing_reset drops all records and totals.            */
+int vct_timing_enable(int on);
+void vct_timing_reset(void);
+/* Number of kernel names with folded records. */
+int vct_timing_count(void);
+/* Entry idx < vct_timing_count(): kernel name (static string owned by the
+ * library), launches and summed milliseconds (host pointers).  VCT_E_ARG for
+ * a bad index or a NULL pointer.                                              */
+int vct_timing_get(int idx, const char** name, int64_t* launches, double* total_ms);
+
 /* ---------------------------------------------------------------- cells */
 
 size_t vct_build_cells_workspace_size(int dim, int64_t n, int64_t ncell);
@@ -219,6 +239,8 @@ typedef struct {
 /* Entries needed in the chunk arrays of a set of n particles on ncell cells. */
 int64_t vct_chunk_capacity(int dim, int64_t n, int64_t ncell);
 
+/* Workspace of vct_neighbors: counts, scan tiles, flags and a staging area of
+ * 128 16-bit entries per particle (256 n bytes). */
 size_t vct_neighbors_workspace_size(int64_t n, int64_t ncell);
 
 /* Neighbour lists S_i = { j != i : d2(i,j) < R*R } (Eq. SPH_neighbor_set) of
@@ -227,12 +249,18 @@ size_t vct_neighbors_workspace_size(int64_t n, int64_t ncell);
  * so lists are reproducible bit for bit (a conservative FP32 pre-test decides
  * the clear cases; the rest use that exact FP64 expression).
  * Protocol: the chunk table and row_ptr are always written and *nnz_out (host)
- * and nl->nnz receive the total.  If both col and col16 are NULL the call stops there
- * (VCT_OK).  If col_cap < nnz it returns VCT_E_CAPACITY.  Otherwise the
- * columns are written, and col_t when it is given (it needs col; the
- * neighbour relation is symmetric, so every entry has its transpose).  With reuse_row_ptr != 0 the chunk table and counts are
- * not recomputed: they must hold the result of an earlier call on the same
- * inputs.  Returns VCT_E_WINDOW if some window exceeds 65535 particles (col16
+ * and nl->nnz receive the total.  If both col and col16 are NULL the call
+ * stops there (VCT_OK).  If col_cap < nnz it returns VCT_E_CAPACITY (row_ptr
+ * and nnz are still valid, so the caller can size the columns and call again).
+ * Otherwise the columns are written (ascending within a row), and col_t when
+ * it is given (it needs col; the neighbour relation is symmetric, so every
+ * entry has its transpose).  With columns requested and reuse_row_ptr == 0 the
+ * search runs once: every row is staged in the workspace while it is counted,
+ * then compacted behind row_ptr; when some row is longer than 128 entries the
+ * search is repeated to write the columns in place.  With reuse_row_ptr != 0
+ * the chunk table and row_ptr are not recomputed (they must hold the result of
+ * an earlier call on the same inputs) and the search writes the columns in
+ * place.  Returns VCT_E_WINDOW if some window exceeds 65535 particles (col16
  * cannot address it).  SYNC (reads nnz).                                       */
 int vct_neighbors(vct_nlist* nl, const double* pos_sorted, int64_t col_cap, int64_t* nnz_out, int reuse_row_ptr,
                   void* ws, size_t ws_bytes, void* stream);

@@ -403,26 +403,26 @@ static int launch_adjoint(AdjArgs a, int64_t cap, const MapParams& mp, double* d
                           hipStream_t s) {
     const int64_t n = a.n;
     if (a.dphi && a.col_t) {
-        hipLaunchKernelGGL((k_adjoint_weights<D, KERNEL>), dim3((unsigned)cap), dim3(kAThreads), 0, s, a);
+        VCT_LAUNCH("k_adjoint_weights", (k_adjoint_weights<D, KERNEL>), dim3((unsigned)cap), dim3(kAThreads), 0, s, a);
         VCT_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_adjoint_gather, dim3((unsigned)((n * kALanes + 255) / 256)), dim3(256), 0, s, n,
+        VCT_LAUNCH("k_adjoint_gather", k_adjoint_gather, dim3((unsigned)((n * kALanes + 255) / 256)), dim3(256), 0, s, n,
                            a.row_ptr, a.wbuf, a.rowsum, a.dphi);
         VCT_LAUNCH_CHECK();
     } else if (a.dphi) {
-        hipLaunchKernelGGL((k_adjoint_pack<D>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, a.state,
+        VCT_LAUNCH("k_adjoint_pack", (k_adjoint_pack<D>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, a.state,
                            a.lap_row, a.u, const_cast<double*>(a.coef));
         VCT_LAUNCH_CHECK();
-        hipLaunchKernelGGL((k_adjoint_dphi<D, KERNEL>), dim3((unsigned)cap), dim3(kAThreads), 0, s, a);
+        VCT_LAUNCH("k_adjoint_dphi", (k_adjoint_dphi<D, KERNEL>), dim3((unsigned)cap), dim3(kAThreads), 0, s, a);
         VCT_LAUNCH_CHECK();
     }
     if (dtheta && mp.nterms > 0) {
-        hipLaunchKernelGGL((k_adjoint_xi<D>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, mp);
+        VCT_LAUNCH("k_adjoint_xi", (k_adjoint_xi<D>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, mp);
         VCT_LAUNCH_CHECK();
         const int64_t nred = (n + kRedThreads - 1) / kRedThreads;
-        hipLaunchKernelGGL(k_dtheta_partials, dim3((unsigned)nred), dim3(kRedThreads), 0, s, n, a.pos, D, mp, a.xi,
+        VCT_LAUNCH("k_dtheta_partials", k_dtheta_partials, dim3((unsigned)nred), dim3(kRedThreads), 0, s, n, a.pos, D, mp, a.xi,
                            partials);
         VCT_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_dtheta_final, dim3((unsigned)mp.nterms), dim3(kRedThreads), 0, s, nred, mp.nterms,
+        VCT_LAUNCH("k_dtheta_final", k_dtheta_final, dim3((unsigned)mp.nterms), dim3(kRedThreads), 0, s, nred, mp.nterms,
                            partials, dtheta);
         VCT_LAUNCH_CHECK();
     }
@@ -465,7 +465,7 @@ extern "C" int vct_apply_ops_adjoint(const vct_nlist* nl, const double* pos_sort
     hipStream_t s = as_stream(stream);
     if (n == 0) {
         if (dtheta && mp.nterms > 0) {
-            hipLaunchKernelGGL(k_zero_f64, dim3(1), dim3(64), 0, s, dtheta, (int64_t)mp.nterms);
+            VCT_LAUNCH("k_zero_f64", k_zero_f64, dim3(1), dim3(64), 0, s, dtheta, (int64_t)mp.nterms);
             VCT_LAUNCH_CHECK();
         }
         return VCT_OK;

@@ -1,6 +1,10 @@
 // Host-side helpers of the C ABI: status strings, error text, map validation,
-// layout queries.
+// layout queries, launch timing.
 #include <string.h>
+
+#include <atomic>
+#include <mutex>
+#include <vector>
 
 #include "common.h"
 #include "map_dev.h"
@@ -49,9 +53,111 @@ int map_params_from(const vct_map* m, int dim, MapParams& p) {
     return VCT_OK;
 }
 
+// ------------------------------------------------------------------ launch timing
+
+namespace {
+struct TimingRec {
+    const char* name;
+    hipEvent_t a, b;
+    bool closed;
+};
+struct TimingAgg {
+    const char* name;
+    int64_t launches;
+    double ms;
+};
+std::atomic<bool> g_timing{false};
+std::mutex g_tmu;
+std::vector<TimingRec> g_pending;
+std::vector<hipEvent_t> g_free_events;
+std::vector<TimingAgg> g_agg;
+
+hipEvent_t take_event() {
+    if (!g_free_events.empty()) {
+        hipEvent_t e = g_free_events.back();
+        g_free_events.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    return hipEventCreate(&e) == hipSuccess ? e : nullptr;
+}
+
+void drop_pending() {
+    for (TimingRec& r : g_pending) {
+        if (r.a) g_free_events.push_back(r.a);
+        if (r.b) g_free_events.push_back(r.b);
+    }
+    g_pending.clear();
+}
+
+// Waits for every closed record and adds its duration to its kernel's total.
+void fold_pending() {
+    for (TimingRec& r : g_pending) {
+        if (!r.closed || !r.a || !r.b) continue;
+        float ms = 0.0f;
+        if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) continue;
+        size_t k = 0;
+        while (k < g_agg.size() && strcmp(g_agg[k].name, r.name) != 0) ++k;
+        if (k == g_agg.size()) g_agg.push_back({r.name, 0, 0.0});
+        g_agg[k].launches += 1;
+        g_agg[k].ms += ms;
+    }
+    drop_pending();
+}
+}  // namespace
+
+bool timing_on() { return g_timing.load(std::memory_order_relaxed); }
+
+int timing_begin(const char* name, hipStream_t s) {
+    std::lock_guard<std::mutex> lk(g_tmu);
+    hipEvent_t a = take_event(), b = take_event();
+    if (!a || !b || hipEventRecord(a, s) != hipSuccess) {
+        if (a) g_free_events.push_back(a);
+        if (b) g_free_events.push_back(b);
+        return -1;
+    }
+    g_pending.push_back({name, a, b, false});
+    return (int)g_pending.size() - 1;
+}
+
+void timing_end(int rec, hipStream_t s) {
+    std::lock_guard<std::mutex> lk(g_tmu);
+    if (rec < 0 || rec >= (int)g_pending.size()) return;
+    g_pending[rec].closed = hipEventRecord(g_pending[rec].b, s) == hipSuccess;
+}
+
 }  // namespace vct
 
 using namespace vct;
+
+extern "C" int vct_timing_enable(int on) {
+    std::lock_guard<std::mutex> lk(g_tmu);
+    const bool was = g_timing.exchange(on != 0);
+    if (was && !on) fold_pending();
+    return was ? 1 : 0;
+}
+
+extern "C" void vct_timing_reset(void) {
+    std::lock_guard<std::mutex> lk(g_tmu);
+    drop_pending();
+    g_agg.clear();
+}
+
+extern "C" int vct_timing_count(void) {
+    std::lock_guard<std::mutex> lk(g_tmu);
+    fold_pending();
+    return (int)g_agg.size();
+}
+
+extern "C" int vct_timing_get(int idx, const char** name, int64_t* launches, double* total_ms) {
+    std::lock_guard<std::mutex> lk(g_tmu);
+    fold_pending();
+    if (idx < 0 || idx >= (int)g_agg.size() || !name || !launches || !total_ms) return VCT_E_ARG;
+    *name = g_agg[idx].name;
+    *launches = g_agg[idx].launches;
+    *total_ms = g_agg[idx].ms;
+    return VCT_OK;
+}
 
 extern "C" const char* vct_status_string(int status) {
     switch (status) {
@@ -62,6 +168,7 @@ extern "C" const char* vct_status_string(int status) {
     case VCT_E_CAPACITY: return "VCT_E_CAPACITY: output capacity too small";
     case VCT_E_NONFINITE: return "VCT_E_NONFINITE: non-finite input position";
     case VCT_E_WORKSPACE: return "VCT_E_WORKSPACE: workspace missing or too small";
+    case VCT_E_WINDOW: return "VCT_E_WINDOW: a neighbour window exceeds 65535 particles";
     default: return "unknown status";
     }
 }

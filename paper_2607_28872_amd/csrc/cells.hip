@@ -25,14 +25,14 @@ __global__ void k_fill_i64(int64_t* p, int64_t n, int64_t v) {
 
 static int fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s) {
     if (n <= 0) return VCT_OK;
-    hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
+    VCT_LAUNCH("k_fill_i32", k_fill_i32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
     VCT_LAUNCH_CHECK();
     return VCT_OK;
 }
 
 static int fill_i64(int64_t* p, int64_t n, int64_t v, hipStream_t s) {
     if (n <= 0) return VCT_OK;
-    hipLaunchKernelGGL(k_fill_i64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
+    VCT_LAUNCH("k_fill_i64", k_fill_i64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
     VCT_LAUNCH_CHECK();
     return VCT_OK;
 }
@@ -115,11 +115,11 @@ static size_t scan_ws_bytes(int64_t n) {
 static int exclusive_scan(const int32_t* in, int64_t n, int64_t* out, int64_t* tile_ws, hipStream_t s) {
     int64_t ntiles = (n + kScanTile - 1) / kScanTile;
     if (ntiles == 0) return fill_i64(out, 1, 0, s);
-    hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)ntiles), dim3(kScanThreads), 0, s, in, n, tile_ws);
+    VCT_LAUNCH("k_scan_tiles", k_scan_tiles, dim3((unsigned)ntiles), dim3(kScanThreads), 0, s, in, n, tile_ws);
     VCT_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanThreads), 0, s, tile_ws, ntiles, out + n);
+    VCT_LAUNCH("k_scan_sums", k_scan_sums, dim3(1), dim3(kScanThreads), 0, s, tile_ws, ntiles, out + n);
     VCT_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)ntiles), dim3(kScanThreads), 0, s, in, n, tile_ws, out);
+    VCT_LAUNCH("k_scan_apply", k_scan_apply, dim3((unsigned)ntiles), dim3(kScanThreads), 0, s, in, n, tile_ws, out);
     VCT_LAUNCH_CHECK();
     return VCT_OK;
 }
@@ -247,14 +247,18 @@ constexpr int kNbLanes = 4;                    // lanes per particle
 constexpr int kNbThreads = kChunk * kNbLanes;  // one chunk per work-group
 constexpr int kNbWindow = 2048;                // LDS window capacity (records)
 
+constexpr int kStage = 128;                    // staged row entries per particle
+
 // One chunk per work-group, kNbLanes lanes per particle.  The window positions
 // are staged in LDS as FP32 offsets from the chunk's first particle; a
 // candidate whose FP32 squared distance is inside or outside R^2 by more than
 // a bound on its rounding error is decided by it, and only the few near the
 // support edge are re-tested with the exact FP64 predicate on the stored
-// positions.  FILL = false writes the counts, FILL = true writes the columns
-// (ascending) as sorted indices and/or 16-bit window offsets.
-template <int D, bool FILL>
+// positions.  MODE 0 writes the counts; MODE 1 writes the columns (ascending)
+// at row_ptr as sorted indices and/or 16-bit window offsets; MODE 2 writes the
+// counts and the first kStage window offsets of every row into a staging
+// buffer (row i at i * kStage), flagging rows that do not fit.
+template <int D, int MODE>
 __global__ __launch_bounds__(kNbThreads) void k_nb_chunk(int64_t n, const double* __restrict__ pos, Grid g,
                                                          double R2, const int64_t* __restrict__ cs,
                                                          const int32_t* __restrict__ cstart,
@@ -264,6 +268,7 @@ __global__ __launch_bounds__(kNbThreads) void k_nb_chunk(int64_t n, const double
                                                          const int64_t* __restrict__ row_ptr,
                                                          int32_t* __restrict__ col, uint16_t* __restrict__ col16,
                                                          int32_t* __restrict__ overflow) {
+    constexpr bool FILL = MODE == 1, STAGE = MODE == 2;
     __shared__ float4 win[kNbWindow];
     __shared__ unsigned int maxoff_bits;
     const uint32_t b = xcd_tile(blockIdx.x, gridDim.x);
@@ -289,7 +294,7 @@ __global__ __launch_bounds__(kNbThreads) void k_nb_chunk(int64_t n, const double
         }
         atomicMax(&maxoff_bits, __float_as_uint(mo));   // non-negative floats order as their bits
     }
-    if (FILL && threadIdx.x == 0 && W > 65535) atomicOr(overflow, 1);
+    if ((FILL || STAGE) && threadIdx.x == 0 && W > 65535) atomicOr(overflow, 1);
     __syncthreads();
     const int lane = threadIdx.x % kNbLanes;
     const int64_t i = p0 + threadIdx.x / kNbLanes;
@@ -313,7 +318,8 @@ __global__ __launch_bounds__(kNbThreads) void k_nb_chunk(int64_t n, const double
     const int64_t zl = cz > 0 ? cz - 1 : 0, zh = cz + 1 < nz ? cz + 1 : nz - 1;
     int self_t = -1;
     int64_t written = 0;
-    const int64_t out0 = FILL ? row_ptr[i] : 0, out1 = FILL ? row_ptr[i + 1] : 0;
+    const int64_t out0 = FILL ? row_ptr[i] : STAGE ? i * kStage : 0;
+    const int64_t out1 = FILL ? row_ptr[i + 1] : STAGE ? out0 + kStage : 0;
     // window ranges are the chunk's columns in order; the particle's candidate
     // cells are the same columns restricted to its z cell +- 1
     int64_t cx, cy = 0;
@@ -351,10 +357,10 @@ __global__ __launch_bounds__(kNbThreads) void k_nb_chunk(int64_t n, const double
                         hit = within_exact(pos[j] - xi0, pos[n + j] - xi1, D == 3 ? pos[2 * n + j] - xi2 : 0.0, R2);
                 }
                 const uint64_t m = (uint64_t)__ballot(hit) & gmask;
-                if (FILL && hit) {
+                if ((FILL || STAGE) && hit) {
                     const int64_t at = out0 + written + __popcll(m & below);
                     if (at < out1) {
-                        if (col) col[at] = (int32_t)(t - base);
+                        if (FILL && col) col[at] = (int32_t)(t - base);
                         if (col16) col16[at] = (uint16_t)t;
                     }
                 }
@@ -363,7 +369,45 @@ __global__ __launch_bounds__(kNbThreads) void k_nb_chunk(int64_t n, const double
             ++r;
         }
     }
-    if (!FILL && lane == 0) counts[i] = (int32_t)written;
+    if (!FILL && lane == 0) {
+        counts[i] = (int32_t)written;
+        if (STAGE && written > kStage) atomicOr(overflow + 2, 1);
+    }
+}
+
+// Copy every staged row to its place in the column arrays (offsets, and
+// sorted indices through the chunk window when col is wanted).  The
+// work-group walks its chunk's contiguous output range one entry per thread,
+// so the stores are coalesced; each entry finds its row by bisection over the
+// chunk's row pointers held in LDS.
+template <int D>
+__global__ __launch_bounds__(512) void k_nb_compact(Grid g, const int64_t* __restrict__ cs,
+                                                    const int32_t* __restrict__ cstart,
+                                                    const int4* __restrict__ cinfo,
+                                                    const int64_t* __restrict__ nchunks,
+                                                    const int64_t* __restrict__ row_ptr,
+                                                    const uint16_t* __restrict__ staged,
+                                                    int32_t* __restrict__ col, uint16_t* __restrict__ col16) {
+    __shared__ WindowT<D> w;
+    __shared__ int64_t rp[kChunk + 1];
+    const uint32_t b = xcd_tile(blockIdx.x, gridDim.x);
+    if (b >= *nchunks) return;   // uniform over the work-group
+    const int64_t p0 = cstart[b];
+    const int np = (int)(cstart[b + 1] - p0);
+    if (col && threadIdx.x < kWave) chunk_window_wave<D>(g, cs, cinfo[b], w);
+    if (threadIdx.x <= (unsigned)np) rp[threadIdx.x] = row_ptr[p0 + threadIdx.x];
+    __syncthreads();
+    const int64_t e0 = rp[0], e1 = rp[np];
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+        int lo = 0, hi = np;   // rp[lo] <= e < rp[hi]
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (rp[mid] <= e) lo = mid; else hi = mid;
+        }
+        const uint16_t t = staged[(p0 + lo) * kStage + (e - rp[lo])];
+        if (col16) col16[e] = t;
+        if (col) col[e] = (int32_t)window_global<D>(w, t);
+    }
 }
 
 }  // namespace vct
@@ -408,20 +452,20 @@ extern "C" int vct_build_cells(int dim, int64_t n, const double* pos, const doub
     if ((st = fill_i32(counts, ncell, 0, s))) return st;
     if ((st = fill_i32(bad, 1, 0, s))) return st;
     if (n > 0) {
-        hipLaunchKernelGGL(k_cell_keys, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, dim, n, pos, g,
+        VCT_LAUNCH("k_cell_keys", k_cell_keys, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, dim, n, pos, g,
                            keys, counts, bad);
         VCT_LAUNCH_CHECK();
     }
     if ((st = exclusive_scan(counts, ncell, cell_start, tiles, s))) return st;
     if (n > 0) {
         if ((st = fill_i32(counts, ncell, 0, s))) return st;
-        hipLaunchKernelGGL(k_cell_scatter, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, keys,
+        VCT_LAUNCH("k_cell_scatter", k_cell_scatter, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, keys,
                            cell_start, counts, perm);
         VCT_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_cell_sort, dim3((unsigned)((ncell + 255) / 256)), dim3(256), 0, s, ncell,
+        VCT_LAUNCH("k_cell_sort", k_cell_sort, dim3((unsigned)((ncell + 255) / 256)), dim3(256), 0, s, ncell,
                            cell_start, perm);
         VCT_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_gather, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, dim, perm, pos,
+        VCT_LAUNCH("k_gather", k_gather, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, dim, perm, pos,
                            pos_sorted);
         VCT_LAUNCH_CHECK();
     }
@@ -436,7 +480,7 @@ extern "C" int vct_gather_sorted(int64_t n, int ncomp, const int32_t* perm, cons
     if (n < 0 || ncomp < 1 || n > INT32_MAX) return VCT_E_ARG;
     if (n == 0) return VCT_OK;
     if (!perm || !src || !dst || src == dst) return VCT_E_ARG;
-    hipLaunchKernelGGL(k_gather, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, as_stream(stream), n, ncomp,
+    VCT_LAUNCH("k_gather", k_gather, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, as_stream(stream), n, ncomp,
                        perm, src, dst);
     VCT_LAUNCH_CHECK();
     return VCT_OK;
@@ -447,7 +491,7 @@ extern "C" int vct_scatter_sorted(int64_t n, int ncomp, const int32_t* perm, con
     if (n < 0 || ncomp < 1 || n > INT32_MAX) return VCT_E_ARG;
     if (n == 0) return VCT_OK;
     if (!perm || !src || !dst || src == dst) return VCT_E_ARG;
-    hipLaunchKernelGGL(k_scatter, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, as_stream(stream), n, ncomp,
+    VCT_LAUNCH("k_scatter", k_scatter, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, as_stream(stream), n, ncomp,
                        perm, src, dst);
     VCT_LAUNCH_CHECK();
     return VCT_OK;
@@ -458,10 +502,15 @@ extern "C" int64_t vct_chunk_capacity(int dim, int64_t n, int64_t ncell) {
     return n / kChunk + ncell + 1;
 }
 
-extern "C" size_t vct_neighbors_workspace_size(int64_t n, int64_t ncell) {
-    if (n < 0 || ncell < 1) return 0;
+// Workspace without the staging buffer (enough for the two-pass search).
+static size_t nb_ws_base(int64_t n, int64_t ncell) {
     const int64_t m = n > ncell ? n : ncell;
     return aligned_sum({(size_t)m * 4, scan_ws_bytes(m), 64});
+}
+
+extern "C" size_t vct_neighbors_workspace_size(int64_t n, int64_t ncell) {
+    if (n < 0 || ncell < 1) return 0;
+    return aligned_sum({nb_ws_base(n, ncell), (size_t)(n > 0 ? n : 1) * kStage * sizeof(uint16_t)});
 }
 
 namespace vct {
@@ -538,25 +587,36 @@ template <int D>
 static int build_chunks(const vct_nlist* nl, const Grid& g, int32_t* tmp, int64_t* tiles, hipStream_t s) {
     const int64_t ncols = D == 3 ? g.nc[0] * g.nc[1] : g.nc[0];
     const unsigned nb = (unsigned)((ncols + 1 + 255) / 256);
-    hipLaunchKernelGGL((k_chunk_count<D>), dim3(nb), dim3(256), 0, s, g, nl->cell_start, tmp);
+    VCT_LAUNCH("k_chunk_count", (k_chunk_count<D>), dim3(nb), dim3(256), 0, s, g, nl->cell_start, tmp);
     VCT_LAUNCH_CHECK();
     int st = exclusive_scan(tmp, ncols, nl->chunk_off, tiles, s);
     if (st) return st;
-    hipLaunchKernelGGL((k_chunk_fill<D>), dim3(nb), dim3(256), 0, s, g, nl->n, nl->cell_start, nl->chunk_off,
+    VCT_LAUNCH("k_chunk_fill", (k_chunk_fill<D>), dim3(nb), dim3(256), 0, s, g, nl->n, nl->cell_start, nl->chunk_off,
                        nl->chunk_start, reinterpret_cast<int4*>(nl->chunk_info));
     VCT_LAUNCH_CHECK();
     return VCT_OK;
 }
 
-template <int D, bool FILL>
+template <int D, int MODE>
 static int launch_nb(const vct_nlist* nl, const double* pos, const Grid& g, int32_t* counts, int32_t* overflow,
-                     hipStream_t s) {
+                     uint16_t* staged, hipStream_t s) {
     const int64_t ncols = D == 3 ? g.nc[0] * g.nc[1] : g.nc[0];
     const int64_t cap = ncols + nl->n / kChunk + 1;   // upper bound of the chunk count
-    hipLaunchKernelGGL((k_nb_chunk<D, FILL>), dim3((unsigned)cap), dim3(kNbThreads), 0, s, nl->n, pos, g,
+    VCT_LAUNCH((MODE == 0 ? "k_nb_chunk (count)" : MODE == 1 ? "k_nb_chunk (fill)" : "k_nb_chunk (stage)"), (k_nb_chunk<D, MODE>), dim3((unsigned)cap), dim3(kNbThreads), 0, s, nl->n, pos, g,
                        nl->R * nl->R, nl->cell_start, nl->chunk_start,
                        reinterpret_cast<const int4*>(nl->chunk_info), nl->chunk_off + ncols, counts, nl->row_ptr,
-                       nl->col, nl->col16, overflow);
+                       MODE == 1 ? nl->col : nullptr, MODE == 1 ? nl->col16 : staged, overflow);
+    VCT_LAUNCH_CHECK();
+    return VCT_OK;
+}
+
+template <int D>
+static int launch_compact(const vct_nlist* nl, const Grid& g, const uint16_t* staged, hipStream_t s) {
+    const int64_t ncols = D == 3 ? g.nc[0] * g.nc[1] : g.nc[0];
+    const int64_t cap = ncols + nl->n / kChunk + 1;
+    VCT_LAUNCH("k_nb_compact", (k_nb_compact<D>), dim3((unsigned)cap), dim3(512), 0, s, g, nl->cell_start,
+                       nl->chunk_start, reinterpret_cast<const int4*>(nl->chunk_info), nl->chunk_off + ncols,
+                       nl->row_ptr, staged, nl->col, nl->col16);
     VCT_LAUNCH_CHECK();
     return VCT_OK;
 }
@@ -575,34 +635,49 @@ extern "C" int vct_neighbors(vct_nlist* nl, const double* pos_sorted, int64_t co
     int32_t* counts = cv.take<int32_t>((size_t)m);
     int64_t* tiles = cv.take<int64_t>(scan_ws_bytes(m) / 8);
     int32_t* flag = cv.take<int32_t>(16);
+    uint16_t* staged = cv.take<uint16_t>((size_t)(n > 0 ? n : 1) * kStage);
     const int D = nl->dim;
+    const bool want_cols = nl->col || nl->col16;
+    // flag[0]: window wider than 16-bit offsets; flag[1]: transpose miss;
+    // flag[2]: a row longer than the staging capacity
+    if ((st = fill_i32(flag, 3, 0, s))) return st;
+    bool staged_ok = false;
     if (!reuse_row_ptr) {
         st = (D == 2) ? build_chunks<2>(nl, g, counts, tiles, s) : build_chunks<3>(nl, g, counts, tiles, s);
         if (st) return st;
         if (n > 0) {
-            st = (D == 2) ? launch_nb<2, false>(nl, pos_sorted, g, counts, flag, s)
-                          : launch_nb<3, false>(nl, pos_sorted, g, counts, flag, s);
+            if (want_cols)
+                st = (D == 2) ? launch_nb<2, 2>(nl, pos_sorted, g, counts, flag, staged, s)
+                              : launch_nb<3, 2>(nl, pos_sorted, g, counts, flag, staged, s);
+            else
+                st = (D == 2) ? launch_nb<2, 0>(nl, pos_sorted, g, counts, flag, nullptr, s)
+                              : launch_nb<3, 0>(nl, pos_sorted, g, counts, flag, nullptr, s);
             if (st) return st;
         }
         if ((st = exclusive_scan(counts, n, nl->row_ptr, tiles, s))) return st;
+        staged_ok = want_cols;
     }
     int64_t nnz = 0;
+    int32_t hflag[3] = {0, 0, 0};
     VCT_HIP_CHECK(hipMemcpyAsync(&nnz, nl->row_ptr + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    VCT_HIP_CHECK(hipMemcpyAsync(hflag, flag, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     VCT_HIP_CHECK(hipStreamSynchronize(s));
     *nnz_out = nnz;
     nl->nnz = nnz;
-    if (!nl->col && !nl->col16) return VCT_OK;
+    if (!want_cols) return VCT_OK;
     if (col_cap < nnz) return VCT_E_CAPACITY;
     if (nl->col_t && (!nl->col || nnz > INT32_MAX)) return VCT_E_ARG;
-    if ((st = fill_i32(flag, 2, 0, s))) return st;
+    if (hflag[0]) return VCT_E_WINDOW;
     if (n > 0) {
-        st = (D == 2) ? launch_nb<2, true>(nl, pos_sorted, g, nullptr, flag, s)
-                      : launch_nb<3, true>(nl, pos_sorted, g, nullptr, flag, s);
+        if (staged_ok && !hflag[2])
+            st = (D == 2) ? launch_compact<2>(nl, g, staged, s) : launch_compact<3>(nl, g, staged, s);
+        else   // rows too long for the staging buffer, or row_ptr given: the fill pass
+            st = (D == 2) ? launch_nb<2, 1>(nl, pos_sorted, g, nullptr, flag, nullptr, s)
+                          : launch_nb<3, 1>(nl, pos_sorted, g, nullptr, flag, nullptr, s);
         if (st) return st;
     }
-    int32_t hflag[2] = {0, 0};
     if (nl->col_t && n > 0) {
-        hipLaunchKernelGGL(k_col_transpose, dim3((unsigned)((n * kTLanes + 255) / 256)), dim3(256), 0, s, n,
+        VCT_LAUNCH("k_col_transpose", k_col_transpose, dim3((unsigned)((n * kTLanes + 255) / 256)), dim3(256), 0, s, n,
                            nl->row_ptr, nl->col, nl->col_t, flag + 1);
         VCT_LAUNCH_CHECK();
     }

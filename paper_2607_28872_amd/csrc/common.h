@@ -30,6 +30,32 @@ void set_last_error(hipError_t e);
 
 inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
+// ------------------------------------------------------------------ launch timing
+
+// While launch timing is on (vct_timing_enable), every launch is bracketed by
+// two events recorded on its stream; the records are folded per kernel name by
+// vct_timing_get.  When off, a launch pays one relaxed atomic load.
+bool timing_on();
+int timing_begin(const char* name, hipStream_t s);
+void timing_end(int rec, hipStream_t s);
+
+struct LaunchTimer {
+    int rec = -1;
+    hipStream_t s;
+    LaunchTimer(const char* name, hipStream_t st) : s(st) {
+        if (timing_on()) rec = timing_begin(name, st);
+    }
+    ~LaunchTimer() {
+        if (rec >= 0) timing_end(rec, s);
+    }
+};
+
+#define VCT_LAUNCH(NAME, KERNEL, GRID, BLOCK, SHM, STREAM, ...)            \
+    do {                                                                  \
+        ::vct::LaunchTimer _vct_lt((NAME), (STREAM));                     \
+        hipLaunchKernelGGL(KERNEL, GRID, BLOCK, SHM, STREAM, __VA_ARGS__); \
+    } while (0)
+
 // Workspace carving: 256-byte aligned slices of a caller buffer.
 struct Carver {
     char* base;

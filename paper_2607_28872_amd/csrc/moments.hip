@@ -527,10 +527,10 @@ static int launch_moments(const vct_nlist* nl, const Grid& g, const double* pos,
     a.cs = nl->cell_start; a.cstart = nl->chunk_start; a.cinfo = reinterpret_cast<const int4*>(nl->chunk_info);
     a.nchunks = nl->chunk_off + ncols; a.mom = mom; a.mflags = mflags;
     const int64_t cap = ncols + n / kChunk + 1;
-    hipLaunchKernelGGL((k_moment_sweeps<D, KERNEL>), dim3((unsigned)cap), dim3(kMThreads), 0, s, a);
+    VCT_LAUNCH("k_moment_sweeps", (k_moment_sweeps<D, KERNEL>), dim3((unsigned)cap), dim3(kMThreads), 0, s, a);
     VCT_LAUNCH_CHECK();
     int64_t nb2 = (n + 127) / 128;
-    hipLaunchKernelGGL((k_moment_solve<D>), dim3((unsigned)nb2), dim3(128), 0, s, n, pos, mom, mflags, invR, mp,
+    VCT_LAUNCH("k_moment_solve", (k_moment_solve<D>), dim3((unsigned)nb2), dim3(128), 0, s, n, pos, mom, mflags, invR, mp,
                        mask, nrows, s64, s32, flags, nflag);
     VCT_LAUNCH_CHECK();
     return VCT_OK;
@@ -569,7 +569,7 @@ extern "C" int vct_moments(const vct_nlist* nl, const double* pos_sorted, const 
     double* mom = cv.take<double>((size_t)n * total);
     uint8_t* mflags = cv.take<uint8_t>((size_t)n);
     unsigned long long* cnt = cv.take<unsigned long long>(8);
-    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, s, cnt);
+    VCT_LAUNCH("k_zero_u64", k_zero_u64, dim3(1), dim3(1), 0, s, cnt);
     VCT_LAUNCH_CHECK();
     if (n > 0) {
         const double invR = 1.0 / nl->R;

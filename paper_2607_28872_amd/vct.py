@@ -87,6 +87,14 @@ def lib():
         L.vct_scatter_sorted.argtypes = [_i64, C.c_int, _vp, _vp, _vp, _vp]
         L.vct_chunk_capacity.restype = _i64
         L.vct_chunk_capacity.argtypes = [C.c_int, _i64, _i64]
+        L.vct_timing_enable.restype = C.c_int
+        L.vct_timing_enable.argtypes = [C.c_int]
+        L.vct_timing_reset.restype = None
+        L.vct_timing_reset.argtypes = []
+        L.vct_timing_count.restype = C.c_int
+        L.vct_timing_count.argtypes = []
+        L.vct_timing_get.restype = C.c_int
+        L.vct_timing_get.argtypes = [C.c_int, C.POINTER(C.c_char_p), C.POINTER(_i64), C.POINTER(C.c_double)]
         L.vct_neighbors_workspace_size.restype = _sz
         L.vct_neighbors_workspace_size.argtypes = [_i64, _i64]
         L.vct_neighbors.restype = C.c_int
@@ -206,6 +214,25 @@ def make_nlist(dim, n, ncell, lo, hi, R, cell_start, chunk_off, chunk_start, chu
     return nl
 
 
+def vct_timing_enable(on):
+    return lib().vct_timing_enable(int(bool(on)))
+
+
+def vct_timing_reset():
+    lib().vct_timing_reset()
+
+
+def vct_timing_read():
+    """{kernel name: (launches, summed ms)} of the launches timed so far."""
+    L = lib()
+    res = {}
+    for k in range(L.vct_timing_count()):
+        nm, cnt, ms = C.c_char_p(), _i64(0), C.c_double(0.0)
+        _check("vct_timing_get", L.vct_timing_get(k, C.byref(nm), C.byref(cnt), C.byref(ms)))
+        res[nm.value.decode()] = (cnt.value, ms.value)
+    return res
+
+
 def vct_neighbors(nl, pos_sorted, col_cap, reuse, ws, stream=None):
     nnz = _i64(0)
     st = lib().vct_neighbors(C.byref(nl), _p(pos_sorted), int(col_cap), C.byref(nnz), int(reuse), _p(ws),
@@ -284,7 +311,11 @@ class Geometry:
         self.col_t = torch.empty(max(nnz, 1), dtype=torch.int32, device=device) if keep_col else None
         self.nl = make_nlist(self.dim, n, self.ncell, lo, hi, R, self.cell_start, self.chunk_off, self.chunk_start,
                              self.chunk_info, self.row_ptr, self.col, self.col16, chunk_cap=cap, col_t=self.col_t)
-        vct_neighbors(self.nl, self.pos, max(nnz, 1), 1, self._nws)
+        # one search that stages the rows and compacts them (falling back to
+        # the fill pass by itself when a row is longer than the staging rows)
+        _, nnz2 = vct_neighbors(self.nl, self.pos, max(nnz, 1), 0, self._nws)
+        if nnz2 != nnz:
+            raise VctError("vct_neighbors", VCT_E_HIP)
         self.state64 = self.state32 = self.flags = None
         self.mask = None
 

@@ -32,7 +32,7 @@ def test_exports_every_declared_symbol(L):
 
 
 def test_status_strings(L):
-    for st in (0, 1, -1, -2, -3, -4, -5):
+    for st in (0, 1, -1, -2, -3, -4, -5, -6):
         assert vct.status_string(st).startswith("VCT_")
     assert vct.status_string(99) == "unknown status"
 
@@ -134,7 +134,21 @@ def test_workspace_errors(L):
     assert L.vct_build_cells_workspace_size(3, 100, nc) > 100 * 4
     assert L.vct_moments_workspace_size(3, 100) >= 100 * 41 * 8
     assert L.vct_adjoint_workspace_size(3, 100, 1000, 16) >= (100 * 7 + 1000) * 8
+    # counts, scan tiles and the 128-entry staging rows of the one-search path
+    assert L.vct_neighbors_workspace_size(1000, nc) >= 1000 * (4 + 128 * 2)
     assert L.vct_chunk_capacity(3, 6400, nc) >= 6400 // 64 + nc
+
+
+def test_launch_timing_registry_without_launches(L):
+    """The timing registry's host protocol (no kernel is launched here)."""
+    vct.vct_timing_reset()
+    assert vct.vct_timing_enable(True) == 0
+    assert vct.vct_timing_enable(True) == 1
+    assert vct.vct_timing_enable(False) == 1
+    assert vct.vct_timing_read() == {}
+    name, cnt, ms = C.c_char_p(), C.c_int64(0), C.c_double(0.0)
+    assert L.vct_timing_get(0, C.byref(name), C.byref(cnt), C.byref(ms)) == vct.VCT_E_ARG
+    assert L.vct_timing_get(-1, None, None, None) == vct.VCT_E_ARG
 
 
 def test_binding_fails_loudly_without_library(monkeypatch):

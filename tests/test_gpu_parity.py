@@ -57,6 +57,33 @@ def test_neighbor_lists_bit_exact(family):
 
 
 @pytest.mark.parametrize("family", FAMILIES)
+def test_staged_search_equals_fill_pass(family):
+    """The one-search path (rows staged, then compacted) writes the same
+    columns, offsets and transposed-entry map as the count + fill passes."""
+    w = I.small(family)
+    g = _geom(w)
+    nl = vct.vct_nlist.from_buffer_copy(g.nl)
+    col, col16, col_t = torch.empty_like(g.col), torch.empty_like(g.col16), torch.empty_like(g.col_t)
+    nl.col, nl.col16, nl.col_t = col.data_ptr(), col16.data_ptr(), col_t.data_ptr()
+    _, nnz = vct.vct_neighbors(nl, g.pos, g.nnz, 1, g._nws)   # row_ptr given: the fill pass
+    assert nnz == g.nnz
+    assert torch.equal(col, g.col) and torch.equal(col16, g.col16) and torch.equal(col_t, g.col_t)
+
+
+def test_long_rows_fall_back_to_the_fill_pass():
+    """Rows longer than the staging rows (here up to about 280 entries) are
+    still listed exactly."""
+    w = I.small("sigma3d")
+    R = 1.4 * w.R
+    g = _geom(w, R=R)
+    rp, col = g.csr_original()
+    assert np.diff(rp).max() > 128
+    orp, ocol = O.neighbors(w.pos, R)
+    assert np.array_equal(rp, orp)
+    assert np.array_equal(col, ocol)
+
+
+@pytest.mark.parametrize("family", FAMILIES)
 @pytest.mark.parametrize("kernel", [I.KERNEL_WENDLAND_C2, I.KERNEL_CUBIC_SPLINE])
 def test_fp64_parity_all_outputs(family, kernel):
     w = I.small(family)
@@ -198,3 +225,23 @@ def test_empty_set():
     assert g.moments(I.MapSpec(), vct.VCT_OUT_DEFAULT) == vct.VCT_OK
     out = g.apply(torch.zeros((1, 1), dtype=torch.float64, device=DEV))
     assert out.shape[0] == 1
+
+
+def test_launch_timing_records_each_kernel():
+    w = I.small("sigma3d")
+    vct.vct_timing_reset()
+    vct.vct_timing_enable(True)
+    try:
+        g = _geom(w)
+        assert g.moments(w.mapspec, vct.VCT_OUT_DEFAULT) == vct.VCT_OK
+        g.apply(g.sorted_field(w.phi), vct.VCT_FP64)
+        g.apply(g.sorted_field(w.phi), vct.VCT_FP64)
+        torch.cuda.synchronize()
+    finally:
+        vct.vct_timing_enable(False)
+    t = vct.vct_timing_read()
+    vct.vct_timing_reset()
+    assert t["k_apply (fp64)"][0] == 2 and t["k_apply (fp64)"][1] > 0.0
+    for k in ("k_cell_keys", "k_nb_chunk (count)", "k_nb_chunk (stage)", "k_nb_compact", "k_moment_sweeps",
+              "k_moment_solve"):
+        assert t[k][0] >= 1, k
