@@ -205,12 +205,19 @@ __global__ __launch_bounds__(256) void k_adjoint_pack(int64_t n, const double* _
 }
 
 // dphi_k = sum_{i in S_k} u_i W_ik - u_k sum_j W_kj, both over the row of k.
+// The chunk's window is walked in sub-windows of kASub particles whose
+// records (position, volume and the packed 128-byte record) are staged in
+// LDS; a row's offsets ascend, so every lane keeps a cursor into its strided
+// share of the row and consumes the entries that fall in the current
+// sub-window.
+constexpr int kASub = 480;   // records per sub-window: 480 x 160 B, two groups per CU
+
 template <int D, int KERNEL>
 __global__ __launch_bounds__(kAThreads, 2) void k_adjoint_dphi(AdjArgs A) {
     using Dm = Dims<D>;
     constexpr int nL = Dm::nL, nk = Dm::nk, m = Dm::m;
-    __shared__ double4 sd[kAWin];   // x, y, z, V
-    __shared__ int32_t sj[kAWin];   // sorted index
+    constexpr int kRec = 1 + kCoef / 4;   // double4 per record: x, y, z, V, then the packed record
+    __shared__ double4 srec[kASub * kRec];
     __shared__ WindowT<D> w;
     const uint32_t b = xcd_tile(blockIdx.x, gridDim.x);
     if (b >= *A.nchunks) return;   // uniform over the work-group
@@ -231,70 +238,71 @@ __global__ __launch_bounds__(kAThreads, 2) void k_adjoint_dphi(AdjArgs A) {
 #pragma unroll
     for (int c = 0; c < nk; ++c) Pk[c] = ck[nL + c];   // u_k P_lap,k
     const double Vk = A.vol[kk];
-    const int64_t rb = valid ? A.row_ptr[kk] : 0, re = valid ? A.row_ptr[kk + 1] : 0;
+    const int64_t re = valid ? A.row_ptr[kk + 1] : 0;
+    int64_t e = (valid ? A.row_ptr[kk] : 0) + lane;
+    int tn = e < re ? (int)A.col16[e] : INT_MAX;
     __syncthreads();
     const int W = __builtin_amdgcn_readfirstlane(w.off[w.nr]);
-    const bool in_lds = W <= kAWin;
-    if (in_lds) {
-        for (int t = threadIdx.x; t < W; t += kAThreads) {
-            const int64_t j = window_global<D>(w, t);
-            sd[t] = make_double4(A.pos[j], A.pos[n + j], D == 3 ? A.pos[2 * n + j] : 0.0, A.vol[j]);
-            sj[t] = (int32_t)j;
-        }
-    }
-    __syncthreads();
     double acc1 = 0.0, self = 0.0;
-    for (int64_t e = rb + lane; e < re; e += kALanes) {
-        const int t = A.col16[e];
-        double4 q;
-        int64_t i;
-        if (in_lds) {
-            q = sd[t];
-            i = sj[t];
-        } else {
-            i = window_global<D>(w, t);
-            q = make_double4(A.pos[i], A.pos[n + i], D == 3 ? A.pos[2 * n + i] : 0.0, A.vol[i]);
+    for (int s0 = 0; s0 < W; s0 += kASub) {
+        const int s1 = W - s0 < kASub ? W : s0 + kASub;
+        if (s0 > 0) __syncthreads();   // the previous sub-window is consumed
+        for (int t = s0 + (int)threadIdx.x; t < s1; t += kAThreads) {
+            const int64_t j = window_global<D>(w, t);
+            double4* dst = srec + (t - s0) * kRec;
+            dst[0] = make_double4(A.pos[j], A.pos[n + j], D == 3 ? A.pos[2 * n + j] : 0.0, A.vol[j]);
+            const double4* src = reinterpret_cast<const double4*>(A.coef + j * kCoef);
+#pragma unroll
+            for (int c = 0; c < kCoef / 4; ++c) dst[1 + c] = src[c];
         }
-        const double2* ci2 = reinterpret_cast<const double2*>(A.coef + i * kCoef);
-        double ci[kCoef];
+        __syncthreads();
+        while (tn < s1) {
+            const double4* rec = srec + (tn - s0) * kRec;
+            e += kALanes;
+            tn = e < re ? (int)A.col16[e] : INT_MAX;
+            const double4 q = rec[0];
+            double ci[kCoef];
 #pragma unroll
-        for (int c = 0; c < kCoef / 2; ++c) {
-            const double2 v = ci2[c];
-            ci[2 * c] = v.x;
-            ci[2 * c + 1] = v.y;
+            for (int c = 0; c < kCoef / 4; ++c) {
+                const double4 v = rec[1 + c];
+                ci[4 * c] = v.x;
+                ci[4 * c + 1] = v.y;
+                ci[4 * c + 2] = v.z;
+                ci[4 * c + 3] = v.w;
+            }
+            double r[D];   // r~_ki
+            r[0] = (q.x - xk[0]) * A.invR;
+            r[1] = (q.y - xk[1]) * A.invR;
+            if (D == 3) r[D - 1] = (q.z - xk[2]) * A.invR;
+            double q2 = 0.0;
+#pragma unroll
+            for (int a = 0; a < D; ++a) q2 += r[a] * r[a];
+            double qv[m];
+#pragma unroll
+            for (int p = 0; p < m; ++p) qv[p] = r[pair_a<D>(p)] * r[pair_b<D>(p)];
+            const double c = kernel_shape<KERNEL>(vsqrt(q2));
+            const double iq4 = vrcp(q2 * q2);
+            double rLk = 0.0, rLi = 0.0, sak = 0.0, ssk = 0.0, sai = 0.0, ssi = 0.0;
+#pragma unroll
+            for (int p = 0; p < nL; ++p) {
+                rLk += Lk2[p] * qv[p];
+                rLi += ci[p] * qv[p];
+            }
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                sak += Pk[a] * r[a];
+                sai += ci[nL + a] * r[a];
+            }
+#pragma unroll
+            for (int p = 0; p < m; ++p) {
+                ssk += Pk[D + p] * qv[p];
+                ssi += ci[nL + D + p] * qv[p];
+            }
+            // u_k W_ki (row k: volume V_i, correction of k) and u_i W_ik (row i:
+            // r~_ik = -r~_ki, volume V_k, correction of i)
+            self += q.w * c * (sak + rLk * iq4 * ssk);
+            acc1 += Vk * c * (rLi * iq4 * ssi - sai);
         }
-        double r[D];   // r~_ki
-        r[0] = (q.x - xk[0]) * A.invR;
-        r[1] = (q.y - xk[1]) * A.invR;
-        if (D == 3) r[D - 1] = (q.z - xk[2]) * A.invR;
-        double q2 = 0.0;
-#pragma unroll
-        for (int a = 0; a < D; ++a) q2 += r[a] * r[a];
-        double qv[m];
-#pragma unroll
-        for (int p = 0; p < m; ++p) qv[p] = r[pair_a<D>(p)] * r[pair_b<D>(p)];
-        const double c = kernel_shape<KERNEL>(vsqrt(q2));
-        const double iq4 = vrcp(q2 * q2);
-        double rLk = 0.0, rLi = 0.0, sak = 0.0, ssk = 0.0, sai = 0.0, ssi = 0.0;
-#pragma unroll
-        for (int p = 0; p < nL; ++p) {
-            rLk += Lk2[p] * qv[p];
-            rLi += ci[p] * qv[p];
-        }
-#pragma unroll
-        for (int a = 0; a < D; ++a) {
-            sak += Pk[a] * r[a];
-            sai += ci[nL + a] * r[a];
-        }
-#pragma unroll
-        for (int p = 0; p < m; ++p) {
-            ssk += Pk[D + p] * qv[p];
-            ssi += ci[nL + D + p] * qv[p];
-        }
-        // u_k W_ki (row k: volume V_i, correction of k) and u_i W_ik (row i:
-        // r~_ik = -r~_ki, volume V_k, correction of i)
-        self += q.w * c * (sak + rLk * iq4 * ssk);
-        acc1 += Vk * c * (rLi * iq4 * ssi - sai);
     }
     acc1 = group_sum(acc1, kALanes);
     self = group_sum(self, kALanes);
@@ -405,12 +413,12 @@ static int launch_adjoint(AdjArgs a, int64_t cap, const MapParams& mp, double* d
     if (a.dphi && a.col_t) {
         VCT_LAUNCH("k_adjoint_weights", (k_adjoint_weights<D, KERNEL>), dim3((unsigned)cap), dim3(kAThreads), 0, s, a);
         VCT_LAUNCH_CHECK();
-        VCT_LAUNCH("k_adjoint_gather", k_adjoint_gather, dim3((unsigned)((n * kALanes + 255) / 256)), dim3(256), 0, s, n,
-                           a.row_ptr, a.wbuf, a.rowsum, a.dphi);
+        VCT_LAUNCH("k_adjoint_gather", k_adjoint_gather, dim3((unsigned)((n * kALanes + 255) / 256)), dim3(256), 0,
+                   s, n, a.row_ptr, a.wbuf, a.rowsum, a.dphi);
         VCT_LAUNCH_CHECK();
     } else if (a.dphi) {
-        VCT_LAUNCH("k_adjoint_pack", (k_adjoint_pack<D>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, a.state,
-                           a.lap_row, a.u, const_cast<double*>(a.coef));
+        VCT_LAUNCH("k_adjoint_pack", (k_adjoint_pack<D>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n,
+                   a.state, a.lap_row, a.u, const_cast<double*>(a.coef));
         VCT_LAUNCH_CHECK();
         VCT_LAUNCH("k_adjoint_dphi", (k_adjoint_dphi<D, KERNEL>), dim3((unsigned)cap), dim3(kAThreads), 0, s, a);
         VCT_LAUNCH_CHECK();
@@ -419,11 +427,11 @@ static int launch_adjoint(AdjArgs a, int64_t cap, const MapParams& mp, double* d
         VCT_LAUNCH("k_adjoint_xi", (k_adjoint_xi<D>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, mp);
         VCT_LAUNCH_CHECK();
         const int64_t nred = (n + kRedThreads - 1) / kRedThreads;
-        VCT_LAUNCH("k_dtheta_partials", k_dtheta_partials, dim3((unsigned)nred), dim3(kRedThreads), 0, s, n, a.pos, D, mp, a.xi,
-                           partials);
+        VCT_LAUNCH("k_dtheta_partials", k_dtheta_partials, dim3((unsigned)nred), dim3(kRedThreads), 0, s, n, a.pos,
+                   D, mp, a.xi, partials);
         VCT_LAUNCH_CHECK();
-        VCT_LAUNCH("k_dtheta_final", k_dtheta_final, dim3((unsigned)mp.nterms), dim3(kRedThreads), 0, s, nred, mp.nterms,
-                           partials, dtheta);
+        VCT_LAUNCH("k_dtheta_final", k_dtheta_final, dim3((unsigned)mp.nterms), dim3(kRedThreads), 0, s, nred,
+                   mp.nterms, partials, dtheta);
         VCT_LAUNCH_CHECK();
     }
     return VCT_OK;

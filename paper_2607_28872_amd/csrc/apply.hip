@@ -419,7 +419,8 @@ __global__ __launch_bounds__(kThreads, ApplyCfg<T>::waves) void k_apply(ApplyArg
 
 template <int D, int KERNEL, class T, class S>
 static int launch_apply(const ApplyArgs<S>& a, int64_t cap, hipStream_t s) {
-    VCT_LAUNCH((sizeof(T) == 4 ? "k_apply (mixed)" : "k_apply (fp64)"), (k_apply<D, KERNEL, T, S>), dim3((unsigned)cap), dim3(kThreads), 0, s, a);
+    const char* name = sizeof(T) == 4 ? "k_apply (mixed)" : "k_apply (fp64)";
+    VCT_LAUNCH(name, (k_apply<D, KERNEL, T, S>), dim3((unsigned)cap), dim3(kThreads), 0, s, a);
     VCT_LAUNCH_CHECK();
     return VCT_OK;
 }

@@ -248,6 +248,7 @@ constexpr int kNbThreads = kChunk * kNbLanes;  // one chunk per work-group
 constexpr int kNbWindow = 2048;                // LDS window capacity (records)
 
 constexpr int kStage = 128;                    // staged row entries per particle
+constexpr int kNbWindowStage = 1520;           // window capacity beside the staged rows (4 groups / CU)
 
 // One chunk per work-group, kNbLanes lanes per particle.  The window positions
 // are staged in LDS as FP32 offsets from the chunk's first particle; a
@@ -257,7 +258,8 @@ constexpr int kStage = 128;                    // staged row entries per particl
 // positions.  MODE 0 writes the counts; MODE 1 writes the columns (ascending)
 // at row_ptr as sorted indices and/or 16-bit window offsets; MODE 2 writes the
 // counts and the first kStage window offsets of every row into a staging
-// buffer (row i at i * kStage), flagging rows that do not fit.
+// buffer (row i at i * kStage), flagging rows that do not fit.  The staged
+// rows are built in LDS and leave as one contiguous block per chunk.
 template <int D, int MODE>
 __global__ __launch_bounds__(kNbThreads) void k_nb_chunk(int64_t n, const double* __restrict__ pos, Grid g,
                                                          double R2, const int64_t* __restrict__ cs,
@@ -269,7 +271,10 @@ __global__ __launch_bounds__(kNbThreads) void k_nb_chunk(int64_t n, const double
                                                          int32_t* __restrict__ col, uint16_t* __restrict__ col16,
                                                          int32_t* __restrict__ overflow) {
     constexpr bool FILL = MODE == 1, STAGE = MODE == 2;
-    __shared__ float4 win[kNbWindow];
+    constexpr int kWin = STAGE ? kNbWindowStage : kNbWindow;
+    __shared__ float4 win[kWin];
+    __shared__ uint4 srow4[STAGE ? kChunk * kStage / 8 : 1];
+    uint16_t* srow = reinterpret_cast<uint16_t*>(srow4);
     __shared__ unsigned int maxoff_bits;
     const uint32_t b = xcd_tile(blockIdx.x, gridDim.x);
     if (b >= *nchunks) return;
@@ -279,7 +284,7 @@ __global__ __launch_bounds__(kNbThreads) void k_nb_chunk(int64_t n, const double
     if (threadIdx.x == 0) chunk_window<D>(g, cs, info, w);
     __syncthreads();
     const int W = w.off[w.nr];
-    const bool in_lds = W <= kNbWindow;
+    const bool in_lds = W <= kWin;
     const double o0 = pos[p0], o1 = pos[n + p0], o2 = (D == 3) ? pos[2 * n + p0] : 0.0;
     if (threadIdx.x == 0) maxoff_bits = 0u;
     __syncthreads();
@@ -298,88 +303,98 @@ __global__ __launch_bounds__(kNbThreads) void k_nb_chunk(int64_t n, const double
     __syncthreads();
     const int lane = threadIdx.x % kNbLanes;
     const int64_t i = p0 + threadIdx.x / kNbLanes;
-    if (i >= p1) return;   // whole 4-lane groups leave together
-    const int gshift = (threadIdx.x % kWave) / kNbLanes * kNbLanes;
-    const uint64_t gmask = 0xFull << gshift;
-    const uint64_t below = (1ull << (threadIdx.x % kWave)) - 1ull;
-    const double xi0 = pos[i], xi1 = pos[n + i], xi2 = (D == 3) ? pos[2 * n + i] : 0.0;
-    // LDS path: offsets from the chunk origin; global path: offsets from the particle
-    const float f0 = in_lds ? (float)(xi0 - o0) : 0.0f, f1 = in_lds ? (float)(xi1 - o1) : 0.0f,
-                f2 = in_lds ? (float)(xi2 - o2) : 0.0f;
-    // Absolute bound on the FP32 error of d2: the two rounded offsets of each
-    // component (magnitude at most the window's largest offset), the rounding
-    // of R^2, and of the FP32 products and sums.
-    const double maxoff = in_lds ? (double)__uint_as_float(maxoff_bits) : 0.0;
-    const double R = sqrt(R2);
-    const double margin = 4.0 * (2.0 * R) * (maxoff * 0x1p-23) + R2 * 0x1p-19;
-    const float in_lim = (float)(R2 - margin), out_lim = (float)(R2 + margin);
-    const int64_t nz = grid_nz<D>(g);
-    const int64_t cz = cell_coord(D == 3 ? xi2 : xi1, g.lo[D - 1], g.inv_cs[D - 1], nz);
-    const int64_t zl = cz > 0 ? cz - 1 : 0, zh = cz + 1 < nz ? cz + 1 : nz - 1;
-    int self_t = -1;
-    int64_t written = 0;
-    const int64_t out0 = FILL ? row_ptr[i] : STAGE ? i * kStage : 0;
-    const int64_t out1 = FILL ? row_ptr[i + 1] : STAGE ? out0 + kStage : 0;
-    // window ranges are the chunk's columns in order; the particle's candidate
-    // cells are the same columns restricted to its z cell +- 1
-    int64_t cx, cy = 0;
-    if (D == 3) { cx = info.x / g.nc[1]; cy = info.x % g.nc[1]; } else cx = info.x;
-    int r = 0;
-    for (int dx = -1; dx <= 1; ++dx) {
-        const int64_t x = cx + dx;
-        if (x < 0 || x >= g.nc[0]) continue;
-        for (int dy = (D == 3 ? -1 : 0); dy <= (D == 3 ? 1 : 0); ++dy) {
-            int64_t colid;
-            if (D == 3) {
-                const int64_t y = cy + dy;
-                if (y < 0 || y >= g.nc[1]) continue;
-                colid = x * g.nc[1] + y;
-            } else {
-                colid = x;
-            }
-            const int64_t ga = cs[col_key<D>(g, colid, zl)], gb = cs[col_key<D>(g, colid, zh) + 1];
-            const int64_t base = (int64_t)w.off[r] - w.gstart[r];   // window offset = sorted index + base
-            if (dx == 0 && dy == 0) self_t = (int)(i + base);
-            const int ta = (int)(ga + base), tb = (int)(gb + base);
-            for (int t0 = ta; t0 < tb; t0 += kNbLanes) {
-                const int t = t0 + lane;
-                bool hit = false;
-                if (t < tb && t != self_t) {
-                    const int64_t j = t - base;
-                    float4 q;
-                    if (in_lds) q = win[t];
-                    else q = make_float4((float)(pos[j] - xi0), (float)(pos[n + j] - xi1),
-                                         D == 3 ? (float)(pos[2 * n + j] - xi2) : 0.0f, 0.0f);
-                    const float ex = q.x - f0, ey = q.y - f1, ez = q.z - f2;
-                    const float d2f = ex * ex + ey * ey + ez * ez;
-                    if (d2f < in_lim) hit = true;
-                    else if (d2f <= out_lim)
-                        hit = within_exact(pos[j] - xi0, pos[n + j] - xi1, D == 3 ? pos[2 * n + j] - xi2 : 0.0, R2);
+    const int np = (int)(p1 - p0);
+    if (!STAGE && i >= p1) return;   // whole 4-lane groups leave together
+    if (i < p1) {
+        const int gshift = (threadIdx.x % kWave) / kNbLanes * kNbLanes;
+        const uint64_t gmask = 0xFull << gshift;
+        const uint64_t below = (1ull << (threadIdx.x % kWave)) - 1ull;
+        const double xi0 = pos[i], xi1 = pos[n + i], xi2 = (D == 3) ? pos[2 * n + i] : 0.0;
+        // LDS path: offsets from the chunk origin; global path: offsets from the particle
+        const float f0 = in_lds ? (float)(xi0 - o0) : 0.0f, f1 = in_lds ? (float)(xi1 - o1) : 0.0f,
+                    f2 = in_lds ? (float)(xi2 - o2) : 0.0f;
+        // Absolute bound on the FP32 error of d2: the two rounded offsets of each
+        // component (magnitude at most the window's largest offset), the rounding
+        // of R^2, and of the FP32 products and sums.
+        const double maxoff = in_lds ? (double)__uint_as_float(maxoff_bits) : 0.0;
+        const double R = sqrt(R2);
+        const double margin = 4.0 * (2.0 * R) * (maxoff * 0x1p-23) + R2 * 0x1p-19;
+        const float in_lim = (float)(R2 - margin), out_lim = (float)(R2 + margin);
+        const int64_t nz = grid_nz<D>(g);
+        const int64_t cz = cell_coord(D == 3 ? xi2 : xi1, g.lo[D - 1], g.inv_cs[D - 1], nz);
+        const int64_t zl = cz > 0 ? cz - 1 : 0, zh = cz + 1 < nz ? cz + 1 : nz - 1;
+        int self_t = -1;
+        int64_t written = 0;
+        const int64_t out0 = FILL ? row_ptr[i] : STAGE ? (i - p0) * kStage : 0;
+        const int64_t out1 = FILL ? row_ptr[i + 1] : STAGE ? out0 + kStage : 0;
+        // window ranges are the chunk's columns in order; the particle's candidate
+        // cells are the same columns restricted to its z cell +- 1
+        int64_t cx, cy = 0;
+        if (D == 3) { cx = info.x / g.nc[1]; cy = info.x % g.nc[1]; } else cx = info.x;
+        int r = 0;
+        for (int dx = -1; dx <= 1; ++dx) {
+            const int64_t x = cx + dx;
+            if (x < 0 || x >= g.nc[0]) continue;
+            for (int dy = (D == 3 ? -1 : 0); dy <= (D == 3 ? 1 : 0); ++dy) {
+                int64_t colid;
+                if (D == 3) {
+                    const int64_t y = cy + dy;
+                    if (y < 0 || y >= g.nc[1]) continue;
+                    colid = x * g.nc[1] + y;
+                } else {
+                    colid = x;
                 }
-                const uint64_t m = (uint64_t)__ballot(hit) & gmask;
-                if ((FILL || STAGE) && hit) {
-                    const int64_t at = out0 + written + __popcll(m & below);
-                    if (at < out1) {
-                        if (FILL && col) col[at] = (int32_t)(t - base);
-                        if (col16) col16[at] = (uint16_t)t;
+                const int64_t ga = cs[col_key<D>(g, colid, zl)], gb = cs[col_key<D>(g, colid, zh) + 1];
+                const int64_t base = (int64_t)w.off[r] - w.gstart[r];   // window offset = sorted index + base
+                if (dx == 0 && dy == 0) self_t = (int)(i + base);
+                const int ta = (int)(ga + base), tb = (int)(gb + base);
+                for (int t0 = ta; t0 < tb; t0 += kNbLanes) {
+                    const int t = t0 + lane;
+                    bool hit = false;
+                    if (t < tb && t != self_t) {
+                        const int64_t j = t - base;
+                        float4 q;
+                        if (in_lds) q = win[t];
+                        else q = make_float4((float)(pos[j] - xi0), (float)(pos[n + j] - xi1),
+                                             D == 3 ? (float)(pos[2 * n + j] - xi2) : 0.0f, 0.0f);
+                        const float ex = q.x - f0, ey = q.y - f1, ez = q.z - f2;
+                        const float d2f = ex * ex + ey * ey + ez * ez;
+                        if (d2f < in_lim) hit = true;
+                        else if (d2f <= out_lim)
+                            hit = within_exact(pos[j] - xi0, pos[n + j] - xi1, D == 3 ? pos[2 * n + j] - xi2 : 0.0, R2);
                     }
+                    const uint64_t m = (uint64_t)__ballot(hit) & gmask;
+                    if ((FILL || STAGE) && hit) {
+                        const int64_t at = out0 + written + __popcll(m & below);
+                        if (at < out1) {
+                            if (FILL && col) col[at] = (int32_t)(t - base);
+                            if (FILL && col16) col16[at] = (uint16_t)t;
+                            if (STAGE) srow[at] = (uint16_t)t;
+                        }
+                    }
+                    written += __popcll(m);
                 }
-                written += __popcll(m);
+                ++r;
             }
-            ++r;
+        }
+        if (!FILL && lane == 0) {
+            counts[i] = (int32_t)written;
+            if (STAGE && written > kStage) atomicOr(overflow + 2, 1);
         }
     }
-    if (!FILL && lane == 0) {
-        counts[i] = (int32_t)written;
-        if (STAGE && written > kStage) atomicOr(overflow + 2, 1);
+    if (STAGE) {   // the chunk's staged rows, contiguous at p0 * kStage
+        __syncthreads();
+        uint4* dst = reinterpret_cast<uint4*>(col16 + p0 * kStage);
+        for (int k = threadIdx.x; k < np * (kStage / 8); k += kNbThreads) dst[k] = srow4[k];
     }
 }
 
 // Copy every staged row to its place in the column arrays (offsets, and
-// sorted indices through the chunk window when col is wanted).  The
-// work-group walks its chunk's contiguous output range one entry per thread,
-// so the stores are coalesced; each entry finds its row by bisection over the
-// chunk's row pointers held in LDS.
+// sorted indices through the chunk window when col is wanted).  The chunk's
+// staged rows are one contiguous block, read into LDS with 16-byte loads;
+// a row map in LDS gives each output entry its row, and the work-group walks
+// the chunk's contiguous output range one entry per thread.  Every row of
+// the chunk holds at most kStage entries (the caller checks the flag first).
 template <int D>
 __global__ __launch_bounds__(512) void k_nb_compact(Grid g, const int64_t* __restrict__ cs,
                                                     const int32_t* __restrict__ cstart,
@@ -388,23 +403,33 @@ __global__ __launch_bounds__(512) void k_nb_compact(Grid g, const int64_t* __res
                                                     const int64_t* __restrict__ row_ptr,
                                                     const uint16_t* __restrict__ staged,
                                                     int32_t* __restrict__ col, uint16_t* __restrict__ col16) {
+    constexpr int kT = 512, kRowLanes = kT / kChunk;
     __shared__ WindowT<D> w;
     __shared__ int64_t rp[kChunk + 1];
+    __shared__ uint4 srow4[kChunk * kStage / 8];
+    __shared__ uint8_t rowof[kChunk * kStage];
+    const uint16_t* srow = reinterpret_cast<const uint16_t*>(srow4);
     const uint32_t b = xcd_tile(blockIdx.x, gridDim.x);
     if (b >= *nchunks) return;   // uniform over the work-group
     const int64_t p0 = cstart[b];
     const int np = (int)(cstart[b + 1] - p0);
     if (col && threadIdx.x < kWave) chunk_window_wave<D>(g, cs, cinfo[b], w);
     if (threadIdx.x <= (unsigned)np) rp[threadIdx.x] = row_ptr[p0 + threadIdx.x];
+    const uint4* src = reinterpret_cast<const uint4*>(staged + p0 * kStage);
+    for (int k = threadIdx.x; k < np * (kStage / 8); k += kT) srow4[k] = src[k];
     __syncthreads();
     const int64_t e0 = rp[0], e1 = rp[np];
-    for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
-        int lo = 0, hi = np;   // rp[lo] <= e < rp[hi]
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (rp[mid] <= e) lo = mid; else hi = mid;
+    {
+        const int r = threadIdx.x / kRowLanes;
+        if (r < np) {
+            const int a0 = (int)(rp[r] - e0), a1 = (int)(rp[r + 1] - e0);
+            for (int k = a0 + (int)(threadIdx.x % kRowLanes); k < a1; k += kRowLanes) rowof[k] = (uint8_t)r;
         }
-        const uint16_t t = staged[(p0 + lo) * kStage + (e - rp[lo])];
+    }
+    __syncthreads();
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += kT) {
+        const int r = rowof[e - e0];
+        const uint16_t t = srow[r * kStage + (int)(e - rp[r])];
         if (col16) col16[e] = t;
         if (col) col[e] = (int32_t)window_global<D>(w, t);
     }
@@ -453,20 +478,20 @@ extern "C" int vct_build_cells(int dim, int64_t n, const double* pos, const doub
     if ((st = fill_i32(bad, 1, 0, s))) return st;
     if (n > 0) {
         VCT_LAUNCH("k_cell_keys", k_cell_keys, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, dim, n, pos, g,
-                           keys, counts, bad);
+                   keys, counts, bad);
         VCT_LAUNCH_CHECK();
     }
     if ((st = exclusive_scan(counts, ncell, cell_start, tiles, s))) return st;
     if (n > 0) {
         if ((st = fill_i32(counts, ncell, 0, s))) return st;
         VCT_LAUNCH("k_cell_scatter", k_cell_scatter, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, keys,
-                           cell_start, counts, perm);
+                   cell_start, counts, perm);
         VCT_LAUNCH_CHECK();
         VCT_LAUNCH("k_cell_sort", k_cell_sort, dim3((unsigned)((ncell + 255) / 256)), dim3(256), 0, s, ncell,
-                           cell_start, perm);
+                   cell_start, perm);
         VCT_LAUNCH_CHECK();
         VCT_LAUNCH("k_gather", k_gather, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, dim, perm, pos,
-                           pos_sorted);
+                   pos_sorted);
         VCT_LAUNCH_CHECK();
     }
     int32_t hbad = 0;
@@ -481,7 +506,7 @@ extern "C" int vct_gather_sorted(int64_t n, int ncomp, const int32_t* perm, cons
     if (n == 0) return VCT_OK;
     if (!perm || !src || !dst || src == dst) return VCT_E_ARG;
     VCT_LAUNCH("k_gather", k_gather, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, as_stream(stream), n, ncomp,
-                       perm, src, dst);
+               perm, src, dst);
     VCT_LAUNCH_CHECK();
     return VCT_OK;
 }
@@ -492,7 +517,7 @@ extern "C" int vct_scatter_sorted(int64_t n, int ncomp, const int32_t* perm, con
     if (n == 0) return VCT_OK;
     if (!perm || !src || !dst || src == dst) return VCT_E_ARG;
     VCT_LAUNCH("k_scatter", k_scatter, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, as_stream(stream), n, ncomp,
-                       perm, src, dst);
+               perm, src, dst);
     VCT_LAUNCH_CHECK();
     return VCT_OK;
 }
@@ -592,7 +617,7 @@ static int build_chunks(const vct_nlist* nl, const Grid& g, int32_t* tmp, int64_
     int st = exclusive_scan(tmp, ncols, nl->chunk_off, tiles, s);
     if (st) return st;
     VCT_LAUNCH("k_chunk_fill", (k_chunk_fill<D>), dim3(nb), dim3(256), 0, s, g, nl->n, nl->cell_start, nl->chunk_off,
-                       nl->chunk_start, reinterpret_cast<int4*>(nl->chunk_info));
+               nl->chunk_start, reinterpret_cast<int4*>(nl->chunk_info));
     VCT_LAUNCH_CHECK();
     return VCT_OK;
 }
@@ -602,10 +627,11 @@ static int launch_nb(const vct_nlist* nl, const double* pos, const Grid& g, int3
                      uint16_t* staged, hipStream_t s) {
     const int64_t ncols = D == 3 ? g.nc[0] * g.nc[1] : g.nc[0];
     const int64_t cap = ncols + nl->n / kChunk + 1;   // upper bound of the chunk count
-    VCT_LAUNCH((MODE == 0 ? "k_nb_chunk (count)" : MODE == 1 ? "k_nb_chunk (fill)" : "k_nb_chunk (stage)"), (k_nb_chunk<D, MODE>), dim3((unsigned)cap), dim3(kNbThreads), 0, s, nl->n, pos, g,
-                       nl->R * nl->R, nl->cell_start, nl->chunk_start,
-                       reinterpret_cast<const int4*>(nl->chunk_info), nl->chunk_off + ncols, counts, nl->row_ptr,
-                       MODE == 1 ? nl->col : nullptr, MODE == 1 ? nl->col16 : staged, overflow);
+    const char* name = MODE == 0 ? "k_nb_chunk (count)" : MODE == 1 ? "k_nb_chunk (fill)" : "k_nb_chunk (stage)";
+    VCT_LAUNCH(name, (k_nb_chunk<D, MODE>), dim3((unsigned)cap), dim3(kNbThreads), 0, s, nl->n, pos, g,
+               nl->R * nl->R, nl->cell_start, nl->chunk_start,
+               reinterpret_cast<const int4*>(nl->chunk_info), nl->chunk_off + ncols, counts, nl->row_ptr,
+               MODE == 1 ? nl->col : nullptr, MODE == 1 ? nl->col16 : staged, overflow);
     VCT_LAUNCH_CHECK();
     return VCT_OK;
 }
@@ -615,8 +641,8 @@ static int launch_compact(const vct_nlist* nl, const Grid& g, const uint16_t* st
     const int64_t ncols = D == 3 ? g.nc[0] * g.nc[1] : g.nc[0];
     const int64_t cap = ncols + nl->n / kChunk + 1;
     VCT_LAUNCH("k_nb_compact", (k_nb_compact<D>), dim3((unsigned)cap), dim3(512), 0, s, g, nl->cell_start,
-                       nl->chunk_start, reinterpret_cast<const int4*>(nl->chunk_info), nl->chunk_off + ncols,
-                       nl->row_ptr, staged, nl->col, nl->col16);
+               nl->chunk_start, reinterpret_cast<const int4*>(nl->chunk_info), nl->chunk_off + ncols,
+               nl->row_ptr, staged, nl->col, nl->col16);
     VCT_LAUNCH_CHECK();
     return VCT_OK;
 }
@@ -678,7 +704,7 @@ extern "C" int vct_neighbors(vct_nlist* nl, const double* pos_sorted, int64_t co
     }
     if (nl->col_t && n > 0) {
         VCT_LAUNCH("k_col_transpose", k_col_transpose, dim3((unsigned)((n * kTLanes + 255) / 256)), dim3(256), 0, s, n,
-                           nl->row_ptr, nl->col, nl->col_t, flag + 1);
+                   nl->row_ptr, nl->col, nl->col_t, flag + 1);
         VCT_LAUNCH_CHECK();
     }
     VCT_HIP_CHECK(hipMemcpyAsync(hflag, flag, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));

@@ -530,8 +530,8 @@ static int launch_moments(const vct_nlist* nl, const Grid& g, const double* pos,
     VCT_LAUNCH("k_moment_sweeps", (k_moment_sweeps<D, KERNEL>), dim3((unsigned)cap), dim3(kMThreads), 0, s, a);
     VCT_LAUNCH_CHECK();
     int64_t nb2 = (n + 127) / 128;
-    VCT_LAUNCH("k_moment_solve", (k_moment_solve<D>), dim3((unsigned)nb2), dim3(128), 0, s, n, pos, mom, mflags, invR, mp,
-                       mask, nrows, s64, s32, flags, nflag);
+    VCT_LAUNCH("k_moment_solve", (k_moment_solve<D>), dim3((unsigned)nb2), dim3(128), 0, s, n, pos, mom, mflags,
+               invR, mp, mask, nrows, s64, s32, flags, nflag);
     VCT_LAUNCH_CHECK();
     return VCT_OK;
 }
