@@ -18,6 +18,8 @@
 // monomial sums.  Kernel 2 (one thread per particle) solves the Schur system
 // with partial pivoting and writes, per output row o and neighbour sum c, the
 // coefficient P_i[o][c] of the physical output in terms of [a; s].
+#include <type_traits>
+
 #include "common.h"
 #include "map_dev.h"
 #include "tiles.h"
@@ -75,13 +77,31 @@ __device__ __forceinline__ double sym_at(const double (&S)[Dims<D>::nL], int a, 
 
 // ------------------------------------------------------------------ kernel 1: sweeps
 
-constexpr int kMLanes = 8;                    // lanes per particle
-constexpr int kMThreads = kChunk * kMLanes;   // one chunk per work-group
-constexpr int kMWin = 1600;                   // LDS window capacity (records)
-#ifndef VCT_SWEEP_WAVES
-#define VCT_SWEEP_WAVES 2
+// Launch shape (overridable at build time for tuning).  A work-group is one
+// chunk with kMLanes lanes per particle; its LDS (window records plus the L
+// and B sums of the chunk, about 53 KB at 1400 records) and its registers (at
+// most 168 VGPRs) let three work-groups share a CU, so the staging of one
+// overlaps the sweeps of the others.  Windows larger than kMWin (about 1% at
+// the 8.4M-particle sigma set) read their records from global memory.
+#ifndef VCT_MLANES
+#define VCT_MLANES 4
 #endif
-constexpr int kMSlots = 14;                   // row entries per lane held in registers
+#ifndef VCT_MWIN
+#define VCT_MWIN 1400
+#endif
+#ifndef VCT_SWEEP_WAVES
+#define VCT_SWEEP_WAVES 3
+#endif
+#ifndef VCT_MSLOTS
+#define VCT_MSLOTS 28
+#endif
+#ifndef VCT_SWEEP2_AHEAD
+#define VCT_SWEEP2_AHEAD true
+#endif
+constexpr int kMLanes = VCT_MLANES;           // lanes per particle
+constexpr int kMThreads = kChunk * kMLanes;   // one chunk per work-group
+constexpr int kMWin = VCT_MWIN;               // LDS window capacity (records)
+constexpr int kMSlots = VCT_MSLOTS;           // row entries per lane held in registers
 
 struct SweepArgs {
     int64_t n;
@@ -109,6 +129,7 @@ __global__ __launch_bounds__(kMThreads, VCT_SWEEP_WAVES) void k_moment_sweeps(Sw
     using Dm = Dims<D>;
     using ML = MomLayout<D>;
     __shared__ double4 sd[kMWin];
+    __shared__ double sLB[ML::oC * kChunk];   // L and B of every particle, kept out of registers in sweep 2
     __shared__ WindowT<D> w;
     const uint32_t b = xcd_tile(blockIdx.x, gridDim.x);
     if (b >= *A.nchunks) return;   // uniform over the work-group
@@ -164,8 +185,8 @@ __global__ __launch_bounds__(kMThreads, VCT_SWEEP_WAVES) void k_moment_sweeps(Sw
     };
     // visits every row entry: the register slots (records read one ahead
     // when the window is in LDS), then the rest of a long row
-    auto sweep = [&](auto&& body) {
-        if (in_lds) {
+    auto sweep = [&](auto&& body, auto ahead) {
+        if (in_lds && decltype(ahead)::value) {
             double4 qn = sd[cols(0)];
 #pragma unroll
             for (int s = 0; s < kMSlots; ++s) {
@@ -175,6 +196,10 @@ __global__ __launch_bounds__(kMThreads, VCT_SWEEP_WAVES) void k_moment_sweeps(Sw
                 if (s < nslot) body(q);
                 __builtin_amdgcn_sched_barrier(0);
             }
+        } else if (in_lds) {
+#pragma unroll
+            for (int s = 0; s < kMSlots; ++s)
+                if (s < nslot) body(sd[cols(s)]);
         } else {
 #pragma unroll 1
             for (int s = 0; s < kMSlots; ++s)
@@ -214,7 +239,7 @@ __global__ __launch_bounds__(kMThreads, VCT_SWEEP_WAVES) void k_moment_sweeps(Sw
         for (int p = 0; p < Dm::nL; ++p) Am[p] += wgt * qv[p];
 #pragma unroll
         for (int t = 0; t < Dm::n3; ++t) B[t] += wgt * cub[t];
-    });
+    }, std::true_type{});
 #pragma unroll
     for (int p = 0; p < Dm::nL; ++p) Am[p] = group_sum(Am[p], kMLanes);
 #pragma unroll
@@ -226,6 +251,9 @@ __global__ __launch_bounds__(kMThreads, VCT_SWEEP_WAVES) void k_moment_sweeps(Sw
     double L2[Dm::nL];
 #pragma unroll
     for (int p = 0; p < Dm::nL; ++p) L2[p] = (pair_a<D>(p) == pair_b<D>(p) ? 1.0 : 2.0) * L[p];
+#pragma unroll
+    for (int v = 0; v < ML::oC; ++v)
+        if (v % kMLanes == lane) sLB[v * kChunk + pl] = v < ML::oB ? L[v] : B[v - ML::oB];
 
     // sweep 2: C (3rd order) and E (4th order), weights V F~ (skipped for a
     // flagged particle: its state is NaN anyway)
@@ -249,7 +277,7 @@ __global__ __launch_bounds__(kMThreads, VCT_SWEEP_WAVES) void k_moment_sweeps(Sw
         for (int t = 0; t < Dm::n4; ++t)
             E[t] += wgt * qv[sym_index<D>(mono_comp<D, 4>(t, 0), mono_comp<D, 4>(t, 1))] *
                     qv[sym_index<D>(mono_comp<D, 4>(t, 2), mono_comp<D, 4>(t, 3))];
-    });
+    }, std::integral_constant<bool, VCT_SWEEP2_AHEAD>{});
 #pragma unroll
     for (int t = 0; t < Dm::n3; ++t) Cm[t] = group_sum(Cm[t], kMLanes);
 #pragma unroll
@@ -261,17 +289,16 @@ __global__ __launch_bounds__(kMThreads, VCT_SWEEP_WAVES) void k_moment_sweeps(Sw
     double* ssum = reinterpret_cast<double*>(sd);
     __syncthreads();
 #pragma unroll
-    for (int v = 0; v < ML::total; ++v) {
+    for (int v = ML::oC; v < ML::total; ++v) {
         if (v % kMLanes != lane) continue;
-        ssum[v * kChunk + pl] = v < ML::oB ? L[v] : v < ML::oC ? B[v - ML::oB] : v < ML::oE ? Cm[v - ML::oC]
-                                                                                             : E[v - ML::oE];
+        ssum[(v - ML::oC) * kChunk + pl] = v < ML::oE ? Cm[v - ML::oC] : E[v - ML::oE];
     }
     __syncthreads();
     {
         const int q = threadIdx.x % kChunk;
         if (p0 + q < p1)
             for (int v = threadIdx.x / kChunk; v < ML::total; v += kMThreads / kChunk)
-                A.mom[(int64_t)v * n + p0 + q] = ssum[v * kChunk + q];
+                A.mom[(int64_t)v * n + p0 + q] = v < ML::oC ? sLB[v * kChunk + q] : ssum[(v - ML::oC) * kChunk + q];
     }
     if (valid && lane == 0) A.mflags[ii] = (uint8_t)fl;
 }
