@@ -33,23 +33,61 @@ namespace vct {
 
 int nlist_check(const vct_nlist* nl, Grid& g);
 
-constexpr int kLanes = 8;                    // lanes per particle
-constexpr int kThreads = kChunk * kLanes;    // one chunk per work-group
 constexpr int kColCap = 7168;                // row entries of a chunk staged in LDS
-constexpr int kColBlocks = (kColCap / 8 + kThreads - 1) / kThreads;   // 16-byte blocks per thread
 
-// Register slots per lane, occupancy target and LDS window capacity (records)
-// of each arithmetic type.
+// Lanes per particle, register slots per lane, occupancy target (waves per
+// SIMD) and LDS window capacity (records) of each arithmetic type
+// (overridable at build time for tuning).  FP32 sums: 512-thread groups at
+// 4 waves per SIMD (two groups per CU).  FP64 sums need about 250 VGPRs, so
+// they run 256-thread groups (4 lanes per particle) at 2 waves per SIMD with a
+// smaller window (about 76 KB of LDS): again two groups per CU, where eight
+// lanes per particle would leave one.
+#ifndef VCT_APPLY_F_LANES
+#define VCT_APPLY_F_LANES 8
+#endif
+#ifndef VCT_APPLY_F_SLOTS
+#define VCT_APPLY_F_SLOTS 14
+#endif
+#ifndef VCT_APPLY_F_WAVES
+#define VCT_APPLY_F_WAVES 4
+#endif
+#ifndef VCT_APPLY_F_WIN
+#define VCT_APPLY_F_WIN 1664
+#endif
+#ifndef VCT_APPLY_D_LANES
+#define VCT_APPLY_D_LANES 4
+#endif
+#ifndef VCT_APPLY_D_SLOTS
+#define VCT_APPLY_D_SLOTS 20
+#endif
+#ifndef VCT_APPLY_D_WAVES
+#define VCT_APPLY_D_WAVES 2
+#endif
+#ifndef VCT_APPLY_D_WIN
+#define VCT_APPLY_D_WIN 1400
+#endif
+#ifndef VCT_APPLY_F_COLS
+#define VCT_APPLY_F_COLS true
+#endif
+#ifndef VCT_APPLY_D_COLS
+#define VCT_APPLY_D_COLS true
+#endif
 template <class T> struct ApplyCfg;
 template <> struct ApplyCfg<float> {
-    static constexpr int slots = 14;
-    static constexpr int waves = 4;
-    static constexpr int win = 1664;
+    static constexpr int lanes = VCT_APPLY_F_LANES;
+    static constexpr int slots = VCT_APPLY_F_SLOTS;
+    static constexpr int waves = VCT_APPLY_F_WAVES;
+    static constexpr int win = VCT_APPLY_F_WIN;
+    static constexpr bool col_lds = VCT_APPLY_F_COLS;   // stage the chunk's row entries in LDS
+    static constexpr int threads = kChunk * lanes;   // one chunk per work-group
 };
 template <> struct ApplyCfg<double> {
-    static constexpr int slots = 14;
-    static constexpr int waves = 2;
-    static constexpr int win = 1600;
+    static constexpr int lanes = VCT_APPLY_D_LANES;
+    static constexpr int slots = VCT_APPLY_D_SLOTS;
+    static constexpr int waves = VCT_APPLY_D_WAVES;
+    static constexpr int win = VCT_APPLY_D_WIN;
+    static constexpr bool col_lds = VCT_APPLY_D_COLS;
+    static constexpr int threads = kChunk * lanes;
 };
 
 template <class S> struct ApplyArgs {
@@ -112,7 +150,7 @@ __device__ __forceinline__ void pair_sums(const T (&r)[D], T q2, T vc, T psi, co
 template <int D, class T>
 __device__ __forceinline__ void group_gradient(const T (&L2)[Dims<D>::nL], T (&a1)[D], T (&Gt)[D]) {
 #pragma unroll
-    for (int a = 0; a < D; ++a) a1[a] = group_sum(a1[a], kLanes);
+    for (int a = 0; a < D; ++a) a1[a] = group_sum(a1[a], ApplyCfg<T>::lanes);
 #pragma unroll
     for (int a = 0; a < D; ++a) {
         T t = T(0);
@@ -156,7 +194,7 @@ __device__ __forceinline__ double out_row(const ApplyArgs<S>& A, int64_t i, int 
 template <int D, int KERNEL, class T, class S>
 __device__ __forceinline__ void apply_chunk_global(const ApplyArgs<S>& A, const WindowT<D>& w, int64_t p0,
                                                 int64_t p1) {
-    constexpr int nk = Dims<D>::nk;
+    constexpr int nk = Dims<D>::nk, kLanes = ApplyCfg<T>::lanes;
     const int64_t n = A.n;
     const int lane = threadIdx.x % kLanes;
     const int64_t i = p0 + threadIdx.x / kLanes;
@@ -215,12 +253,14 @@ __device__ __forceinline__ void apply_chunk_global(const ApplyArgs<S>& A, const 
 }
 
 template <int D, int KERNEL, class T, class S>
-__global__ __launch_bounds__(kThreads, ApplyCfg<T>::waves) void k_apply(ApplyArgs<S> A) {
+__global__ __launch_bounds__(ApplyCfg<T>::threads, ApplyCfg<T>::waves) void k_apply(ApplyArgs<S> A) {
     using Dm = Dims<D>;
     constexpr int nk = Dm::nk, kS = ApplyCfg<T>::slots, kW = ApplyCfg<T>::win;
+    constexpr int kLanes = ApplyCfg<T>::lanes, kThreads = ApplyCfg<T>::threads;
+    constexpr int kColBlocks = (kColCap / 8 + kThreads - 1) / kThreads;   // 16-byte blocks per thread
     __shared__ double4 sd[kW];
     __shared__ T sv[kW];
-    __shared__ uint4 scol4[kColCap / 8];
+    __shared__ uint4 scol4[ApplyCfg<T>::col_lds ? kColCap / 8 : 1];
     __shared__ T sacc[kChunk][nk + D];
     __shared__ WindowT<D> w;
     const uint32_t b = xcd_tile(blockIdx.x, gridDim.x);
@@ -243,27 +283,19 @@ __global__ __launch_bounds__(kThreads, ApplyCfg<T>::waves) void k_apply(ApplyArg
     // the chunk's row entries [cb, ce), staged from the 16-byte aligned cb8
     const int64_t cb = A.row_ptr[p0], ce = A.row_ptr[p1], nnz = A.row_ptr[n];
     const int64_t cb8 = cb & ~int64_t(7);
-    const bool col_lds = ce - cb8 <= kColCap;
+    const bool col_lds = ApplyCfg<T>::col_lds && ce - cb8 <= kColCap;
     __syncthreads();
     const int W = __builtin_amdgcn_readfirstlane(w.off[w.nr]);
     if (W > kW) {
         apply_chunk_global<D, KERNEL, T, S>(A, w, p0, p1);
         return;
     }
-    // stage the window records and the chunk's row entries; every load of a
-    // thread is issued before its first LDS store
+    // stage the window records and the chunk's row entries, in batches of
+    // loads that are all issued before the batch's first LDS store
     {
         constexpr int kRep = (kW + kThreads - 1) / kThreads;
+        constexpr int kBatch = kRep < 4 ? kRep : 4;
         const double* ph = A.phi;
-        double4 q[kRep];
-        T v[kRep];
-#pragma unroll
-        for (int k = 0; k < kRep; ++k) {
-            const int t = threadIdx.x + k * kThreads;
-            const int64_t j = window_global<D>(w, t < W ? t : 0);
-            q[k] = make_double4(A.pos[j], A.pos[n + j], D == 3 ? A.pos[2 * n + j] : 0.0, ph[j]);
-            v[k] = T(A.vol[j]);
-        }
         uint4 cv[kColBlocks];
         if (col_lds) {
 #pragma unroll
@@ -283,11 +315,23 @@ __global__ __launch_bounds__(kThreads, ApplyCfg<T>::waves) void k_apply(ApplyArg
             }
         }
 #pragma unroll
-        for (int k = 0; k < kRep; ++k) {
-            const int t = threadIdx.x + k * kThreads;
-            if (t < W) {
-                sd[t] = q[k];
-                sv[t] = v[k];
+        for (int k0 = 0; k0 < kRep; k0 += kBatch) {
+            double4 q[kBatch];
+            T v[kBatch];
+#pragma unroll
+            for (int k = 0; k < kBatch; ++k) {
+                const int t = threadIdx.x + (k0 + k) * kThreads;
+                const int64_t j = window_global<D>(w, t < W ? t : 0);
+                q[k] = make_double4(A.pos[j], A.pos[n + j], D == 3 ? A.pos[2 * n + j] : 0.0, ph[j]);
+                v[k] = T(A.vol[j]);
+            }
+#pragma unroll
+            for (int k = 0; k < kBatch; ++k) {
+                const int t = threadIdx.x + (k0 + k) * kThreads;
+                if (t < W) {
+                    sd[t] = q[k];
+                    sv[t] = v[k];
+                }
             }
         }
         if (col_lds) {
@@ -365,7 +409,11 @@ __global__ __launch_bounds__(kThreads, ApplyCfg<T>::waves) void k_apply(ApplyArg
         double Gp[D];
 #pragma unroll
         for (int a = 0; a < D; ++a) Gp[a] = (double)Gt[a] * A.invR;
-        // pass 2: sums of the residual psi_ij = phi_ij - (x_j - x_i) . G
+        // pass 2: sums of the residual psi_ij = phi_ij - (x_j - x_i) . G.
+        // The empty asm makes the packed offsets opaque, so the record
+        // addresses are recomputed here instead of being kept live from pass 1.
+#pragma unroll
+        for (int k = 0; k < (kS + 1) / 2; ++k) asm volatile("" : "+v"(cpk[k]));
         T acc[nk];
 #pragma unroll
         for (int c = 0; c < nk; ++c) acc[c] = T(0);
@@ -420,7 +468,7 @@ __global__ __launch_bounds__(kThreads, ApplyCfg<T>::waves) void k_apply(ApplyArg
 template <int D, int KERNEL, class T, class S>
 static int launch_apply(const ApplyArgs<S>& a, int64_t cap, hipStream_t s) {
     const char* name = sizeof(T) == 4 ? "k_apply (mixed)" : "k_apply (fp64)";
-    VCT_LAUNCH(name, (k_apply<D, KERNEL, T, S>), dim3((unsigned)cap), dim3(kThreads), 0, s, a);
+    VCT_LAUNCH(name, (k_apply<D, KERNEL, T, S>), dim3((unsigned)cap), dim3(ApplyCfg<T>::threads), 0, s, a);
     VCT_LAUNCH_CHECK();
     return VCT_OK;
 }
