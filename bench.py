@@ -185,7 +185,8 @@ def main():
         mark()
         vct.vct_neighbors(nl, pos_s, nnz, 0, ws_nb)
         mark()
-        vct.vct_moments(nl, pos_s, vol_s, w.kernel, cmap, fwd_mask, st64, st32, flags, False, ws_mom)
+        # the forward only runs the mixed apply: the FP32 state is all it reads
+        vct.vct_moments(nl, pos_s, vol_s, w.kernel, cmap, fwd_mask, None, st32, flags, False, ws_mom)
         mark()
         vct.vct_apply_ops(nl, nf, phi_s, pos_s, vol_s, w.kernel, st32, fwd_mask, vct.VCT_MIXED, out)
         mark()
@@ -233,6 +234,7 @@ def main():
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / reps
 
+    vct.vct_moments(nl, pos_s, vol_s, w.kernel, cmap, fwd_mask, st64, st32, flags, False, ws_mom)
     t_apply_mixed = time_apply(vct.VCT_MIXED, st32)
     t_apply_fp64 = time_apply(vct.VCT_FP64, st64)
 

@@ -270,8 +270,9 @@ int vct_neighbors(vct_nlist* nl, const double* pos_sorted, int64_t col_cap, int6
 /* Per-particle moment assembly and solve, always in FP64 (Eqs. gra_1st and
  * sec_SPH2).  For every particle i it forms the first-order correction matrix
  * and the SPH(2) system, equivalently the (d+m) x (d+m) block system of the
- * Taylor moments (m = 3 in 2-D, 6 in 3-D), solves it with partial pivoting, and
- * folds the solution with the VCT coefficients of `map` at the particle into
+ * Taylor moments (m = 3 in 2-D, 6 in 3-D), eliminates the first block row
+ * (Schur complement M), inverts M by Gauss-Jordan elimination with partial
+ * pivoting, and folds the solution with the VCT coefficients of `map` at the particle into
  * the state consumed by vct_apply_ops:
  *   state[k][i], k < nL               dimensionless first-order correction
  *                                     matrix (symmetric, upper triangle) in
@@ -281,8 +282,9 @@ int vct_neighbors(vct_nlist* nl, const double* pos_sorted, int64_t col_cap, int6
  *   state[nL + n_out*(d+m) + o*d + a][i]  response of output row o to a unit
  *                                     projected gradient along axis a (the
  *                                     operator applied to a linear field)
- * state64 [stride][n] (FP64) is required; state32 (FP32 copy, same layout) may
- * be NULL.  flags [n] (may be NULL) receives VCT_FLAG_* bits; flagged particles
+ * state64 [stride][n] (FP64) and state32 (its FP32 rounding, same layout)
+ * are each optional, but one of them must be given: a caller that only runs
+ * the mixed apply can skip the FP64 copy.  flags [n] (may be NULL) receives VCT_FLAG_* bits; flagged particles
  * get NaN state rows, hence NaN outputs.  If n_flagged (host) is not NULL the
  * call is SYNC and returns VCT_W_FLAGGED when the count is non-zero.          */
 int vct_moments(const vct_nlist* nl, const double* pos_sorted, const double* vol_sorted, int kernel,

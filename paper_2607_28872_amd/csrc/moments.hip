@@ -305,21 +305,26 @@ __global__ __launch_bounds__(kMThreads, VCT_SWEEP_WAVES) void k_moment_sweeps(Sw
 
 // ------------------------------------------------------------------ kernel 2: solve + fold
 
+// In-place inverse by Gauss-Jordan elimination with partial (row) pivoting;
+// false if a pivot falls below kPivotTol times the largest entry.  One
+// division per pivot; the row interchanges become column interchanges of the
+// inverse, undone at the end.
 template <int M>
-__device__ __forceinline__ bool lu_factor(double (&A)[M][M], int (&piv)[M]) {
+__device__ __forceinline__ bool gj_invert(double (&A)[M][M]) {
     double scale = 0.0;
 #pragma unroll
     for (int r = 0; r < M; ++r)
 #pragma unroll
         for (int c = 0; c < M; ++c) scale = fmax(scale, fabs(A[r][c]));
     bool bad = !(scale > 0.0) || !isfinite(scale);
+    int piv[M];
 #pragma unroll
     for (int c = 0; c < M; ++c) {
         int p = c;
         double best = fabs(A[c][c]);
 #pragma unroll
         for (int r = c + 1; r < M; ++r) {
-            double v = fabs(A[r][c]);
+            const double v = fabs(A[r][c]);
             if (v > best) { best = v; p = r; }
         }
         piv[c] = p;
@@ -328,40 +333,33 @@ __device__ __forceinline__ bool lu_factor(double (&A)[M][M], int (&piv)[M]) {
         for (int r = c + 1; r < M; ++r) {
             if (r == p) {
 #pragma unroll
-                for (int k = 0; k < M; ++k) { double t = A[c][k]; A[c][k] = A[r][k]; A[r][k] = t; }
+                for (int k = 0; k < M; ++k) { const double t = A[c][k]; A[c][k] = A[r][k]; A[r][k] = t; }
             }
         }
         const double inv = 1.0 / A[c][c];
+        A[c][c] = 1.0;
+#pragma unroll
+        for (int k = 0; k < M; ++k) A[c][k] *= inv;
+#pragma unroll
+        for (int r = 0; r < M; ++r) {
+            if (r == c) continue;
+            const double f = A[r][c];
+            A[r][c] = 0.0;
+#pragma unroll
+            for (int k = 0; k < M; ++k) A[r][k] -= f * A[c][k];
+        }
+    }
+#pragma unroll
+    for (int c = M - 1; c >= 0; --c) {
 #pragma unroll
         for (int r = c + 1; r < M; ++r) {
-            const double f = A[r][c] * inv;
-            A[r][c] = f;
+            if (r == piv[c]) {
 #pragma unroll
-            for (int k = c + 1; k < M; ++k) A[r][k] -= f * A[c][k];
+                for (int k = 0; k < M; ++k) { const double t = A[k][c]; A[k][c] = A[k][r]; A[k][r] = t; }
+            }
         }
     }
     return !bad;
-}
-
-template <int M>
-__device__ __forceinline__ void lu_solve(const double (&A)[M][M], const int (&piv)[M], double (&b)[M]) {
-#pragma unroll
-    for (int c = 0; c < M; ++c) {
-#pragma unroll
-        for (int r = c + 1; r < M; ++r) {
-            if (r == piv[c]) { double t = b[c]; b[c] = b[r]; b[r] = t; }
-        }
-    }
-#pragma unroll
-    for (int r = 1; r < M; ++r)
-#pragma unroll
-        for (int k = 0; k < r; ++k) b[r] -= A[r][k] * b[k];
-#pragma unroll
-    for (int r = M - 1; r >= 0; --r) {
-#pragma unroll
-        for (int k = r + 1; k < M; ++k) b[r] -= A[r][k] * b[k];
-        b[r] /= A[r][r];
-    }
 }
 
 // Physical (and projected) outputs from a projected gradient pg and projected
@@ -412,8 +410,11 @@ __device__ __forceinline__ int emit_rows(uint32_t mask, const MapCoef<double>& c
     return o;
 }
 
+#ifndef VCT_SOLVE_WAVES
+#define VCT_SOLVE_WAVES 2
+#endif
 template <int D>
-__global__ __launch_bounds__(256) void k_moment_solve(int64_t n, const double* __restrict__ pos,
+__global__ __launch_bounds__(128, VCT_SOLVE_WAVES) void k_moment_solve(int64_t n, const double* __restrict__ pos,
                                                       const double* __restrict__ mom,
                                                       const uint8_t* __restrict__ mflags, double invR,
                                                       MapParams mp, uint32_t mask, int nrows,
@@ -472,8 +473,20 @@ __global__ __launch_bounds__(256) void k_moment_solve(int64_t n, const double* _
             CL[p][a] = t;
         }
     }
-    int piv[m];
-    if (!fl && !lu_factor<m>(M, piv)) fl |= VCT_FLAG_SINGULAR_M;
+    // Q^T and C L wait in LDS (one column per thread) while M is inverted and
+    // are read back per output column, which keeps them out of registers
+    __shared__ double sQC[2 * d * m][128];
+    const int tq = threadIdx.x;
+#pragma unroll
+    for (int a = 0; a < d; ++a)
+#pragma unroll
+        for (int p = 0; p < m; ++p) {
+            sQC[a * m + p][tq] = Qt[a][p];
+            sQC[d * m + p * d + a][tq] = CL[p][a];
+        }
+    asm volatile("" ::: "memory");
+    if (!fl && !gj_invert<m>(M)) fl |= VCT_FLAG_SINGULAR_M;   // M now holds M^-1
+    asm volatile("" ::: "memory");
 
     // VCT coefficients at the particle
     const double x = pos[i], y = (D == 3) ? pos[n + i] : 0.0, zh = pos[(int64_t)(D - 1) * n + i];
@@ -486,16 +499,29 @@ __global__ __launch_bounds__(256) void k_moment_solve(int64_t n, const double* _
 
 #pragma unroll
     for (int k = 0; k < nk; ++k) {
+        // z = M^-1 (C L e_k) for the first-order sums, the column of M^-1 for the others
         double z[m];
+        if (k < d) {
+            double cl[m];
 #pragma unroll
-        for (int p = 0; p < m; ++p) z[p] = (k < d) ? CL[p][k] : (p == k - d ? 1.0 : 0.0);
-        lu_solve<m>(M, piv, z);
+            for (int q = 0; q < m; ++q) cl[q] = sQC[d * m + q * d + k][tq];
+#pragma unroll
+            for (int p = 0; p < m; ++p) {
+                double t = 0.0;
+#pragma unroll
+                for (int q = 0; q < m; ++q) t += M[p][q] * cl[q];
+                z[p] = t;
+            }
+        } else {
+#pragma unroll
+            for (int p = 0; p < m; ++p) z[p] = M[p][k - d];
+        }
         double pg[d], ph[m];
 #pragma unroll
         for (int a = 0; a < d; ++a) {
             double t = 0.0;
 #pragma unroll
-            for (int p = 0; p < m; ++p) t += Qt[a][p] * z[p];
+            for (int p = 0; p < m; ++p) t += sQC[a * m + p][tq] * z[p];
             double g;
             if (k < d) g = sym_at<D>(L, a, k) + (grad1 ? 0.0 : t);
             else g = grad1 ? 0.0 : -t;
@@ -509,7 +535,7 @@ __global__ __launch_bounds__(256) void k_moment_solve(int64_t n, const double* _
         emit_rows<D>(mask, mc, pg, ph, [&](int o, double v) {
             v = fl ? nanv : v;
             const int64_t idx = (int64_t)(nL + o * nk + k) * n + i;
-            state64[idx] = v;
+            if (state64) state64[idx] = v;
             if (state32) state32[idx] = (float)v;
         });
     }
@@ -527,14 +553,14 @@ __global__ __launch_bounds__(256) void k_moment_solve(int64_t n, const double* _
         emit_rows<D>(mask, mc, pg, ph, [&](int o, double v) {
             v = fl ? nanv : v;
             const int64_t idx = (int64_t)(wbase + o * d + a) * n + i;
-            state64[idx] = v;
+            if (state64) state64[idx] = v;
             if (state32) state32[idx] = (float)v;
         });
     }
 #pragma unroll
     for (int p = 0; p < nL; ++p) {
         const double v = fl ? nanv : L[p];
-        state64[(int64_t)p * n + i] = v;
+        if (state64) state64[(int64_t)p * n + i] = v;
         if (state32) state32[(int64_t)p * n + i] = (float)v;
     }
     if (flags_out) flags_out[i] = (uint8_t)fl;
@@ -588,7 +614,7 @@ extern "C" int vct_moments(const vct_nlist* nl, const double* pos_sorted, const 
     MapParams mp;
     st = map_params_from(map, dim, mp);
     if (st) return st;
-    if (n > 0 && (!pos_sorted || !vol_sorted || !nl->col16 || !state64)) return VCT_E_ARG;
+    if (n > 0 && (!pos_sorted || !vol_sorted || !nl->col16 || (!state64 && !state32))) return VCT_E_ARG;
     if (!ws || ws_bytes < vct_moments_workspace_size(dim, n)) return VCT_E_WORKSPACE;
     hipStream_t s = as_stream(stream);
     Carver cv(ws, ws_bytes);

@@ -340,13 +340,15 @@ class Geometry:
             out[..., idx, :] = x
         return out
 
-    def moments(self, mapspec, mask=VCT_OUT_DEFAULT, fp32_copy=False, count_flagged=True):
+    def moments(self, mapspec, mask=VCT_OUT_DEFAULT, fp32_copy=False, count_flagged=True, fp64=True):
+        """Per-particle state for `mask`; fp64=False with fp32_copy=True keeps
+        only the FP32 state (enough for the mixed apply)."""
         import torch
         n, dim = self.n, self.dim
         stride = vct_state_stride(dim, mask)
         self.cmap = make_map(mapspec)
         self.mask = mask
-        self.state64 = torch.empty((stride, max(n, 1)), dtype=torch.float64, device=self.device)
+        self.state64 = torch.empty((stride, max(n, 1)), dtype=torch.float64, device=self.device) if fp64 else None
         self.state32 = torch.empty((stride, max(n, 1)), dtype=torch.float32, device=self.device) if fp32_copy else None
         self.flags = torch.empty(max(n, 1), dtype=torch.uint8, device=self.device)
         ws = _bytes(lib().vct_moments_workspace_size(dim, n), self.device)

@@ -170,6 +170,18 @@ def test_determinism_bitwise():
         assert np.array_equal(a, b)
 
 
+def test_fp32_only_state_matches_the_rounded_fp64_state():
+    """vct_moments without the FP64 state writes the same FP32 state."""
+    w = I.small("sigma3d")
+    g = _geom(w)
+    g.moments(w.mapspec, vct.VCT_OUT_DEFAULT, fp32_copy=True)
+    s64, s32 = g.state64.clone(), g.state32.clone()
+    g.moments(w.mapspec, vct.VCT_OUT_DEFAULT, fp32_copy=True, fp64=False)
+    assert g.state64 is None
+    assert torch.equal(g.state32, s32)
+    assert torch.equal(s32, s64.to(torch.float32))
+
+
 @pytest.mark.parametrize("form", ["transposed", "gather"])
 def test_adjoint_against_oracle(form):
     w = I.small("sigma3d-adj")
