@@ -60,6 +60,8 @@ def parse():
     p.add_argument("--nf", type=int, default=1)
     p.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--copy-calibration", action="store_true",
+                   help="only run a 1 GiB device-to-device copy five times (reference for HBM byte counters)")
     return p.parse_args()
 
 
@@ -68,6 +70,10 @@ def kernel_hash():
     for f in sorted(os.listdir(os.path.join(ROOT, "paper_2607_28872_amd", "csrc"))):
         h.update(open(os.path.join(ROOT, "paper_2607_28872_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
+
+
+def progress(msg):
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
 
 
 def measured_traffic(kernel_name, launches_bytes):
@@ -96,12 +102,22 @@ def main():
     import numpy as np
     import torch
 
+    if args.copy_calibration:
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": src.numel() * 8, "copy_bytes_written": dst.numel() * 8, "copies": 5}))
+        return
+
     from paper_2607_28872_amd import inputs as I
     from paper_2607_28872_amd import vct
 
     dev = "cuda:0"
     torch.cuda.set_device(0)
     w = I.config(args.config)
+    progress(f"workload {args.config}: {w.n} particles generated")
     n, dim = w.n, w.dim
     nf = args.nf
     phis = np.concatenate([w.phi] * ((nf + w.phi.shape[0] - 1) // w.phi.shape[0]))[:nf]
@@ -200,6 +216,7 @@ def main():
         mark()
         return marks
 
+    progress(f"buffers ready, {nnz} neighbour entries; warm-up")
     for _ in range(args.warmup):
         step(False)
     # one more untimed step with launch timing on, so that the events the
@@ -210,6 +227,7 @@ def main():
     vct.vct_timing_enable(False)
     vct.vct_timing_reset()
     stage_ms = {k: [] for k in stage_names}
+    progress(f"timing {args.steps} steps")
     vct.vct_timing_enable(True)
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -235,6 +253,7 @@ def main():
         return e0.elapsed_time(e1) / reps
 
     vct.vct_moments(nl, pos_s, vol_s, w.kernel, cmap, fwd_mask, st64, st32, flags, False, ws_mom)
+    progress("apply-only timing")
     t_apply_mixed = time_apply(vct.VCT_MIXED, st32)
     t_apply_fp64 = time_apply(vct.VCT_FP64, st64)
 
@@ -313,6 +332,7 @@ def main():
     }
 
     if not args.no_cpu_baseline:
+        progress("CPU oracle on a sample")
         res["cpu_baseline"] = cpu_baseline(w, nf, args.cpu_seconds)
     print(json.dumps(res), flush=True)
 
