@@ -135,9 +135,19 @@ __global__ __launch_bounds__(kAThreads, 2) void k_adjoint_weights(AdjArgs A) {
     const int W = __builtin_amdgcn_readfirstlane(w.off[w.nr]);
     const bool in_lds = W <= kAWin;
     if (in_lds) {
-        for (int t = threadIdx.x; t < W; t += kAThreads) {
-            const int64_t j = window_global<D>(w, t);
-            sd[t] = make_double4(A.pos[j], A.pos[n + j], D == 3 ? A.pos[2 * n + j] : 0.0, A.vol[j]);
+        // every load of a thread is issued before its first LDS store
+        constexpr int kRep = (kAWin + kAThreads - 1) / kAThreads;
+        double4 q[kRep];
+#pragma unroll
+        for (int k = 0; k < kRep; ++k) {
+            const int t = threadIdx.x + k * kAThreads;
+            const int64_t j = window_global<D>(w, t < W ? t : 0);
+            q[k] = make_double4(A.pos[j], A.pos[n + j], D == 3 ? A.pos[2 * n + j] : 0.0, A.vol[j]);
+        }
+#pragma unroll
+        for (int k = 0; k < kRep; ++k) {
+            const int t = threadIdx.x + k * kAThreads;
+            if (t < W) sd[t] = q[k];
         }
     }
     __syncthreads();

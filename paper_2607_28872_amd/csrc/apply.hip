@@ -109,28 +109,44 @@ template <class S> struct ApplyArgs {
     double* out;
 };
 
-// Pair geometry: FP64 offset dx = x_j - x_i, r~ = dx / R, q^2 = |r~|^2 and
-// V_j c~(q) in the arithmetic type T.
-template <int D, int KERNEL, class T>
+// The mixed form keeps positions in units of R (x / R, in FP64): the FP64
+// offset is then r~ itself and only needs rounding to FP32.  The FP64 form
+// keeps positions as they are, so its offsets are exact differences.
+template <class T> struct Scaled {
+    static constexpr bool value = std::is_same<T, float>::value;
+};
+
+// Pair geometry: FP64 offset dx = x_j - x_i (in units of R for the mixed
+// form), r~ = dx / R, q^2 = |r~|^2 and V_j c~(q) in the arithmetic type T;
+// with IQ4 also 1 / q^4 (from one reciprocal square root in FP32).
+template <int D, int KERNEL, class T, bool IQ4 = false>
 __device__ __forceinline__ void pair_geom(const double4& q, T vj, const double (&xi)[3], T invR,
-                                          double (&dx)[D], T (&r)[D], T& q2, T& vc) {
+                                          double (&dx)[D], T (&r)[D], T& q2, T& vc, T* iq4 = nullptr) {
     dx[0] = q.x - xi[0];
     dx[1] = q.y - xi[1];
     if (D == 3) dx[D - 1] = q.z - xi[2];
     q2 = T(0);
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-        r[a] = T(dx[a]) * invR;
+        r[a] = Scaled<T>::value ? T(dx[a]) : T(dx[a]) * invR;
         q2 += r[a] * r[a];
     }
-    vc = vj * kernel_shape<KERNEL>(vsqrt(q2));
+    if (IQ4 && Scaled<T>::value) {
+        const T rs = __builtin_amdgcn_rsqf(q2);
+        const T rs2 = rs * rs;
+        vc = vj * kernel_shape<KERNEL>(q2 * rs);
+        *iq4 = rs2 * rs2;
+    } else {
+        vc = vj * kernel_shape<KERNEL>(vsqrt(q2));
+        if (IQ4) *iq4 = vrcp(q2 * q2);
+    }
 }
 
 // Sums of one pair with residual psi: a~ += V c~ psi r~ and
 // s~ += V c~ psi (r~' L~ r~) / |r~|^4 r~ r~'  (L2 holds L~ with doubled
 // off-diagonal entries).
 template <int D, class T>
-__device__ __forceinline__ void pair_sums(const T (&r)[D], T q2, T vc, T psi, const T (&L2)[Dims<D>::nL],
+__device__ __forceinline__ void pair_sums(const T (&r)[D], T iq4, T vc, T psi, const T (&L2)[Dims<D>::nL],
                                           T (&acc)[Dims<D>::nk]) {
     using Dm = Dims<D>;
     T qv[Dm::m];
@@ -139,7 +155,7 @@ __device__ __forceinline__ void pair_sums(const T (&r)[D], T q2, T vc, T psi, co
     T rLr = T(0);
 #pragma unroll
     for (int p = 0; p < Dm::nL; ++p) rLr += L2[p] * qv[p];
-    const T wa = vc * psi, ws = wa * rLr * vrcp(q2 * q2);
+    const T wa = vc * psi, ws = wa * rLr * iq4;
 #pragma unroll
     for (int a = 0; a < D; ++a) acc[a] += wa * r[a];
 #pragma unroll
@@ -200,9 +216,10 @@ __device__ __forceinline__ void apply_chunk_global(const ApplyArgs<S>& A, const 
     const int64_t i = p0 + threadIdx.x / kLanes;
     if (i >= p1) return;   // whole groups leave together
     const T invR = T(A.invR);
+    const double ps = Scaled<T>::value ? A.invR : 1.0;   // position scale
     double xi[3];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) xi[a] = a < D ? A.pos[a * n + i] : 0.0;
+    for (int a = 0; a < 3; ++a) xi[a] = a < D ? A.pos[a * n + i] * ps : 0.0;
     T L2[Dims<D>::nL];
     load_L<D, T, S>(A, i, L2);
     const int64_t rb = A.row_ptr[i], re = A.row_ptr[i + 1];
@@ -211,7 +228,7 @@ __device__ __forceinline__ void apply_chunk_global(const ApplyArgs<S>& A, const 
         const double phi_i = ph[i];
         auto fetch = [&](int t, double4& q, T& v) {
             const int64_t j = window_global<D>(w, t);
-            q = make_double4(A.pos[j], A.pos[n + j], D == 3 ? A.pos[2 * n + j] : 0.0, ph[j]);
+            q = make_double4(A.pos[j] * ps, A.pos[n + j] * ps, D == 3 ? A.pos[2 * n + j] * ps : 0.0, ph[j]);
             v = T(A.vol[j]);
         };
         T a1[D], Gt[D];
@@ -230,7 +247,7 @@ __device__ __forceinline__ void apply_chunk_global(const ApplyArgs<S>& A, const 
         group_gradient<D, T>(L2, a1, Gt);
         double Gp[D];
 #pragma unroll
-        for (int a = 0; a < D; ++a) Gp[a] = (double)Gt[a] * A.invR;
+        for (int a = 0; a < D; ++a) Gp[a] = Scaled<T>::value ? (double)Gt[a] : (double)Gt[a] * A.invR;
         T acc[nk];
 #pragma unroll
         for (int c = 0; c < nk; ++c) acc[c] = T(0);
@@ -239,11 +256,12 @@ __device__ __forceinline__ void apply_chunk_global(const ApplyArgs<S>& A, const 
             T vj, r[D], q2, vc;
             double dx[D];
             fetch(A.col16[e], q, vj);
-            pair_geom<D, KERNEL, T>(q, vj, xi, invR, dx, r, q2, vc);
+            T iq4;
+            pair_geom<D, KERNEL, T, true>(q, vj, xi, invR, dx, r, q2, vc, &iq4);
             double psi = q.w - phi_i;
 #pragma unroll
             for (int a = 0; a < D; ++a) psi -= dx[a] * Gp[a];
-            pair_sums<D, T>(r, q2, vc, T(psi), L2, acc);
+            pair_sums<D, T>(r, iq4, vc, T(psi), L2, acc);
         }
 #pragma unroll
         for (int c = 0; c < nk; ++c) acc[c] = group_sum(acc[c], kLanes);
@@ -274,9 +292,10 @@ __global__ __launch_bounds__(ApplyCfg<T>::threads, ApplyCfg<T>::waves) void k_ap
     const int64_t i = p0 + pl;
     const bool valid = i < p1;
     const int64_t ii = valid ? i : p0;
+    const double ps = Scaled<T>::value ? A.invR : 1.0;   // position scale
     double xi[3];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) xi[a] = a < D ? A.pos[a * n + ii] : 0.0;
+    for (int a = 0; a < 3; ++a) xi[a] = a < D ? A.pos[a * n + ii] * ps : 0.0;
     T L2[Dm::nL];
     load_L<D, T, S>(A, ii, L2);
     const int64_t rb = valid ? A.row_ptr[ii] : 0, re = valid ? A.row_ptr[ii + 1] : 0;
@@ -322,7 +341,7 @@ __global__ __launch_bounds__(ApplyCfg<T>::threads, ApplyCfg<T>::waves) void k_ap
             for (int k = 0; k < kBatch; ++k) {
                 const int t = threadIdx.x + (k0 + k) * kThreads;
                 const int64_t j = window_global<D>(w, t < W ? t : 0);
-                q[k] = make_double4(A.pos[j], A.pos[n + j], D == 3 ? A.pos[2 * n + j] : 0.0, ph[j]);
+                q[k] = make_double4(A.pos[j] * ps, A.pos[n + j] * ps, D == 3 ? A.pos[2 * n + j] * ps : 0.0, ph[j]);
                 v[k] = T(A.vol[j]);
             }
 #pragma unroll
@@ -408,7 +427,7 @@ __global__ __launch_bounds__(ApplyCfg<T>::threads, ApplyCfg<T>::waves) void k_ap
         group_gradient<D, T>(L2, a1, Gt);
         double Gp[D];
 #pragma unroll
-        for (int a = 0; a < D; ++a) Gp[a] = (double)Gt[a] * A.invR;
+        for (int a = 0; a < D; ++a) Gp[a] = Scaled<T>::value ? (double)Gt[a] : (double)Gt[a] * A.invR;
         // pass 2: sums of the residual psi_ij = phi_ij - (x_j - x_i) . G.
         // The empty asm makes the packed offsets opaque, so the record
         // addresses are recomputed here instead of being kept live from pass 1.
@@ -420,11 +439,12 @@ __global__ __launch_bounds__(ApplyCfg<T>::threads, ApplyCfg<T>::waves) void k_ap
         auto term2 = [&](const double4& q, T vj, bool use) {
             double dx[D];
             T r[D], q2, vc;
-            pair_geom<D, KERNEL, T>(q, vj, xi, invR, dx, r, q2, vc);
+            T iq4;
+            pair_geom<D, KERNEL, T, true>(q, vj, xi, invR, dx, r, q2, vc, &iq4);
             double psi = q.w - phi_i;
 #pragma unroll
             for (int a = 0; a < D; ++a) psi -= dx[a] * Gp[a];
-            pair_sums<D, T>(r, use ? q2 : T(1), use ? vc : T(0), T(psi), L2, acc);
+            pair_sums<D, T>(r, use ? iq4 : T(0), use ? vc : T(0), T(psi), L2, acc);
         };
         qn = sd[cols(0)];
         vn = sv[cols(0)];

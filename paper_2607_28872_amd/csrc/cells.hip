@@ -289,13 +289,27 @@ __global__ __launch_bounds__(kNbThreads) void k_nb_chunk(int64_t n, const double
     if (threadIdx.x == 0) maxoff_bits = 0u;
     __syncthreads();
     if (in_lds) {
+        // every load of a thread is issued before its first LDS store
+        constexpr int kRep = (kWin + kNbThreads - 1) / kNbThreads;
+        double px[kRep], py[kRep], pz[kRep];
+#pragma unroll
+        for (int k = 0; k < kRep; ++k) {
+            const int t = threadIdx.x + k * kNbThreads;
+            const int64_t j = window_global<D>(w, t < W ? t : 0);
+            px[k] = pos[j];
+            py[k] = pos[n + j];
+            pz[k] = D == 3 ? pos[2 * n + j] : 0.0;
+        }
         float mo = 0.0f;
-        for (int t = threadIdx.x; t < W; t += kNbThreads) {
-            const int64_t j = window_global<D>(w, t);
-            const float4 q = make_float4((float)(pos[j] - o0), (float)(pos[n + j] - o1),
-                                         D == 3 ? (float)(pos[2 * n + j] - o2) : 0.0f, 0.0f);
-            win[t] = q;
-            mo = fmaxf(mo, fmaxf(fabsf(q.x), fmaxf(fabsf(q.y), fabsf(q.z))));
+#pragma unroll
+        for (int k = 0; k < kRep; ++k) {
+            const int t = threadIdx.x + k * kNbThreads;
+            if (t < W) {
+                const float4 q = make_float4((float)(px[k] - o0), (float)(py[k] - o1),
+                                             D == 3 ? (float)(pz[k] - o2) : 0.0f, 0.0f);
+                win[t] = q;
+                mo = fmaxf(mo, fmaxf(fabsf(q.x), fmaxf(fabsf(q.y), fabsf(q.z))));
+            }
         }
         atomicMax(&maxoff_bits, __float_as_uint(mo));   // non-negative floats order as their bits
     }

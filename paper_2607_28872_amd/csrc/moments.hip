@@ -164,9 +164,19 @@ __global__ __launch_bounds__(kMThreads, VCT_SWEEP_WAVES) void k_moment_sweeps(Sw
     const int W = __builtin_amdgcn_readfirstlane(w.off[w.nr]);
     const bool in_lds = W <= kMWin;
     if (in_lds) {
-        for (int t = threadIdx.x; t < W; t += kMThreads) {
-            const int64_t j = window_global<D>(w, t);
-            sd[t] = make_double4(A.pos[j], A.pos[n + j], D == 3 ? A.pos[2 * n + j] : 0.0, A.vol[j]);
+        // every load of a thread is issued before its first LDS store
+        constexpr int kRep = (kMWin + kMThreads - 1) / kMThreads;
+        double4 q[kRep];
+#pragma unroll
+        for (int k = 0; k < kRep; ++k) {
+            const int t = threadIdx.x + k * kMThreads;
+            const int64_t j = window_global<D>(w, t < W ? t : 0);
+            q[k] = make_double4(A.pos[j], A.pos[n + j], D == 3 ? A.pos[2 * n + j] : 0.0, A.vol[j]);
+        }
+#pragma unroll
+        for (int k = 0; k < kRep; ++k) {
+            const int t = threadIdx.x + k * kMThreads;
+            if (t < W) sd[t] = q[k];
         }
     }
     __syncthreads();
