@@ -220,14 +220,17 @@ __global__ __launch_bounds__(256) void k_adjoint_pack(int64_t n, const double* _
 // LDS; a row's offsets ascend, so every lane keeps a cursor into its strided
 // share of the row and consumes the entries that fall in the current
 // sub-window.
-constexpr int kASub = 480;   // records per sub-window: 480 x 160 B, two groups per CU
+// A record is 11 16-byte slots (176 B = 44 banks of 4 B, an odd multiple of
+// 16 B): the lanes reading 16 consecutive records in one LDS pass start on 16
+// different bank quadruples, where a 160-byte record would give 8.
+constexpr int kASub = 448;   // records per sub-window: 448 x 176 B, two groups per CU
 
 template <int D, int KERNEL>
 __global__ __launch_bounds__(kAThreads, 2) void k_adjoint_dphi(AdjArgs A) {
     using Dm = Dims<D>;
     constexpr int nL = Dm::nL, nk = Dm::nk, m = Dm::m;
-    constexpr int kRec = 1 + kCoef / 4;   // double4 per record: x, y, z, V, then the packed record
-    __shared__ double4 srec[kASub * kRec];
+    constexpr int kRec = 11;   // double2 per record: (x, y), (z, V), the packed record, one pad
+    __shared__ double2 srec[kASub * kRec];
     __shared__ WindowT<D> w;
     const uint32_t b = xcd_tile(blockIdx.x, gridDim.x);
     if (b >= *A.nchunks) return;   // uniform over the work-group
@@ -259,26 +262,26 @@ __global__ __launch_bounds__(kAThreads, 2) void k_adjoint_dphi(AdjArgs A) {
         if (s0 > 0) __syncthreads();   // the previous sub-window is consumed
         for (int t = s0 + (int)threadIdx.x; t < s1; t += kAThreads) {
             const int64_t j = window_global<D>(w, t);
-            double4* dst = srec + (t - s0) * kRec;
-            dst[0] = make_double4(A.pos[j], A.pos[n + j], D == 3 ? A.pos[2 * n + j] : 0.0, A.vol[j]);
-            const double4* src = reinterpret_cast<const double4*>(A.coef + j * kCoef);
+            double2* dst = srec + (t - s0) * kRec;
+            dst[0] = make_double2(A.pos[j], A.pos[n + j]);
+            dst[1] = make_double2(D == 3 ? A.pos[2 * n + j] : 0.0, A.vol[j]);
+            const double2* src = reinterpret_cast<const double2*>(A.coef + j * kCoef);
 #pragma unroll
-            for (int c = 0; c < kCoef / 4; ++c) dst[1 + c] = src[c];
+            for (int c = 0; c < kCoef / 2; ++c) dst[2 + c] = src[c];
         }
         __syncthreads();
         while (tn < s1) {
-            const double4* rec = srec + (tn - s0) * kRec;
+            const double2* rec = srec + (tn - s0) * kRec;
             e += kALanes;
             tn = e < re ? (int)A.col16[e] : INT_MAX;
-            const double4 q = rec[0];
+            const double2 qa = rec[0], qb = rec[1];
+            const double4 q = make_double4(qa.x, qa.y, qb.x, qb.y);
             double ci[kCoef];
 #pragma unroll
-            for (int c = 0; c < kCoef / 4; ++c) {
-                const double4 v = rec[1 + c];
-                ci[4 * c] = v.x;
-                ci[4 * c + 1] = v.y;
-                ci[4 * c + 2] = v.z;
-                ci[4 * c + 3] = v.w;
+            for (int c = 0; c < kCoef / 2; ++c) {
+                const double2 v = rec[2 + c];
+                ci[2 * c] = v.x;
+                ci[2 * c + 1] = v.y;
             }
             double r[D];   // r~_ki
             r[0] = (q.x - xk[0]) * A.invR;

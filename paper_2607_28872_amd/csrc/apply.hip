@@ -118,7 +118,7 @@ template <class T> struct Scaled {
 
 // Pair geometry: FP64 offset dx = x_j - x_i (in units of R for the mixed
 // form), r~ = dx / R, q^2 = |r~|^2 and V_j c~(q) in the arithmetic type T;
-// with IQ4 also 1 / q^4 (from one reciprocal square root in FP32).
+// with IQ4 also 1 / q^4, both from one reciprocal square root.
 template <int D, int KERNEL, class T, bool IQ4 = false>
 __device__ __forceinline__ void pair_geom(const double4& q, T vj, const double (&xi)[3], T invR,
                                           double (&dx)[D], T (&r)[D], T& q2, T& vc, T* iq4 = nullptr) {
@@ -131,14 +131,15 @@ __device__ __forceinline__ void pair_geom(const double4& q, T vj, const double (
         r[a] = Scaled<T>::value ? T(dx[a]) : T(dx[a]) * invR;
         q2 += r[a] * r[a];
     }
-    if (IQ4 && Scaled<T>::value) {
-        const T rs = __builtin_amdgcn_rsqf(q2);
+    if (IQ4) {
+        T rs;
+        if constexpr (Scaled<T>::value) rs = __builtin_amdgcn_rsqf(q2);
+        else rs = vrsq(q2);
         const T rs2 = rs * rs;
         vc = vj * kernel_shape<KERNEL>(q2 * rs);
         *iq4 = rs2 * rs2;
     } else {
         vc = vj * kernel_shape<KERNEL>(vsqrt(q2));
-        if (IQ4) *iq4 = vrcp(q2 * q2);
     }
 }
 

@@ -249,6 +249,12 @@ template <> __device__ __forceinline__ double vsqrt<double>(double x) {
 }
 template <> __device__ __forceinline__ float vsqrt<float>(float x) { return __builtin_amdgcn_sqrtf(x); }
 
+// 1/sqrt(x) for x > 0, the same refined estimate as vsqrt uses
+__device__ __forceinline__ double vrsq(double x) {
+    const double y = __builtin_amdgcn_rsq(x);
+    return y * fma(-0.5 * x, y * y, 1.5);
+}
+
 template <class T> __device__ __forceinline__ T vrcp(T x);
 template <> __device__ __forceinline__ double vrcp<double>(double x) {
     double y = __builtin_amdgcn_rcp(x);

@@ -280,7 +280,9 @@ __global__ __launch_bounds__(kMThreads, VCT_SWEEP_WAVES) void k_moment_sweeps(Sw
         double rLr = 0.0;
 #pragma unroll
         for (int p = 0; p < Dm::nL; ++p) rLr += L2[p] * qv[p];
-        const double wgt = live ? q.w * kernel_shape<KERNEL>(vsqrt(q2)) * rLr * vrcp(q2 * q2) : 0.0;
+        // q = q2 / sqrt(q2) and 1/q^4 = (1/sqrt(q2))^4 from one refined reciprocal square root
+        const double y = vrsq(q2), y2 = y * y;
+        const double wgt = live ? q.w * kernel_shape<KERNEL>(q2 * y) * rLr * (y2 * y2) : 0.0;
 #pragma unroll
         for (int t = 0; t < Dm::n3; ++t) Cm[t] += wgt * cub[t];
 #pragma unroll
