@@ -243,23 +243,28 @@ __device__ __forceinline__ bool within_exact(double dx, double dy, double dz, do
     return d2 < R2;
 }
 
-constexpr int kNbLanes = 4;                    // lanes per particle
-constexpr int kNbThreads = kChunk * kNbLanes;  // one chunk per work-group
-constexpr int kNbWindow = 2048;                // LDS window capacity (records)
-
+constexpr int kNbWaves = 4;                    // waves per work-group
+constexpr int kNbThreads = kNbWaves * kWave;   // one chunk per work-group, lane = particle
+constexpr int kNbSeg = 1536;                   // window records per LDS segment (24 KB)
+constexpr int kNbWords = kNbSeg / 32;          // 32-candidate words per segment
 constexpr int kStage = 128;                    // staged row entries per particle
-constexpr int kNbWindowStage = 1520;           // window capacity beside the staged rows (4 groups / CU)
+constexpr int kRowPad = kStage + 2;            // LDS row stride of the staged rows (bank spread)
 
-// One chunk per work-group, kNbLanes lanes per particle.  The window positions
-// are staged in LDS as FP32 offsets from the chunk's first particle; a
-// candidate whose FP32 squared distance is inside or outside R^2 by more than
-// a bound on its rounding error is decided by it, and only the few near the
-// support edge are re-tested with the exact FP64 predicate on the stored
-// positions.  MODE 0 writes the counts; MODE 1 writes the columns (ascending)
-// at row_ptr as sorted indices and/or 16-bit window offsets; MODE 2 writes the
-// counts and the first kStage window offsets of every row into a staging
-// buffer (row i at i * kStage), flagging rows that do not fit.  The staged
-// rows are built in LDS and leave as one contiguous block per chunk.
+// One chunk per work-group; every wave holds the whole chunk, lane = particle,
+// and takes a quarter of the window's candidates.  The window is staged in
+// LDS segment by segment as FP32 offsets from the chunk's first particle; all
+// lanes of a wave test the same candidate (one broadcast LDS read), so a test
+// costs a few VALU instructions.  A candidate whose FP32 squared distance is
+// inside or outside R^2 by more than a bound on its rounding error is decided
+// by it; the few near the support edge are re-tested with the exact FP64
+// predicate on the stored positions.  Hits are collected as one bit per
+// candidate (32-candidate words in LDS, [word][particle]); a per-particle
+// prefix over the waves' hit counts then places every wave's hits, in
+// ascending window order, in the particle's row.
+// MODE 0 writes the counts; MODE 1 writes the columns at row_ptr (sorted
+// indices and/or 16-bit window offsets); MODE 2 writes the counts and stages
+// the first kStage window offsets of every row at i * kStage, flagging rows
+// that do not fit (overflow[2]).  overflow[0] flags windows beyond 65535.
 template <int D, int MODE>
 __global__ __launch_bounds__(kNbThreads) void k_nb_chunk(int64_t n, const double* __restrict__ pos, Grid g,
                                                          double R2, const int64_t* __restrict__ cs,
@@ -271,135 +276,153 @@ __global__ __launch_bounds__(kNbThreads) void k_nb_chunk(int64_t n, const double
                                                          int32_t* __restrict__ col, uint16_t* __restrict__ col16,
                                                          int32_t* __restrict__ overflow) {
     constexpr bool FILL = MODE == 1, STAGE = MODE == 2;
-    constexpr int kWin = STAGE ? kNbWindowStage : kNbWindow;
-    __shared__ float4 win[kWin];
-    __shared__ uint4 srow4[STAGE ? kChunk * kStage / 8 : 1];
-    uint16_t* srow = reinterpret_cast<uint16_t*>(srow4);
-    __shared__ unsigned int maxoff_bits;
+    static_assert(kChunk == kWave, "lane = particle");
+    static_assert(kChunk * kRowPad * 2 <= kNbSeg * 16, "staged rows must fit in the window buffer");
+    __shared__ float4 win[kNbSeg];
+    __shared__ uint32_t bm[kNbWords][kChunk];
+    __shared__ int32_t wcnt[kNbWaves][kChunk];
+    __shared__ float wmax[kNbWaves];
+    __shared__ WindowT<D> w;
     const uint32_t b = xcd_tile(blockIdx.x, gridDim.x);
-    if (b >= *nchunks) return;
+    if (b >= *nchunks) return;   // uniform over the work-group
     const int64_t p0 = cstart[b], p1 = cstart[b + 1];
-    const int4 info = cinfo[b];
-    __shared__ WindowT<D> w;   // one copy per work-group: runtime-indexed, so kept in LDS
-    if (threadIdx.x == 0) chunk_window<D>(g, cs, info, w);
+    const int np = (int)(p1 - p0);
+    const int wv = threadIdx.x / kWave, pl = threadIdx.x % kWave;
+    if (wv == 0) chunk_window_wave<D>(g, cs, cinfo[b], w);
+    const int64_t i = p0 + pl;
+    const bool valid = pl < np;
+    const int64_t ii = valid ? i : p0;
+    const double o0 = pos[p0], o1 = pos[n + p0], o2 = (D == 3) ? pos[2 * n + p0] : 0.0;
+    const double xi0 = pos[ii], xi1 = pos[n + ii], xi2 = (D == 3) ? pos[2 * n + ii] : 0.0;
+    // offsets from the chunk origin in FP32 (the same rounding as the records)
+    const float f0 = (float)(xi0 - o0), f1 = (float)(xi1 - o1), f2 = (float)(xi2 - o2);
+    const float fmax_own = fmaxf(fabsf(f0), fmaxf(fabsf(f1), fabsf(f2)));
+    const double R = sqrt(R2);
+    const int64_t rlo = FILL ? row_ptr[ii] : 0, rlen = FILL ? row_ptr[ii + 1] - rlo : 0;
     __syncthreads();
     const int W = w.off[w.nr];
-    const bool in_lds = W <= kWin;
-    const double o0 = pos[p0], o1 = pos[n + p0], o2 = (D == 3) ? pos[2 * n + p0] : 0.0;
-    if (threadIdx.x == 0) maxoff_bits = 0u;
-    __syncthreads();
-    if (in_lds) {
-        // every load of a thread is issued before its first LDS store
-        constexpr int kRep = (kWin + kNbThreads - 1) / kNbThreads;
-        double px[kRep], py[kRep], pz[kRep];
-#pragma unroll
-        for (int k = 0; k < kRep; ++k) {
-            const int t = threadIdx.x + k * kNbThreads;
-            const int64_t j = window_global<D>(w, t < W ? t : 0);
-            px[k] = pos[j];
-            py[k] = pos[n + j];
-            pz[k] = D == 3 ? pos[2 * n + j] : 0.0;
-        }
-        float mo = 0.0f;
-#pragma unroll
-        for (int k = 0; k < kRep; ++k) {
-            const int t = threadIdx.x + k * kNbThreads;
-            if (t < W) {
-                const float4 q = make_float4((float)(px[k] - o0), (float)(py[k] - o1),
-                                             D == 3 ? (float)(pz[k] - o2) : 0.0f, 0.0f);
-                win[t] = q;
-                mo = fmaxf(mo, fmaxf(fabsf(q.x), fmaxf(fabsf(q.y), fabsf(q.z))));
-            }
-        }
-        atomicMax(&maxoff_bits, __float_as_uint(mo));   // non-negative floats order as their bits
-    }
     if ((FILL || STAGE) && threadIdx.x == 0 && W > 65535) atomicOr(overflow, 1);
-    __syncthreads();
-    const int lane = threadIdx.x % kNbLanes;
-    const int64_t i = p0 + threadIdx.x / kNbLanes;
-    const int np = (int)(p1 - p0);
-    if (!STAGE && i >= p1) return;   // whole 4-lane groups leave together
-    if (i < p1) {
-        const int gshift = (threadIdx.x % kWave) / kNbLanes * kNbLanes;
-        const uint64_t gmask = 0xFull << gshift;
-        const uint64_t below = (1ull << (threadIdx.x % kWave)) - 1ull;
-        const double xi0 = pos[i], xi1 = pos[n + i], xi2 = (D == 3) ? pos[2 * n + i] : 0.0;
-        // LDS path: offsets from the chunk origin; global path: offsets from the particle
-        const float f0 = in_lds ? (float)(xi0 - o0) : 0.0f, f1 = in_lds ? (float)(xi1 - o1) : 0.0f,
-                    f2 = in_lds ? (float)(xi2 - o2) : 0.0f;
-        // Absolute bound on the FP32 error of d2: the two rounded offsets of each
-        // component (magnitude at most the window's largest offset), the rounding
-        // of R^2, and of the FP32 products and sums.
-        const double maxoff = in_lds ? (double)__uint_as_float(maxoff_bits) : 0.0;
-        const double R = sqrt(R2);
+    // the particle's own window offset (it is never its own neighbour)
+    int self_t = -1;
+    for (int r = 0; r < w.nr; ++r) {
+        const int64_t d = i - w.gstart[r];
+        if (d >= 0 && d < w.off[r + 1] - w.off[r]) self_t = w.off[r] + (int)d;
+    }
+    const bool single = W <= kNbSeg;   // staged rows are built in LDS only then
+    uint16_t* srow = reinterpret_cast<uint16_t*>(win);
+    int rowpos = 0;                     // entries of the row found so far
+    for (int s0 = 0; s0 < W; s0 += kNbSeg) {
+        const int sW = W - s0 < kNbSeg ? W - s0 : kNbSeg;
+        if (s0 > 0) __syncthreads();   // the previous segment is consumed
+        // stage the segment: every load of a thread before its first LDS store
+        {
+            constexpr int kRep = kNbSeg / kNbThreads;
+            double px[kRep], py[kRep], pz[kRep];
+#pragma unroll
+            for (int k = 0; k < kRep; ++k) {
+                const int t = threadIdx.x + k * kNbThreads;
+                const int64_t j = window_global<D>(w, s0 + (t < sW ? t : 0));
+                px[k] = pos[j];
+                py[k] = pos[n + j];
+                pz[k] = D == 3 ? pos[2 * n + j] : 0.0;
+            }
+            float mo = 0.0f;
+#pragma unroll
+            for (int k = 0; k < kRep; ++k) {
+                const int t = threadIdx.x + k * kNbThreads;
+                if (t < sW) {
+                    const float4 q = make_float4((float)(px[k] - o0), (float)(py[k] - o1),
+                                                 D == 3 ? (float)(pz[k] - o2) : 0.0f, 0.0f);
+                    win[t] = q;
+                    mo = fmaxf(mo, fmaxf(fabsf(q.x), fmaxf(fabsf(q.y), fabsf(q.z))));
+                }
+            }
+#pragma unroll
+            for (int m = kWave / 2; m >= 1; m >>= 1) mo = fmaxf(mo, __shfl_xor(mo, m, kWave));
+            if (pl == 0) wmax[wv] = mo;
+        }
+        __syncthreads();
+        // Absolute bound on the FP32 error of d2: the rounded offsets of each
+        // component (magnitude at most the largest staged or own offset), the
+        // rounding of R^2, and of the FP32 products and sums.
+        const float mseg = fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3]));
+        const double maxoff = (double)fmaxf(mseg, fmax_own);
         const double margin = 4.0 * (2.0 * R) * (maxoff * 0x1p-23) + R2 * 0x1p-19;
         const float in_lim = (float)(R2 - margin), out_lim = (float)(R2 + margin);
-        const int64_t nz = grid_nz<D>(g);
-        const int64_t cz = cell_coord(D == 3 ? xi2 : xi1, g.lo[D - 1], g.inv_cs[D - 1], nz);
-        const int64_t zl = cz > 0 ? cz - 1 : 0, zh = cz + 1 < nz ? cz + 1 : nz - 1;
-        int self_t = -1;
-        int64_t written = 0;
-        const int64_t out0 = FILL ? row_ptr[i] : STAGE ? (i - p0) * kStage : 0;
-        const int64_t out1 = FILL ? row_ptr[i + 1] : STAGE ? out0 + kStage : 0;
-        // window ranges are the chunk's columns in order; the particle's candidate
-        // cells are the same columns restricted to its z cell +- 1
-        int64_t cx, cy = 0;
-        if (D == 3) { cx = info.x / g.nc[1]; cy = info.x % g.nc[1]; } else cx = info.x;
-        int r = 0;
-        for (int dx = -1; dx <= 1; ++dx) {
-            const int64_t x = cx + dx;
-            if (x < 0 || x >= g.nc[0]) continue;
-            for (int dy = (D == 3 ? -1 : 0); dy <= (D == 3 ? 1 : 0); ++dy) {
-                int64_t colid;
-                if (D == 3) {
-                    const int64_t y = cy + dy;
-                    if (y < 0 || y >= g.nc[1]) continue;
-                    colid = x * g.nc[1] + y;
-                } else {
-                    colid = x;
-                }
-                const int64_t ga = cs[col_key<D>(g, colid, zl)], gb = cs[col_key<D>(g, colid, zh) + 1];
-                const int64_t base = (int64_t)w.off[r] - w.gstart[r];   // window offset = sorted index + base
-                if (dx == 0 && dy == 0) self_t = (int)(i + base);
-                const int ta = (int)(ga + base), tb = (int)(gb + base);
-                for (int t0 = ta; t0 < tb; t0 += kNbLanes) {
-                    const int t = t0 + lane;
-                    bool hit = false;
-                    if (t < tb && t != self_t) {
-                        const int64_t j = t - base;
-                        float4 q;
-                        if (in_lds) q = win[t];
-                        else q = make_float4((float)(pos[j] - xi0), (float)(pos[n + j] - xi1),
-                                             D == 3 ? (float)(pos[2 * n + j] - xi2) : 0.0f, 0.0f);
-                        const float ex = q.x - f0, ey = q.y - f1, ez = q.z - f2;
-                        const float d2f = ex * ex + ey * ey + ez * ez;
-                        if (d2f < in_lim) hit = true;
-                        else if (d2f <= out_lim)
-                            hit = within_exact(pos[j] - xi0, pos[n + j] - xi1, D == 3 ? pos[2 * n + j] - xi2 : 0.0, R2);
+        const int nw = (sW + 31) / 32;
+        const int k0 = wv * nw / kNbWaves, k1 = (wv + 1) * nw / kNbWaves;
+        int cnt = 0;
+        for (int k = k0; k < k1; ++k) {
+            uint32_t bits = 0u, amb = 0u;
+            const float4* wp = win + 32 * k;
+#pragma unroll
+            for (int u = 0; u < 32; ++u) {
+                const float4 q = wp[u];   // the same record for every lane
+                const float ex = q.x - f0, ey = q.y - f1, ez = q.z - f2;
+                const float d2f = ex * ex + ey * ey + ez * ez;
+                bits |= d2f < in_lim ? (1u << u) : 0u;
+                amb |= (d2f >= in_lim && d2f <= out_lim) ? (1u << u) : 0u;
+            }
+            // drop the tail beyond the segment, the particle itself, idle lanes
+            const int tb = s0 + 32 * k;
+            uint32_t keep = (sW - 32 * k) >= 32 ? 0xffffffffu : ((1u << (sW - 32 * k)) - 1u);
+            if (self_t >= tb && self_t < tb + 32) keep &= ~(1u << (self_t - tb));
+            if (!valid) keep = 0u;
+            bits &= keep;
+            amb &= keep;
+            while (amb) {   // near the support edge: the exact FP64 predicate
+                const int u = __builtin_ctz(amb);
+                amb &= amb - 1u;
+                const int64_t j = window_global<D>(w, tb + u);
+                if (within_exact(pos[j] - xi0, pos[n + j] - xi1, D == 3 ? pos[2 * n + j] - xi2 : 0.0, R2))
+                    bits |= 1u << u;
+            }
+            bm[k][pl] = bits;
+            cnt += __popc(bits);
+        }
+        wcnt[wv][pl] = cnt;
+        __syncthreads();
+        // place this wave's hits after those of the earlier waves
+        int pos0 = rowpos, total = 0;
+#pragma unroll
+        for (int v = 0; v < kNbWaves; ++v) {
+            const int c = wcnt[v][pl];
+            if (v < wv) pos0 += c;
+            total += c;
+        }
+        if (MODE != 0 && valid) {
+            int at = pos0;
+            for (int k = k0; k < k1; ++k) {
+                uint32_t bits = bm[k][pl];
+                while (bits) {
+                    const int t = s0 + 32 * k + __builtin_ctz(bits);
+                    bits &= bits - 1u;
+                    if (STAGE && at < kStage) {
+                        if (single) srow[pl * kRowPad + at] = (uint16_t)t;
+                        else col16[i * kStage + at] = (uint16_t)t;
                     }
-                    const uint64_t m = (uint64_t)__ballot(hit) & gmask;
-                    if ((FILL || STAGE) && hit) {
-                        const int64_t at = out0 + written + __popcll(m & below);
-                        if (at < out1) {
-                            if (FILL && col) col[at] = (int32_t)(t - base);
-                            if (FILL && col16) col16[at] = (uint16_t)t;
-                            if (STAGE) srow[at] = (uint16_t)t;
-                        }
+                    if (FILL && at < rlen) {
+                        if (col) col[rlo + at] = (int32_t)window_global<D>(w, t);
+                        if (col16) col16[rlo + at] = (uint16_t)t;
                     }
-                    written += __popcll(m);
+                    ++at;
                 }
-                ++r;
             }
         }
-        if (!FILL && lane == 0) {
-            counts[i] = (int32_t)written;
-            if (STAGE && written > kStage) atomicOr(overflow + 2, 1);
-        }
+        rowpos += total;
     }
-    if (STAGE) {   // the chunk's staged rows, contiguous at p0 * kStage
+    if (!FILL && wv == 0 && valid) {
+        counts[i] = rowpos;
+        if (STAGE && rowpos > kStage) atomicOr(overflow + 2, 1);
+    }
+    if (STAGE && single) {   // the chunk's staged rows, contiguous at p0 * kStage
         __syncthreads();
-        uint4* dst = reinterpret_cast<uint4*>(col16 + p0 * kStage);
-        for (int k = threadIdx.x; k < np * (kStage / 8); k += kNbThreads) dst[k] = srow4[k];
+        const uint32_t* src = reinterpret_cast<const uint32_t*>(srow);
+        uint32_t* dst = reinterpret_cast<uint32_t*>(col16 + p0 * kStage);
+        for (int k = threadIdx.x; k < np * (kStage / 2); k += kNbThreads) {
+            const int r = k / (kStage / 2), c = k % (kStage / 2);
+            dst[k] = src[r * (kRowPad / 2) + c];
+        }
     }
 }
 
