@@ -19,6 +19,46 @@ void set_last_error(hipError_t e) {
     g_last_error[sizeof(g_last_error) - 1] = '\0';
 }
 
+// Index of the factor (kind, frequency) of one axis in the separable table,
+// inserted when new; -1 if the table is full.
+static int sep_factor(int kind, double f, int32_t* fkind, int32_t* fslot, double* freq, int32_t& nf,
+                      int32_t& nq) {
+    int q = 0;
+    if (kind == VCT_BASIS_COS || kind == VCT_BASIS_SIN) {
+        q = -1;
+        for (int j = 0; j < nq; ++j)
+            if (freq[j] == f) q = j;
+        if (q < 0) {
+            if (nq == kMapFq) return -1;
+            q = nq;
+            freq[nq++] = f;
+        }
+    }
+    for (int a = 0; a < nf; ++a)
+        if (fkind[a] == kind && fslot[a] == q) return a;
+    if (nf == kMapFn) return -1;
+    fkind[nf] = kind;
+    fslot[nf] = q;
+    return nf++;
+}
+
+// The separable table of the bottom terms (sep = 0 when it does not fit).
+static void build_separable(MapParams& p) {
+    p.sep = 0;
+    p.nfx = p.nfy = p.nqx = p.nqy = 0;
+    for (int t = 0; t < p.nterms; ++t) {
+        const int a = sep_factor(p.bx[t], p.fx[t], p.fx_kind, p.fx_q, p.qx, p.nfx, p.nqx);
+        const int b = sep_factor(p.by[t], p.fy[t], p.fy_kind, p.fy_q, p.qy, p.nfy, p.nqy);
+        if (a < 0 || b < 0) {
+            memset(p.cm, 0, sizeof(p.cm));
+            p.nfx = p.nfy = p.nqx = p.nqy = 0;
+            return;
+        }
+        p.cm[a][b] += p.coef[t];
+    }
+    p.sep = 1;
+}
+
 int map_params_from(const vct_map* m, int dim, MapParams& p) {
     memset(&p, 0, sizeof(p));
     if (!m) return VCT_E_ARG;
@@ -50,6 +90,7 @@ int map_params_from(const vct_map* m, int dim, MapParams& p) {
         p.fx[t] = tr.fx;
         p.fy[t] = tr.fy;
     }
+    build_separable(p);
     return VCT_OK;
 }
 

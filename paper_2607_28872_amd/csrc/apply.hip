@@ -372,11 +372,14 @@ __global__ __launch_bounds__(ApplyCfg<T>::threads, ApplyCfg<T>::waves) void k_ap
     int nslot = 0;
     {
         const uint32_t first = re > rb ? (uint32_t)col_at(rb) : 0u;
+        const int len = (int)(re - rb);   // 32-bit row-local indices: one LDS base, immediate offsets
+        const uint16_t* srow = scol + (col_lds ? (int)(rb - cb8) : 0) + lane;
 #pragma unroll
         for (int s = 0; s < kS; ++s) {
-            const int64_t e = rb + lane + (int64_t)kLanes * s;
-            const uint32_t c = e < re ? (uint32_t)col_at(e) : first;
-            nslot += e < re ? 1 : 0;
+            const int idx = lane + kLanes * s;
+            const bool in = idx < len;
+            const uint32_t c = in ? (col_lds ? (uint32_t)srow[kLanes * s] : (uint32_t)A.col16[rb + idx]) : first;
+            nslot += in ? 1 : 0;
             if (s % 2 == 0) cpk[s / 2] = c;
             else cpk[s / 2] |= c << 16;
         }

@@ -13,6 +13,9 @@
 
 namespace vct {
 
+constexpr int kMapFn = 6;   // distinct factors per axis in the separable table
+constexpr int kMapFq = 4;   // distinct frequencies per axis in the separable table
+
 struct MapParams {
     int32_t kind;
     int32_t nterms;
@@ -22,6 +25,16 @@ struct MapParams {
     double coef[VCT_MAX_TERMS];
     int32_t bx[VCT_MAX_TERMS], by[VCT_MAX_TERMS];
     double fx[VCT_MAX_TERMS], fy[VCT_MAX_TERMS];
+    // The same bottom as h = sum_ab cm[a][b] X_a(x) Y_b(y) over the distinct
+    // factors of each axis (kind and frequency slot), filled by the host when
+    // the terms have at most kMapFn factors and kMapFq frequencies per axis
+    // (sep = 1): each frequency's sine and cosine are then evaluated once per
+    // particle instead of once per term.
+    int32_t sep;
+    int32_t nfx, nfy, nqx, nqy;
+    int32_t fx_kind[kMapFn], fx_q[kMapFn], fy_kind[kMapFn], fy_q[kMapFn];
+    double qx[kMapFq], qy[kMapFq];
+    double cm[kMapFn][kMapFn];
 };
 
 int map_params_from(const vct_map* m, int dim, MapParams& p);  // host, returns status
@@ -51,9 +64,88 @@ __device__ __forceinline__ void term_derivs(const MapParams& mp, int t, double x
     o[5] = bx[0] * by[2];
 }
 
+// F(s), F'(s), F''(s) of factor a of the separable table along one axis;
+// kind and slot are uniform, so every choice is a select
+__device__ __forceinline__ void sep_factor_values(int a, int nf, int kind, int q, const double (&freq)[kMapFq],
+                                                  const double (&sn)[kMapFq], const double (&cs)[kMapFq],
+                                                  double s, double& F0, double& F1, double& F2) {
+    double vs = sn[0], vc = cs[0], f = freq[0];
+#pragma unroll
+    for (int j = 1; j < kMapFq; ++j) {
+        vs = q == j ? sn[j] : vs;
+        vc = q == j ? cs[j] : vc;
+        f = q == j ? freq[j] : f;
+    }
+    const double w = 2.0 * M_PI * f;
+    const bool on = a < nf;
+    const bool c = kind == VCT_BASIS_COS, sk = kind == VCT_BASIS_SIN;
+    const double t0 = c ? vc : vs, t1 = c ? -w * vs : w * vc;
+    F0 = !on ? 0.0 : kind == VCT_BASIS_ONE ? 1.0 : kind == VCT_BASIS_LIN ? s : (c || sk) ? t0 : 0.0;
+    F1 = !on ? 0.0 : kind == VCT_BASIS_LIN ? 1.0 : (c || sk) ? t1 : 0.0;
+    F2 = !on ? 0.0 : (c || sk) ? -w * w * t0 : 0.0;
+}
+
+// Every factor of the separable table at (x, y): X*[a] = X_a, X_a', X_a''
+// and the same for Y (zero y-derivatives in 2-D).
+struct SepFactors {
+    double X0[kMapFn], X1[kMapFn], X2[kMapFn], Y0[kMapFn], Y1[kMapFn], Y2[kMapFn];
+};
+__device__ __forceinline__ void sep_table(const MapParams& mp, double x, double y, SepFactors& F) {
+    double sx[kMapFq], cx[kMapFq], sy[kMapFq], cy[kMapFq];
+#pragma unroll
+    for (int q = 0; q < kMapFq; ++q) {
+        sx[q] = sy[q] = 0.0;
+        cx[q] = cy[q] = 1.0;
+        double sv, cv;
+        if (q < mp.nqx) {
+            sincospi(2.0 * mp.qx[q] * x, &sv, &cv);
+            sx[q] = sv;
+            cx[q] = cv;
+        }
+        if (q < mp.nqy) {
+            sincospi(2.0 * mp.qy[q] * y, &sv, &cv);
+            sy[q] = sv;
+            cy[q] = cv;
+        }
+    }
+    double qx[kMapFq], qy[kMapFq];
+#pragma unroll
+    for (int q = 0; q < kMapFq; ++q) {
+        qx[q] = mp.qx[q];
+        qy[q] = mp.qy[q];
+    }
+#pragma unroll
+    for (int a = 0; a < kMapFn; ++a) {
+        sep_factor_values(a, mp.nfx, mp.fx_kind[a], mp.fx_q[a], qx, sx, cx, x, F.X0[a], F.X1[a], F.X2[a]);
+        sep_factor_values(a, mp.nfy, mp.fy_kind[a], mp.fy_q[a], qy, sy, cy, y, F.Y0[a], F.Y1[a], F.Y2[a]);
+        if (mp.dim == 2) F.Y1[a] = F.Y2[a] = 0.0;
+    }
+}
+
 // h, h_x, h_y, h_xx, h_xy, h_yy at (x, y)
 __device__ __forceinline__ void bottom6(const MapParams& mp, double x, double y, double h[6]) {
     for (int k = 0; k < 6; ++k) h[k] = 0.0;
+    if (mp.sep) {
+        SepFactors F;
+        sep_table(mp, x, y, F);
+#pragma unroll
+        for (int a = 0; a < kMapFn; ++a) {
+            double u0 = 0.0, u1 = 0.0, u2 = 0.0;   // sum_b cm[a][b] (Y_b, Y_b', Y_b'')
+#pragma unroll
+            for (int b = 0; b < kMapFn; ++b) {
+                u0 += mp.cm[a][b] * F.Y0[b];
+                u1 += mp.cm[a][b] * F.Y1[b];
+                u2 += mp.cm[a][b] * F.Y2[b];
+            }
+            h[0] += F.X0[a] * u0;
+            h[1] += F.X1[a] * u0;
+            h[2] += F.X0[a] * u1;
+            h[3] += F.X2[a] * u0;
+            h[4] += F.X1[a] * u1;
+            h[5] += F.X0[a] * u2;
+        }
+        return;
+    }
     for (int t = 0; t < mp.nterms; ++t) {
         double o[6];
         term_derivs(mp, t, x, y, o);

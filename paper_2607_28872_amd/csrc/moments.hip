@@ -150,11 +150,13 @@ __global__ __launch_bounds__(kMThreads, VCT_SWEEP_WAVES) void k_moment_sweeps(Sw
     int nslot = 0;
     {
         const uint32_t first = re > rb ? (uint32_t)A.col16[rb] : 0u;
+        const int len = (int)(re - rb);        // 32-bit row-local indices: one base address,
+        const uint16_t* crow = A.col16 + rb + lane;   // immediate offsets per slot
 #pragma unroll
         for (int s = 0; s < kMSlots; ++s) {
-            const int64_t e = rb + lane + (int64_t)kMLanes * s;
-            const uint32_t c = e < re ? (uint32_t)A.col16[e] : first;
-            nslot += e < re ? 1 : 0;
+            const bool in = lane + kMLanes * s < len;
+            const uint32_t c = in ? (uint32_t)crow[kMLanes * s] : first;
+            nslot += in ? 1 : 0;
             if (s % 2 == 0) cpk[s / 2] = c;
             else cpk[s / 2] |= c << 16;
         }
@@ -242,7 +244,6 @@ __global__ __launch_bounds__(kMThreads, VCT_SWEEP_WAVES) void k_moment_sweeps(Sw
         double r[D], q2, qv[Dm::m], cub[Dm::n3];
         geom(q, r, q2);
         if (q2 == 0.0) fl |= VCT_FLAG_DUPLICATE;
-        if (!isfinite(q2) || !isfinite(q.w)) fl |= VCT_FLAG_NONFINITE;
         monos(r, qv, cub);
         const double wgt = q.w * kernel_shape<KERNEL>(vsqrt(q2));
 #pragma unroll
@@ -254,6 +255,16 @@ __global__ __launch_bounds__(kMThreads, VCT_SWEEP_WAVES) void k_moment_sweeps(Sw
     for (int p = 0; p < Dm::nL; ++p) Am[p] = group_sum(Am[p], kMLanes);
 #pragma unroll
     for (int t = 0; t < Dm::n3; ++t) B[t] = group_sum(B[t], kMLanes);
+    // a non-finite neighbour position or volume makes some sum non-finite
+    // (every weight is positive), which is cheaper to test once than per pair
+    {
+        bool sf = true;
+#pragma unroll
+        for (int p = 0; p < Dm::nL; ++p) sf = sf && isfinite(Am[p]);
+#pragma unroll
+        for (int t = 0; t < Dm::n3; ++t) sf = sf && isfinite(B[t]);
+        if (!sf) fl |= VCT_FLAG_NONFINITE;
+    }
     for (int m_ = kMLanes >> 1; m_ >= 1; m_ >>= 1) fl |= __shfl_xor(fl, m_, kWave);
 
     double L[Dm::nL];
