@@ -301,6 +301,23 @@ def main():
     roof_apply = kernel_roofline("k_apply (mixed)")
     roof_apply["apply_only_ms"] = round(t_apply_mixed, 4)
 
+    # measured device-copy bandwidth (1 GiB read + 1 GiB written), the
+    # attainable HBM figure beside the vendor peak
+    src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0 = ev()
+    for _ in range(5):
+        dst.copy_(src)
+    e1 = ev()
+    torch.cuda.synchronize()
+    copy_gbs = 2.0 * src.numel() * 8 * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    for r in (roofline, roof_apply):
+        if r.get("bound") == "hbm":
+            r["frac_of_copy"] = round(r["achieved"] / copy_gbs, 4)
+
     value = n * nf / t_step
     res = {
         "metric": "particle-operator evals/s (grad+lap+cross), mixed vs FP64 GPU; HBM GB/s",
@@ -328,38 +345,84 @@ def main():
                        "fp64_alg_GBs": round(b_fp64 / (t_apply_fp64 * 1e-3) / 1e9, 1)},
         "roofline": roofline,
         "roofline_apply": roof_apply,
+        "copy_GBs": round(copy_gbs, 1),
         "kernels": kernels,
     }
 
     if not args.no_cpu_baseline:
         progress("CPU oracle on a sample")
-        res["cpu_baseline"] = cpu_baseline(w, nf, args.cpu_seconds)
+        cb, rows, rec = cpu_baseline(w, phis, ms, args.cpu_seconds)
+        res["cpu_baseline"] = cb
+        # per-operator errors of both GPU paths against the oracle at the sampled particles
+        inv = np.empty(n, dtype=np.int64)
+        inv[perm.cpu().numpy().astype(np.int64)] = np.arange(n)
+        idx = torch.as_tensor(inv[rows], device=dev)
+        vct.vct_moments(nl, pos_s, vol_s, w.kernel, cmap, fwd_mask, st64, st32, flags, False, ws_mom)
+        errs = {"sample": int(len(rows)), "bars": {"grad": 1e-5, "lap_cross": 1e-4, "fp64": 1e-12}}
+        for prec, state, nm in ((vct.VCT_FP64, st64, "fp64"), (vct.VCT_MIXED, st32, "mixed")):
+            vct.vct_apply_ops(nl, nf, phi_s, pos_s, vol_s, w.kernel, state, fwd_mask, prec, out)
+            errs[nm] = operator_errors(out[:, idx, :].cpu().numpy(), rec, dim)
+        res["error_vs_oracle"] = errs
     print(json.dumps(res), flush=True)
 
 
-def cpu_baseline(w, nf, target_s):
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(w, phis, mapspec, target_s):
     """The CPU oracle (neighbour search + SPH(2) operators, FP64, OpenMP) timed
-    on a bounded sample of particles of the same set; reported in evals/s."""
+    on a bounded sample of particles of the same set, on every host thread and
+    on one; reported in evals/s.  Also returns the sampled rows and the
+    oracle's records there, for the error report."""
     import numpy as np
     import oracle
 
     oracle.lib()
+    nf = phis.shape[0]
     rng = np.random.default_rng(123)
-    phis = np.concatenate([w.phi] * nf)[:nf] if nf > w.phi.shape[0] else w.phi[:nf]
-    size = 2000
-    t = 0.0
-    while True:
-        rows = np.sort(rng.choice(w.n, size=min(size, w.n), replace=False))
-        t0 = time.perf_counter()
-        csr = oracle.neighbors(w.pos, w.R, rows=rows)
-        oracle.sph2(w.pos, w.vol, phis, w.kernel, w.R, w.mapspec, rows=rows, csr=csr)
-        t = time.perf_counter() - t0
-        if t >= target_s / 4 or size >= w.n:
-            break
-        size = int(min(w.n, size * max(2.0, 0.5 * target_s / max(t, 1e-3))))
-    return {"value": size * nf / t, "unit": "evals/s", "cores": oracle.threads(), "kind": "oracle",
-            "sample": f"{size} random particles of the {w.n}-particle set (neighbour grid over all particles "
-                      f"+ SPH(2) at the sampled rows), {t:.1f} s"}
+
+    def timed(size, budget):
+        while True:
+            rows = np.sort(rng.choice(w.n, size=min(size, w.n), replace=False))
+            t0 = time.perf_counter()
+            csr = oracle.neighbors(w.pos, w.R, rows=rows)
+            rec, _ = oracle.sph2(w.pos, w.vol, phis, w.kernel, w.R, mapspec, rows=rows, csr=csr)
+            t = time.perf_counter() - t0
+            if t >= budget / 4 or size >= w.n:
+                return size, t, rows, rec
+            size = int(min(w.n, size * max(2.0, 0.5 * budget / max(t, 1e-3))))
+
+    cores = oracle.threads()
+    size, t, rows, rec = timed(2000, target_s)
+    oracle.set_threads(1)
+    try:
+        size1, t1, _, _ = timed(500, target_s / 3)
+    finally:
+        oracle.set_threads(cores)
+    res = {"value": size * nf / t, "unit": "evals/s", "cores": cores, "kind": "oracle",
+           "sample": f"{size} random particles of the {w.n}-particle set (neighbour grid over all particles "
+                     f"+ SPH(2) at the sampled rows), {t:.1f} s",
+           "single_core": {"value": size1 * nf / t1, "sample": f"{size1} particles, {t1:.1f} s"},
+           "cpu_model": cpu_model()}
+    return res, rows, rec
+
+
+def operator_errors(out_sampled, rec, dim):
+    """Normwise error per output row (max |gpu - oracle| / max |oracle| over
+    the sample, worst field) for the default rows: gradient, Laplacian, cross."""
+    import numpy as np
+    cols, names = ([0, 1, 2, 3, 4, 5, 6], ["grad_x", "grad_y", "grad_z", "lap", "cross_xy", "cross_xz", "cross_yz"]) \
+        if dim == 3 else ([0, 2, 3, 5], ["grad_x", "grad_z", "lap", "cross_xz"])
+    ref = np.transpose(rec[:, :, cols], (1, 0, 2))
+    err = (np.abs(out_sampled - ref).max(axis=1) / np.abs(ref).max(axis=1)).max(axis=0)
+    return {nm: float(f"{e:.3e}") for nm, e in zip(names, err)}
 
 
 if __name__ == "__main__":

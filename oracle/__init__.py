@@ -83,6 +83,8 @@ def lib():
         L.orc_kernel_eval.restype = None
         L.orc_kernel_eval.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, dp, dp]
         L.orc_threads.restype = C.c_int
+        L.orc_set_threads.restype = None
+        L.orc_set_threads.argtypes = [C.c_int]
         _lib = L
     return _lib
 
@@ -103,6 +105,11 @@ def _map_args(ms):
 
 def threads():
     return lib().orc_threads()
+
+
+def set_threads(n):
+    """OpenMP threads of the following oracle calls (for timing)."""
+    lib().orc_set_threads(int(n))
 
 
 def kernel_eval(kernel, dim, R, r):

@@ -728,3 +728,13 @@ int orc_threads(void)
     return 1;
 #endif
 }
+
+/* Thread count of the following parallel regions (timing only; n <= 0 keeps it). */
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
