@@ -223,10 +223,16 @@ __global__ __launch_bounds__(256) void k_adjoint_pack(int64_t n, const double* _
 // A record is 11 16-byte slots (176 B = 44 banks of 4 B, an odd multiple of
 // 16 B): the lanes reading 16 consecutive records in one LDS pass start on 16
 // different bank quadruples, where a 160-byte record would give 8.
-constexpr int kASub = 448;   // records per sub-window: 448 x 176 B, two groups per CU
+#ifndef VCT_ASUB
+#define VCT_ASUB 448
+#endif
+#ifndef VCT_DPHI_GROUPS
+#define VCT_DPHI_GROUPS 2
+#endif
+constexpr int kASub = VCT_ASUB;   // records per sub-window: 448 x 176 B, two groups per CU
 
 template <int D, int KERNEL>
-__global__ __launch_bounds__(kAThreads, 2) void k_adjoint_dphi(AdjArgs A) {
+__global__ __launch_bounds__(kAThreads, VCT_DPHI_GROUPS) void k_adjoint_dphi(AdjArgs A) {
     using Dm = Dims<D>;
     constexpr int nL = Dm::nL, nk = Dm::nk, m = Dm::m;
     constexpr int kRec = 11;   // double2 per record: (x, y), (z, V), the packed record, one pad

@@ -232,24 +232,26 @@ __global__ __launch_bounds__(kMThreads, VCT_SWEEP_WAVES) void k_moment_sweeps(Sw
     for (int p = 0; p < Dm::nL; ++p) Am[p] = 0.0;
 #pragma unroll
     for (int t = 0; t < Dm::n3; ++t) B[t] = 0.0;
-    // monomials of r~ built from the pair products: qv (2nd), cub (3rd), quartic on the fly
-    auto monos = [&](const double (&r)[D], double (&qv)[Dm::m], double (&cub)[Dm::n3]) {
+    // The weighted pair products wq = wgt q~ are formed once per pair; the
+    // cubic and quartic sums are then one multiply-add each (wq times r~ or
+    // q~), not a monomial product followed by a weighted multiply-add.
+    auto pairs = [&](const double (&r)[D], double (&qv)[Dm::m]) {
 #pragma unroll
         for (int p = 0; p < Dm::m; ++p) qv[p] = r[pair_a<D>(p)] * r[pair_b<D>(p)];
-#pragma unroll
-        for (int t = 0; t < Dm::n3; ++t)
-            cub[t] = qv[sym_index<D>(mono_comp<D, 3>(t, 0), mono_comp<D, 3>(t, 1))] * r[mono_comp<D, 3>(t, 2)];
     };
     sweep([&](const double4& q) {
-        double r[D], q2, qv[Dm::m], cub[Dm::n3];
+        double r[D], q2, qv[Dm::m], wq[Dm::m];
         geom(q, r, q2);
         if (q2 == 0.0) fl |= VCT_FLAG_DUPLICATE;
-        monos(r, qv, cub);
+        pairs(r, qv);
         const double wgt = q.w * kernel_shape<KERNEL>(vsqrt(q2));
 #pragma unroll
-        for (int p = 0; p < Dm::nL; ++p) Am[p] += wgt * qv[p];
+        for (int p = 0; p < Dm::m; ++p) wq[p] = wgt * qv[p];
 #pragma unroll
-        for (int t = 0; t < Dm::n3; ++t) B[t] += wgt * cub[t];
+        for (int p = 0; p < Dm::nL; ++p) Am[p] += wq[p];
+#pragma unroll
+        for (int t = 0; t < Dm::n3; ++t)
+            B[t] += wq[sym_index<D>(mono_comp<D, 3>(t, 0), mono_comp<D, 3>(t, 1))] * r[mono_comp<D, 3>(t, 2)];
     }, std::true_type{});
 #pragma unroll
     for (int p = 0; p < Dm::nL; ++p) Am[p] = group_sum(Am[p], kMLanes);
@@ -285,9 +287,9 @@ __global__ __launch_bounds__(kMThreads, VCT_SWEEP_WAVES) void k_moment_sweeps(Sw
     for (int t = 0; t < Dm::n4; ++t) E[t] = 0.0;
     const bool live = fl == 0;
     sweep([&](const double4& q) {
-        double r[D], q2, qv[Dm::m], cub[Dm::n3];
+        double r[D], q2, qv[Dm::m], wq[Dm::m];
         geom(q, r, q2);
-        monos(r, qv, cub);
+        pairs(r, qv);
         double rLr = 0.0;
 #pragma unroll
         for (int p = 0; p < Dm::nL; ++p) rLr += L2[p] * qv[p];
@@ -295,10 +297,13 @@ __global__ __launch_bounds__(kMThreads, VCT_SWEEP_WAVES) void k_moment_sweeps(Sw
         const double y = vrsq(q2), y2 = y * y;
         const double wgt = live ? q.w * kernel_shape<KERNEL>(q2 * y) * rLr * (y2 * y2) : 0.0;
 #pragma unroll
-        for (int t = 0; t < Dm::n3; ++t) Cm[t] += wgt * cub[t];
+        for (int p = 0; p < Dm::m; ++p) wq[p] = wgt * qv[p];
+#pragma unroll
+        for (int t = 0; t < Dm::n3; ++t)
+            Cm[t] += wq[sym_index<D>(mono_comp<D, 3>(t, 0), mono_comp<D, 3>(t, 1))] * r[mono_comp<D, 3>(t, 2)];
 #pragma unroll
         for (int t = 0; t < Dm::n4; ++t)
-            E[t] += wgt * qv[sym_index<D>(mono_comp<D, 4>(t, 0), mono_comp<D, 4>(t, 1))] *
+            E[t] += wq[sym_index<D>(mono_comp<D, 4>(t, 0), mono_comp<D, 4>(t, 1))] *
                     qv[sym_index<D>(mono_comp<D, 4>(t, 2), mono_comp<D, 4>(t, 3))];
     }, std::integral_constant<bool, VCT_SWEEP2_AHEAD>{});
 #pragma unroll
