@@ -146,6 +146,7 @@ def main():
     chunk_off = torch.empty(ncols + 1, dtype=torch.int64, device=dev)
     chunk_start = torch.empty(cap + 1, dtype=torch.int32, device=dev)
     chunk_info = torch.empty((cap, 4), dtype=torch.int32, device=dev)
+    chunk_win = torch.empty((cap, 32), dtype=torch.int32, device=dev)
     ws_cells = torch.empty(L.vct_build_cells_workspace_size(dim, n, ncell), dtype=torch.uint8, device=dev)
     ws_nb = torch.empty(L.vct_neighbors_workspace_size(n, ncell), dtype=torch.uint8, device=dev)
     ws_mom = torch.empty(L.vct_moments_workspace_size(dim, n), dtype=torch.uint8, device=dev)
@@ -175,7 +176,7 @@ def main():
     # map): the geometry is rebuilt every step, and building the map costs more
     # than it saves in a single adjoint call
     nl = vct.make_nlist(dim, n, ncell, w.lo, w.hi, w.R, cell_start, chunk_off, chunk_start, chunk_info, row_ptr,
-                        None, col16)
+                        None, col16, chunk_win=chunk_win)
     ws_adj = torch.empty(L.vct_adjoint_workspace_size(dim, n, nnz, nterms), dtype=torch.uint8, device=dev)
     torch.cuda.synchronize()
 

@@ -234,6 +234,9 @@ typedef struct {
     int32_t* col_t;         /* [nnz] or NULL: for entry e = (i, j) of row i, the position of
                                the entry (j, i) in row j (needs col); read by the adjoint */
     int64_t nnz;            /* written by vct_neighbors (the total of row_ptr) */
+    int32_t* chunk_win;     /* [chunk_cap][32] or NULL: every chunk's window (its column
+                               ranges), written by vct_neighbors and read by the other
+                               calls instead of recomputing it from cell_start */
 } vct_nlist;
 
 /* Entries needed in the chunk arrays of a set of n particles on ncell cells. */

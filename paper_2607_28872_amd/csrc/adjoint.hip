@@ -47,6 +47,7 @@ struct AdjArgs {
     const int64_t* cs;
     const int32_t* cstart;
     const int4* cinfo;
+    const int32_t* cwin;   // stored windows or NULL
     const int64_t* nchunks;
     int lap_row, pg_row, ph_row, nrows;
     const double* coef;   // [n][kCoef] packed records of the gather form
@@ -98,7 +99,10 @@ __global__ __launch_bounds__(kAThreads, 2) void k_adjoint_weights(AdjArgs A) {
     if (b >= *A.nchunks) return;   // uniform over the work-group
     const int64_t n = A.n;
     const int64_t p0 = A.cstart[b], p1 = A.cstart[b + 1];
-    if (threadIdx.x < kWave) chunk_window_wave<D>(A.g, A.cs, A.cinfo[b], w);
+    if (threadIdx.x < kWave) {
+        if (A.cwin) window_load<D>(A.cwin, b, w);
+        else chunk_window_wave<D>(A.g, A.cs, A.cinfo[b], w);
+    }
     const int lane = threadIdx.x % kALanes;
     const int64_t i = p0 + threadIdx.x / kALanes;
     const bool valid = i < p1;
@@ -242,7 +246,10 @@ __global__ __launch_bounds__(kAThreads, VCT_DPHI_GROUPS) void k_adjoint_dphi(Adj
     if (b >= *A.nchunks) return;   // uniform over the work-group
     const int64_t n = A.n;
     const int64_t p0 = A.cstart[b], p1 = A.cstart[b + 1];
-    if (threadIdx.x < kWave) chunk_window_wave<D>(A.g, A.cs, A.cinfo[b], w);
+    if (threadIdx.x < kWave) {
+        if (A.cwin) window_load<D>(A.cwin, b, w);
+        else chunk_window_wave<D>(A.g, A.cs, A.cinfo[b], w);
+    }
     const int lane = threadIdx.x % kALanes;
     const int64_t k = p0 + threadIdx.x / kALanes;
     const bool valid = k < p1;
@@ -514,6 +521,7 @@ extern "C" int vct_apply_ops_adjoint(const vct_nlist* nl, const double* pos_sort
     a.n = n; a.invR = 1.0 / nl->R; a.g = g; a.pos = pos_sorted; a.vol = vol_sorted; a.state = state64; a.u = u;
     a.proj = proj; a.row_ptr = nl->row_ptr; a.col16 = nl->col16; a.col_t = nl->col_t; a.cs = nl->cell_start;
     a.cstart = nl->chunk_start; a.cinfo = reinterpret_cast<const int4*>(nl->chunk_info);
+    a.cwin = nl->chunk_win;
     a.nchunks = nl->chunk_off + ncols;
     a.lap_row = group_row(dim, out_mask, VCT_OUT_LAP);
     a.pg_row = group_row(dim, out_mask, VCT_OUT_PGRAD);

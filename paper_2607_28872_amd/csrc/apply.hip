@@ -104,6 +104,7 @@ template <class S> struct ApplyArgs {
     const int64_t* cs;
     const int32_t* cstart;
     const int4* cinfo;
+    const int32_t* cwin;   // stored windows or NULL
     const int64_t* nchunks;
     const S* state;
     double* out;
@@ -286,7 +287,10 @@ __global__ __launch_bounds__(ApplyCfg<T>::threads, ApplyCfg<T>::waves) void k_ap
     if (b >= *A.nchunks) return;   // uniform over the work-group
     const int64_t n = A.n;
     const int64_t p0 = A.cstart[b], p1 = A.cstart[b + 1];
-    if (threadIdx.x < kWave) chunk_window_wave<D>(A.g, A.cs, A.cinfo[b], w);
+    if (threadIdx.x < kWave) {
+        if (A.cwin) window_load<D>(A.cwin, b, w);
+        else chunk_window_wave<D>(A.g, A.cs, A.cinfo[b], w);
+    }
     // per-particle data, requested while the window is formed
     const int lane = threadIdx.x % kLanes;
     const int pl = threadIdx.x / kLanes;
@@ -524,7 +528,7 @@ static ApplyArgs<S> make_args(const vct_nlist* nl, const Grid& g, int nf, const 
     a.col16 = nl->col16;
     a.cs = nl->cell_start;
     a.cstart = nl->chunk_start;
-    a.cinfo = reinterpret_cast<const int4*>(nl->chunk_info);
+    a.cinfo = reinterpret_cast<const int4*>(nl->chunk_info); a.cwin = nl->chunk_win;
     a.nchunks = nl->chunk_off + ncols;
     a.state = state;
     a.out = out;

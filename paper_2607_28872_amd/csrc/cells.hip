@@ -274,7 +274,8 @@ __global__ __launch_bounds__(kNbThreads) void k_nb_chunk(int64_t n, const double
                                                          int32_t* __restrict__ counts,
                                                          const int64_t* __restrict__ row_ptr,
                                                          int32_t* __restrict__ col, uint16_t* __restrict__ col16,
-                                                         int32_t* __restrict__ overflow) {
+                                                         int32_t* __restrict__ overflow,
+                                                         int32_t* __restrict__ win_tab) {
     constexpr bool FILL = MODE == 1, STAGE = MODE == 2;
     static_assert(kChunk == kWave, "lane = particle");
     static_assert(kChunk * kRowPad * 2 <= kNbSeg * 16, "staged rows must fit in the window buffer");
@@ -302,6 +303,7 @@ __global__ __launch_bounds__(kNbThreads) void k_nb_chunk(int64_t n, const double
     __syncthreads();
     const int W = w.off[w.nr];
     if ((FILL || STAGE) && threadIdx.x == 0 && W > 65535) atomicOr(overflow, 1);
+    if (win_tab && wv == 0) window_store<D>(w, win_tab, b);   // for the later calls
     // the particle's own window offset (it is never its own neighbour)
     int self_t = -1;
     for (int r = 0; r < w.nr; ++r) {
@@ -668,7 +670,7 @@ static int launch_nb(const vct_nlist* nl, const double* pos, const Grid& g, int3
     VCT_LAUNCH(name, (k_nb_chunk<D, MODE>), dim3((unsigned)cap), dim3(kNbThreads), 0, s, nl->n, pos, g,
                nl->R * nl->R, nl->cell_start, nl->chunk_start,
                reinterpret_cast<const int4*>(nl->chunk_info), nl->chunk_off + ncols, counts, nl->row_ptr,
-               MODE == 1 ? nl->col : nullptr, MODE == 1 ? nl->col16 : staged, overflow);
+               MODE == 1 ? nl->col : nullptr, MODE == 1 ? nl->col16 : staged, overflow, nl->chunk_win);
     VCT_LAUNCH_CHECK();
     return VCT_OK;
 }

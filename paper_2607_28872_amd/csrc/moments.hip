@@ -114,6 +114,7 @@ struct SweepArgs {
     const int64_t* cs;
     const int32_t* cstart;
     const int4* cinfo;
+    const int32_t* cwin;   // stored windows or NULL
     const int64_t* nchunks;
     double* mom;
     uint8_t* mflags;
@@ -135,7 +136,10 @@ __global__ __launch_bounds__(kMThreads, VCT_SWEEP_WAVES) void k_moment_sweeps(Sw
     if (b >= *A.nchunks) return;   // uniform over the work-group
     const int64_t n = A.n;
     const int64_t p0 = A.cstart[b], p1 = A.cstart[b + 1];
-    if (threadIdx.x < kWave) chunk_window_wave<D>(A.g, A.cs, A.cinfo[b], w);
+    if (threadIdx.x < kWave) {
+        if (A.cwin) window_load<D>(A.cwin, b, w);
+        else chunk_window_wave<D>(A.g, A.cs, A.cinfo[b], w);
+    }
     const int lane = threadIdx.x % kMLanes;
     const int pl = threadIdx.x / kMLanes;
     const int64_t i = p0 + pl;
@@ -606,6 +610,7 @@ static int launch_moments(const vct_nlist* nl, const Grid& g, const double* pos,
     SweepArgs a;
     a.n = n; a.invR = invR; a.g = g; a.pos = pos; a.vol = vol; a.row_ptr = nl->row_ptr; a.col16 = nl->col16;
     a.cs = nl->cell_start; a.cstart = nl->chunk_start; a.cinfo = reinterpret_cast<const int4*>(nl->chunk_info);
+    a.cwin = nl->chunk_win;
     a.nchunks = nl->chunk_off + ncols; a.mom = mom; a.mflags = mflags;
     const int64_t cap = ncols + n / kChunk + 1;
     VCT_LAUNCH("k_moment_sweeps", (k_moment_sweeps<D, KERNEL>), dim3((unsigned)cap), dim3(kMThreads), 0, s, a);

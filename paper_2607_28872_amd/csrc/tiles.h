@@ -127,6 +127,23 @@ __device__ __forceinline__ void chunk_window_wave(const Grid& g, const int64_t* 
     }
 }
 
+// Stored windows: chunk b's WindowT at tab + 32 b (int32 words).
+static_assert(sizeof(WindowT<3>) <= 32 * sizeof(int32_t), "a stored window fits 32 words");
+static_assert(sizeof(WindowT<2>) == sizeof(WindowT<3>), "one stored layout for both dimensions");
+
+// Store (lanes 0..31 of the wave that formed w) or load (lanes 0..31 of any
+// wave) a window as 32 int32 words.
+template <int D>
+__device__ __forceinline__ void window_store(const WindowT<D>& w, int32_t* __restrict__ tab, uint32_t b) {
+    const int lane = threadIdx.x % kWave;
+    if (lane < (int)(sizeof(WindowT<D>) / 4)) tab[(int64_t)b * 32 + lane] = reinterpret_cast<const int32_t*>(&w)[lane];
+}
+template <int D>
+__device__ __forceinline__ void window_load(const int32_t* __restrict__ tab, uint32_t b, WindowT<D>& w) {
+    const int lane = threadIdx.x % kWave;
+    if (lane < (int)(sizeof(WindowT<D>) / 4)) reinterpret_cast<int32_t*>(&w)[lane] = tab[(int64_t)b * 32 + lane];
+}
+
 // global sorted index of window offset t
 template <int D>
 __device__ __forceinline__ int64_t window_global(const WindowT<D>& w, int t) {

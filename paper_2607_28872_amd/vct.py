@@ -51,7 +51,7 @@ class vct_nlist(C.Structure):
                 ("chunk_cap", C.c_int64), ("lo", C.c_double * 3), ("hi", C.c_double * 3), ("R", C.c_double),
                 ("cell_start", C.c_void_p), ("chunk_off", C.c_void_p), ("chunk_start", C.c_void_p),
                 ("chunk_info", C.c_void_p), ("row_ptr", C.c_void_p), ("col", C.c_void_p), ("col16", C.c_void_p),
-                ("col_t", C.c_void_p), ("nnz", C.c_int64)]
+                ("col_t", C.c_void_p), ("nnz", C.c_int64), ("chunk_win", C.c_void_p)]
 
 
 _lib = None
@@ -197,7 +197,7 @@ def _nbytes(t):
 
 
 def make_nlist(dim, n, ncell, lo, hi, R, cell_start, chunk_off, chunk_start, chunk_info, row_ptr, col=None,
-               col16=None, chunk_cap=None, col_t=None):
+               col16=None, chunk_cap=None, col_t=None, chunk_win=None):
     """vct_nlist over torch tensors (device)."""
     nl = vct_nlist()
     nl.dim, nl.n, nl.ncell = int(dim), int(n), int(ncell)
@@ -211,6 +211,7 @@ def make_nlist(dim, n, ncell, lo, hi, R, cell_start, chunk_off, chunk_start, chu
     nl.col = col.data_ptr() if col is not None else None
     nl.col16 = col16.data_ptr() if col16 is not None else None
     nl.col_t = col_t.data_ptr() if col_t is not None else None
+    nl.chunk_win = chunk_win.data_ptr() if chunk_win is not None else None
     return nl
 
 
@@ -300,9 +301,10 @@ class Geometry:
         self.chunk_off = torch.empty(ncols + 1, dtype=torch.int64, device=device)
         self.chunk_start = torch.empty(cap + 1, dtype=torch.int32, device=device)
         self.chunk_info = torch.empty((cap, 4), dtype=torch.int32, device=device)
+        self.chunk_win = torch.empty((cap, 32), dtype=torch.int32, device=device)
         self._nws = _bytes(lib().vct_neighbors_workspace_size(n, self.ncell), device)
         nl = make_nlist(self.dim, n, self.ncell, lo, hi, R, self.cell_start, self.chunk_off, self.chunk_start,
-                        self.chunk_info, self.row_ptr, chunk_cap=cap)
+                        self.chunk_info, self.row_ptr, chunk_cap=cap, chunk_win=self.chunk_win)
         _, nnz = vct_neighbors(nl, self.pos, 0, 0, self._nws)
         self.nnz = nnz
         self.col = torch.empty(max(nnz, 1), dtype=torch.int32, device=device) if keep_col else None
@@ -310,7 +312,8 @@ class Geometry:
         # transposed-entry map, for the adjoint (needs the int32 columns)
         self.col_t = torch.empty(max(nnz, 1), dtype=torch.int32, device=device) if keep_col else None
         self.nl = make_nlist(self.dim, n, self.ncell, lo, hi, R, self.cell_start, self.chunk_off, self.chunk_start,
-                             self.chunk_info, self.row_ptr, self.col, self.col16, chunk_cap=cap, col_t=self.col_t)
+                             self.chunk_info, self.row_ptr, self.col, self.col16, chunk_cap=cap, col_t=self.col_t,
+                             chunk_win=self.chunk_win)
         # one search that stages the rows and compacts them (falling back to
         # the fill pass by itself when a row is longer than the staging rows)
         _, nnz2 = vct_neighbors(self.nl, self.pos, max(nnz, 1), 0, self._nws)

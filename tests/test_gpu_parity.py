@@ -70,6 +70,22 @@ def test_staged_search_equals_fill_pass(family):
     assert torch.equal(col, g.col) and torch.equal(col16, g.col16) and torch.equal(col_t, g.col_t)
 
 
+def test_stored_windows_give_the_same_bits():
+    """The consumers reading the per-chunk window table written by the
+    neighbour search produce the same bits as when they rebuild the windows."""
+    w = I.small("sigma3d")
+    g = _geom(w)
+    assert g.nl.chunk_win
+    g.moments(w.mapspec, ALL_OUT, fp32_copy=True)
+    phi = g.sorted_field(w.phi)
+    s1 = g.state64.clone()
+    a1, m1 = g.apply(phi, vct.VCT_FP64).clone(), g.apply(phi, vct.VCT_MIXED).clone()
+    g.nl.chunk_win = None
+    g.moments(w.mapspec, ALL_OUT, fp32_copy=True)
+    assert torch.equal(g.state64, s1)
+    assert torch.equal(g.apply(phi, vct.VCT_FP64), a1) and torch.equal(g.apply(phi, vct.VCT_MIXED), m1)
+
+
 def test_long_rows_fall_back_to_the_fill_pass():
     """Rows longer than the staging rows (here up to about 280 entries) are
     still listed exactly."""
