@@ -345,9 +345,12 @@ __global__ __launch_bounds__(ApplyCfg<T>::threads, ApplyCfg<T>::waves) void k_ap
 #pragma unroll
             for (int k = 0; k < kBatch; ++k) {
                 const int t = threadIdx.x + (k0 + k) * kThreads;
-                const int64_t j = window_global<D>(w, t < W ? t : 0);
-                q[k] = make_double4(A.pos[j] * ps, A.pos[n + j] * ps, D == 3 ? A.pos[2 * n + j] * ps : 0.0, ph[j]);
-                v[k] = T(A.vol[j]);
+                if (t < W) {   // lanes past the window load nothing (whole waves skip)
+                    const int64_t j = window_global<D>(w, t);
+                    q[k] = make_double4(A.pos[j] * ps, A.pos[n + j] * ps, D == 3 ? A.pos[2 * n + j] * ps : 0.0,
+                                        ph[j]);
+                    v[k] = T(A.vol[j]);
+                }
             }
 #pragma unroll
             for (int k = 0; k < kBatch; ++k) {

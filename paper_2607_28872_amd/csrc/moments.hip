@@ -176,8 +176,10 @@ __global__ __launch_bounds__(kMThreads, VCT_SWEEP_WAVES) void k_moment_sweeps(Sw
 #pragma unroll
         for (int k = 0; k < kRep; ++k) {
             const int t = threadIdx.x + k * kMThreads;
-            const int64_t j = window_global<D>(w, t < W ? t : 0);
-            q[k] = make_double4(A.pos[j], A.pos[n + j], D == 3 ? A.pos[2 * n + j] : 0.0, A.vol[j]);
+            if (t < W) {   // lanes past the window load nothing (whole waves skip)
+                const int64_t j = window_global<D>(w, t);
+                q[k] = make_double4(A.pos[j], A.pos[n + j], D == 3 ? A.pos[2 * n + j] : 0.0, A.vol[j]);
+            }
         }
 #pragma unroll
         for (int k = 0; k < kRep; ++k) {
