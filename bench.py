@@ -2,10 +2,12 @@
 
 One step = one pass of the whole hot path over the 3-D sigma-SPH particle set
 (512 x 512 x 32 = 8,388,608 particles, sloped-beach bathymetry, 5% jitter):
-  cell sort -> neighbour lists (one staged search) -> FP64 moments + solve (with the
-  FP32 copy of the state) -> mixed-precision operator apply (grad + lap +
-  cross) -> FP64 moments recomputed for the adjoint -> adjoint (d/dphi and
-  d/d bathymetry coefficients).
+  cell sort -> neighbour lists (one staged search) -> FP64 moments + solve (the
+  FP32 state only) -> mixed-precision operator apply (grad + lap + cross) ->
+  FP64 state of the adjoint's rows, solved again from the moment sums the
+  forward kept -> FP64 apply of those rows -> adjoint (d/dphi and d/d
+  bathymetry coefficients).  --adjoint-state recompute runs both moment sweeps
+  again in the backward instead.
 Inputs are resident in HBM before the timed region.  `value` is particle-
 operator evaluations (particles x fields) per second of the whole step.
 
@@ -60,6 +62,8 @@ def parse():
     p.add_argument("--nf", type=int, default=1)
     p.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--adjoint-state", choices=["resolve", "recompute"], default="resolve",
+                   help="backward state: solved from the forward's kept moment sums, or sweeps + solve again")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a 1 GiB device-to-device copy five times (reference for HBM byte counters)")
     return p.parse_args()
@@ -207,8 +211,12 @@ def main():
         mark()
         vct.vct_apply_ops(nl, nf, phi_s, pos_s, vol_s, w.kernel, st32, fwd_mask, vct.VCT_MIXED, out)
         mark()
-        # backward of loss = sum (lap f - g)^2 with the state recomputed
-        vct.vct_moments(nl, pos_s, vol_s, w.kernel, cmap, adj_mask, sta, None, flags, False, ws_mom)
+        # backward of loss = sum (lap f - g)^2: the FP64 state of its rows,
+        # from the moment sums the forward left in ws_mom (or recomputed)
+        if args.adjoint_state == "resolve":
+            vct.vct_moments_resolve(nl, pos_s, cmap, adj_mask, sta, None, flags, False, ws_mom)
+        else:
+            vct.vct_moments(nl, pos_s, vol_s, w.kernel, cmap, adj_mask, sta, None, flags, False, ws_mom)
         mark()
         vct.vct_apply_ops(nl, 1, phi_s, pos_s, vol_s, w.kernel, sta, adj_mask, vct.VCT_FP64, proj)
         torch.sub(proj[0, :, 0], g_s, out=u)
@@ -335,7 +343,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"3-D sigma-SPH sloped beach {w.counts[0]}x{w.counts[1]}x{w.counts[2]} "
                                f"({n} particles), Wendland C2 R=3dx, 5% jitter, {nf} field(s), mixed apply, "
-                               f"adjoint with recomputed moments",
+                               + ("adjoint state solved from the forward's moment sums"
+                                  if args.adjoint_state == "resolve" else "adjoint with recomputed moments"),
                    "particles": n, "fields": nf, "neighbours_per_particle": round(deg, 2),
                    "parallelism": "single GPU"},
         "stage_ms": {k: round(v, 4) for k, v in stage.items()},

@@ -296,6 +296,21 @@ int vct_moments(const vct_nlist* nl, const double* pos_sorted, const double* vol
 
 size_t vct_moments_workspace_size(int dim, int64_t n);
 
+/* The solve and fold of vct_moments alone, from the moment sums that the last
+ * vct_moments call left in `ws`.  The sums depend only on the neighbour list,
+ * positions, volumes, kernel and R, not on `map` or `out_mask`, so a second
+ * state for other outputs or another map (the Laplacian and projected rows of
+ * an adjoint after a forward that wrote the default outputs, say) costs one
+ * solve instead of two sweeps over the rows.  `ws` must come from a
+ * vct_moments call on the same nl, pos_sorted and vol_sorted, ordered before
+ * this one on the stream, and must not be used by another call in between;
+ * the library cannot check this.  Arguments, state layout, flags and
+ * n_flagged as in vct_moments; the results are bitwise those of a vct_moments
+ * call with the same map and out_mask.                                         */
+int vct_moments_resolve(const vct_nlist* nl, const double* pos_sorted, const vct_map* map /* host */,
+                        uint32_t out_mask, double* state64, float* state32, uint8_t* flags, int64_t* n_flagged,
+                        void* ws, size_t ws_bytes, void* stream);
+
 /* ---------------------------------------------------------------- apply */
 
 /* Apply the operators to nf fields (Eqs. grad_VCT, lap_VCT, sec_SPH2):

@@ -685,3 +685,49 @@ extern "C" int vct_moments(const vct_nlist* nl, const double* pos_sorted, const 
     }
     return VCT_OK;
 }
+
+extern "C" int vct_moments_resolve(const vct_nlist* nl, const double* pos_sorted, const vct_map* map,
+                                   uint32_t out_mask, double* state64, float* state32, uint8_t* flags,
+                                   int64_t* n_flagged, void* ws, size_t ws_bytes, void* stream) {
+    Grid g;
+    int st = nlist_check(nl, g);
+    if (st) return st;
+    const int dim = nl->dim;
+    const int64_t n = nl->n;
+    if (!map || !mask_valid(out_mask)) return VCT_E_ARG;
+    MapParams mp;
+    st = map_params_from(map, dim, mp);
+    if (st) return st;
+    if (n > 0 && (!pos_sorted || (!state64 && !state32))) return VCT_E_ARG;
+    if (!ws || ws_bytes < vct_moments_workspace_size(dim, n)) return VCT_E_WORKSPACE;
+    hipStream_t s = as_stream(stream);
+    // the same carving as vct_moments: the sums and sweep flags it left behind
+    Carver cv(ws, ws_bytes);
+    const int total = dim == 2 ? MomLayout<2>::total : MomLayout<3>::total;
+    const double* mom = cv.take<double>((size_t)n * total);
+    const uint8_t* mflags = cv.take<uint8_t>((size_t)n);
+    unsigned long long* cnt = cv.take<unsigned long long>(8);
+    VCT_LAUNCH("k_zero_u64", k_zero_u64, dim3(1), dim3(1), 0, s, cnt);
+    VCT_LAUNCH_CHECK();
+    if (n > 0) {
+        const double invR = 1.0 / nl->R;
+        const int nrows = n_out_rows(dim, out_mask);
+        const int64_t nb2 = (n + 127) / 128;
+        if (dim == 2) {
+            VCT_LAUNCH("k_moment_solve", (k_moment_solve<2>), dim3((unsigned)nb2), dim3(128), 0, s, n, pos_sorted,
+                       mom, mflags, invR, mp, out_mask, nrows, state64, state32, flags, cnt);
+        } else {
+            VCT_LAUNCH("k_moment_solve", (k_moment_solve<3>), dim3((unsigned)nb2), dim3(128), 0, s, n, pos_sorted,
+                       mom, mflags, invR, mp, out_mask, nrows, state64, state32, flags, cnt);
+        }
+        VCT_LAUNCH_CHECK();
+    }
+    if (n_flagged) {
+        unsigned long long h = 0;
+        VCT_HIP_CHECK(hipMemcpyAsync(&h, cnt, sizeof(h), hipMemcpyDeviceToHost, s));
+        VCT_HIP_CHECK(hipStreamSynchronize(s));
+        *n_flagged = (int64_t)h;
+        return h ? VCT_W_FLAGGED : VCT_OK;
+    }
+    return VCT_OK;
+}

@@ -104,6 +104,9 @@ def lib():
         L.vct_moments.restype = C.c_int
         L.vct_moments.argtypes = [_nlp, _vp, _vp, C.c_int, C.POINTER(vct_map), C.c_uint32, _vp, _vp, _vp,
                                   C.POINTER(_i64), _vp, _sz, _vp]
+        L.vct_moments_resolve.restype = C.c_int
+        L.vct_moments_resolve.argtypes = [_nlp, _vp, C.POINTER(vct_map), C.c_uint32, _vp, _vp, _vp,
+                                          C.POINTER(_i64), _vp, _sz, _vp]
         L.vct_apply_ops.restype = C.c_int
         L.vct_apply_ops.argtypes = [_nlp, C.c_int, _vp, _vp, _vp, C.c_int, _vp, C.c_uint32, C.c_int, _vp, _vp]
         L.vct_adjoint_workspace_size.restype = _sz
@@ -254,6 +257,15 @@ def vct_moments(nl, pos_sorted, vol_sorted, kernel, cmap, mask, state64, state32
     return st, cnt.value
 
 
+def vct_moments_resolve(nl, pos_sorted, cmap, mask, state64, state32, flags, count_flagged, ws, stream=None):
+    cnt = _i64(0)
+    st = lib().vct_moments_resolve(C.byref(nl), _p(pos_sorted), C.byref(cmap), mask, _p(state64), _p(state32),
+                                   _p(flags), C.byref(cnt) if count_flagged else None, _p(ws), _nbytes(ws),
+                                   _stream(stream))
+    _check("vct_moments_resolve", st)
+    return st, cnt.value
+
+
 def vct_apply_ops(nl, nf, phi_sorted, pos_sorted, vol_sorted, kernel, state, mask, precision, out, stream=None):
     return _check("vct_apply_ops", lib().vct_apply_ops(
         C.byref(nl), nf, _p(phi_sorted), _p(pos_sorted), _p(vol_sorted), kernel, _p(state), mask, precision, _p(out),
@@ -354,9 +366,27 @@ class Geometry:
         self.state64 = torch.empty((stride, max(n, 1)), dtype=torch.float64, device=self.device) if fp64 else None
         self.state32 = torch.empty((stride, max(n, 1)), dtype=torch.float32, device=self.device) if fp32_copy else None
         self.flags = torch.empty(max(n, 1), dtype=torch.uint8, device=self.device)
-        ws = _bytes(lib().vct_moments_workspace_size(dim, n), self.device)
+        self.ws_mom = ws = _bytes(lib().vct_moments_workspace_size(dim, n), self.device)
         st, nflag = vct_moments(self.nl, self.pos, self.vol, self.kernel, self.cmap, mask, self.state64, self.state32,
                                 self.flags, count_flagged, ws)
+        self.n_flagged = nflag
+        return st
+
+    def resolve(self, mapspec, mask=VCT_OUT_DEFAULT, fp32_copy=False, count_flagged=True, fp64=True):
+        """The state for another mask or map, solved from the moment sums the
+        last moments() call kept in its workspace (no sweep over the rows)."""
+        import torch
+        if getattr(self, "ws_mom", None) is None:
+            raise ValueError("resolve() needs an earlier moments() call")
+        n, dim = self.n, self.dim
+        stride = vct_state_stride(dim, mask)
+        self.cmap = make_map(mapspec)
+        self.mask = mask
+        self.state64 = torch.empty((stride, max(n, 1)), dtype=torch.float64, device=self.device) if fp64 else None
+        self.state32 = torch.empty((stride, max(n, 1)), dtype=torch.float32, device=self.device) if fp32_copy else None
+        self.flags = torch.empty(max(n, 1), dtype=torch.uint8, device=self.device)
+        st, nflag = vct_moments_resolve(self.nl, self.pos, self.cmap, mask, self.state64, self.state32, self.flags,
+                                        count_flagged, self.ws_mom)
         self.n_flagged = nflag
         return st
 

@@ -113,6 +113,12 @@ def test_argument_errors_are_caught_on_the_host(L):
     sig = vct.vct_map(4, 0, -1.0, 0.0, 0.0, 0.0, None)
     assert L.vct_moments(C.byref(nl), None, None, 0, C.byref(sig), 3, None, None, None, None, None, 0,
                          None) == E              # sigma with Hhat <= 0
+    assert L.vct_moments_resolve(C.byref(nl), None, C.byref(m), 0, None, None, None, None, None, 0,
+                                 None) == E      # empty output mask
+    assert L.vct_moments_resolve(C.byref(nl), None, C.byref(badm), 3, None, None, None, None, None, 0,
+                                 None) == E      # unknown map kind
+    assert L.vct_moments_resolve(C.byref(nl), None, C.byref(m), 3, None, None, None, None, None, 0,
+                                 None) == E      # no positions, no state
     assert L.vct_apply_ops(C.byref(nl), 0, None, None, None, 0, None, 3, 0, None, None) == E   # nf
     assert L.vct_apply_ops(C.byref(nl), 1, None, None, None, 0, None, 3, 5, None, None) == E   # precision
     assert L.vct_apply_ops(C.byref(nl), 1, None, None, None, 0, None, 3, 0, None, None) == E   # null arrays
@@ -132,6 +138,9 @@ def test_workspace_errors(L):
     assert L.vct_neighbors(C.byref(nl), C.c_void_p(256), 0, C.byref(nnz), 0, None, 0,
                            None) == vct.VCT_E_WORKSPACE
     assert L.vct_build_cells_workspace_size(3, 100, nc) > 100 * 4
+    m = vct.make_map(__import__("paper_2607_28872_amd.inputs", fromlist=["MapSpec"]).MapSpec())
+    assert L.vct_moments_resolve(C.byref(nl), C.c_void_p(256), C.byref(m), 3, C.c_void_p(256), None, None, None,
+                                 None, 0, None) == vct.VCT_E_WORKSPACE
     assert L.vct_moments_workspace_size(3, 100) >= 100 * 41 * 8
     assert L.vct_adjoint_workspace_size(3, 100, 1000, 16) >= (100 * 7 + 1000) * 8
     # counts, scan tiles and the 128-entry staging rows of the one-search path

@@ -215,6 +215,31 @@ def test_fp32_only_state_matches_the_rounded_fp64_state():
     assert torch.equal(s32, s64.to(torch.float32))
 
 
+@pytest.mark.parametrize("family", ["sigma3d-adj", "bf2d-degenerate"])
+def test_resolve_from_kept_sums_gives_the_same_bits(family):
+    """A state solved from the sums an earlier call with another mask and map
+    kept equals, bit for bit, the state of a full call (flags included)."""
+    if family == "bf2d-degenerate":
+        w = I.small("bf2d")
+        pos = np.concatenate([w.pos, [[0.5], [10.0]], w.pos[:, :1]], axis=1)
+        vol = np.concatenate([w.vol, [w.vol[0], w.vol[0]]])
+        g = vct.Geometry(pos, vol, w.lo, w.hi, w.R, w.kernel, device=DEV)
+        mask = vct.VCT_OUT_HESS | vct.VCT_OUT_PGRAD
+    else:
+        w = I.small(family)
+        g = _geom(w)
+        mask = vct.VCT_OUT_LAP | vct.VCT_OUT_PGRAD | vct.VCT_OUT_PHESS
+    st_full = g.moments(w.mapspec, mask, fp32_copy=True)
+    s64, s32, fl = g.state64.clone(), g.state32.clone(), g.flags.clone()
+    # the forward's call: default outputs, the identity map, FP32 state only
+    g.moments(I.MapSpec(), vct.VCT_OUT_DEFAULT, fp32_copy=True, fp64=False)
+    st = g.resolve(w.mapspec, mask, fp32_copy=True)
+    assert st == st_full
+    assert torch.equal(g.flags, fl)
+    assert torch.equal(g.state64.view(torch.int64), s64.view(torch.int64))
+    assert torch.equal(g.state32.view(torch.int32), s32.view(torch.int32))
+
+
 @pytest.mark.parametrize("form", ["transposed", "gather"])
 def test_adjoint_against_oracle(form):
     w = I.small("sigma3d-adj")
