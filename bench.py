@@ -133,15 +133,14 @@ def main():
 
     # ---------------------------------------------------------------- resident inputs + buffers
     pos = torch.as_tensor(w.pos, device=dev).contiguous()
-    vol = torch.as_tensor(w.vol, device=dev).contiguous()
-    phi_in = torch.as_tensor(phis, device=dev).contiguous()
-    g_in = torch.as_tensor(target, device=dev).contiguous()
+    # the per-particle input fields in one (2 + nf, n) array: volume, the
+    # fields, the loss target; one gather brings them all into sorted order
+    fields_in = torch.as_tensor(np.concatenate([w.vol[None], phis, target[None]]), device=dev).contiguous()
     ncell, _ = vct.vct_grid_dims(dim, w.lo, w.hi, w.R)
     perm = torch.empty(n, dtype=torch.int32, device=dev)
     pos_s = torch.empty((dim, n), dtype=torch.float64, device=dev)
-    vol_s = torch.empty(n, dtype=torch.float64, device=dev)
-    phi_s = torch.empty((nf, n), dtype=torch.float64, device=dev)
-    g_s = torch.empty(n, dtype=torch.float64, device=dev)
+    fields_s = torch.empty((2 + nf, n), dtype=torch.float64, device=dev)
+    vol_s, phi_s, g_s = fields_s[0], fields_s[1:1 + nf], fields_s[1 + nf]
     cell_start = torch.empty(ncell + 1, dtype=torch.int64, device=dev)
     row_ptr = torch.empty(n + 1, dtype=torch.int64, device=dev)
     _, dims = vct.vct_grid_dims(dim, w.lo, w.hi, w.R)
@@ -200,9 +199,7 @@ def main():
                 marks.append(ev())
 
         vct.vct_build_cells(dim, n, pos, w.lo, w.hi, w.R, perm, pos_s, cell_start, ncell, ws_cells)
-        vct.vct_gather_sorted(n, 1, perm, vol, vol_s)
-        vct.vct_gather_sorted(n, nf, perm, phi_in, phi_s)
-        vct.vct_gather_sorted(n, 1, perm, g_in, g_s)
+        vct.vct_gather_sorted(n, 2 + nf, perm, fields_in, fields_s)
         mark()
         vct.vct_neighbors(nl, pos_s, nnz, 0, ws_nb)
         mark()

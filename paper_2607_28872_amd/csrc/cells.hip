@@ -172,12 +172,23 @@ __global__ void k_cell_sort(int64_t ncell, const int64_t* __restrict__ cell_star
     }
 }
 
+// Components move in groups of four whose loads are all issued before the
+// first store: the scattered side then costs one memory latency per group,
+// not one per component.
 __global__ void k_gather(int64_t n, int ncomp, const int32_t* __restrict__ perm,
                          const double* __restrict__ src, double* __restrict__ dst) {
     int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
     int64_t o = perm[s];
-    for (int c = 0; c < ncomp; ++c) dst[c * n + s] = src[c * n + o];
+    for (int c0 = 0; c0 < ncomp; c0 += 4) {
+        double v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (c0 + k < ncomp) v[k] = src[(c0 + k) * n + o];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (c0 + k < ncomp) dst[(c0 + k) * n + s] = v[k];
+    }
 }
 
 __global__ void k_scatter(int64_t n, int ncomp, const int32_t* __restrict__ perm,
@@ -185,7 +196,15 @@ __global__ void k_scatter(int64_t n, int ncomp, const int32_t* __restrict__ perm
     int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
     int64_t o = perm[s];
-    for (int c = 0; c < ncomp; ++c) dst[c * n + o] = src[c * n + s];
+    for (int c0 = 0; c0 < ncomp; c0 += 4) {
+        double v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (c0 + k < ncomp) v[k] = src[(c0 + k) * n + s];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (c0 + k < ncomp) dst[(c0 + k) * n + o] = v[k];
+    }
 }
 
 // ------------------------------------------------------------------ chunk table
