@@ -2,7 +2,8 @@
 
 Each translation unit under csrc/ is compiled with hipcc for gfx950 only, then
 linked into paper_2607_28872_amd/libvct.so.  Packed FP32 instructions are
-disabled (-packed-fp32-ops); FP64 contraction is left to the compiler except
+disabled (-packed-fp32-ops), and with them the straight-line vectoriser, whose
+two-wide FP32 groups would only be split again and cost registers; FP64 contraction is left to the compiler except
 where the source turns it off (the neighbour test).
 """
 from __future__ import annotations
@@ -22,7 +23,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno-unused-function",
-          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-fno-slp-vectorize",
           "-I", os.path.join(ROOT, "include")]
 
 

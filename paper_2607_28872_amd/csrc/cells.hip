@@ -262,6 +262,14 @@ __device__ __forceinline__ bool within_exact(double dx, double dy, double dz, do
     return d2 < R2;
 }
 
+// d2 - lim for an FP32 window record q and the particle's FP32 offsets, the
+// threshold folded into the first multiply-add: each of the three roundings
+// is relative to a partial result no larger than max(d2, lim).
+__device__ __forceinline__ float d2_minus(const float4& q, float f0, float f1, float f2, float lim) {
+    const float ex = q.x - f0, ey = q.y - f1, ez = q.z - f2;
+    return fmaf(ez, ez, fmaf(ey, ey, fmaf(ex, ex, -lim)));
+}
+
 constexpr int kNbWaves = 4;                    // waves per work-group
 constexpr int kNbThreads = kNbWaves * kWave;   // one chunk per work-group, lane = particle
 constexpr int kNbSeg = 1536;                   // window records per LDS segment (24 KB)
@@ -370,33 +378,54 @@ __global__ __launch_bounds__(kNbThreads) void k_nb_chunk(int64_t n, const double
         const double maxoff = (double)fmaxf(mseg, fmax_own);
         const double margin = 4.0 * (2.0 * R) * (maxoff * 0x1p-23) + R2 * 0x1p-19;
         const float in_lim = (float)(R2 - margin), out_lim = (float)(R2 + margin);
+        // t = d2 - in_lim: t < 0 is a certain hit, 0 <= t <= band is the
+        // uncertain band (as unsigned integers, exactly the non-negative t up
+        // to band: a negative t has its sign bit set), t > band certainly
+        // lies outside.  band is exact (in_lim and out_lim are within a factor
+        // of two of each other).
+        const float band = out_lim - in_lim;
+        const uint32_t band_u = __float_as_uint(band);
         const int nw = (sW + 31) / 32;
         const int k0 = wv * nw / kNbWaves, k1 = (wv + 1) * nw / kNbWaves;
         int cnt = 0;
         for (int k = k0; k < k1; ++k) {
-            uint32_t bits = 0u, amb = 0u;
+            // Hits shift in as the sign bits of t (the first candidate ends in
+            // bit 31, reversed below); whether any candidate of the word lies
+            // in the band is one flag per lane, rarely set.
+            uint32_t bits = 0u;
+            bool amb_any = false;
             const float4* wp = win + 32 * k;
 #pragma unroll
             for (int u = 0; u < 32; ++u) {
-                const float4 q = wp[u];   // the same record for every lane
-                const float ex = q.x - f0, ey = q.y - f1, ez = q.z - f2;
-                const float d2f = ex * ex + ey * ey + ez * ez;
-                bits |= d2f < in_lim ? (1u << u) : 0u;
-                amb |= (d2f >= in_lim && d2f <= out_lim) ? (1u << u) : 0u;
+                const uint32_t t = __float_as_uint(d2_minus(wp[u], f0, f1, f2, in_lim));   // same record, every lane
+                bits = __builtin_amdgcn_alignbit(bits, t, 31);
+                amb_any = amb_any || t <= band_u;
             }
+            bits = __builtin_bitreverse32(bits);
             // drop the tail beyond the segment, the particle itself, idle lanes
             const int tb = s0 + 32 * k;
             uint32_t keep = (sW - 32 * k) >= 32 ? 0xffffffffu : ((1u << (sW - 32 * k)) - 1u);
             if (self_t >= tb && self_t < tb + 32) keep &= ~(1u << (self_t - tb));
             if (!valid) keep = 0u;
             bits &= keep;
-            amb &= keep;
-            while (amb) {   // near the support edge: the exact FP64 predicate
-                const int u = __builtin_ctz(amb);
-                amb &= amb - 1u;
-                const int64_t j = window_global<D>(w, tb + u);
-                if (within_exact(pos[j] - xi0, pos[n + j] - xi1, D == 3 ? pos[2 * n + j] - xi2 : 0.0, R2))
-                    bits |= 1u << u;
+            if (amb_any) {
+                // the word's candidates in the band, from the same arithmetic
+                // (the empty asm keeps the compiler from carrying the t of the
+                // loop above over to here), then the exact FP64 predicate
+                float g0 = f0, g1 = f1, g2 = f2;
+                asm volatile("" : "+v"(g0), "+v"(g1), "+v"(g2));
+                uint32_t amb = 0u;
+#pragma unroll 1
+                for (int u = 0; u < 32; ++u)
+                    if (__float_as_uint(d2_minus(wp[u], g0, g1, g2, in_lim)) <= band_u) amb |= 1u << u;
+                amb &= keep;
+                while (amb) {
+                    const int u = __builtin_ctz(amb);
+                    amb &= amb - 1u;
+                    const int64_t j = window_global<D>(w, tb + u);
+                    if (within_exact(pos[j] - xi0, pos[n + j] - xi1, D == 3 ? pos[2 * n + j] - xi2 : 0.0, R2))
+                        bits |= 1u << u;
+                }
             }
             bm[k][pl] = bits;
             cnt += __popc(bits);

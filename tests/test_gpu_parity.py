@@ -56,6 +56,26 @@ def test_neighbor_lists_bit_exact(family):
     assert np.array_equal(col, ocol)
 
 
+@pytest.mark.parametrize("dim", [2, 3])
+def test_neighbor_lists_on_an_unjittered_lattice(dim):
+    """On a lattice with R = 3 spacings many pairs lie at the support radius
+    up to rounding: the FP32 test leaves them in its uncertain band and the
+    FP64 predicate (strict <) decides each, as the brute force does."""
+    m = 48 if dim == 2 else 16
+    h = 1.0 / m
+    axes = [(np.arange(m) + 0.5) * h] * dim
+    pos = np.stack([a.ravel() for a in np.meshgrid(*axes, indexing="ij")])
+    vol = np.full(pos.shape[1], h ** dim)
+    g = vct.Geometry(pos, vol, (0.0,) * dim, (1.0,) * dim, 3 * h, device=DEV)
+    rp, col = g.csr_original()
+    orp, ocol = O.neighbors(pos, 3 * h, brute=True)
+    assert np.array_equal(rp, orp)
+    assert np.array_equal(col, ocol)
+    # interior rows hold the lattice points strictly inside the radius (24 in
+    # 2-D, 92 in 3-D); in 2-D rounding puts some on-radius pairs inside
+    assert (np.diff(rp) == (24 if dim == 2 else 92)).any()
+
+
 @pytest.mark.parametrize("family", FAMILIES)
 def test_staged_search_equals_fill_pass(family):
     """The one-search path (rows staged, then compacted) writes the same
