@@ -12,7 +12,9 @@ are held fixed, so theta enters only through the mapping coefficients.
 With recompute=True the per-particle state (moment matrices, folded
 operators) is dropped after the forward and recomputed by vct_moments in the
 backward, which runs the same kernels on the same inputs and so gives the
-same bits as keeping it.
+same bits as keeping it.  With recompute="solve" only the moment sums are
+kept (41 values per particle in 3-D instead of the 126 of the state) and the
+backward runs the solve alone (vct_moments_resolve), again with the same bits.
 """
 from __future__ import annotations
 
@@ -52,6 +54,7 @@ class VctLaplacian(torch.autograd.Function):
         ctx.nbase = len(base_map.terms)
         ctx.theta_meta = (theta.dtype, theta.device)
         ctx.state = None if recompute else geom.state64
+        ctx.ws = geom.ws_mom if recompute == "solve" else None
         if recompute:
             geom.state64 = None
         ctx.save_for_backward(phi)
@@ -61,7 +64,11 @@ class VctLaplacian(torch.autograd.Function):
     def backward(ctx, grad_lap):
         (phi,) = ctx.saved_tensors
         g = ctx.geom
-        if ctx.recompute:
+        if ctx.recompute == "solve":
+            st = g.resolve(ctx.spec, ADJ_MASK, ws=ctx.ws)
+            if st < 0:
+                raise vct.VctError("vct_moments_resolve", st)
+        elif ctx.recompute:
             st = g.moments(ctx.spec, ADJ_MASK)
             if st < 0:
                 raise vct.VctError("vct_moments", st)

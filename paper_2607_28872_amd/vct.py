@@ -372,11 +372,13 @@ class Geometry:
         self.n_flagged = nflag
         return st
 
-    def resolve(self, mapspec, mask=VCT_OUT_DEFAULT, fp32_copy=False, count_flagged=True, fp64=True):
+    def resolve(self, mapspec, mask=VCT_OUT_DEFAULT, fp32_copy=False, count_flagged=True, fp64=True, ws=None):
         """The state for another mask or map, solved from the moment sums the
-        last moments() call kept in its workspace (no sweep over the rows)."""
+        last moments() call kept in its workspace (or in `ws`, the workspace of
+        an earlier call on this geometry); no sweep over the rows."""
         import torch
-        if getattr(self, "ws_mom", None) is None:
+        ws = ws if ws is not None else getattr(self, "ws_mom", None)
+        if ws is None:
             raise ValueError("resolve() needs an earlier moments() call")
         n, dim = self.n, self.dim
         stride = vct_state_stride(dim, mask)
@@ -386,7 +388,7 @@ class Geometry:
         self.state32 = torch.empty((stride, max(n, 1)), dtype=torch.float32, device=self.device) if fp32_copy else None
         self.flags = torch.empty(max(n, 1), dtype=torch.uint8, device=self.device)
         st, nflag = vct_moments_resolve(self.nl, self.pos, self.cmap, mask, self.state64, self.state32, self.flags,
-                                        count_flagged, self.ws_mom)
+                                        count_flagged, ws)
         self.n_flagged = nflag
         return st
 

@@ -1,8 +1,9 @@
 """Adjoint of the Laplacian loss on the full 2.1M-particle sigma-SPH set with 16
 bathymetry coefficients, through the torch.autograd bridge.
 
-  * backward with the state recomputed equals backward with the state kept,
-    bit for bit (the same kernels on the same inputs);
+  * backward with the state recomputed, or solved again from the kept moment
+    sums, equals backward with the state kept, bit for bit (the same kernels
+    on the same inputs);
   * d/dphi along a seeded direction and d/dtheta for each coefficient against
     central differences with step 1e-6, within 1e-6 relative.  The loss is
     quadratic in phi, and the difference of squares is formed as
@@ -59,6 +60,15 @@ def _dloss(c, lp, lm):
 def test_recomputed_state_gives_the_same_bits(c4):
     gp1, gt1 = _grads(c4, True)
     gp2, gt2 = _grads(c4, False)
+    assert torch.equal(gp1, gp2)
+    assert torch.equal(gt1, gt2)
+
+
+def test_resolved_state_gives_the_same_bits(c4):
+    """Backward from the kept moment sums (solve only) equals backward with
+    the whole state recomputed."""
+    gp1, gt1 = _grads(c4, True)
+    gp2, gt2 = _grads(c4, "solve")
     assert torch.equal(gp1, gp2)
     assert torch.equal(gt1, gt2)
 
