@@ -244,17 +244,40 @@ __global__ __launch_bounds__(kAThreads, VCT_DPHI_GROUPS) void k_adjoint_dphi(Adj
     constexpr int kRec = 11;   // double2 per record: (x, y), (z, V), the packed record, one pad
     __shared__ double2 srec[kASub * kRec];
     __shared__ WindowT<D> w;
+    __shared__ double sx[kChunk];
+    __shared__ int sord[kChunk];
     const uint32_t b = xcd_tile(blockIdx.x, gridDim.x);
     if (b >= *A.nchunks) return;   // uniform over the work-group
     const int64_t n = A.n;
     const int64_t p0 = A.cstart[b], p1 = A.cstart[b + 1];
+    const int np = (int)(p1 - p0);
     if (threadIdx.x < kWave) {
         if (A.cwin) window_load<D>(A.cwin, b, w);
         else chunk_window_wave<D>(A.g, A.cs, A.cinfo[b], w);
+    } else if (threadIdx.x < 2 * kWave) {
+        const int q = threadIdx.x - kWave;
+        if (q < np) sx[q] = A.pos[p0 + q];
     }
+    __syncthreads();
+    // The waves take the chunk's particles in order of x: a sub-window holds
+    // about one x-layer of the window's columns, so particles with close x
+    // have similar shares of their rows in it, and the cursor loops of a wave
+    // end together (ties by index).
+    if (threadIdx.x < kChunk && (int)threadIdx.x < np) {
+        const int q = threadIdx.x;
+        const double xq = sx[q];
+        int r = 0;
+        for (int j = 0; j < np; ++j) {
+            const double xj = sx[j];
+            r += (xj < xq || (xj == xq && j < q)) ? 1 : 0;
+        }
+        sord[r] = q;
+    }
+    __syncthreads();
     const int lane = threadIdx.x % kALanes;
-    const int64_t k = p0 + threadIdx.x / kALanes;
-    const bool valid = k < p1;
+    const int slot = threadIdx.x / kALanes;
+    const bool valid = slot < np;
+    const int64_t k = p0 + (valid ? sord[slot] : 0);
     const int64_t kk = valid ? k : p0;
     double xk[3];
 #pragma unroll
@@ -269,7 +292,6 @@ __global__ __launch_bounds__(kAThreads, VCT_DPHI_GROUPS) void k_adjoint_dphi(Adj
     const int64_t re = valid ? A.row_ptr[kk + 1] : 0;
     int64_t e = (valid ? A.row_ptr[kk] : 0) + lane;
     int tn = e < re ? (int)A.col16[e] : INT_MAX;
-    __syncthreads();
     const int W = __builtin_amdgcn_readfirstlane(w.off[w.nr]);
     double acc1 = 0.0, self = 0.0;
     for (int s0 = 0; s0 < W; s0 += kASub) {
