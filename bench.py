@@ -156,7 +156,9 @@ def main():
     nterms = cmap.nterms
 
     fwd_mask = vct.VCT_OUT_DEFAULT
-    adj_mask = vct.VCT_OUT_LAP | vct.VCT_OUT_PGRAD | vct.VCT_OUT_PHESS
+    # the adjoint's rows: the Laplacian (for u) and the projected derivatives
+    # whose mapping coefficients depend on the bathymetry (for dtheta)
+    adj_mask = vct.VCT_OUT_LAP | vct.VCT_OUT_PZ
     n_out = vct.vct_n_out(dim, fwd_mask)
     stride_f = vct.vct_state_stride(dim, fwd_mask)
     stride_a = vct.vct_state_stride(dim, adj_mask)

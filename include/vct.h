@@ -78,6 +78,12 @@ enum { VCT_BASIS_ONE = 0, VCT_BASIS_LIN = 1, VCT_BASIS_COS = 2, VCT_BASIS_SIN = 
  *   HESS   physical Hessian             2-D: xx, zz, xz   3-D: xx, yy, zz, xy, xz, yz
  *   PGRAD  projected gradient           2-D: x^, z^       3-D: x^, y^, z^
  *   PHESS  projected second derivatives (same component order as HESS)
+ *   PZ     the projected derivatives whose coefficients in the physical
+ *          Laplacian depend on the mapping (Eq. lap_VCT)
+ *                                       2-D: z^, z^z^, x^z^
+ *                                       3-D: z^, z^z^, x^z^, y^z^
+ *          (the same values as those rows of PGRAD and PHESS; enough, with
+ *          LAP, for the adjoint's dtheta, at less than half their state)
  * VCT_OPT_GRAD1 makes every gradient (and the dz^ entering LAP, CROSS and HESS)
  * the first-order corrected one (Eq. gra_1st) instead of the second-order
  * gradient SPH(2) provides.                                                    */
@@ -88,6 +94,7 @@ enum {
     VCT_OUT_HESS = 1u << 3,
     VCT_OUT_PGRAD = 1u << 4,
     VCT_OUT_PHESS = 1u << 5,
+    VCT_OUT_PZ = 1u << 6,
     VCT_OPT_GRAD1 = 1u << 8
 };
 #define VCT_OUT_DEFAULT (VCT_OUT_GRAD | VCT_OUT_LAP | VCT_OUT_CROSS)
@@ -352,8 +359,9 @@ size_t vct_adjoint_workspace_size(int dim, int64_t n, int64_t nnz, int nterms);
  *     128-byte packed record of i (correction matrix and u_i times its
  *     Laplacian row), which it reads per neighbour.
  * dtheta: per particle from D^ phi_i, reduced in a fixed order.
- * `state64` must come from vct_moments with out_mask containing
- * VCT_OUT_LAP | VCT_OUT_PGRAD | VCT_OUT_PHESS (pass the same mask).
+ * `state64` must come from vct_moments with out_mask containing VCT_OUT_LAP
+ * and either VCT_OUT_PZ or both VCT_OUT_PGRAD and VCT_OUT_PHESS (pass the same
+ * mask).
  * `proj` [n][n_out] FP64 is the output of vct_apply_ops (nf = 1, VCT_FP64,
  * the same state and mask) for the field whose dtheta is wanted; it supplies
  * D^ phi and is needed only when dtheta is not NULL.  dphi [n] and

@@ -13,7 +13,7 @@ With recompute=True the per-particle state (moment matrices, folded
 operators) is dropped after the forward and recomputed by vct_moments in the
 backward, which runs the same kernels on the same inputs and so gives the
 same bits as keeping it.  With recompute="solve" only the moment sums are
-kept (41 values per particle in 3-D instead of the 126 of the state) and the
+kept (41 values per particle in 3-D instead of the 66 of the state) and the
 backward runs the solve alone (vct_moments_resolve), again with the same bits.
 """
 from __future__ import annotations
@@ -23,7 +23,8 @@ import torch
 
 from . import vct
 
-ADJ_MASK = vct.VCT_OUT_LAP | vct.VCT_OUT_PGRAD | vct.VCT_OUT_PHESS
+# the Laplacian and the projected derivatives its mapping coefficients multiply
+ADJ_MASK = vct.VCT_OUT_LAP | vct.VCT_OUT_PZ
 
 # perturbation basis of the bathymetry: (basis kind, frequency)
 _B_ONE, _B_COS, _B_SIN = 0, 2, 3

@@ -49,7 +49,8 @@ struct AdjArgs {
     const int4* cinfo;
     const int32_t* cwin;   // stored windows or NULL
     const int64_t* nchunks;
-    int lap_row, pg_row, ph_row, nrows;
+    int lap_row, nrows;
+    int r_gz, r_zz, r_xz, r_yz;   // rows of dz^, z^z^, x^z^, y^z^ (-1 in 2-D) in proj
     const double* coef;   // [n][kCoef] packed records of the gather form
     double* wbuf;      // [nnz]: u_i W_ij at the transposed position
     double* rowsum;    // [n]:  u_i sum_j W_ij
@@ -385,10 +386,10 @@ __global__ __launch_bounds__(256) void k_adjoint_xi(AdjArgs A, MapParams mp) {
     if (i >= n) return;
     const double* pr = A.proj + i * A.nrows;
     // projected derivatives needed by c_trans: dz^, zz, xz, (yz)
-    const double gz = pr[A.pg_row + D - 1];
-    const double Hzz = (D == 3) ? pr[A.ph_row + 2] : pr[A.ph_row + 1];
-    const double Hxz = (D == 3) ? pr[A.ph_row + 4] : pr[A.ph_row + 2];
-    const double Hyz = (D == 3) ? pr[A.ph_row + 5] : 0.0;
+    const double gz = pr[A.r_gz];
+    const double Hzz = pr[A.r_zz];
+    const double Hxz = pr[A.r_xz];
+    const double Hyz = (D == 3) ? pr[A.r_yz] : 0.0;
     double x[D];
 #pragma unroll
     for (int a = 0; a < D; ++a) x[a] = A.pos[a * n + i];
@@ -508,13 +509,15 @@ extern "C" int vct_apply_ops_adjoint(const vct_nlist* nl, const double* pos_sort
                                      int kernel, const double* state64, uint32_t out_mask, const vct_map* map,
                                      const double* proj, const double* u, double* dphi, double* dtheta, void* ws,
                                      size_t ws_bytes, void* stream) {
-    const uint32_t need = VCT_OUT_LAP | VCT_OUT_PGRAD | VCT_OUT_PHESS;
+    // the Laplacian row, and dz^, z^z^, x^z^ (y^z^) from PZ or from PGRAD + PHESS
+    const bool pz = (out_mask & VCT_OUT_PZ) != 0;
+    const bool pgh = (out_mask & (VCT_OUT_PGRAD | VCT_OUT_PHESS)) == (VCT_OUT_PGRAD | VCT_OUT_PHESS);
     Grid g;
     int st = nlist_check(nl, g);
     if (st) return st;
     const int dim = nl->dim;
     const int64_t n = nl->n;
-    if (!map || !mask_valid(out_mask) || (out_mask & need) != need ||
+    if (!map || !mask_valid(out_mask) || !(out_mask & VCT_OUT_LAP) || !(pz || pgh) ||
         (kernel != VCT_KERNEL_WENDLAND_C2 && kernel != VCT_KERNEL_CUBIC_SPLINE))
         return VCT_E_ARG;
     MapParams mp;
@@ -548,8 +551,16 @@ extern "C" int vct_apply_ops_adjoint(const vct_nlist* nl, const double* pos_sort
     a.cwin = nl->chunk_win;
     a.nchunks = nl->chunk_off + ncols;
     a.lap_row = group_row(dim, out_mask, VCT_OUT_LAP);
-    a.pg_row = group_row(dim, out_mask, VCT_OUT_PGRAD);
-    a.ph_row = group_row(dim, out_mask, VCT_OUT_PHESS);
+    if (pz) {
+        const int r = group_row(dim, out_mask, VCT_OUT_PZ);
+        a.r_gz = r, a.r_zz = r + 1, a.r_xz = r + 2, a.r_yz = dim == 3 ? r + 3 : -1;
+    } else {   // PHESS component order: 3-D xx, yy, zz, xy, xz, yz; 2-D xx, zz, xz
+        const int rg = group_row(dim, out_mask, VCT_OUT_PGRAD), rh = group_row(dim, out_mask, VCT_OUT_PHESS);
+        a.r_gz = rg + dim - 1;
+        a.r_zz = dim == 3 ? rh + 2 : rh + 1;
+        a.r_xz = dim == 3 ? rh + 4 : rh + 2;
+        a.r_yz = dim == 3 ? rh + 5 : -1;
+    }
     a.nrows = n_out_rows(dim, out_mask);
     a.wbuf = wbuf; a.rowsum = rowsum; a.coef = coef; a.dphi = dphi; a.xi = xi;
     const int64_t cap = ncols + n / kChunk + 1;

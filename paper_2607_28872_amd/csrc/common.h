@@ -298,12 +298,13 @@ inline int n_out_rows(int dim, uint32_t mask) {
     if (mask & VCT_OUT_HESS) n += m;
     if (mask & VCT_OUT_PGRAD) n += d;
     if (mask & VCT_OUT_PHESS) n += m;
+    if (mask & VCT_OUT_PZ) n += d + 1;
     return n;
 }
 
 inline bool mask_valid(uint32_t mask) {
     const uint32_t outs = VCT_OUT_GRAD | VCT_OUT_LAP | VCT_OUT_CROSS | VCT_OUT_HESS | VCT_OUT_PGRAD |
-                          VCT_OUT_PHESS;
+                          VCT_OUT_PHESS | VCT_OUT_PZ;
     return (mask & outs) != 0 && (mask & ~(outs | VCT_OPT_GRAD1)) == 0;
 }
 
@@ -311,8 +312,8 @@ inline bool mask_valid(uint32_t mask) {
 inline int group_row(int dim, uint32_t mask, uint32_t group) {
     if (!(mask & group)) return -1;
     int row = 0;
-    const uint32_t order[6] = {VCT_OUT_GRAD, VCT_OUT_LAP, VCT_OUT_CROSS, VCT_OUT_HESS, VCT_OUT_PGRAD,
-                               VCT_OUT_PHESS};
+    const uint32_t order[7] = {VCT_OUT_GRAD, VCT_OUT_LAP, VCT_OUT_CROSS, VCT_OUT_HESS, VCT_OUT_PGRAD,
+                               VCT_OUT_PHESS, VCT_OUT_PZ};
     for (uint32_t g : order) {
         if (g == group) return row;
         if (mask & g) row += n_out_rows(dim, g);

@@ -426,6 +426,7 @@ __device__ __forceinline__ int emit_rows(uint32_t mask, const MapCoef<double>& c
         }
         if (mask & VCT_OUT_PGRAD) { out(o++, pg[0]); out(o++, pg[1]); out(o++, pg[2]); }
         if (mask & VCT_OUT_PHESS) for (int p = 0; p < 6; ++p) out(o++, ph[p]);
+        if (mask & VCT_OUT_PZ) { out(o++, gz); out(o++, Hzz); out(o++, Hxz); out(o++, Hyz); }
     } else {
         const double gz = pg[1];
         const double Hxx = ph[0], Hzz = ph[1], Hxz = ph[2];
@@ -440,6 +441,7 @@ __device__ __forceinline__ int emit_rows(uint32_t mask, const MapCoef<double>& c
         }
         if (mask & VCT_OUT_PGRAD) { out(o++, pg[0]); out(o++, pg[1]); }
         if (mask & VCT_OUT_PHESS) for (int p = 0; p < 3; ++p) out(o++, ph[p]);
+        if (mask & VCT_OUT_PZ) { out(o++, gz); out(o++, Hzz); out(o++, Hxz); }
     }
     return o;
 }

@@ -24,6 +24,7 @@ VCT_E_ARG, VCT_E_HIP, VCT_E_CAPACITY, VCT_E_NONFINITE, VCT_E_WORKSPACE, VCT_E_WI
 VCT_KERNEL_WENDLAND_C2, VCT_KERNEL_CUBIC_SPLINE = 0, 1
 VCT_FP64, VCT_MIXED, VCT_MIXED_S64 = 0, 1, 2
 VCT_OUT_GRAD, VCT_OUT_LAP, VCT_OUT_CROSS, VCT_OUT_HESS, VCT_OUT_PGRAD, VCT_OUT_PHESS = 1, 2, 4, 8, 16, 32
+VCT_OUT_PZ = 64
 VCT_OPT_GRAD1 = 256
 VCT_OUT_DEFAULT = VCT_OUT_GRAD | VCT_OUT_LAP | VCT_OUT_CROSS
 VCT_MAX_TERMS = 32

@@ -12,7 +12,7 @@ EXT_KAPPA = 1e-13        # GPU vs extended precision, per unit of kappa_i
 ORC_KAPPA = 1e-11        # GPU vs FP64 oracle (the oracle's own rounding dominates)
 
 ALL_OUT = (vct.VCT_OUT_GRAD | vct.VCT_OUT_LAP | vct.VCT_OUT_CROSS | vct.VCT_OUT_HESS | vct.VCT_OUT_PGRAD
-           | vct.VCT_OUT_PHESS)
+           | vct.VCT_OUT_PHESS | vct.VCT_OUT_PZ)
 
 
 def oracle_rows(rec, dim, mask):
@@ -27,6 +27,7 @@ def oracle_rows(rec, dim, mask):
             (vct.VCT_OUT_HESS, [7, 8, 9, 10, 11, 12], [1] * 6),
             (vct.VCT_OUT_PGRAD, [13, 14, 15] if g1 else [16, 17, 18], [1, 1, 1]),
             (vct.VCT_OUT_PHESS, [19, 20, 21, 22, 23, 24], [1, 1, 1, 0.5, 0.5, 0.5]),
+            (vct.VCT_OUT_PZ, [15 if g1 else 18, 21, 23, 24], [1, 1, 0.5, 0.5]),
         ]
     else:
         groups = [
@@ -36,6 +37,7 @@ def oracle_rows(rec, dim, mask):
             (vct.VCT_OUT_HESS, [7, 9, 11], [1, 1, 1]),
             (vct.VCT_OUT_PGRAD, [13, 15] if g1 else [16, 18], [1, 1]),
             (vct.VCT_OUT_PHESS, [19, 21, 23], [1, 1, 0.5]),
+            (vct.VCT_OUT_PZ, [15 if g1 else 18, 21, 23], [1, 1, 0.5]),
         ]
     for bit, c, s in groups:
         if mask & bit:
@@ -52,11 +54,12 @@ def row_names(dim, mask):
                  (vct.VCT_OUT_CROSS, ["xy", "xz", "yz"]),
                  (vct.VCT_OUT_HESS, ["Hxx", "Hyy", "Hzz", "Hxy", "Hxz", "Hyz"]),
                  (vct.VCT_OUT_PGRAD, ["pgx", "pgy", "pgz"]),
-                 (vct.VCT_OUT_PHESS, ["pxx", "pyy", "pzz", "pxy", "pxz", "pyz"])]
+                 (vct.VCT_OUT_PHESS, ["pxx", "pyy", "pzz", "pxy", "pxz", "pyz"]),
+                 (vct.VCT_OUT_PZ, ["zgz", "zzz", "zxz", "zyz"])]
     else:
         table = [(vct.VCT_OUT_GRAD, ["gx", "gz"]), (vct.VCT_OUT_LAP, ["lap"]), (vct.VCT_OUT_CROSS, ["xz"]),
                  (vct.VCT_OUT_HESS, ["Hxx", "Hzz", "Hxz"]), (vct.VCT_OUT_PGRAD, ["pgx", "pgz"]),
-                 (vct.VCT_OUT_PHESS, ["pxx", "pzz", "pxz"])]
+                 (vct.VCT_OUT_PHESS, ["pxx", "pzz", "pxz"]), (vct.VCT_OUT_PZ, ["zgz", "zzz", "zxz"])]
     for bit, nm in table:
         if mask & bit:
             names += nm

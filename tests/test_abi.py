@@ -44,6 +44,9 @@ def test_layout_queries(L):
     assert vct.vct_state_stride(2, vct.VCT_OUT_DEFAULT) == 3 + 4 * (5 + 2)
     full = 63
     assert vct.vct_n_out(3, full) == 3 + 1 + 3 + 6 + 3 + 6
+    assert vct.vct_n_out(3, full | vct.VCT_OUT_PZ) == 3 + 1 + 3 + 6 + 3 + 6 + 4
+    assert vct.vct_n_out(2, vct.VCT_OUT_PZ) == 3
+    assert vct.vct_state_stride(3, vct.VCT_OUT_LAP | vct.VCT_OUT_PZ) == 6 + 5 * (9 + 3)
     assert vct.vct_n_out(3, 0) == 0 and vct.vct_n_out(4, 1) == 0
     assert vct.vct_n_out(3, 1 << 12) == 0
 
@@ -122,9 +125,11 @@ def test_argument_errors_are_caught_on_the_host(L):
     assert L.vct_apply_ops(C.byref(nl), 0, None, None, None, 0, None, 3, 0, None, None) == E   # nf
     assert L.vct_apply_ops(C.byref(nl), 1, None, None, None, 0, None, 3, 5, None, None) == E   # precision
     assert L.vct_apply_ops(C.byref(nl), 1, None, None, None, 0, None, 3, 0, None, None) == E   # null arrays
-    # the adjoint needs LAP | PGRAD | PHESS rows in the state
-    assert L.vct_apply_ops_adjoint(C.byref(nl), None, None, 0, None, vct.VCT_OUT_DEFAULT, C.byref(m), None, None,
-                                   None, None, None, 0, None) == E
+    # the adjoint needs the LAP rows and either PZ or PGRAD + PHESS in the state
+    for mask in (vct.VCT_OUT_DEFAULT, vct.VCT_OUT_PZ, vct.VCT_OUT_LAP | vct.VCT_OUT_PGRAD,
+                 vct.VCT_OUT_LAP | vct.VCT_OUT_PHESS):
+        assert L.vct_apply_ops_adjoint(C.byref(nl), None, None, 0, None, mask, C.byref(m), None, None,
+                                       None, None, None, 0, None) == E
 
 
 def test_workspace_errors(L):

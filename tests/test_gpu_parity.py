@@ -260,6 +260,37 @@ def test_resolve_from_kept_sums_gives_the_same_bits(family):
     assert torch.equal(g.state32.view(torch.int32), s32.view(torch.int32))
 
 
+@pytest.mark.parametrize("family", ["bf2d", "sigma3d"])
+def test_pz_rows_equal_the_projected_rows(family):
+    """The PZ group repeats rows of PGRAD and PHESS: the same state
+    coefficients, so the same bits in both precisions."""
+    w = I.small(family)
+    g = _geom(w)
+    mask = vct.VCT_OUT_PGRAD | vct.VCT_OUT_PHESS | vct.VCT_OUT_PZ
+    g.moments(w.mapspec, mask, fp32_copy=True)
+    d = w.dim
+    # dz^ is the last PGRAD row; zz, xz (, yz) of PHESS follow its component order
+    same = [d - 1] + ([d + 2, d + 4, d + 5] if d == 3 else [d + 1, d + 2])
+    npz = d + 1
+    for prec in (vct.VCT_FP64, vct.VCT_MIXED):
+        out = g.apply(g.sorted_field(w.phi), prec)[:, : g.n]
+        assert torch.equal(out[..., -npz:], out[..., same])
+
+
+def test_adjoint_with_pz_rows_gives_the_same_bits():
+    w = I.small("sigma3d-adj")
+    res = []
+    for mask in (vct.VCT_OUT_LAP | vct.VCT_OUT_PGRAD | vct.VCT_OUT_PHESS, vct.VCT_OUT_LAP | vct.VCT_OUT_PZ):
+        g = vct.Geometry(w.pos, w.vol, w.lo, w.hi, w.R, w.kernel, device=DEV)
+        g.moments(w.mapspec, mask)
+        phi = g.sorted_field(w.phi[0])
+        proj = g.apply(phi, vct.VCT_FP64)
+        u = 2.0 * (proj[0, : g.n, 0] - g.sorted_field(w.extra["target"])[0])
+        res.append(g.adjoint(u, proj))
+    assert torch.equal(res[0][0], res[1][0])
+    assert torch.equal(res[0][1], res[1][1])
+
+
 @pytest.mark.parametrize("form", ["transposed", "gather"])
 def test_adjoint_against_oracle(form):
     w = I.small("sigma3d-adj")
