@@ -306,8 +306,8 @@ size_t vct_moments_workspace_size(int dim, int64_t n);
 /* The solve and fold of vct_moments alone, from the moment sums that the last
  * vct_moments call left in `ws`.  The sums depend only on the neighbour list,
  * positions, volumes, kernel and R, not on `map` or `out_mask`, so a second
- * state for other outputs or another map (the Laplacian and projected rows of
- * an adjoint after a forward that wrote the default outputs, say) costs one
+ * state for other outputs or another map (the LAP and PZ rows of an adjoint
+ * after a forward that wrote the default outputs, say) costs one
  * solve instead of two sweeps over the rows.  `ws` must come from a
  * vct_moments call on the same nl, pos_sorted and vol_sorted, ordered before
  * this one on the stream, and must not be used by another call in between;
@@ -359,12 +359,14 @@ size_t vct_adjoint_workspace_size(int dim, int64_t n, int64_t nnz, int nterms);
  *     128-byte packed record of i (correction matrix and u_i times its
  *     Laplacian row), which it reads per neighbour.
  * dtheta: per particle from D^ phi_i, reduced in a fixed order.
- * `state64` must come from vct_moments with out_mask containing VCT_OUT_LAP
+ * `state64` must come from vct_moments (or vct_moments_resolve) with out_mask
+ * containing VCT_OUT_LAP
  * and either VCT_OUT_PZ or both VCT_OUT_PGRAD and VCT_OUT_PHESS (pass the same
  * mask).
  * `proj` [n][n_out] FP64 is the output of vct_apply_ops (nf = 1, VCT_FP64,
  * the same state and mask) for the field whose dtheta is wanted; it supplies
- * D^ phi and is needed only when dtheta is not NULL.  dphi [n] and
+ * the projected derivatives that c_trans weights (dz^, z^z^, x^z^, y^z^) and
+ * is needed only when dtheta is not NULL.  dphi [n] and
  * dtheta [map->nterms] are device outputs; either may be NULL.  The workspace
  * holds nnz + 7 n doubles and the reduction partials
  * (vct_adjoint_workspace_size, with nnz = nl->nnz).                            */
