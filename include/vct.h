@@ -360,9 +360,8 @@ size_t vct_adjoint_workspace_size(int dim, int64_t n, int64_t nnz, int nterms);
  *     Laplacian row), which it reads per neighbour.
  * dtheta: per particle from D^ phi_i, reduced in a fixed order.
  * `state64` must come from vct_moments (or vct_moments_resolve) with out_mask
- * containing VCT_OUT_LAP
- * and either VCT_OUT_PZ or both VCT_OUT_PGRAD and VCT_OUT_PHESS (pass the same
- * mask).
+ * containing VCT_OUT_LAP and either VCT_OUT_PZ or both VCT_OUT_PGRAD and
+ * VCT_OUT_PHESS (pass the same mask).
  * `proj` [n][n_out] FP64 is the output of vct_apply_ops (nf = 1, VCT_FP64,
  * the same state and mask) for the field whose dtheta is wanted; it supplies
  * the projected derivatives that c_trans weights (dz^, z^z^, x^z^, y^z^) and
