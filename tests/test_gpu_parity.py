@@ -119,6 +119,30 @@ def test_long_rows_fall_back_to_the_fill_pass():
     assert np.array_equal(col, ocol)
 
 
+def test_windows_beyond_the_lds_capacity():
+    """With R = 4.2 spacings some chunk windows exceed what the moment and
+    apply kernels stage in LDS (1,400 and 1,664 records): those chunks take the
+    paths that read the records from the memory hierarchy, with the same
+    results."""
+    w = I.small("sigma3d")
+    R = 1.4 * w.R
+    g = _geom(w, R=R)
+    win = g.chunk_win.cpu().numpy()
+    nch = int(g.chunk_off[-1].item())
+    sizes = win[np.arange(nch), 20 + win[:nch, 0]]
+    assert sizes.max() > 1664 and sizes.min() <= 1400   # both paths run
+    mask = vct.VCT_OUT_DEFAULT | vct.VCT_OUT_PZ
+    g.moments(w.mapspec, mask, fp32_copy=True)
+    rec, _ = O.sph2(w.pos, w.vol, w.phi, w.kernel, R, w.mapspec)
+    ref = oracle_rows(rec, w.dim, mask)
+    e64 = normwise(_gpu_out(g, w.phi, vct.VCT_FP64), ref)
+    e32 = normwise(_gpu_out(g, w.phi, vct.VCT_MIXED), ref)
+    print(f"\nwindows up to {sizes.max()} records: FP64 {e64.max():.2e}, mixed grad {e32[:, :3].max():.2e} "
+          f"other {e32[:, 3:].max():.2e}")
+    assert e64.max() <= 1e-11
+    assert e32[:, :3].max() <= 1e-5 and e32[:, 3:].max() <= 1e-4
+
+
 @pytest.mark.parametrize("family", FAMILIES)
 @pytest.mark.parametrize("kernel", [I.KERNEL_WENDLAND_C2, I.KERNEL_CUBIC_SPLINE])
 def test_fp64_parity_all_outputs(family, kernel):
