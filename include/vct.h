@@ -367,7 +367,7 @@ size_t vct_adjoint_workspace_size(int dim, int64_t n, int64_t nnz, int nterms);
  * the projected derivatives that c_trans weights (dz^, z^z^, x^z^, y^z^) and
  * is needed only when dtheta is not NULL.  dphi [n] and
  * dtheta [map->nterms] are device outputs; either may be NULL.  The workspace
- * holds nnz + 7 n doubles and the reduction partials
+ * holds nnz + 17 n doubles and the reduction partials
  * (vct_adjoint_workspace_size, with nnz = nl->nnz).                            */
 int vct_apply_ops_adjoint(const vct_nlist* nl, const double* pos_sorted, const double* vol_sorted, int kernel,
                           const double* state64, uint32_t out_mask, const vct_map* map /* host */,

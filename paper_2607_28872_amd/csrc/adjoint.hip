@@ -55,7 +55,6 @@ struct AdjArgs {
     double* wbuf;      // [nnz]: u_i W_ij at the transposed position
     double* rowsum;    // [n]:  u_i sum_j W_ij
     double* dphi;
-    double* xi;
 };
 
 // Pass 1: u_i W_ij for every entry of row i, written transposed.  The first
@@ -377,67 +376,98 @@ __global__ __launch_bounds__(256) void k_adjoint_gather(int64_t n, const int64_t
     if (valid && lane == 0) dphi[k] = s - rowsum[k];
 }
 
-// Per particle: D^ phi from the projected rows of the forward apply, then
-// xi_k = u_i * d(c_trans . D^)/d h^(k) for the six bottom quantities.
-template <int D>
-__global__ __launch_bounds__(256) void k_adjoint_xi(AdjArgs A, MapParams mp) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t n = A.n;
-    if (i >= n) return;
-    const double* pr = A.proj + i * A.nrows;
-    // projected derivatives needed by c_trans: dz^, zz, xz, (yz)
-    const double gz = pr[A.r_gz];
-    const double Hzz = pr[A.r_zz];
-    const double Hxz = pr[A.r_xz];
-    const double Hyz = (D == 3) ? pr[A.r_yz] : 0.0;
-    double x[D];
-#pragma unroll
-    for (int a = 0; a < D; ++a) x[a] = A.pos[a * n + i];
-    double h[6];
-    bottom6(mp, x[0], D == 3 ? x[1] : 0.0, h);
-    Dual6 hd[6];
-#pragma unroll
-    for (int q = 0; q < 6; ++q) {
-        hd[q] = Dual6(h[q]);
-        hd[q].d[q] = 1.0;
-    }
-    const MapCoef<Dual6> mc = map_coef<Dual6>(mp, hd, x[D - 1]);
-    const double ui = A.u[i];
-#pragma unroll
-    for (int q = 0; q < 6; ++q)
-        A.xi[(int64_t)q * n + i] = ui * (mc.c0.d[q] * gz + mc.c3.d[q] * Hzz + mc.c4.d[q] * Hxz + mc.c5.d[q] * Hyz);
-}
-
 constexpr int kRedThreads = 256;
 
-__global__ __launch_bounds__(kRedThreads) void k_dtheta_partials(int64_t n, const double* __restrict__ pos,
-                                                                  int dim, MapParams mp,
-                                                                  const double* __restrict__ xi,
+// dtheta, first level.  Per particle (one thread): the projected derivatives
+// that c_trans weights, from the rows of the forward apply, then
+// xi_q = u_i d(c_trans . D^)/d h^(q) for the six bottom quantities h^ (dual
+// numbers through the mapping coefficients), and for every bathymetry term t
+// the contribution sum_q xi_q dh^(q)/dcoef_t.  With the separable table the
+// terms' factor products come from the factors evaluated once per particle,
+// one sum per factor pair (X_a, Y_b) that some term uses; otherwise term by
+// term.  Each sum is taken over a wave (fixed lane order), the waves' sums in
+// wave order: one partial per work-group and term.
+template <int D>
+__global__ __launch_bounds__(kRedThreads) void k_dtheta_partials(AdjArgs A, MapParams mp,
                                                                   double* __restrict__ partials) {
-    __shared__ double red[kRedThreads];
+    constexpr int kW = kRedThreads / kWave;
+    constexpr int kSlots = kMapFn * kMapFn > VCT_MAX_TERMS ? kMapFn * kMapFn : VCT_MAX_TERMS;
+    __shared__ double red[kW][kSlots];
+    const int64_t n = A.n;
     const int64_t i = (int64_t)blockIdx.x * kRedThreads + threadIdx.x;
-    double xv[6] = {0, 0, 0, 0, 0, 0};
-    double x = 0.0, y = 0.0;
-    if (i < n) {
-        for (int q = 0; q < 6; ++q) xv[q] = xi[(int64_t)q * n + i];
-        x = pos[i];
-        y = (dim == 3) ? pos[n + i] : 0.0;
+    const bool valid = i < n;
+    double x[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) x[a] = valid ? A.pos[a * n + i] : 0.0;
+    const double xs = x[0], ys = D == 3 ? x[1] : 0.0;
+    SepFactors F;
+    double h[6];
+    if (mp.sep) {
+        sep_table(mp, xs, ys, F);
+        bottom6_sep(mp, F, h);
+    } else {
+        bottom6(mp, xs, ys, h);
     }
-    for (int t = 0; t < mp.nterms; ++t) {
+    double xv[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (valid) {
+        const double* pr = A.proj + i * A.nrows;
+        const double gz = pr[A.r_gz];
+        const double Hzz = pr[A.r_zz];
+        const double Hxz = pr[A.r_xz];
+        const double Hyz = (D == 3) ? pr[A.r_yz] : 0.0;
+        Dual6 hd[6];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            hd[q] = Dual6(h[q]);
+            hd[q].d[q] = 1.0;
+        }
+        const MapCoef<Dual6> mc = map_coef<Dual6>(mp, hd, x[D - 1]);
+        const double ui = A.u[i];
+#pragma unroll
+        for (int q = 0; q < 6; ++q)
+            xv[q] = ui * (mc.c0.d[q] * gz + mc.c3.d[q] * Hzz + mc.c4.d[q] * Hxz + mc.c5.d[q] * Hyz);
+    }
+    const int wv = threadIdx.x / kWave;
+    const bool lead = threadIdx.x % kWave == 0;
+    // uniform loops: every lane takes part in the wave sums
+    if (mp.sep) {
+#pragma unroll
+        for (int a = 0; a < kMapFn; ++a) {
+            if (a >= mp.nfx) break;
+#pragma unroll
+            for (int b = 0; b < kMapFn; ++b) {
+                if (b >= mp.nfy) break;
+                double v = xv[0] * (F.X0[a] * F.Y0[b]);
+                v += xv[1] * (F.X1[a] * F.Y0[b]);
+                v += xv[2] * (F.X0[a] * F.Y1[b]);
+                v += xv[3] * (F.X2[a] * F.Y0[b]);
+                v += xv[4] * (F.X1[a] * F.Y1[b]);
+                v += xv[5] * (F.X0[a] * F.Y2[b]);
+                v = group_sum(v, kWave);
+                if (lead) red[wv][a * kMapFn + b] = v;
+            }
+        }
+    } else {
+        for (int t = 0; t < mp.nterms; ++t) {
+            double v = 0.0;
+            if (valid) {
+                double o[6];
+                term_derivs(mp, t, xs, ys, o);
+#pragma unroll
+                for (int q = 0; q < 6; ++q) v += xv[q] * o[q];
+            }
+            v = group_sum(v, kWave);
+            if (lead) red[wv][t] = v;
+        }
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < mp.nterms) {
+        const int t = threadIdx.x;
+        const int slot = mp.sep ? mp.term_a[t] * kMapFn + mp.term_b[t] : t;
         double v = 0.0;
-        if (i < n) {
-            double o[6];
-            term_derivs(mp, t, x, y, o);
-            for (int q = 0; q < 6; ++q) v += xv[q] * o[q];
-        }
-        red[threadIdx.x] = v;
-        __syncthreads();
-        for (int s = kRedThreads / 2; s > 0; s >>= 1) {
-            if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) partials[(int64_t)blockIdx.x * mp.nterms + t] = red[0];
-        __syncthreads();
+#pragma unroll
+        for (int w = 0; w < kW; ++w) v += red[w][slot];
+        partials[(int64_t)blockIdx.x * mp.nterms + t] = v;
     }
 }
 
@@ -475,11 +505,9 @@ static int launch_adjoint(AdjArgs a, int64_t cap, const MapParams& mp, double* d
         VCT_LAUNCH_CHECK();
     }
     if (dtheta && mp.nterms > 0) {
-        VCT_LAUNCH("k_adjoint_xi", (k_adjoint_xi<D>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, mp);
-        VCT_LAUNCH_CHECK();
         const int64_t nred = (n + kRedThreads - 1) / kRedThreads;
-        VCT_LAUNCH("k_dtheta_partials", k_dtheta_partials, dim3((unsigned)nred), dim3(kRedThreads), 0, s, n, a.pos,
-                   D, mp, a.xi, partials);
+        VCT_LAUNCH("k_dtheta_partials", (k_dtheta_partials<D>), dim3((unsigned)nred), dim3(kRedThreads), 0, s, a,
+                   mp, partials);
         VCT_LAUNCH_CHECK();
         VCT_LAUNCH("k_dtheta_final", k_dtheta_final, dim3((unsigned)mp.nterms), dim3(kRedThreads), 0, s, nred,
                    mp.nterms, partials, dtheta);
@@ -500,7 +528,7 @@ using namespace vct;
 extern "C" size_t vct_adjoint_workspace_size(int dim, int64_t n, int64_t nnz, int nterms) {
     if ((dim != 2 && dim != 3) || n < 0 || nnz < 0 || nterms < 0) return 0;
     const int64_t nred = (n + kRedThreads - 1) / kRedThreads;
-    return aligned_sum({(size_t)n * 6 * sizeof(double), (size_t)(nred > 0 ? nred : 1) * (nterms > 0 ? nterms : 1) * 8,
+    return aligned_sum({(size_t)(nred > 0 ? nred : 1) * (nterms > 0 ? nterms : 1) * 8,
                         (size_t)(nnz > 0 ? nnz : 1) * sizeof(double), (size_t)(n > 0 ? n : 1) * sizeof(double),
                         (size_t)(n > 0 ? n : 1) * kCoef * sizeof(double)});
 }
@@ -537,7 +565,6 @@ extern "C" int vct_apply_ops_adjoint(const vct_nlist* nl, const double* pos_sort
     if (nnz < 0) return VCT_E_ARG;
     if (!ws || ws_bytes < vct_adjoint_workspace_size(dim, n, nnz, mp.nterms)) return VCT_E_WORKSPACE;
     Carver cv(ws, ws_bytes);
-    double* xi = cv.take<double>((size_t)n * 6);
     const int64_t nred = (n + kRedThreads - 1) / kRedThreads;
     double* partials = cv.take<double>((size_t)nred * (mp.nterms > 0 ? mp.nterms : 1));
     double* wbuf = cv.take<double>((size_t)(nnz > 0 ? nnz : 1));
@@ -562,7 +589,7 @@ extern "C" int vct_apply_ops_adjoint(const vct_nlist* nl, const double* pos_sort
         a.r_yz = dim == 3 ? rh + 5 : -1;
     }
     a.nrows = n_out_rows(dim, out_mask);
-    a.wbuf = wbuf; a.rowsum = rowsum; a.coef = coef; a.dphi = dphi; a.xi = xi;
+    a.wbuf = wbuf; a.rowsum = rowsum; a.coef = coef; a.dphi = dphi;
     const int64_t cap = ncols + n / kChunk + 1;
     if (dim == 2)
         st = (kernel == VCT_KERNEL_WENDLAND_C2)

@@ -55,6 +55,8 @@ static void build_separable(MapParams& p) {
             return;
         }
         p.cm[a][b] += p.coef[t];
+        p.term_a[t] = a;
+        p.term_b[t] = b;
     }
     p.sep = 1;
 }

@@ -35,6 +35,7 @@ struct MapParams {
     int32_t fx_kind[kMapFn], fx_q[kMapFn], fy_kind[kMapFn], fy_q[kMapFn];
     double qx[kMapFq], qy[kMapFq];
     double cm[kMapFn][kMapFn];
+    int32_t term_a[VCT_MAX_TERMS], term_b[VCT_MAX_TERMS];   // factors (X_a, Y_b) of every term
 };
 
 int map_params_from(const vct_map* m, int dim, MapParams& p);  // host, returns status
@@ -119,6 +120,27 @@ __device__ __forceinline__ void sep_table(const MapParams& mp, double x, double 
         sep_factor_values(a, mp.nfx, mp.fx_kind[a], mp.fx_q[a], qx, sx, cx, x, F.X0[a], F.X1[a], F.X2[a]);
         sep_factor_values(a, mp.nfy, mp.fy_kind[a], mp.fy_q[a], qy, sy, cy, y, F.Y0[a], F.Y1[a], F.Y2[a]);
         if (mp.dim == 2) F.Y1[a] = F.Y2[a] = 0.0;
+    }
+}
+
+// h, h_x, h_y, h_xx, h_xy, h_yy from the separable table's factors
+__device__ __forceinline__ void bottom6_sep(const MapParams& mp, const SepFactors& F, double h[6]) {
+    for (int k = 0; k < 6; ++k) h[k] = 0.0;
+#pragma unroll
+    for (int a = 0; a < kMapFn; ++a) {
+        double u0 = 0.0, u1 = 0.0, u2 = 0.0;   // sum_b cm[a][b] (Y_b, Y_b', Y_b'')
+#pragma unroll
+        for (int b = 0; b < kMapFn; ++b) {
+            u0 += mp.cm[a][b] * F.Y0[b];
+            u1 += mp.cm[a][b] * F.Y1[b];
+            u2 += mp.cm[a][b] * F.Y2[b];
+        }
+        h[0] += F.X0[a] * u0;
+        h[1] += F.X1[a] * u0;
+        h[2] += F.X0[a] * u1;
+        h[3] += F.X2[a] * u0;
+        h[4] += F.X1[a] * u1;
+        h[5] += F.X0[a] * u2;
     }
 }
 

@@ -247,6 +247,27 @@ def test_separable_bottom_matches_term_by_term():
     assert rel <= 1e-12
 
 
+def test_dtheta_separable_matches_term_by_term():
+    """dtheta through the factor table agrees with the term-by-term path
+    (forced by four extra zero-coefficient terms that overflow the table)."""
+    w = I.small("sigma3d-adj")
+    mask = vct.VCT_OUT_LAP | vct.VCT_OUT_PZ
+    extra = [(0.0, I.B_COS, f, I.B_ONE, 0.0) for f in (3.0, 5.0, 7.0, 9.0)]
+    res = []
+    for spec in (w.mapspec, w.mapspec.with_terms(extra)):
+        g = _geom(w)
+        assert g.moments(spec, mask) == vct.VCT_OK
+        proj = g.apply(g.sorted_field(w.phi[0]), vct.VCT_FP64)
+        u = 2.0 * (proj[0, : g.n, 0] - g.sorted_field(w.extra["target"])[0])
+        res.append(g.adjoint(u, proj))
+    nt = len(w.mapspec.terms)
+    assert res[1][1].numel() == nt + len(extra)
+    for a, b in ((res[0][0], res[1][0]), (res[0][1], res[1][1][:nt])):
+        rel = float((a - b).abs().max() / a.abs().max())
+        print(f"\nseparable vs term-by-term adjoint: {rel:.2e}")
+        assert rel <= 1e-12
+
+
 def test_fp32_only_state_matches_the_rounded_fp64_state():
     """vct_moments without the FP64 state writes the same FP32 state."""
     w = I.small("sigma3d")
