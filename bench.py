@@ -100,7 +100,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
-              "the multi-GPU sharding is a design note in DESIGN.md, not an implemented path.", file=sys.stderr)
+              "sharding across GPUs is designed (spatial slabs with halo exchanges) but not implemented.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
