@@ -99,7 +99,7 @@ def measured_traffic(kernel_name, launches_bytes):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
+        print(f"bench.py: the benchmark runs on one GPU only (asked for {args.gpus}); "
               "sharding across GPUs is designed (spatial slabs with halo exchanges) but not implemented.", file=sys.stderr)
         sys.exit(2)
 
