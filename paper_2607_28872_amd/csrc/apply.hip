@@ -402,17 +402,36 @@ __global__ __launch_bounds__(ApplyCfg<T>::threads, ApplyCfg<T>::waves) void k_ap
             __syncthreads();
         }
         const double phi_i = ph[ii];
-        // pass 1: first-order sums and G~ = L~ a~
-        T a1[D], Gt[D];
+        // pass 1: first-order sums and G~ = L~ a~, in FP32 for both forms.  G
+        // only sets the residual psi of pass 2; out = P [a; s](psi) + W G
+        // holds for any G, so an FP32 G leaves the FP64 form's sums FP64 and
+        // its result as accurate (psi keeps a linear part of relative size
+        // 1e-7, which the operator reproduces exactly).
+        float a1[D];
+        T Gt[D];
 #pragma unroll
-        for (int a = 0; a < D; ++a) a1[a] = T(0);
+        for (int a = 0; a < D; ++a) a1[a] = 0.0f;
+        const float invRf = (float)A.invR;
         auto term1 = [&](const double4& q, T vj, bool use) {
-            double dx[D];
-            T r[D], q2, vc;
-            pair_geom<D, KERNEL, T>(q, vj, xi, invR, dx, r, q2, vc);
-            const T wgt = use ? vc * T(q.w - phi_i) : T(0);
+            if constexpr (Scaled<T>::value) {
+                double dx[D];
+                T r[D], q2, vc;
+                pair_geom<D, KERNEL, T>(q, vj, xi, invR, dx, r, q2, vc);
+                const T wgt = use ? vc * T(q.w - phi_i) : T(0);
 #pragma unroll
-            for (int a = 0; a < D; ++a) a1[a] += wgt * r[a];
+                for (int a = 0; a < D; ++a) a1[a] += wgt * r[a];
+            } else {
+                float r[D], q2 = 0.0f;
+                r[0] = (float)(q.x - xi[0]) * invRf;
+                r[1] = (float)(q.y - xi[1]) * invRf;
+                if (D == 3) r[D - 1] = (float)(q.z - xi[2]) * invRf;
+#pragma unroll
+                for (int a = 0; a < D; ++a) q2 += r[a] * r[a];
+                const float vc = (float)vj * kernel_shape<KERNEL>(vsqrt(q2));
+                const float wgt = use ? vc * (float)(q.w - phi_i) : 0.0f;
+#pragma unroll
+                for (int a = 0; a < D; ++a) a1[a] += wgt * r[a];
+            }
         };
         // software pipeline: the record of slot s + 1 is read while slot s is
         // summed (the scheduling barriers keep the compiler from hoisting
@@ -435,7 +454,18 @@ __global__ __launch_bounds__(ApplyCfg<T>::threads, ApplyCfg<T>::waves) void k_ap
             const int t = col_at(e);
             term1(sd[t], sv[t], true);
         }
-        group_gradient<D, T>(L2, a1, Gt);
+#pragma unroll
+        for (int a = 0; a < D; ++a) a1[a] = group_sum(a1[a], kLanes);
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            T t = T(0);
+#pragma unroll
+            for (int c = 0; c < D; ++c) {
+                const int p = sym_index<D>(a, c);
+                t += (a == c ? L2[p] : T(0.5) * L2[p]) * T(a1[c]);
+            }
+            Gt[a] = t;
+        }
         double Gp[D];
 #pragma unroll
         for (int a = 0; a < D; ++a) Gp[a] = Scaled<T>::value ? (double)Gt[a] : (double)Gt[a] * A.invR;
