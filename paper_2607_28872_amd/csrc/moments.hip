@@ -193,13 +193,17 @@ __global__ __launch_bounds__(kMThreads, VCT_SWEEP_WAVES) void k_moment_sweeps(Sw
         const int64_t j = window_global<D>(w, t);
         return make_double4(A.pos[j], A.pos[n + j], D == 3 ? A.pos[2 * n + j] : 0.0, A.vol[j]);
     };
-    auto geom = [&](const double4& q, double (&r)[D], double& q2) {
+    // r~ and its pair products q~ (q~ holds the squares first, so |r~|^2 is
+    // their sum)
+    auto geom = [&](const double4& q, double (&r)[D], double (&qv)[Dm::m], double& q2) {
         r[0] = (q.x - xi[0]) * A.invR;
         r[1] = (q.y - xi[1]) * A.invR;
         if (D == 3) r[D - 1] = (q.z - xi[2]) * A.invR;
-        q2 = 0.0;
 #pragma unroll
-        for (int a = 0; a < D; ++a) q2 += r[a] * r[a];
+        for (int p = 0; p < Dm::m; ++p) qv[p] = r[pair_a<D>(p)] * r[pair_b<D>(p)];
+        q2 = qv[0];
+#pragma unroll
+        for (int a = 1; a < D; ++a) q2 += qv[a];
     };
     // visits every row entry: the register slots (records read one ahead
     // when the window is in LDS), then the rest of a long row
@@ -238,26 +242,21 @@ __global__ __launch_bounds__(kMThreads, VCT_SWEEP_WAVES) void k_moment_sweeps(Sw
     for (int p = 0; p < Dm::nL; ++p) Am[p] = 0.0;
 #pragma unroll
     for (int t = 0; t < Dm::n3; ++t) B[t] = 0.0;
-    // The weighted pair products wq = wgt q~ are formed once per pair; the
-    // cubic and quartic sums are then one multiply-add each (wq times r~ or
-    // q~), not a monomial product followed by a weighted multiply-add.
-    auto pairs = [&](const double (&r)[D], double (&qv)[Dm::m]) {
-#pragma unroll
-        for (int p = 0; p < Dm::m; ++p) qv[p] = r[pair_a<D>(p)] * r[pair_b<D>(p)];
-    };
+    // The weighted offsets wr = wgt r~ are formed once per pair; the pair and
+    // cubic sums are then one multiply-add each (wr times r~ or q~), not a
+    // monomial product followed by a weighted multiply-add.
     sweep([&](const double4& q) {
-        double r[D], q2, qv[Dm::m], wq[Dm::m];
-        geom(q, r, q2);
+        double r[D], q2, qv[Dm::m], wr[D];
+        geom(q, r, qv, q2);
         if (q2 == 0.0) fl |= VCT_FLAG_DUPLICATE;
-        pairs(r, qv);
         const double wgt = q.w * kernel_shape<KERNEL>(vsqrt(q2));
 #pragma unroll
-        for (int p = 0; p < Dm::m; ++p) wq[p] = wgt * qv[p];
+        for (int a = 0; a < D; ++a) wr[a] = wgt * r[a];
 #pragma unroll
-        for (int p = 0; p < Dm::nL; ++p) Am[p] += wq[p];
+        for (int p = 0; p < Dm::nL; ++p) Am[p] += wr[pair_a<D>(p)] * r[pair_b<D>(p)];
 #pragma unroll
         for (int t = 0; t < Dm::n3; ++t)
-            B[t] += wq[sym_index<D>(mono_comp<D, 3>(t, 0), mono_comp<D, 3>(t, 1))] * r[mono_comp<D, 3>(t, 2)];
+            B[t] += wr[mono_comp<D, 3>(t, 0)] * qv[sym_index<D>(mono_comp<D, 3>(t, 1), mono_comp<D, 3>(t, 2))];
     }, std::true_type{});
 #pragma unroll
     for (int p = 0; p < Dm::nL; ++p) Am[p] = group_sum(Am[p], kMLanes);
@@ -294,8 +293,7 @@ __global__ __launch_bounds__(kMThreads, VCT_SWEEP_WAVES) void k_moment_sweeps(Sw
     const bool live = fl == 0;
     sweep([&](const double4& q) {
         double r[D], q2, qv[Dm::m], wq[Dm::m];
-        geom(q, r, q2);
-        pairs(r, qv);
+        geom(q, r, qv, q2);
         double rLr = 0.0;
 #pragma unroll
         for (int p = 0; p < Dm::nL; ++p) rLr += L2[p] * qv[p];
