@@ -119,10 +119,14 @@ template <class T> struct Scaled {
 
 // Pair geometry: FP64 offset dx = x_j - x_i (in units of R for the mixed
 // form), r~ = dx / R, q^2 = |r~|^2 and V_j c~(q) in the arithmetic type T;
-// with IQ4 also 1 / q^4, both from one reciprocal square root.
+// with IQ4 also 1 / q^4, both from one reciprocal square root.  An empty
+// register slot (use false) takes q^2 = 4, outside the support: c~ = 0
+// exactly, 1 / q^4 stays finite, and its terms add zero without a mask on
+// each product.
 template <int D, int KERNEL, class T, bool IQ4 = false>
 __device__ __forceinline__ void pair_geom(const double4& q, T vj, const double (&xi)[3], T invR,
-                                          double (&dx)[D], T (&r)[D], T& q2, T& vc, T* iq4 = nullptr) {
+                                          double (&dx)[D], T (&r)[D], T& q2, T& vc, T* iq4 = nullptr,
+                                          bool use = true) {
     dx[0] = q.x - xi[0];
     dx[1] = q.y - xi[1];
     if (D == 3) dx[D - 1] = q.z - xi[2];
@@ -132,6 +136,7 @@ __device__ __forceinline__ void pair_geom(const double4& q, T vj, const double (
         r[a] = Scaled<T>::value ? T(dx[a]) : T(dx[a]) * invR;
         q2 += r[a] * r[a];
     }
+    q2 = use ? q2 : T(4);
     if (IQ4) {
         T rs;
         if constexpr (Scaled<T>::value) rs = __builtin_amdgcn_rsqf(q2);
@@ -412,14 +417,18 @@ __global__ __launch_bounds__(ApplyCfg<T>::threads, ApplyCfg<T>::waves) void k_ap
 #pragma unroll
         for (int a = 0; a < D; ++a) a1[a] = 0.0f;
         const float invRf = (float)A.invR;
-        auto term1 = [&](const double4& q, T vj, bool use) {
+        // The mixed form keeps each register slot's V_j c~ from pass 1, so
+        // pass 2 forms only 1 / q^4 (the FP64 form needs its own FP64 c~).
+        float vcs[kS];
+        auto term1 = [&](const double4& q, T vj, bool use) -> float {
             if constexpr (Scaled<T>::value) {
                 double dx[D];
                 T r[D], q2, vc;
-                pair_geom<D, KERNEL, T>(q, vj, xi, invR, dx, r, q2, vc);
-                const T wgt = use ? vc * T(q.w - phi_i) : T(0);
+                pair_geom<D, KERNEL, T>(q, vj, xi, invR, dx, r, q2, vc, nullptr, use);
+                const T wgt = vc * T(q.w - phi_i);
 #pragma unroll
                 for (int a = 0; a < D; ++a) a1[a] += wgt * r[a];
+                return vc;
             } else {
                 float r[D], q2 = 0.0f;
                 r[0] = (float)(q.x - xi[0]) * invRf;
@@ -427,10 +436,12 @@ __global__ __launch_bounds__(ApplyCfg<T>::threads, ApplyCfg<T>::waves) void k_ap
                 if (D == 3) r[D - 1] = (float)(q.z - xi[2]) * invRf;
 #pragma unroll
                 for (int a = 0; a < D; ++a) q2 += r[a] * r[a];
+                q2 = use ? q2 : 4.0f;
                 const float vc = (float)vj * kernel_shape<KERNEL>(vsqrt(q2));
-                const float wgt = use ? vc * (float)(q.w - phi_i) : 0.0f;
+                const float wgt = vc * (float)(q.w - phi_i);
 #pragma unroll
                 for (int a = 0; a < D; ++a) a1[a] += wgt * r[a];
+                return 0.0f;
             }
         };
         // software pipeline: the record of slot s + 1 is read while slot s is
@@ -447,7 +458,7 @@ __global__ __launch_bounds__(ApplyCfg<T>::threads, ApplyCfg<T>::waves) void k_ap
                 vn = sv[cols(s + 1)];
             }
             __builtin_amdgcn_sched_barrier(0);
-            term1(q, vj, s < nslot);
+            vcs[s] = term1(q, vj, s < nslot);
             __builtin_amdgcn_sched_barrier(0);
         }
         for (int64_t e = tail + lane; e < re; e += kLanes) {
@@ -477,15 +488,31 @@ __global__ __launch_bounds__(ApplyCfg<T>::threads, ApplyCfg<T>::waves) void k_ap
         T acc[nk];
 #pragma unroll
         for (int c = 0; c < nk; ++c) acc[c] = T(0);
-        auto term2 = [&](const double4& q, T vj, bool use) {
+        auto term2 = [&](const double4& q, T vj, bool use, int s) {
             double dx[D];
             T r[D], q2, vc;
             T iq4;
-            pair_geom<D, KERNEL, T, true>(q, vj, xi, invR, dx, r, q2, vc, &iq4);
+            if (Scaled<T>::value && s >= 0) {   // V c~ from pass 1; 1 / q^4 here
+#pragma unroll
+                for (int a = 0; a < D; ++a) {
+                    dx[a] = (a == 0 ? q.x : a == 1 ? q.y : q.z) - xi[a];
+                    r[a] = T(dx[a]);
+                }
+                q2 = r[0] * r[0];
+#pragma unroll
+                for (int a = 1; a < D; ++a) q2 += r[a] * r[a];
+                q2 = use ? q2 : T(4);
+                const T rs = __builtin_amdgcn_rsqf(q2);
+                const T rs2 = rs * rs;
+                iq4 = rs2 * rs2;
+                vc = vcs[s];
+            } else {
+                pair_geom<D, KERNEL, T, true>(q, vj, xi, invR, dx, r, q2, vc, &iq4, use);
+            }
             double psi = q.w - phi_i;
 #pragma unroll
             for (int a = 0; a < D; ++a) psi -= dx[a] * Gp[a];
-            pair_sums<D, T>(r, use ? iq4 : T(0), use ? vc : T(0), T(psi), L2, acc);
+            pair_sums<D, T>(r, iq4, vc, T(psi), L2, acc);
         };
         qn = sd[cols(0)];
         vn = sv[cols(0)];
@@ -498,12 +525,12 @@ __global__ __launch_bounds__(ApplyCfg<T>::threads, ApplyCfg<T>::waves) void k_ap
                 vn = sv[cols(s + 1)];
             }
             __builtin_amdgcn_sched_barrier(0);
-            term2(q, vj, s < nslot);
+            term2(q, vj, s < nslot, s);
             __builtin_amdgcn_sched_barrier(0);
         }
         for (int64_t e = tail + lane; e < re; e += kLanes) {
             const int t = col_at(e);
-            term2(sd[t], sv[t], true);
+            term2(sd[t], sv[t], true, -1);
         }
         // epilogue: the group's sums to LDS, then one thread per (row, particle)
 #pragma unroll
