@@ -150,10 +150,10 @@ __device__ __forceinline__ void pair_geom(const double4& q, T vj, const double (
 }
 
 // Sums of one pair with residual psi: a~ += V c~ psi r~ and
-// s~ += V c~ psi (r~' L~ r~) / |r~|^4 r~ r~'  (L2 holds L~ with doubled
-// off-diagonal entries).
+// s~ += V c~ psi (r~' L~ r~) / |r~|^4 r~ r~' (L2 holds L~ with doubled
+// off-diagonal entries), with vq = V c~ / |r~|^4 given.
 template <int D, class T>
-__device__ __forceinline__ void pair_sums(const T (&r)[D], T iq4, T vc, T psi, const T (&L2)[Dims<D>::nL],
+__device__ __forceinline__ void pair_sums(const T (&r)[D], T vq, T vc, T psi, const T (&L2)[Dims<D>::nL],
                                           T (&acc)[Dims<D>::nk]) {
     using Dm = Dims<D>;
     T qv[Dm::m];
@@ -162,7 +162,7 @@ __device__ __forceinline__ void pair_sums(const T (&r)[D], T iq4, T vc, T psi, c
     T rLr = T(0);
 #pragma unroll
     for (int p = 0; p < Dm::nL; ++p) rLr += L2[p] * qv[p];
-    const T wa = vc * psi, ws = wa * rLr * iq4;
+    const T wa = vc * psi, ws = vq * psi * rLr;
 #pragma unroll
     for (int a = 0; a < D; ++a) acc[a] += wa * r[a];
 #pragma unroll
@@ -268,7 +268,7 @@ __device__ __forceinline__ void apply_chunk_global(const ApplyArgs<S>& A, const 
             double psi = q.w - phi_i;
 #pragma unroll
             for (int a = 0; a < D; ++a) psi -= dx[a] * Gp[a];
-            pair_sums<D, T>(r, iq4, vc, T(psi), L2, acc);
+            pair_sums<D, T>(r, vc * iq4, vc, T(psi), L2, acc);
         }
 #pragma unroll
         for (int c = 0; c < nk; ++c) acc[c] = group_sum(acc[c], kLanes);
@@ -417,14 +417,16 @@ __global__ __launch_bounds__(ApplyCfg<T>::threads, ApplyCfg<T>::waves) void k_ap
 #pragma unroll
         for (int a = 0; a < D; ++a) a1[a] = 0.0f;
         const float invRf = (float)A.invR;
-        // The mixed form keeps each register slot's V_j c~ from pass 1, so
-        // pass 2 forms only 1 / q^4 (the FP64 form needs its own FP64 c~).
-        float vcs[kS];
-        auto term1 = [&](const double4& q, T vj, bool use) -> float {
+        // The mixed form keeps each register slot's V_j c~ and V_j c~ / q^4
+        // from pass 1, so pass 2 forms neither (the FP64 form needs its own
+        // FP64 values).
+        float vcs[kS], vqs[kS];
+        auto term1 = [&](const double4& q, T vj, bool use, float& vq) -> float {
             if constexpr (Scaled<T>::value) {
                 double dx[D];
-                T r[D], q2, vc;
-                pair_geom<D, KERNEL, T>(q, vj, xi, invR, dx, r, q2, vc, nullptr, use);
+                T r[D], q2, vc, iq4;
+                pair_geom<D, KERNEL, T, true>(q, vj, xi, invR, dx, r, q2, vc, &iq4, use);
+                vq = vc * iq4;
                 const T wgt = vc * T(q.w - phi_i);
 #pragma unroll
                 for (int a = 0; a < D; ++a) a1[a] += wgt * r[a];
@@ -441,6 +443,7 @@ __global__ __launch_bounds__(ApplyCfg<T>::threads, ApplyCfg<T>::waves) void k_ap
                 const float wgt = vc * (float)(q.w - phi_i);
 #pragma unroll
                 for (int a = 0; a < D; ++a) a1[a] += wgt * r[a];
+                vq = 0.0f;
                 return 0.0f;
             }
         };
@@ -458,12 +461,13 @@ __global__ __launch_bounds__(ApplyCfg<T>::threads, ApplyCfg<T>::waves) void k_ap
                 vn = sv[cols(s + 1)];
             }
             __builtin_amdgcn_sched_barrier(0);
-            vcs[s] = term1(q, vj, s < nslot);
+            vcs[s] = term1(q, vj, s < nslot, vqs[s]);
             __builtin_amdgcn_sched_barrier(0);
         }
         for (int64_t e = tail + lane; e < re; e += kLanes) {
             const int t = col_at(e);
-            term1(sd[t], sv[t], true);
+            float vq_;
+            term1(sd[t], sv[t], true, vq_);
         }
 #pragma unroll
         for (int a = 0; a < D; ++a) a1[a] = group_sum(a1[a], kLanes);
@@ -492,27 +496,25 @@ __global__ __launch_bounds__(ApplyCfg<T>::threads, ApplyCfg<T>::waves) void k_ap
             double dx[D];
             T r[D], q2, vc;
             T iq4;
-            if (Scaled<T>::value && s >= 0) {   // V c~ from pass 1; 1 / q^4 here
+            if (Scaled<T>::value && s >= 0) {   // V c~ and V c~ / q^4 from pass 1
 #pragma unroll
                 for (int a = 0; a < D; ++a) {
                     dx[a] = (a == 0 ? q.x : a == 1 ? q.y : q.z) - xi[a];
                     r[a] = T(dx[a]);
                 }
-                q2 = r[0] * r[0];
-#pragma unroll
-                for (int a = 1; a < D; ++a) q2 += r[a] * r[a];
-                q2 = use ? q2 : T(4);
-                const T rs = __builtin_amdgcn_rsqf(q2);
-                const T rs2 = rs * rs;
-                iq4 = rs2 * rs2;
                 vc = vcs[s];
+                double psi = q.w - phi_i;
+#pragma unroll
+                for (int a = 0; a < D; ++a) psi -= dx[a] * Gp[a];
+                pair_sums<D, T>(r, T(vqs[s]), vc, T(psi), L2, acc);
+                return;
             } else {
                 pair_geom<D, KERNEL, T, true>(q, vj, xi, invR, dx, r, q2, vc, &iq4, use);
             }
             double psi = q.w - phi_i;
 #pragma unroll
             for (int a = 0; a < D; ++a) psi -= dx[a] * Gp[a];
-            pair_sums<D, T>(r, iq4, vc, T(psi), L2, acc);
+            pair_sums<D, T>(r, vc * iq4, vc, T(psi), L2, acc);
         };
         qn = sd[cols(0)];
         vn = sv[cols(0)];
