@@ -360,20 +360,29 @@ def test_adjoint_against_oracle(form):
 
 def test_degenerate_particles_flagged():
     # an isolated particle (outside the box: clamped into a boundary cell, no
-    # neighbours) and an exact duplicate of particle 0
+    # neighbours: every register slot of its row is empty) and an exact
+    # duplicate of particle 0; in both applies their outputs are NaN and the
+    # other particles of their chunks are unaffected
     w = I.small("bf2d")
     pos = np.concatenate([w.pos, [[0.5], [10.0]], w.pos[:, :1]], axis=1)
     vol = np.concatenate([w.vol, [w.vol[0], w.vol[0]]])
     g = vct.Geometry(pos, vol, w.lo, w.hi, w.R, w.kernel, device=DEV)
-    st = g.moments(w.mapspec, vct.VCT_OUT_DEFAULT)
+    st = g.moments(w.mapspec, vct.VCT_OUT_DEFAULT, fp32_copy=True)
     assert st == vct.VCT_W_FLAGGED
     flags = g.unsort(g.flags[: g.n]).cpu().numpy()
     assert flags[w.n] & vct.FLAG_FEW
     assert flags[w.n + 1] & vct.FLAG_DUPLICATE and flags[0] & vct.FLAG_DUPLICATE
-    out = _gpu_out(g, np.zeros((1, g.n)), vct.VCT_FP64)
-    assert np.isnan(out[0, w.n]).all() and np.isnan(out[0, w.n + 1]).all()
     ok = flags == 0
-    assert ok.sum() > w.n - 40 and np.isfinite(out[0, ok]).all()
+    assert ok.sum() > w.n - 40
+    phi = np.concatenate([w.phi, w.phi[:, :1], w.phi[:, :1]], axis=1)
+    out = {}
+    for prec in (vct.VCT_FP64, vct.VCT_MIXED):
+        o = _gpu_out(g, phi, prec)
+        assert np.isnan(o[:, w.n]).all() and np.isnan(o[:, w.n + 1]).all()
+        assert np.isfinite(o[:, ok]).all()
+        out[prec] = o[:, ok]
+    err = normwise(out[vct.VCT_MIXED], out[vct.VCT_FP64])
+    assert err[:, :2].max() <= 1e-5 and err[:, 2:].max() <= 1e-4
 
 
 def test_nonfinite_position_rejected():
