@@ -37,11 +37,11 @@ constexpr int kColCap = 7168;                // row entries of a chunk staged in
 
 // Lanes per particle, register slots per lane, occupancy target (waves per
 // SIMD) and LDS window capacity (records) of each arithmetic type
-// (overridable at build time for tuning).  FP32 sums: 512-thread groups at
-// 4 waves per SIMD (two groups per CU).  FP64 sums need about 250 VGPRs, so
-// they run 256-thread groups (4 lanes per particle) at 2 waves per SIMD with a
-// smaller window (about 76 KB of LDS): again two groups per CU, where eight
-// lanes per particle would leave one.
+// (overridable at build time for tuning).  Both forms run 512-thread groups
+// (8 lanes per particle) at 4 waves per SIMD, two groups per CU.  The FP64
+// form's FP64 records and sums take a smaller window (about 77 KB of LDS per
+// group) and fill the 128 VGPRs that 4 waves allow (a few prologue and
+// epilogue values go to scratch, none of the pair loops' values).
 #ifndef VCT_APPLY_F_LANES
 #define VCT_APPLY_F_LANES 8
 #endif
@@ -55,13 +55,13 @@ constexpr int kColCap = 7168;                // row entries of a chunk staged in
 #define VCT_APPLY_F_WIN 1664
 #endif
 #ifndef VCT_APPLY_D_LANES
-#define VCT_APPLY_D_LANES 4
+#define VCT_APPLY_D_LANES 8
 #endif
 #ifndef VCT_APPLY_D_SLOTS
-#define VCT_APPLY_D_SLOTS 20
+#define VCT_APPLY_D_SLOTS 14
 #endif
 #ifndef VCT_APPLY_D_WAVES
-#define VCT_APPLY_D_WAVES 2
+#define VCT_APPLY_D_WAVES 4
 #endif
 #ifndef VCT_APPLY_D_WIN
 #define VCT_APPLY_D_WIN 1400
