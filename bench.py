@@ -358,6 +358,28 @@ def main():
         "kernels": kernels,
     }
 
+    # The adjoint's d loss / d phi along a seeded direction v against the
+    # central difference of the loss with the FP64 Laplacian (outside the
+    # timed steps).  The loss is quadratic in phi and the difference of
+    # squares is formed as (a - b)(a + b - 2 g), so the central difference is
+    # exact up to rounding.
+    progress("adjoint against a central difference")
+    fd_step = 1e-6
+    v = torch.randn(n, generator=torch.Generator().manual_seed(17), dtype=torch.float64).to(dev)
+    lap_pm = []
+    for sgn in (1.0, -1.0):
+        ph = (phi_s[0] + sgn * fd_step * v).unsqueeze(0).contiguous()
+        o = torch.empty_like(proj)
+        vct.vct_apply_ops(nl, 1, ph, pos_s, vol_s, w.kernel, sta, adj_mask, vct.VCT_FP64, o)
+        lap_pm.append(o[0, :, 0])
+    a, b = lap_pm
+    fd = float(((a - b) * (a + b - 2.0 * g_s)).sum().item()) / (2.0 * fd_step)
+    adj = float(torch.dot(dphi, v).item())
+    res["adjoint_fd"] = {"quantity": "d loss / d phi along a seeded normal direction, loss = sum (lap f - g)^2",
+                         "step": fd_step, "central_difference": fd, "adjoint": adj,
+                         "rel_err": abs(fd - adj) / abs(adj)}
+    del lap_pm, a, b, o, ph, v
+
     if not args.no_cpu_baseline:
         progress("CPU oracle on a sample")
         cb, rows, rec = cpu_baseline(w, phis, ms, args.cpu_seconds)
