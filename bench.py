@@ -41,14 +41,16 @@ FP64_PEAK_TFLOPS = 78.6
 #   pass 2 = offsets and q^2 (11), monomials (16), r~.L~.r~ (12), weight (12),
 #   C sums (20), E sums of the 15 quartic monomials (45);
 #   moment solve, per particle: the Schur LU and folds (about 3200);
-#   adjoint d/dphi, per pair: offsets and q^2 (11), pair monomials (6), kernel
-#   value and 1/q^4 (10), r~.L~.r~ for both particles (24), the Laplacian row
-#   contractions for both particles (36), the combination (10);
+#   adjoint d/dphi, per directed neighbour entry: the method needs one
+#   Laplacian weight W_ik per entry (the row sums u_k sum_j W_kj are a
+#   by-product of the same weights): offsets and q^2 (11), pair monomials (6),
+#   kernel value and 1/q^4 (10), r~.L~.r~ (12), the Laplacian row contraction
+#   (18), the combination and the sum (5);
 #   neighbour search, per candidate: offset difference, squared distance and
 #   the two comparisons in FP32 (9).
 MOMENT_FLOP_PER_PAIR_3D = (11 + 16 + 8 + 32) + (11 + 16 + 12 + 12 + 20 + 45)
 MOMENT_FLOP_SOLVE_3D = 3200
-ADJOINT_DPHI_FLOP_PER_PAIR_3D = 11 + 6 + 10 + 24 + 36 + 10
+ADJOINT_DPHI_FLOP_PER_ENTRY_3D = 11 + 6 + 10 + 12 + 18 + 5
 NB_FLOP_PER_CANDIDATE = 9
 FP32_VALU_PEAK_TFLOPS = 157.3        # published FP32 vector peak (packed instructions)
 
@@ -284,7 +286,7 @@ def main():
         "k_apply (fp64)": ("hbm", b_fp64_adj, HBM_PEAK_GBS),
         "k_moment_sweeps": ("alu", pairs * MOMENT_FLOP_PER_PAIR_3D, FP64_PEAK_TFLOPS),
         "k_moment_solve": ("alu", n * MOMENT_FLOP_SOLVE_3D, FP64_PEAK_TFLOPS),
-        "k_adjoint_dphi": ("alu", pairs * ADJOINT_DPHI_FLOP_PER_PAIR_3D, FP64_PEAK_TFLOPS),
+        "k_adjoint_dphi": ("alu", pairs * ADJOINT_DPHI_FLOP_PER_ENTRY_3D, FP64_PEAK_TFLOPS),
         "k_nb_chunk (stage)": ("alu", candidates * NB_FLOP_PER_CANDIDATE, FP32_VALU_PEAK_TFLOPS),
     }
     kernels = {k: {"launches_per_step": c / args.steps, "ms_per_step": round(t / args.steps, 4),

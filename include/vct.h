@@ -105,7 +105,10 @@ enum {
     VCT_FLAG_SINGULAR_A = 2, /* first-order correction matrix numerically singular */
     VCT_FLAG_SINGULAR_M = 4, /* SPH(2) moment matrix numerically singular */
     VCT_FLAG_NONFINITE = 8,  /* non-finite position or volume at the particle or a neighbour */
-    VCT_FLAG_DUPLICATE = 16  /* a neighbour at zero distance */
+    VCT_FLAG_DUPLICATE = 16, /* a neighbour at zero distance */
+    VCT_FLAG_MAP = 32        /* the mapping is invalid at the particle: alpha (or one of the
+                                mapping coefficients) not finite, or alpha <= 0 (Sec. 2.1
+                                requires alpha > 0; e.g. a dry sigma column without limiter) */
 };
 
 /* Bottom elevation term: h(x, y) += coef * Bx(x) * By(y) with
@@ -126,6 +129,10 @@ typedef struct {
  *             D_eff = (D + dmin + sqrt((D - dmin)^2 + eps^2)) / 2 when dmin > 0 or
  *             eps > 0 (the paper asks for a constant alpha outside an unstated
  *             applicable range; this smooth limiter is the reading used), else D.
+ *             dmin > 0 needs eps > 0 (VCT_E_ARG otherwise: with eps = 0 the
+ *             limiter is a hard max whose second derivative is undefined at
+ *             D = dmin).  Particles where alpha is not positive and finite are
+ *             flagged VCT_FLAG_MAP by vct_moments.
  * `terms` is a HOST pointer to nterms (<= VCT_MAX_TERMS) entries; it is read
  * during the call only.                                                        */
 typedef struct {

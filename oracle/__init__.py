@@ -34,7 +34,7 @@ I_D = slice(19, 25)
 I_DHAT = slice(25, 31)
 I_LAP_TRACE = 31
 
-F_FEW, F_SINGULAR_A, F_SINGULAR_M, F_NONFINITE, F_DUPLICATE = 1, 2, 4, 8, 16
+F_FEW, F_SINGULAR_A, F_SINGULAR_M, F_NONFINITE, F_DUPLICATE, F_MAP = 1, 2, 4, 8, 16, 32
 
 
 def build(verbose=False):

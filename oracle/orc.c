@@ -35,7 +35,9 @@
  *  - the physical cross derivatives are not printed; they come from the chain
  *    rule above.
  *  - a particle with fewer than d + m neighbours, a singular A_i or M_i, a
- *    duplicate position or a non-finite input gets NaN outputs and a flag.
+ *    duplicate position, a non-finite input, or a mapping whose alpha is not
+ *    positive and finite there (Sec. 2.1 needs alpha > 0) gets NaN outputs
+ *    and a flag.
  */
 #include <complex.h>
 #undef I            /* loop indices below use I; the imaginary unit is _Complex_I */
@@ -515,6 +517,8 @@ static int orc_particle_field(const orc_ctx* c, int64_t i, const int32_t* nb, in
     double x = c->pos[i], y = (d == 3) ? c->pos[n + i] : 0.0, zh = c->pos[(d - 1) * n + i];
     double Jm[3][3], ct[6], hz[3][3];
     orc_r_map_coeffs(&c->map, d, x, y, zh, -1, 0.0, Jm, ct, hz);
+    /* the transformation needs alpha > 0 (Sec. 2.1); Jm[2][2] is alpha */
+    if (!(Jm[2][2] > 0.0) || !isfinite(Jm[2][2] + Jm[0][2] + Jm[1][2] + ct[0] + hz[0][1])) return ORC_F_MAP;
     double Dhat[6] = {gh[2], Hh[0][0], Hh[1][1], Hh[2][2], Hh[0][2], Hh[1][2]};
     double lap = 0.0;
     for (int k = 0; k < 6; ++k) lap += ct[k] * Dhat[k];

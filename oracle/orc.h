@@ -14,7 +14,8 @@ enum {
     ORC_F_SINGULAR_A = 2,   /* first-order correction matrix singular */
     ORC_F_SINGULAR_M = 4,   /* SPH(2) matrix M singular */
     ORC_F_NONFINITE = 8,    /* non-finite position or volume */
-    ORC_F_DUPLICATE = 16    /* a neighbour at zero distance */
+    ORC_F_DUPLICATE = 16,   /* a neighbour at zero distance */
+    ORC_F_MAP = 32          /* alpha not finite or not positive (Sec. 2.1 needs alpha > 0) */
 };
 
 #define ORC_PIVOT_TOL 1e-12

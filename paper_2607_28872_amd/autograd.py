@@ -9,12 +9,14 @@ c in {1, cos 2 pi s, sin 2 pi s, cos 4 pi s}.  Its backward calls the adjoint
 kernels (vct_apply_ops_adjoint) for d/dphi and d/dtheta; projected positions
 are held fixed, so theta enters only through the mapping coefficients.
 
-With recompute=True the per-particle state (moment matrices, folded
-operators) is dropped after the forward and recomputed by vct_moments in the
-backward, which runs the same kernels on the same inputs and so gives the
-same bits as keeping it.  With recompute="solve" only the moment sums are
-kept (41 values per particle in 3-D instead of the 66 of the state) and the
-backward runs the solve alone (vct_moments_resolve), again with the same bits.
+Between forward and backward the function holds, per particle:
+  recompute=False    the FP64 state of the adjoint's rows (66 values in 3-D);
+  recompute="solve"  the moment sums only (41 values in 3-D); the backward
+                     runs the solve alone (vct_moments_resolve);
+  recompute=True     neither; the backward runs vct_moments again.
+Each mode runs the same kernels on the same inputs, so all three give the
+same bits.  The forward releases the geometry's own references to the state
+and to the moment workspace, so that only what the mode keeps stays alive.
 """
 from __future__ import annotations
 
@@ -54,8 +56,10 @@ class VctLaplacian(torch.autograd.Function):
         ctx.geom, ctx.spec, ctx.recompute = geom, spec, recompute
         ctx.nbase = len(base_map.terms)
         ctx.theta_meta = (theta.dtype, theta.device)
+        solve_only = isinstance(recompute, str) and recompute == "solve"
         ctx.state = None if recompute else geom.state64
-        ctx.ws = geom.ws_mom if recompute == "solve" else None
+        ctx.ws = geom.ws_mom if solve_only else None
+        geom.ws_mom = None
         if recompute:
             geom.state64 = None
         ctx.save_for_backward(phi)
@@ -65,7 +69,7 @@ class VctLaplacian(torch.autograd.Function):
     def backward(ctx, grad_lap):
         (phi,) = ctx.saved_tensors
         g = ctx.geom
-        if ctx.recompute == "solve":
+        if isinstance(ctx.recompute, str) and ctx.recompute == "solve":
             st = g.resolve(ctx.spec, ADJ_MASK, ws=ctx.ws)
             if st < 0:
                 raise vct.VctError("vct_moments_resolve", st)

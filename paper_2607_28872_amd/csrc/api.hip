@@ -79,6 +79,9 @@ int map_params_from(const vct_map* m, int dim, MapParams& p) {
     if (m->kind == VCT_MAP_SIGMA) {
         if (!(m->Hhat > 0.0) || !isfinite(m->Hhat) || !isfinite(m->H) || !(m->dmin >= 0.0) || !(m->eps >= 0.0))
             return VCT_E_ARG;
+        // a limiter with eps = 0 is a hard max(D, dmin): its second derivative
+        // is 0/0 where D = dmin, so the smooth limiter needs eps > 0
+        if (m->dmin > 0.0 && !(m->eps > 0.0)) return VCT_E_ARG;
         p.limiter = (m->dmin > 0.0 || m->eps > 0.0) ? 1 : 0;
     }
     for (int t = 0; t < m->nterms; ++t) {

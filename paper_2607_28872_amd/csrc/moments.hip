@@ -527,6 +527,9 @@ __global__ __launch_bounds__(128, VCT_SOLVE_WAVES) void k_moment_solve(int64_t n
     double h[6];
     bottom6(mp, x, y, h);
     const MapCoef<double> mc = map_coef<double>(mp, h, zh);
+    // Sec. 2.1 requires alpha > 0 (a dry sigma column without the limiter
+    // gives alpha <= 0 or infinite); such a particle is flagged
+    if (!(mc.alpha > 0.0) || !isfinite(mc.alpha + mc.gx + mc.gy + mc.c0 + mc.zxy)) fl |= VCT_FLAG_MAP;
     const bool grad1 = (mask & VCT_OPT_GRAD1) != 0;
     const double invR2 = invR * invR;
     const double nanv = __builtin_nan("");

@@ -28,7 +28,7 @@ VCT_OUT_PZ = 64
 VCT_OPT_GRAD1 = 256
 VCT_OUT_DEFAULT = VCT_OUT_GRAD | VCT_OUT_LAP | VCT_OUT_CROSS
 VCT_MAX_TERMS = 32
-FLAG_FEW, FLAG_SINGULAR_A, FLAG_SINGULAR_M, FLAG_NONFINITE, FLAG_DUPLICATE = 1, 2, 4, 8, 16
+FLAG_FEW, FLAG_SINGULAR_A, FLAG_SINGULAR_M, FLAG_NONFINITE, FLAG_DUPLICATE, FLAG_MAP = 1, 2, 4, 8, 16, 32
 
 
 class VctError(RuntimeError):

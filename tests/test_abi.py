@@ -116,6 +116,9 @@ def test_argument_errors_are_caught_on_the_host(L):
     sig = vct.vct_map(4, 0, -1.0, 0.0, 0.0, 0.0, None)
     assert L.vct_moments(C.byref(nl), None, None, 0, C.byref(sig), 3, None, None, None, None, None, 0,
                          None) == E              # sigma with Hhat <= 0
+    hard = vct.vct_map(4, 0, 1.0, 0.0, 0.125, 0.0, None)
+    assert L.vct_moments(C.byref(nl), None, None, 0, C.byref(hard), 3, None, None, None, None, None, 0,
+                         None) == E              # sigma limiter with dmin > 0 and eps = 0
     assert L.vct_moments_resolve(C.byref(nl), None, C.byref(m), 0, None, None, None, None, None, 0,
                                  None) == E      # empty output mask
     assert L.vct_moments_resolve(C.byref(nl), None, C.byref(badm), 3, None, None, None, None, None, 0,

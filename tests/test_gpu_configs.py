@@ -47,6 +47,22 @@ def _mixed_bars(w, got, ref, label):
     assert err[:, w.dim:].max() <= 1e-4
 
 
+@pytest.mark.parametrize("name", ["c1", "c2"])
+def test_neighbor_lists_full_set(name):
+    """The whole CSR of the 1M-particle BFE and 2.1M-particle sigma sets,
+    bit-exact against the oracle's grid search (the FP32 pre-test's margin
+    depends on each set's offsets and cell size)."""
+    w = I.config(name)
+    g = vct.Geometry(w.pos, w.vol, w.lo, w.hi, w.R, w.kernel, device=DEV, keep_col=True)
+    rp, col = g.csr_original()
+    del g
+    torch.cuda.empty_cache()
+    orp, ocol = O.neighbors(w.pos, w.R)
+    print(f"\n{name}: {col.shape[0]} neighbour entries")
+    assert np.array_equal(rp, orp)
+    assert np.array_equal(col, ocol)
+
+
 @pytest.mark.parametrize("name", ["c0", "c1"])
 def test_fp64_full_set(name):
     w = I.config(name)

@@ -164,6 +164,46 @@ def test_fp64_parity_all_outputs(family, kernel):
           f"GPU {e_gpu}, FP64 oracle {e_ref}")
 
 
+@pytest.mark.parametrize("family", ["bf2d", "sigma3d"])
+@pytest.mark.parametrize("kind", ["E", "identity"])
+def test_fp64_parity_other_maps(family, kind):
+    """The E-SPH map (constant alpha = Hhat / H) and the identity map on the
+    same particle sets, every output group, FP64 and mixed."""
+    w = I.small(family)
+    ms = I.MapSpec(kind=I.MAP_E, Hhat=2.5, H=1.0) if kind == "E" else I.MapSpec()
+    w.mapspec = ms
+    g = _geom(w)
+    st = g.moments(ms, ALL_OUT, fp32_copy=True)
+    assert st == vct.VCT_OK and g.n_flagged == 0
+    got = _gpu_out(g, w.phi, vct.VCT_FP64)
+    rec, fl = O.sph2(w.pos, w.vol, w.phi, w.kernel, w.R, ms)
+    assert not fl.any()
+    ref = oracle_rows(rec, w.dim, ALL_OUT)
+    rep = fp64_check(w, w.kernel, w.R, got, ref, ALL_OUT, label=f"{family} {kind}")
+    err = normwise(_gpu_out(g, w.phi, vct.VCT_MIXED), ref)
+    print(f"{family} {kind} mixed: grad {err[:, :w.dim].max():.2e} others {err[:, w.dim:].max():.2e}")
+    assert err[:, :w.dim].max() <= 1e-5 and err[:, w.dim:].max() <= 1e-4
+
+
+def test_dry_sigma_column_is_flagged():
+    """sigma-SPH without limiter where the depth is negative: alpha < 0,
+    which Sec. 2.1 excludes.  The library flags the same particles as the
+    oracle and writes NaN outputs for them only."""
+    w = I.small("sigma3d")
+    dry = [(-1.0, I.B_ONE, 0, I.B_ONE, 0), (1.2, I.B_LIN, 0, I.B_ONE, 0)]
+    ms = I.MapSpec(kind=I.MAP_SIGMA, Hhat=w.mapspec.Hhat, H=0.0, terms=dry)
+    g = _geom(w)
+    st = g.moments(ms, vct.VCT_OUT_DEFAULT)
+    assert st == vct.VCT_W_FLAGGED
+    flags = g.unsort(g.flags[: g.n]).cpu().numpy()
+    _, ofl = O.sph2(w.pos, w.vol, w.phi[:1], w.kernel, w.R, ms)
+    assert np.array_equal(flags & vct.FLAG_MAP, ofl & O.F_MAP)
+    assert (flags & vct.FLAG_MAP).any() and not (flags & np.uint8(0xFF ^ vct.FLAG_MAP)).any()
+    out = _gpu_out(g, w.phi, vct.VCT_FP64)
+    bad = (flags & vct.FLAG_MAP) != 0
+    assert np.isnan(out[:, bad]).all() and np.isfinite(out[:, ~bad]).all()
+
+
 @pytest.mark.parametrize("family", FAMILIES)
 def test_first_order_gradient_option(family):
     w = I.small(family)

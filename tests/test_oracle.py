@@ -395,6 +395,110 @@ def test_physical_quadratics_exact_under_affine_maps(orc, kind):
     assert np.abs(out[:, 0, 3] - out[:, 0, O.I_LAP_TRACE]).max() < 1e-9
 
 
+def _map_values(ms, x, y):
+    """alpha and beta of a mapping at horizontal points, written from the
+    definitions of Sec. 2.2 (and the smooth depth limiter read for sigma-SPH),
+    independently of the oracle's own evaluation."""
+    h = I.bottom(ms.terms, x, y)
+    one = np.ones_like(x)
+    if ms.kind == I.MAP_IDENTITY:
+        return one, 0.0 * one
+    if ms.kind == I.MAP_E:
+        return (ms.Hhat / ms.H) * one, 0.0 * one
+    if ms.kind == I.MAP_BF:
+        return one, -h
+    if ms.kind == I.MAP_BFE:
+        return (ms.Hhat / ms.H) * one, -h
+    D = ms.H - h
+    if ms.dmin > 0 or ms.eps > 0:
+        D = 0.5 * (D + ms.dmin + np.sqrt((D - ms.dmin) ** 2 + ms.eps ** 2))
+    return ms.Hhat / D, D - ms.H
+
+
+def _fd_physical_derivatives(fun, p, h):
+    """Gradient and Hessian of fun (a function of a list of coordinate arrays)
+    at the points p (dim, N) by fourth-order central differences of step h:
+    first derivatives and pure second derivatives by the 5-point stencils,
+    mixed ones by nesting the first-derivative stencil."""
+    d = p.shape[0]
+    w1 = ((-2, 1.0), (-1, -8.0), (1, 8.0), (2, -1.0))          # / 12 h
+    w2 = ((-2, -1.0), (-1, 16.0), (0, -30.0), (1, 16.0), (2, -1.0))   # / 12 h^2
+
+    def at(offs):
+        q = [p[a] + offs.get(a, 0) * h for a in range(d)]
+        return fun(q)
+
+    g = np.zeros((d, p.shape[1]))
+    H = np.zeros((d, d, p.shape[1]))
+    for a in range(d):
+        g[a] = sum(c * at({a: s}) for s, c in w1) / (12 * h)
+        H[a, a] = sum(c * at({a: s}) for s, c in w2) / (12 * h * h)
+        for b in range(a + 1, d):
+            H[a, b] = H[b, a] = sum(ca * cb * at({a: sa, b: sb}) for sa, ca in w1 for sb, cb in w1) / (144 * h * h)
+    return g, H
+
+
+@pytest.mark.parametrize("family", ["bf2d", "bfe2d", "sigma3d"])
+def test_physical_chain_rule_under_nonaffine_maps(orc, family):
+    """The physical derivatives the oracle assembles (gradient J grad^ phi,
+    Laplacian c_trans . D^ phi, cross derivatives and Hessian
+    J H^ J^T + phi_z^ grad grad z^, and the Hessian trace) against finite
+    differences taken in physical coordinates.  The field is a quadratic P in
+    the projected coordinates, which SPH(2) reproduces exactly, so the
+    projected derivatives are exact and every physical slot must equal the
+    derivative of phi(x, y, z) = P(x, y, alpha(x, y) (z + beta(x, y))) at the
+    particle's physical position.  The maps are non-affine (curved bottom,
+    sigma layers), so grad grad z^ does not vanish; the test also checks that
+    every compared slot, and the phi_z^ grad grad z^ term, are large against
+    the tolerance, so that dropping or flipping any of them fails it."""
+    w = I.small(family)
+    d, ms, c = w.dim, w.mapspec, w.extra["pquad"]
+    x = w.pos[0]
+    y = w.pos[1] if d == 3 else None
+    a, b = _map_values(ms, x, y)
+    zp = w.pos[d - 1] / a - b                               # physical heights
+
+    def phi_phys(q):
+        qy = q[1] if d == 3 else None
+        aa, bb = _map_values(ms, q[0], qy)
+        zh = aa * (q[d - 1] + bb)
+        return I.eval_quadratic(c, np.stack(list(q[:d - 1]) + [zh]))
+
+    pphys = np.stack(([x, w.pos[1]] if d == 3 else [x]) + [zp])
+    # h = 1e-4: the sigma limiter's transition (width eps = 0.01) needs a step
+    # well below eps for the stencils' truncation error to stay small
+    g_fd, H_fd = _fd_physical_derivatives(phi_phys, pphys, 1e-4)
+    out, fl = orc.sph2(w.pos, w.vol, I.eval_quadratic(c, w.pos), w.kernel, w.R, ms)
+    assert np.all(fl == 0)
+    rec = out[:, 0]
+    ax = [0, 1, 2] if d == 3 else [0, 2]      # record slots of the physical axes
+    checks = {"lap": (rec[:, O.I_LAP], np.trace(H_fd)), "trace": (rec[:, O.I_LAP_TRACE], np.trace(H_fd))}
+    for k in range(d):
+        checks[f"grad{k}"] = (rec[:, ax[k]], g_fd[k])
+    hess_slot = {(0, 0): 7, (1, 1): 8, (2, 2): 9, (0, 1): 10, (0, 2): 11, (1, 2): 12}
+    cross_slot = {(0, 1): 4, (0, 2): 5, (1, 2): 6}
+    for p in range(d):
+        for q in range(p, d):
+            key = (ax[p], ax[q])
+            checks[f"H{p}{q}"] = (rec[:, hess_slot[key]], H_fd[p, q])
+            if p != q:
+                checks[f"cross{p}{q}"] = (rec[:, cross_slot[key]], H_fd[p, q])
+    tol = 1e-6
+    worst = {}
+    for nm, (got, ref) in checks.items():
+        sc = np.abs(ref).max()
+        assert sc > 1e3 * tol * np.abs(g_fd).max(), f"{nm} is too small to discriminate"
+        worst[nm] = np.abs(got - ref).max() / sc
+    print(f"\n{family} physical slots vs finite differences:", {k: float(f"{v:.1e}") for k, v in worst.items()})
+    assert max(worst.values()) <= tol, worst
+    # the curvature term phi_z^ grad grad z^ of the Hessian is itself large:
+    # the assembly without it would miss the bar by orders of magnitude
+    mev = orc.map_eval(d, x, y, w.pos[d - 1], ms)
+    hz = mev[:, 15:].reshape(-1, 3, 3)
+    curv = np.abs(rec[:, O.I_G2][:, 2, None, None] * hz).max()
+    assert curv > 1e3 * tol * np.abs(H_fd).max()
+
+
 def _golden_hydro():
     import os
     rows = []
@@ -568,3 +672,17 @@ def test_degenerate_particles_are_flagged(orc):
     pos2[1, 5] = np.nan
     out2, fl2 = orc.sph2(pos2, w.vol, w.phi[0], w.kernel, w.R, w.mapspec)
     assert fl2[5] & O.F_NONFINITE and np.isnan(out2[5]).all()
+
+
+def test_dry_sigma_column_is_flagged(orc):
+    """sigma-SPH without the depth limiter where the bottom rises above the
+    still surface: the depth, hence alpha, is negative there, which Sec. 2.1
+    excludes (alpha > 0).  Those particles are flagged and get NaN outputs;
+    the wet ones are unaffected."""
+    w = I.small("sigma3d")
+    dry = [(-1.0, I.B_ONE, 0, I.B_ONE, 0), (1.2, I.B_LIN, 0, I.B_ONE, 0)]   # depth 1 - 1.2 x
+    ms = I.MapSpec(kind=I.MAP_SIGMA, Hhat=w.mapspec.Hhat, H=0.0, terms=dry)
+    out, fl = orc.sph2(w.pos, w.vol, w.phi, w.kernel, w.R, ms)
+    depth = 1.0 - 1.2 * w.pos[0]
+    assert np.all((fl & O.F_MAP != 0) == (depth <= 0))
+    assert np.isnan(out[depth <= 0]).all() and np.isfinite(out[depth > 0]).all()
