@@ -37,16 +37,25 @@ I_LAP_TRACE = 31
 F_FEW, F_SINGULAR_A, F_SINGULAR_M, F_NONFINITE, F_DUPLICATE, F_MAP = 1, 2, 4, 8, 16, 32
 
 
-def build(verbose=False):
-    """Compile orc.c into liborc.so (plain gcc, no fused multiply-add)."""
+SAN_FLAGS = ["-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer", "-g"]
+
+
+def build(verbose=False, sanitize=False, out=None):
+    """Compile orc.c into liborc.so (plain gcc, no fused multiply-add).  With
+    sanitize=True the same source is built with AddressSanitizer and
+    UndefinedBehaviorSanitizer into `out` (for a run with the gcc ASan
+    runtime preloaded; ORACLE_LIB names it to lib())."""
     src = os.path.join(HERE, "orc.c")
+    dst = out or (os.path.join(HERE, "liborc_san.so") if sanitize else LIB_PATH)
     cmd = ["gcc", "-O2", "-std=gnu11", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
-           "-fPIC", "-shared", "-Wall", "-Wno-unused-function", src, "-o", LIB_PATH, "-lm"]
+           "-fPIC", "-shared", "-Wall", "-Wno-unused-function", *(SAN_FLAGS if sanitize else []), src, "-o", dst,
+           "-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)
     global _lib
     _lib = None
+    return dst
 
 
 _lib = None
@@ -55,9 +64,10 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB_PATH):
+        path = os.environ.get("ORACLE_LIB") or LIB_PATH
+        if not os.path.exists(path):
             build()
-        L = C.CDLL(LIB_PATH)
+        L = C.CDLL(path)
         dp, ip64, ip32, u8p = (C.POINTER(C.c_double), C.POINTER(C.c_int64),
                                C.POINTER(C.c_int32), C.POINTER(C.c_uint8))
         L.orc_neighbors.restype = C.c_int64

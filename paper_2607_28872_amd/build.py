@@ -27,12 +27,24 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno
           "-I", os.path.join(ROOT, "include")]
 
 
-def build(verbose: bool = False, extra=None) -> str:
-    os.makedirs(BUILD_DIR, exist_ok=True)
-    extra = list(extra or [])
+# Host-side sanitizers for the library's host code (argument checks, map
+# set-up, workspace carving, launch timing); device code is not instrumented.
+HOST_SAN = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined", "-Xarch_host",
+            "-fno-sanitize-recover=all", "-Xarch_host", "-fno-omit-frame-pointer"]
+
+
+def build(verbose: bool = False, extra=None, sanitize_host: bool = False, out=None) -> str:
+    """Compile and link the library.  sanitize_host=True builds the host code
+    with AddressSanitizer and UndefinedBehaviorSanitizer into `out` (default
+    _build/libvct_san.so), for runs with the clang ASan runtime preloaded
+    (VCT_LIB names it to the binding)."""
+    build_dir = os.path.join(BUILD_DIR, "san") if sanitize_host else BUILD_DIR
+    os.makedirs(build_dir, exist_ok=True)
+    extra = list(extra or []) + (HOST_SAN if sanitize_host else [])
+    lib_out = out or (os.path.join(build_dir, "libvct_san.so") if sanitize_host else LIB)
 
     def compile_one(src):
-        obj = os.path.join(BUILD_DIR, os.path.splitext(src)[0] + ".o")
+        obj = os.path.join(build_dir, os.path.splitext(src)[0] + ".o")
         cmd = [HIPCC, *COMMON, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
@@ -45,15 +57,15 @@ def build(verbose: bool = False, extra=None) -> str:
 
     with ThreadPoolExecutor(max_workers=min(len(SOURCES), os.cpu_count() or 4)) as ex:
         objs = list(ex.map(compile_one, SOURCES))
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC, "-shared", f"--offload-arch={ARCH}", *objs, "-o", tmp]
+    tmp = lib_out + ".tmp"
+    cmd = [HIPCC, "-shared", f"--offload-arch={ARCH}", *(HOST_SAN if sanitize_host else []), *objs, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib_out)
+    return lib_out
 
 
 if __name__ == "__main__":

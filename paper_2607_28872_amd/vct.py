@@ -63,10 +63,11 @@ _nlp = C.POINTER(vct_nlist)
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB_PATH):
-            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+        path = os.environ.get("VCT_LIB") or LIB_PATH
+        if not os.path.exists(path):
+            raise RuntimeError(f"{path} is not built; run __graft_entry__.build() "
                                "(the operators have no CPU fallback)")
-        L = C.CDLL(LIB_PATH)
+        L = C.CDLL(path)
         L.vct_status_string.restype = C.c_char_p
         L.vct_status_string.argtypes = [C.c_int]
         L.vct_last_error.restype = C.c_char_p

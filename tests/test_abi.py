@@ -169,6 +169,7 @@ def test_launch_timing_registry_without_launches(L):
 
 
 def test_binding_fails_loudly_without_library(monkeypatch):
+    monkeypatch.delenv("VCT_LIB", raising=False)
     monkeypatch.setattr(vct, "_lib", None)
     monkeypatch.setattr(vct, "LIB_PATH", "/nonexistent/libvct.so")
     with pytest.raises(RuntimeError, match="not built"):
