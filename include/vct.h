@@ -356,15 +356,20 @@ size_t vct_adjoint_workspace_size(int dim, int64_t n, int64_t nnz, int nterms);
  *   dtheta_t = sum_i u_i (d c_trans_i / d coef_t) . D^ phi_i
  *              for every bathymetry term t of `map` (projected positions held
  *              fixed).
- * dphi, two forms, both without atomics and with a fixed summation order
- * (the same bits on every run):
+ * dphi, two forms; each evaluates every weight W_ij once and gives the same
+ * bits on every run (no floating-point atomics):
  *   with nl->col_t: every particle i writes u_i W_ij for its row into the
  *     workspace at the transposed position col_t[e], then every particle k sums
  *     its row of that buffer in row order (the map costs a binary search per
  *     entry to build, so this pays when one geometry serves many adjoints);
- *   without: every particle k walks its own row and rebuilds u_i W_ik from a
- *     128-byte packed record of i (correction matrix and u_i times its
- *     Laplacian row), which it reads per neighbour.
+ *   without (push form; needs nl->chunk_win, VCT_E_ARG otherwise): per
+ *     background-cell column, every particle i adds
+ *     u_i W_ij (and -u_i sum_j W_ij to itself) to accumulators of the
+ *     column's window held in LDS as exact integers: each term is scaled by
+ *     2^k from a per-column bound M on the terms (k = 61 - ilogb(M)), rounded
+ *     and summed in two 64-bit integer parts, so the order of arrival does not
+ *     matter; the column's totals go to one of 3^(d-1) slots per particle,
+ *     summed in slot order.  The rounding of each term is at most 2^-62 M.
  * dtheta: per particle from D^ phi_i, reduced in a fixed order.
  * `state64` must come from vct_moments (or vct_moments_resolve) with out_mask
  * containing VCT_OUT_LAP and either VCT_OUT_PZ or both VCT_OUT_PGRAD and
@@ -373,8 +378,9 @@ size_t vct_adjoint_workspace_size(int dim, int64_t n, int64_t nnz, int nterms);
  * the same state and mask) for the field whose dtheta is wanted; it supplies
  * the projected derivatives that c_trans weights (dz^, z^z^, x^z^, y^z^) and
  * is needed only when dtheta is not NULL.  dphi [n] and
- * dtheta [map->nterms] are device outputs; either may be NULL.  The workspace
- * holds nnz + 17 n doubles and the reduction partials
+ * dtheta [map->nterms] are device outputs; either may be NULL.  A term that
+ * is not finite makes the outputs it reaches NaN.  The workspace holds
+ * nnz + (1 + 3^(d-1)) n doubles and the reduction partials
  * (vct_adjoint_workspace_size, with nnz = nl->nnz).                            */
 int vct_apply_ops_adjoint(const vct_nlist* nl, const double* pos_sorted, const double* vol_sorted, int kernel,
                           const double* state64, uint32_t out_mask, const vct_map* map /* host */,

@@ -6,11 +6,16 @@
 // (P_a,i, P_s,i the first- and second-order parts of particle i's Laplacian
 // row of the state), the field cotangent is
 //   dphi_k = sum_{i in S_k} u_i W_ik  -  sum_{j in S_k} u_k W_kj .
-// Every particle i evaluates u_i W_ij once for its own row, with its own state
-// in registers, and writes it at the transposed position col_t[e] (the entry
-// (j, i) of row j) of a buffer, and its row sum to a second buffer; then every
-// particle k sums its row of the first buffer in row order and subtracts its
-// row sum.  No atomics, a fixed summation order, the same bits on every run.
+// Both forms below evaluate each weight once, with particle i's own state in
+// registers, and sum without floating-point atomics, so every run gives the
+// same bits:
+//   transposed form (needs the transposed-entry map col_t): every particle i
+//     writes u_i W_ij at the transposed position of its entries and its row
+//     sum to a second buffer; every particle k then sums its row of the first
+//     buffer in row order and subtracts its row sum;
+//   push form (no map): every particle adds u_i W_ij to the accumulator of j
+//     in LDS as an exact integer (below), per cell column, and the columns'
+//     totals are summed per particle in a fixed order.
 //
 // Bathymetry coefficients enter only through the VCT coefficients (projected
 // positions are held fixed), so
@@ -49,9 +54,11 @@ struct AdjArgs {
     const int4* cinfo;
     const int32_t* cwin;   // stored windows or NULL
     const int64_t* nchunks;
+    const int64_t* chunk_off;   // [ncols + 1]: first chunk of every column
     int lap_row, nrows;
     int r_gz, r_zz, r_xz, r_yz;   // rows of dz^, z^z^, x^z^, y^z^ (-1 in 2-D) in proj
-    const double* coef;   // [n][kCoef] packed records of the gather form
+    double* partial;   // [3^(d-1)][n] per-source-column totals of the push form
+    int32_t* wide;     // [2 + n / 256 + 2]: count of wide columns, longest row, list of wide columns
     double* wbuf;      // [nnz]: u_i W_ij at the transposed position
     double* rowsum;    // [n]:  u_i sum_j W_ij
     double* dphi;
@@ -72,21 +79,24 @@ __device__ __forceinline__ double adj_weight(const double4& q, const double (&xi
     r[0] = (q.x - xi[0]) * invR;
     r[1] = (q.y - xi[1]) * invR;
     if (D == 3) r[D - 1] = (q.z - xi[2]) * invR;
-    double q2 = 0.0;
+    double q2 = r[0] * r[0];
 #pragma unroll
-    for (int a = 0; a < D; ++a) q2 += r[a] * r[a];
+    for (int a = 1; a < D; ++a) q2 = fma(r[a], r[a], q2);
     double qv[m];
 #pragma unroll
     for (int p = 0; p < m; ++p) qv[p] = r[pair_a<D>(p)] * r[pair_b<D>(p)];
-    double rLr = 0.0, sa = 0.0, ss = 0.0;
+    double rLr = L2[0] * qv[0], sa = Pl[0] * r[0], ss = Pl[D] * qv[0];
 #pragma unroll
-    for (int p = 0; p < nL; ++p) rLr += L2[p] * qv[p];
+    for (int p = 1; p < nL; ++p) rLr = fma(L2[p], qv[p], rLr);
 #pragma unroll
-    for (int a = 0; a < D; ++a) sa += Pl[a] * r[a];
+    for (int a = 1; a < D; ++a) sa = fma(Pl[a], r[a], sa);
 #pragma unroll
-    for (int p = 0; p < m; ++p) ss += Pl[D + p] * qv[p];
-    const double vc = q.w * kernel_shape<KERNEL>(vsqrt(q2));
-    return vc * (sa + rLr * vrcp(q2 * q2) * ss);
+    for (int p = 1; p < m; ++p) ss = fma(Pl[D + p], qv[p], ss);
+    // y = 1/|r~| (refined estimate); |r~| = q2 y and 1/|r~|^4 = (y^2)^2
+    const double y = vrsq(q2);
+    const double y2 = y * y;
+    const double vc = q.w * kernel_shape<KERNEL>(q2 > 0.0 ? q2 * y : 0.0);
+    return vc * fma(rLr * (y2 * y2), ss, sa);
 }
 
 template <int D, int KERNEL>
@@ -196,167 +206,353 @@ __global__ __launch_bounds__(kAThreads, 2) void k_adjoint_weights(AdjArgs A) {
     if (valid && lane == 0) A.rowsum[ii] = sum;
 }
 
-// Gather form (no transposed map): per particle, [L~ (nL, off-diagonals
-// doubled), u P_lap (d + m), 0...] packed in one 128-byte record, so the
-// rebuild of W_ik from row i reads a single cache line per neighbour.
-constexpr int kCoef = 16;
-template <int D>
-__global__ __launch_bounds__(256) void k_adjoint_pack(int64_t n, const double* __restrict__ state, int lap_row,
-                                                      const double* __restrict__ u, double* __restrict__ coef) {
-    using Dm = Dims<D>;
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    double c[kCoef];
-#pragma unroll
-    for (int k = 0; k < kCoef; ++k) c[k] = 0.0;
-#pragma unroll
-    for (int p = 0; p < Dm::nL; ++p)
-        c[p] = (pair_a<D>(p) == pair_b<D>(p) ? 1.0 : 2.0) * state[(int64_t)p * n + i];
-    const double ui = u[i];
-#pragma unroll
-    for (int k = 0; k < Dm::nk; ++k) c[Dm::nL + k] = ui * state[(int64_t)(Dm::nL + lap_row * Dm::nk + k) * n + i];
-    double2* dst = reinterpret_cast<double2*>(coef + i * kCoef);
-#pragma unroll
-    for (int k = 0; k < kCoef / 2; ++k) dst[k] = make_double2(c[2 * k], c[2 * k + 1]);
+// Push form (no transposed map).  Every particle i evaluates u_i W_ij once
+// for each entry of its own row, with its state in registers, and adds it to
+// the accumulator of j; particle j receives these from the particles of the
+// 3^(d-1) cell columns around its own.  One work-group takes one cell column:
+// its accumulators cover the column's window (every particle of the
+// neighbouring columns, all z cells) in LDS, next to the window's records.
+// The self term -u_i sum_j W_ij is added at particle i's own accumulator.  At
+// the end the column writes, for every particle j of its window, its total
+// into slot s of j (s = position of j's column relative to the source
+// column), and k_adjoint_combine sums the slots of each particle in a fixed
+// order.
+//
+// The accumulation is exact and order-free.  With a per-column bound M on the
+// terms (below) and d_max the longest row of the set, every term w is scaled
+// by 2^k, k = 61 - ilogb(M) - bitlen(2 d_max), rounded to the integer
+// X = rint(w 2^k), and added by a 64-bit integer atomic.  The accumulator of
+// particle j receives at most one term per neighbour of j (the neighbour
+// relation is symmetric) and one self term of at most d_max M, so its sum
+// stays below 2^63; integer sums do not depend on the order of arrival, so
+// the result has the same bits on every run.  The total is converted once to
+// FP64 and scaled back.  The resolution 2^-k is at most 2^-52 d_max M, about
+// one FP64 rounding of a sum of d_max terms of size M.
+//
+// Bound: with r~ = r/R (|r~| < 1 inside the support), |q~_p| <= |r~|^2 and
+// |r~' L~ r~| <= (sum |L~|) |r~|^2, so for the kernel shape c~ <= c_max
+//   |u_i W_ij| <= V_j c_max (sum_a |u P_a,i| + (sum |L~_i|) (sum_p |u P_s,i|)).
+constexpr int kPThreads = 1024;   // 128 particles at a time, 8 lanes each
+constexpr int kPAcc = 3840;       // accumulators (and staged records) per pass over a column's window
+constexpr int kPChunks = 24;      // chunk windows of one column held in LDS
+constexpr int kPSlots = 16;       // row entries per lane loaded into registers at a time
+// the int32 side buffer of the push form: count of wide columns, longest row, list of wide columns
+constexpr int kWideCount = 0, kWideMaxDeg = 1, kWideList = 2;
+
+// X = rint(x) as a 64-bit integer when |X| < 2^62 (then true); false for a
+// value out of range or not finite
+__device__ __forceinline__ bool quantize(double x, unsigned long long& X) {
+    const double xs = rint(x);
+    const bool ok = fabs(xs) < 0x1p62;
+    const double v = ok ? xs : 0.0;
+    const double hd = floor(v * 0x1p-32);                       // |hd| < 2^30
+    const unsigned int l = (unsigned int)fma(hd, -0x1p32, v);   // exact, in [0, 2^32)
+    X = ((unsigned long long)(unsigned int)(int)hd << 32) | l;
+    return ok;
 }
 
-// dphi_k = sum_{i in S_k} u_i W_ik - u_k sum_j W_kj, both over the row of k.
-// The chunk's window is walked in sub-windows of kASub particles whose
-// records (position, volume and the packed 128-byte record) are staged in
-// LDS; a row's offsets ascend, so every lane keeps a cursor into its strided
-// share of the row and consumes the entries that fall in the current
-// sub-window.
-// A record is 11 16-byte slots (176 B = 44 banks of 4 B, an odd multiple of
-// 16 B): the lanes reading 16 consecutive records in one LDS pass start on 16
-// different bank quadruples, where a 160-byte record would give 8.
-#ifndef VCT_ASUB
-#define VCT_ASUB 448
-#endif
-#ifndef VCT_DPHI_GROUPS
-#define VCT_DPHI_GROUPS 2
-#endif
-constexpr int kASub = VCT_ASUB;   // records per sub-window: 448 x 176 B, two groups per CU
+template <class T>
+__device__ __forceinline__ T wave_max(T v) {
+    for (int m = 1; m < kWave; m <<= 1) {
+        const T o = __shfl_xor(v, m, kWave);
+        v = o > v ? o : v;
+    }
+    return v;
+}
 
-template <int D, int KERNEL>
-__global__ __launch_bounds__(kAThreads, VCT_DPHI_GROUPS) void k_adjoint_dphi(AdjArgs A) {
+// One column.  FAST = true handles a column whose window fits the
+// accumulators (one pass, records in LDS) and appends any other column to the
+// list `wide` ([0] = count); FAST = false handles a listed column (passes over
+// the window, records read from memory).
+template <int D, int KERNEL, bool FAST>
+__device__ __forceinline__ void push_column(const AdjArgs& A, double* __restrict__ partial, int64_t c,
+                                            int32_t* __restrict__ wide) {
     using Dm = Dims<D>;
     constexpr int nL = Dm::nL, nk = Dm::nk, m = Dm::m;
-    constexpr int kRec = 11;   // double2 per record: (x, y), (z, V), the packed record, one pad
-    __shared__ double2 srec[kASub * kRec];
-    __shared__ WindowT<D> w;
-    __shared__ double sx[kChunk];
-    __shared__ int sord[kChunk];
-    const uint32_t b = xcd_tile(blockIdx.x, gridDim.x);
-    if (b >= *A.nchunks) return;   // uniform over the work-group
+    constexpr int NS = D == 3 ? 9 : 3;
+    constexpr int kW = kPThreads / kWave;
+    __shared__ unsigned long long s_acc[kPAcc];
+    __shared__ double4 s_pos[FAST ? kPAcc : 1];
+    __shared__ uint32_t s_nan[kPAcc / 32];
+    __shared__ WindowT<D> s_cw;
+    __shared__ WindowT<D> s_chw[kPChunks];
+    // per chunk of the current group: range starts in its window (INT_MAX past
+    // the last range) and the shift from its window to the column window
+    __shared__ int s_off[kPChunks][kMaxRanges + 1];
+    __shared__ int s_sh[kPChunks][kMaxRanges];
+    __shared__ int s_slot[kMaxRanges];
+    __shared__ double s_red[2][kW];
+
     const int64_t n = A.n;
-    const int64_t p0 = A.cstart[b], p1 = A.cstart[b + 1];
-    const int np = (int)(p1 - p0);
-    if (threadIdx.x < kWave) {
-        if (A.cwin) window_load<D>(A.cwin, b, w);
-        else chunk_window_wave<D>(A.g, A.cs, A.cinfo[b], w);
-    } else if (threadIdx.x < 2 * kWave) {
-        const int q = threadIdx.x - kWave;
-        if (q < np) sx[q] = A.pos[p0 + q];
-    }
-    __syncthreads();
-    // The waves take the chunk's particles in order of x: a sub-window holds
-    // about one x-layer of the window's columns, so particles with close x
-    // have similar shares of their rows in it, and the cursor loops of a wave
-    // end together (ties by index).
-    if (threadIdx.x < kChunk && (int)threadIdx.x < np) {
-        const int q = threadIdx.x;
-        const double xq = sx[q];
+    const int tid = threadIdx.x;
+    const int wv = tid / kWave;
+    const int64_t nz = grid_nz<D>(A.g);
+    const int64_t b0 = A.chunk_off[c], b1 = A.chunk_off[c + 1];
+    const int nch = (int)(b1 - b0);
+    if (wv == 0) {
+        chunk_window_wave<D>(A.g, A.cs, make_int4((int)c, 0, (int)(nz - 1), 0), s_cw);
+    } else if (tid == kWave) {
+        // relative position of every range's column, in the order of the ranges
         int r = 0;
-        for (int j = 0; j < np; ++j) {
-            const double xj = sx[j];
-            r += (xj < xq || (xj == xq && j < q)) ? 1 : 0;
+        for (int sl = 0; sl < NS; ++sl) {
+            int64_t x, y = 0;
+            if (D == 3) { x = c / A.g.nc[1] + sl / 3 - 1; y = c % A.g.nc[1] + sl % 3 - 1; }
+            else x = c + sl - 1;
+            if (x >= 0 && x < A.g.nc[0] && (D == 2 || (y >= 0 && y < A.g.nc[1]))) s_slot[r++] = sl;
         }
-        sord[r] = q;
     }
     __syncthreads();
-    const int lane = threadIdx.x % kALanes;
-    const int slot = threadIdx.x / kALanes;
-    const bool valid = slot < np;
-    const int64_t k = p0 + (valid ? sord[slot] : 0);
-    const int64_t kk = valid ? k : p0;
-    double xk[3];
+    const int Wc = s_cw.off[s_cw.nr];
+    if (FAST && Wc > kPAcc) {   // uniform: left to the wide pass
+        if (tid == 0) wide[kWideList + atomicAdd(&wide[kWideCount], 1)] = (int32_t)c;
+        return;
+    }
+    int rown = 0;   // the column's own range
+    for (int r = 0; r < kMaxRanges; ++r)
+        if (r < s_cw.nr && s_slot[r] == NS / 2) rown = r;
+    const int64_t q0 = s_cw.gstart[rown];
+
+    // records of the whole window in LDS (FAST), and the column's scale: the
+    // largest volume of the window, the largest per-particle bound and the
+    // longest row of the column's particles
+    double vmax = 0.0, bmax = 0.0;
+    for (int t = tid; t < Wc; t += kPThreads) {
+        const int64_t j = window_global<D>(s_cw, t);
+        const double v = A.vol[j];
+        vmax = fmax(vmax, v);
+        if (FAST) s_pos[t] = make_double4(A.pos[j], A.pos[n + j], D == 3 ? A.pos[2 * n + j] : 0.0, v);
+    }
+    // the first group of chunk windows, loaded alongside
+    for (int cb = wv; cb < (nch < kPChunks ? nch : kPChunks); cb += kW)
+        window_load<D>(A.cwin, (uint32_t)(b0 + cb), s_chw[cb]);
+    const int qlen = s_cw.off[rown + 1] - s_cw.off[rown];
+    for (int q = tid; q < qlen; q += kPThreads) {
+        const int64_t i = q0 + q;
+        double sL = 0.0, sa = 0.0, ss = 0.0;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) xk[a] = a < D ? A.pos[a * n + kk] : 0.0;
-    const double* ck = A.coef + kk * kCoef;
-    double Lk2[nL], Pk[nk];
+        for (int p = 0; p < nL; ++p) sL += (pair_a<D>(p) == pair_b<D>(p) ? 1.0 : 2.0) * fabs(A.state[(int64_t)p * n + i]);
 #pragma unroll
-    for (int p = 0; p < nL; ++p) Lk2[p] = ck[p];
+        for (int a = 0; a < D; ++a) sa += fabs(A.state[(int64_t)(nL + A.lap_row * nk + a) * n + i]);
 #pragma unroll
-    for (int c = 0; c < nk; ++c) Pk[c] = ck[nL + c];   // u_k P_lap,k
-    const double Vk = A.vol[kk];
-    const int64_t re = valid ? A.row_ptr[kk + 1] : 0;
-    int64_t e = (valid ? A.row_ptr[kk] : 0) + lane;
-    int tn = e < re ? (int)A.col16[e] : INT_MAX;
-    const int W = __builtin_amdgcn_readfirstlane(w.off[w.nr]);
-    double acc1 = 0.0, self = 0.0;
-    for (int s0 = 0; s0 < W; s0 += kASub) {
-        const int s1 = W - s0 < kASub ? W : s0 + kASub;
-        if (s0 > 0) __syncthreads();   // the previous sub-window is consumed
-        for (int t = s0 + (int)threadIdx.x; t < s1; t += kAThreads) {
-            const int64_t j = window_global<D>(w, t);
-            double2* dst = srec + (t - s0) * kRec;
-            dst[0] = make_double2(A.pos[j], A.pos[n + j]);
-            dst[1] = make_double2(D == 3 ? A.pos[2 * n + j] : 0.0, A.vol[j]);
-            const double2* src = reinterpret_cast<const double2*>(A.coef + j * kCoef);
+        for (int p = 0; p < m; ++p) ss += fabs(A.state[(int64_t)(nL + A.lap_row * nk + D + p) * n + i]);
+        const double bnd = fabs(A.u[i]) * (sa + sL * ss);
+        if (bnd <= 1.7976931348623157e308) bmax = fmax(bmax, bnd);   // skips NaN and infinity
+    }
+    vmax = wave_max(vmax);
+    bmax = wave_max(bmax);
+    if (tid % kWave == 0) {
+        s_red[0][wv] = vmax;
+        s_red[1][wv] = bmax;
+    }
+    __syncthreads();
+    vmax = 0.0;
+    bmax = 0.0;
 #pragma unroll
-            for (int c = 0; c < kCoef / 2; ++c) dst[2 + c] = src[c];
+    for (int w = 0; w < kW; ++w) {
+        vmax = fmax(vmax, s_red[0][w]);
+        bmax = fmax(bmax, s_red[1][w]);
+    }
+    const double cmax = KERNEL == VCT_KERNEL_WENDLAND_C2 ? 1.0 : 3.0;
+    const double Mb = vmax * cmax * 1.0625 * bmax;   // the factor covers |r~| rounded above 1
+    // terms reaching one accumulator: at most one per neighbour of its
+    // particle, plus the self term of at most (longest row) x M
+    const double nterm = 2.0 * (double)wide[kWideMaxDeg];
+    const int k = (Mb > 0.0 && Mb <= 1.7976931348623157e308) ? 61 - ilogb(Mb) - (ilogb(fmax(nterm, 1.0)) + 1) : 0;
+
+    const int lane = tid % kALanes;
+    const int slot = tid / kALanes;
+    constexpr int kBatch = kPThreads / kALanes;
+
+    // one particle's row
+    auto rows = [&](int cb, int64_t ii, bool valid, int q, int t0, int tn) {
+        double xi[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) xi[a] = a < D ? A.pos[a * n + ii] : 0.0;
+        double L2[nL], Pl[nk];
+        const double ui = A.u[ii];
+#pragma unroll
+        for (int p = 0; p < nL; ++p)
+            L2[p] = (pair_a<D>(p) == pair_b<D>(p) ? 1.0 : 2.0) * A.state[(int64_t)p * n + ii];
+#pragma unroll
+        for (int cc = 0; cc < nk; ++cc) Pl[cc] = ui * A.state[(int64_t)(nL + A.lap_row * nk + cc) * n + ii];
+        const int tci = s_cw.off[rown] + q - t0;   // the particle's own accumulator
+        const bool self_in = valid && (FAST || (unsigned)tci < (unsigned)tn);
+        const int64_t rb = valid ? A.row_ptr[ii] : 0, re = valid ? A.row_ptr[ii + 1] : 0;
+        // every lane takes a contiguous block of the row
+        const int nb = (int)((re - rb + kALanes - 1) / kALanes);
+        const int64_t lb = rb + (int64_t)lane * nb;
+        const int64_t le = lb + nb < re ? lb + nb : re;
+        // range cursor: the entries ascend, so the range only moves forward;
+        // it starts at the range of the block's first entry
+        int r = 0;
+        if (lb < le) {
+            const int t0e = A.col16[lb];
+#pragma unroll
+            for (int kk = 1; kk < kMaxRanges; ++kk) r += t0e >= s_off[cb][kk] ? 1 : 0;
+        }
+        int nxt = s_off[cb][r + 1];
+        int sh = s_sh[cb][r];
+        auto column_offset = [&](int t) {   // window offset of the chunk -> of the column
+            while (t >= nxt) {
+                ++r;
+                nxt = s_off[cb][r + 1];
+                sh = s_sh[cb][r];
+            }
+            return t + sh;
+        };
+        double rowsum = 0.0;
+        // the block in pieces of kPSlots entries, each piece's offsets loaded
+        // together (two 16-bit offsets per register) before any is used
+        for (int64_t eb = lb; eb < le; eb += kPSlots) {
+            const int cnt = (int)(le - eb < kPSlots ? le - eb : kPSlots);
+            uint32_t cpk[kPSlots / 2];
+#pragma unroll
+            for (int s2 = 0; s2 < kPSlots; ++s2) {
+                const int64_t e = eb + s2;
+                const uint32_t cv = e < le ? (uint32_t)A.col16[e] : 0u;
+                if (s2 % 2 == 0) cpk[s2 / 2] = cv;
+                else cpk[s2 / 2] |= cv << 16;
+            }
+            // fully unrolled: the slots past the block's end are masked
+#pragma unroll
+            for (int s2 = 0; s2 < kPSlots; ++s2) {
+                if (s2 < cnt) {
+                    const int tg = column_offset((int)((cpk[s2 / 2] >> (16 * (s2 % 2))) & 0xffffu));
+                    const int tc = tg - t0;
+                    const bool here = FAST || (unsigned)tc < (unsigned)tn;
+                    if (here || self_in) {
+                        double4 qv;
+                        if (FAST) {
+                            qv = s_pos[tg];
+                        } else {
+                            const int64_t j = s_cw.gstart[r] + (tg - s_cw.off[r]);
+                            qv = make_double4(A.pos[j], A.pos[n + j], D == 3 ? A.pos[2 * n + j] : 0.0, A.vol[j]);
+                        }
+                        const double wij = adj_weight<D, KERNEL>(qv, xi, A.invR, L2, Pl);
+                        rowsum += wij;
+                        if (here) {
+                            unsigned long long X;
+                            if (quantize(ldexp(wij, k), X)) atomicAdd(&s_acc[tc], X);
+                            else atomicOr(&s_nan[tc >> 5], 1u << (tc & 31));
+                        }
+                    }
+                }
+            }
+        }
+        rowsum = group_sum(rowsum, kALanes);
+        if (self_in && lane == 0) {
+            unsigned long long X;
+            if (quantize(ldexp(-rowsum, k), X)) atomicAdd(&s_acc[tci], X);
+            else atomicOr(&s_nan[tci >> 5], 1u << (tci & 31));
+        }
+    };
+
+    // passes over the column window (one unless it exceeds the accumulators)
+    for (int t0 = 0; t0 < Wc; t0 += kPAcc) {
+        const int tn = Wc - t0 < kPAcc ? Wc - t0 : kPAcc;
+        for (int t = tid; t < tn; t += kPThreads) s_acc[t] = 0ull;
+        for (int t = tid; t < (tn + 31) / 32; t += kPThreads) s_nan[t] = 0u;
+        // the column's chunks, kPChunks at a time
+        for (int g0 = 0; g0 < nch; g0 += kPChunks) {
+            const int ncl = nch - g0 < kPChunks ? nch - g0 : kPChunks;
+            if (g0 > 0 || (t0 > 0 && nch > kPChunks)) {   // else the prologue loaded them
+                __syncthreads();   // the previous group's tables consumed
+                for (int cb = wv; cb < ncl; cb += kW) window_load<D>(A.cwin, (uint32_t)(b0 + g0 + cb), s_chw[cb]);
+            }
+            __syncthreads();   // windows loaded; accumulators cleared
+            if (tid < ncl * (kMaxRanges + 1)) {
+                const int cb = tid / (kMaxRanges + 1), r = tid % (kMaxRanges + 1);
+                const WindowT<D>& w = s_chw[cb];   // both windows list the same columns in the same order
+                s_off[cb][r] = r < w.nr ? w.off[r] : INT_MAX;
+                if (r < kMaxRanges)
+                    s_sh[cb][r] = r < w.nr ? s_cw.off[r] - w.off[r] + (int)(w.gstart[r] - s_cw.gstart[r]) : 0;
+            }
+            __syncthreads();
+            const int qa = (int)(A.cstart[b0 + g0] - q0), qb = (int)(A.cstart[b0 + g0 + ncl] - q0);
+            // the group's particles, 128 at a time; the waves run independently
+            for (int q = qa + slot; q - slot < qb; q += kBatch) {
+                const bool valid = q < qb;
+                const int64_t ii = q0 + (valid ? q : qa);
+                int cb = 0;   // the particle's chunk within the group
+                for (int kk = 1; kk < ncl; ++kk)
+                    if ((int64_t)A.cstart[b0 + g0 + kk] <= ii) cb = kk;
+                rows(cb, ii, valid, q, t0, tn);
+            }
         }
         __syncthreads();
-        while (tn < s1) {
-            const double2* rec = srec + (tn - s0) * kRec;
-            e += kALanes;
-            tn = e < re ? (int)A.col16[e] : INT_MAX;
-            const double2 qa = rec[0], qb = rec[1];
-            const double4 q = make_double4(qa.x, qa.y, qb.x, qb.y);
-            double ci[kCoef];
+        // this pass's totals, into the slot of each destination
+        for (int t = tid; t < tn; t += kPThreads) {
+            const int tt = t0 + t;
+            int r = 0;
 #pragma unroll
-            for (int c = 0; c < kCoef / 2; ++c) {
-                const double2 v = rec[2 + c];
-                ci[2 * c] = v.x;
-                ci[2 * c + 1] = v.y;
-            }
-            double r[D];   // r~_ki
-            r[0] = (q.x - xk[0]) * A.invR;
-            r[1] = (q.y - xk[1]) * A.invR;
-            if (D == 3) r[D - 1] = (q.z - xk[2]) * A.invR;
-            double q2 = 0.0;
-#pragma unroll
-            for (int a = 0; a < D; ++a) q2 += r[a] * r[a];
-            double qv[m];
-#pragma unroll
-            for (int p = 0; p < m; ++p) qv[p] = r[pair_a<D>(p)] * r[pair_b<D>(p)];
-            const double c = kernel_shape<KERNEL>(vsqrt(q2));
-            const double iq4 = vrcp(q2 * q2);
-            double rLk = 0.0, rLi = 0.0, sak = 0.0, ssk = 0.0, sai = 0.0, ssi = 0.0;
-#pragma unroll
-            for (int p = 0; p < nL; ++p) {
-                rLk += Lk2[p] * qv[p];
-                rLi += ci[p] * qv[p];
-            }
-#pragma unroll
-            for (int a = 0; a < D; ++a) {
-                sak += Pk[a] * r[a];
-                sai += ci[nL + a] * r[a];
-            }
-#pragma unroll
-            for (int p = 0; p < m; ++p) {
-                ssk += Pk[D + p] * qv[p];
-                ssi += ci[nL + D + p] * qv[p];
-            }
-            // u_k W_ki (row k: volume V_i, correction of k) and u_i W_ik (row i:
-            // r~_ik = -r~_ki, volume V_k, correction of i)
-            self += q.w * c * (sak + rLk * iq4 * ssk);
-            acc1 += Vk * c * (rLi * iq4 * ssi - sai);
+            for (int kk = 1; kk < kMaxRanges; ++kk)
+                if (kk < s_cw.nr && tt >= s_cw.off[kk]) r = kk;
+            const int64_t j = s_cw.gstart[r] + (tt - s_cw.off[r]);
+            const unsigned long long X = s_acc[t];
+            const double hv = (double)(int)(unsigned int)(X >> 32), lv = (double)(unsigned int)X;
+            double v = ldexp(fma(hv, 0x1p32, lv), -k);
+            if ((s_nan[t >> 5] >> (t & 31)) & 1u) v = __builtin_nan("");
+            partial[(int64_t)s_slot[r] * n + j] = v;
         }
+        __syncthreads();
     }
-    acc1 = group_sum(acc1, kALanes);
-    self = group_sum(self, kALanes);
-    if (valid && lane == 0) A.dphi[kk] = acc1 - self;
+}
+
+template <int D, int KERNEL>
+__global__ __launch_bounds__(kPThreads, 1) void k_adjoint_push(AdjArgs A, double* __restrict__ partial,
+                                                               int32_t* __restrict__ wide) {
+    const int64_t c = xcd_tile(blockIdx.x, gridDim.x);
+    if (c >= grid_ncols<D>(A.g)) return;   // uniform over the work-group
+    push_column<D, KERNEL, true>(A, partial, c, wide);
+}
+
+// the listed wide columns, taken in turn by a fixed grid
+template <int D, int KERNEL>
+__global__ __launch_bounds__(kPThreads, 1) void k_adjoint_push_wide(AdjArgs A, double* __restrict__ partial,
+                                                                    int32_t* __restrict__ wide) {
+    const int cnt = wide[kWideCount];
+    for (int w = blockIdx.x; w < cnt; w += gridDim.x) {
+        push_column<D, KERNEL, false>(A, partial, wide[kWideList + w], wide);
+        __syncthreads();
+    }
+}
+
+// the longest row of the set, into wide[kWideMaxDeg] (zeroed before)
+__global__ __launch_bounds__(256) void k_adjoint_maxdeg(int64_t n, const int64_t* __restrict__ row_ptr,
+                                                        int32_t* __restrict__ wide) {
+    int d = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t di = row_ptr[i + 1] - row_ptr[i];
+        d = di > d ? (int)(di < INT_MAX ? di : INT_MAX) : d;
+    }
+    d = wave_max(d);
+    if (threadIdx.x % kWave == 0) atomicMax(&wide[kWideMaxDeg], d);
+}
+
+__global__ void k_zero_wide(int32_t* p) {
+    p[kWideCount] = 0;
+    p[kWideMaxDeg] = 0;
+}
+
+// dphi_j = sum of the slots of j, in slot order, over the source columns that
+// exist (the column of j minus each relative position)
+template <int D>
+__global__ __launch_bounds__(256) void k_adjoint_combine(int64_t n, Grid g, const double* __restrict__ pos,
+                                                         const double* __restrict__ partial,
+                                                         double* __restrict__ dphi) {
+    constexpr int NS = D == 3 ? 9 : 3;
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const int64_t cx = cell_coord(pos[j], g.lo[0], g.inv_cs[0], g.nc[0]);
+    const int64_t cy = D == 3 ? cell_coord(pos[n + j], g.lo[1], g.inv_cs[1], g.nc[1]) : 0;
+    double s = 0.0;
+#pragma unroll
+    for (int sl = 0; sl < NS; ++sl) {
+        const int64_t sx = cx - (D == 3 ? sl / 3 - 1 : sl - 1);
+        const int64_t sy = cy - (D == 3 ? sl % 3 - 1 : 0);
+        if (sx >= 0 && sx < g.nc[0] && (D == 2 || (sy >= 0 && sy < g.nc[1]))) s += partial[(int64_t)sl * n + j];
+    }
+    dphi[j] = s;
 }
 
 // Pass 2: dphi_k = (row k of the transposed buffer, summed in row order) - rowsum_k.
@@ -498,10 +694,19 @@ static int launch_adjoint(AdjArgs a, int64_t cap, const MapParams& mp, double* d
                    s, n, a.row_ptr, a.wbuf, a.rowsum, a.dphi);
         VCT_LAUNCH_CHECK();
     } else if (a.dphi) {
-        VCT_LAUNCH("k_adjoint_pack", (k_adjoint_pack<D>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n,
-                   a.state, a.lap_row, a.u, const_cast<double*>(a.coef));
+        const int64_t ncols = D == 3 ? a.g.nc[0] * a.g.nc[1] : a.g.nc[0];
+        VCT_LAUNCH("k_zero_wide", k_zero_wide, dim3(1), dim3(1), 0, s, a.wide);
         VCT_LAUNCH_CHECK();
-        VCT_LAUNCH("k_adjoint_dphi", (k_adjoint_dphi<D, KERNEL>), dim3((unsigned)cap), dim3(kAThreads), 0, s, a);
+        VCT_LAUNCH("k_adjoint_maxdeg", k_adjoint_maxdeg, dim3(512), dim3(256), 0, s, n, a.row_ptr, a.wide);
+        VCT_LAUNCH_CHECK();
+        VCT_LAUNCH("k_adjoint_push", (k_adjoint_push<D, KERNEL>), dim3((unsigned)ncols), dim3(kPThreads), 0, s, a,
+                   a.partial, a.wide);
+        VCT_LAUNCH_CHECK();
+        VCT_LAUNCH("k_adjoint_push (wide)", (k_adjoint_push_wide<D, KERNEL>), dim3(256), dim3(kPThreads), 0, s, a,
+                   a.partial, a.wide);
+        VCT_LAUNCH_CHECK();
+        VCT_LAUNCH("k_adjoint_combine", (k_adjoint_combine<D>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                   n, a.g, a.pos, a.partial, a.dphi);
         VCT_LAUNCH_CHECK();
     }
     if (dtheta && mp.nterms > 0) {
@@ -525,12 +730,17 @@ __global__ void k_zero_f64(double* p, int64_t cnt) {
 
 using namespace vct;
 
+// Columns whose window exceeds kPAcc particles: each particle lies in at most
+// 3^(d-1) <= 9 windows, so there are fewer than 9 n / kPAcc < n / 256 of them.
+static int64_t wide_list_len(int64_t n) { return n / 256 + 2; }
+
 extern "C" size_t vct_adjoint_workspace_size(int dim, int64_t n, int64_t nnz, int nterms) {
     if ((dim != 2 && dim != 3) || n < 0 || nnz < 0 || nterms < 0) return 0;
     const int64_t nred = (n + kRedThreads - 1) / kRedThreads;
+    const int ns = dim == 3 ? 9 : 3;
     return aligned_sum({(size_t)(nred > 0 ? nred : 1) * (nterms > 0 ? nterms : 1) * 8,
                         (size_t)(nnz > 0 ? nnz : 1) * sizeof(double), (size_t)(n > 0 ? n : 1) * sizeof(double),
-                        (size_t)(n > 0 ? n : 1) * kCoef * sizeof(double)});
+                        (size_t)(n > 0 ? n : 1) * ns * sizeof(double), (size_t)(wide_list_len(n) + kWideList) * 4});
 }
 
 extern "C" int vct_apply_ops_adjoint(const vct_nlist* nl, const double* pos_sorted, const double* vol_sorted,
@@ -560,6 +770,7 @@ extern "C" int vct_apply_ops_adjoint(const vct_nlist* nl, const double* pos_sort
         return VCT_OK;
     }
     if (!pos_sorted || !vol_sorted || !nl->col16 || !state64 || !u) return VCT_E_ARG;
+    if (dphi && !nl->col_t && !nl->chunk_win) return VCT_E_ARG;   // the push form reads the stored windows
     if (dtheta && !proj) return VCT_E_ARG;
     const int64_t nnz = (dphi && nl->col_t) ? nl->nnz : 0;   // the buffer is indexed by entries
     if (nnz < 0) return VCT_E_ARG;
@@ -569,7 +780,8 @@ extern "C" int vct_apply_ops_adjoint(const vct_nlist* nl, const double* pos_sort
     double* partials = cv.take<double>((size_t)nred * (mp.nterms > 0 ? mp.nterms : 1));
     double* wbuf = cv.take<double>((size_t)(nnz > 0 ? nnz : 1));
     double* rowsum = cv.take<double>((size_t)n);
-    double* coef = cv.take<double>((size_t)n * kCoef);
+    double* partial = cv.take<double>((size_t)n * (dim == 3 ? 9 : 3));
+    int32_t* wide = cv.take<int32_t>((size_t)(wide_list_len(n) + kWideList));
     const int64_t ncols = dim == 3 ? g.nc[0] * g.nc[1] : g.nc[0];
     AdjArgs a;
     a.n = n; a.invR = 1.0 / nl->R; a.g = g; a.pos = pos_sorted; a.vol = vol_sorted; a.state = state64; a.u = u;
@@ -577,6 +789,7 @@ extern "C" int vct_apply_ops_adjoint(const vct_nlist* nl, const double* pos_sort
     a.cstart = nl->chunk_start; a.cinfo = reinterpret_cast<const int4*>(nl->chunk_info);
     a.cwin = nl->chunk_win;
     a.nchunks = nl->chunk_off + ncols;
+    a.chunk_off = nl->chunk_off;
     a.lap_row = group_row(dim, out_mask, VCT_OUT_LAP);
     if (pz) {
         const int r = group_row(dim, out_mask, VCT_OUT_PZ);
@@ -589,7 +802,7 @@ extern "C" int vct_apply_ops_adjoint(const vct_nlist* nl, const double* pos_sort
         a.r_yz = dim == 3 ? rh + 5 : -1;
     }
     a.nrows = n_out_rows(dim, out_mask);
-    a.wbuf = wbuf; a.rowsum = rowsum; a.coef = coef; a.dphi = dphi;
+    a.wbuf = wbuf; a.rowsum = rowsum; a.partial = partial; a.wide = wide; a.dphi = dphi;
     const int64_t cap = ncols + n / kChunk + 1;
     if (dim == 2)
         st = (kernel == VCT_KERNEL_WENDLAND_C2)

@@ -73,10 +73,10 @@ def test_resolved_state_gives_the_same_bits(c4):
     assert torch.equal(gt1, gt2)
 
 
-def test_gather_and_transposed_forms_agree(c4):
+def test_push_and_transposed_forms_agree(c4):
     g = c4["g"]
     gp1, gt1 = _grads(c4, True)
-    saved, g.nl.col_t = g.nl.col_t, None       # the gather form
+    saved, g.nl.col_t = g.nl.col_t, None       # the push form
     try:
         gp2, gt2 = _grads(c4, True)
     finally:
