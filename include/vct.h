@@ -387,6 +387,34 @@ int vct_apply_ops_adjoint(const vct_nlist* nl, const double* pos_sorted, const d
                           const double* proj, const double* u, double* dphi, double* dtheta, void* ws,
                           size_t ws_bytes, void* stream);
 
+/* ---------------------------------------------------------------- allocation-free adjoint */
+
+/* Size of the library's own scratch for vct_apply_ops_adjoint_noalloc. */
+#define VCT_NOALLOC_SCRATCH_BYTES (64ull << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * computation as vct_apply_ops_adjoint in its push form (nl->col_t is
+ * ignored; nl->chunk_win is required when dphi is requested), with the
+ * workspace taken from a fixed scratch array inside the library instead of a
+ * caller buffer.  The caller still passes every input and output.  No device
+ * memory is allocated or freed, and no allocating library routine is called.
+ *   - Limit: vct_adjoint_workspace_size(dim, n, 0, nterms) must not exceed
+ *     VCT_NOALLOC_SCRATCH_BYTES (64 MiB: about 830,000 particles in 3-D and
+ *     2,000,000 in 2-D); larger sets return VCT_E_CAPACITY before any HIP
+ *     call.
+ *   - The scratch of the CURRENT device is used (the stream must belong to
+ *     it).  Each device holds one copy for the life of the process; its
+ *     address is looked up on the first call on that device.
+ *   - Every call on one device shares that device's scratch, and a call
+ *     leaves its contents behind (the next call clears what it needs).  Calls
+ *     that overlap on one device race: serialise them (one stream, or events).
+ * Results are bit-identical to vct_apply_ops_adjoint's push form on the same
+ * inputs.                                                                      */
+int vct_apply_ops_adjoint_noalloc(const vct_nlist* nl, const double* pos_sorted, const double* vol_sorted,
+                                  int kernel, const double* state64, uint32_t out_mask, const vct_map* map /* host */,
+                                  const double* proj, const double* u, double* dphi, double* dtheta, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -25,6 +25,8 @@
 // and d h^(k) / d coef_t the t-th term's basis products.  Per-particle
 // contributions are reduced per work-group, then across work-groups, in a
 // fixed order.
+#include <mutex>
+
 #include "common.h"
 #include "map_dev.h"
 #include "tiles.h"
@@ -743,10 +745,12 @@ extern "C" size_t vct_adjoint_workspace_size(int dim, int64_t n, int64_t nnz, in
                         (size_t)(n > 0 ? n : 1) * ns * sizeof(double), (size_t)(wide_list_len(n) + kWideList) * 4});
 }
 
-extern "C" int vct_apply_ops_adjoint(const vct_nlist* nl, const double* pos_sorted, const double* vol_sorted,
-                                     int kernel, const double* state64, uint32_t out_mask, const vct_map* map,
-                                     const double* proj, const double* u, double* dphi, double* dtheta, void* ws,
-                                     size_t ws_bytes, void* stream) {
+// The body of both adjoint entry points; push_only ignores a transposed-entry
+// map (the allocation-free variant has no room for its entry buffer).
+static int adjoint_run(const vct_nlist* nl, const double* pos_sorted, const double* vol_sorted, int kernel,
+                       const double* state64, uint32_t out_mask, const vct_map* map, const double* proj,
+                       const double* u, double* dphi, double* dtheta, void* ws, size_t ws_bytes, bool push_only,
+                       void* stream) {
     // the Laplacian row, and dz^, z^z^, x^z^ (y^z^) from PZ or from PGRAD + PHESS
     const bool pz = (out_mask & VCT_OUT_PZ) != 0;
     const bool pgh = (out_mask & (VCT_OUT_PGRAD | VCT_OUT_PHESS)) == (VCT_OUT_PGRAD | VCT_OUT_PHESS);
@@ -770,9 +774,10 @@ extern "C" int vct_apply_ops_adjoint(const vct_nlist* nl, const double* pos_sort
         return VCT_OK;
     }
     if (!pos_sorted || !vol_sorted || !nl->col16 || !state64 || !u) return VCT_E_ARG;
-    if (dphi && !nl->col_t && !nl->chunk_win) return VCT_E_ARG;   // the push form reads the stored windows
+    const int32_t* col_t = push_only ? nullptr : nl->col_t;
+    if (dphi && !col_t && !nl->chunk_win) return VCT_E_ARG;   // the push form reads the stored windows
     if (dtheta && !proj) return VCT_E_ARG;
-    const int64_t nnz = (dphi && nl->col_t) ? nl->nnz : 0;   // the buffer is indexed by entries
+    const int64_t nnz = (dphi && col_t) ? nl->nnz : 0;   // the buffer is indexed by entries
     if (nnz < 0) return VCT_E_ARG;
     if (!ws || ws_bytes < vct_adjoint_workspace_size(dim, n, nnz, mp.nterms)) return VCT_E_WORKSPACE;
     Carver cv(ws, ws_bytes);
@@ -785,7 +790,7 @@ extern "C" int vct_apply_ops_adjoint(const vct_nlist* nl, const double* pos_sort
     const int64_t ncols = dim == 3 ? g.nc[0] * g.nc[1] : g.nc[0];
     AdjArgs a;
     a.n = n; a.invR = 1.0 / nl->R; a.g = g; a.pos = pos_sorted; a.vol = vol_sorted; a.state = state64; a.u = u;
-    a.proj = proj; a.row_ptr = nl->row_ptr; a.col16 = nl->col16; a.col_t = nl->col_t; a.cs = nl->cell_start;
+    a.proj = proj; a.row_ptr = nl->row_ptr; a.col16 = nl->col16; a.col_t = col_t; a.cs = nl->cell_start;
     a.cstart = nl->chunk_start; a.cinfo = reinterpret_cast<const int4*>(nl->chunk_info);
     a.cwin = nl->chunk_win;
     a.nchunks = nl->chunk_off + ncols;
@@ -813,4 +818,59 @@ extern "C" int vct_apply_ops_adjoint(const vct_nlist* nl, const double* pos_sort
                  ? launch_adjoint<3, VCT_KERNEL_WENDLAND_C2>(a, cap, mp, dtheta, partials, s)
                  : launch_adjoint<3, VCT_KERNEL_CUBIC_SPLINE>(a, cap, mp, dtheta, partials, s);
     return st;
+}
+
+extern "C" int vct_apply_ops_adjoint(const vct_nlist* nl, const double* pos_sorted, const double* vol_sorted,
+                                     int kernel, const double* state64, uint32_t out_mask, const vct_map* map,
+                                     const double* proj, const double* u, double* dphi, double* dtheta, void* ws,
+                                     size_t ws_bytes, void* stream) {
+    return adjoint_run(nl, pos_sorted, vol_sorted, kernel, state64, out_mask, map, proj, u, dphi, dtheta, ws,
+                       ws_bytes, false, stream);
+}
+
+// ------------------------------------------------------------------ allocation-free variant
+
+// Scratch of vct_apply_ops_adjoint_noalloc.  Every GPU the library runs on
+// holds its own copy until the process ends.  In host code the name `scratch`
+// is a host-side stand-in, not a device address: host code only ever uses the
+// address hipGetSymbolAddress returns on each device.
+static __device__ __align__(256) unsigned char scratch[VCT_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+// the current device's copy of `scratch`, looked up once per device
+static int scratch_on_current_device(void** out) {
+    int dev = -1;
+    VCT_HIP_CHECK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return VCT_E_ARG;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        VCT_HIP_CHECK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return VCT_E_HIP;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return VCT_OK;
+}
+
+extern "C" int vct_apply_ops_adjoint_noalloc(const vct_nlist* nl, const double* pos_sorted, const double* vol_sorted,
+                                             int kernel, const double* state64, uint32_t out_mask, const vct_map* map,
+                                             const double* proj, const double* u, double* dphi, double* dtheta,
+                                             void* stream) {
+    if (!nl || (nl->dim != 2 && nl->dim != 3) || nl->n < 0 || !map || map->nterms < 0 ||
+        map->nterms > VCT_MAX_TERMS)
+        return VCT_E_ARG;
+    // the push form's workspace (no entry buffer) must fit the scratch
+    if (vct_adjoint_workspace_size(nl->dim, nl->n, 0, map->nterms) > (size_t)VCT_NOALLOC_SCRATCH_BYTES)
+        return VCT_E_CAPACITY;
+    void* ws = nullptr;
+    const int st = scratch_on_current_device(&ws);
+    if (st) return st;
+    return adjoint_run(nl, pos_sorted, vol_sorted, kernel, state64, out_mask, map, proj, u, dphi, dtheta, ws,
+                       (size_t)VCT_NOALLOC_SCRATCH_BYTES, true, stream);
 }

@@ -116,6 +116,9 @@ def lib():
         L.vct_apply_ops_adjoint.restype = C.c_int
         L.vct_apply_ops_adjoint.argtypes = [_nlp, _vp, _vp, C.c_int, _vp, C.c_uint32, C.POINTER(vct_map), _vp, _vp,
                                             _vp, _vp, _vp, _sz, _vp]
+        L.vct_apply_ops_adjoint_noalloc.restype = C.c_int
+        L.vct_apply_ops_adjoint_noalloc.argtypes = [_nlp, _vp, _vp, C.c_int, _vp, C.c_uint32, C.POINTER(vct_map), _vp,
+                                                    _vp, _vp, _vp, _vp]
         _lib = L
     return _lib
 
@@ -279,6 +282,13 @@ def vct_apply_ops_adjoint(nl, pos_sorted, vol_sorted, kernel, state64, mask, cma
     return _check("vct_apply_ops_adjoint", lib().vct_apply_ops_adjoint(
         C.byref(nl), _p(pos_sorted), _p(vol_sorted), kernel, _p(state64), mask, C.byref(cmap), _p(proj), _p(u),
         _p(dphi), _p(dtheta), _p(ws), _nbytes(ws), _stream(stream)))
+
+
+def vct_apply_ops_adjoint_noalloc(nl, pos_sorted, vol_sorted, kernel, state64, mask, cmap, proj, u, dphi, dtheta,
+                                  stream=None):
+    return _check("vct_apply_ops_adjoint_noalloc", lib().vct_apply_ops_adjoint_noalloc(
+        C.byref(nl), _p(pos_sorted), _p(vol_sorted), kernel, _p(state64), mask, C.byref(cmap), _p(proj), _p(u),
+        _p(dphi), _p(dtheta), _stream(stream)))
 
 
 # ---------------------------------------------------------------- orchestration
