@@ -92,6 +92,21 @@ def lib():
                                      C.c_double, C.c_double, C.c_int, dp, dp]
         L.orc_kernel_eval.restype = None
         L.orc_kernel_eval.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, dp, dp]
+        L.orc_lap_weights.restype = C.c_int
+        L.orc_lap_weights.argtypes = [C.c_int, C.c_int64, dp, dp, C.c_int, C.c_double, C.c_int, C.c_double,
+                                      C.c_double, C.c_double, C.c_double, C.c_int, dp, C.c_int, C.c_int64, ip64,
+                                      ip64, ip32, dp, u8p]
+        L.orc_ppe_rhs.restype = C.c_int
+        L.orc_ppe_rhs.argtypes = [C.c_int, C.c_int64, dp, dp, C.c_int, C.c_double, C.c_int, C.c_double, C.c_double,
+                                  C.c_double, C.c_double, C.c_int, dp, dp, C.c_double, C.c_double, C.c_double, dp,
+                                  u8p, dp, ip64, ip32, dp, dp, dp]
+        L.orc_ppe_correct.restype = C.c_int
+        L.orc_ppe_correct.argtypes = [C.c_int, C.c_int64, dp, dp, C.c_int, C.c_double, C.c_int, C.c_double,
+                                      C.c_double, C.c_double, C.c_double, C.c_int, dp, dp, dp, C.c_double,
+                                      C.c_double, ip64, ip32, dp]
+        L.orc_ppe_bicgstab.restype = C.c_int
+        L.orc_ppe_bicgstab.argtypes = [C.c_int64, ip64, ip32, dp, u8p, dp, dp, C.c_double, C.c_int,
+                                       C.POINTER(C.c_int), C.POINTER(C.c_double)]
         L.orc_threads.restype = C.c_int
         L.orc_set_threads.restype = None
         L.orc_set_threads.argtypes = [C.c_int]
@@ -229,3 +244,93 @@ def alpha_beta(dim, x, y, mapspec):
     kind, Hh, H, dmin, eps, nt, terms = _map_args(mapspec)
     lib().orc_alpha_beta(dim, x.shape[0], _p(x), _p(y), kind, Hh, H, dmin, eps, nt, _p(terms), _p(out))
     return out
+
+
+# ---------------------------------------------------------------- ISPH pressure step (Sec. 3.3)
+
+def _csr(pos, R, csr):
+    if csr is None:
+        csr = neighbors(pos, R)
+    rp, col = csr
+    return np.ascontiguousarray(rp, dtype=np.int64), np.ascontiguousarray(col, dtype=np.int32)
+
+
+def _u8(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.uint8)
+
+
+def lap_weights(pos, vol, kernel, R, mapspec, csr=None, grad_order=2):
+    """Weights W (CSR layout of `csr`) of the physical Laplacian,
+    lap_i = sum_j W_ij (phi_j - phi_i), and per-particle flags."""
+    pos, vol = _f64(pos), _f64(vol)
+    dim, n = pos.shape
+    rp, col = _csr(pos, R, csr)
+    W = np.zeros(max(col.shape[0], 1))
+    flags = np.zeros(n, dtype=np.uint8)
+    kind, Hh, H, dmin, eps, nt, terms = _map_args(mapspec)
+    st = lib().orc_lap_weights(dim, n, _p(pos), _p(vol), int(kernel), float(R), kind, Hh, H, dmin, eps, nt,
+                               _p(terms), int(grad_order), n, None, _p(rp, C.c_int64),
+                               _p(col if col.size else np.zeros(1, np.int32), C.c_int32), _p(W), _p(flags, C.c_uint8))
+    if st != 0:
+        raise RuntimeError("orc_lap_weights failed")
+    return (rp, col, W[: col.shape[0]]), flags
+
+
+def ppe_rhs(pos, vol, kernel, R, mapspec, v, rho, dt, gamma, jr=None, dirichlet=None, pbc=None, csr=None):
+    """(rhs, div, dens) of the pressure Poisson equation."""
+    pos, vol, v = _f64(pos), _f64(vol), _f64(v)
+    dim, n = pos.shape
+    rp, col = _csr(pos, R, csr)
+    rhs, div, dens = np.zeros(n), np.zeros(n), np.zeros(n)
+    kind, Hh, H, dmin, eps, nt, terms = _map_args(mapspec)
+    jr_a = None if jr is None else _f64(jr)
+    pbc_a = None if pbc is None else _f64(pbc)
+    dir_a = _u8(dirichlet)
+    st = lib().orc_ppe_rhs(dim, n, _p(pos), _p(vol), int(kernel), float(R), kind, Hh, H, dmin, eps, nt, _p(terms),
+                           _p(v), float(rho), float(dt), float(gamma), _p(jr_a), _p(dir_a, C.c_uint8), _p(pbc_a),
+                           _p(rp, C.c_int64), _p(col if col.size else np.zeros(1, np.int32), C.c_int32), _p(rhs),
+                           _p(div), _p(dens))
+    if st != 0:
+        raise RuntimeError("orc_ppe_rhs failed")
+    return rhs, div, dens
+
+
+def ppe_correct(pos, vol, kernel, R, mapspec, p, vstar, rho, dt, csr=None):
+    """v* - dt / rho * (physical first-order pressure gradient), (dim, n)."""
+    pos, vol, p, vstar = _f64(pos), _f64(vol), _f64(p), _f64(vstar)
+    dim, n = pos.shape
+    rp, col = _csr(pos, R, csr)
+    out = np.zeros((dim, n))
+    kind, Hh, H, dmin, eps, nt, terms = _map_args(mapspec)
+    st = lib().orc_ppe_correct(dim, n, _p(pos), _p(vol), int(kernel), float(R), kind, Hh, H, dmin, eps, nt,
+                               _p(terms), _p(p), _p(vstar), float(rho), float(dt), _p(rp, C.c_int64),
+                               _p(col if col.size else np.zeros(1, np.int32), C.c_int32), _p(out))
+    if st != 0:
+        raise RuntimeError("orc_ppe_correct failed")
+    return out
+
+
+def ppe_matvec(weights, dirichlet, x):
+    """A x of the pressure system (numpy, for checks)."""
+    rp, col, W = weights
+    n = rp.shape[0] - 1
+    rows = np.repeat(np.arange(n), np.diff(rp))
+    y = np.zeros(n)
+    np.add.at(y, rows, W * (x[col] - x[rows]))
+    if dirichlet is not None:
+        d = np.asarray(dirichlet, dtype=bool)
+        y[d] = x[d]
+    return y
+
+
+def ppe_bicgstab(weights, dirichlet, b, x0=None, tol=1e-10, maxit=2000):
+    """BiCGSTAB on the pressure system; returns (x, iterations, relres, status)."""
+    rp, col, W = weights
+    n = rp.shape[0] - 1
+    x = np.zeros(n) if x0 is None else _f64(x0).copy()
+    b = _f64(b)
+    it, rr = C.c_int(0), C.c_double(0.0)
+    st = lib().orc_ppe_bicgstab(n, _p(rp, C.c_int64), _p(col if col.size else np.zeros(1, np.int32), C.c_int32),
+                                _p(_f64(W)), _p(_u8(dirichlet), C.c_uint8), _p(b), _p(x), float(tol), int(maxit),
+                                C.byref(it), C.byref(rr))
+    return x, it.value, rr.value, st

@@ -742,3 +742,320 @@ void orc_set_threads(int n)
     (void)n;
 #endif
 }
+
+/* ================================================= ISPH pressure step (Sec. 3.3) */
+
+/* Weights of the physical Laplacian (Eq. lap_VCT with the SPH(2) second
+ * derivatives of Eq. sec_SPH2): lap_i(phi) = sum_j W_ij (phi_j - phi_i).  The
+ * operator is linear in the differences phi_ij, so W_ij is the operator applied
+ * to the field whose differences are phi_ik = delta_kj.  The steps are those of
+ * orc_particle_field, taken for every such unit field of the row at once:
+ *   g1(e_j)  = V_j L_i grad w_ij                                   (Eq. gra_1st)
+ *   b(e_j)   = V_j F_ij q_ij - (sum_k V_k F_ik q_ik r_ik^T) g1(e_j)
+ *   D(e_j)   = 2 M_i^-1 b(e_j)                                     (Eq. sec_SPH2)
+ *   g2(e_j)  = g1(e_j) - 1/2 Q_i^T D(e_j)
+ *   W_ij     = c_trans . D^(e_j)                                   (Eq. lap_VCT)
+ * W has the layout of col (row r of the CSR holds the weights of rows[r]).
+ * Flagged particles get NaN weights. */
+int orc_lap_weights(int dim, int64_t n, const double* pos, const double* vol, int kernel, double R,
+                    int map_kind, double Hhat, double H, double dmin, double eps, int nterms,
+                    const double* terms, int grad_order, int64_t nrows, const int64_t* rows,
+                    const int64_t* row_ptr, const int32_t* col, double* W, uint8_t* flags)
+{
+    if ((dim != 2 && dim != 3) || n < 0 || !(R > 0)) return -1;
+    orc_ctx c;
+    ctx_init(&c, dim, n, pos, vol, kernel, R, map_kind, Hhat, H, dmin, eps, nterms, terms, grad_order);
+    const int d = dim, m = c.m;
+    #pragma omp parallel
+    {
+        orc_scratch s;
+        memset(&s, 0, sizeof s);
+        int64_t bcap = 0;
+        double* B = NULL;
+        #pragma omp for schedule(dynamic, 64)
+        for (int64_t r = 0; r < nrows; ++r) {
+            int64_t i = rows ? rows[r] : r;
+            const int32_t* nb = col + row_ptr[r];
+            int64_t deg = row_ptr[r + 1] - row_ptr[r];
+            double* w = W + row_ptr[r];
+            int fl = scratch_reserve(&s, deg) ? ORC_F_NONFINITE : 0;
+            if (deg > bcap) { bcap = deg + 64; free(B); B = (double*)malloc((size_t)bcap * 6 * sizeof(double)); }
+            orc_geom G;
+            if (!fl) fl = orc_particle_geometry(&c, i, nb, deg, &s, &G);
+            /* C_i = sum_k V_k F_ik q_ik r_ik^T (m x d) */
+            double Cm[18] = {0};
+            if (!fl) {
+                for (int64_t k = 0; k < deg; ++k) {
+                    double VF = c.vol[nb[k]] * s.F[k];
+                    for (int a = 0; a < m; ++a)
+                        for (int b = 0; b < d; ++b) Cm[a * d + b] += VF * s.q[6 * k + a] * s.r[3 * k + b];
+                }
+                /* right-hand sides b(e_j), one column per neighbour (row-major m x deg) */
+                for (int64_t j = 0; j < deg; ++j) {
+                    double Vj = c.vol[nb[j]];
+                    for (int a = 0; a < m; ++a) {
+                        double t = 0.0;
+                        for (int b = 0; b < d; ++b) t += Cm[a * d + b] * Vj * s.gt[3 * j + b];
+                        B[a * deg + j] = Vj * s.F[j] * s.q[6 * j + a] - t;
+                    }
+                }
+                double M[36];
+                memcpy(M, G.M, sizeof(double) * m * m);
+                if (orc_gepp(m, M, (int)deg, B, ORC_PIVOT_TOL)) fl |= ORC_F_SINGULAR_M;
+            }
+            double Jm[3][3], ct[6], hz[3][3];
+            if (!fl) {
+                double x = c.pos[i], y = (d == 3) ? c.pos[n + i] : 0.0, zh = c.pos[(d - 1) * n + i];
+                orc_r_map_coeffs(&c.map, d, x, y, zh, -1, 0.0, Jm, ct, hz);
+                if (!(Jm[2][2] > 0.0) || !isfinite(Jm[2][2] + Jm[0][2] + Jm[1][2] + ct[0] + hz[0][1])) fl |= ORC_F_MAP;
+            }
+            for (int64_t j = 0; j < deg; ++j) {
+                if (fl) { w[j] = NAN; continue; }
+                double Vj = c.vol[nb[j]];
+                double D[6], g1[3], g2[3];
+                for (int a = 0; a < m; ++a) D[a] = 2.0 * B[a * deg + j];
+                for (int a = 0; a < d; ++a) {
+                    g1[a] = Vj * s.gt[3 * j + a];
+                    double t = 0.0;
+                    for (int p = 0; p < m; ++p) t += G.Q[p * d + a] * D[p];
+                    g2[a] = g1[a] - 0.5 * t;
+                }
+                const double* gs = (grad_order == 1) ? g1 : g2;
+                double Dhat[6];
+                if (d == 2) {   /* (x, z): D = [xx, zz, 2xz] */
+                    Dhat[0] = gs[1]; Dhat[1] = D[0]; Dhat[2] = 0.0; Dhat[3] = D[1]; Dhat[4] = 0.5 * D[2]; Dhat[5] = 0.0;
+                } else {        /* D = [xx, yy, zz, 2xy, 2xz, 2yz] */
+                    Dhat[0] = gs[2]; Dhat[1] = D[0]; Dhat[2] = D[1]; Dhat[3] = D[2]; Dhat[4] = 0.5 * D[4]; Dhat[5] = 0.5 * D[5];
+                }
+                double t = 0.0;
+                for (int k = 0; k < 6; ++k) t += ct[k] * Dhat[k];
+                w[j] = t;
+            }
+            if (flags) flags[r] = (uint8_t)fl;
+        }
+        free(B);
+        scratch_free(&s);
+    }
+    return 0;
+}
+
+/* First-order projected gradient <grad^ f>^(1)_i = sum_j V_j f_ij L_i grad w_ij
+ * (Eqs. gra_1st, div_1st) of one scalar field at particle i, given its
+ * geometry; g[3] in the 3-D component order (2-D: x^, 0, z^). */
+static void orc_grad1(const orc_ctx* c, int64_t i, const int32_t* nb, int64_t deg, const orc_scratch* s,
+                      const double* f, double g[3])
+{
+    double t[3] = {0.0, 0.0, 0.0};
+    for (int64_t k = 0; k < deg; ++k) {
+        double fij = f[nb[k]] - f[i];
+        double V = c->vol[nb[k]];
+        for (int a = 0; a < c->dim; ++a) t[a] += V * fij * s->gt[3 * k + a];
+    }
+    g[0] = t[0];
+    g[1] = (c->dim == 3) ? t[1] : 0.0;
+    g[2] = t[c->dim - 1];
+}
+
+/* geometry of particle i for the first-order operators: flags if the state the
+ * library would write is NaN there (any geometry flag, a singular M, alpha) */
+static int orc_first_order_geometry(const orc_ctx* c, int64_t i, const int32_t* nb, int64_t deg, orc_scratch* s,
+                                    double Jm[3][3])
+{
+    orc_geom G;
+    int fl = orc_particle_geometry(c, i, nb, deg, s, &G);
+    if (fl) return fl;
+    double M[36], b[6] = {0, 0, 0, 0, 0, 0};
+    memcpy(M, G.M, sizeof(double) * c->m * c->m);
+    if (orc_gepp(c->m, M, 1, b, ORC_PIVOT_TOL)) return ORC_F_SINGULAR_M;
+    double ct[6], hz[3][3];
+    double x = c->pos[i], y = (c->dim == 3) ? c->pos[c->n + i] : 0.0, zh = c->pos[(c->dim - 1) * c->n + i];
+    orc_r_map_coeffs(&c->map, c->dim, x, y, zh, -1, 0.0, Jm, ct, hz);
+    if (!(Jm[2][2] > 0.0) || !isfinite(Jm[2][2] + Jm[0][2] + Jm[1][2] + ct[0] + hz[0][1])) return ORC_F_MAP;
+    return 0;
+}
+
+/* Right-hand side of the pressure Poisson equation (Eqs. VCT_ppe, VCT_ppe_w):
+ *   rhs_i = rho / dt * div_i + gamma * (rho * jr_i - dens_i) / dt^2
+ *   div_i  = sum_{I,K} J_IK <d v_I / d x^_K>^(1)_i     physical divergence of v
+ *            through the projected first-order gradients (Eqs. div_1st, jacobi);
+ *            v is (dim x n), components along the physical axes
+ *   dens_i = rho * (sum_{j in S_i} V_j w_ij + V_i w(0))  numerical density in the
+ *            projected space (kernel summation over S_i and i itself)
+ *   jr_i   = Jbar_i / J_i of Eq. VCT_ppe_w (1 when jr is NULL, Eq. VCT_ppe)
+ * Dirichlet rows (dirichlet[i] != 0) get rhs_i = pbc_i (0 if pbc is NULL).
+ * div and dens are written when not NULL; flagged particles get NaN. */
+int orc_ppe_rhs(int dim, int64_t n, const double* pos, const double* vol, int kernel, double R, int map_kind,
+                double Hhat, double H, double dmin, double eps, int nterms, const double* terms, const double* v,
+                double rho, double dt, double gamma, const double* jr, const uint8_t* dirichlet, const double* pbc,
+                const int64_t* row_ptr, const int32_t* col, double* rhs, double* div, double* dens)
+{
+    if ((dim != 2 && dim != 3) || n < 0 || !(R > 0)) return -1;
+    orc_ctx c;
+    ctx_init(&c, dim, n, pos, vol, kernel, R, map_kind, Hhat, H, dmin, eps, nterms, terms, 2);
+    double w0, dw0;
+    orc_kernel_eval(kernel, dim, R, 0.0, &w0, &dw0);
+    #pragma omp parallel
+    {
+        orc_scratch s;
+        memset(&s, 0, sizeof s);
+        #pragma omp for schedule(dynamic, 64)
+        for (int64_t i = 0; i < n; ++i) {
+            const int32_t* nb = col + row_ptr[i];
+            int64_t deg = row_ptr[i + 1] - row_ptr[i];
+            double Jm[3][3];
+            int fl = scratch_reserve(&s, deg) ? ORC_F_NONFINITE : 0;
+            if (!fl) fl = orc_first_order_geometry(&c, i, nb, deg, &s, Jm);
+            double dv = NAN, ds = NAN;
+            if (!fl) {
+                dv = 0.0;
+                for (int I = 0; I < dim; ++I) {
+                    double g[3];
+                    orc_grad1(&c, i, nb, deg, &s, v + (size_t)I * n, g);
+                    int Ip = (dim == 3) ? I : (I == 0 ? 0 : 2);   /* physical axis of component I */
+                    for (int K = 0; K < 3; ++K) dv += Jm[Ip][K] * g[K];
+                }
+                double sw = c.vol[i] * w0;
+                for (int64_t k = 0; k < deg; ++k) {
+                    int64_t j = nb[k];
+                    double d2 = 0.0;
+                    for (int a = 0; a < dim; ++a) {
+                        double t = c.pos[a * n + j] - c.pos[a * n + i];
+                        d2 += t * t;
+                    }
+                    double wv, dwv;
+                    orc_kernel_eval(kernel, dim, R, sqrt(d2), &wv, &dwv);
+                    sw += c.vol[j] * wv;
+                }
+                ds = rho * sw;
+            }
+            if (div) div[i] = dv;
+            if (dens) dens[i] = ds;
+            double jri = jr ? jr[i] : 1.0;
+            rhs[i] = (dirichlet && dirichlet[i]) ? (pbc ? pbc[i] : 0.0)
+                                                 : rho / dt * dv + gamma * (rho * jri - ds) / (dt * dt);
+        }
+        scratch_free(&s);
+    }
+    return 0;
+}
+
+/* Corrector (Sec. 3.3): v_out = v* - dt / rho * J <grad^ p>^(1) (Eqs. gra_1st,
+ * grad_VCT), v and v_out (dim x n) along the physical axes. */
+int orc_ppe_correct(int dim, int64_t n, const double* pos, const double* vol, int kernel, double R, int map_kind,
+                    double Hhat, double H, double dmin, double eps, int nterms, const double* terms,
+                    const double* p, const double* vstar, double rho, double dt, const int64_t* row_ptr,
+                    const int32_t* col, double* vout)
+{
+    if ((dim != 2 && dim != 3) || n < 0 || !(R > 0)) return -1;
+    orc_ctx c;
+    ctx_init(&c, dim, n, pos, vol, kernel, R, map_kind, Hhat, H, dmin, eps, nterms, terms, 2);
+    #pragma omp parallel
+    {
+        orc_scratch s;
+        memset(&s, 0, sizeof s);
+        #pragma omp for schedule(dynamic, 64)
+        for (int64_t i = 0; i < n; ++i) {
+            const int32_t* nb = col + row_ptr[i];
+            int64_t deg = row_ptr[i + 1] - row_ptr[i];
+            double Jm[3][3];
+            int fl = scratch_reserve(&s, deg) ? ORC_F_NONFINITE : 0;
+            if (!fl) fl = orc_first_order_geometry(&c, i, nb, deg, &s, Jm);
+            double g[3] = {NAN, NAN, NAN}, gp[3] = {NAN, NAN, NAN};
+            if (!fl) {
+                orc_grad1(&c, i, nb, deg, &s, p, g);
+                for (int I = 0; I < 3; ++I) {
+                    double t = 0.0;
+                    for (int K = 0; K < 3; ++K) t += Jm[I][K] * g[K];
+                    gp[I] = t;
+                }
+            }
+            for (int I = 0; I < dim; ++I) {
+                int Ip = (dim == 3) ? I : (I == 0 ? 0 : 2);
+                vout[(size_t)I * n + i] = vstar[(size_t)I * n + i] - dt / rho * gp[Ip];
+            }
+        }
+        scratch_free(&s);
+    }
+    return 0;
+}
+
+/* A x on the pressure system: sum_j W_ij (x_j - x_i) on ordinary rows, x_i on
+ * Dirichlet rows; each row summed in its own order. */
+static void orc_ppe_matvec(int64_t n, const int64_t* row_ptr, const int32_t* col, const double* W,
+                           const uint8_t* dirichlet, const double* x, double* y)
+{
+    #pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        if (dirichlet && dirichlet[i]) { y[i] = x[i]; continue; }
+        double t = 0.0;
+        for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) t += W[e] * (x[col[e]] - x[i]);
+        y[i] = t;
+    }
+}
+
+static double orc_dot(int64_t n, const double* a, const double* b)
+{
+    double t = 0.0;
+    for (int64_t i = 0; i < n; ++i) t += a[i] * b[i];
+    return t;
+}
+
+/* Solve the pressure system A x = b by BiCGSTAB (van der Vorst, 1992) with the
+ * Jacobi preconditioner on the right (diag_i = -sum_j W_ij on ordinary rows, 1
+ * on Dirichlet rows):
+ *   r = b - A x, r^ = r, rho = alpha = omega = 1, v = p = 0
+ *   repeat: rho' = (r^, r), beta = (rho'/rho)(alpha/omega),
+ *           p = r + beta (p - omega v), p^ = diag^-1 p, v = A p^,
+ *           alpha = rho' / (r^, v), s = r - alpha v, s^ = diag^-1 s, t = A s^,
+ *           omega = (t, s) / (t, t), x += alpha p^ + omega s^, r = s - omega t
+ *   until ||r|| <= tol ||b|| or maxit iterations.
+ * x holds the initial guess on entry.  *iters receives the iterations taken and
+ * *relres the true relative residual ||b - A x|| / ||b||.  Returns 0, 1 if it
+ * stopped without converging, 2 on a breakdown. */
+int orc_ppe_bicgstab(int64_t n, const int64_t* row_ptr, const int32_t* col, const double* W,
+                     const uint8_t* dirichlet, const double* b, double* x, double tol, int maxit, int* iters,
+                     double* relres)
+{
+    double* buf = (double*)malloc((size_t)(n > 0 ? n : 1) * 9 * sizeof(double));
+    if (!buf) return -1;
+    double *r = buf, *rh = buf + n, *p = buf + 2 * n, *v = buf + 3 * n, *s = buf + 4 * n, *t = buf + 5 * n;
+    double *ph = buf + 6 * n, *sh = buf + 7 * n, *dinv = buf + 8 * n;
+    for (int64_t i = 0; i < n; ++i) {
+        double dg = 1.0;
+        if (!(dirichlet && dirichlet[i])) {
+            dg = 0.0;
+            for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) dg -= W[e];
+        }
+        dinv[i] = 1.0 / dg;
+    }
+    orc_ppe_matvec(n, row_ptr, col, W, dirichlet, x, r);
+    for (int64_t i = 0; i < n; ++i) { r[i] = b[i] - r[i]; rh[i] = r[i]; p[i] = 0.0; v[i] = 0.0; }
+    double bb = sqrt(orc_dot(n, b, b));
+    double rho = 1.0, alpha = 1.0, omega = 1.0;
+    int it = 0, status = 1;
+    if (sqrt(orc_dot(n, r, r)) <= tol * bb) status = 0;
+    while (status == 1 && it < maxit) {
+        double rho1 = orc_dot(n, rh, r);
+        double beta = (rho1 / rho) * (alpha / omega);
+        for (int64_t i = 0; i < n; ++i) { p[i] = r[i] + beta * (p[i] - omega * v[i]); ph[i] = dinv[i] * p[i]; }
+        orc_ppe_matvec(n, row_ptr, col, W, dirichlet, ph, v);
+        double rv = orc_dot(n, rh, v);
+        if (rv == 0.0) { status = 2; break; }
+        alpha = rho1 / rv;
+        for (int64_t i = 0; i < n; ++i) { s[i] = r[i] - alpha * v[i]; sh[i] = dinv[i] * s[i]; }
+        orc_ppe_matvec(n, row_ptr, col, W, dirichlet, sh, t);
+        double tt = orc_dot(n, t, t);
+        if (tt == 0.0) { status = 2; break; }
+        omega = orc_dot(n, t, s) / tt;
+        for (int64_t i = 0; i < n; ++i) { x[i] += alpha * ph[i] + omega * sh[i]; r[i] = s[i] - omega * t[i]; }
+        rho = rho1;
+        ++it;
+        if (sqrt(orc_dot(n, r, r)) <= tol * bb) status = 0;
+    }
+    orc_ppe_matvec(n, row_ptr, col, W, dirichlet, x, t);
+    for (int64_t i = 0; i < n; ++i) t[i] = b[i] - t[i];
+    *iters = it;
+    *relres = bb > 0.0 ? sqrt(orc_dot(n, t, t)) / bb : sqrt(orc_dot(n, t, t));
+    free(buf);
+    return status;
+}

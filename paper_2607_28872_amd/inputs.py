@@ -260,6 +260,15 @@ def target_field(pos, Hhat, scale=100.0, seed=SEED_TARGET, nmodes=8):
     return g * (scale / (rms if rms > 0 else 1.0))
 
 
+def boundary_layer(pos, lo, hi, width):
+    """Particles within `width` of a face of the box [lo, hi) (bool, n): the
+    Dirichlet rows of the synthetic pressure problems."""
+    pos = np.asarray(pos)
+    lo = np.asarray(lo, dtype=np.float64)[:, None]
+    hi = np.asarray(hi, dtype=np.float64)[:, None]
+    return np.any((pos < lo + width) | (pos >= hi - width), axis=0)
+
+
 def theta0(seed=SEED_THETA):
     return np.random.default_rng(seed).uniform(-0.01, 0.01, size=16)
 
