@@ -66,6 +66,7 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--adjoint-state", choices=["resolve", "recompute"], default="resolve",
                    help="backward state: solved from the forward's kept moment sums, or sweeps + solve again")
+    p.add_argument("--ppe-iters", type=int, default=100, help="BiCGSTAB iterations of the pressure-step measurement")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a 1 GiB device-to-device copy five times (reference for HBM byte counters)")
     return p.parse_args()
@@ -382,6 +383,8 @@ def main():
                          "rel_err": abs(fd - adj) / abs(adj)}
     del lap_pm, a, b, o, ph, v
 
+    res["ppe"] = ppe_measure(args, w, vct, L, nl, pos_s, vol_s, sta, adj_mask, ms, perm, dev)
+
     if not args.no_cpu_baseline:
         progress("CPU oracle on a sample")
         cb, rows, rec = cpu_baseline(w, phis, ms, args.cpu_seconds)
@@ -397,6 +400,48 @@ def main():
             errs[nm] = operator_errors(out[:, idx, :].cpu().numpy(), rec, dim)
         res["error_vs_oracle"] = errs
     print(json.dumps(res), flush=True)
+
+
+def ppe_measure(args, w, vct, L, nl, pos_s, vol_s, sta, mask, ms, perm, dev):
+    """The pressure step on the benchmark geometry (outside the timed
+    steps): the right-hand side of Eq. VCT_ppe from a smooth test velocity,
+    Dirichlet rows on the boundary layer of width R, then a fixed budget of
+    BiCGSTAB iterations with the FP64 Laplacian (the adjoint's state, which
+    holds the LAP row) as the matrix-free operator."""
+    import numpy as np
+    import torch
+    from paper_2607_28872_amd import inputs as I
+    progress("pressure step")
+    n, dim = w.n, w.dim
+    cmap = vct.make_map(ms)
+    idx = perm[:n].long().cpu().numpy()
+    dirichlet = torch.as_tensor(I.boundary_layer(w.pos, w.lo, w.hi, w.R).astype(np.uint8)[idx], device=dev)
+    v = torch.as_tensor(np.ascontiguousarray(I.velocity_field(w.pos)[:, idx]), device=dev)
+    rhs = torch.empty(n, dtype=torch.float64, device=dev)
+    ws = torch.empty(L.vct_ppe_workspace_size(dim, n, mask), dtype=torch.uint8, device=dev)
+    p = torch.zeros(n, dtype=torch.float64, device=dev)
+    vct.vct_ppe_rhs(nl, pos_s, vol_s, w.kernel, sta, mask, cmap, v, 1.0, 1e-3, 0.1, None, dirichlet, None, rhs)
+    vct.vct_ppe_solve(nl, pos_s, vol_s, w.kernel, sta, mask, dirichlet, rhs, p, 1e-30, 8, ws)   # warm-up
+    iters = args.ppe_iters
+    p.zero_()
+    vct.vct_timing_reset()
+    vct.vct_timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    vct.vct_ppe_rhs(nl, pos_s, vol_s, w.kernel, sta, mask, cmap, v, 1.0, 1e-3, 0.1, None, dirichlet, None, rhs)
+    st, it, rr = vct.vct_ppe_solve(nl, pos_s, vol_s, w.kernel, sta, mask, dirichlet, rhs, p, 1e-30, iters, ws)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    vct.vct_timing_enable(False)
+    kt = vct.vct_timing_read()
+    vct.vct_timing_reset()
+    matvec = kt.get("k_apply (fp64)", (0, 0.0))
+    return {"what": "pressure Poisson solve (Eq. VCT_ppe): BiCGSTAB, Jacobi preconditioner, SPH(2) Laplacian "
+                    "matrix-free; fixed iteration budget (tol 0), rhs from a smooth velocity, Dirichlet boundary layer",
+            "iterations": it, "relres": rr, "ms_total": round(t * 1e3, 3),
+            "ms_per_iteration": round(t * 1e3 / max(it, 1), 4),
+            "matvec_avg_ms": round(matvec[1] / max(matvec[0], 1), 4), "matvecs": matvec[0],
+            "kernels": {k: {"launches": c, "avg_ms": round(ms_ / c, 4)} for k, (c, ms_) in sorted(kt.items())}}
 
 
 def cpu_model():

@@ -44,6 +44,7 @@ extern "C" {
 enum {
     VCT_OK = 0,
     VCT_W_FLAGGED = 1,      /* some particles were flagged; their outputs are NaN */
+    VCT_W_NOCONV = 2,       /* an iterative solve stopped before its tolerance (result written) */
     VCT_E_ARG = -1,         /* invalid argument (null pointer, size, enum, range) */
     VCT_E_HIP = -2,         /* a HIP runtime call or kernel launch failed */
     VCT_E_CAPACITY = -3,    /* an output array is too small; the required size is reported */
@@ -386,6 +387,59 @@ int vct_apply_ops_adjoint(const vct_nlist* nl, const double* pos_sorted, const d
                           const double* state64, uint32_t out_mask, const vct_map* map /* host */,
                           const double* proj, const double* u, double* dphi, double* dtheta, void* ws,
                           size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------- pressure step (Sec. 3.3) */
+
+/* The pressure step of the projection method through the VCT (paper
+ * Sec. 3.3, Eqs. VCT_ppe, VCT_ppe_w and the corrector of VCT_predictor).
+ * `state64` comes from vct_moments with `out_mask` containing VCT_OUT_LAP
+ * (VCT_OUT_LAP alone is enough; the first-order correction matrix at the
+ * head of every state is what the divergence and gradient use).  Vector
+ * fields are [dim][n] along the physical axes (2-D: x, z), in sorted order.
+ *
+ * vct_ppe_rhs: right-hand side of the pressure Poisson equation
+ *   rhs_i = rho / dt * div_i + gamma * (rho * jr_i - dens_i) / dt^2
+ * with
+ *   div_i  = sum_{I,K} J_IK <d v*_I / d x^_K>^(1)_i: the physical divergence
+ *            through the first-order projected gradients (Eqs. div_1st,
+ *            jacobi; the printed "J <div^ v*>" is read this way);
+ *   dens_i = rho * (V_i w(0) + sum_{j in S_i} V_j w_ij): the numerical density
+ *            in the projected space (normalised kernel of unit integral);
+ *   jr_i   = Jbar_i / J_i of Eq. VCT_ppe_w (NULL: 1, Eq. VCT_ppe).
+ * Rows with dirichlet[i] != 0 get rhs_i = pbc[i] (pbc NULL: 0).  div and dens
+ * (may be NULL) receive the two terms.  Particles with a NaN state get NaN.
+ * Asynchronous.                                                               */
+int vct_ppe_rhs(const vct_nlist* nl, const double* pos_sorted, const double* vol_sorted, int kernel,
+                const double* state64, uint32_t out_mask, const vct_map* map /* host */, const double* vstar,
+                double rho, double dt, double gamma, const double* jr, const uint8_t* dirichlet, const double* pbc,
+                double* rhs, double* div, double* dens, void* stream);
+
+/* vct_ppe_correct: v = v* - dt / rho * J <grad^ p>^(1) (Eqs. gra_1st and
+ * grad_VCT: the first-order pressure gradient, as the paper's ISPH(2) uses),
+ * vout [dim][n].  Asynchronous.                                               */
+int vct_ppe_correct(const vct_nlist* nl, const double* pos_sorted, const double* vol_sorted, int kernel,
+                    const double* state64, uint32_t out_mask, const vct_map* map /* host */, const double* p,
+                    const double* vstar, double rho, double dt, double* vout, void* stream);
+
+size_t vct_ppe_workspace_size(int dim, int64_t n, uint32_t out_mask);
+
+/* vct_ppe_solve: the pressure Poisson equation c_trans . <D^ p>_i = rhs_i
+ * (Eq. VCT_ppe) on rows with dirichlet[i] == 0 and p_i = rhs_i on the others
+ * (dirichlet may be NULL), by BiCGSTAB with the Jacobi preconditioner on the
+ * right (diagonal: the coefficient of p_i in row i).  The operator is
+ * matrix-free: the FP64 Laplacian of vct_apply_ops on the fixed state.  `p`
+ * holds the initial guess on entry and the solution on return.  Stops when
+ * ||r|| <= tol ||rhs|| (the recurrence residual) or after max_iter
+ * iterations.  The scalars of the method stay on the device; every inner
+ * product is a fixed-order sum, so a solve gives the same bits on every run.
+ * *iters (host, may be NULL) receives the iterations taken and *relres (host,
+ * may be NULL) the true relative residual ||rhs - A p|| / ||rhs||.  Returns
+ * VCT_OK when converged, VCT_W_NOCONV when it stopped on max_iter or a
+ * breakdown.  SYNC (reads the scalars every 8 iterations).                    */
+int vct_ppe_solve(const vct_nlist* nl, const double* pos_sorted, const double* vol_sorted, int kernel,
+                  const double* state64, uint32_t out_mask, const uint8_t* dirichlet, const double* rhs, double* p,
+                  double tol, int max_iter, int* iters /* host */, double* relres /* host */, void* ws,
+                  size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------- allocation-free adjoint */
 

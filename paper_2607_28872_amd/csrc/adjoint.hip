@@ -29,6 +29,7 @@
 
 #include "common.h"
 #include "map_dev.h"
+#include "lapw.h"
 #include "tiles.h"
 
 namespace vct {
@@ -71,35 +72,6 @@ struct AdjArgs {
 // loaded into registers up front; the window records are read from LDS one
 // slot ahead of the arithmetic.
 constexpr int kWSlots = 14;
-
-template <int D, int KERNEL>
-__device__ __forceinline__ double adj_weight(const double4& q, const double (&xi)[3], double invR,
-                                             const double (&L2)[Dims<D>::nL], const double (&Pl)[Dims<D>::nk]) {
-    using Dm = Dims<D>;
-    constexpr int nL = Dm::nL, m = Dm::m;
-    double r[D];
-    r[0] = (q.x - xi[0]) * invR;
-    r[1] = (q.y - xi[1]) * invR;
-    if (D == 3) r[D - 1] = (q.z - xi[2]) * invR;
-    double q2 = r[0] * r[0];
-#pragma unroll
-    for (int a = 1; a < D; ++a) q2 = fma(r[a], r[a], q2);
-    double qv[m];
-#pragma unroll
-    for (int p = 0; p < m; ++p) qv[p] = r[pair_a<D>(p)] * r[pair_b<D>(p)];
-    double rLr = L2[0] * qv[0], sa = Pl[0] * r[0], ss = Pl[D] * qv[0];
-#pragma unroll
-    for (int p = 1; p < nL; ++p) rLr = fma(L2[p], qv[p], rLr);
-#pragma unroll
-    for (int a = 1; a < D; ++a) sa = fma(Pl[a], r[a], sa);
-#pragma unroll
-    for (int p = 1; p < m; ++p) ss = fma(Pl[D + p], qv[p], ss);
-    // y = 1/|r~| (refined estimate); |r~| = q2 y and 1/|r~|^4 = (y^2)^2
-    const double y = vrsq(q2);
-    const double y2 = y * y;
-    const double vc = q.w * kernel_shape<KERNEL>(q2 > 0.0 ? q2 * y : 0.0);
-    return vc * fma(rLr * (y2 * y2), ss, sa);
-}
 
 template <int D, int KERNEL>
 __global__ __launch_bounds__(kAThreads, 2) void k_adjoint_weights(AdjArgs A) {
@@ -183,7 +155,7 @@ __global__ __launch_bounds__(kAThreads, 2) void k_adjoint_weights(AdjArgs A) {
             if (s + 1 < kWSlots) qn = sd[cols(s + 1)];
             __builtin_amdgcn_sched_barrier(0);
             if (s < nslot) {
-                const double wij = adj_weight<D, KERNEL>(q, xi, A.invR, L2, Pl);
+                const double wij = lap_weight<D, KERNEL>(q, xi, A.invR, L2, Pl);
                 A.wbuf[tcol[s]] = wij;
                 sum += wij;
             }
@@ -193,14 +165,14 @@ __global__ __launch_bounds__(kAThreads, 2) void k_adjoint_weights(AdjArgs A) {
 #pragma unroll 1
         for (int s = 0; s < kWSlots; ++s) {
             if (s < nslot) {
-                const double wij = adj_weight<D, KERNEL>(fetch(cols(s)), xi, A.invR, L2, Pl);
+                const double wij = lap_weight<D, KERNEL>(fetch(cols(s)), xi, A.invR, L2, Pl);
                 A.wbuf[tcol[s]] = wij;
                 sum += wij;
             }
         }
     }
     for (int64_t e = rb + lane + (int64_t)kALanes * kWSlots; e < re; e += kALanes) {
-        const double wij = adj_weight<D, KERNEL>(fetch(A.col16[e]), xi, A.invR, L2, Pl);
+        const double wij = lap_weight<D, KERNEL>(fetch(A.col16[e]), xi, A.invR, L2, Pl);
         A.wbuf[A.col_t[e]] = wij;
         sum += wij;
     }
@@ -430,7 +402,7 @@ __device__ __forceinline__ void push_column(const AdjArgs& A, double* __restrict
                             const int64_t j = s_cw.gstart[r] + (tg - s_cw.off[r]);
                             qv = make_double4(A.pos[j], A.pos[n + j], D == 3 ? A.pos[2 * n + j] : 0.0, A.vol[j]);
                         }
-                        const double wij = adj_weight<D, KERNEL>(qv, xi, A.invR, L2, Pl);
+                        const double wij = lap_weight<D, KERNEL>(qv, xi, A.invR, L2, Pl);
                         rowsum += wij;
                         if (here) {
                             unsigned long long X;

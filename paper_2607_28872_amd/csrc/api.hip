@@ -209,6 +209,7 @@ extern "C" const char* vct_status_string(int status) {
     switch (status) {
     case VCT_OK: return "VCT_OK";
     case VCT_W_FLAGGED: return "VCT_W_FLAGGED: some particles were flagged (NaN outputs)";
+    case VCT_W_NOCONV: return "VCT_W_NOCONV: the iterative solve stopped before its tolerance";
     case VCT_E_ARG: return "VCT_E_ARG: invalid argument";
     case VCT_E_HIP: return "VCT_E_HIP: HIP runtime error";
     case VCT_E_CAPACITY: return "VCT_E_CAPACITY: output capacity too small";

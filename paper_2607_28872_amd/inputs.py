@@ -269,6 +269,15 @@ def boundary_layer(pos, lo, hi, width):
     return np.any((pos < lo + width) | (pos >= hi - width), axis=0)
 
 
+def velocity_field(pos):
+    """A smooth seeded-free test velocity (dim, n) for the pressure step:
+    v_I = sin(2 pi x + I) cos(pi z / z_max) + 0.1 (I + 1)."""
+    pos = np.asarray(pos)
+    zmax = float(pos[-1].max()) if pos.size else 1.0
+    return np.stack([np.sin(2 * math.pi * pos[0] + a) * np.cos(math.pi * pos[-1] / zmax) + 0.1 * (a + 1)
+                     for a in range(pos.shape[0])])
+
+
 def theta0(seed=SEED_THETA):
     return np.random.default_rng(seed).uniform(-0.01, 0.01, size=16)
 

@@ -19,7 +19,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libvct.so")
 
-VCT_OK, VCT_W_FLAGGED = 0, 1
+VCT_OK, VCT_W_FLAGGED, VCT_W_NOCONV = 0, 1, 2
 VCT_E_ARG, VCT_E_HIP, VCT_E_CAPACITY, VCT_E_NONFINITE, VCT_E_WORKSPACE, VCT_E_WINDOW = -1, -2, -3, -4, -5, -6
 VCT_KERNEL_WENDLAND_C2, VCT_KERNEL_CUBIC_SPLINE = 0, 1
 VCT_FP64, VCT_MIXED, VCT_MIXED_S64 = 0, 1, 2
@@ -116,6 +116,17 @@ def lib():
         L.vct_apply_ops_adjoint.restype = C.c_int
         L.vct_apply_ops_adjoint.argtypes = [_nlp, _vp, _vp, C.c_int, _vp, C.c_uint32, C.POINTER(vct_map), _vp, _vp,
                                             _vp, _vp, _vp, _sz, _vp]
+        L.vct_ppe_rhs.restype = C.c_int
+        L.vct_ppe_rhs.argtypes = [_nlp, _vp, _vp, C.c_int, _vp, C.c_uint32, C.POINTER(vct_map), _vp, C.c_double,
+                                  C.c_double, C.c_double, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+        L.vct_ppe_correct.restype = C.c_int
+        L.vct_ppe_correct.argtypes = [_nlp, _vp, _vp, C.c_int, _vp, C.c_uint32, C.POINTER(vct_map), _vp, _vp,
+                                      C.c_double, C.c_double, _vp, _vp]
+        L.vct_ppe_workspace_size.restype = _sz
+        L.vct_ppe_workspace_size.argtypes = [C.c_int, _i64, C.c_uint32]
+        L.vct_ppe_solve.restype = C.c_int
+        L.vct_ppe_solve.argtypes = [_nlp, _vp, _vp, C.c_int, _vp, C.c_uint32, _vp, _vp, _vp, C.c_double, C.c_int,
+                                    C.POINTER(C.c_int), C.POINTER(C.c_double), _vp, _sz, _vp]
         L.vct_apply_ops_adjoint_noalloc.restype = C.c_int
         L.vct_apply_ops_adjoint_noalloc.argtypes = [_nlp, _vp, _vp, C.c_int, _vp, C.c_uint32, C.POINTER(vct_map), _vp,
                                                     _vp, _vp, _vp, _vp]
@@ -289,6 +300,30 @@ def vct_apply_ops_adjoint_noalloc(nl, pos_sorted, vol_sorted, kernel, state64, m
     return _check("vct_apply_ops_adjoint_noalloc", lib().vct_apply_ops_adjoint_noalloc(
         C.byref(nl), _p(pos_sorted), _p(vol_sorted), kernel, _p(state64), mask, C.byref(cmap), _p(proj), _p(u),
         _p(dphi), _p(dtheta), _stream(stream)))
+
+
+def vct_ppe_rhs(nl, pos_sorted, vol_sorted, kernel, state64, mask, cmap, vstar, rho, dt, gamma, jr, dirichlet, pbc,
+                rhs, div=None, dens=None, stream=None):
+    return _check("vct_ppe_rhs", lib().vct_ppe_rhs(
+        C.byref(nl), _p(pos_sorted), _p(vol_sorted), kernel, _p(state64), mask, C.byref(cmap), _p(vstar), float(rho),
+        float(dt), float(gamma), _p(jr), _p(dirichlet), _p(pbc), _p(rhs), _p(div), _p(dens), _stream(stream)))
+
+
+def vct_ppe_correct(nl, pos_sorted, vol_sorted, kernel, state64, mask, cmap, p, vstar, rho, dt, vout, stream=None):
+    return _check("vct_ppe_correct", lib().vct_ppe_correct(
+        C.byref(nl), _p(pos_sorted), _p(vol_sorted), kernel, _p(state64), mask, C.byref(cmap), _p(p), _p(vstar),
+        float(rho), float(dt), _p(vout), _stream(stream)))
+
+
+def vct_ppe_solve(nl, pos_sorted, vol_sorted, kernel, state64, mask, dirichlet, rhs, p, tol, max_iter, ws,
+                  stream=None):
+    """Returns (status, iterations, relative residual)."""
+    it, rr = C.c_int(0), C.c_double(0.0)
+    st = lib().vct_ppe_solve(C.byref(nl), _p(pos_sorted), _p(vol_sorted), kernel, _p(state64), mask, _p(dirichlet),
+                             _p(rhs), _p(p), float(tol), int(max_iter), C.byref(it), C.byref(rr), _p(ws),
+                             _nbytes(ws), _stream(stream))
+    _check("vct_ppe_solve", st)
+    return st, it.value, rr.value
 
 
 # ---------------------------------------------------------------- orchestration
