@@ -107,6 +107,17 @@ def lib():
         L.orc_ppe_bicgstab.restype = C.c_int
         L.orc_ppe_bicgstab.argtypes = [C.c_int64, ip64, ip32, dp, u8p, dp, dp, C.c_double, C.c_int,
                                        C.POINTER(C.c_int), C.POINTER(C.c_double)]
+        L.orc_ops0.restype = C.c_int
+        L.orc_ops0.argtypes = [C.c_int, C.c_int64, dp, dp, C.c_int, dp, C.c_int, C.c_double, C.c_int,
+                               C.c_double, C.c_double, C.c_double, C.c_double, C.c_int, dp, C.c_int64, ip64,
+                               ip64, ip32, dp, u8p]
+        L.orc_lap0.restype = C.c_int
+        L.orc_lap0.argtypes = [C.c_int, C.c_int64, dp, dp, C.c_int, dp, C.c_int, C.c_double, C.c_int64, ip64,
+                               ip64, ip32, dp]
+        L.orc_grad_sum.restype = C.c_int
+        L.orc_grad_sum.argtypes = [C.c_int, C.c_int64, dp, dp, dp, C.c_double, dp, C.c_int, C.c_double, C.c_int,
+                                   C.c_double, C.c_double, C.c_double, C.c_double, C.c_int, dp, C.c_int64, ip64,
+                                   ip64, ip32, dp, u8p]
         L.orc_threads.restype = C.c_int
         L.orc_set_threads.restype = None
         L.orc_set_threads.argtypes = [C.c_int]
@@ -334,3 +345,71 @@ def ppe_bicgstab(weights, dirichlet, b, x0=None, tol=1e-10, maxit=2000):
                                 _p(_f64(W)), _p(_u8(dirichlet), C.c_uint8), _p(b), _p(x), float(tol), int(maxit),
                                 C.byref(it), C.byref(rr))
     return x, it.value, rr.value, st
+
+
+# ------------------------------------------------------ conventional ISPH operators
+
+
+def _rows_csr(pos, R, rows, csr):
+    n = pos.shape[1]
+    rows_a = None if rows is None else np.ascontiguousarray(rows, dtype=np.int64)
+    if csr is None:
+        csr = neighbors(pos, R, rows=rows_a)
+    row_ptr = np.ascontiguousarray(csr[0], dtype=np.int64)
+    col = np.ascontiguousarray(csr[1], dtype=np.int32)
+    if col.size == 0:
+        col = np.zeros(1, np.int32)
+    nr = n if rows_a is None else rows_a.shape[0]
+    return rows_a, row_ptr, col, nr
+
+
+def ops0(pos, vol, phi, kernel, R, mapspec, rows=None, csr=None):
+    """0th-order operator records (Sec. 3.1, Eq. sec_0th) through the map:
+    (nrows, nf, REC) in sph2()'s layout, and flags (nrows,)."""
+    pos, vol = _f64(pos), _f64(vol)
+    phi = _f64(np.atleast_2d(phi))
+    dim, n = pos.shape
+    nf = phi.shape[0]
+    rows_a, row_ptr, col, nr = _rows_csr(pos, R, rows, csr)
+    out = np.zeros((nr, nf, REC))
+    flags = np.zeros(nr, dtype=np.uint8)
+    kind, Hh, H, dmin, eps, nt, terms = _map_args(mapspec)
+    st = lib().orc_ops0(dim, n, _p(pos), _p(vol), nf, _p(phi), int(kernel), float(R), kind, Hh, H, dmin, eps,
+                        nt, _p(terms), nr, _p(rows_a, C.c_int64), _p(row_ptr, C.c_int64), _p(col, C.c_int32),
+                        _p(out), _p(flags, C.c_uint8))
+    if st != 0:
+        raise RuntimeError(f"orc_ops0 failed ({st})")
+    return out, flags
+
+
+def lap0(pos, vol, phi, kernel, R, rows=None, csr=None):
+    """The 0th-order (Brookshaw) Laplacian in the projected space, (nrows, nf)."""
+    pos, vol = _f64(pos), _f64(vol)
+    phi = _f64(np.atleast_2d(phi))
+    dim, n = pos.shape
+    nf = phi.shape[0]
+    rows_a, row_ptr, col, nr = _rows_csr(pos, R, rows, csr)
+    out = np.zeros((nr, nf))
+    st = lib().orc_lap0(dim, n, _p(pos), _p(vol), nf, _p(phi), int(kernel), float(R), nr, _p(rows_a, C.c_int64),
+                        _p(row_ptr, C.c_int64), _p(col, C.c_int32), _p(out))
+    if st != 0:
+        raise RuntimeError(f"orc_lap0 failed ({st})")
+    return out
+
+
+def grad_sum(pos, vol, p, kernel, R, mapspec, rho=None, rho0=1.0, rows=None, csr=None):
+    """Summation pressure gradient (Eq. gra_sum): physical (nrows, 3),
+    projected (nrows, 3) in the 3-D slot order, flags (nrows,)."""
+    pos, vol, p = _f64(pos), _f64(vol), _f64(p)
+    rho_a = None if rho is None else _f64(rho)
+    dim, n = pos.shape
+    rows_a, row_ptr, col, nr = _rows_csr(pos, R, rows, csr)
+    out = np.zeros((nr, 6))
+    flags = np.zeros(nr, dtype=np.uint8)
+    kind, Hh, H, dmin, eps, nt, terms = _map_args(mapspec)
+    st = lib().orc_grad_sum(dim, n, _p(pos), _p(vol), _p(rho_a), float(rho0), _p(p), int(kernel), float(R), kind,
+                            Hh, H, dmin, eps, nt, _p(terms), nr, _p(rows_a, C.c_int64), _p(row_ptr, C.c_int64),
+                            _p(col, C.c_int32), _p(out), _p(flags, C.c_uint8))
+    if st != 0:
+        raise RuntimeError(f"orc_grad_sum failed ({st})")
+    return out[:, :3], out[:, 3:], flags

@@ -465,11 +465,55 @@ static int orc_particle_geometry(const orc_ctx* c, int64_t i, const int32_t* nb,
 
 /* Field part for particle i given the phi_ij values in s->phiij; writes one
  * ORC_REC record.  Returns flag bits. */
+/* Physical derivatives at particle i from projected ones (Sec. 2.1): the
+ * gradient J grad^ (Eq. grad_VCT), the Laplacian c_trans . D^ (Eq. lap_VCT)
+ * and the Hessian J H^ J^T + (d phi/d z^) (d2 z^) (the chain rule, of which
+ * Eq. lap_VCT is the trace).  gh and Hh in the 3-D component order (x, y, z^);
+ * fills rec[0:13], rec[25:32]; returns ORC_F_MAP where alpha is not positive. */
+static int orc_physical_record(const orc_ctx* c, int64_t i, const double gh[3], double Hh[3][3], double* rec)
+{
+    const int d = c->dim;
+    const int64_t n = c->n;
+    double x = c->pos[i], y = (d == 3) ? c->pos[n + i] : 0.0, zh = c->pos[(d - 1) * n + i];
+    double Jm[3][3], ct[6], hz[3][3];
+    orc_r_map_coeffs(&c->map, d, x, y, zh, -1, 0.0, Jm, ct, hz);
+    /* the transformation needs alpha > 0 (Sec. 2.1); Jm[2][2] is alpha */
+    if (!(Jm[2][2] > 0.0) || !isfinite(Jm[2][2] + Jm[0][2] + Jm[1][2] + ct[0] + hz[0][1])) return ORC_F_MAP;
+    double Dhat[6] = {gh[2], Hh[0][0], Hh[1][1], Hh[2][2], Hh[0][2], Hh[1][2]};
+    double lap = 0.0;
+    for (int k = 0; k < 6; ++k) lap += ct[k] * Dhat[k];
+    double gp[3];
+    for (int I = 0; I < 3; ++I) {
+        double t = 0.0;
+        for (int K = 0; K < 3; ++K) t += Jm[I][K] * gh[K];
+        gp[I] = t;
+    }
+    double Hp[3][3];
+    for (int I = 0; I < 3; ++I)
+        for (int L = 0; L < 3; ++L) {
+            double t = 0.0;
+            for (int K = 0; K < 3; ++K)
+                for (int Mx = 0; Mx < 3; ++Mx) t += Jm[I][K] * Hh[K][Mx] * Jm[L][Mx];
+            Hp[I][L] = t + gh[2] * hz[I][L];
+        }
+    if (d == 2) {
+        /* the 2-D plane has no y: drop the y row and column */
+        Hp[1][1] = 0.0; Hp[0][1] = Hp[1][0] = Hp[1][2] = Hp[2][1] = 0.0; gp[1] = 0.0;
+    }
+    rec[0] = gp[0]; rec[1] = gp[1]; rec[2] = gp[2];
+    rec[3] = lap;
+    rec[4] = Hp[0][1]; rec[5] = Hp[0][2]; rec[6] = Hp[1][2];
+    rec[7] = Hp[0][0]; rec[8] = Hp[1][1]; rec[9] = Hp[2][2];
+    rec[10] = Hp[0][1]; rec[11] = Hp[0][2]; rec[12] = Hp[1][2];
+    for (int k = 0; k < 6; ++k) rec[25 + k] = Dhat[k];
+    rec[31] = Hp[0][0] + Hp[1][1] + Hp[2][2];
+    return 0;
+}
+
 static int orc_particle_field(const orc_ctx* c, int64_t i, const int32_t* nb, int64_t deg,
                               const orc_scratch* s, const orc_geom* G, double* rec)
 {
     const int d = c->dim, m = c->m;
-    const int64_t n = c->n;
     for (int k = 0; k < ORC_REC; ++k) rec[k] = 0.0;
     /* g1_i = sum_j V_j phi_ij L_i grad w_ij */
     double g1[3] = {0, 0, 0};
@@ -513,43 +557,9 @@ static int orc_particle_field(const orc_ctx* c, int64_t i, const int32_t* nb, in
         Hh[1][2] = Hh[2][1] = 0.5 * D[5];
         for (int k = 0; k < 6; ++k) De[k] = D[k];
     }
-    /* mapping coefficients at the particle */
-    double x = c->pos[i], y = (d == 3) ? c->pos[n + i] : 0.0, zh = c->pos[(d - 1) * n + i];
-    double Jm[3][3], ct[6], hz[3][3];
-    orc_r_map_coeffs(&c->map, d, x, y, zh, -1, 0.0, Jm, ct, hz);
-    /* the transformation needs alpha > 0 (Sec. 2.1); Jm[2][2] is alpha */
-    if (!(Jm[2][2] > 0.0) || !isfinite(Jm[2][2] + Jm[0][2] + Jm[1][2] + ct[0] + hz[0][1])) return ORC_F_MAP;
-    double Dhat[6] = {gh[2], Hh[0][0], Hh[1][1], Hh[2][2], Hh[0][2], Hh[1][2]};
-    double lap = 0.0;
-    for (int k = 0; k < 6; ++k) lap += ct[k] * Dhat[k];
-    double gp[3];
-    for (int I = 0; I < 3; ++I) {
-        double t = 0.0;
-        for (int K = 0; K < 3; ++K) t += Jm[I][K] * gh[K];
-        gp[I] = t;
-    }
-    /* physical Hessian J H^ J^T + phi_z^ (d2 z^) */
-    double Hp[3][3];
-    for (int I = 0; I < 3; ++I)
-        for (int L = 0; L < 3; ++L) {
-            double t = 0.0;
-            for (int K = 0; K < 3; ++K)
-                for (int Mx = 0; Mx < 3; ++Mx) t += Jm[I][K] * Hh[K][Mx] * Jm[L][Mx];
-            Hp[I][L] = t + gh[2] * hz[I][L];
-        }
-    if (d == 2) {
-        /* the 2-D plane has no y: drop the y row and column */
-        Hp[1][1] = 0.0; Hp[0][1] = Hp[1][0] = Hp[1][2] = Hp[2][1] = 0.0; gp[1] = 0.0;
-    }
-    rec[0] = gp[0]; rec[1] = gp[1]; rec[2] = gp[2];
-    rec[3] = lap;
-    rec[4] = Hp[0][1]; rec[5] = Hp[0][2]; rec[6] = Hp[1][2];
-    rec[7] = Hp[0][0]; rec[8] = Hp[1][1]; rec[9] = Hp[2][2];
-    rec[10] = Hp[0][1]; rec[11] = Hp[0][2]; rec[12] = Hp[1][2];
     for (int a = 0; a < 3; ++a) { rec[13 + a] = g1e[a]; rec[16 + a] = g2e[a]; }
-    for (int k = 0; k < 6; ++k) { rec[19 + k] = De[k]; rec[25 + k] = Dhat[k]; }
-    rec[31] = Hp[0][0] + Hp[1][1] + Hp[2][2];
-    return 0;
+    for (int k = 0; k < 6; ++k) rec[19 + k] = De[k];
+    return orc_physical_record(c, i, gh, Hh, rec);
 }
 
 static void nan_record(double* rec) { for (int k = 0; k < ORC_REC; ++k) rec[k] = NAN; }
@@ -1058,4 +1068,182 @@ int orc_ppe_bicgstab(int64_t n, const int64_t* row_ptr, const int32_t* col, cons
     *relres = bb > 0.0 ? sqrt(orc_dot(n, t, t)) / bb : sqrt(orc_dot(n, t, t));
     free(buf);
     return status;
+}
+
+/* ================================================ conventional ISPH operators */
+
+/* The 0th-order models of Sec. 3.1 and the summation pressure gradient of
+ * Sec. 3.3, the operators of the ISPH case of Table case_names.  No correction
+ * matrix enters.  With r_ij = r_j - r_i and grad w_ij = -w'(r) r_ij / r (the
+ * gradient with respect to r_i of w(|r_j - r_i|)), r_ij . grad w_ij / |r_ij|^2
+ * is -w'(r) / r, written G below, and grad w_ij = G r_ij. */
+
+/* G = -w'(r)/r of the normalised kernel; NaN at r = 0 */
+static double orc_gfac(const orc_ctx* c, double r)
+{
+    double w, dwdr;
+    orc_kernel_eval(c->kernel, c->dim, c->R, r, &w, &dwdr);
+    return -dwdr / r;
+}
+
+/* projected offset r_ij and its squared length */
+static double orc_offset(const orc_ctx* c, int64_t i, int64_t j, double r[3])
+{
+    double r2 = 0.0;
+    for (int a = 0; a < c->dim; ++a) {
+        r[a] = c->pos[a * c->n + j] - c->pos[a * c->n + i];
+        r2 += r[a] * r[a];
+    }
+    return r2;
+}
+
+/* At particle i, for one field:
+ *   <grad^ phi>^(0)_i   = sum_j V_j phi_ij grad w_ij                (Sec. 3.1)
+ *   <d2 phi / dx^I dx^J>^(0)_i
+ *       = sum_j V_j (c r_ij^I r_ij^J / |r_ij|^2 - delta^IJ)
+ *                   (r_ij . grad w_ij / |r_ij|^2) phi_ij,  c = 4 (2-D), 5 (3-D)
+ *                                                   (Eq. sec_0th, Espanol & Revenga)
+ * then the physical record as for SPH(2).  Record slots 13:19 hold the 0th-order
+ * projected gradient (twice) and 19:25 the second derivatives in the SPH(2)
+ * vector order with doubled cross terms. */
+static int orc_particle_ops0(const orc_ctx* c, int64_t i, const int32_t* nb, int64_t deg, const double* ph,
+                             double* rec)
+{
+    const int d = c->dim;
+    const double cc = (d == 2) ? 4.0 : 5.0;
+    for (int k = 0; k < ORC_REC; ++k) rec[k] = 0.0;
+    double g[3] = {0, 0, 0}, H[3][3] = {{0}};
+    for (int64_t k = 0; k < deg; ++k) {
+        int64_t j = nb[k];
+        double r[3];
+        double r2 = orc_offset(c, i, j, r);
+        if (!(r2 > 0.0)) return ORC_F_DUPLICATE;
+        double G = orc_gfac(c, sqrt(r2));
+        double V = c->vol[j], fij = ph[j] - ph[i];
+        for (int a = 0; a < d; ++a) g[a] += V * fij * G * r[a];
+        for (int a = 0; a < d; ++a)
+            for (int b = 0; b < d; ++b)
+                H[a][b] += V * (cc * r[a] * r[b] / r2 - (a == b ? 1.0 : 0.0)) * G * fij;
+    }
+    /* embed in the 3-D component order (x, y, z^) */
+    double gh[3] = {0, 0, 0}, Hh[3][3] = {{0}};
+    int ax[3] = {0, 1, 2};
+    if (d == 2) { ax[0] = 0; ax[1] = 2; }
+    for (int a = 0; a < d; ++a) {
+        gh[ax[a]] = g[a];
+        for (int b = 0; b < d; ++b) Hh[ax[a]][ax[b]] = H[a][b];
+    }
+    for (int a = 0; a < 3; ++a) { rec[13 + a] = gh[a]; rec[16 + a] = gh[a]; }
+    if (d == 2) {
+        rec[19] = Hh[0][0]; rec[20] = Hh[2][2]; rec[21] = 2.0 * Hh[0][2];
+    } else {
+        rec[19] = Hh[0][0]; rec[20] = Hh[1][1]; rec[21] = Hh[2][2];
+        rec[22] = 2.0 * Hh[0][1]; rec[23] = 2.0 * Hh[0][2]; rec[24] = 2.0 * Hh[1][2];
+    }
+    return orc_physical_record(c, i, gh, Hh, rec);
+}
+
+/* 0th-order records for nf fields at rows (all particles if rows is NULL),
+ * laid out as orc_sph2's; flagged particles get NaN records. */
+int orc_ops0(int dim, int64_t n, const double* pos, const double* vol, int nf, const double* phi, int kernel,
+             double R, int map_kind, double Hhat, double H, double dmin, double eps, int nterms,
+             const double* terms, int64_t nrows, const int64_t* rows, const int64_t* row_ptr, const int32_t* col,
+             double* out, uint8_t* flags)
+{
+    if ((dim != 2 && dim != 3) || n < 0 || nf < 0 || !(R > 0)) return -1;
+    orc_ctx c;
+    ctx_init(&c, dim, n, pos, vol, kernel, R, map_kind, Hhat, H, dmin, eps, nterms, terms, 2);
+    #pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t r = 0; r < nrows; ++r) {
+        int64_t i = rows ? rows[r] : r;
+        const int32_t* nb = col + row_ptr[r];
+        int64_t deg = row_ptr[r + 1] - row_ptr[r];
+        int fl = 0;
+        for (int f = 0; f < nf; ++f) {
+            double* rec = out + ((size_t)r * nf + f) * ORC_REC;
+            int ff = orc_particle_ops0(&c, i, nb, deg, phi + (size_t)f * n, rec);
+            if (ff) nan_record(rec);
+            fl |= ff;
+        }
+        if (flags) flags[r] = (uint8_t)fl;
+    }
+    return 0;
+}
+
+/* 0th-order Laplacian of Sec. 3.1 (the Brookshaw form), in the projected space:
+ *   <lap phi>^(0)_i = 2 sum_j V_j (r_ij . grad w_ij / |r_ij|^2) phi_ij.
+ * out [nrows][nf]; NaN where a neighbour sits at zero distance. */
+int orc_lap0(int dim, int64_t n, const double* pos, const double* vol, int nf, const double* phi, int kernel,
+             double R, int64_t nrows, const int64_t* rows, const int64_t* row_ptr, const int32_t* col, double* out)
+{
+    if ((dim != 2 && dim != 3) || n < 0 || nf < 0 || !(R > 0)) return -1;
+    orc_ctx c;
+    ctx_init(&c, dim, n, pos, vol, kernel, R, ORC_MAP_IDENTITY, 1.0, 1.0, 0.0, 0.0, 0, NULL, 2);
+    #pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t r = 0; r < nrows; ++r) {
+        int64_t i = rows ? rows[r] : r;
+        for (int f = 0; f < nf; ++f) {
+            const double* ph = phi + (size_t)f * n;
+            double t = 0.0;
+            for (int64_t k = row_ptr[r]; k < row_ptr[r + 1]; ++k) {
+                double rv[3];
+                double r2 = orc_offset(&c, i, col[k], rv);
+                double G = r2 > 0.0 ? orc_gfac(&c, sqrt(r2)) : NAN;
+                t += c.vol[col[k]] * G * (ph[col[k]] - ph[i]);
+            }
+            out[(size_t)r * nf + f] = 2.0 * t;
+        }
+    }
+    return 0;
+}
+
+/* Summation pressure gradient (Eq. gra_sum) in the projected space,
+ *   <grad^ p>^+_i = rho_i sum_j m_j (p_j / rho_j^2 + p_i / rho_i^2) grad w_ij,
+ * with masses m_j = rho_j V_j (rho NULL: rho_j = rho0 for all j), and its
+ * physical form J <grad^ p>^+_i (Eq. grad_VCT).  out [nrows][6]: physical
+ * (x, y, z) then projected (x^, y^, z^); 2-D sets leave the y slots zero.
+ * NaN where alpha is not positive or a neighbour sits at zero distance. */
+int orc_grad_sum(int dim, int64_t n, const double* pos, const double* vol, const double* rho, double rho0,
+                 const double* p, int kernel, double R, int map_kind, double Hhat, double H, double dmin, double eps,
+                 int nterms, const double* terms, int64_t nrows, const int64_t* rows, const int64_t* row_ptr,
+                 const int32_t* col, double* out, uint8_t* flags)
+{
+    if ((dim != 2 && dim != 3) || n < 0 || !(R > 0)) return -1;
+    orc_ctx c;
+    ctx_init(&c, dim, n, pos, vol, kernel, R, map_kind, Hhat, H, dmin, eps, nterms, terms, 2);
+    #pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t r = 0; r < nrows; ++r) {
+        int64_t i = rows ? rows[r] : r;
+        double rhoi = rho ? rho[i] : rho0;
+        double t[3] = {0, 0, 0};
+        int fl = 0;
+        for (int64_t k = row_ptr[r]; k < row_ptr[r + 1]; ++k) {
+            int64_t j = col[k];
+            double rv[3];
+            double r2 = orc_offset(&c, i, j, rv);
+            if (!(r2 > 0.0)) fl |= ORC_F_DUPLICATE;
+            double G = orc_gfac(&c, sqrt(r2));
+            double rhoj = rho ? rho[j] : rho0;
+            double mj = rhoj * c.vol[j];
+            double s = mj * (p[j] / (rhoj * rhoj) + p[i] / (rhoi * rhoi));
+            for (int a = 0; a < dim; ++a) t[a] += s * G * rv[a];
+        }
+        double gh[3] = {rhoi * t[0], dim == 3 ? rhoi * t[1] : 0.0, rhoi * t[dim - 1]};
+        double x = c.pos[i], y = (dim == 3) ? c.pos[n + i] : 0.0, zh = c.pos[(dim - 1) * n + i];
+        double Jm[3][3], ct[6], hz[3][3];
+        orc_r_map_coeffs(&c.map, dim, x, y, zh, -1, 0.0, Jm, ct, hz);
+        if (!(Jm[2][2] > 0.0) || !isfinite(Jm[2][2] + Jm[0][2] + Jm[1][2])) fl |= ORC_F_MAP;
+        double* o = out + (size_t)r * 6;
+        for (int I = 0; I < 3; ++I) {
+            double v = 0.0;
+            for (int K = 0; K < 3; ++K) v += Jm[I][K] * gh[K];
+            o[I] = v;
+            o[3 + I] = gh[I];
+        }
+        if (dim == 2) o[1] = 0.0;
+        if (fl)
+            for (int a = 0; a < 6; ++a) o[a] = NAN;
+        if (flags) flags[r] = (uint8_t)fl;
+    }
+    return 0;
 }

@@ -1,7 +1,7 @@
 """Host code under AddressSanitizer and UndefinedBehaviorSanitizer (no GPU).
 
   * the oracle (orc.c) built with gcc -fsanitize=address,undefined runs every
-    oracle pin of test_oracle.py;
+    oracle pin (test_oracle.py, test_oracle_ppe.py, test_oracle_isph.py);
   * the library's host code (argument checks, map set-up, separable table,
     workspace carving, launch-timing registry) built with the same sanitizers
     on the host side only runs the ABI checks of test_abi.py.
@@ -17,13 +17,13 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def _run(env_extra, test_file):
+def _run(env_extra, *test_files):
     env = dict(os.environ)
     env.update(env_extra)
     env["ASAN_OPTIONS"] = "detect_leaks=0:abort_on_error=1"     # the interpreter itself is not instrumented
     env["UBSAN_OPTIONS"] = "print_stacktrace=1:halt_on_error=1"
     r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider", "-m", "not gpu",
-                        os.path.join(ROOT, "tests", test_file)], cwd=ROOT, env=env, capture_output=True, text=True,
+                        *[os.path.join(ROOT, "tests", f) for f in test_files]], cwd=ROOT, env=env, capture_output=True, text=True,
                        timeout=900)
     tail = (r.stdout + r.stderr)[-3000:]
     assert r.returncode == 0, tail
@@ -42,7 +42,7 @@ def test_oracle_pins_under_asan_ubsan():
     if rt is None:
         pytest.skip("gcc ASan runtime not installed")
     lib = oracle.build(sanitize=True, out=os.path.join(ROOT, "_build", "liborc_san.so"))
-    print(_run({"LD_PRELOAD": rt, "ORACLE_LIB": lib}, "test_oracle.py"))
+    print(_run({"LD_PRELOAD": rt, "ORACLE_LIB": lib}, "test_oracle.py", "test_oracle_ppe.py", "test_oracle_isph.py"))
 
 
 def test_library_host_code_under_asan_ubsan():
