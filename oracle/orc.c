@@ -1134,12 +1134,9 @@ static int orc_particle_ops0(const orc_ctx* c, int64_t i, const int32_t* nb, int
         for (int b = 0; b < d; ++b) Hh[ax[a]][ax[b]] = H[a][b];
     }
     for (int a = 0; a < 3; ++a) { rec[13 + a] = gh[a]; rec[16 + a] = gh[a]; }
-    if (d == 2) {
-        rec[19] = Hh[0][0]; rec[20] = Hh[2][2]; rec[21] = 2.0 * Hh[0][2];
-    } else {
-        rec[19] = Hh[0][0]; rec[20] = Hh[1][1]; rec[21] = Hh[2][2];
-        rec[22] = 2.0 * Hh[0][1]; rec[23] = 2.0 * Hh[0][2]; rec[24] = 2.0 * Hh[1][2];
-    }
+    /* 3-D slot order (xx, yy, zz, 2xy, 2xz, 2yz); 2-D sets leave the y slots zero */
+    rec[19] = Hh[0][0]; rec[20] = Hh[1][1]; rec[21] = Hh[2][2];
+    rec[22] = 2.0 * Hh[0][1]; rec[23] = 2.0 * Hh[0][2]; rec[24] = 2.0 * Hh[1][2];
     return orc_physical_record(c, i, gh, Hh, rec);
 }
 

@@ -67,6 +67,24 @@ def test_sec0th_trace_is_the_brookshaw_laplacian(family):
     assert np.abs(out[:, :, O.I_LAP] - lb).max() <= 1e-13 * np.abs(lb).max()
 
 
+@pytest.mark.parametrize("family", ["bf2d", "sigma3d"])
+def test_record_slots_follow_the_record_layout(family):
+    """The D slots (xx, yy, zz, 2xy, 2xz, 2yz) and the D^ slots
+    (dz^, xx, yy, zz, xz, yz) hold the same second derivatives, the gradient
+    slots the same gradient, and 2-D records leave every y slot zero."""
+    w = I.small(family)
+    out, _ = O.ops0(w.pos, w.vol, w.phi, w.kernel, w.R, w.mapspec, rows=np.arange(0, w.n, 11))
+    r = out.reshape(-1, O.REC)
+    D, Dh = r[:, O.I_D], r[:, O.I_DHAT]
+    assert np.array_equal(D[:, 0], Dh[:, 1]) and np.array_equal(D[:, 1], Dh[:, 2])
+    assert np.array_equal(D[:, 2], Dh[:, 3])
+    assert np.array_equal(D[:, 4], 2 * Dh[:, 4]) and np.array_equal(D[:, 5], 2 * Dh[:, 5])
+    assert np.array_equal(r[:, O.I_G1], r[:, O.I_G2]) and np.array_equal(r[:, O.I_G1][:, 2], Dh[:, 0])
+    if w.dim == 2:
+        y = [1, 4, 6, 8, 10, 12, 14, 17, 20, 22, 24, 27, 30]
+        assert not r[:, y].any()
+
+
 @pytest.mark.parametrize("dim", [2, 3])
 @pytest.mark.parametrize("kernel", [I.KERNEL_WENDLAND_C2, I.KERNEL_CUBIC_SPLINE])
 def test_zeroth_order_models_tend_to_the_exact_derivatives(dim, kernel):
