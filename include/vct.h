@@ -441,6 +441,43 @@ int vct_ppe_solve(const vct_nlist* nl, const double* pos_sorted, const double* v
                   double tol, int max_iter, int* iters /* host */, double* relres /* host */, void* ws,
                   size_t ws_bytes, void* stream);
 
+/* ---------------------------------------------------------------- conventional ISPH operators */
+
+/* The operators of the standard ISPH case of Table case_names, for comparison
+ * with SPH(2) on the same particles.  Neither needs vct_moments (no correction
+ * matrix).  Kernel gradient grad w_ij = -w'(r) r_ij / r, r_ij = r^_j - r^_i,
+ * of the normalised kernel (unit integral); outputs [nf][n][n_out] in sorted
+ * order, rows in the order of the mask as for vct_apply_ops.  A particle with
+ * a neighbour at zero distance, a non-finite position, or where the mapping is
+ * invalid (alpha not positive and finite) gets NaN outputs.  Asynchronous.
+ *
+ * vct_apply_ops0: the 0th-order models of Sec. 3.1 in the projected space,
+ *   grad^ phi_i   = sum_j V_j phi_ij grad w_ij
+ *   H^_IJ phi_i   = sum_j V_j (c r_ij^I r_ij^J / |r_ij|^2 - delta_IJ)
+ *                             (r_ij . grad w_ij / |r_ij|^2) phi_ij
+ *                   with c = 4 (2-D), 5 (3-D)             (Eq. sec_0th)
+ * mapped like the SPH(2) derivatives: GRAD = J grad^, LAP = c_trans . D^,
+ * CROSS and HESS = J H^ J^T + (d phi / d z^) (d2 z^)  (Eqs. grad_VCT, lap_VCT);
+ * PGRAD, PHESS and PZ are the projected values.  Under the identity map LAP is
+ * the trace of H^, which equals the Brookshaw Laplacian
+ * 2 sum_j V_j (r_ij . grad w_ij / |r_ij|^2) phi_ij of Sec. 3.1 (the weights
+ * c r^I r^I / |r|^2 - 1 sum to c - d = 2).  out_mask: any of GRAD, LAP, CROSS,
+ * HESS, PGRAD, PHESS, PZ (VCT_OPT_GRAD1 is an SPH(2) option: VCT_E_ARG).     */
+int vct_apply_ops0(const vct_nlist* nl, int nf, const double* phi_sorted, const double* pos_sorted,
+                   const double* vol_sorted, int kernel, const vct_map* map /* host */, uint32_t out_mask,
+                   double* out, void* stream);
+
+/* vct_grad_sum: the summation pressure gradient (Eq. gra_sum) in the projected
+ * space and its physical form (Eq. grad_VCT),
+ *   grad^ p_i = rho_i sum_j m_j (p_j / rho_j^2 + p_i / rho_i^2) grad w_ij,
+ *   m_j = rho_j V_j,
+ * with rho [n] per particle, or rho_j = rho0 for all j when rho is NULL
+ * (rho0 must then be finite and non-zero).  out_mask: GRAD (J grad^ p) and/or
+ * PGRAD (grad^ p); out [n][n_out].                                            */
+int vct_grad_sum(const vct_nlist* nl, const double* pos_sorted, const double* vol_sorted, int kernel,
+                 const vct_map* map /* host */, const double* rho, double rho0, const double* p, uint32_t out_mask,
+                 double* out, void* stream);
+
 /* ---------------------------------------------------------------- allocation-free adjoint */
 
 /* Size of the library's own scratch for vct_apply_ops_adjoint_noalloc. */

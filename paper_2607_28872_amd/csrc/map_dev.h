@@ -273,4 +273,54 @@ __device__ __forceinline__ MapCoef<T> map_coef(const MapParams& mp, const T h[6]
     return c;
 }
 
+// Physical (and projected) outputs from a projected gradient pg and projected
+// second derivatives ph (pairs order), in the row order of the output mask.
+// Linear in (pg, ph): applied to one column of the solved system it yields
+// that column of P.  Eq. grad_VCT, Eq. lap_VCT, and the chain rule
+// Hess = J H^ J^T + dz^phi (d2 z^) for the cross and full Hessian rows.
+template <int D, class Put>
+__device__ __forceinline__ int emit_rows(uint32_t mask, const MapCoef<double>& c, const double* pg,
+                                         const double* ph, Put&& out) {
+    int o = 0;
+    if (D == 3) {
+        const double gz = pg[2];
+        const double Hxx = ph[0], Hyy = ph[1], Hzz = ph[2], Hxy = ph[3], Hxz = ph[4], Hyz = ph[5];
+        const double xy = Hxy + c.gy * Hxz + c.gx * Hyz + c.gx * c.gy * Hzz + c.zxy * gz;
+        const double xz = c.alpha * (Hxz + c.gx * Hzz) + c.zxz * gz;
+        const double yz = c.alpha * (Hyz + c.gy * Hzz) + c.zyz * gz;
+        if (mask & VCT_OUT_GRAD) {
+            out(o++, pg[0] + c.gx * gz);
+            out(o++, pg[1] + c.gy * gz);
+            out(o++, c.alpha * gz);
+        }
+        if (mask & VCT_OUT_LAP) out(o++, c.c0 * gz + Hxx + Hyy + c.c3 * Hzz + c.c4 * Hxz + c.c5 * Hyz);
+        if (mask & VCT_OUT_CROSS) { out(o++, xy); out(o++, xz); out(o++, yz); }
+        if (mask & VCT_OUT_HESS) {
+            out(o++, Hxx + 2.0 * c.gx * Hxz + c.gx * c.gx * Hzz + c.zxx * gz);
+            out(o++, Hyy + 2.0 * c.gy * Hyz + c.gy * c.gy * Hzz + c.zyy * gz);
+            out(o++, c.alpha * c.alpha * Hzz);
+            out(o++, xy); out(o++, xz); out(o++, yz);
+        }
+        if (mask & VCT_OUT_PGRAD) { out(o++, pg[0]); out(o++, pg[1]); out(o++, pg[2]); }
+        if (mask & VCT_OUT_PHESS) for (int p = 0; p < 6; ++p) out(o++, ph[p]);
+        if (mask & VCT_OUT_PZ) { out(o++, gz); out(o++, Hzz); out(o++, Hxz); out(o++, Hyz); }
+    } else {
+        const double gz = pg[1];
+        const double Hxx = ph[0], Hzz = ph[1], Hxz = ph[2];
+        const double xz = c.alpha * (Hxz + c.gx * Hzz) + c.zxz * gz;
+        if (mask & VCT_OUT_GRAD) { out(o++, pg[0] + c.gx * gz); out(o++, c.alpha * gz); }
+        if (mask & VCT_OUT_LAP) out(o++, c.c0 * gz + Hxx + c.c3 * Hzz + c.c4 * Hxz);
+        if (mask & VCT_OUT_CROSS) out(o++, xz);
+        if (mask & VCT_OUT_HESS) {
+            out(o++, Hxx + 2.0 * c.gx * Hxz + c.gx * c.gx * Hzz + c.zxx * gz);
+            out(o++, c.alpha * c.alpha * Hzz);
+            out(o++, xz);
+        }
+        if (mask & VCT_OUT_PGRAD) { out(o++, pg[0]); out(o++, pg[1]); }
+        if (mask & VCT_OUT_PHESS) for (int p = 0; p < 3; ++p) out(o++, ph[p]);
+        if (mask & VCT_OUT_PZ) { out(o++, gz); out(o++, Hzz); out(o++, Hxz); }
+    }
+    return o;
+}
+
 }  // namespace vct

@@ -80,7 +80,7 @@ __device__ __forceinline__ double kernel_value(double q, double R) {
 //   MODE 0: right-hand side (nc = dim velocity components);
 //   MODE 1: corrector (nc = 1, the pressure).
 template <int D, int KERNEL, int MODE>
-__global__ __launch_bounds__(kQThreads, 2) void k_ppe_first(PpeArgs A, MapParams mp) {
+__global__ __launch_bounds__(kQThreads, 4) void k_ppe_first(PpeArgs A, MapParams mp) {
     using Dm = Dims<D>;
     constexpr int nL = Dm::nL;
     constexpr int NC = MODE == 0 ? D : 1;

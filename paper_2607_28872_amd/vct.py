@@ -127,6 +127,11 @@ def lib():
         L.vct_ppe_solve.restype = C.c_int
         L.vct_ppe_solve.argtypes = [_nlp, _vp, _vp, C.c_int, _vp, C.c_uint32, _vp, _vp, _vp, C.c_double, C.c_int,
                                     C.POINTER(C.c_int), C.POINTER(C.c_double), _vp, _sz, _vp]
+        L.vct_apply_ops0.restype = C.c_int
+        L.vct_apply_ops0.argtypes = [_nlp, C.c_int, _vp, _vp, _vp, C.c_int, C.POINTER(vct_map), C.c_uint32, _vp, _vp]
+        L.vct_grad_sum.restype = C.c_int
+        L.vct_grad_sum.argtypes = [_nlp, _vp, _vp, C.c_int, C.POINTER(vct_map), _vp, C.c_double, _vp, C.c_uint32,
+                                   _vp, _vp]
         L.vct_apply_ops_adjoint_noalloc.restype = C.c_int
         L.vct_apply_ops_adjoint_noalloc.argtypes = [_nlp, _vp, _vp, C.c_int, _vp, C.c_uint32, C.POINTER(vct_map), _vp,
                                                     _vp, _vp, _vp, _vp]
@@ -326,6 +331,18 @@ def vct_ppe_solve(nl, pos_sorted, vol_sorted, kernel, state64, mask, dirichlet, 
     return st, it.value, rr.value
 
 
+def vct_apply_ops0(nl, nf, phi_sorted, pos_sorted, vol_sorted, kernel, cmap, mask, out, stream=None):
+    return _check("vct_apply_ops0", lib().vct_apply_ops0(
+        C.byref(nl), int(nf), _p(phi_sorted), _p(pos_sorted), _p(vol_sorted), kernel, C.byref(cmap), mask, _p(out),
+        _stream(stream)))
+
+
+def vct_grad_sum(nl, pos_sorted, vol_sorted, kernel, cmap, rho, rho0, p, mask, out, stream=None):
+    return _check("vct_grad_sum", lib().vct_grad_sum(
+        C.byref(nl), _p(pos_sorted), _p(vol_sorted), kernel, C.byref(cmap), _p(rho), float(rho0), _p(p), mask,
+        _p(out), _stream(stream)))
+
+
 # ---------------------------------------------------------------- orchestration
 
 def _bytes(nbytes, device):
@@ -449,6 +466,25 @@ class Geometry:
         if state is None:
             raise ValueError("VCT_MIXED needs moments(..., fp32_copy=True)")
         vct_apply_ops(self.nl, nf, phi_sorted, self.pos, self.vol, self.kernel, state, self.mask, precision, out)
+        return out
+
+    def apply0(self, mapspec, phi_sorted, mask=VCT_OUT_DEFAULT, out=None):
+        """The 0th-order operators (conventional ISPH) of nf sorted fields:
+        (nf, n, n_out) FP64.  Needs no moments."""
+        import torch
+        nf = int(phi_sorted.shape[0])
+        nout = vct_n_out(self.dim, mask)
+        if out is None:
+            out = torch.empty((nf, max(self.n, 1), nout), dtype=torch.float64, device=self.device)
+        vct_apply_ops0(self.nl, nf, phi_sorted, self.pos, self.vol, self.kernel, make_map(mapspec), mask, out)
+        return out
+
+    def grad_sum(self, mapspec, p_sorted, rho_sorted=None, rho0=1.0, mask=VCT_OUT_GRAD | VCT_OUT_PGRAD):
+        """Summation pressure gradient (n, n_out) FP64 of a sorted pressure field."""
+        import torch
+        out = torch.empty((max(self.n, 1), vct_n_out(self.dim, mask)), dtype=torch.float64, device=self.device)
+        vct_grad_sum(self.nl, self.pos, self.vol, self.kernel, make_map(mapspec), rho_sorted, rho0, p_sorted, mask,
+                     out)
         return out
 
     def adjoint(self, u_sorted, proj=None, want_dtheta=True):

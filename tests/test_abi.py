@@ -133,6 +133,16 @@ def test_argument_errors_are_caught_on_the_host(L):
                  vct.VCT_OUT_LAP | vct.VCT_OUT_PHESS):
         assert L.vct_apply_ops_adjoint(C.byref(nl), None, None, 0, None, mask, C.byref(m), None, None,
                                        None, None, None, 0, None) == E
+    # conventional ISPH operators
+    assert L.vct_apply_ops0(C.byref(nl), 1, None, None, None, 0, C.byref(m), 3, None, None) == E  # no arrays
+    assert L.vct_apply_ops0(C.byref(nl), 1, None, None, None, 0, None, 3, None, None) == E        # no map
+    assert L.vct_apply_ops0(C.byref(nl), 1, None, None, None, 0, C.byref(m), 3 | vct.VCT_OPT_GRAD1, None,
+                            None) == E                                                           # SPH(2) option
+    assert L.vct_apply_ops0(C.byref(nl), -1, None, None, None, 0, C.byref(m), 3, None, None) == E  # nf
+    assert L.vct_grad_sum(C.byref(nl), None, None, 0, C.byref(m), None, 1.0, None, vct.VCT_OUT_LAP, None,
+                          None) == E                                                             # rows
+    assert L.vct_grad_sum(C.byref(nl), None, None, 0, C.byref(m), None, 0.0, None, vct.VCT_OUT_GRAD, None,
+                          None) == E                                                             # rho0 = 0
 
 
 def test_workspace_errors(L):
