@@ -41,7 +41,7 @@ FP64_PEAK_TFLOPS = 78.6
 #   pass 2 = offsets and q^2 (11), monomials (16), r~.L~.r~ (12), weight (12),
 #   C sums (20), E sums of the 15 quartic monomials (45);
 #   moment solve, per particle: the Schur LU and folds (about 3200);
-#   adjoint d/dphi, per directed neighbour entry: the method needs one
+#   adjoint d/dphi (push form), per directed neighbour entry: the method needs one
 #   Laplacian weight W_ik per entry (the row sums u_k sum_j W_kj are a
 #   by-product of the same weights): offsets and q^2 (11), pair monomials (6),
 #   kernel value and 1/q^4 (10), r~.L~.r~ (12), the Laplacian row contraction
@@ -287,7 +287,7 @@ def main():
         "k_apply (fp64)": ("hbm", b_fp64_adj, HBM_PEAK_GBS),
         "k_moment_sweeps": ("alu", pairs * MOMENT_FLOP_PER_PAIR_3D, FP64_PEAK_TFLOPS),
         "k_moment_solve": ("alu", n * MOMENT_FLOP_SOLVE_3D, FP64_PEAK_TFLOPS),
-        "k_adjoint_dphi": ("alu", pairs * ADJOINT_DPHI_FLOP_PER_ENTRY_3D, FP64_PEAK_TFLOPS),
+        "k_adjoint_push": ("alu", pairs * ADJOINT_DPHI_FLOP_PER_ENTRY_3D, FP64_PEAK_TFLOPS),
         "k_nb_chunk (stage)": ("alu", candidates * NB_FLOP_PER_CANDIDATE, FP32_VALU_PEAK_TFLOPS),
     }
     kernels = {k: {"launches_per_step": c / args.steps, "ms_per_step": round(t / args.steps, 4),

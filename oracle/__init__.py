@@ -77,6 +77,8 @@ def lib():
         L.orc_sph2.argtypes = [C.c_int, C.c_int64, dp, dp, C.c_int, dp, C.c_int, C.c_double,
                                C.c_int, C.c_double, C.c_double, C.c_double, C.c_double, C.c_int, dp,
                                C.c_int, C.c_int64, ip64, ip64, ip32, dp, u8p]
+        L.orc_jbar_smooth.restype = C.c_int
+        L.orc_jbar_smooth.argtypes = [C.c_int, C.c_int64, dp, dp, dp, C.c_double, C.c_double, ip64, ip64, ip32]
         L.orc_adjoint_dphi.restype = C.c_int
         L.orc_adjoint_dphi.argtypes = [C.c_int, C.c_int64, dp, dp, C.c_int, C.c_double, C.c_int,
                                        C.c_double, C.c_double, C.c_double, C.c_double, C.c_int, dp,
@@ -413,3 +415,24 @@ def grad_sum(pos, vol, p, kernel, R, mapspec, rho=None, rho0=1.0, rows=None, csr
     if st != 0:
         raise RuntimeError(f"orc_grad_sum failed ({st})")
     return out[:, :3], out[:, 3:], flags
+
+
+# ------------------------------------------------------ volume smoothing (Sec. 3.6)
+
+
+def jbar_smooth(pos, J, jbar, cv, re, order=None, csr=None):
+    """Jbar^N from Jbar^(N-1) by Eq. VCT_bar_a, sequentially: targets in
+    `order` (index order if None), the neighbours of each in the order of its
+    CSR row (`csr` in original indices; the oracle's grid search if None)."""
+    pos = _f64(pos)
+    dim, n = pos.shape
+    rp, col = _csr(pos, re, csr)
+    out = _f64(jbar).copy()
+    order_a = None if order is None else np.ascontiguousarray(order, dtype=np.int64)
+    if order_a is not None and (order_a.shape != (n,) or not np.array_equal(np.sort(order_a), np.arange(n))):
+        raise ValueError("order must be a permutation of the particles")
+    st = lib().orc_jbar_smooth(dim, n, _p(pos), _p(_f64(J)), _p(out), float(cv), float(re), _p(order_a, C.c_int64),
+                               _p(rp, C.c_int64), _p(col if col.size else np.zeros(1, np.int32), C.c_int32))
+    if st != 0:
+        raise RuntimeError("orc_jbar_smooth failed")
+    return out

@@ -1244,3 +1244,45 @@ int orc_grad_sum(int dim, int64_t n, const double* pos, const double* vol, const
     }
     return 0;
 }
+
+/* ------------------------------------------------------------------ volume smoothing (Sec. 3.6) */
+
+/* Smoothed Jacobian determinant Jbar^N from Jbar^(N-1) (Sec. 3.6, Eq. VCT_bar_a).
+ *
+ * With the representative volume V_i = J_i / Jbar_i V, a neighbour pair (i, j)
+ * exchanges the volume dV_ij = dJ_ij V,
+ *   dJ_ij = C_V (r_e - |r^_ij|) / r_e (J_j / Jbar_j - J_i / Jbar_i),
+ * and the two smoothed determinants become
+ *   Jbar_i <- J_i Jbar_i / (J_i + Jbar_i dJ_ij),
+ *   Jbar_j <- J_j Jbar_j / (J_j - Jbar_j dJ_ij).
+ * The paper applies this to the neighbours j of a target particle i one after
+ * the other, each update seen by the next.  Readings: every particle is a
+ * target once, so each neighbour pair is visited from both of its ends; the
+ * paper leaves the order of the targets open, so it is an argument (`order`,
+ * a permutation of 0..n-1, NULL for index order), and the neighbours of a
+ * target are taken in the order of its CSR row.  |r^_ij| is the projected
+ * distance (r_e is the support radius of the neighbour set).  Sequential,
+ * single-threaded.  jbar is updated in place. */
+int orc_jbar_smooth(int dim, int64_t n, const double* pos, const double* J, double* jbar, double cv, double re,
+                    const int64_t* order, const int64_t* row_ptr, const int32_t* col)
+{
+    if (dim != 2 && dim != 3) return -1;
+    for (int64_t s = 0; s < n; ++s) {
+        int64_t i = order ? order[s] : s;
+        if (i < 0 || i >= n) return -1;
+        for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
+            int64_t j = col[k];
+            double r2 = 0.0;
+            for (int a = 0; a < dim; ++a) {
+                double d = pos[a * n + j] - pos[a * n + i];
+                r2 += d * d;
+            }
+            double dJ = cv * (re - sqrt(r2)) / re * (J[j] / jbar[j] - J[i] / jbar[i]);
+            double bi = J[i] * jbar[i] / (J[i] + jbar[i] * dJ);
+            double bj = J[j] * jbar[j] / (J[j] - jbar[j] * dJ);
+            jbar[i] = bi;
+            jbar[j] = bj;
+        }
+    }
+    return 0;
+}

@@ -40,7 +40,7 @@ MAP_NAMES = {MAP_IDENTITY: "identity", MAP_E: "E-SPH", MAP_BF: "BF-SPH",
 
 KERNEL_WENDLAND_C2, KERNEL_CUBIC_SPLINE = 0, 1
 
-SEED_POS, SEED_QUAD, SEED_PQUAD, SEED_THETA, SEED_TARGET, SEED_ORDER = 0, 1, 2, 3, 4, 5
+SEED_POS, SEED_QUAD, SEED_PQUAD, SEED_THETA, SEED_TARGET, SEED_ORDER, SEED_JBAR = 0, 1, 2, 3, 4, 5, 6
 
 
 @dataclass
@@ -276,6 +276,13 @@ def velocity_field(pos):
     zmax = float(pos[-1].max()) if pos.size else 1.0
     return np.stack([np.sin(2 * math.pi * pos[0] + a) * np.cos(math.pi * pos[-1] / zmax) + 0.1 * (a + 1)
                      for a in range(pos.shape[0])])
+
+
+def volume_perturbation(n, amp=0.05, seed=SEED_JBAR):
+    """Seeded factors 1 + U(-amp, amp) (n,): multiplied into the Jacobian
+    determinant they give a previous smoothed determinant Jbar^(N-1) whose
+    volume ratios J / Jbar scatter by about amp, as after particle motion."""
+    return 1.0 + np.random.default_rng(seed).uniform(-amp, amp, size=n)
 
 
 def theta0(seed=SEED_THETA):
