@@ -384,6 +384,7 @@ def main():
     del lap_pm, a, b, o, ph, v
 
     res["ppe"] = ppe_measure(args, w, vct, L, nl, pos_s, vol_s, sta, adj_mask, ms, perm, dev)
+    res["jbar"] = jbar_measure(w, vct, L, nl, pos_s, cmap, perm, dev)
 
     if not args.no_cpu_baseline:
         progress("CPU oracle on a sample")
@@ -442,6 +443,43 @@ def ppe_measure(args, w, vct, L, nl, pos_s, vol_s, sta, mask, ms, perm, dev):
             "ms_per_iteration": round(t * 1e3 / max(it, 1), 4),
             "matvec_avg_ms": round(matvec[1] / max(matvec[0], 1), 4), "matvecs": matvec[0],
             "kernels": {k: {"launches": c, "avg_ms": round(ms_ / c, 4)} for k, (c, ms_) in sorted(kt.items())}}
+
+
+def jbar_measure(w, vct, L, nl, pos_s, cmap, perm, dev, reps=3):
+    """The volume smoothing of the sigma method (Eq. VCT_bar_a) on the
+    benchmark geometry (outside the timed steps): J = alpha of the mapping at
+    every particle, Jbar^(N-1) = J scaled by seeded factors 1 + U(-0.05, 0.05),
+    C_V = 1e-2 (dt x 10^2 with dt = 1e-4), r_e = R."""
+    import numpy as np
+    import torch
+    from paper_2607_28872_amd import inputs as I
+    progress("volume smoothing")
+    n = w.n
+    J = torch.empty(n, dtype=torch.float64, device=dev)
+    vct.vct_map_alpha(w.dim, n, pos_s, cmap, J)
+    fac = torch.as_tensor(I.volume_perturbation(n)[perm[:n].long().cpu().numpy()], device=dev)
+    jb0 = J * fac
+    ws = torch.empty(L.vct_jbar_workspace_size(n), dtype=torch.uint8, device=dev)
+    jb = jb0.clone()
+    vct.vct_jbar_smooth(nl, pos_s, J, jb, 1e-2, w.R, ws)   # warm-up
+    torch.cuda.synchronize()
+    vct.vct_timing_reset()
+    vct.vct_timing_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        jb.copy_(jb0)
+        vct.vct_jbar_smooth(nl, pos_s, J, jb, 1e-2, w.R, ws)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / reps
+    vct.vct_timing_enable(False)
+    kt = vct.vct_timing_read()
+    vct.vct_timing_reset()
+    v0 = float((J / jb0).sum().item())
+    v1 = float((J / jb).sum().item())
+    return {"what": "smoothed Jacobian determinant (Eq. VCT_bar_a), 27 colour phases of cells, C_V = 1e-2",
+            "ms": round(t * 1e3, 3), "volume_drift": abs(v1 - v0) / v0,
+            "kernels": {k: {"launches": c // reps, "ms_per_call": round(ms_ / reps, 4)} for k, (c, ms_) in sorted(kt.items())
+                        if k.startswith("k_jbar")}}
 
 
 def cpu_model():

@@ -478,6 +478,43 @@ int vct_grad_sum(const vct_nlist* nl, const double* pos_sorted, const double* vo
                  const vct_map* map /* host */, const double* rho, double rho0, const double* p, uint32_t out_mask,
                  double* out, void* stream);
 
+/* ---------------------------------------------------------------- volume smoothing (Sec. 3.6) */
+
+/* The Jacobian determinant J = det J = alpha of the mapping (Sec. 2.1,
+ * Eq. det_jacobi) at n points pos (SoA [dim][n], projected; any order):
+ * J^N for vct_jbar_smooth and for the ratio Jbar / J of vct_ppe_rhs.  alpha
+ * [n] device output.  Asynchronous.                                         */
+int vct_map_alpha(int dim, int64_t n, const double* pos, const vct_map* map /* host */, double* alpha, void* stream);
+
+/* Workspace of vct_jbar_smooth: n doubles. */
+size_t vct_jbar_workspace_size(int64_t n);
+
+/* The smoothed Jacobian determinant Jbar^N of the sigma method (paper
+ * Sec. 3.6, Eq. VCT_bar_a), used by Eq. VCT_ppe_w (jr = Jbar / J of
+ * vct_ppe_rhs).  With V_i = J_i / Jbar_i V, each neighbour pair (i, j)
+ * exchanges the volume
+ *   dJ_ij V,  dJ_ij = cv (re - |r^_ij|) / re (J_j / Jbar_j - J_i / Jbar_i),
+ *   Jbar_i <- J_i Jbar_i / (J_i + Jbar_i dJ_ij),
+ *   Jbar_j <- J_j Jbar_j / (J_j - Jbar_j dJ_ij),
+ * along the neighbours j of each target particle i in turn, each update seen
+ * by the next; every particle is a target once (so each pair is visited from
+ * both ends).  The paper leaves the order of the targets open; here it is:
+ * cells in 3^d phases, the cell with coordinates (cx, [cy,] cz) in phase
+ * (cx mod 3) + 3 (cy mod 3) + 9 (cz mod 3) (2-D: (cx mod 3) + 3 (cz mod 3)),
+ * phases in increasing order, the targets of a cell in sorted order, the
+ * neighbours of a target in the order of its row.  Cells of one phase touch
+ * disjoint particles, so they run in parallel; the result is that of the
+ * sequential update in this order, up to rounding (the exchanges are formed
+ * as J / Jbar values and a prefix scan over each row).
+ *   J     [n]  Jacobian determinant J^N (alpha of the mapping, Eq. det_jacobi)
+ *   jbar  [n]  in: Jbar^(N-1); out: Jbar^N (in place)
+ *   cv         C_V (finite); re: r_e > 0 (normally the support radius nl->R)
+ * Needs the neighbour lists (col16, chunk table) of vct_neighbors on the same
+ * pos_sorted.  Non-finite J or Jbar propagate NaN to the particles they reach.
+ * Asynchronous.                                                               */
+int vct_jbar_smooth(const vct_nlist* nl, const double* pos_sorted, const double* J, double* jbar, double cv,
+                    double re, void* ws, size_t ws_bytes, void* stream);
+
 /* ---------------------------------------------------------------- allocation-free adjoint */
 
 /* Size of the library's own scratch for vct_apply_ops_adjoint_noalloc. */

@@ -18,7 +18,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libvct.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
-SOURCES = ["api.hip", "cells.hip", "moments.hip", "apply.hip", "adjoint.hip", "ppe.hip", "isph.hip"]
+SOURCES = ["api.hip", "cells.hip", "moments.hip", "apply.hip", "adjoint.hip", "ppe.hip", "isph.hip", "jbar.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

@@ -135,6 +135,12 @@ def lib():
         L.vct_apply_ops_adjoint_noalloc.restype = C.c_int
         L.vct_apply_ops_adjoint_noalloc.argtypes = [_nlp, _vp, _vp, C.c_int, _vp, C.c_uint32, C.POINTER(vct_map), _vp,
                                                     _vp, _vp, _vp, _vp]
+        L.vct_map_alpha.restype = C.c_int
+        L.vct_map_alpha.argtypes = [C.c_int, _i64, _vp, C.POINTER(vct_map), _vp, _vp]
+        L.vct_jbar_workspace_size.restype = _sz
+        L.vct_jbar_workspace_size.argtypes = [_i64]
+        L.vct_jbar_smooth.restype = C.c_int
+        L.vct_jbar_smooth.argtypes = [_nlp, _vp, _vp, _vp, C.c_double, C.c_double, _vp, _sz, _vp]
         _lib = L
     return _lib
 
@@ -343,6 +349,16 @@ def vct_grad_sum(nl, pos_sorted, vol_sorted, kernel, cmap, rho, rho0, p, mask, o
         _p(out), _stream(stream)))
 
 
+def vct_map_alpha(dim, n, pos, cmap, alpha, stream=None):
+    return _check("vct_map_alpha", lib().vct_map_alpha(int(dim), int(n), _p(pos), C.byref(cmap), _p(alpha),
+                                                       _stream(stream)))
+
+
+def vct_jbar_smooth(nl, pos_sorted, J, jbar, cv, re, ws, stream=None):
+    return _check("vct_jbar_smooth", lib().vct_jbar_smooth(
+        C.byref(nl), _p(pos_sorted), _p(J), _p(jbar), float(cv), float(re), _p(ws), _nbytes(ws), _stream(stream)))
+
+
 # ---------------------------------------------------------------- orchestration
 
 def _bytes(nbytes, device):
@@ -499,6 +515,20 @@ class Geometry:
         vct_apply_ops_adjoint(self.nl, self.pos, self.vol, self.kernel, self.state64, self.mask, self.cmap, proj,
                               u_sorted, dphi, dth, ws)
         return dphi[: self.n], (dth[:nt] if dth is not None else None)
+
+    def map_alpha(self, mapspec):
+        """J = alpha of the mapping at the sorted particles (n,) FP64."""
+        import torch
+        out = torch.empty(max(self.n, 1), dtype=torch.float64, device=self.device)
+        vct_map_alpha(self.dim, self.n, self.pos, make_map(mapspec), out)
+        return out[: self.n]
+
+    def jbar_smooth(self, J_sorted, jbar_sorted, cv, re=None):
+        """Jbar^N from Jbar^(N-1) (sorted, updated in place) for the Jacobian
+        determinants J (sorted); r_e defaults to the support radius."""
+        ws = _bytes(lib().vct_jbar_workspace_size(self.n), self.device)
+        vct_jbar_smooth(self.nl, self.pos, J_sorted, jbar_sorted, cv, self.R if re is None else re, ws)
+        return jbar_sorted
 
     def csr_original(self):
         """Neighbour lists in original indices, rows in original order, columns
