@@ -79,6 +79,16 @@ def lib():
                                C.c_int, C.c_int64, ip64, ip64, ip32, dp, u8p]
         L.orc_jbar_smooth.restype = C.c_int
         L.orc_jbar_smooth.argtypes = [C.c_int, C.c_int64, dp, dp, dp, C.c_double, C.c_double, ip64, ip64, ip32]
+        L.orc_r2_dzhat.restype = C.c_int
+        L.orc_r2_dzhat.argtypes = [C.c_int, C.c_int64, dp, dp, dp, C.c_int, C.c_double, C.c_int, C.c_double,
+                                   C.c_double, C.c_double, C.c_double, C.c_int, dp, dp, C.c_int, C.c_int64, ip64,
+                                   ip64, ip32, dp]
+        L.orc_project.restype = C.c_int
+        L.orc_project.argtypes = [C.c_int, C.c_int64, dp, C.c_int, C.c_double, C.c_double, C.c_double, C.c_double,
+                                  C.c_int, dp, dp]
+        L.orc_r2_dtheta.restype = C.c_int
+        L.orc_r2_dtheta.argtypes = [C.c_int, C.c_int64, dp, dp, dp, dp, C.c_int, C.c_double, C.c_int, C.c_double,
+                                    C.c_double, C.c_double, C.c_double, C.c_int, dp, C.c_int, ip32, ip64, ip32, dp]
         L.orc_adjoint_dphi.restype = C.c_int
         L.orc_adjoint_dphi.argtypes = [C.c_int, C.c_int64, dp, dp, C.c_int, C.c_double, C.c_int,
                                        C.c_double, C.c_double, C.c_double, C.c_double, C.c_int, dp,
@@ -435,4 +445,53 @@ def jbar_smooth(pos, J, jbar, cv, re, order=None, csr=None):
                                _p(rp, C.c_int64), _p(col if col.size else np.zeros(1, np.int32), C.c_int32))
     if st != 0:
         raise RuntimeError("orc_jbar_smooth failed")
+    return out
+
+
+# ------------------------------------------------ bathymetry adjoint, reading R2
+
+
+def project(phys, mapspec):
+    """Projected positions of physical points (dim, n): z^ = alpha (z + beta)."""
+    phys = _f64(phys)
+    dim, n = phys.shape
+    out = np.zeros_like(phys)
+    kind, Hh, H, dmin, eps, nt, terms = _map_args(mapspec)
+    lib().orc_project(dim, n, _p(phys), kind, Hh, H, dmin, eps, nt, _p(terms), _p(out))
+    return out
+
+
+def r2_dzhat(pos, vol, phi, kernel, R, mapspec, u, ks=None, csr=None, ct_dep=True):
+    """d loss / d z^_k (loss = sum (lap - g)^2, u = 2 (lap - g)) at sampled
+    particles, by the complex step of z^_k; ct_dep=False holds c_trans."""
+    pos, vol, phi, u = _f64(pos), _f64(vol), _f64(phi).reshape(-1), _f64(u)
+    dim, n = pos.shape
+    rp, col = _csr(pos, R, csr)
+    ks_a = None if ks is None else np.ascontiguousarray(ks, dtype=np.int64)
+    nk = n if ks_a is None else ks_a.shape[0]
+    out = np.zeros(nk)
+    kind, Hh, H, dmin, eps, nt, terms = _map_args(mapspec)
+    st = lib().orc_r2_dzhat(dim, n, _p(pos), _p(vol), _p(phi), int(kernel), float(R), kind, Hh, H, dmin, eps, nt,
+                            _p(terms), _p(u), int(bool(ct_dep)), nk, _p(ks_a, C.c_int64), _p(rp, C.c_int64),
+                            _p(col if col.size else np.zeros(1, np.int32), C.c_int32), _p(out))
+    if st != 0:
+        raise RuntimeError("orc_r2_dzhat failed")
+    return out
+
+
+def r2_dtheta(phys, vol, phi, g, kernel, R, mapspec, tlist, csr):
+    """d loss / d coef_t with physical positions fixed (reading R2), by the
+    complex step through the whole evaluation; csr: neighbour lists of the
+    projected positions (original indices)."""
+    phys, vol, phi, g = _f64(phys), _f64(vol), _f64(phi).reshape(-1), _f64(g)
+    dim, n = phys.shape
+    rp, col = np.ascontiguousarray(csr[0], dtype=np.int64), np.ascontiguousarray(csr[1], dtype=np.int32)
+    tl = np.ascontiguousarray(tlist, dtype=np.int32)
+    out = np.zeros(tl.shape[0])
+    kind, Hh, H, dmin, eps, nt, terms = _map_args(mapspec)
+    st = lib().orc_r2_dtheta(dim, n, _p(phys), _p(vol), _p(phi), _p(g), int(kernel), float(R), kind, Hh, H, dmin,
+                             eps, nt, _p(terms), tl.shape[0], _p(tl, C.c_int32), _p(rp, C.c_int64),
+                             _p(col if col.size else np.zeros(1, np.int32), C.c_int32), _p(out))
+    if st != 0:
+        raise RuntimeError("orc_r2_dtheta failed")
     return out

@@ -1286,3 +1286,286 @@ int orc_jbar_smooth(int dim, int64_t n, const double* pos, const double* J, doub
     }
     return 0;
 }
+
+/* ------------------------------------------------ bathymetry adjoint, reading R2 */
+
+/* Under reading R2 the particles' PHYSICAL positions are held fixed while the
+ * bathymetry coefficients change, so the projected heights move with them,
+ * z^_j = alpha(x_j, y_j) (z_j + beta(x_j, y_j)) (Sec. 2.1, Eq. VCT), and the
+ * SPH(2) derivatives of every row change through the offsets r^_ij, the
+ * correction matrices L_i and the moment matrices M_i (Eq. sec_SPH2).  The
+ * oracle differentiates the literal two-stage formula by the complex step:
+ * the rows below repeat the steps of orc_particle_geometry and
+ * orc_particle_field in complex arithmetic (analytic in the heights; pivots and
+ * kernel branches are chosen on real parts, which equal the real evaluation).
+ * Field values, volumes, the loss target and the neighbour lists are fixed. */
+
+/* -w'(r)/r of the normalised kernel at complex r^2 (r = csqrt(d2)) */
+static double complex orc_c_gfac(int kernel, int dim, double R, double complex d2)
+{
+    double complex r = csqrt(d2);
+    if (kernel == ORC_K_WENDLAND) {
+        double C = (dim == 2) ? 7.0 / (M_PI * R * R) : 21.0 / (2.0 * M_PI * R * R * R);
+        double complex q = r / R;
+        if (creal(q) >= 1.0) return 0.0;
+        double complex a = 1.0 - q;
+        return C * 20.0 * a * a * a / (R * R);   /* -dw/dr / r with dw/dr = -20 C q a^3 / R */
+    }
+    double l = 0.5 * R;
+    double ad = (dim == 2) ? 10.0 / (7.0 * M_PI * l * l) : 1.0 / (M_PI * l * l * l);
+    double complex s = r / l;
+    if (creal(s) <= 1.0) return ad * (3.0 - 2.25 * s) / (l * l);
+    if (creal(s) < 2.0) {
+        double complex t = 2.0 - s;
+        return ad * 0.75 * t * t / (s * l * l);
+    }
+    return 0.0;
+}
+
+/* A X = B, complex, partial pivoting on the real parts; 1 if a pivot is 0 */
+static int orc_cgepp(int n, double complex* A, int nrhs, double complex* B)
+{
+    for (int c = 0; c < n; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < n; ++r)
+            if (fabs(creal(A[r * n + c])) > fabs(creal(A[piv * n + c]))) piv = r;
+        if (creal(A[piv * n + c]) == 0.0) return 1;
+        if (piv != c) {
+            for (int k = 0; k < n; ++k) { double complex t = A[c * n + k]; A[c * n + k] = A[piv * n + k]; A[piv * n + k] = t; }
+            for (int k = 0; k < nrhs; ++k) { double complex t = B[c * nrhs + k]; B[c * nrhs + k] = B[piv * nrhs + k]; B[piv * nrhs + k] = t; }
+        }
+        for (int r = c + 1; r < n; ++r) {
+            double complex f = A[r * n + c] / A[c * n + c];
+            for (int k = c; k < n; ++k) A[r * n + k] -= f * A[c * n + k];
+            for (int k = 0; k < nrhs; ++k) B[r * nrhs + k] -= f * B[c * nrhs + k];
+        }
+    }
+    for (int c = n - 1; c >= 0; --c)
+        for (int k = 0; k < nrhs; ++k) {
+            double complex s = B[c * nrhs + k];
+            for (int j = c + 1; j < n; ++j) s -= A[c * n + j] * B[j * nrhs + k];
+            B[c * nrhs + k] = s / A[c * n + c];
+        }
+    return 0;
+}
+
+/* The projected derivative vector D^ = [dz^, xx, yy, zz, xz, yz] of one field
+ * at particle i by the two-stage formula of Eq. sec_SPH2 (second-order
+ * gradient), in complex arithmetic.  The vertical projected coordinate of
+ * particle j is zc[j] when zc is given, else the real one plus dzk at j == kp.
+ * Returns 1 when a system is singular. */
+static int orc_c_row_dhat(const orc_ctx* c, const double complex* zc, int64_t kp, double complex dzk, int64_t i,
+                          const int32_t* nb, int64_t deg, const double* phi, double complex Dh[6])
+{
+    const int d = c->dim, m = c->m;
+    const int64_t n = c->n;
+    #define ZOF(j) (zc ? zc[j] : c->pos[(d - 1) * n + (j)] + ((j) == kp ? dzk : 0.0))
+    double complex* r = malloc((size_t)(deg > 0 ? deg : 1) * 3 * sizeof(double complex));
+    double complex* gt = malloc((size_t)(deg > 0 ? deg : 1) * 3 * sizeof(double complex));
+    double complex* q = malloc((size_t)(deg > 0 ? deg : 1) * 6 * sizeof(double complex));
+    double complex* F = malloc((size_t)(deg > 0 ? deg : 1) * sizeof(double complex));
+    double complex* G = malloc((size_t)(deg > 0 ? deg : 1) * sizeof(double complex));
+    int bad = !(r && gt && q && F && G);
+    if (!bad) {
+        double complex zi = ZOF(i);
+        /* offsets, -w'(r)/r, monomials */
+        double complex A[9] = {0}, L[9] = {0};
+        for (int64_t k = 0; k < deg; ++k) {
+            int64_t j = nb[k];
+            double complex d2 = 0.0;
+            for (int a = 0; a < d - 1; ++a) {
+                r[3 * k + a] = c->pos[a * n + j] - c->pos[a * n + i];
+                d2 += r[3 * k + a] * r[3 * k + a];
+            }
+            r[3 * k + d - 1] = ZOF(j) - zi;
+            d2 += r[3 * k + d - 1] * r[3 * k + d - 1];
+            F[k] = d2;
+            G[k] = orc_c_gfac(c->kernel, d, c->R, d2);
+            double complex* rq = r + 3 * k;
+            double complex* qq = q + 6 * k;
+            if (d == 2) { qq[0] = rq[0] * rq[0]; qq[1] = rq[1] * rq[1]; qq[2] = rq[0] * rq[1]; }
+            else {
+                qq[0] = rq[0] * rq[0]; qq[1] = rq[1] * rq[1]; qq[2] = rq[2] * rq[2];
+                qq[3] = rq[0] * rq[1]; qq[4] = rq[0] * rq[2]; qq[5] = rq[1] * rq[2];
+            }
+            /* A_i = sum_j V_j grad w_ij (x) r_ij, grad w_ij = G r_ij */
+            double V = c->vol[j];
+            for (int a = 0; a < d; ++a)
+                for (int b = 0; b < d; ++b) A[a * d + b] += V * G[k] * rq[a] * rq[b];
+        }
+        for (int a = 0; a < d; ++a) L[a * d + a] = 1.0;
+        bad = orc_cgepp(d, A, d, L);
+        /* corrected gradients L grad w, Q_i, F_ij, p_ij, M_i */
+        double complex Q[18] = {0}, M[36] = {0}, b[6] = {0}, g1[3] = {0};
+        if (!bad) {
+            for (int64_t k = 0; k < deg; ++k)
+                for (int a = 0; a < d; ++a) {
+                    double complex t = 0.0;
+                    for (int bb = 0; bb < d; ++bb) t += L[a * d + bb] * G[k] * r[3 * k + bb];
+                    gt[3 * k + a] = t;
+                }
+            for (int64_t k = 0; k < deg; ++k) {
+                double V = c->vol[nb[k]];
+                for (int mm = 0; mm < m; ++mm)
+                    for (int a = 0; a < d; ++a) Q[mm * d + a] += V * q[6 * k + mm] * gt[3 * k + a];
+                double pij = phi[nb[k]] - phi[i];
+                for (int a = 0; a < d; ++a) g1[a] += V * pij * gt[3 * k + a];
+            }
+            for (int64_t k = 0; k < deg; ++k) {
+                double complex rg = 0.0;
+                for (int a = 0; a < d; ++a) rg += r[3 * k + a] * gt[3 * k + a];
+                double complex d2 = F[k];
+                F[k] = rg / (d2 * d2);
+                double complex p[6];
+                for (int mm = 0; mm < m; ++mm) {
+                    double complex t = 0.0;
+                    for (int a = 0; a < d; ++a) t += Q[mm * d + a] * r[3 * k + a];
+                    p[mm] = q[6 * k + mm] - t;
+                }
+                double V = c->vol[nb[k]];
+                double complex rg1 = 0.0;
+                for (int a = 0; a < d; ++a) rg1 += r[3 * k + a] * g1[a];
+                double complex t = V * F[k] * ((phi[nb[k]] - phi[i]) - rg1);
+                for (int aa = 0; aa < m; ++aa) {
+                    b[aa] += t * q[6 * k + aa];
+                    for (int bb = 0; bb < m; ++bb) M[aa * m + bb] += V * F[k] * q[6 * k + aa] * p[bb];
+                }
+            }
+            bad = orc_cgepp(m, M, 1, b);
+        }
+        if (!bad) {
+            double complex D[6];
+            for (int mm = 0; mm < m; ++mm) D[mm] = 2.0 * b[mm];
+            double complex g2[3];
+            for (int a = 0; a < d; ++a) {
+                double complex t = 0.0;
+                for (int mm = 0; mm < m; ++mm) t += Q[mm * d + a] * D[mm];
+                g2[a] = g1[a] - 0.5 * t;
+            }
+            if (d == 2) {
+                Dh[0] = g2[1]; Dh[1] = D[0]; Dh[2] = 0.0; Dh[3] = D[1]; Dh[4] = 0.5 * D[2]; Dh[5] = 0.0;
+            } else {
+                Dh[0] = g2[2]; Dh[1] = D[0]; Dh[2] = D[1]; Dh[3] = D[2]; Dh[4] = 0.5 * D[4]; Dh[5] = 0.5 * D[5];
+            }
+        }
+    }
+    #undef ZOF
+    free(r); free(gt); free(q); free(F); free(G);
+    return bad ? 1 : 0;
+}
+
+/* d loss / d z^_k at sampled particles k, loss = sum_i (lap_i - g_i)^2 with
+ * lap_i = c_trans_i . D^_i, for a fixed mapping: by the complex step of z^_k
+ * alone, which changes the rows of k and of its neighbours.  u_i = 2 (lap_i -
+ * g_i) comes from the real evaluation.  With ct_dep = 0 c_trans is held at
+ * its value (only the SPH(2) derivatives move). */
+int orc_r2_dzhat(int dim, int64_t n, const double* pos, const double* vol, const double* phi, int kernel, double R,
+                 int map_kind, double Hhat, double H, double dmin, double eps, int nterms, const double* terms,
+                 const double* u, int ct_dep, int64_t nk, const int64_t* ks, const int64_t* row_ptr,
+                 const int32_t* col, double* out)
+{
+    orc_ctx c;
+    ctx_init(&c, dim, n, pos, vol, kernel, R, map_kind, Hhat, H, dmin, eps, nterms, terms, 2);
+    const double h = 1e-30;
+    int status = 0;
+    #pragma omp parallel for schedule(dynamic, 4) reduction(| : status)
+    for (int64_t s = 0; s < nk; ++s) {
+        int64_t k = ks ? ks[s] : s;
+        const double complex dz = h * _Complex_I;
+        double acc = 0.0;
+        for (int64_t e = row_ptr[k] - 1; e < row_ptr[k + 1]; ++e) {
+            int64_t i = e < row_ptr[k] ? k : col[e];   /* the row of k first, then its neighbours' */
+            double complex Dh[6];
+            if (orc_c_row_dhat(&c, NULL, k, dz, i, col + row_ptr[i], row_ptr[i + 1] - row_ptr[i], phi, Dh)) {
+                status = 1;
+                continue;
+            }
+            double x = pos[i], y = (dim == 3) ? pos[n + i] : 0.0, zh = pos[(dim - 1) * n + i];
+            double complex ct[6];
+            orc_c_map_ct(&c.map, dim, x, y, (ct_dep && i == k) ? zh + dz : zh, -1, 0.0, ct);
+            double complex lap = 0.0;
+            for (int q = 0; q < 6; ++q) lap += ct[q] * Dh[q];
+            acc += u[i] * cimag(lap) / h;
+        }
+        out[s] = acc;
+    }
+    return status ? -1 : 0;
+}
+
+/* Projected positions of physical points (x, [y], z): z^ = alpha (z + beta). */
+int orc_project(int dim, int64_t n, const double* phys, int map_kind, double Hhat, double H, double dmin, double eps,
+                int nterms, const double* terms, double* proj)
+{
+    orc_map mp;
+    mp.kind = map_kind; mp.Hhat = Hhat; mp.H = H; mp.dmin = dmin; mp.eps = eps;
+    mp.nterms = nterms; mp.terms = terms;
+    #pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        double x = phys[i], y = (dim == 3) ? phys[n + i] : 0.0, z = phys[(dim - 1) * n + i];
+        double ab[12];
+        orc_r_alpha_beta(&mp, dim, x, y, -1, 0.0, ab);
+        for (int a = 0; a < dim - 1; ++a) proj[a * n + i] = phys[a * n + i];
+        proj[(dim - 1) * n + i] = ab[0] * (z + ab[6]);
+    }
+    return 0;
+}
+
+/* d loss / d coef_t under reading R2, by the complex step of coef_t through
+ * the whole evaluation: every particle's projected height
+ * z^_j = alpha_c (z_j + beta_c) with the perturbed mapping, every row's D^ and
+ * c_trans, then the loss.  phys: physical positions (x, [y], z); the
+ * neighbour lists are those of the real projected positions. */
+int orc_r2_dtheta(int dim, int64_t n, const double* phys, const double* vol, const double* phi, const double* g,
+                  int kernel, double R, int map_kind, double Hhat, double H, double dmin, double eps, int nterms,
+                  const double* terms, int nt, const int32_t* tlist, const int64_t* row_ptr, const int32_t* col,
+                  double* dtheta)
+{
+    orc_map mp;
+    mp.kind = map_kind; mp.Hhat = Hhat; mp.H = H; mp.dmin = dmin; mp.eps = eps;
+    mp.nterms = nterms; mp.terms = terms;
+    const double h = 1e-30;
+    double* proj = malloc((size_t)(n > 0 ? n : 1) * dim * sizeof(double));
+    double complex* zc = malloc((size_t)(n > 0 ? n : 1) * sizeof(double complex));
+    double* part = malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+    if (!proj || !zc || !part) { free(proj); free(zc); free(part); return -1; }
+    orc_project(dim, n, phys, map_kind, Hhat, H, dmin, eps, nterms, terms, proj);
+    orc_ctx c;
+    ctx_init(&c, dim, n, proj, vol, kernel, R, map_kind, Hhat, H, dmin, eps, nterms, terms, 2);
+    int status = 0;
+    for (int tt = 0; tt < nt; ++tt) {
+        const int t = tlist[tt];
+        const double complex dc = h * _Complex_I;
+        #pragma omp parallel for schedule(static)
+        for (int64_t j = 0; j < n; ++j) {
+            double x = phys[j], y = (dim == 3) ? phys[n + j] : 0.0, z = phys[(dim - 1) * n + j];
+            double complex ab[12];
+            orc_c_alpha_beta(&mp, dim, x, y, t, dc, ab);
+            zc[j] = ab[0] * (z + ab[6]);
+        }
+        #pragma omp parallel for schedule(dynamic, 16) reduction(| : status)
+        for (int64_t i = 0; i < n; ++i) {
+            double complex Dh[6];
+            part[i] = 0.0;
+            if (orc_c_row_dhat(&c, zc, -1, 0.0, i, col + row_ptr[i], row_ptr[i + 1] - row_ptr[i], phi, Dh)) {
+                status = 1;
+                continue;
+            }
+            double x = phys[i], y = (dim == 3) ? phys[n + i] : 0.0;
+            double complex ct[6];
+            orc_c_map_ct(&mp, dim, x, y, zc[i], t, dc, ct);
+            double complex lap = 0.0;
+            for (int q = 0; q < 6; ++q) lap += ct[q] * Dh[q];
+            double complex e = lap - g[i];
+            part[i] = cimag(e * e) / h;
+        }
+        double sum = 0.0, comp = 0.0;   /* fixed order, Kahan */
+        for (int64_t i = 0; i < n; ++i) {
+            double yv = part[i] - comp, tv = sum + yv;
+            comp = (tv - sum) - yv;
+            sum = tv;
+        }
+        dtheta[tt] = sum;
+    }
+    free(proj); free(zc); free(part);
+    return status ? -1 : 0;
+}

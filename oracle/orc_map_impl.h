@@ -124,3 +124,25 @@ static void ORC_FN(map_coeffs)(const orc_map* mp, int dim, double x, double y, d
     hz[1][2] = hz[2][1] = ay;
     hz[2][2] = 0;
 }
+
+/* c_trans (Eq. lap_VCT) at a point whose projected height zh is itself of the
+ * scalar type, for complex-step derivatives in which both the bathymetry
+ * coefficient t_pert and z^ carry an imaginary part (physical positions held
+ * fixed, so z^ moves with the bottom).  Same statements as map_coeffs. */
+static void ORC_FN(map_ct)(const orc_map* mp, int dim, double x, double y, ORC_T zh, int t_pert, ORC_T dc,
+                           ORC_T ct[6])
+{
+    ORC_T ab[12];
+    ORC_FN(alpha_beta)(mp, dim, x, y, t_pert, dc, ab);
+    ORC_T a = ab[0], ax = ab[1], ay = ab[2], axx = ab[3], ayy = ab[5];
+    ORC_T bx = ab[7], by = ab[8], bxx = ab[9], byy = ab[11];
+    ORC_T zb = zh / a;                        /* z + beta */
+    ORC_T gx = ax * zb + a * bx;
+    ORC_T gy = ay * zb + a * by;
+    ct[0] = (axx + ayy) * zb + 2.0 * (ax * bx + ay * by) + a * (bxx + byy);
+    ct[1] = 1;
+    ct[2] = 1;
+    ct[3] = a * a + gx * gx + gy * gy;
+    ct[4] = 2.0 * gx;
+    ct[5] = 2.0 * gy;
+}
