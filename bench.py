@@ -385,6 +385,8 @@ def main():
 
     res["ppe"] = ppe_measure(args, w, vct, L, nl, pos_s, vol_s, sta, adj_mask, ms, perm, dev)
     res["jbar"] = jbar_measure(w, vct, L, nl, pos_s, cmap, perm, dev)
+    res["adjoint_r2"] = r2_measure(w, vct, L, dim, n, ncell, cell_start, chunk_off, chunk_start, chunk_info, row_ptr,
+                                   chunk_win, cap, col16, nnz, ws_nb, pos_s, vol_s, phi_s, g_s, cmap, dev)
 
     if not args.no_cpu_baseline:
         progress("CPU oracle on a sample")
@@ -443,6 +445,51 @@ def ppe_measure(args, w, vct, L, nl, pos_s, vol_s, sta, mask, ms, perm, dev):
             "ms_per_iteration": round(t * 1e3 / max(it, 1), 4),
             "matvec_avg_ms": round(matvec[1] / max(matvec[0], 1), 4), "matvecs": matvec[0],
             "kernels": {k: {"launches": c, "avg_ms": round(ms_ / c, 4)} for k, (c, ms_) in sorted(kt.items())}}
+
+
+def r2_measure(w, vct, L, dim, n, ncell, cell_start, chunk_off, chunk_start, chunk_info, row_ptr, chunk_win, cap,
+               col16, nnz, ws_nb, pos_s, vol_s, phi_s, g_s, cmap, dev, reps=3):
+    """The bathymetry adjoint with physical positions fixed (reading R2) on
+    the benchmark geometry (outside the timed steps): the int32 columns and the
+    transposed-entry map it reads are built first (untimed), then the FP64
+    state and apply of LAP + PGRAD + PHESS, then the timed adjoint calls."""
+    import torch
+    progress("R2 adjoint")
+    col = torch.empty(max(nnz, 8), dtype=torch.int32, device=dev)
+    col_t = torch.empty(max(nnz, 8), dtype=torch.int32, device=dev)
+    nl2 = vct.make_nlist(dim, n, ncell, w.lo, w.hi, w.R, cell_start, chunk_off, chunk_start, chunk_info, row_ptr,
+                         col, col16, chunk_cap=cap, col_t=col_t, chunk_win=chunk_win)
+    vct.vct_neighbors(nl2, pos_s, nnz, 1, ws_nb)
+    mask = vct.VCT_OUT_LAP | vct.VCT_OUT_PGRAD | vct.VCT_OUT_PHESS
+    stride = vct.vct_state_stride(dim, mask)
+    st = torch.empty((stride, n), dtype=torch.float64, device=dev)
+    flags = torch.empty(n, dtype=torch.uint8, device=dev)
+    ws_mom = torch.empty(L.vct_moments_workspace_size(dim, n), dtype=torch.uint8, device=dev)
+    vct.vct_moments(nl2, pos_s, vol_s, w.kernel, cmap, mask, st, None, flags, False, ws_mom)
+    del ws_mom
+    proj = torch.empty((1, n, vct.vct_n_out(dim, mask)), dtype=torch.float64, device=dev)
+    vct.vct_apply_ops(nl2, 1, phi_s[:1].contiguous(), pos_s, vol_s, w.kernel, st, mask, vct.VCT_FP64, proj)
+    u = (2.0 * (proj[0, :, 0] - g_s)).contiguous()
+    phi0 = phi_s[0].contiguous()
+    nt = cmap.nterms
+    dth = torch.empty(max(nt, 1), dtype=torch.float64, device=dev)
+    ws = torch.empty(L.vct_adjoint_r2_workspace_size(dim, n, nnz, nt), dtype=torch.uint8, device=dev)
+    vct.vct_apply_ops_adjoint_r2(nl2, pos_s, vol_s, w.kernel, st, mask, cmap, proj, phi0, u, dth, None, ws)
+    torch.cuda.synchronize()
+    vct.vct_timing_reset()
+    vct.vct_timing_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        vct.vct_apply_ops_adjoint_r2(nl2, pos_s, vol_s, w.kernel, st, mask, cmap, proj, phi0, u, dth, None, ws)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / reps
+    vct.vct_timing_enable(False)
+    kt = vct.vct_timing_read()
+    vct.vct_timing_reset()
+    return {"what": "d loss / d bathymetry coefficients with physical positions fixed (reading R2): per-entry "
+                    "position derivatives of the SPH(2) rows (two sweeps), transposed gather, dtheta reduction",
+            "ms": round(t * 1e3, 3),
+            "kernels": {k: {"launches": c // reps, "ms_per_call": round(ms_ / reps, 4)} for k, (c, ms_) in sorted(kt.items())}}
 
 
 def jbar_measure(w, vct, L, nl, pos_s, cmap, perm, dev, reps=3):

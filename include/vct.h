@@ -388,6 +388,44 @@ int vct_apply_ops_adjoint(const vct_nlist* nl, const double* pos_sorted, const d
                           const double* proj, const double* u, double* dphi, double* dtheta, void* ws,
                           size_t ws_bytes, void* stream);
 
+/* ---------------------------------------------------------------- bathymetry adjoint, reading R2 */
+
+/* Workspace of vct_apply_ops_adjoint_r2: nnz + 2 n doubles and the reduction
+ * partials. */
+size_t vct_adjoint_r2_workspace_size(int dim, int64_t n, int64_t nnz, int nterms);
+
+/* Sensitivity of loss = sum_i (lap_i - g_i)^2 to the bathymetry coefficients
+ * when the particles' PHYSICAL positions are held fixed, so that their
+ * projected heights z^_j = alpha (z_j + beta) move with the bottom (Sec. 2.1,
+ * Eq. VCT; vct_apply_ops_adjoint is the other reading, projected positions
+ * fixed).  Every row's SPH(2) derivatives then change through the offsets
+ * r^_ij, the correction matrix L_i and the moment matrix M_i (Sec. 3.1,
+ * Eq. sec_SPH2), and c_trans through z + beta = z^ / alpha:
+ *   dtheta_t = sum_i u_i (d c_trans_i / d coef_t)|_{z^} . D^_i
+ *            + sum_k (d loss / d z^_k) (d z^_k / d coef_t)|_{z},
+ *   d loss / d z^_k = sum_{i in S_k + k} u_i d lap_i / d z^_k,
+ * with the row derivatives by implicit differentiation of the SPH(2) system
+ * (each term a function of one offset, so the transposed form sums them).
+ * Field values, volumes and the target stay fixed; d loss / d phi does not
+ * change between the readings (vct_apply_ops_adjoint gives it).
+ *   state64   vct_moments state whose out_mask holds LAP, PGRAD and PHESS
+ *             (and not VCT_OPT_GRAD1: the system's own second-order gradient)
+ *   proj      [n][n_out] FP64 vct_apply_ops output of phi with that mask
+ *   phi [n], u [n] = 2 (lap - g)
+ *   dtheta    [map->nterms] or NULL;  dzhat [n] or NULL: d loss / d z^_k
+ * Needs nl->col and the transposed-entry map nl->col_t (vct_neighbors).
+ * Non-finite terms make the outputs they reach NaN.  Asynchronous.            */
+int vct_apply_ops_adjoint_r2(const vct_nlist* nl, const double* pos_sorted, const double* vol_sorted, int kernel,
+                             const double* state64, uint32_t out_mask, const vct_map* map /* host */,
+                             const double* proj, const double* phi, const double* u, double* dtheta, double* dzhat,
+                             void* ws, size_t ws_bytes, void* stream);
+
+/* Projected positions of physical points (Sec. 2.1, Eq. VCT): x^ = x,
+ * y^ = y, z^ = alpha (z + beta); phys and proj SoA [dim][n] (distinct
+ * buffers), any order.  Asynchronous.                                         */
+int vct_map_project(int dim, int64_t n, const double* phys, const vct_map* map /* host */, double* proj,
+                    void* stream);
+
 /* ---------------------------------------------------------------- pressure step (Sec. 3.3) */
 
 /* The pressure step of the projection method through the VCT (paper

@@ -17,6 +17,14 @@ Between forward and backward the function holds, per particle:
 Each mode runs the same kernels on the same inputs, so all three give the
 same bits.  The forward releases the geometry's own references to the state
 and to the moment workspace, so that only what the mode keeps stays alive.
+
+`VctLaplacianR2.apply(phi, theta, phys, vol, box, base_map)` is the same
+Laplacian with the particles' PHYSICAL positions held fixed: the forward
+projects them with the perturbed mapping (z^ = alpha (z + beta)), builds the
+geometry there and applies the operator; phi and the result are in the
+caller's particle order.  Its backward gives d/dphi (the same adjoint as
+above) and d/dtheta through the moving projected heights
+(vct_apply_ops_adjoint_r2).
 """
 from __future__ import annotations
 
@@ -92,3 +100,46 @@ def laplacian_loss(geom, phi, theta, base_map, target, recompute=True):
     """sum_i (lap_i - target_i)^2 on sorted particles, differentiable in phi and theta."""
     lap = VctLaplacian.apply(phi, theta, geom, base_map, recompute)
     return ((lap - target) ** 2).sum()
+
+
+# the Laplacian and the projected derivatives the position adjoint reads
+R2_MASK = vct.VCT_OUT_LAP | vct.VCT_OUT_PGRAD | vct.VCT_OUT_PHESS
+
+
+class VctLaplacianR2(torch.autograd.Function):
+    """phi: (n,) FP64 in the caller's order; theta: (4, 4); phys: (dim, n)
+    physical positions (device tensor); vol: (n,); box: (lo, hi, R, kernel)."""
+
+    @staticmethod
+    def forward(ctx, phi, theta, phys, vol, box, base_map):
+        lo, hi, R, kernel = box
+        spec = base_map.with_terms(perturbation_terms(theta.detach().cpu().numpy()))
+        cmap = vct.make_map(spec)
+        phys = phys.to(torch.float64).contiguous()
+        pos = torch.empty_like(phys)
+        vct.vct_map_project(phys.shape[0], phys.shape[1], phys, cmap, pos)
+        geom = vct.Geometry(pos, vol, lo, hi, R, kernel, device=phys.device, keep_col=True)
+        st = geom.moments(spec, R2_MASK)
+        if st < 0:
+            raise vct.VctError("vct_moments", st)
+        phis = geom.sorted_field(phi.detach())
+        proj = geom.apply(phis, vct.VCT_FP64)
+        ctx.geom, ctx.proj, ctx.phis = geom, proj, phis
+        ctx.nbase = len(base_map.terms)
+        ctx.theta_meta = (theta.dtype, theta.device)
+        return geom.unsort(proj[0, : geom.n, 0].contiguous())
+
+    @staticmethod
+    def backward(ctx, grad_lap):
+        g = ctx.geom
+        u = g.sorted_field(grad_lap.to(torch.float64))[0].contiguous()
+        dphi = None
+        if ctx.needs_input_grad[0]:
+            dphi_s, _ = g.adjoint(u, ctx.proj, want_dtheta=False)
+            dphi = g.unsort(dphi_s.contiguous())
+        dtheta = None
+        if ctx.needs_input_grad[1]:
+            dth, _ = g.adjoint_r2(ctx.phis[0].contiguous(), u, ctx.proj)
+            dtype, dev = ctx.theta_meta
+            dtheta = dth[ctx.nbase:].to(device=dev, dtype=dtype).reshape(4, 4)
+        return dphi, dtheta, None, None, None, None

@@ -26,6 +26,7 @@
 // contributions are reduced per work-group, then across work-groups, in a
 // fixed order.
 #include <mutex>
+#include <string.h>
 
 #include "common.h"
 #include "map_dev.h"
@@ -65,6 +66,11 @@ struct AdjArgs {
     double* wbuf;      // [nnz]: u_i W_ij at the transposed position
     double* rowsum;    // [n]:  u_i sum_j W_ij
     double* dphi;
+    // reading R2 (physical positions fixed)
+    const double* phi;   // [n] the field
+    int r_pg, r_ph;      // first rows of PGRAD and PHESS in proj
+    const double* gz;    // [n] d loss / d z^ through the SPH(2) derivatives (c_trans held)
+    double* dzhat;       // [n] or NULL: the total d loss / d z^ (c_trans's dependence added)
 };
 
 // Pass 1: u_i W_ij for every entry of row i, written transposed.  The first
@@ -546,6 +552,222 @@ __global__ __launch_bounds__(256) void k_adjoint_gather(int64_t n, const int64_t
     if (valid && lane == 0) dphi[k] = s - rowsum[k];
 }
 
+// ------------------------------------------------------------------ reading R2
+
+// With the physical positions fixed the projected heights move with the
+// bathymetry, and the rows of the Laplacian change through their offsets.
+// For row i write the SPH(2) system as K x = b with x = [R grad^ phi;
+// R^2 D / 2], b = sum_j V_j t_ij phi_ij, K = sum_j V_j t_ij m_ij^T, t_ij =
+// [c~ r~; F~ q~], m_ij = [r~; q~] and F~ = c~ (r~' L~ r~) / |r~|^4, L~ = A~^-1,
+// A~ = sum_j V_j c~ r~ r~^T (the formulation of the moment kernels).  Then
+// d(u_i lap_i) = u_i P_lap,i (db - dK x) (implicit differentiation), and
+// b - K x = sum_j V_j t_ij psi_ij with the Taylor residual
+// psi_ij = phi_ij - r~ . R grad^ phi - (1/2) r~' R^2 H^ r~.  With x held, the
+// offsets enter directly and through L~; dL~ = -L~ dA~ L~ turns the latter into
+// one more pair term.  So, with W_ij(r~) = V_j c~ [P_a . r~ + (r~' L~ r~)
+// / |r~|^4 P_s . q~] (u_i folded into P, as in lap_weight),
+//   G_i  = sum_j V_j c~ psi_ij (P_s . q~) / |r~|^4  r~ r~^T,   H_i = L~ G_i L~,
+//   Phi_ij(r~) = W_ij(r~) psi_ij(r~) - V_j c~(|r~|) r~' H_i r~,
+// d(u_i lap_i) / d z^_j = (1/R) d Phi_ij / d r~_z for j in S_i and minus their
+// sum for j = i (every term depends on the offset only).  k_r2_weights
+// evaluates G_i in a first sweep over the row and the derivatives in a
+// second, writing them at the transposed positions; k_adjoint_gather then
+// forms, for every particle k, sum_{i in S_k} d(u_i lap_i)/d z^_k minus the
+// row sum of k.
+
+// d c~ / dq of the kernel shape (kernel_shape)
+template <int KERNEL>
+__device__ __forceinline__ double kernel_shape_dq(double q) {
+    if (KERNEL == VCT_KERNEL_WENDLAND_C2) {
+        const double t = q < 1.0 ? 1.0 - q : 0.0;
+        return -3.0 * t * t;
+    } else {
+        const double s = 2.0 * q;
+        const double t = s < 2.0 ? 2.0 - s : 0.0;
+        const double outer = 2.0 * 0.75 * (-2.0 * t / s - t * t / (s * s));
+        return s <= 1.0 ? -4.5 : outer;
+    }
+}
+
+template <int D, int KERNEL>
+__global__ __launch_bounds__(kAThreads, 2) void k_r2_weights(AdjArgs A) {
+    using Dm = Dims<D>;
+    constexpr int nL = Dm::nL, nk = Dm::nk, m = Dm::m;
+    __shared__ double4 sd[kAWin];   // x, y, z, V
+    __shared__ double sf[kAWin];    // phi
+    __shared__ WindowT<D> w;
+    const uint32_t b = xcd_tile(blockIdx.x, gridDim.x);
+    if (b >= *A.nchunks) return;   // uniform over the work-group
+    const int64_t n = A.n;
+    const double R = 1.0 / A.invR;
+    const int64_t p0 = A.cstart[b], p1 = A.cstart[b + 1];
+    if (threadIdx.x < kWave) {
+        if (A.cwin) window_load<D>(A.cwin, b, w);
+        else chunk_window_wave<D>(A.g, A.cs, A.cinfo[b], w);
+    }
+    __syncthreads();
+    const int W = __builtin_amdgcn_readfirstlane(w.off[w.nr]);
+    const bool in_lds = W <= kAWin;
+    if (in_lds)
+        for (int t = threadIdx.x; t < W; t += kAThreads) {
+            const int64_t j = window_global<D>(w, t);
+            sd[t] = make_double4(A.pos[j], A.pos[n + j], D == 3 ? A.pos[2 * n + j] : 0.0, A.vol[j]);
+            sf[t] = A.phi[j];
+        }
+    __syncthreads();
+    auto fetch = [&](int t, double& ph) -> double4 {
+        if (in_lds) {
+            ph = sf[t];
+            return sd[t];
+        }
+        const int64_t j = window_global<D>(w, t);
+        ph = A.phi[j];
+        return make_double4(A.pos[j], A.pos[n + j], D == 3 ? A.pos[2 * n + j] : 0.0, A.vol[j]);
+    };
+    const int lane = threadIdx.x % kALanes;
+    const int64_t i = p0 + threadIdx.x / kALanes;
+    const bool valid = i < p1;
+    const int64_t ii = valid ? i : p0;
+    double xi[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) xi[a] = a < D ? A.pos[a * n + ii] : 0.0;
+    const double phi_i = A.phi[ii];
+    // L~ (pairs, off-diagonals doubled for the quadratic form), u_i P_lap
+    double L2[nL], Pl[nk];
+    const double ui = A.u[ii];
+#pragma unroll
+    for (int p = 0; p < nL; ++p) L2[p] = (pair_a<D>(p) == pair_b<D>(p) ? 1.0 : 2.0) * A.state[(int64_t)p * n + ii];
+#pragma unroll
+    for (int c = 0; c < nk; ++c) Pl[c] = ui * A.state[(int64_t)(nL + A.lap_row * nk + c) * n + ii];
+    // the solution x at i in units of R: R grad^ phi and the Taylor coefficients
+    // of (1/2) r~' R^2 H^ r~ on the pair monomials
+    double gt[D], hh[m];
+    {
+        const double* pr = A.proj + ii * A.nrows;
+#pragma unroll
+        for (int a = 0; a < D; ++a) gt[a] = R * pr[A.r_pg + a];
+#pragma unroll
+        for (int p = 0; p < m; ++p) hh[p] = R * R * pr[A.r_ph + p] * (pair_a<D>(p) == pair_b<D>(p) ? 0.5 : 1.0);
+    }
+    const int64_t rb = valid ? A.row_ptr[ii] : 0, re = valid ? A.row_ptr[ii + 1] : 0;
+
+    // the pair quantities shared by both sweeps
+    struct Pair {
+        double r[D], qv[m], y, y2, q, ct, sa, ss, rLr, psi, vol;
+    };
+    auto pair = [&](const double4& qr, double ph) {
+        Pair P;
+        P.r[0] = (qr.x - xi[0]) * A.invR;
+        P.r[1] = (qr.y - xi[1]) * A.invR;
+        if (D == 3) P.r[D - 1] = (qr.z - xi[2]) * A.invR;
+        double q2 = P.r[0] * P.r[0];
+#pragma unroll
+        for (int a = 1; a < D; ++a) q2 = fma(P.r[a], P.r[a], q2);
+#pragma unroll
+        for (int p = 0; p < m; ++p) P.qv[p] = P.r[pair_a<D>(p)] * P.r[pair_b<D>(p)];
+        P.y = vrsq(q2);
+        P.y2 = P.y * P.y;
+        P.q = q2 > 0.0 ? q2 * P.y : 0.0;
+        P.ct = kernel_shape<KERNEL>(P.q);
+        P.vol = qr.w;
+        double rLr = 0.0, sa = 0.0, ss = 0.0, quad = 0.0, lin = 0.0;
+#pragma unroll
+        for (int p = 0; p < nL; ++p) rLr = fma(L2[p], P.qv[p], rLr);
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            sa = fma(Pl[a], P.r[a], sa);
+            lin = fma(gt[a], P.r[a], lin);
+        }
+#pragma unroll
+        for (int p = 0; p < m; ++p) {
+            ss = fma(Pl[D + p], P.qv[p], ss);
+            quad = fma(hh[p], P.qv[p], quad);
+        }
+        P.rLr = rLr; P.sa = sa; P.ss = ss;
+        P.psi = (ph - phi_i) - lin - quad;
+        return P;
+    };
+
+    // sweep 1: G_i (pairs order)
+    double Gp[nL];
+#pragma unroll
+    for (int p = 0; p < nL; ++p) Gp[p] = 0.0;
+    for (int64_t e = rb + lane; e < re; e += kALanes) {
+        double ph;
+        const double4 qr = fetch(A.col16[e], ph);
+        const Pair P = pair(qr, ph);
+        const double kap = P.vol * P.ct * P.psi * P.ss * (P.y2 * P.y2);
+#pragma unroll
+        for (int p = 0; p < nL; ++p) Gp[p] = fma(kap, P.qv[p], Gp[p]);
+    }
+#pragma unroll
+    for (int p = 0; p < nL; ++p) Gp[p] = group_sum(Gp[p], kALanes);
+    // H_i = L~ G_i L~ (symmetric; L~ off-diagonals are L2 / 2)
+    double Lm[D][D], Gm[D][D], Hm[D][D];
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            const int p = sym_index<D>(a, c);
+            Lm[a][c] = a == c ? L2[p] : 0.5 * L2[p];
+            Gm[a][c] = Gp[p];
+        }
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            double t = 0.0;
+#pragma unroll
+            for (int e1 = 0; e1 < D; ++e1)
+#pragma unroll
+                for (int e2 = 0; e2 < D; ++e2) t = fma(Lm[a][e1], Gm[e1][e2] * Lm[e2][c], t);
+            Hm[a][c] = t;
+        }
+    // sweep 2: d Phi_ij / d r~_z, written at the transposed position
+    constexpr int Z = D - 1;
+    double rowsum = 0.0;
+    for (int64_t e = rb + lane; e < re; e += kALanes) {
+        double ph;
+        const double4 qr = fetch(A.col16[e], ph);
+        const Pair P = pair(qr, ph);
+        const double zc = P.r[Z];
+        const double y4 = P.y2 * P.y2;
+        const double dct = kernel_shape_dq<KERNEL>(P.q) * zc * P.y;   // d c~ / d r~_z
+        double Lr = 0.0, Hr = 0.0, Htr = 0.0, rHr = 0.0;              // (L~ r~)_z, (H r~)_z, (H^~ r~)_z, r~' H r~
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            Lr = fma(Lm[Z][a], P.r[a], Lr);
+            Hr = fma(Hm[Z][a], P.r[a], Hr);
+            double ha = 0.0;
+#pragma unroll
+            for (int c = 0; c < D; ++c) ha = fma(Hm[a][c], P.r[c], ha);
+            rHr = fma(P.r[a], ha, rHr);
+            // R^2 H^ from the Taylor coefficients: diagonal 2 hh, off-diagonal hh
+            const int p = sym_index<D>(Z, a);
+            Htr = fma(a == Z ? 2.0 * hh[p] : hh[p], P.r[a], Htr);
+        }
+        double dss = 0.0;   // d (P_s . q~) / d r~_z
+#pragma unroll
+        for (int p = 0; p < m; ++p) {
+            const int pa = pair_a<D>(p), pb = pair_b<D>(p);
+            const double dq = (pa == Z ? P.r[pb] : 0.0) + (pb == Z ? P.r[pa] : 0.0);
+            dss = fma(Pl[D + p], dq, dss);
+        }
+        const double F = P.rLr * y4;
+        const double dF = 2.0 * Lr * y4 - 4.0 * P.rLr * y4 * P.y2 * zc;
+        const double s1 = fma(F, P.ss, P.sa);
+        const double Wv = P.vol * P.ct * s1;
+        const double dW = P.vol * (dct * s1 + P.ct * (Pl[Z] + dF * P.ss + F * dss));
+        const double dpsi = -gt[Z] - Htr;
+        const double dZ = P.vol * (dct * rHr + 2.0 * P.ct * Hr);
+        const double t = (dW * P.psi + Wv * dpsi - dZ) * A.invR;
+        A.wbuf[A.col_t[e]] = t;
+        rowsum += t;
+    }
+    rowsum = group_sum(rowsum, kALanes);
+    if (valid && lane == 0) A.rowsum[ii] = rowsum;
+}
+
 constexpr int kRedThreads = 256;
 
 // dtheta, first level.  Per particle (one thread): the projected derivatives
@@ -557,7 +779,7 @@ constexpr int kRedThreads = 256;
 // one sum per factor pair (X_a, Y_b) that some term uses; otherwise term by
 // term.  Each sum is taken over a wave (fixed lane order), the waves' sums in
 // wave order: one partial per work-group and term.
-template <int D>
+template <int D, bool R2 = false>
 __global__ __launch_bounds__(kRedThreads) void k_dtheta_partials(AdjArgs A, MapParams mp,
                                                                   double* __restrict__ partials) {
     constexpr int kW = kRedThreads / kWave;
@@ -596,6 +818,21 @@ __global__ __launch_bounds__(kRedThreads) void k_dtheta_partials(AdjArgs A, MapP
 #pragma unroll
         for (int q = 0; q < 6; ++q)
             xv[q] = ui * (mc.c0.d[q] * gz + mc.c3.d[q] * Hzz + mc.c4.d[q] * Hxz + mc.c5.d[q] * Hyz);
+        if (R2) {
+            // reading R2: z^ = alpha (z + beta) moves with the bottom at fixed z.
+            // The total d loss / d z^ adds c_trans's own dependence on z^ (through
+            // z + beta = z^ / alpha) to the SPH(2) part, and every bottom quantity
+            // reaches it through d z^ / d h^(q) = alpha_q (z + beta) + alpha beta_q.
+            const double a = mc.alpha.v, zb = x[D - 1] / a, ia = 1.0 / a;
+            const double ax = mc.zxz.v, ay = mc.zyz.v;
+            const double dc0 = (mc.axx.v + mc.ayy.v) * ia;
+            const double dc3 = 2.0 * (mc.gx.v * ax + mc.gy.v * ay) * ia;
+            const double dc4 = 2.0 * ax * ia, dc5 = 2.0 * ay * ia;
+            const double gzt = A.gz[i] + ui * (dc0 * gz + dc3 * Hzz + dc4 * Hxz + dc5 * Hyz);
+            if (A.dzhat) A.dzhat[i] = gzt;
+#pragma unroll
+            for (int q = 0; q < 6; ++q) xv[q] += gzt * (mc.alpha.d[q] * zb + a * mc.beta.d[q]);
+        }
     }
     const int wv = threadIdx.x / kWave;
     const bool lead = threadIdx.x % kWave == 0;
@@ -688,6 +925,28 @@ static int launch_adjoint(AdjArgs a, int64_t cap, const MapParams& mp, double* d
         VCT_LAUNCH("k_dtheta_partials", (k_dtheta_partials<D>), dim3((unsigned)nred), dim3(kRedThreads), 0, s, a,
                    mp, partials);
         VCT_LAUNCH_CHECK();
+        VCT_LAUNCH("k_dtheta_final", k_dtheta_final, dim3((unsigned)mp.nterms), dim3(kRedThreads), 0, s, nred,
+                   mp.nterms, partials, dtheta);
+        VCT_LAUNCH_CHECK();
+    }
+    return VCT_OK;
+}
+
+template <int D, int KERNEL>
+static int launch_r2(AdjArgs a, int64_t cap, const MapParams& mp, double* gz, double* dtheta, double* partials,
+                     hipStream_t s) {
+    const int64_t n = a.n;
+    VCT_LAUNCH("k_r2_weights", (k_r2_weights<D, KERNEL>), dim3((unsigned)cap), dim3(kAThreads), 0, s, a);
+    VCT_LAUNCH_CHECK();
+    VCT_LAUNCH("k_adjoint_gather", k_adjoint_gather, dim3((unsigned)((n * kALanes + 255) / 256)), dim3(256), 0, s, n,
+               a.row_ptr, a.wbuf, a.rowsum, gz);
+    VCT_LAUNCH_CHECK();
+    a.gz = gz;
+    const int64_t nred = (n + kRedThreads - 1) / kRedThreads;
+    VCT_LAUNCH("k_dtheta_partials (R2)", (k_dtheta_partials<D, true>), dim3((unsigned)nred), dim3(kRedThreads), 0, s,
+               a, mp, partials);
+    VCT_LAUNCH_CHECK();
+    if (dtheta && mp.nterms > 0) {
         VCT_LAUNCH("k_dtheta_final", k_dtheta_final, dim3((unsigned)mp.nterms), dim3(kRedThreads), 0, s, nred,
                    mp.nterms, partials, dtheta);
         VCT_LAUNCH_CHECK();
@@ -798,6 +1057,83 @@ extern "C" int vct_apply_ops_adjoint(const vct_nlist* nl, const double* pos_sort
                                      size_t ws_bytes, void* stream) {
     return adjoint_run(nl, pos_sorted, vol_sorted, kernel, state64, out_mask, map, proj, u, dphi, dtheta, ws,
                        ws_bytes, false, stream);
+}
+
+// ------------------------------------------------------------------ reading R2 entry point
+
+extern "C" size_t vct_adjoint_r2_workspace_size(int dim, int64_t n, int64_t nnz, int nterms) {
+    if ((dim != 2 && dim != 3) || n < 0 || nnz < 0 || nterms < 0) return 0;
+    const int64_t nred = (n + kRedThreads - 1) / kRedThreads;
+    return aligned_sum({(size_t)(nred > 0 ? nred : 1) * (nterms > 0 ? nterms : 1) * 8,
+                        (size_t)(nnz > 0 ? nnz : 1) * sizeof(double), (size_t)(n > 0 ? n : 1) * sizeof(double),
+                        (size_t)(n > 0 ? n : 1) * sizeof(double)});
+}
+
+extern "C" int vct_apply_ops_adjoint_r2(const vct_nlist* nl, const double* pos_sorted, const double* vol_sorted,
+                                        int kernel, const double* state64, uint32_t out_mask, const vct_map* map,
+                                        const double* proj, const double* phi, const double* u, double* dtheta,
+                                        double* dzhat, void* ws, size_t ws_bytes, void* stream) {
+    Grid g;
+    int st = nlist_check(nl, g);
+    if (st) return st;
+    const int dim = nl->dim;
+    const int64_t n = nl->n;
+    const uint32_t need = VCT_OUT_LAP | VCT_OUT_PGRAD | VCT_OUT_PHESS;
+    if (!map || !mask_valid(out_mask) || (out_mask & need) != need || (out_mask & VCT_OPT_GRAD1) ||
+        (kernel != VCT_KERNEL_WENDLAND_C2 && kernel != VCT_KERNEL_CUBIC_SPLINE))
+        return VCT_E_ARG;
+    MapParams mp;
+    st = map_params_from(map, dim, mp);
+    if (st) return st;
+    hipStream_t s = as_stream(stream);
+    if (n == 0) {
+        if (dtheta && mp.nterms > 0) {
+            VCT_LAUNCH("k_zero_f64", k_zero_f64, dim3(1), dim3(64), 0, s, dtheta, (int64_t)mp.nterms);
+            VCT_LAUNCH_CHECK();
+        }
+        return VCT_OK;
+    }
+    if (!pos_sorted || !vol_sorted || !state64 || !proj || !phi || !u || !nl->col16 || !nl->col_t) return VCT_E_ARG;
+    if (!dtheta && !dzhat) return VCT_OK;
+    const int64_t nnz = nl->nnz;
+    if (nnz < 0) return VCT_E_ARG;
+    if (!ws || ws_bytes < vct_adjoint_r2_workspace_size(dim, n, nnz, mp.nterms)) return VCT_E_WORKSPACE;
+    Carver cv(ws, ws_bytes);
+    const int64_t nred = (n + kRedThreads - 1) / kRedThreads;
+    double* partials = cv.take<double>((size_t)nred * (mp.nterms > 0 ? mp.nterms : 1));
+    double* wbuf = cv.take<double>((size_t)(nnz > 0 ? nnz : 1));
+    double* rowsum = cv.take<double>((size_t)n);
+    double* gz = cv.take<double>((size_t)n);
+    const int64_t ncols = dim == 3 ? g.nc[0] * g.nc[1] : g.nc[0];
+    AdjArgs a;
+    memset(&a, 0, sizeof(a));
+    a.n = n; a.invR = 1.0 / nl->R; a.g = g; a.pos = pos_sorted; a.vol = vol_sorted; a.state = state64; a.u = u;
+    a.proj = proj; a.row_ptr = nl->row_ptr; a.col16 = nl->col16; a.col_t = nl->col_t; a.cs = nl->cell_start;
+    a.cstart = nl->chunk_start; a.cinfo = reinterpret_cast<const int4*>(nl->chunk_info);
+    a.cwin = nl->chunk_win;
+    a.nchunks = nl->chunk_off + ncols;
+    a.chunk_off = nl->chunk_off;
+    a.lap_row = group_row(dim, out_mask, VCT_OUT_LAP);
+    const int rg = group_row(dim, out_mask, VCT_OUT_PGRAD), rh = group_row(dim, out_mask, VCT_OUT_PHESS);
+    a.r_pg = rg;
+    a.r_ph = rh;
+    // PHESS component order: 3-D xx, yy, zz, xy, xz, yz; 2-D xx, zz, xz
+    a.r_gz = rg + dim - 1;
+    a.r_zz = dim == 3 ? rh + 2 : rh + 1;
+    a.r_xz = dim == 3 ? rh + 4 : rh + 2;
+    a.r_yz = dim == 3 ? rh + 5 : -1;
+    a.nrows = n_out_rows(dim, out_mask);
+    a.wbuf = wbuf; a.rowsum = rowsum; a.phi = phi; a.dzhat = dzhat;
+    const int64_t cap = ncols + n / kChunk + 1;
+    if (dim == 2)
+        st = (kernel == VCT_KERNEL_WENDLAND_C2)
+                 ? launch_r2<2, VCT_KERNEL_WENDLAND_C2>(a, cap, mp, gz, dtheta, partials, s)
+                 : launch_r2<2, VCT_KERNEL_CUBIC_SPLINE>(a, cap, mp, gz, dtheta, partials, s);
+    else
+        st = (kernel == VCT_KERNEL_WENDLAND_C2)
+                 ? launch_r2<3, VCT_KERNEL_WENDLAND_C2>(a, cap, mp, gz, dtheta, partials, s)
+                 : launch_r2<3, VCT_KERNEL_CUBIC_SPLINE>(a, cap, mp, gz, dtheta, partials, s);
+    return st;
 }
 
 // ------------------------------------------------------------------ allocation-free variant

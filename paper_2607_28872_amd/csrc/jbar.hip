@@ -500,6 +500,19 @@ __global__ __launch_bounds__(256) void k_map_alpha(int dim, int64_t n, const dou
     alpha[i] = map_coef<double>(mp, h, zh).alpha;
 }
 
+// projected positions of physical points: x^ = x, y^ = y, z^ = alpha (z + beta) (Eq. VCT)
+__global__ __launch_bounds__(256) void k_map_project(int dim, int64_t n, const double* __restrict__ phys, MapParams mp,
+                                                     double* __restrict__ proj) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double x = phys[i], y = dim == 3 ? phys[n + i] : 0.0, z = phys[(int64_t)(dim - 1) * n + i];
+    double h[6];
+    bottom6(mp, x, y, h);
+    const MapCoef<double> c = map_coef<double>(mp, h, 0.0);
+    for (int a = 0; a < dim - 1; ++a) proj[(int64_t)a * n + i] = phys[(int64_t)a * n + i];
+    proj[(int64_t)(dim - 1) * n + i] = c.alpha * (z + c.beta);
+}
+
 }  // namespace vct
 
 using namespace vct;
@@ -557,6 +570,19 @@ extern "C" int vct_map_alpha(int dim, int64_t n, const double* pos, const vct_ma
     if (!pos || !alpha) return VCT_E_ARG;
     VCT_LAUNCH("k_map_alpha", k_map_alpha, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, as_stream(stream), dim, n,
                pos, mp, alpha);
+    VCT_LAUNCH_CHECK();
+    return VCT_OK;
+}
+
+extern "C" int vct_map_project(int dim, int64_t n, const double* phys, const vct_map* map, double* proj, void* stream) {
+    if ((dim != 2 && dim != 3) || n < 0 || !map) return VCT_E_ARG;
+    MapParams mp;
+    const int st = map_params_from(map, dim, mp);
+    if (st) return st;
+    if (n == 0) return VCT_OK;
+    if (!phys || !proj || phys == proj) return VCT_E_ARG;
+    VCT_LAUNCH("k_map_project", k_map_project, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, as_stream(stream),
+               dim, n, phys, mp, proj);
     VCT_LAUNCH_CHECK();
     return VCT_OK;
 }

@@ -219,16 +219,17 @@ __device__ __forceinline__ double value(const Dual6& a) { return a.v; }
 //   second derivatives of z^ with respect to (x, y, z): zxx, zyy, zxy, zxz, zyz (zzz = 0)
 template <class T> struct MapCoef {
     T alpha, gx, gy, c0, c3, c4, c5, zxx, zyy, zxy, zxz, zyz;
+    T beta, axx, ayy;   // beta, d2 alpha / dx2, d2 alpha / dy2
 };
 
 // From h (and derivatives) and the projected height zh; z + beta = zh / alpha.
 template <class T>
 __device__ __forceinline__ MapCoef<T> map_coef(const MapParams& mp, const T h[6], double zh) {
     T a(1.0), ax(0.0), ay(0.0), axx(0.0), axy(0.0), ayy(0.0);
-    T bx(0.0), by(0.0), bxx(0.0), bxy(0.0), byy(0.0);
+    T bet(0.0), bx(0.0), by(0.0), bxx(0.0), bxy(0.0), byy(0.0);
     if (mp.kind == VCT_MAP_E || mp.kind == VCT_MAP_BFE) a = T(mp.Hhat / mp.H);
     if (mp.kind == VCT_MAP_BF || mp.kind == VCT_MAP_BFE) {
-        bx = -h[1]; by = -h[2]; bxx = -h[3]; bxy = -h[4]; byy = -h[5];
+        bet = -h[0]; bx = -h[1]; by = -h[2]; bxx = -h[3]; bxy = -h[4]; byy = -h[5];
     }
     if (mp.kind == VCT_MAP_SIGMA) {
         // depth D = H - h, smoothly limited from below: E = smax(D, dmin; eps)
@@ -254,11 +255,15 @@ __device__ __forceinline__ MapCoef<T> map_coef(const MapParams& mp, const T h[6]
         axx = a * iE * (T(2.0) * Ex * Ex * iE - Exx);
         axy = a * iE * (T(2.0) * Ex * Ey * iE - Exy);
         ayy = a * iE * (T(2.0) * Ey * Ey * iE - Eyy);
+        bet = E - T(mp.H);
         bx = Ex; by = Ey; bxx = Exx; bxy = Exy; byy = Eyy;
     }
     T zb = T(zh) / a;  // z + beta
     MapCoef<T> c;
     c.alpha = a;
+    c.beta = bet;
+    c.axx = axx;
+    c.ayy = ayy;
     c.gx = ax * zb + a * bx;
     c.gy = ay * zb + a * by;
     c.zxx = axx * zb + T(2.0) * ax * bx + a * bxx;

@@ -137,6 +137,13 @@ def lib():
                                                     _vp, _vp, _vp, _vp]
         L.vct_map_alpha.restype = C.c_int
         L.vct_map_alpha.argtypes = [C.c_int, _i64, _vp, C.POINTER(vct_map), _vp, _vp]
+        L.vct_adjoint_r2_workspace_size.restype = _sz
+        L.vct_adjoint_r2_workspace_size.argtypes = [C.c_int, _i64, _i64, C.c_int]
+        L.vct_apply_ops_adjoint_r2.restype = C.c_int
+        L.vct_apply_ops_adjoint_r2.argtypes = [_nlp, _vp, _vp, C.c_int, _vp, C.c_uint32, C.POINTER(vct_map), _vp,
+                                               _vp, _vp, _vp, _vp, _vp, _sz, _vp]
+        L.vct_map_project.restype = C.c_int
+        L.vct_map_project.argtypes = [C.c_int, _i64, _vp, C.POINTER(vct_map), _vp, _vp]
         L.vct_jbar_workspace_size.restype = _sz
         L.vct_jbar_workspace_size.argtypes = [_i64]
         L.vct_jbar_smooth.restype = C.c_int
@@ -349,6 +356,18 @@ def vct_grad_sum(nl, pos_sorted, vol_sorted, kernel, cmap, rho, rho0, p, mask, o
         _p(out), _stream(stream)))
 
 
+def vct_apply_ops_adjoint_r2(nl, pos_sorted, vol_sorted, kernel, state64, mask, cmap, proj, phi, u, dtheta, dzhat,
+                             ws, stream=None):
+    return _check("vct_apply_ops_adjoint_r2", lib().vct_apply_ops_adjoint_r2(
+        C.byref(nl), _p(pos_sorted), _p(vol_sorted), kernel, _p(state64), mask, C.byref(cmap), _p(proj), _p(phi),
+        _p(u), _p(dtheta), _p(dzhat), _p(ws), _nbytes(ws), _stream(stream)))
+
+
+def vct_map_project(dim, n, phys, cmap, proj, stream=None):
+    return _check("vct_map_project", lib().vct_map_project(int(dim), int(n), _p(phys), C.byref(cmap), _p(proj),
+                                                           _stream(stream)))
+
+
 def vct_map_alpha(dim, n, pos, cmap, alpha, stream=None):
     return _check("vct_map_alpha", lib().vct_map_alpha(int(dim), int(n), _p(pos), C.byref(cmap), _p(alpha),
                                                        _stream(stream)))
@@ -529,6 +548,19 @@ class Geometry:
         ws = _bytes(lib().vct_jbar_workspace_size(self.n), self.device)
         vct_jbar_smooth(self.nl, self.pos, J_sorted, jbar_sorted, cv, self.R if re is None else re, ws)
         return jbar_sorted
+
+    def adjoint_r2(self, phi_sorted, u_sorted, proj, want_dzhat=False):
+        """dtheta (and d loss / d z^, sorted) with physical positions fixed;
+        needs keep_col (the transposed-entry map) and a state whose mask holds
+        LAP, PGRAD and PHESS; proj is the FP64 apply output (1, n, n_out)."""
+        import torch
+        nt = self.cmap.nterms
+        dth = torch.empty(max(nt, 1), dtype=torch.float64, device=self.device)
+        dz = torch.empty(max(self.n, 1), dtype=torch.float64, device=self.device) if want_dzhat else None
+        ws = _bytes(lib().vct_adjoint_r2_workspace_size(self.dim, self.n, self.nnz, nt), self.device)
+        vct_apply_ops_adjoint_r2(self.nl, self.pos, self.vol, self.kernel, self.state64, self.mask, self.cmap, proj,
+                                 phi_sorted, u_sorted, dth, dz, ws)
+        return dth[:nt], (dz[: self.n] if dz is not None else None)
 
     def csr_original(self):
         """Neighbour lists in original indices, rows in original order, columns
