@@ -67,6 +67,9 @@ def parse():
     p.add_argument("--adjoint-state", choices=["resolve", "recompute"], default="resolve",
                    help="backward state: solved from the forward's kept moment sums, or sweeps + solve again")
     p.add_argument("--ppe-iters", type=int, default=100, help="BiCGSTAB iterations of the pressure-step measurement")
+    p.add_argument("--skip", default="",
+                   help="comma-separated side measurements to leave out (outside the timed steps): "
+                        "fd (adjoint central difference), ppe, jbar, r2 -- for profiler runs")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a 1 GiB device-to-device copy five times (reference for HBM byte counters)")
     return p.parse_args()
@@ -361,32 +364,17 @@ def main():
         "kernels": kernels,
     }
 
-    # The adjoint's d loss / d phi along a seeded direction v against the
-    # central difference of the loss with the FP64 Laplacian (outside the
-    # timed steps).  The loss is quadratic in phi and the difference of
-    # squares is formed as (a - b)(a + b - 2 g), so the central difference is
-    # exact up to rounding.
-    progress("adjoint against a central difference")
-    fd_step = 1e-6
-    v = torch.randn(n, generator=torch.Generator().manual_seed(17), dtype=torch.float64).to(dev)
-    lap_pm = []
-    for sgn in (1.0, -1.0):
-        ph = (phi_s[0] + sgn * fd_step * v).unsqueeze(0).contiguous()
-        o = torch.empty_like(proj)
-        vct.vct_apply_ops(nl, 1, ph, pos_s, vol_s, w.kernel, sta, adj_mask, vct.VCT_FP64, o)
-        lap_pm.append(o[0, :, 0])
-    a, b = lap_pm
-    fd = float(((a - b) * (a + b - 2.0 * g_s)).sum().item()) / (2.0 * fd_step)
-    adj = float(torch.dot(dphi, v).item())
-    res["adjoint_fd"] = {"quantity": "d loss / d phi along a seeded normal direction, loss = sum (lap f - g)^2",
-                         "step": fd_step, "central_difference": fd, "adjoint": adj,
-                         "rel_err": abs(fd - adj) / abs(adj)}
-    del lap_pm, a, b, o, ph, v
-
-    res["ppe"] = ppe_measure(args, w, vct, L, nl, pos_s, vol_s, sta, adj_mask, ms, perm, dev)
-    res["jbar"] = jbar_measure(w, vct, L, nl, pos_s, cmap, perm, dev)
-    res["adjoint_r2"] = r2_measure(w, vct, L, dim, n, ncell, cell_start, chunk_off, chunk_start, chunk_info, row_ptr,
-                                   chunk_win, cap, col16, nnz, ws_nb, pos_s, vol_s, phi_s, g_s, cmap, dev)
+    # side measurements, outside the timed steps
+    skip = set(x for x in args.skip.split(",") if x)
+    if "fd" not in skip:
+        res["adjoint_fd"] = adjoint_fd_check(vct, nl, w, phi_s, pos_s, vol_s, sta, adj_mask, proj, g_s, dphi, n, dev)
+    if "ppe" not in skip:
+        res["ppe"] = ppe_measure(args, w, vct, L, nl, pos_s, vol_s, sta, adj_mask, ms, perm, dev)
+    if "jbar" not in skip:
+        res["jbar"] = jbar_measure(w, vct, L, nl, pos_s, cmap, perm, dev)
+    if "r2" not in skip:
+        res["adjoint_r2"] = r2_measure(w, vct, L, dim, n, ncell, cell_start, chunk_off, chunk_start, chunk_info,
+                                       row_ptr, chunk_win, cap, col16, nnz, ws_nb, pos_s, vol_s, phi_s, g_s, cmap, dev)
 
     if not args.no_cpu_baseline:
         progress("CPU oracle on a sample")
@@ -403,6 +391,28 @@ def main():
             errs[nm] = operator_errors(out[:, idx, :].cpu().numpy(), rec, dim)
         res["error_vs_oracle"] = errs
     print(json.dumps(res), flush=True)
+
+
+def adjoint_fd_check(vct, nl, w, phi_s, pos_s, vol_s, sta, adj_mask, proj, g_s, dphi, n, dev):
+    """The adjoint's d loss / d phi along a seeded direction v against the
+    central difference of the loss with the FP64 Laplacian.  The loss is
+    quadratic in phi and the difference of squares is formed as
+    (a - b)(a + b - 2 g), so the central difference is exact up to rounding."""
+    import torch
+    progress("adjoint against a central difference")
+    fd_step = 1e-6
+    v = torch.randn(n, generator=torch.Generator().manual_seed(17), dtype=torch.float64).to(dev)
+    lap_pm = []
+    for sgn in (1.0, -1.0):
+        ph = (phi_s[0] + sgn * fd_step * v).unsqueeze(0).contiguous()
+        o = torch.empty_like(proj)
+        vct.vct_apply_ops(nl, 1, ph, pos_s, vol_s, w.kernel, sta, adj_mask, vct.VCT_FP64, o)
+        lap_pm.append(o[0, :, 0])
+    a, b = lap_pm
+    fd = float(((a - b) * (a + b - 2.0 * g_s)).sum().item()) / (2.0 * fd_step)
+    adj = float(torch.dot(dphi, v).item())
+    return {"quantity": "d loss / d phi along a seeded normal direction, loss = sum (lap f - g)^2",
+            "step": fd_step, "central_difference": fd, "adjoint": adj, "rel_err": abs(fd - adj) / abs(adj)}
 
 
 def ppe_measure(args, w, vct, L, nl, pos_s, vol_s, sta, mask, ms, perm, dev):
