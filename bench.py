@@ -579,10 +579,37 @@ def cpu_baseline(w, phis, mapspec, target_s):
         size1, t1, _, _ = timed(500, target_s / 3)
     finally:
         oracle.set_threads(cores)
+    # per stage, on every thread: the neighbour search and the SPH(2)
+    # operators at the sampled rows timed apart, and the adjoint d/dphi (each
+    # sampled particle needs the Laplacian weights of its neighbours' rows)
+    t0 = time.perf_counter()
+    csr = oracle.neighbors(w.pos, w.R, rows=rows)
+    t_nb = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oracle.sph2(w.pos, w.vol, phis, w.kernel, w.R, mapspec, rows=rows, csr=csr)
+    t_op = time.perf_counter() - t0
+    u = rng.standard_normal(w.n)
+    nadj = max(64, size // 200)
+    ks = np.sort(rng.choice(w.n, size=min(nadj, w.n), replace=False))
+    t0 = time.perf_counter()
+    # the rows the sampled entries read: the sampled particles and their neighbours
+    rp_k, col_k = oracle.neighbors(w.pos, w.R, rows=ks)
+    need = np.unique(np.concatenate([ks, col_k.astype(np.int64)]))
+    rp_n, col_n = oracle.neighbors(w.pos, w.R, rows=need)
+    row_ptr = np.zeros(w.n + 1, dtype=np.int64)
+    row_ptr[need + 1] = np.diff(rp_n)
+    row_ptr = np.cumsum(row_ptr)
+    oracle.adjoint_dphi(w.pos, w.vol, w.kernel, w.R, mapspec, u, ks=ks, csr=(row_ptr, col_n))
+    t_adj = time.perf_counter() - t0
     res = {"value": size * nf / t, "unit": "evals/s", "cores": cores, "kind": "oracle",
            "sample": f"{size} random particles of the {w.n}-particle set (neighbour grid over all particles "
                      f"+ SPH(2) at the sampled rows), {t:.1f} s",
            "single_core": {"value": size1 * nf / t1, "sample": f"{size1} particles, {t1:.1f} s"},
+           "per_stage": {
+               "neighbours": {"particles_per_s": size / t_nb, "sample": f"{size} rows, {t_nb:.2f} s"},
+               "moments_and_apply": {"particles_per_s": size * nf / t_op, "sample": f"{size} rows, {t_op:.2f} s"},
+               "adjoint_dphi": {"particles_per_s": len(ks) / t_adj,
+                                "sample": f"{len(ks)} particles (their neighbours' rows searched and re-evaluated), {t_adj:.2f} s"}},
            "cpu_model": cpu_model()}
     return res, rows, rec
 
