@@ -64,7 +64,8 @@ enum {
 };
 
 /* mapping kinds (paper Sec. 2.2) */
-enum { VCT_MAP_IDENTITY = 0, VCT_MAP_E = 1, VCT_MAP_BF = 2, VCT_MAP_BFE = 3, VCT_MAP_SIGMA = 4 };
+enum { VCT_MAP_IDENTITY = 0, VCT_MAP_E = 1, VCT_MAP_BF = 2, VCT_MAP_BFE = 3, VCT_MAP_SIGMA = 4,
+       VCT_MAP_PER_PARTICLE = 5 };
 
 /* one separable factor B(s) of a bathymetry term */
 enum { VCT_BASIS_ONE = 0, VCT_BASIS_LIN = 1, VCT_BASIS_COS = 2, VCT_BASIS_SIN = 3 };
@@ -134,6 +135,17 @@ typedef struct {
  *             limiter is a hard max whose second derivative is undefined at
  *             D = dmin).  Particles where alpha is not positive and finite are
  *             flagged VCT_FLAG_MAP by vct_moments.
+ *   PER_PARTICLE  alpha, beta and their first and second horizontal
+ *             derivatives given at every point (a measured or tabulated
+ *             bottom, any transformation of the form of Eq. VCT): `coef` is a
+ *             DEVICE array [12][coef_n] with rows alpha, alpha_x, alpha_y,
+ *             alpha_xx, alpha_xy, alpha_yy, beta, beta_x, beta_y, beta_xx,
+ *             beta_xy, beta_yy, in the order of the call's points (sorted
+ *             order for the calls on a neighbour list); coef_n must equal the
+ *             call's number of points and nterms must be 0 (no bathymetry
+ *             coefficients to differentiate: the adjoints give no dtheta, and
+ *             vct_apply_ops_adjoint_r2 returns VCT_E_ARG).  In 2-D the y
+ *             rows are ignored.  Read by the device during the call.
  * `terms` is a HOST pointer to nterms (<= VCT_MAX_TERMS) entries; it is read
  * during the call only.                                                        */
 typedef struct {
@@ -141,6 +153,8 @@ typedef struct {
     int32_t nterms;
     double Hhat, H, dmin, eps;
     const vct_term* terms;
+    const double* coef;     /* PER_PARTICLE only, else NULL */
+    int64_t coef_n;
 } vct_map;
 
 /* ---------------------------------------------------------------- queries */

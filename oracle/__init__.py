@@ -77,6 +77,8 @@ def lib():
         L.orc_sph2.argtypes = [C.c_int, C.c_int64, dp, dp, C.c_int, dp, C.c_int, C.c_double,
                                C.c_int, C.c_double, C.c_double, C.c_double, C.c_double, C.c_int, dp,
                                C.c_int, C.c_int64, ip64, ip64, ip32, dp, u8p]
+        L.orc_set_per_particle.restype = None
+        L.orc_set_per_particle.argtypes = [dp, C.c_int64]
         L.orc_jbar_smooth.restype = C.c_int
         L.orc_jbar_smooth.argtypes = [C.c_int, C.c_int64, dp, dp, dp, C.c_double, C.c_double, ip64, ip64, ip32]
         L.orc_r2_dzhat.restype = C.c_int
@@ -145,7 +147,21 @@ def _f64(a):
     return np.ascontiguousarray(a, dtype=np.float64)
 
 
+_PP_KEEP = None   # the per-particle table the library points at
+
+
 def _map_args(ms):
+    """The mapping as C arguments; a per-particle table (kind 5, ms.pp of
+    shape (12, n) in the particles' order) is handed to the library first."""
+    global _PP_KEEP
+    if int(ms.kind) == 5:
+        _PP_KEEP = _f64(ms.pp)
+        if _PP_KEEP.ndim != 2 or _PP_KEEP.shape[0] != 12:
+            raise ValueError("per-particle map: pp must be (12, n)")
+        lib().orc_set_per_particle(_p(_PP_KEEP), _PP_KEEP.shape[1])
+    else:
+        _PP_KEEP = None
+        lib().orc_set_per_particle(None, 0)
     terms = _f64(ms.as_array())
     return (int(ms.kind), float(ms.Hhat), float(ms.H), float(ms.dmin), float(ms.eps),
             int(terms.shape[0]), terms)

@@ -66,6 +66,18 @@ static void orc_basis(int kind, double f, double s, double b[3])
     }
 }
 
+/* per-particle mapping table: [12][n] alpha, alpha_x, alpha_y, alpha_xx,
+ * alpha_xy, alpha_yy, beta, beta_x, beta_y, beta_xx, beta_xy, beta_yy of
+ * every point, for maps of kind ORC_MAP_PER_PARTICLE (set before the calls) */
+static const double* g_orc_pp = NULL;
+static int64_t g_orc_pp_n = 0;
+
+void orc_set_per_particle(const double* pp, int64_t n)
+{
+    g_orc_pp = pp;
+    g_orc_pp_n = pp ? n : 0;
+}
+
 /* real instantiation of the mapping coefficients */
 #define ORC_T double
 #define ORC_SQRT sqrt
@@ -476,7 +488,7 @@ static int orc_physical_record(const orc_ctx* c, int64_t i, const double gh[3], 
     const int64_t n = c->n;
     double x = c->pos[i], y = (d == 3) ? c->pos[n + i] : 0.0, zh = c->pos[(d - 1) * n + i];
     double Jm[3][3], ct[6], hz[3][3];
-    orc_r_map_coeffs(&c->map, d, x, y, zh, -1, 0.0, Jm, ct, hz);
+    orc_r_map_coeffs(&c->map, d, x, y, zh, i, -1, 0.0, Jm, ct, hz);
     /* the transformation needs alpha > 0 (Sec. 2.1); Jm[2][2] is alpha */
     if (!(Jm[2][2] > 0.0) || !isfinite(Jm[2][2] + Jm[0][2] + Jm[1][2] + ct[0] + hz[0][1])) return ORC_F_MAP;
     double Dhat[6] = {gh[2], Hh[0][0], Hh[1][1], Hh[2][2], Hh[0][2], Hh[1][2]};
@@ -679,7 +691,7 @@ int orc_dtheta(int dim, int64_t n, const double* pos, int map_kind, double Hhat,
         for (int64_t i = 0; i < n; ++i) {
             double x = pos[i], y = (dim == 3) ? pos[n + i] : 0.0, zh = pos[(dim - 1) * n + i];
             double complex Jm[3][3], ct[6], hz[3][3];
-            orc_c_map_coeffs(&mp, dim, x, y, zh, t, hstep * _Complex_I, Jm, ct, hz);
+            orc_c_map_coeffs(&mp, dim, x, y, zh, i, t, hstep * _Complex_I, Jm, ct, hz);
             double v = 0.0;
             for (int k = 0; k < 6; ++k) v += cimag(ct[k]) / hstep * Dhat[6 * i + k];
             double yv = u[i] * v - comp;
@@ -706,14 +718,14 @@ int orc_map_eval(int dim, int64_t np, const double* x, const double* y, const do
         double* o = out + 24 * p;
         if (t < 0) {
             double Jm[3][3], ct[6], hz[3][3];
-            orc_r_map_coeffs(&mp, dim, x[p], y ? y[p] : 0.0, zh[p], -1, 0.0, Jm, ct, hz);
+            orc_r_map_coeffs(&mp, dim, x[p], y ? y[p] : 0.0, zh[p], p, -1, 0.0, Jm, ct, hz);
             for (int a = 0; a < 9; ++a) o[a] = Jm[a / 3][a % 3];
             for (int a = 0; a < 6; ++a) o[9 + a] = ct[a];
             for (int a = 0; a < 9; ++a) o[15 + a] = hz[a / 3][a % 3];
         } else {
             const double hstep = 1e-30;
             double complex Jm[3][3], ct[6], hz[3][3];
-            orc_c_map_coeffs(&mp, dim, x[p], y ? y[p] : 0.0, zh[p], t, hstep * _Complex_I, Jm, ct, hz);
+            orc_c_map_coeffs(&mp, dim, x[p], y ? y[p] : 0.0, zh[p], p, t, hstep * _Complex_I, Jm, ct, hz);
             for (int a = 0; a < 9; ++a) o[a] = cimag(Jm[a / 3][a % 3]) / hstep;
             for (int a = 0; a < 6; ++a) o[9 + a] = cimag(ct[a]) / hstep;
             for (int a = 0; a < 9; ++a) o[15 + a] = cimag(hz[a / 3][a % 3]) / hstep;
@@ -730,7 +742,7 @@ int orc_alpha_beta(int dim, int64_t np, const double* x, const double* y, int ma
     mp.kind = map_kind; mp.Hhat = Hhat; mp.H = H; mp.dmin = dmin; mp.eps = eps;
     mp.nterms = nterms; mp.terms = terms;
     for (int64_t p = 0; p < np; ++p)
-        orc_r_alpha_beta(&mp, dim, x[p], y ? y[p] : 0.0, -1, 0.0, out + 12 * p);
+        orc_r_alpha_beta(&mp, dim, x[p], y ? y[p] : 0.0, p, -1, 0.0, out + 12 * p);
     return 0;
 }
 
@@ -816,7 +828,7 @@ int orc_lap_weights(int dim, int64_t n, const double* pos, const double* vol, in
             double Jm[3][3], ct[6], hz[3][3];
             if (!fl) {
                 double x = c.pos[i], y = (d == 3) ? c.pos[n + i] : 0.0, zh = c.pos[(d - 1) * n + i];
-                orc_r_map_coeffs(&c.map, d, x, y, zh, -1, 0.0, Jm, ct, hz);
+                orc_r_map_coeffs(&c.map, d, x, y, zh, i, -1, 0.0, Jm, ct, hz);
                 if (!(Jm[2][2] > 0.0) || !isfinite(Jm[2][2] + Jm[0][2] + Jm[1][2] + ct[0] + hz[0][1])) fl |= ORC_F_MAP;
             }
             for (int64_t j = 0; j < deg; ++j) {
@@ -879,7 +891,7 @@ static int orc_first_order_geometry(const orc_ctx* c, int64_t i, const int32_t* 
     if (orc_gepp(c->m, M, 1, b, ORC_PIVOT_TOL)) return ORC_F_SINGULAR_M;
     double ct[6], hz[3][3];
     double x = c->pos[i], y = (c->dim == 3) ? c->pos[c->n + i] : 0.0, zh = c->pos[(c->dim - 1) * c->n + i];
-    orc_r_map_coeffs(&c->map, c->dim, x, y, zh, -1, 0.0, Jm, ct, hz);
+    orc_r_map_coeffs(&c->map, c->dim, x, y, zh, i, -1, 0.0, Jm, ct, hz);
     if (!(Jm[2][2] > 0.0) || !isfinite(Jm[2][2] + Jm[0][2] + Jm[1][2] + ct[0] + hz[0][1])) return ORC_F_MAP;
     return 0;
 }
@@ -1228,7 +1240,7 @@ int orc_grad_sum(int dim, int64_t n, const double* pos, const double* vol, const
         double gh[3] = {rhoi * t[0], dim == 3 ? rhoi * t[1] : 0.0, rhoi * t[dim - 1]};
         double x = c.pos[i], y = (dim == 3) ? c.pos[n + i] : 0.0, zh = c.pos[(dim - 1) * n + i];
         double Jm[3][3], ct[6], hz[3][3];
-        orc_r_map_coeffs(&c.map, dim, x, y, zh, -1, 0.0, Jm, ct, hz);
+        orc_r_map_coeffs(&c.map, dim, x, y, zh, i, -1, 0.0, Jm, ct, hz);
         if (!(Jm[2][2] > 0.0) || !isfinite(Jm[2][2] + Jm[0][2] + Jm[1][2])) fl |= ORC_F_MAP;
         double* o = out + (size_t)r * 6;
         for (int I = 0; I < 3; ++I) {
@@ -1482,7 +1494,7 @@ int orc_r2_dzhat(int dim, int64_t n, const double* pos, const double* vol, const
             }
             double x = pos[i], y = (dim == 3) ? pos[n + i] : 0.0, zh = pos[(dim - 1) * n + i];
             double complex ct[6];
-            orc_c_map_ct(&c.map, dim, x, y, (ct_dep && i == k) ? zh + dz : zh, -1, 0.0, ct);
+            orc_c_map_ct(&c.map, dim, x, y, (ct_dep && i == k) ? zh + dz : zh, i, -1, 0.0, ct);
             double complex lap = 0.0;
             for (int q = 0; q < 6; ++q) lap += ct[q] * Dh[q];
             acc += u[i] * cimag(lap) / h;
@@ -1503,7 +1515,7 @@ int orc_project(int dim, int64_t n, const double* phys, int map_kind, double Hha
     for (int64_t i = 0; i < n; ++i) {
         double x = phys[i], y = (dim == 3) ? phys[n + i] : 0.0, z = phys[(dim - 1) * n + i];
         double ab[12];
-        orc_r_alpha_beta(&mp, dim, x, y, -1, 0.0, ab);
+        orc_r_alpha_beta(&mp, dim, x, y, i, -1, 0.0, ab);
         for (int a = 0; a < dim - 1; ++a) proj[a * n + i] = phys[a * n + i];
         proj[(dim - 1) * n + i] = ab[0] * (z + ab[6]);
     }
@@ -1539,7 +1551,7 @@ int orc_r2_dtheta(int dim, int64_t n, const double* phys, const double* vol, con
         for (int64_t j = 0; j < n; ++j) {
             double x = phys[j], y = (dim == 3) ? phys[n + j] : 0.0, z = phys[(dim - 1) * n + j];
             double complex ab[12];
-            orc_c_alpha_beta(&mp, dim, x, y, t, dc, ab);
+            orc_c_alpha_beta(&mp, dim, x, y, j, t, dc, ab);
             zc[j] = ab[0] * (z + ab[6]);
         }
         #pragma omp parallel for schedule(dynamic, 16) reduction(| : status)
@@ -1552,7 +1564,7 @@ int orc_r2_dtheta(int dim, int64_t n, const double* phys, const double* vol, con
             }
             double x = phys[i], y = (dim == 3) ? phys[n + i] : 0.0;
             double complex ct[6];
-            orc_c_map_ct(&mp, dim, x, y, zc[i], t, dc, ct);
+            orc_c_map_ct(&mp, dim, x, y, zc[i], i, t, dc, ct);
             double complex lap = 0.0;
             for (int q = 0; q < 6; ++q) lap += ct[q] * Dh[q];
             double complex e = lap - g[i];

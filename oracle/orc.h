@@ -5,7 +5,8 @@
 #include <stdint.h>
 
 enum { ORC_B_ONE = 0, ORC_B_LIN = 1, ORC_B_COS = 2, ORC_B_SIN = 3 };
-enum { ORC_MAP_IDENTITY = 0, ORC_MAP_E = 1, ORC_MAP_BF = 2, ORC_MAP_BFE = 3, ORC_MAP_SIGMA = 4 };
+enum { ORC_MAP_IDENTITY = 0, ORC_MAP_E = 1, ORC_MAP_BF = 2, ORC_MAP_BFE = 3, ORC_MAP_SIGMA = 4,
+       ORC_MAP_PER_PARTICLE = 5 };
 enum { ORC_K_WENDLAND = 0, ORC_K_SPLINE = 1 };
 
 /* per-particle flag bits */

@@ -14,6 +14,8 @@
  *   BF-SPH   : alpha = 1,                beta = -h
  *   BFE-SPH  : alpha = Hhat / H,         beta = -h
  *   sigma-SPH: alpha = Hhat / (H - h),   beta = -h
+ *   per-particle: alpha, beta and their derivatives given at every point
+ *              (any transformation of the form of Eq. VCT)
  * For sigma-SPH the depth D = H - h is limited from below (the paper asks for
  * a constant alpha outside the applicable range without giving the range); the
  * reading used here replaces D by the smooth maximum
@@ -48,12 +50,19 @@ static void ORC_FN(bottom)(const double* terms, int nterms, int dim, double x, d
 /* alpha, beta and their derivatives:
  *   ab[0..5]  = alpha, alpha_x, alpha_y, alpha_xx, alpha_xy, alpha_yy
  *   ab[6..11] = beta,  beta_x,  beta_y,  beta_xx,  beta_xy,  beta_yy      */
-static void ORC_FN(alpha_beta)(const orc_map* mp, int dim, double x, double y, int t_pert,
+static void ORC_FN(alpha_beta)(const orc_map* mp, int dim, double x, double y, int64_t idx, int t_pert,
                                ORC_T dc, ORC_T ab[12])
 {
     for (int k = 0; k < 12; ++k) ab[k] = 0;
     ab[0] = 1;
     if (mp->kind == ORC_MAP_IDENTITY) return;
+    if (mp->kind == ORC_MAP_PER_PARTICLE) {
+        /* given at every point (point idx of the table orc_set_per_particle set) */
+        for (int k = 0; k < 12; ++k)
+            ab[k] = (g_orc_pp && idx >= 0 && idx < g_orc_pp_n) ? g_orc_pp[k * g_orc_pp_n + idx] : NAN;
+        if (dim == 2) { ab[2] = 0; ab[4] = 0; ab[5] = 0; ab[8] = 0; ab[10] = 0; ab[11] = 0; }
+        return;
+    }
     if (mp->kind == ORC_MAP_E) { ab[0] = mp->Hhat / mp->H; return; }
     ORC_T h[6];
     ORC_FN(bottom)(mp->terms, mp->nterms, dim, x, y, t_pert, dc, h);
@@ -97,12 +106,12 @@ static void ORC_FN(alpha_beta)(const orc_map* mp, int dim, double x, double y, i
  *   hz[3][3]  second derivatives of z^ with respect to physical (x, y, z)
  * z + beta is recovered from the projected height as zh / alpha.  In 2-D the
  * vertical plane (x, z) is used: y = 0 and every y-derivative vanishes.    */
-static void ORC_FN(map_coeffs)(const orc_map* mp, int dim, double x, double y, double zh,
+static void ORC_FN(map_coeffs)(const orc_map* mp, int dim, double x, double y, double zh, int64_t idx,
                                int t_pert, ORC_T dc,
                                ORC_T Jm[3][3], ORC_T ct[6], ORC_T hz[3][3])
 {
     ORC_T ab[12];
-    ORC_FN(alpha_beta)(mp, dim, x, y, t_pert, dc, ab);
+    ORC_FN(alpha_beta)(mp, dim, x, y, idx, t_pert, dc, ab);
     ORC_T a = ab[0], ax = ab[1], ay = ab[2], axx = ab[3], axy = ab[4], ayy = ab[5];
     ORC_T bx = ab[7], by = ab[8], bxx = ab[9], bxy = ab[10], byy = ab[11];
     ORC_T zb = zh / a;                        /* z + beta */
@@ -129,11 +138,11 @@ static void ORC_FN(map_coeffs)(const orc_map* mp, int dim, double x, double y, d
  * scalar type, for complex-step derivatives in which both the bathymetry
  * coefficient t_pert and z^ carry an imaginary part (physical positions held
  * fixed, so z^ moves with the bottom).  Same statements as map_coeffs. */
-static void ORC_FN(map_ct)(const orc_map* mp, int dim, double x, double y, ORC_T zh, int t_pert, ORC_T dc,
-                           ORC_T ct[6])
+static void ORC_FN(map_ct)(const orc_map* mp, int dim, double x, double y, ORC_T zh, int64_t idx, int t_pert,
+                           ORC_T dc, ORC_T ct[6])
 {
     ORC_T ab[12];
-    ORC_FN(alpha_beta)(mp, dim, x, y, t_pert, dc, ab);
+    ORC_FN(alpha_beta)(mp, dim, x, y, idx, t_pert, dc, ab);
     ORC_T a = ab[0], ax = ab[1], ay = ab[2], axx = ab[3], ayy = ab[5];
     ORC_T bx = ab[7], by = ab[8], bxx = ab[9], byy = ab[11];
     ORC_T zb = zh / a;                        /* z + beta */

@@ -19,7 +19,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libvct.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 SOURCES = ["api.hip", "cells.hip", "moments.hip", "apply.hip", "adjoint.hip", "ppe.hip", "isph.hip", "jbar.hip"]
-HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+ROCM = "/opt/rocm"
+HIPCC = os.environ.get("HIPCC", os.path.join(ROCM, "bin", "hipcc"))
 ARCH = "gfx950"
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno-unused-function",
@@ -58,7 +59,8 @@ def build(verbose: bool = False, extra=None, sanitize_host: bool = False, out=No
     with ThreadPoolExecutor(max_workers=min(len(SOURCES), os.cpu_count() or 4)) as ex:
         objs = list(ex.map(compile_one, SOURCES))
     tmp = lib_out + ".tmp"
-    cmd = [HIPCC, "-shared", f"--offload-arch={ARCH}", *(HOST_SAN if sanitize_host else []), *objs, "-o", tmp]
+    cmd = [HIPCC, "-shared", f"--offload-arch={ARCH}", *(HOST_SAN if sanitize_host else []), *objs, "-o", tmp,
+           "-L", os.path.join(ROCM, "lib"), "-lrocprofiler-sdk-roctx", f"-Wl,-rpath,{os.path.join(ROCM, 'lib')}"]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

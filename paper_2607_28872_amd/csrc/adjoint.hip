@@ -994,7 +994,7 @@ static int adjoint_run(const vct_nlist* nl, const double* pos_sorted, const doub
         (kernel != VCT_KERNEL_WENDLAND_C2 && kernel != VCT_KERNEL_CUBIC_SPLINE))
         return VCT_E_ARG;
     MapParams mp;
-    st = map_params_from(map, dim, mp);
+    st = map_params_from(map, dim, n, mp);
     if (st) return st;
     hipStream_t s = as_stream(stream);
     if (n == 0) {
@@ -1055,6 +1055,7 @@ extern "C" int vct_apply_ops_adjoint(const vct_nlist* nl, const double* pos_sort
                                      int kernel, const double* state64, uint32_t out_mask, const vct_map* map,
                                      const double* proj, const double* u, double* dphi, double* dtheta, void* ws,
                                      size_t ws_bytes, void* stream) {
+    VCT_API_RANGE("vct_apply_ops_adjoint");
     return adjoint_run(nl, pos_sorted, vol_sorted, kernel, state64, out_mask, map, proj, u, dphi, dtheta, ws,
                        ws_bytes, false, stream);
 }
@@ -1073,6 +1074,7 @@ extern "C" int vct_apply_ops_adjoint_r2(const vct_nlist* nl, const double* pos_s
                                         int kernel, const double* state64, uint32_t out_mask, const vct_map* map,
                                         const double* proj, const double* phi, const double* u, double* dtheta,
                                         double* dzhat, void* ws, size_t ws_bytes, void* stream) {
+    VCT_API_RANGE("vct_apply_ops_adjoint_r2");
     Grid g;
     int st = nlist_check(nl, g);
     if (st) return st;
@@ -1083,8 +1085,9 @@ extern "C" int vct_apply_ops_adjoint_r2(const vct_nlist* nl, const double* pos_s
         (kernel != VCT_KERNEL_WENDLAND_C2 && kernel != VCT_KERNEL_CUBIC_SPLINE))
         return VCT_E_ARG;
     MapParams mp;
-    st = map_params_from(map, dim, mp);
+    st = map_params_from(map, dim, n, mp);
     if (st) return st;
+    if (mp.kind == VCT_MAP_PER_PARTICLE) return VCT_E_ARG;   // the heights move with the bottom terms
     hipStream_t s = as_stream(stream);
     if (n == 0) {
         if (dtheta && mp.nterms > 0) {
@@ -1170,6 +1173,7 @@ extern "C" int vct_apply_ops_adjoint_noalloc(const vct_nlist* nl, const double* 
                                              int kernel, const double* state64, uint32_t out_mask, const vct_map* map,
                                              const double* proj, const double* u, double* dphi, double* dtheta,
                                              void* stream) {
+    VCT_API_RANGE("vct_apply_ops_adjoint_noalloc");
     if (!nl || (nl->dim != 2 && nl->dim != 3) || nl->n < 0 || !map || map->nterms < 0 ||
         map->nterms > VCT_MAX_TERMS)
         return VCT_E_ARG;

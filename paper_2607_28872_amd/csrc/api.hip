@@ -61,11 +61,17 @@ static void build_separable(MapParams& p) {
     p.sep = 1;
 }
 
-int map_params_from(const vct_map* m, int dim, MapParams& p) {
+int map_params_from(const vct_map* m, int dim, int64_t n, MapParams& p) {
     memset(&p, 0, sizeof(p));
     if (!m) return VCT_E_ARG;
-    if (m->kind < VCT_MAP_IDENTITY || m->kind > VCT_MAP_SIGMA) return VCT_E_ARG;
+    if (m->kind < VCT_MAP_IDENTITY || m->kind > VCT_MAP_PER_PARTICLE) return VCT_E_ARG;
     if (m->nterms < 0 || m->nterms > VCT_MAX_TERMS || (m->nterms > 0 && !m->terms)) return VCT_E_ARG;
+    if (m->kind == VCT_MAP_PER_PARTICLE) {
+        // the table replaces the bottom terms; it must cover every point of the call
+        if (m->nterms != 0 || m->coef_n != n || (n > 0 && !m->coef)) return VCT_E_ARG;
+        p.pp = m->coef;
+        p.pp_n = m->coef_n;
+    }
     p.kind = m->kind;
     p.nterms = m->nterms;
     p.dim = dim;

@@ -604,6 +604,7 @@ using namespace vct;
 extern "C" int vct_apply_ops(const vct_nlist* nl, int nf, const double* phi_sorted, const double* pos_sorted,
                              const double* vol_sorted, int kernel, const void* state, uint32_t out_mask,
                              int precision, double* out, void* stream) {
+    VCT_API_RANGE("vct_apply_ops");
     Grid g;
     int st = nlist_check(nl, g);
     if (st) return st;

@@ -546,6 +546,7 @@ extern "C" size_t vct_build_cells_workspace_size(int dim, int64_t n, int64_t nce
 extern "C" int vct_build_cells(int dim, int64_t n, const double* pos, const double* lo, const double* hi,
                                double R, int32_t* perm, double* pos_sorted, int64_t* cell_start,
                                int64_t ncell, void* ws, size_t ws_bytes, void* stream) {
+    VCT_API_RANGE("vct_build_cells");
     if ((dim != 2 && dim != 3) || n < 0 || n > INT32_MAX || !lo || !hi || !(R > 0.0) || !isfinite(R))
         return VCT_E_ARG;
     Grid g;
@@ -589,6 +590,7 @@ extern "C" int vct_build_cells(int dim, int64_t n, const double* pos, const doub
 
 extern "C" int vct_gather_sorted(int64_t n, int ncomp, const int32_t* perm, const double* src, double* dst,
                                  void* stream) {
+    VCT_API_RANGE("vct_gather_sorted");
     if (n < 0 || ncomp < 1 || n > INT32_MAX) return VCT_E_ARG;
     if (n == 0) return VCT_OK;
     if (!perm || !src || !dst || src == dst) return VCT_E_ARG;
@@ -600,6 +602,7 @@ extern "C" int vct_gather_sorted(int64_t n, int ncomp, const int32_t* perm, cons
 
 extern "C" int vct_scatter_sorted(int64_t n, int ncomp, const int32_t* perm, const double* src, double* dst,
                                   void* stream) {
+    VCT_API_RANGE("vct_scatter_sorted");
     if (n < 0 || ncomp < 1 || n > INT32_MAX) return VCT_E_ARG;
     if (n == 0) return VCT_OK;
     if (!perm || !src || !dst || src == dst) return VCT_E_ARG;
@@ -736,6 +739,7 @@ static int launch_compact(const vct_nlist* nl, const Grid& g, const uint16_t* st
 
 extern "C" int vct_neighbors(vct_nlist* nl, const double* pos_sorted, int64_t col_cap, int64_t* nnz_out,
                              int reuse_row_ptr, void* ws, size_t ws_bytes, void* stream) {
+    VCT_API_RANGE("vct_neighbors");
     Grid g;
     int st = nlist_check(nl, g);
     if (st) return st;

@@ -3,6 +3,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 #include <stdint.h>
 #include <math.h>
 
@@ -49,6 +50,18 @@ struct LaunchTimer {
         if (rec >= 0) timing_end(rec, s);
     }
 };
+
+// A roctx range around every C-ABI entry point, named after it, so that a
+// profiler run with marker tracing (rocprofv3 --marker-trace) shows the
+// library's calls on the host timeline around the kernels they launch.  When
+// no tool is attached the two calls return at once.
+struct ApiRange {
+    explicit ApiRange(const char* name) { roctxRangePushA(name); }
+    ~ApiRange() { roctxRangePop(); }
+    ApiRange(const ApiRange&) = delete;
+    ApiRange& operator=(const ApiRange&) = delete;
+};
+#define VCT_API_RANGE(NAME) ::vct::ApiRange _vct_api_range(NAME)
 
 #define VCT_LAUNCH(NAME, KERNEL, GRID, BLOCK, SHM, STREAM, ...)            \
     do {                                                                  \

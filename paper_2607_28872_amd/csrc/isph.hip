@@ -111,9 +111,7 @@ __global__ __launch_bounds__(kZThreads, 4) void k_ops0(ZeroArgs A, MapParams mp)
     }
     const int64_t rb = valid ? A.row_ptr[ii] : 0, re = valid ? A.row_ptr[ii + 1] : 0;
     // the mapping at the particle (lane 0 writes)
-    double h[6];
-    bottom6(mp, xi[0], D == 3 ? xi[1] : 0.0, h);
-    const MapCoef<double> mc = map_coef<double>(mp, h, xi[D - 1]);
+    const MapCoef<double> mc = map_coef_at(mp, ii, xi[0], D == 3 ? xi[1] : 0.0, xi[D - 1]);
     const bool map_ok = mc.alpha > 0.0 && isfinite(mc.alpha + mc.gx + mc.gy + mc.c0 + mc.zxy);
     const double nanv = __builtin_nan("");
     for (int f = 0; f < A.nf; ++f) {
@@ -241,9 +239,7 @@ __global__ __launch_bounds__(kZThreads, 4) void k_grad_sum(ZeroArgs A, MapParams
     for (int a = 0; a < D; ++a) acc[a] = group_sum(acc[a], kZLanes);
     bad = group_sum(bad, kZLanes);
     if (!valid || lane != 0) return;
-    double h[6];
-    bottom6(mp, xi[0], D == 3 ? xi[1] : 0.0, h);
-    const MapCoef<double> mc = map_coef<double>(mp, h, xi[D - 1]);
+    const MapCoef<double> mc = map_coef_at(mp, ii, xi[0], D == 3 ? xi[1] : 0.0, xi[D - 1]);
     const bool map_ok = mc.alpha > 0.0 && isfinite(mc.alpha + mc.gx + mc.gy) && bad == 0.0;
     const double nanv = __builtin_nan("");
     double pg[D], ph[Dims<D>::m];
@@ -262,7 +258,7 @@ static int zero_common(const vct_nlist* nl, Grid& g, const double* pos_sorted, c
     if (st) return st;
     if (!map || !mask || (mask & ~allowed) || (kernel != VCT_KERNEL_WENDLAND_C2 && kernel != VCT_KERNEL_CUBIC_SPLINE))
         return VCT_E_ARG;
-    st = map_params_from(map, nl->dim, mp);
+    st = map_params_from(map, nl->dim, nl->n, mp);
     if (st) return st;
     const int64_t n = nl->n;
     if (n > 0 && (!pos_sorted || !vol_sorted || !nl->col16)) return VCT_E_ARG;
@@ -289,6 +285,7 @@ using namespace vct;
 extern "C" int vct_apply_ops0(const vct_nlist* nl, int nf, const double* phi_sorted, const double* pos_sorted,
                               const double* vol_sorted, int kernel, const vct_map* map, uint32_t out_mask, double* out,
                               void* stream) {
+    VCT_API_RANGE("vct_apply_ops0");
     Grid g;
     ZeroArgs a;
     MapParams mp;
@@ -318,6 +315,7 @@ extern "C" int vct_apply_ops0(const vct_nlist* nl, int nf, const double* phi_sor
 extern "C" int vct_grad_sum(const vct_nlist* nl, const double* pos_sorted, const double* vol_sorted, int kernel,
                             const vct_map* map, const double* rho, double rho0, const double* p, uint32_t out_mask,
                             double* out, void* stream) {
+    VCT_API_RANGE("vct_grad_sum");
     Grid g;
     ZeroArgs a;
     MapParams mp;

@@ -495,9 +495,7 @@ __global__ __launch_bounds__(256) void k_map_alpha(int dim, int64_t n, const dou
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const double x = pos[i], y = dim == 3 ? pos[n + i] : 0.0, zh = pos[(int64_t)(dim - 1) * n + i];
-    double h[6];
-    bottom6(mp, x, y, h);
-    alpha[i] = map_coef<double>(mp, h, zh).alpha;
+    alpha[i] = map_coef_at(mp, i, x, y, zh).alpha;
 }
 
 // projected positions of physical points: x^ = x, y^ = y, z^ = alpha (z + beta) (Eq. VCT)
@@ -506,9 +504,7 @@ __global__ __launch_bounds__(256) void k_map_project(int dim, int64_t n, const d
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const double x = phys[i], y = dim == 3 ? phys[n + i] : 0.0, z = phys[(int64_t)(dim - 1) * n + i];
-    double h[6];
-    bottom6(mp, x, y, h);
-    const MapCoef<double> c = map_coef<double>(mp, h, 0.0);
+    const MapCoef<double> c = map_coef_at(mp, i, x, y, 0.0);
     for (int a = 0; a < dim - 1; ++a) proj[(int64_t)a * n + i] = phys[(int64_t)a * n + i];
     proj[(int64_t)(dim - 1) * n + i] = c.alpha * (z + c.beta);
 }
@@ -524,6 +520,7 @@ extern "C" size_t vct_jbar_workspace_size(int64_t n) {
 
 extern "C" int vct_jbar_smooth(const vct_nlist* nl, const double* pos_sorted, const double* J, double* jbar, double cv,
                                double re, void* ws, size_t ws_bytes, void* stream) {
+    VCT_API_RANGE("vct_jbar_smooth");
     Grid g;
     int st = nlist_check(nl, g);
     if (st) return st;
@@ -562,9 +559,10 @@ extern "C" int vct_jbar_smooth(const vct_nlist* nl, const double* pos_sorted, co
 }
 
 extern "C" int vct_map_alpha(int dim, int64_t n, const double* pos, const vct_map* map, double* alpha, void* stream) {
+    VCT_API_RANGE("vct_map_alpha");
     if ((dim != 2 && dim != 3) || n < 0 || !map) return VCT_E_ARG;
     MapParams mp;
-    const int st = map_params_from(map, dim, mp);
+    const int st = map_params_from(map, dim, n, mp);
     if (st) return st;
     if (n == 0) return VCT_OK;
     if (!pos || !alpha) return VCT_E_ARG;
@@ -575,9 +573,10 @@ extern "C" int vct_map_alpha(int dim, int64_t n, const double* pos, const vct_ma
 }
 
 extern "C" int vct_map_project(int dim, int64_t n, const double* phys, const vct_map* map, double* proj, void* stream) {
+    VCT_API_RANGE("vct_map_project");
     if ((dim != 2 && dim != 3) || n < 0 || !map) return VCT_E_ARG;
     MapParams mp;
-    const int st = map_params_from(map, dim, mp);
+    const int st = map_params_from(map, dim, n, mp);
     if (st) return st;
     if (n == 0) return VCT_OK;
     if (!phys || !proj || phys == proj) return VCT_E_ARG;

@@ -36,9 +36,15 @@ struct MapParams {
     double qx[kMapFq], qy[kMapFq];
     double cm[kMapFn][kMapFn];
     int32_t term_a[VCT_MAX_TERMS], term_b[VCT_MAX_TERMS];   // factors (X_a, Y_b) of every term
+    // VCT_MAP_PER_PARTICLE: alpha, beta and their derivatives of every point,
+    // [12][pp_n] (order of vct_map.coef)
+    const double* pp;
+    int64_t pp_n;
 };
 
-int map_params_from(const vct_map* m, int dim, MapParams& p);  // host, returns status
+// host, returns status; n = the number of points of the call (checked
+// against the per-particle coefficient count)
+int map_params_from(const vct_map* m, int dim, int64_t n, MapParams& p);
 
 // B(s), B'(s), B''(s) of one separable factor
 __device__ __forceinline__ void basis3(int kind, double f, double s, double b[3]) {
@@ -222,6 +228,10 @@ template <class T> struct MapCoef {
     T beta, axx, ayy;   // beta, d2 alpha / dx2, d2 alpha / dy2
 };
 
+template <class T>
+__device__ __forceinline__ MapCoef<T> map_coef_ab(T a, T ax, T ay, T axx, T axy, T ayy, T bet, T bx, T by, T bxx,
+                                                  T bxy, T byy, double zh);
+
 // From h (and derivatives) and the projected height zh; z + beta = zh / alpha.
 template <class T>
 __device__ __forceinline__ MapCoef<T> map_coef(const MapParams& mp, const T h[6], double zh) {
@@ -258,6 +268,14 @@ __device__ __forceinline__ MapCoef<T> map_coef(const MapParams& mp, const T h[6]
         bet = E - T(mp.H);
         bx = Ex; by = Ey; bxx = Exx; bxy = Exy; byy = Eyy;
     }
+    return map_coef_ab<T>(a, ax, ay, axx, axy, ayy, bet, bx, by, bxx, bxy, byy, zh);
+}
+
+// The coefficients from alpha, beta and their derivatives at the point
+// (Eqs. jacobi, lap_VCT and the second derivatives of z^).
+template <class T>
+__device__ __forceinline__ MapCoef<T> map_coef_ab(T a, T ax, T ay, T axx, T axy, T ayy, T bet, T bx, T by, T bxx,
+                                                  T bxy, T byy, double zh) {
     T zb = T(zh) / a;  // z + beta
     MapCoef<T> c;
     c.alpha = a;
@@ -276,6 +294,22 @@ __device__ __forceinline__ MapCoef<T> map_coef(const MapParams& mp, const T h[6]
     c.c4 = T(2.0) * c.gx;
     c.c5 = T(2.0) * c.gy;
     return c;
+}
+
+// The coefficients at point i of a call, at (x, y, zh): from the bottom
+// terms, or read from the per-particle table (2-D: the y derivatives are 0).
+__device__ __forceinline__ MapCoef<double> map_coef_at(const MapParams& mp, int64_t i, double x, double y, double zh) {
+    if (mp.kind == VCT_MAP_PER_PARTICLE) {
+        const double* c = mp.pp;
+        const int64_t n = mp.pp_n;
+        const bool d3 = mp.dim == 3;
+        return map_coef_ab<double>(c[i], c[n + i], d3 ? c[2 * n + i] : 0.0, c[3 * n + i], d3 ? c[4 * n + i] : 0.0,
+                                   d3 ? c[5 * n + i] : 0.0, c[6 * n + i], c[7 * n + i], d3 ? c[8 * n + i] : 0.0,
+                                   c[9 * n + i], d3 ? c[10 * n + i] : 0.0, d3 ? c[11 * n + i] : 0.0, zh);
+    }
+    double h[6];
+    bottom6(mp, x, y, h);
+    return map_coef<double>(mp, h, zh);
 }
 
 // Physical (and projected) outputs from a projected gradient pg and projected

@@ -474,9 +474,7 @@ __global__ __launch_bounds__(128, VCT_SOLVE_WAVES) void k_moment_solve(int64_t n
 
     // VCT coefficients at the particle
     const double x = pos[i], y = (D == 3) ? pos[n + i] : 0.0, zh = pos[(int64_t)(D - 1) * n + i];
-    double h[6];
-    bottom6(mp, x, y, h);
-    const MapCoef<double> mc = map_coef<double>(mp, h, zh);
+    const MapCoef<double> mc = map_coef_at(mp, i, x, y, zh);
     // Sec. 2.1 requires alpha > 0 (a dry sigma column without the limiter
     // gives alpha <= 0 or infinite); such a particle is flagged
     if (!(mc.alpha > 0.0) || !isfinite(mc.alpha + mc.gx + mc.gy + mc.c0 + mc.zxy)) fl |= VCT_FLAG_MAP;
@@ -592,6 +590,7 @@ __global__ void k_zero_u64(unsigned long long* p) { *p = 0ull; }
 extern "C" int vct_moments(const vct_nlist* nl, const double* pos_sorted, const double* vol_sorted, int kernel,
                            const vct_map* map, uint32_t out_mask, double* state64, float* state32, uint8_t* flags,
                            int64_t* n_flagged, void* ws, size_t ws_bytes, void* stream) {
+    VCT_API_RANGE("vct_moments");
     Grid g;
     int st = nlist_check(nl, g);
     if (st) return st;
@@ -600,7 +599,7 @@ extern "C" int vct_moments(const vct_nlist* nl, const double* pos_sorted, const 
     if (!map || !mask_valid(out_mask) || (kernel != VCT_KERNEL_WENDLAND_C2 && kernel != VCT_KERNEL_CUBIC_SPLINE))
         return VCT_E_ARG;
     MapParams mp;
-    st = map_params_from(map, dim, mp);
+    st = map_params_from(map, dim, n, mp);
     if (st) return st;
     if (n > 0 && (!pos_sorted || !vol_sorted || !nl->col16 || (!state64 && !state32))) return VCT_E_ARG;
     if (!ws || ws_bytes < vct_moments_workspace_size(dim, n)) return VCT_E_WORKSPACE;
@@ -642,6 +641,7 @@ extern "C" int vct_moments(const vct_nlist* nl, const double* pos_sorted, const 
 extern "C" int vct_moments_resolve(const vct_nlist* nl, const double* pos_sorted, const vct_map* map,
                                    uint32_t out_mask, double* state64, float* state32, uint8_t* flags,
                                    int64_t* n_flagged, void* ws, size_t ws_bytes, void* stream) {
+    VCT_API_RANGE("vct_moments_resolve");
     Grid g;
     int st = nlist_check(nl, g);
     if (st) return st;
@@ -649,7 +649,7 @@ extern "C" int vct_moments_resolve(const vct_nlist* nl, const double* pos_sorted
     const int64_t n = nl->n;
     if (!map || !mask_valid(out_mask)) return VCT_E_ARG;
     MapParams mp;
-    st = map_params_from(map, dim, mp);
+    st = map_params_from(map, dim, n, mp);
     if (st) return st;
     if (n > 0 && (!pos_sorted || (!state64 && !state32))) return VCT_E_ARG;
     if (!ws || ws_bytes < vct_moments_workspace_size(dim, n)) return VCT_E_WORKSPACE;

@@ -187,9 +187,7 @@ __global__ __launch_bounds__(kQThreads, 4) void k_ppe_first(PpeArgs A, MapParams
         G[c][2] = g[D - 1];
     }
     // the Jacobian column of z^ at the particle: J = [[1,0,gx],[0,1,gy],[0,0,alpha]]
-    double h[6];
-    bottom6(mp, xi[0], D == 3 ? xi[1] : 0.0, h);
-    const MapCoef<double> mc = map_coef<double>(mp, h, xi[D - 1]);
+    const MapCoef<double> mc = map_coef_at(mp, ii, xi[0], D == 3 ? xi[1] : 0.0, xi[D - 1]);
     const double nanv = __builtin_nan("");
     if (MODE == 0) {
         // physical divergence: sum_I (J grad^ v_I)_I; component I along physical axis I
@@ -511,13 +509,14 @@ extern "C" int vct_ppe_rhs(const vct_nlist* nl, const double* pos_sorted, const 
                            const double* state64, uint32_t out_mask, const vct_map* map, const double* vstar,
                            double rho, double dt, double gamma, const double* jr, const uint8_t* dirichlet,
                            const double* pbc, double* rhs, double* div, double* dens, void* stream) {
+    VCT_API_RANGE("vct_ppe_rhs");
     Grid g;
     PpeArgs a;
     int st = ppe_common(nl, g, pos_sorted, vol_sorted, kernel, state64, out_mask, a);
     if (st) return st;
     if (!map || !(dt > 0.0) || !isfinite(rho) || !isfinite(gamma)) return VCT_E_ARG;
     MapParams mp;
-    st = map_params_from(map, nl->dim, mp);
+    st = map_params_from(map, nl->dim, nl->n, mp);
     if (st) return st;
     if (nl->n == 0) return VCT_OK;
     if (!vstar || !rhs) return VCT_E_ARG;
@@ -529,13 +528,14 @@ extern "C" int vct_ppe_rhs(const vct_nlist* nl, const double* pos_sorted, const 
 extern "C" int vct_ppe_correct(const vct_nlist* nl, const double* pos_sorted, const double* vol_sorted, int kernel,
                                const double* state64, uint32_t out_mask, const vct_map* map, const double* p,
                                const double* vstar, double rho, double dt, double* vout, void* stream) {
+    VCT_API_RANGE("vct_ppe_correct");
     Grid g;
     PpeArgs a;
     int st = ppe_common(nl, g, pos_sorted, vol_sorted, kernel, state64, out_mask, a);
     if (st) return st;
     if (!map || !isfinite(dt) || !(rho != 0.0) || !isfinite(rho)) return VCT_E_ARG;
     MapParams mp;
-    st = map_params_from(map, nl->dim, mp);
+    st = map_params_from(map, nl->dim, nl->n, mp);
     if (st) return st;
     if (nl->n == 0) return VCT_OK;
     if (!p || !vstar || !vout) return VCT_E_ARG;
@@ -554,6 +554,7 @@ extern "C" int vct_ppe_solve(const vct_nlist* nl, const double* pos_sorted, cons
                              const double* state64, uint32_t out_mask, const uint8_t* dirichlet, const double* rhs,
                              double* p, double tol, int max_iter, int* iters, double* relres, void* ws,
                              size_t ws_bytes, void* stream) {
+    VCT_API_RANGE("vct_ppe_solve");
     Grid g;
     PpeArgs a;
     int st = ppe_common(nl, g, pos_sorted, vol_sorted, kernel, state64, out_mask, a);

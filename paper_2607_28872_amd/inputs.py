@@ -34,9 +34,9 @@ import numpy as np
 B_ONE, B_LIN, B_COS, B_SIN = 0, 1, 2, 3
 
 # mapping kinds (paper Sec. 2.2)
-MAP_IDENTITY, MAP_E, MAP_BF, MAP_BFE, MAP_SIGMA = 0, 1, 2, 3, 4
+MAP_IDENTITY, MAP_E, MAP_BF, MAP_BFE, MAP_SIGMA, MAP_PER_PARTICLE = 0, 1, 2, 3, 4, 5
 MAP_NAMES = {MAP_IDENTITY: "identity", MAP_E: "E-SPH", MAP_BF: "BF-SPH",
-             MAP_BFE: "BFE-SPH", MAP_SIGMA: "sigma-SPH"}
+             MAP_BFE: "BFE-SPH", MAP_SIGMA: "sigma-SPH", MAP_PER_PARTICLE: "per-particle"}
 
 KERNEL_WENDLAND_C2, KERNEL_CUBIC_SPLINE = 0, 1
 
@@ -52,6 +52,9 @@ class MapSpec:
              sigma: alpha = Hhat/(H - h))
     dmin, eps: sigma-SPH depth limiter, D_eff = smooth max(H - h, dmin; eps)
     terms  : list of (coef, bx, fx, by, fy) giving h = sum coef*Bx(x)*By(y)
+    pp     : MAP_PER_PARTICLE only: (12, n) alpha, alpha_x, alpha_y, alpha_xx,
+             alpha_xy, alpha_yy, beta, beta_x, beta_y, beta_xx, beta_xy,
+             beta_yy at every particle (the particles' order)
     """
     kind: int = MAP_IDENTITY
     Hhat: float = 1.0
@@ -59,10 +62,11 @@ class MapSpec:
     dmin: float = 0.0
     eps: float = 0.0
     terms: list = field(default_factory=list)
+    pp: object = None
 
     def with_terms(self, extra):
         return MapSpec(self.kind, self.Hhat, self.H, self.dmin, self.eps,
-                       list(self.terms) + list(extra))
+                       list(self.terms) + list(extra), self.pp)
 
     def as_array(self):
         """Terms as an (nterms, 5) float64 array: coef, bx, fx, by, fy."""

@@ -28,6 +28,7 @@ VCT_OUT_PZ = 64
 VCT_OPT_GRAD1 = 256
 VCT_OUT_DEFAULT = VCT_OUT_GRAD | VCT_OUT_LAP | VCT_OUT_CROSS
 VCT_MAX_TERMS = 32
+VCT_MAP_PER_PARTICLE = 5
 FLAG_FEW, FLAG_SINGULAR_A, FLAG_SINGULAR_M, FLAG_NONFINITE, FLAG_DUPLICATE, FLAG_MAP = 1, 2, 4, 8, 16, 32
 
 
@@ -44,7 +45,8 @@ class vct_term(C.Structure):
 
 class vct_map(C.Structure):
     _fields_ = [("kind", C.c_int32), ("nterms", C.c_int32), ("Hhat", C.c_double), ("H", C.c_double),
-                ("dmin", C.c_double), ("eps", C.c_double), ("terms", C.POINTER(vct_term))]
+                ("dmin", C.c_double), ("eps", C.c_double), ("terms", C.POINTER(vct_term)), ("coef", C.c_void_p),
+                ("coef_n", C.c_int64)]
 
 
 class vct_nlist(C.Structure):
@@ -180,8 +182,10 @@ def _d3(v):
     return a
 
 
-def make_map(mapspec):
-    """vct_map (plus the term array it points to) from an inputs.MapSpec."""
+def make_map(mapspec, coef=None):
+    """vct_map (plus the term array it points to) from an inputs.MapSpec; for
+    the per-particle kind, `coef` is the (12, n) FP64 device table in the
+    order of the call's points."""
     terms = mapspec.as_array()
     nt = terms.shape[0]
     if nt > VCT_MAX_TERMS:
@@ -191,8 +195,13 @@ def make_map(mapspec):
         arr[t] = vct_term(float(terms[t, 0]), int(terms[t, 1]), int(terms[t, 3]), float(terms[t, 2]),
                           float(terms[t, 4]))
     m = vct_map(int(mapspec.kind), nt, float(mapspec.Hhat), float(mapspec.H), float(mapspec.dmin),
-                float(mapspec.eps), C.cast(arr, C.POINTER(vct_term)))
-    m._keep = arr
+                float(mapspec.eps), C.cast(arr, C.POINTER(vct_term)), None, 0)
+    if coef is not None:
+        if coef.dtype != __import__("torch").float64 or not coef.is_contiguous() or coef.dim() != 2 \
+                or coef.shape[0] != 12:
+            raise ValueError("per-particle coefficients: a contiguous (12, n) float64 tensor")
+        m.coef, m.coef_n = coef.data_ptr(), int(coef.shape[1])
+    m._keep = (arr, coef)
     return m
 
 
@@ -433,6 +442,14 @@ class Geometry:
         self.state64 = self.state32 = self.flags = None
         self.mask = None
 
+    def map_for(self, mapspec):
+        """vct_map of a MapSpec for calls on this geometry: a per-particle
+        table (mapspec.pp, (12, n) in the caller's order) goes to the device
+        in sorted order."""
+        if int(mapspec.kind) != VCT_MAP_PER_PARTICLE:
+            return make_map(mapspec)
+        return make_map(mapspec, self.sorted_field(mapspec.pp).contiguous())
+
     def sorted_field(self, phi):
         """(nf, n) field in the caller's order -> sorted order (device)."""
         import torch
@@ -460,7 +477,7 @@ class Geometry:
         import torch
         n, dim = self.n, self.dim
         stride = vct_state_stride(dim, mask)
-        self.cmap = make_map(mapspec)
+        self.cmap = self.map_for(mapspec)
         self.mask = mask
         self.state64 = torch.empty((stride, max(n, 1)), dtype=torch.float64, device=self.device) if fp64 else None
         self.state32 = torch.empty((stride, max(n, 1)), dtype=torch.float32, device=self.device) if fp32_copy else None
@@ -481,7 +498,7 @@ class Geometry:
             raise ValueError("resolve() needs an earlier moments() call")
         n, dim = self.n, self.dim
         stride = vct_state_stride(dim, mask)
-        self.cmap = make_map(mapspec)
+        self.cmap = self.map_for(mapspec)
         self.mask = mask
         self.state64 = torch.empty((stride, max(n, 1)), dtype=torch.float64, device=self.device) if fp64 else None
         self.state32 = torch.empty((stride, max(n, 1)), dtype=torch.float32, device=self.device) if fp32_copy else None
@@ -511,14 +528,14 @@ class Geometry:
         nout = vct_n_out(self.dim, mask)
         if out is None:
             out = torch.empty((nf, max(self.n, 1), nout), dtype=torch.float64, device=self.device)
-        vct_apply_ops0(self.nl, nf, phi_sorted, self.pos, self.vol, self.kernel, make_map(mapspec), mask, out)
+        vct_apply_ops0(self.nl, nf, phi_sorted, self.pos, self.vol, self.kernel, self.map_for(mapspec), mask, out)
         return out
 
     def grad_sum(self, mapspec, p_sorted, rho_sorted=None, rho0=1.0, mask=VCT_OUT_GRAD | VCT_OUT_PGRAD):
         """Summation pressure gradient (n, n_out) FP64 of a sorted pressure field."""
         import torch
         out = torch.empty((max(self.n, 1), vct_n_out(self.dim, mask)), dtype=torch.float64, device=self.device)
-        vct_grad_sum(self.nl, self.pos, self.vol, self.kernel, make_map(mapspec), rho_sorted, rho0, p_sorted, mask,
+        vct_grad_sum(self.nl, self.pos, self.vol, self.kernel, self.map_for(mapspec), rho_sorted, rho0, p_sorted, mask,
                      out)
         return out
 
@@ -539,7 +556,7 @@ class Geometry:
         """J = alpha of the mapping at the sorted particles (n,) FP64."""
         import torch
         out = torch.empty(max(self.n, 1), dtype=torch.float64, device=self.device)
-        vct_map_alpha(self.dim, self.n, self.pos, make_map(mapspec), out)
+        vct_map_alpha(self.dim, self.n, self.pos, self.map_for(mapspec), out)
         return out[: self.n]
 
     def jbar_smooth(self, J_sorted, jbar_sorted, cv, re=None):

@@ -119,6 +119,17 @@ def test_argument_errors_are_caught_on_the_host(L):
     hard = vct.vct_map(4, 0, 1.0, 0.0, 0.125, 0.0, None)
     assert L.vct_moments(C.byref(nl), None, None, 0, C.byref(hard), 3, None, None, None, None, None, 0,
                          None) == E              # sigma limiter with dmin > 0 and eps = 0
+    # per-particle table: present, covering exactly the call's points, no bottom terms
+    for pp in (vct.vct_map(5, 0, 1.0, 1.0, 0.0, 0.0, None, None, nl.n),      # no table
+               vct.vct_map(5, 0, 1.0, 1.0, 0.0, 0.0, None, 256, nl.n - 1),   # too short
+               vct.vct_map(5, 1, 1.0, 1.0, 0.0, 0.0, None, 256, nl.n)):      # terms with a table
+        assert L.vct_moments(C.byref(nl), None, None, 0, C.byref(pp), 3, None, None, None, None, None, 0,
+                             None) == E
+        assert L.vct_map_alpha(3, nl.n, C.c_void_p(256), C.byref(pp), C.c_void_p(256), None) == E
+    pp = vct.vct_map(5, 0, 1.0, 1.0, 0.0, 0.0, None, 256, nl.n)
+    r2mask = vct.VCT_OUT_LAP | vct.VCT_OUT_PGRAD | vct.VCT_OUT_PHESS
+    assert L.vct_apply_ops_adjoint_r2(C.byref(nl), None, None, 0, None, r2mask, C.byref(pp), None, None, None,
+                                      None, None, None, 0, None) == E     # R2 needs bottom terms
     assert L.vct_moments_resolve(C.byref(nl), None, C.byref(m), 0, None, None, None, None, None, 0,
                                  None) == E      # empty output mask
     assert L.vct_moments_resolve(C.byref(nl), None, C.byref(badm), 3, None, None, None, None, None, 0,

@@ -2,7 +2,7 @@
 
   * the oracle (orc.c) built with gcc -fsanitize=address,undefined runs every
     oracle pin (test_oracle.py, test_oracle_ppe.py, test_oracle_isph.py,
-    test_oracle_jbar.py, test_oracle_r2.py);
+    test_oracle_jbar.py, test_oracle_r2.py, test_oracle_perparticle.py);
   * the library's host code (argument checks, map set-up, separable table,
     workspace carving, launch-timing registry) built with the same sanitizers
     on the host side only runs the ABI checks of test_abi.py.
@@ -44,7 +44,8 @@ def test_oracle_pins_under_asan_ubsan():
         pytest.skip("gcc ASan runtime not installed")
     lib = oracle.build(sanitize=True, out=os.path.join(ROOT, "_build", "liborc_san.so"))
     print(_run({"LD_PRELOAD": rt, "ORACLE_LIB": lib}, "test_oracle.py", "test_oracle_ppe.py", "test_oracle_isph.py",
-         "test_oracle_jbar.py", "test_oracle_r2.py"))
+         "test_oracle_jbar.py", "test_oracle_r2.py",
+         "test_oracle_perparticle.py"))
 
 
 def test_library_host_code_under_asan_ubsan():
