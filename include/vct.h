@@ -404,9 +404,10 @@ int vct_apply_ops_adjoint(const vct_nlist* nl, const double* pos_sorted, const d
 
 /* ---------------------------------------------------------------- bathymetry adjoint, reading R2 */
 
-/* Workspace of vct_apply_ops_adjoint_r2: nnz + 2 n doubles and the reduction
- * partials. */
-size_t vct_adjoint_r2_workspace_size(int dim, int64_t n, int64_t nnz, int nterms);
+/* Workspace of vct_apply_ops_adjoint_r2: 3^(d-1) + npairs + 2 doubles per
+ * particle (npairs = 3 in 2-D, 6 in 3-D), the reduction partials and a short
+ * int32 list. */
+size_t vct_adjoint_r2_workspace_size(int dim, int64_t n, int nterms);
 
 /* Sensitivity of loss = sum_i (lap_i - g_i)^2 to the bathymetry coefficients
  * when the particles' PHYSICAL positions are held fixed, so that their
@@ -419,7 +420,8 @@ size_t vct_adjoint_r2_workspace_size(int dim, int64_t n, int64_t nnz, int nterms
  *            + sum_k (d loss / d z^_k) (d z^_k / d coef_t)|_{z},
  *   d loss / d z^_k = sum_{i in S_k + k} u_i d lap_i / d z^_k,
  * with the row derivatives by implicit differentiation of the SPH(2) system
- * (each term a function of one offset, so the transposed form sums them).
+ * (each term a function of one offset, summed in the push form of
+ * vct_apply_ops_adjoint: exact integer sums, the same bits on every run).
  * Field values, volumes and the target stay fixed; d loss / d phi does not
  * change between the readings (vct_apply_ops_adjoint gives it).
  *   state64   vct_moments state whose out_mask holds LAP, PGRAD and PHESS
@@ -427,7 +429,8 @@ size_t vct_adjoint_r2_workspace_size(int dim, int64_t n, int64_t nnz, int nterms
  *   proj      [n][n_out] FP64 vct_apply_ops output of phi with that mask
  *   phi [n], u [n] = 2 (lap - g)
  *   dtheta    [map->nterms] or NULL;  dzhat [n] or NULL: d loss / d z^_k
- * Needs nl->col and the transposed-entry map nl->col_t (vct_neighbors).
+ * Needs nl->col16 and the stored chunk windows nl->chunk_win (vct_neighbors);
+ * nl->col and nl->col_t are not read.
  * Non-finite terms make the outputs they reach NaN.  Asynchronous.            */
 int vct_apply_ops_adjoint_r2(const vct_nlist* nl, const double* pos_sorted, const double* vol_sorted, int kernel,
                              const double* state64, uint32_t out_mask, const vct_map* map /* host */,

@@ -118,7 +118,7 @@ class VctLaplacianR2(torch.autograd.Function):
         phys = phys.to(torch.float64).contiguous()
         pos = torch.empty_like(phys)
         vct.vct_map_project(phys.shape[0], phys.shape[1], phys, cmap, pos)
-        geom = vct.Geometry(pos, vol, lo, hi, R, kernel, device=phys.device, keep_col=True)
+        geom = vct.Geometry(pos, vol, lo, hi, R, kernel, device=phys.device, keep_col=False)
         st = geom.moments(spec, R2_MASK)
         if st < 0:
             raise vct.VctError("vct_moments", st)

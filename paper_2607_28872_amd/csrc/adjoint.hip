@@ -15,7 +15,9 @@
 //     buffer in row order and subtracts its row sum;
 //   push form (no map): every particle adds u_i W_ij to the accumulator of j
 //     in LDS as an exact integer (below), per cell column, and the columns'
-//     totals are summed per particle in a fixed order.
+//     totals are summed per particle in a fixed order.  The bathymetry
+//     adjoint with physical positions fixed (reading R2, below) sums its
+//     position terms the same way.
 //
 // Bathymetry coefficients enter only through the VCT coefficients (projected
 // positions are held fixed), so
@@ -71,6 +73,8 @@ struct AdjArgs {
     int r_pg, r_ph;      // first rows of PGRAD and PHESS in proj
     const double* gz;    // [n] d loss / d z^ through the SPH(2) derivatives (c_trans held)
     double* dzhat;       // [n] or NULL: the total d loss / d z^ (c_trans's dependence added)
+    const double* r2h;   // [pairs][n] H_i of the first sweep
+    const double* r2b;   // [n] bound on the row's second-sweep terms per unit volume
 };
 
 // Pass 1: u_i W_ij for every entry of row i, written transposed.  The first
@@ -186,6 +190,285 @@ __global__ __launch_bounds__(kAThreads, 2) void k_adjoint_weights(AdjArgs A) {
     if (valid && lane == 0) A.rowsum[ii] = sum;
 }
 
+// ------------------------------------------------------------------ reading R2
+
+// With the physical positions fixed the projected heights move with the
+// bathymetry, and the rows of the Laplacian change through their offsets.
+// For row i write the SPH(2) system as K x = b with x = [R grad^ phi;
+// R^2 D / 2], b = sum_j V_j t_ij phi_ij, K = sum_j V_j t_ij m_ij^T, t_ij =
+// [c~ r~; F~ q~], m_ij = [r~; q~] and F~ = c~ (r~' L~ r~) / |r~|^4, L~ = A~^-1,
+// A~ = sum_j V_j c~ r~ r~^T (the formulation of the moment kernels).  Then
+// d(u_i lap_i) = u_i P_lap,i (db - dK x) (implicit differentiation), and
+// b - K x = sum_j V_j t_ij psi_ij with the Taylor residual
+// psi_ij = phi_ij - r~ . R grad^ phi - (1/2) r~' R^2 H^ r~.  With x held, the
+// offsets enter directly and through L~; dL~ = -L~ dA~ L~ turns the latter into
+// one more pair term.  So, with W_ij(r~) = V_j c~ [P_a . r~ + (r~' L~ r~)
+// / |r~|^4 P_s . q~] (u_i folded into P, as in lap_weight),
+//   G_i  = sum_j V_j c~ psi_ij (P_s . q~) / |r~|^4  r~ r~^T,   H_i = L~ G_i L~,
+//   Phi_ij(r~) = W_ij(r~) psi_ij(r~) - V_j c~(|r~|) r~' H_i r~,
+// d(u_i lap_i) / d z^_j = (1/R) d Phi_ij / d r~_z for j in S_i and minus their
+// sum for j = i.  Every term is a function of one offset, so the push form
+// below sums them like the Laplacian weights of the field adjoint:
+// k_r2_prep runs the first sweep over each row (G_i, H_i and a bound on the
+// row's terms), and the push kernels the second.
+
+// d c~ / dq of the kernel shape (kernel_shape)
+template <int KERNEL>
+__device__ __forceinline__ double kernel_shape_dq(double q) {
+    if (KERNEL == VCT_KERNEL_WENDLAND_C2) {
+        const double t = q < 1.0 ? 1.0 - q : 0.0;
+        return -3.0 * t * t;
+    } else {
+        const double s = 2.0 * q;
+        const double t = s < 2.0 ? 2.0 - s : 0.0;
+        const double outer = 2.0 * 0.75 * (-2.0 * t / s - t * t / (s * s));
+        return s <= 1.0 ? -4.5 : outer;
+    }
+}
+
+// One particle's row data for the position derivatives: its position and
+// field value, L~ (pairs, off-diagonals doubled for the quadratic form),
+// u_i P_lap, the solution at i in units of R (R grad^ phi, and the Taylor
+// coefficients of (1/2) r~' R^2 H^ r~ on the pair monomials) and H_i.
+template <int D> struct R2Row {
+    double xi[3], phi_i;
+    double L2[Dims<D>::nL], Pl[Dims<D>::nk];
+    double gt[D], hh[Dims<D>::m];
+    double Hm[D][D];
+};
+
+template <int D>
+__device__ __forceinline__ void r2_row_load(const AdjArgs& A, int64_t ii, R2Row<D>& w) {
+    using Dm = Dims<D>;
+    constexpr int nL = Dm::nL, nk = Dm::nk, m = Dm::m;
+    const int64_t n = A.n;
+    const double R = 1.0 / A.invR;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) w.xi[a] = a < D ? A.pos[a * n + ii] : 0.0;
+    w.phi_i = A.phi[ii];
+    const double ui = A.u[ii];
+#pragma unroll
+    for (int p = 0; p < nL; ++p) w.L2[p] = (pair_a<D>(p) == pair_b<D>(p) ? 1.0 : 2.0) * A.state[(int64_t)p * n + ii];
+#pragma unroll
+    for (int c = 0; c < nk; ++c) w.Pl[c] = ui * A.state[(int64_t)(nL + A.lap_row * nk + c) * n + ii];
+    const double* pr = A.proj + ii * A.nrows;
+#pragma unroll
+    for (int a = 0; a < D; ++a) w.gt[a] = R * pr[A.r_pg + a];
+#pragma unroll
+    for (int p = 0; p < m; ++p) w.hh[p] = R * R * pr[A.r_ph + p] * (pair_a<D>(p) == pair_b<D>(p) ? 0.5 : 1.0);
+}
+
+// H_i from the first sweep's pairs
+template <int D>
+__device__ __forceinline__ void r2_row_h(const AdjArgs& A, int64_t ii, R2Row<D>& w) {
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int c = 0; c < D; ++c) w.Hm[a][c] = A.r2h[(int64_t)sym_index<D>(a, c) * A.n + ii];
+}
+
+// the pair quantities of both sweeps
+template <int D> struct R2Pair {
+    double r[D], qv[Dims<D>::m], y, y2, q, ct, sa, ss, rLr, psi, vol;
+};
+
+template <int D, int KERNEL>
+__device__ __forceinline__ R2Pair<D> r2_pair(const R2Row<D>& w, const double4& qr, double ph, double invR) {
+    using Dm = Dims<D>;
+    constexpr int nL = Dm::nL, m = Dm::m;
+    R2Pair<D> P;
+    P.r[0] = (qr.x - w.xi[0]) * invR;
+    P.r[1] = (qr.y - w.xi[1]) * invR;
+    if (D == 3) P.r[D - 1] = (qr.z - w.xi[2]) * invR;
+    double q2 = P.r[0] * P.r[0];
+#pragma unroll
+    for (int a = 1; a < D; ++a) q2 = fma(P.r[a], P.r[a], q2);
+#pragma unroll
+    for (int p = 0; p < m; ++p) P.qv[p] = P.r[pair_a<D>(p)] * P.r[pair_b<D>(p)];
+    P.y = vrsq(q2);
+    P.y2 = P.y * P.y;
+    P.q = q2 > 0.0 ? q2 * P.y : 0.0;
+    P.ct = kernel_shape<KERNEL>(P.q);
+    P.vol = qr.w;
+    double rLr = 0.0, sa = 0.0, ss = 0.0, quad = 0.0, lin = 0.0;
+#pragma unroll
+    for (int p = 0; p < nL; ++p) rLr = fma(w.L2[p], P.qv[p], rLr);
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        sa = fma(w.Pl[a], P.r[a], sa);
+        lin = fma(w.gt[a], P.r[a], lin);
+    }
+#pragma unroll
+    for (int p = 0; p < m; ++p) {
+        ss = fma(w.Pl[D + p], P.qv[p], ss);
+        quad = fma(w.hh[p], P.qv[p], quad);
+    }
+    P.rLr = rLr; P.sa = sa; P.ss = ss;
+    P.psi = (ph - w.phi_i) - lin - quad;
+    return P;
+}
+
+// the second sweep's term: d Phi_ij / d z^_j
+template <int D, int KERNEL>
+__device__ __forceinline__ double r2_term(const R2Row<D>& w, const double4& qr, double ph, double invR) {
+    using Dm = Dims<D>;
+    constexpr int m = Dm::m;
+    constexpr int Z = D - 1;
+    const R2Pair<D> P = r2_pair<D, KERNEL>(w, qr, ph, invR);
+    const double zc = P.r[Z];
+    const double y4 = P.y2 * P.y2;
+    const double dct = kernel_shape_dq<KERNEL>(P.q) * zc * P.y;   // d c~ / d r~_z
+    double Lr = 0.0, Hr = 0.0, Htr = 0.0, rHr = 0.0;              // (L~ r~)_z, (H r~)_z, (H^~ r~)_z, r~' H r~
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        const int pz = sym_index<D>(Z, a);
+        Lr = fma(a == Z ? w.L2[pz] : 0.5 * w.L2[pz], P.r[a], Lr);
+        Hr = fma(w.Hm[Z][a], P.r[a], Hr);
+        double ha = 0.0;
+#pragma unroll
+        for (int c = 0; c < D; ++c) ha = fma(w.Hm[a][c], P.r[c], ha);
+        rHr = fma(P.r[a], ha, rHr);
+        // R^2 H^ from the Taylor coefficients: diagonal 2 hh, off-diagonal hh
+        Htr = fma(a == Z ? 2.0 * w.hh[pz] : w.hh[pz], P.r[a], Htr);
+    }
+    double dss = 0.0;   // d (P_s . q~) / d r~_z
+#pragma unroll
+    for (int p = 0; p < m; ++p) {
+        const int pa = pair_a<D>(p), pb = pair_b<D>(p);
+        const double dq = (pa == Z ? P.r[pb] : 0.0) + (pb == Z ? P.r[pa] : 0.0);
+        dss = fma(w.Pl[D + p], dq, dss);
+    }
+    const double F = P.rLr * y4;
+    const double dF = 2.0 * Lr * y4 - 4.0 * P.rLr * y4 * P.y2 * zc;
+    const double s1 = fma(F, P.ss, P.sa);
+    const double Wv = P.vol * P.ct * s1;
+    const double dW = P.vol * (dct * s1 + P.ct * (w.Pl[Z] + dF * P.ss + F * dss));
+    const double dpsi = -w.gt[Z] - Htr;
+    const double dZ = P.vol * (dct * rHr + 2.0 * P.ct * Hr);
+    return (dW * P.psi + Wv * dpsi - dZ) * invR;
+}
+
+// First sweep per particle (one chunk per work-group, kALanes lanes per
+// particle, window records and field values in LDS):
+//   G_i and H_i = L~ G_i L~, written as r2h[pairs][n];
+//   r2b[i], a bound on |term| / V_j of the row's terms and on nothing else:
+//   with q >= q_min over the row, |r~| < 1, cmax >= c~, dcmax >= |dc~/dq|,
+//   L1 = sum |L2|, Pa1 = sum |P_a|, Ps1 = sum |P_s| (|P_s . q~| <= Ps1 q^2):
+//     |W| / V    <= cmax (Pa1 + L1 Ps1)
+//     |dW| / V   <= dcmax (Pa1 + L1 Ps1) + cmax (Pa1 + 8 L1 Ps1 / q_min)
+//     |dpsi|     <= |R dz^phi| + sum_a |R^2 H^_za|,  |psi| <= max over the row
+//     |dZ| / V   <= (dcmax + 2 cmax) sum |H|
+//   term <= (|dW| max|psi| + |W| |dpsi| + |dZ|) / R.
+template <int D, int KERNEL>
+__global__ __launch_bounds__(kAThreads, 2) void k_r2_prep(AdjArgs A, double* __restrict__ r2h,
+                                                         double* __restrict__ r2b) {
+    using Dm = Dims<D>;
+    constexpr int nL = Dm::nL, m = Dm::m;
+    __shared__ double4 sd[kAWin];   // x, y, z, V
+    __shared__ double sf[kAWin];    // phi
+    __shared__ WindowT<D> w;
+    const uint32_t b = xcd_tile(blockIdx.x, gridDim.x);
+    if (b >= *A.nchunks) return;   // uniform over the work-group
+    const int64_t n = A.n;
+    const int64_t p0 = A.cstart[b], p1 = A.cstart[b + 1];
+    if (threadIdx.x < kWave) {
+        if (A.cwin) window_load<D>(A.cwin, b, w);
+        else chunk_window_wave<D>(A.g, A.cs, A.cinfo[b], w);
+    }
+    __syncthreads();
+    const int W = __builtin_amdgcn_readfirstlane(w.off[w.nr]);
+    const bool in_lds = W <= kAWin;
+    if (in_lds)
+        for (int t = threadIdx.x; t < W; t += kAThreads) {
+            const int64_t j = window_global<D>(w, t);
+            sd[t] = make_double4(A.pos[j], A.pos[n + j], D == 3 ? A.pos[2 * n + j] : 0.0, A.vol[j]);
+            sf[t] = A.phi[j];
+        }
+    __syncthreads();
+    auto fetch = [&](int t, double& ph) -> double4 {
+        if (in_lds) {
+            ph = sf[t];
+            return sd[t];
+        }
+        const int64_t j = window_global<D>(w, t);
+        ph = A.phi[j];
+        return make_double4(A.pos[j], A.pos[n + j], D == 3 ? A.pos[2 * n + j] : 0.0, A.vol[j]);
+    };
+    const int lane = threadIdx.x % kALanes;
+    const int64_t i = p0 + threadIdx.x / kALanes;
+    const bool valid = i < p1;
+    const int64_t ii = valid ? i : p0;
+    R2Row<D> row;
+    r2_row_load<D>(A, ii, row);
+    const int64_t rb = valid ? A.row_ptr[ii] : 0, re = valid ? A.row_ptr[ii + 1] : 0;
+    double Gp[nL];
+#pragma unroll
+    for (int p = 0; p < nL; ++p) Gp[p] = 0.0;
+    double psimax = 0.0, qmin = 2.0;
+    for (int64_t e = rb + lane; e < re; e += kALanes) {
+        double ph;
+        const double4 qr = fetch(A.col16[e], ph);
+        const R2Pair<D> P = r2_pair<D, KERNEL>(row, qr, ph, A.invR);
+        const double kap = P.vol * P.ct * P.psi * P.ss * (P.y2 * P.y2);
+#pragma unroll
+        for (int p = 0; p < nL; ++p) Gp[p] = fma(kap, P.qv[p], Gp[p]);
+        psimax = fmax(psimax, fabs(P.psi));
+        qmin = fmin(qmin, P.q);
+    }
+#pragma unroll
+    for (int p = 0; p < nL; ++p) Gp[p] = group_sum(Gp[p], kALanes);
+    for (int s2 = 1; s2 < kALanes; s2 <<= 1) {
+        psimax = fmax(psimax, __shfl_xor(psimax, s2, kALanes));
+        qmin = fmin(qmin, __shfl_xor(qmin, s2, kALanes));
+    }
+    // H_i = L~ G_i L~ (symmetric; L~ off-diagonals are L2 / 2)
+    double Lm[D][D], Gm[D][D];
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            const int p = sym_index<D>(a, c);
+            Lm[a][c] = a == c ? row.L2[p] : 0.5 * row.L2[p];
+            Gm[a][c] = Gp[p];
+        }
+    double Hp[nL];
+#pragma unroll
+    for (int p = 0; p < nL; ++p) {
+        const int a = pair_a<D>(p), c = pair_b<D>(p);
+        double t = 0.0;
+#pragma unroll
+        for (int e1 = 0; e1 < D; ++e1)
+#pragma unroll
+            for (int e2 = 0; e2 < D; ++e2) t = fma(Lm[a][e1], Gm[e1][e2] * Lm[e2][c], t);
+        Hp[p] = t;
+    }
+    if (!valid || lane != 0) return;
+#pragma unroll
+    for (int p = 0; p < nL; ++p) r2h[(int64_t)p * n + i] = Hp[p];
+    // the bound
+    const double cmax = KERNEL == VCT_KERNEL_WENDLAND_C2 ? 1.0 : 3.0;
+    const double dcmax = KERNEL == VCT_KERNEL_WENDLAND_C2 ? 3.0 : 4.5;
+    double L1 = 0.0, Pa1 = 0.0, Ps1 = 0.0, Hs = 0.0, dps = fabs(row.gt[D - 1]);
+#pragma unroll
+    for (int p = 0; p < nL; ++p) {
+        L1 += fabs(row.L2[p]);
+        Hs += (pair_a<D>(p) == pair_b<D>(p) ? 1.0 : 2.0) * fabs(Hp[p]);
+    }
+#pragma unroll
+    for (int a = 0; a < D; ++a) Pa1 += fabs(row.Pl[a]);
+#pragma unroll
+    for (int p = 0; p < m; ++p) Ps1 += fabs(row.Pl[D + p]);
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        const int p = sym_index<D>(D - 1, a);
+        dps += (a == D - 1 ? 2.0 : 1.0) * fabs(row.hh[p]);
+    }
+    const double w1 = cmax * (Pa1 + L1 * Ps1);
+    const double dw1 = dcmax * (Pa1 + L1 * Ps1) + cmax * (Pa1 + 8.0 * L1 * Ps1 / qmin);
+    const double dz1 = (dcmax + 2.0 * cmax) * Hs;
+    r2b[i] = (dw1 * psimax + w1 * dps + dz1) * A.invR;
+}
+
 // Push form (no transposed map).  Every particle i evaluates u_i W_ij once
 // for each entry of its own row, with its state in registers, and adds it to
 // the accumulator of j; particle j receives these from the particles of the
@@ -212,7 +495,7 @@ __global__ __launch_bounds__(kAThreads, 2) void k_adjoint_weights(AdjArgs A) {
 // Bound: with r~ = r/R (|r~| < 1 inside the support), |q~_p| <= |r~|^2 and
 // |r~' L~ r~| <= (sum |L~|) |r~|^2, so for the kernel shape c~ <= c_max
 //   |u_i W_ij| <= V_j c_max (sum_a |u P_a,i| + (sum |L~_i|) (sum_p |u P_s,i|)).
-constexpr int kPThreads = 1024;   // 128 particles at a time, 8 lanes each
+constexpr int kPThreads = 1024;   // 128 particles at a time, 8 lanes each (the field adjoint)
 constexpr int kPAcc = 3840;       // accumulators (and staged records) per pass over a column's window
 constexpr int kPChunks = 24;      // chunk windows of one column held in LDS
 constexpr int kPSlots = 16;       // row entries per lane loaded into registers at a time
@@ -240,20 +523,36 @@ __device__ __forceinline__ T wave_max(T v) {
     return v;
 }
 
+// What the push form sums: the Laplacian weights u_i W_ij of the field
+// adjoint, or the position terms d Phi_ij / d z^_j of reading R2 (these read
+// the field values too, staged with the records).
+// R2 runs half the threads: its rows hold about twice the registers.
+struct PushLap {
+    static constexpr int kAcc = kPAcc, kThreads = kPThreads;
+    static constexpr bool kR2 = false;
+};
+struct PushR2 {
+    static constexpr int kAcc = 3200, kThreads = kPThreads / 2;
+    static constexpr bool kR2 = true;
+};
+
 // One column.  FAST = true handles a column whose window fits the
 // accumulators (one pass, records in LDS) and appends any other column to the
 // list `wide` ([0] = count); FAST = false handles a listed column (passes over
 // the window, records read from memory).
-template <int D, int KERNEL, bool FAST>
+template <int D, int KERNEL, class OP, bool FAST>
 __device__ __forceinline__ void push_column(const AdjArgs& A, double* __restrict__ partial, int64_t c,
                                             int32_t* __restrict__ wide) {
     using Dm = Dims<D>;
     constexpr int nL = Dm::nL, nk = Dm::nk, m = Dm::m;
     constexpr int NS = D == 3 ? 9 : 3;
-    constexpr int kW = kPThreads / kWave;
-    __shared__ unsigned long long s_acc[kPAcc];
-    __shared__ double4 s_pos[FAST ? kPAcc : 1];
-    __shared__ uint32_t s_nan[kPAcc / 32];
+    constexpr int kThreads = OP::kThreads;
+    constexpr int kW = kThreads / kWave;
+    constexpr int kAcc = OP::kAcc;
+    __shared__ unsigned long long s_acc[kAcc];
+    __shared__ double4 s_pos[FAST ? kAcc : 1];
+    __shared__ double s_phi[FAST && OP::kR2 ? kAcc : 1];
+    __shared__ uint32_t s_nan[kAcc / 32];
     __shared__ WindowT<D> s_cw;
     __shared__ WindowT<D> s_chw[kPChunks];
     // per chunk of the current group: range starts in its window (INT_MAX past
@@ -283,7 +582,7 @@ __device__ __forceinline__ void push_column(const AdjArgs& A, double* __restrict
     }
     __syncthreads();
     const int Wc = s_cw.off[s_cw.nr];
-    if (FAST && Wc > kPAcc) {   // uniform: left to the wide pass
+    if (FAST && Wc > kAcc) {   // uniform: left to the wide pass
         if (tid == 0) wide[kWideList + atomicAdd(&wide[kWideCount], 1)] = (int32_t)c;
         return;
     }
@@ -296,26 +595,32 @@ __device__ __forceinline__ void push_column(const AdjArgs& A, double* __restrict
     // largest volume of the window, the largest per-particle bound and the
     // longest row of the column's particles
     double vmax = 0.0, bmax = 0.0;
-    for (int t = tid; t < Wc; t += kPThreads) {
+    for (int t = tid; t < Wc; t += kThreads) {
         const int64_t j = window_global<D>(s_cw, t);
         const double v = A.vol[j];
         vmax = fmax(vmax, v);
         if (FAST) s_pos[t] = make_double4(A.pos[j], A.pos[n + j], D == 3 ? A.pos[2 * n + j] : 0.0, v);
+        if (FAST && OP::kR2) s_phi[t] = A.phi[j];
     }
     // the first group of chunk windows, loaded alongside
     for (int cb = wv; cb < (nch < kPChunks ? nch : kPChunks); cb += kW)
         window_load<D>(A.cwin, (uint32_t)(b0 + cb), s_chw[cb]);
     const int qlen = s_cw.off[rown + 1] - s_cw.off[rown];
-    for (int q = tid; q < qlen; q += kPThreads) {
+    for (int q = tid; q < qlen; q += kThreads) {
         const int64_t i = q0 + q;
-        double sL = 0.0, sa = 0.0, ss = 0.0;
+        double bnd;
+        if constexpr (OP::kR2) {
+            bnd = A.r2b[i];
+        } else {
+            double sL = 0.0, sa = 0.0, ss = 0.0;
 #pragma unroll
-        for (int p = 0; p < nL; ++p) sL += (pair_a<D>(p) == pair_b<D>(p) ? 1.0 : 2.0) * fabs(A.state[(int64_t)p * n + i]);
+            for (int p = 0; p < nL; ++p) sL += (pair_a<D>(p) == pair_b<D>(p) ? 1.0 : 2.0) * fabs(A.state[(int64_t)p * n + i]);
 #pragma unroll
-        for (int a = 0; a < D; ++a) sa += fabs(A.state[(int64_t)(nL + A.lap_row * nk + a) * n + i]);
+            for (int a = 0; a < D; ++a) sa += fabs(A.state[(int64_t)(nL + A.lap_row * nk + a) * n + i]);
 #pragma unroll
-        for (int p = 0; p < m; ++p) ss += fabs(A.state[(int64_t)(nL + A.lap_row * nk + D + p) * n + i]);
-        const double bnd = fabs(A.u[i]) * (sa + sL * ss);
+            for (int p = 0; p < m; ++p) ss += fabs(A.state[(int64_t)(nL + A.lap_row * nk + D + p) * n + i]);
+            bnd = fabs(A.u[i]) * (sa + sL * ss);
+        }
         if (bnd <= 1.7976931348623157e308) bmax = fmax(bmax, bnd);   // skips NaN and infinity
     }
     vmax = wave_max(vmax);
@@ -332,7 +637,8 @@ __device__ __forceinline__ void push_column(const AdjArgs& A, double* __restrict
         vmax = fmax(vmax, s_red[0][w]);
         bmax = fmax(bmax, s_red[1][w]);
     }
-    const double cmax = KERNEL == VCT_KERNEL_WENDLAND_C2 ? 1.0 : 3.0;
+    // (the R2 bound already holds the kernel-shape factors)
+    const double cmax = OP::kR2 ? 1.0 : KERNEL == VCT_KERNEL_WENDLAND_C2 ? 1.0 : 3.0;
     const double Mb = vmax * cmax * 1.0625 * bmax;   // the factor covers |r~| rounded above 1
     // terms reaching one accumulator: at most one per neighbour of its
     // particle, plus the self term of at most (longest row) x M
@@ -341,20 +647,24 @@ __device__ __forceinline__ void push_column(const AdjArgs& A, double* __restrict
 
     const int lane = tid % kALanes;
     const int slot = tid / kALanes;
-    constexpr int kBatch = kPThreads / kALanes;
+    constexpr int kBatch = kThreads / kALanes;
 
     // one particle's row
     auto rows = [&](int cb, int64_t ii, bool valid, int q, int t0, int tn) {
-        double xi[3];
+        R2Row<D> row;
+        if constexpr (OP::kR2) {
+            r2_row_load<D>(A, ii, row);
+            r2_row_h<D>(A, ii, row);
+        } else {
 #pragma unroll
-        for (int a = 0; a < 3; ++a) xi[a] = a < D ? A.pos[a * n + ii] : 0.0;
-        double L2[nL], Pl[nk];
-        const double ui = A.u[ii];
+            for (int a = 0; a < 3; ++a) row.xi[a] = a < D ? A.pos[a * n + ii] : 0.0;
+            const double ui = A.u[ii];
 #pragma unroll
-        for (int p = 0; p < nL; ++p)
-            L2[p] = (pair_a<D>(p) == pair_b<D>(p) ? 1.0 : 2.0) * A.state[(int64_t)p * n + ii];
+            for (int p = 0; p < nL; ++p)
+                row.L2[p] = (pair_a<D>(p) == pair_b<D>(p) ? 1.0 : 2.0) * A.state[(int64_t)p * n + ii];
 #pragma unroll
-        for (int cc = 0; cc < nk; ++cc) Pl[cc] = ui * A.state[(int64_t)(nL + A.lap_row * nk + cc) * n + ii];
+            for (int cc = 0; cc < nk; ++cc) row.Pl[cc] = ui * A.state[(int64_t)(nL + A.lap_row * nk + cc) * n + ii];
+        }
         const int tci = s_cw.off[rown] + q - t0;   // the particle's own accumulator
         const bool self_in = valid && (FAST || (unsigned)tci < (unsigned)tn);
         const int64_t rb = valid ? A.row_ptr[ii] : 0, re = valid ? A.row_ptr[ii + 1] : 0;
@@ -402,13 +712,18 @@ __device__ __forceinline__ void push_column(const AdjArgs& A, double* __restrict
                     const bool here = FAST || (unsigned)tc < (unsigned)tn;
                     if (here || self_in) {
                         double4 qv;
+                        double ph = 0.0;
                         if (FAST) {
                             qv = s_pos[tg];
+                            if (OP::kR2) ph = s_phi[tg];
                         } else {
                             const int64_t j = s_cw.gstart[r] + (tg - s_cw.off[r]);
                             qv = make_double4(A.pos[j], A.pos[n + j], D == 3 ? A.pos[2 * n + j] : 0.0, A.vol[j]);
+                            if (OP::kR2) ph = A.phi[j];
                         }
-                        const double wij = lap_weight<D, KERNEL>(qv, xi, A.invR, L2, Pl);
+                        double wij;
+                        if constexpr (OP::kR2) wij = r2_term<D, KERNEL>(row, qv, ph, A.invR);
+                        else wij = lap_weight<D, KERNEL>(qv, row.xi, A.invR, row.L2, row.Pl);
                         rowsum += wij;
                         if (here) {
                             unsigned long long X;
@@ -428,10 +743,10 @@ __device__ __forceinline__ void push_column(const AdjArgs& A, double* __restrict
     };
 
     // passes over the column window (one unless it exceeds the accumulators)
-    for (int t0 = 0; t0 < Wc; t0 += kPAcc) {
-        const int tn = Wc - t0 < kPAcc ? Wc - t0 : kPAcc;
-        for (int t = tid; t < tn; t += kPThreads) s_acc[t] = 0ull;
-        for (int t = tid; t < (tn + 31) / 32; t += kPThreads) s_nan[t] = 0u;
+    for (int t0 = 0; t0 < Wc; t0 += kAcc) {
+        const int tn = Wc - t0 < kAcc ? Wc - t0 : kAcc;
+        for (int t = tid; t < tn; t += kThreads) s_acc[t] = 0ull;
+        for (int t = tid; t < (tn + 31) / 32; t += kThreads) s_nan[t] = 0u;
         // the column's chunks, kPChunks at a time
         for (int g0 = 0; g0 < nch; g0 += kPChunks) {
             const int ncl = nch - g0 < kPChunks ? nch - g0 : kPChunks;
@@ -461,7 +776,7 @@ __device__ __forceinline__ void push_column(const AdjArgs& A, double* __restrict
         }
         __syncthreads();
         // this pass's totals, into the slot of each destination
-        for (int t = tid; t < tn; t += kPThreads) {
+        for (int t = tid; t < tn; t += kThreads) {
             const int tt = t0 + t;
             int r = 0;
 #pragma unroll
@@ -478,21 +793,21 @@ __device__ __forceinline__ void push_column(const AdjArgs& A, double* __restrict
     }
 }
 
-template <int D, int KERNEL>
-__global__ __launch_bounds__(kPThreads, 1) void k_adjoint_push(AdjArgs A, double* __restrict__ partial,
+template <int D, int KERNEL, class OP>
+__global__ __launch_bounds__(OP::kThreads, 1) void k_adjoint_push(AdjArgs A, double* __restrict__ partial,
                                                                int32_t* __restrict__ wide) {
     const int64_t c = xcd_tile(blockIdx.x, gridDim.x);
     if (c >= grid_ncols<D>(A.g)) return;   // uniform over the work-group
-    push_column<D, KERNEL, true>(A, partial, c, wide);
+    push_column<D, KERNEL, OP, true>(A, partial, c, wide);
 }
 
 // the listed wide columns, taken in turn by a fixed grid
-template <int D, int KERNEL>
-__global__ __launch_bounds__(kPThreads, 1) void k_adjoint_push_wide(AdjArgs A, double* __restrict__ partial,
+template <int D, int KERNEL, class OP>
+__global__ __launch_bounds__(OP::kThreads, 1) void k_adjoint_push_wide(AdjArgs A, double* __restrict__ partial,
                                                                     int32_t* __restrict__ wide) {
     const int cnt = wide[kWideCount];
     for (int w = blockIdx.x; w < cnt; w += gridDim.x) {
-        push_column<D, KERNEL, false>(A, partial, wide[kWideList + w], wide);
+        push_column<D, KERNEL, OP, false>(A, partial, wide[kWideList + w], wide);
         __syncthreads();
     }
 }
@@ -550,222 +865,6 @@ __global__ __launch_bounds__(256) void k_adjoint_gather(int64_t n, const int64_t
     }
     s = group_sum(s, kALanes);
     if (valid && lane == 0) dphi[k] = s - rowsum[k];
-}
-
-// ------------------------------------------------------------------ reading R2
-
-// With the physical positions fixed the projected heights move with the
-// bathymetry, and the rows of the Laplacian change through their offsets.
-// For row i write the SPH(2) system as K x = b with x = [R grad^ phi;
-// R^2 D / 2], b = sum_j V_j t_ij phi_ij, K = sum_j V_j t_ij m_ij^T, t_ij =
-// [c~ r~; F~ q~], m_ij = [r~; q~] and F~ = c~ (r~' L~ r~) / |r~|^4, L~ = A~^-1,
-// A~ = sum_j V_j c~ r~ r~^T (the formulation of the moment kernels).  Then
-// d(u_i lap_i) = u_i P_lap,i (db - dK x) (implicit differentiation), and
-// b - K x = sum_j V_j t_ij psi_ij with the Taylor residual
-// psi_ij = phi_ij - r~ . R grad^ phi - (1/2) r~' R^2 H^ r~.  With x held, the
-// offsets enter directly and through L~; dL~ = -L~ dA~ L~ turns the latter into
-// one more pair term.  So, with W_ij(r~) = V_j c~ [P_a . r~ + (r~' L~ r~)
-// / |r~|^4 P_s . q~] (u_i folded into P, as in lap_weight),
-//   G_i  = sum_j V_j c~ psi_ij (P_s . q~) / |r~|^4  r~ r~^T,   H_i = L~ G_i L~,
-//   Phi_ij(r~) = W_ij(r~) psi_ij(r~) - V_j c~(|r~|) r~' H_i r~,
-// d(u_i lap_i) / d z^_j = (1/R) d Phi_ij / d r~_z for j in S_i and minus their
-// sum for j = i (every term depends on the offset only).  k_r2_weights
-// evaluates G_i in a first sweep over the row and the derivatives in a
-// second, writing them at the transposed positions; k_adjoint_gather then
-// forms, for every particle k, sum_{i in S_k} d(u_i lap_i)/d z^_k minus the
-// row sum of k.
-
-// d c~ / dq of the kernel shape (kernel_shape)
-template <int KERNEL>
-__device__ __forceinline__ double kernel_shape_dq(double q) {
-    if (KERNEL == VCT_KERNEL_WENDLAND_C2) {
-        const double t = q < 1.0 ? 1.0 - q : 0.0;
-        return -3.0 * t * t;
-    } else {
-        const double s = 2.0 * q;
-        const double t = s < 2.0 ? 2.0 - s : 0.0;
-        const double outer = 2.0 * 0.75 * (-2.0 * t / s - t * t / (s * s));
-        return s <= 1.0 ? -4.5 : outer;
-    }
-}
-
-template <int D, int KERNEL>
-__global__ __launch_bounds__(kAThreads, 2) void k_r2_weights(AdjArgs A) {
-    using Dm = Dims<D>;
-    constexpr int nL = Dm::nL, nk = Dm::nk, m = Dm::m;
-    __shared__ double4 sd[kAWin];   // x, y, z, V
-    __shared__ double sf[kAWin];    // phi
-    __shared__ WindowT<D> w;
-    const uint32_t b = xcd_tile(blockIdx.x, gridDim.x);
-    if (b >= *A.nchunks) return;   // uniform over the work-group
-    const int64_t n = A.n;
-    const double R = 1.0 / A.invR;
-    const int64_t p0 = A.cstart[b], p1 = A.cstart[b + 1];
-    if (threadIdx.x < kWave) {
-        if (A.cwin) window_load<D>(A.cwin, b, w);
-        else chunk_window_wave<D>(A.g, A.cs, A.cinfo[b], w);
-    }
-    __syncthreads();
-    const int W = __builtin_amdgcn_readfirstlane(w.off[w.nr]);
-    const bool in_lds = W <= kAWin;
-    if (in_lds)
-        for (int t = threadIdx.x; t < W; t += kAThreads) {
-            const int64_t j = window_global<D>(w, t);
-            sd[t] = make_double4(A.pos[j], A.pos[n + j], D == 3 ? A.pos[2 * n + j] : 0.0, A.vol[j]);
-            sf[t] = A.phi[j];
-        }
-    __syncthreads();
-    auto fetch = [&](int t, double& ph) -> double4 {
-        if (in_lds) {
-            ph = sf[t];
-            return sd[t];
-        }
-        const int64_t j = window_global<D>(w, t);
-        ph = A.phi[j];
-        return make_double4(A.pos[j], A.pos[n + j], D == 3 ? A.pos[2 * n + j] : 0.0, A.vol[j]);
-    };
-    const int lane = threadIdx.x % kALanes;
-    const int64_t i = p0 + threadIdx.x / kALanes;
-    const bool valid = i < p1;
-    const int64_t ii = valid ? i : p0;
-    double xi[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) xi[a] = a < D ? A.pos[a * n + ii] : 0.0;
-    const double phi_i = A.phi[ii];
-    // L~ (pairs, off-diagonals doubled for the quadratic form), u_i P_lap
-    double L2[nL], Pl[nk];
-    const double ui = A.u[ii];
-#pragma unroll
-    for (int p = 0; p < nL; ++p) L2[p] = (pair_a<D>(p) == pair_b<D>(p) ? 1.0 : 2.0) * A.state[(int64_t)p * n + ii];
-#pragma unroll
-    for (int c = 0; c < nk; ++c) Pl[c] = ui * A.state[(int64_t)(nL + A.lap_row * nk + c) * n + ii];
-    // the solution x at i in units of R: R grad^ phi and the Taylor coefficients
-    // of (1/2) r~' R^2 H^ r~ on the pair monomials
-    double gt[D], hh[m];
-    {
-        const double* pr = A.proj + ii * A.nrows;
-#pragma unroll
-        for (int a = 0; a < D; ++a) gt[a] = R * pr[A.r_pg + a];
-#pragma unroll
-        for (int p = 0; p < m; ++p) hh[p] = R * R * pr[A.r_ph + p] * (pair_a<D>(p) == pair_b<D>(p) ? 0.5 : 1.0);
-    }
-    const int64_t rb = valid ? A.row_ptr[ii] : 0, re = valid ? A.row_ptr[ii + 1] : 0;
-
-    // the pair quantities shared by both sweeps
-    struct Pair {
-        double r[D], qv[m], y, y2, q, ct, sa, ss, rLr, psi, vol;
-    };
-    auto pair = [&](const double4& qr, double ph) {
-        Pair P;
-        P.r[0] = (qr.x - xi[0]) * A.invR;
-        P.r[1] = (qr.y - xi[1]) * A.invR;
-        if (D == 3) P.r[D - 1] = (qr.z - xi[2]) * A.invR;
-        double q2 = P.r[0] * P.r[0];
-#pragma unroll
-        for (int a = 1; a < D; ++a) q2 = fma(P.r[a], P.r[a], q2);
-#pragma unroll
-        for (int p = 0; p < m; ++p) P.qv[p] = P.r[pair_a<D>(p)] * P.r[pair_b<D>(p)];
-        P.y = vrsq(q2);
-        P.y2 = P.y * P.y;
-        P.q = q2 > 0.0 ? q2 * P.y : 0.0;
-        P.ct = kernel_shape<KERNEL>(P.q);
-        P.vol = qr.w;
-        double rLr = 0.0, sa = 0.0, ss = 0.0, quad = 0.0, lin = 0.0;
-#pragma unroll
-        for (int p = 0; p < nL; ++p) rLr = fma(L2[p], P.qv[p], rLr);
-#pragma unroll
-        for (int a = 0; a < D; ++a) {
-            sa = fma(Pl[a], P.r[a], sa);
-            lin = fma(gt[a], P.r[a], lin);
-        }
-#pragma unroll
-        for (int p = 0; p < m; ++p) {
-            ss = fma(Pl[D + p], P.qv[p], ss);
-            quad = fma(hh[p], P.qv[p], quad);
-        }
-        P.rLr = rLr; P.sa = sa; P.ss = ss;
-        P.psi = (ph - phi_i) - lin - quad;
-        return P;
-    };
-
-    // sweep 1: G_i (pairs order)
-    double Gp[nL];
-#pragma unroll
-    for (int p = 0; p < nL; ++p) Gp[p] = 0.0;
-    for (int64_t e = rb + lane; e < re; e += kALanes) {
-        double ph;
-        const double4 qr = fetch(A.col16[e], ph);
-        const Pair P = pair(qr, ph);
-        const double kap = P.vol * P.ct * P.psi * P.ss * (P.y2 * P.y2);
-#pragma unroll
-        for (int p = 0; p < nL; ++p) Gp[p] = fma(kap, P.qv[p], Gp[p]);
-    }
-#pragma unroll
-    for (int p = 0; p < nL; ++p) Gp[p] = group_sum(Gp[p], kALanes);
-    // H_i = L~ G_i L~ (symmetric; L~ off-diagonals are L2 / 2)
-    double Lm[D][D], Gm[D][D], Hm[D][D];
-#pragma unroll
-    for (int a = 0; a < D; ++a)
-#pragma unroll
-        for (int c = 0; c < D; ++c) {
-            const int p = sym_index<D>(a, c);
-            Lm[a][c] = a == c ? L2[p] : 0.5 * L2[p];
-            Gm[a][c] = Gp[p];
-        }
-#pragma unroll
-    for (int a = 0; a < D; ++a)
-#pragma unroll
-        for (int c = 0; c < D; ++c) {
-            double t = 0.0;
-#pragma unroll
-            for (int e1 = 0; e1 < D; ++e1)
-#pragma unroll
-                for (int e2 = 0; e2 < D; ++e2) t = fma(Lm[a][e1], Gm[e1][e2] * Lm[e2][c], t);
-            Hm[a][c] = t;
-        }
-    // sweep 2: d Phi_ij / d r~_z, written at the transposed position
-    constexpr int Z = D - 1;
-    double rowsum = 0.0;
-    for (int64_t e = rb + lane; e < re; e += kALanes) {
-        double ph;
-        const double4 qr = fetch(A.col16[e], ph);
-        const Pair P = pair(qr, ph);
-        const double zc = P.r[Z];
-        const double y4 = P.y2 * P.y2;
-        const double dct = kernel_shape_dq<KERNEL>(P.q) * zc * P.y;   // d c~ / d r~_z
-        double Lr = 0.0, Hr = 0.0, Htr = 0.0, rHr = 0.0;              // (L~ r~)_z, (H r~)_z, (H^~ r~)_z, r~' H r~
-#pragma unroll
-        for (int a = 0; a < D; ++a) {
-            Lr = fma(Lm[Z][a], P.r[a], Lr);
-            Hr = fma(Hm[Z][a], P.r[a], Hr);
-            double ha = 0.0;
-#pragma unroll
-            for (int c = 0; c < D; ++c) ha = fma(Hm[a][c], P.r[c], ha);
-            rHr = fma(P.r[a], ha, rHr);
-            // R^2 H^ from the Taylor coefficients: diagonal 2 hh, off-diagonal hh
-            const int p = sym_index<D>(Z, a);
-            Htr = fma(a == Z ? 2.0 * hh[p] : hh[p], P.r[a], Htr);
-        }
-        double dss = 0.0;   // d (P_s . q~) / d r~_z
-#pragma unroll
-        for (int p = 0; p < m; ++p) {
-            const int pa = pair_a<D>(p), pb = pair_b<D>(p);
-            const double dq = (pa == Z ? P.r[pb] : 0.0) + (pb == Z ? P.r[pa] : 0.0);
-            dss = fma(Pl[D + p], dq, dss);
-        }
-        const double F = P.rLr * y4;
-        const double dF = 2.0 * Lr * y4 - 4.0 * P.rLr * y4 * P.y2 * zc;
-        const double s1 = fma(F, P.ss, P.sa);
-        const double Wv = P.vol * P.ct * s1;
-        const double dW = P.vol * (dct * s1 + P.ct * (Pl[Z] + dF * P.ss + F * dss));
-        const double dpsi = -gt[Z] - Htr;
-        const double dZ = P.vol * (dct * rHr + 2.0 * P.ct * Hr);
-        const double t = (dW * P.psi + Wv * dpsi - dZ) * A.invR;
-        A.wbuf[A.col_t[e]] = t;
-        rowsum += t;
-    }
-    rowsum = group_sum(rowsum, kALanes);
-    if (valid && lane == 0) A.rowsum[ii] = rowsum;
 }
 
 constexpr int kRedThreads = 256;
@@ -910,11 +1009,11 @@ static int launch_adjoint(AdjArgs a, int64_t cap, const MapParams& mp, double* d
         VCT_LAUNCH_CHECK();
         VCT_LAUNCH("k_adjoint_maxdeg", k_adjoint_maxdeg, dim3(512), dim3(256), 0, s, n, a.row_ptr, a.wide);
         VCT_LAUNCH_CHECK();
-        VCT_LAUNCH("k_adjoint_push", (k_adjoint_push<D, KERNEL>), dim3((unsigned)ncols), dim3(kPThreads), 0, s, a,
-                   a.partial, a.wide);
+        VCT_LAUNCH("k_adjoint_push", (k_adjoint_push<D, KERNEL, PushLap>), dim3((unsigned)ncols), dim3(PushLap::kThreads),
+                   0, s, a, a.partial, a.wide);
         VCT_LAUNCH_CHECK();
-        VCT_LAUNCH("k_adjoint_push (wide)", (k_adjoint_push_wide<D, KERNEL>), dim3(256), dim3(kPThreads), 0, s, a,
-                   a.partial, a.wide);
+        VCT_LAUNCH("k_adjoint_push (wide)", (k_adjoint_push_wide<D, KERNEL, PushLap>), dim3(256), dim3(PushLap::kThreads), 0,
+                   s, a, a.partial, a.wide);
         VCT_LAUNCH_CHECK();
         VCT_LAUNCH("k_adjoint_combine", (k_adjoint_combine<D>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
                    n, a.g, a.pos, a.partial, a.dphi);
@@ -934,12 +1033,25 @@ static int launch_adjoint(AdjArgs a, int64_t cap, const MapParams& mp, double* d
 
 template <int D, int KERNEL>
 static int launch_r2(AdjArgs a, int64_t cap, const MapParams& mp, double* gz, double* dtheta, double* partials,
-                     hipStream_t s) {
+                     double* r2h, double* r2b, hipStream_t s) {
     const int64_t n = a.n;
-    VCT_LAUNCH("k_r2_weights", (k_r2_weights<D, KERNEL>), dim3((unsigned)cap), dim3(kAThreads), 0, s, a);
+    const int64_t ncols = D == 3 ? a.g.nc[0] * a.g.nc[1] : a.g.nc[0];
+    VCT_LAUNCH("k_zero_wide", k_zero_wide, dim3(1), dim3(1), 0, s, a.wide);
     VCT_LAUNCH_CHECK();
-    VCT_LAUNCH("k_adjoint_gather", k_adjoint_gather, dim3((unsigned)((n * kALanes + 255) / 256)), dim3(256), 0, s, n,
-               a.row_ptr, a.wbuf, a.rowsum, gz);
+    VCT_LAUNCH("k_adjoint_maxdeg", k_adjoint_maxdeg, dim3(512), dim3(256), 0, s, n, a.row_ptr, a.wide);
+    VCT_LAUNCH_CHECK();
+    VCT_LAUNCH("k_r2_prep", (k_r2_prep<D, KERNEL>), dim3((unsigned)cap), dim3(kAThreads), 0, s, a, r2h, r2b);
+    VCT_LAUNCH_CHECK();
+    a.r2h = r2h;
+    a.r2b = r2b;
+    VCT_LAUNCH("k_adjoint_push (R2)", (k_adjoint_push<D, KERNEL, PushR2>), dim3((unsigned)ncols), dim3(PushR2::kThreads), 0,
+               s, a, a.partial, a.wide);
+    VCT_LAUNCH_CHECK();
+    VCT_LAUNCH("k_adjoint_push (R2, wide)", (k_adjoint_push_wide<D, KERNEL, PushR2>), dim3(256), dim3(PushR2::kThreads), 0,
+               s, a, a.partial, a.wide);
+    VCT_LAUNCH_CHECK();
+    VCT_LAUNCH("k_adjoint_combine", (k_adjoint_combine<D>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n,
+               a.g, a.pos, a.partial, gz);
     VCT_LAUNCH_CHECK();
     a.gz = gz;
     const int64_t nred = (n + kRedThreads - 1) / kRedThreads;
@@ -963,8 +1075,9 @@ __global__ void k_zero_f64(double* p, int64_t cnt) {
 
 using namespace vct;
 
-// Columns whose window exceeds kPAcc particles: each particle lies in at most
-// 3^(d-1) <= 9 windows, so there are fewer than 9 n / kPAcc < n / 256 of them.
+// Columns whose window exceeds the accumulators (at least 3200 particles):
+// each particle lies in at most 3^(d-1) <= 9 windows, so there are fewer than
+// 9 n / 3200 < n / 256 of them.
 static int64_t wide_list_len(int64_t n) { return n / 256 + 2; }
 
 extern "C" size_t vct_adjoint_workspace_size(int dim, int64_t n, int64_t nnz, int nterms) {
@@ -1062,12 +1175,14 @@ extern "C" int vct_apply_ops_adjoint(const vct_nlist* nl, const double* pos_sort
 
 // ------------------------------------------------------------------ reading R2 entry point
 
-extern "C" size_t vct_adjoint_r2_workspace_size(int dim, int64_t n, int64_t nnz, int nterms) {
-    if ((dim != 2 && dim != 3) || n < 0 || nnz < 0 || nterms < 0) return 0;
+extern "C" size_t vct_adjoint_r2_workspace_size(int dim, int64_t n, int nterms) {
+    if ((dim != 2 && dim != 3) || n < 0 || nterms < 0) return 0;
     const int64_t nred = (n + kRedThreads - 1) / kRedThreads;
-    return aligned_sum({(size_t)(nred > 0 ? nred : 1) * (nterms > 0 ? nterms : 1) * 8,
-                        (size_t)(nnz > 0 ? nnz : 1) * sizeof(double), (size_t)(n > 0 ? n : 1) * sizeof(double),
-                        (size_t)(n > 0 ? n : 1) * sizeof(double)});
+    const size_t n1 = (size_t)(n > 0 ? n : 1);
+    const int ns = dim == 3 ? 9 : 3, npairs = dim == 3 ? 6 : 3;
+    return aligned_sum({(size_t)(nred > 0 ? nred : 1) * (nterms > 0 ? nterms : 1) * 8, n1 * ns * sizeof(double),
+                        n1 * npairs * sizeof(double), n1 * sizeof(double), n1 * sizeof(double),
+                        (size_t)(wide_list_len(n) + kWideList) * 4});
 }
 
 extern "C" int vct_apply_ops_adjoint_r2(const vct_nlist* nl, const double* pos_sorted, const double* vol_sorted,
@@ -1096,22 +1211,23 @@ extern "C" int vct_apply_ops_adjoint_r2(const vct_nlist* nl, const double* pos_s
         }
         return VCT_OK;
     }
-    if (!pos_sorted || !vol_sorted || !state64 || !proj || !phi || !u || !nl->col16 || !nl->col_t) return VCT_E_ARG;
+    if (!pos_sorted || !vol_sorted || !state64 || !proj || !phi || !u || !nl->col16 || !nl->chunk_win)
+        return VCT_E_ARG;
     if (!dtheta && !dzhat) return VCT_OK;
-    const int64_t nnz = nl->nnz;
-    if (nnz < 0) return VCT_E_ARG;
-    if (!ws || ws_bytes < vct_adjoint_r2_workspace_size(dim, n, nnz, mp.nterms)) return VCT_E_WORKSPACE;
+    if (!ws || ws_bytes < vct_adjoint_r2_workspace_size(dim, n, mp.nterms)) return VCT_E_WORKSPACE;
     Carver cv(ws, ws_bytes);
     const int64_t nred = (n + kRedThreads - 1) / kRedThreads;
     double* partials = cv.take<double>((size_t)nred * (mp.nterms > 0 ? mp.nterms : 1));
-    double* wbuf = cv.take<double>((size_t)(nnz > 0 ? nnz : 1));
-    double* rowsum = cv.take<double>((size_t)n);
+    double* partial = cv.take<double>((size_t)n * (dim == 3 ? 9 : 3));
+    double* r2h = cv.take<double>((size_t)n * (dim == 3 ? 6 : 3));
+    double* r2b = cv.take<double>((size_t)n);
     double* gz = cv.take<double>((size_t)n);
+    int32_t* wide = cv.take<int32_t>((size_t)(wide_list_len(n) + kWideList));
     const int64_t ncols = dim == 3 ? g.nc[0] * g.nc[1] : g.nc[0];
     AdjArgs a;
     memset(&a, 0, sizeof(a));
     a.n = n; a.invR = 1.0 / nl->R; a.g = g; a.pos = pos_sorted; a.vol = vol_sorted; a.state = state64; a.u = u;
-    a.proj = proj; a.row_ptr = nl->row_ptr; a.col16 = nl->col16; a.col_t = nl->col_t; a.cs = nl->cell_start;
+    a.proj = proj; a.row_ptr = nl->row_ptr; a.col16 = nl->col16; a.cs = nl->cell_start;
     a.cstart = nl->chunk_start; a.cinfo = reinterpret_cast<const int4*>(nl->chunk_info);
     a.cwin = nl->chunk_win;
     a.nchunks = nl->chunk_off + ncols;
@@ -1126,16 +1242,16 @@ extern "C" int vct_apply_ops_adjoint_r2(const vct_nlist* nl, const double* pos_s
     a.r_xz = dim == 3 ? rh + 4 : rh + 2;
     a.r_yz = dim == 3 ? rh + 5 : -1;
     a.nrows = n_out_rows(dim, out_mask);
-    a.wbuf = wbuf; a.rowsum = rowsum; a.phi = phi; a.dzhat = dzhat;
+    a.partial = partial; a.wide = wide; a.phi = phi; a.dzhat = dzhat;
     const int64_t cap = ncols + n / kChunk + 1;
     if (dim == 2)
         st = (kernel == VCT_KERNEL_WENDLAND_C2)
-                 ? launch_r2<2, VCT_KERNEL_WENDLAND_C2>(a, cap, mp, gz, dtheta, partials, s)
-                 : launch_r2<2, VCT_KERNEL_CUBIC_SPLINE>(a, cap, mp, gz, dtheta, partials, s);
+                 ? launch_r2<2, VCT_KERNEL_WENDLAND_C2>(a, cap, mp, gz, dtheta, partials, r2h, r2b, s)
+                 : launch_r2<2, VCT_KERNEL_CUBIC_SPLINE>(a, cap, mp, gz, dtheta, partials, r2h, r2b, s);
     else
         st = (kernel == VCT_KERNEL_WENDLAND_C2)
-                 ? launch_r2<3, VCT_KERNEL_WENDLAND_C2>(a, cap, mp, gz, dtheta, partials, s)
-                 : launch_r2<3, VCT_KERNEL_CUBIC_SPLINE>(a, cap, mp, gz, dtheta, partials, s);
+                 ? launch_r2<3, VCT_KERNEL_WENDLAND_C2>(a, cap, mp, gz, dtheta, partials, r2h, r2b, s)
+                 : launch_r2<3, VCT_KERNEL_CUBIC_SPLINE>(a, cap, mp, gz, dtheta, partials, r2h, r2b, s);
     return st;
 }
 

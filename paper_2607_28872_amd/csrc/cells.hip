@@ -640,7 +640,10 @@ constexpr int kTSlots = 16;
 __global__ __launch_bounds__(256) void k_col_transpose(int64_t n, const int64_t* __restrict__ row_ptr,
                                                        const int32_t* __restrict__ col, int32_t* __restrict__ col_t,
                                                        int32_t* __restrict__ miss) {
-    const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kTLanes;
+    // consecutive particles on one XCD: the rows a search reads are those of
+    // nearby particles, which then stay in that XCD's L2
+    const int64_t blk = xcd_tile(blockIdx.x, gridDim.x);
+    const int64_t i = (blk * blockDim.x + threadIdx.x) / kTLanes;
     const int lane = threadIdx.x % kTLanes;
     if (i >= n) return;
     const int64_t rb = row_ptr[i], re = row_ptr[i + 1];

@@ -140,7 +140,7 @@ def lib():
         L.vct_map_alpha.restype = C.c_int
         L.vct_map_alpha.argtypes = [C.c_int, _i64, _vp, C.POINTER(vct_map), _vp, _vp]
         L.vct_adjoint_r2_workspace_size.restype = _sz
-        L.vct_adjoint_r2_workspace_size.argtypes = [C.c_int, _i64, _i64, C.c_int]
+        L.vct_adjoint_r2_workspace_size.argtypes = [C.c_int, _i64, C.c_int]
         L.vct_apply_ops_adjoint_r2.restype = C.c_int
         L.vct_apply_ops_adjoint_r2.argtypes = [_nlp, _vp, _vp, C.c_int, _vp, C.c_uint32, C.POINTER(vct_map), _vp,
                                                _vp, _vp, _vp, _vp, _vp, _sz, _vp]
@@ -568,13 +568,13 @@ class Geometry:
 
     def adjoint_r2(self, phi_sorted, u_sorted, proj, want_dzhat=False):
         """dtheta (and d loss / d z^, sorted) with physical positions fixed;
-        needs keep_col (the transposed-entry map) and a state whose mask holds
-        LAP, PGRAD and PHESS; proj is the FP64 apply output (1, n, n_out)."""
+        needs a state whose mask holds LAP, PGRAD and PHESS; proj is the FP64
+        apply output (1, n, n_out)."""
         import torch
         nt = self.cmap.nterms
         dth = torch.empty(max(nt, 1), dtype=torch.float64, device=self.device)
         dz = torch.empty(max(self.n, 1), dtype=torch.float64, device=self.device) if want_dzhat else None
-        ws = _bytes(lib().vct_adjoint_r2_workspace_size(self.dim, self.n, self.nnz, nt), self.device)
+        ws = _bytes(lib().vct_adjoint_r2_workspace_size(self.dim, self.n, nt), self.device)
         vct_apply_ops_adjoint_r2(self.nl, self.pos, self.vol, self.kernel, self.state64, self.mask, self.cmap, proj,
                                  phi_sorted, u_sorted, dth, dz, ws)
         return dth[:nt], (dz[: self.n] if dz is not None else None)

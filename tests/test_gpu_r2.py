@@ -67,7 +67,7 @@ def _gpu_r2(w, g, phys, ms=None):
     """dtheta (all terms) and d loss / d z^ (original order) on the GPU."""
     ms = w.mapspec if ms is None else ms
     pos = _project_gpu(phys, ms)
-    geo = vct.Geometry(pos, w.vol, w.lo, w.hi, w.R, w.kernel, device=DEV, keep_col=True)
+    geo = vct.Geometry(pos, w.vol, w.lo, w.hi, w.R, w.kernel, device=DEV, keep_col=False)
     geo.moments(ms, MASK)
     phi = geo.sorted_field(w.phi[0])
     proj = geo.apply(phi)
