@@ -490,7 +490,9 @@ __global__ __launch_bounds__(kAThreads, 2) void k_r2_prep(AdjArgs A, double* __r
 // stays below 2^63; integer sums do not depend on the order of arrival, so
 // the result has the same bits on every run.  The total is converted once to
 // FP64 and scaled back.  The resolution 2^-k is at most 2^-52 d_max M, about
-// one FP64 rounding of a sum of d_max terms of size M.
+// one FP64 rounding of a sum of d_max terms of size M.  (A coarser 2^-50 M,
+// which a one-instruction rounding would allow, loses terms far below the
+// bound systematically: the R2 sums then drift by parts in 1e10.)
 //
 // Bound: with r~ = r/R (|r~| < 1 inside the support), |q~_p| <= |r~|^2 and
 // |r~' L~ r~| <= (sum |L~|) |r~|^2, so for the kernel shape c~ <= c_max
@@ -526,14 +528,16 @@ __device__ __forceinline__ T wave_max(T v) {
 // What the push form sums: the Laplacian weights u_i W_ij of the field
 // adjoint, or the position terms d Phi_ij / d z^_j of reading R2 (these read
 // the field values too, staged with the records).
-// R2 runs half the threads: its rows hold about twice the registers.
+// R2 runs half the threads: its rows hold about twice the registers.  With
+// two waves per SIMD it also reads the range shifts of a piece of entries up
+// front (kShiftWin), which the Laplacian's four waves do not gain from.
 struct PushLap {
     static constexpr int kAcc = kPAcc, kThreads = kPThreads;
-    static constexpr bool kR2 = false;
+    static constexpr bool kR2 = false, kShiftWin = false;
 };
 struct PushR2 {
     static constexpr int kAcc = 3200, kThreads = kPThreads / 2;
-    static constexpr bool kR2 = true;
+    static constexpr bool kR2 = true, kShiftWin = true;
 };
 
 // One column.  FAST = true handles a column whose window fits the
@@ -696,18 +700,50 @@ __device__ __forceinline__ void push_column(const AdjArgs& A, double* __restrict
         for (int64_t eb = lb; eb < le; eb += kPSlots) {
             const int cnt = (int)(le - eb < kPSlots ? le - eb : kPSlots);
             uint32_t cpk[kPSlots / 2];
+            const uint16_t* cp = A.col16 + eb;
 #pragma unroll
             for (int s2 = 0; s2 < kPSlots; ++s2) {
-                const int64_t e = eb + s2;
-                const uint32_t cv = e < le ? (uint32_t)A.col16[e] : 0u;
+                // with kShiftWin the slots past the block's end re-read its
+                // last entry (no branch; the last slot then holds that entry)
+                uint32_t cv;
+                if (OP::kShiftWin) cv = cp[(uint32_t)(s2 < cnt ? s2 : cnt - 1)];
+                else cv = s2 < cnt ? (uint32_t)cp[s2] : 0u;
                 if (s2 % 2 == 0) cpk[s2 / 2] = cv;
                 else cpk[s2 / 2] |= cv << 16;
+            }
+            // FAST: the shifts of the ranges of the piece's first entry and the
+            // three after it, read together; a piece that reaches further (a
+            // few in a thousand) moves the cursor entry by entry instead
+            int b1 = 0, b2 = 0, b3 = 0, h0 = 0, h1 = 0, h2 = 0, h3 = 0;
+            bool fastp = false;
+            if (FAST && OP::kShiftWin) {
+                const int tf = (int)(cpk[0] & 0xffffu), tl = (int)(cpk[kPSlots / 2 - 1] >> 16);   // first, last
+                while (tf >= nxt) {
+                    ++r;
+                    nxt = s_off[cb][r + 1];
+                    sh = s_sh[cb][r];
+                }
+                auto off_at = [&](int m) { return s_off[cb][r + m < kMaxRanges ? r + m : kMaxRanges]; };
+                auto sh_at = [&](int m) { return s_sh[cb][r + m < kMaxRanges - 1 ? r + m : kMaxRanges - 1]; };
+                b1 = nxt; b2 = off_at(2); b3 = off_at(3);
+                h0 = sh; h1 = sh_at(1); h2 = sh_at(2); h3 = sh_at(3);
+                fastp = tl < off_at(4);
             }
             // fully unrolled: the slots past the block's end are masked
 #pragma unroll
             for (int s2 = 0; s2 < kPSlots; ++s2) {
                 if (s2 < cnt) {
-                    const int tg = column_offset((int)((cpk[s2 / 2] >> (16 * (s2 % 2))) & 0xffffu));
+                    const int t = (int)((cpk[s2 / 2] >> (16 * (s2 % 2))) & 0xffffu);
+                    int tg;
+                    if (FAST && OP::kShiftWin) {
+                        int hs = h0;
+                        hs = t >= b1 ? h1 : hs;
+                        hs = t >= b2 ? h2 : hs;
+                        hs = t >= b3 ? h3 : hs;
+                        tg = fastp ? t + hs : column_offset(t);
+                    } else {
+                        tg = column_offset(t);
+                    }
                     const int tc = tg - t0;
                     const bool here = FAST || (unsigned)tc < (unsigned)tn;
                     if (here || self_in) {
