@@ -200,6 +200,26 @@ int vct_timing_count(void);
  * a bad index or a NULL pointer.                                              */
 int vct_timing_get(int idx, const char** name, int64_t* launches, double* total_ms);
 
+/* ---------------------------------------------------------------- device checks */
+
+/* A debug build of the library (compiled with VCT_DEVICE_CHECKS=1) checks on
+ * the device the indices its kernels derive from the neighbour data: window
+ * offsets against their window (col16 of every entry point that reads it),
+ * staged neighbour offsets against the staging capacity, and the push form's
+ * accumulator indices against the column window.  A failed check sets its bit
+ * (below) and the index is replaced by 0, which stays in bounds, so every
+ * kernel still runs to its end; the outputs are then meaningless.
+ * vct_device_checks waits for the device (SYNC), ORs the bits set since the
+ * previous call into *bits and clears them.  Returns 1 for a checked build, 0
+ * for a release build (*bits = 0: nothing is checked), or a negative status.
+ * Not meant for concurrent use with running work.  Host only.                 */
+enum {
+    VCT_CHECK_WINDOW = 1,     /* a window offset at or past the end of its window */
+    VCT_CHECK_CAPACITY = 2,   /* an index past the buffer a count is staged in */
+    VCT_CHECK_ACCUM = 4       /* an accumulator index past the column window */
+};
+int vct_device_checks(uint32_t* bits);
+
 /* ---------------------------------------------------------------- cells */
 
 size_t vct_build_cells_workspace_size(int dim, int64_t n, int64_t ncell);

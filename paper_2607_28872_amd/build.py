@@ -34,15 +34,21 @@ HOST_SAN = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=unde
             "-fno-sanitize-recover=all", "-Xarch_host", "-fno-omit-frame-pointer"]
 
 
-def build(verbose: bool = False, extra=None, sanitize_host: bool = False, out=None) -> str:
+CHECKED_LIB = os.path.join(HERE, "libvct_checked.so")
+
+
+def build(verbose: bool = False, extra=None, sanitize_host: bool = False, out=None, checks: bool = False) -> str:
     """Compile and link the library.  sanitize_host=True builds the host code
     with AddressSanitizer and UndefinedBehaviorSanitizer into `out` (default
     _build/libvct_san.so), for runs with the clang ASan runtime preloaded
-    (VCT_LIB names it to the binding)."""
-    build_dir = os.path.join(BUILD_DIR, "san") if sanitize_host else BUILD_DIR
+    (VCT_LIB names it to the binding).  checks=True builds the debug library
+    with device bounds checks (VCT_DEVICE_CHECKS=1) into `out` (default
+    libvct_checked.so beside libvct.so; VCT_LIB names it to the binding)."""
+    sub = "san" if sanitize_host else "checked" if checks else None
+    build_dir = os.path.join(BUILD_DIR, sub) if sub else BUILD_DIR
     os.makedirs(build_dir, exist_ok=True)
-    extra = list(extra or []) + (HOST_SAN if sanitize_host else [])
-    lib_out = out or (os.path.join(build_dir, "libvct_san.so") if sanitize_host else LIB)
+    extra = list(extra or []) + (HOST_SAN if sanitize_host else []) + (["-DVCT_DEVICE_CHECKS=1"] if checks else [])
+    lib_out = out or (os.path.join(build_dir, "libvct_san.so") if sanitize_host else CHECKED_LIB if checks else LIB)
 
     def compile_one(src):
         obj = os.path.join(build_dir, os.path.splitext(src)[0] + ".o")

@@ -128,9 +128,9 @@ __global__ __launch_bounds__(kAThreads, 2) void k_adjoint_weights(AdjArgs A) {
             else cpk[s / 2] |= c << 16;
         }
     }
-    auto cols = [&](int s) -> int { return (int)((cpk[s / 2] >> (16 * (s % 2))) & 0xffffu); };
     __syncthreads();
     const int W = __builtin_amdgcn_readfirstlane(w.off[w.nr]);
+    auto cols = [&](int s) -> int { return dcheck((int)((cpk[s / 2] >> (16 * (s % 2))) & 0xffffu), W, kChkWindow); };
     const bool in_lds = W <= kAWin;
     if (in_lds) {
         // every load of a thread is issued before its first LDS store
@@ -152,6 +152,7 @@ __global__ __launch_bounds__(kAThreads, 2) void k_adjoint_weights(AdjArgs A) {
     }
     __syncthreads();
     auto fetch = [&](int t) -> double4 {
+        t = dcheck(t, W, kChkWindow);
         if (in_lds) return sd[t];
         const int64_t j = window_global<D>(w, t);
         return make_double4(A.pos[j], A.pos[n + j], D == 3 ? A.pos[2 * n + j] : 0.0, A.vol[j]);
@@ -386,6 +387,7 @@ __global__ __launch_bounds__(kAThreads, 2) void k_r2_prep(AdjArgs A, double* __r
         }
     __syncthreads();
     auto fetch = [&](int t, double& ph) -> double4 {
+        t = dcheck(t, W, kChkWindow);
         if (in_lds) {
             ph = sf[t];
             return sd[t];
@@ -744,6 +746,7 @@ __device__ __forceinline__ void push_column(const AdjArgs& A, double* __restrict
                     } else {
                         tg = column_offset(t);
                     }
+                    tg = dcheck(tg, Wc, kChkAccum);
                     const int tc = tg - t0;
                     const bool here = FAST || (unsigned)tc < (unsigned)tn;
                     if (here || self_in) {
@@ -1106,6 +1109,8 @@ __global__ void k_zero_f64(double* p, int64_t cnt) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < cnt) p[i] = 0.0;
 }
+
+VCT_CHECKS_TU(checks_adjoint)
 
 }  // namespace vct
 

@@ -178,6 +178,8 @@ void timing_end(int rec, hipStream_t s) {
     g_pending[rec].closed = hipEventRecord(g_pending[rec].b, s) == hipSuccess;
 }
 
+VCT_CHECKS_TU(checks_api)
+
 }  // namespace vct
 
 using namespace vct;
@@ -209,6 +211,29 @@ extern "C" int vct_timing_get(int idx, const char** name, int64_t* launches, dou
     *launches = g_agg[idx].launches;
     *total_ms = g_agg[idx].ms;
     return VCT_OK;
+}
+
+namespace vct {
+int checks_adjoint(uint32_t*);
+int checks_apply(uint32_t*);
+int checks_cells(uint32_t*);
+int checks_isph(uint32_t*);
+int checks_jbar(uint32_t*);
+int checks_moments(uint32_t*);
+int checks_ppe(uint32_t*);
+}  // namespace vct
+
+extern "C" int vct_device_checks(uint32_t* bits) {
+    if (!bits) return VCT_E_ARG;
+    *bits = 0;
+    VCT_HIP_CHECK(hipDeviceSynchronize());
+    int (*const take[])(uint32_t*) = {checks_api, checks_adjoint, checks_apply, checks_cells,
+                                      checks_isph, checks_jbar, checks_moments, checks_ppe};
+    for (auto f : take) {
+        const int st = f(bits);
+        if (st) return st;
+    }
+    return VCT_DEVICE_CHECKS ? 1 : 0;
 }
 
 extern "C" const char* vct_status_string(int status) {

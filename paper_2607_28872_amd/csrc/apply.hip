@@ -378,7 +378,9 @@ __global__ __launch_bounds__(ApplyCfg<T>::threads, ApplyCfg<T>::waves) void k_ap
     // register slots: entry rb + lane + kLanes s; an empty slot repeats the
     // row's first entry (offset 0 for an empty row) and is masked out
     const uint16_t* scol = reinterpret_cast<const uint16_t*>(scol4);
-    auto col_at = [&](int64_t e) -> int { return col_lds ? (int)scol[e - cb8] : (int)A.col16[e]; };
+    auto col_at = [&](int64_t e) -> int {
+        return dcheck(col_lds ? (int)scol[e - cb8] : (int)A.col16[e], W, kChkWindow);
+    };
     // (two 16-bit offsets per register)
     uint32_t cpk[(kS + 1) / 2];
     int nslot = 0;
@@ -396,7 +398,7 @@ __global__ __launch_bounds__(ApplyCfg<T>::threads, ApplyCfg<T>::waves) void k_ap
             else cpk[s / 2] |= c << 16;
         }
     }
-    auto cols = [&](int s) -> int { return (int)((cpk[s / 2] >> (16 * (s % 2))) & 0xffffu); };
+    auto cols = [&](int s) -> int { return dcheck((int)((cpk[s / 2] >> (16 * (s % 2))) & 0xffffu), W, kChkWindow); };
     const int64_t tail = rb + (int64_t)kLanes * kS;
     const T invR = T(A.invR);
     for (int f = 0; f < A.nf; ++f) {
@@ -596,6 +598,8 @@ static ApplyArgs<S> make_args(const vct_nlist* nl, const Grid& g, int nf, const 
     a.out = out;
     return a;
 }
+
+VCT_CHECKS_TU(checks_apply)
 
 }  // namespace vct
 

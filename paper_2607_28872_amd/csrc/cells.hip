@@ -515,12 +515,14 @@ __global__ __launch_bounds__(512) void k_nb_compact(Grid g, const int64_t* __res
     }
     __syncthreads();
     for (int64_t e = e0 + threadIdx.x; e < e1; e += kT) {
-        const int r = rowof[e - e0];
-        const uint16_t t = srow[r * kStage + (int)(e - rp[r])];
+        const int r = rowof[dcheck((int)(e - e0), kChunk * kStage, kChkCapacity)];
+        const uint16_t t = srow[r * kStage + dcheck((int)(e - rp[r]), kStage, kChkCapacity)];
         if (col16) col16[e] = t;
         if (col) col[e] = (int32_t)window_global<D>(w, t);
     }
 }
+
+VCT_CHECKS_TU(checks_cells)
 
 }  // namespace vct
 

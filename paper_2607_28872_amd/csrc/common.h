@@ -31,6 +31,56 @@ void set_last_error(hipError_t e);
 
 inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
+// ------------------------------------------------------------------ device checks
+
+// A build with VCT_DEVICE_CHECKS=1 (the package's build with checks=True)
+// bounds-checks the indices that kernels derive from the neighbour data: a
+// failed check sets a bit of its translation unit's check word and replaces
+// the index by 0, which stays inside the buffer, so the kernel still runs to
+// its end; vct_device_checks reads and clears the words.  Other builds
+// compile the checks out.
+#ifndef VCT_DEVICE_CHECKS
+#define VCT_DEVICE_CHECKS 0
+#endif
+enum : uint32_t {
+    kChkWindow = VCT_CHECK_WINDOW,       // a window offset at or past the end of its window
+    kChkCapacity = VCT_CHECK_CAPACITY,   // an index past the buffer a count is staged in
+    kChkAccum = VCT_CHECK_ACCUM,         // an accumulator past the column window (push form)
+};
+#if VCT_DEVICE_CHECKS
+[[maybe_unused]] static __device__ unsigned int g_checks;
+#endif
+
+// idx when 0 <= idx < lim; else, in a checked build, flag `bit` and return 0
+template <class I, class L>
+__device__ __forceinline__ I dcheck(I idx, L lim, uint32_t bit) {
+#if VCT_DEVICE_CHECKS
+    if (!((long long)idx >= 0 && (long long)idx < (long long)lim)) {
+        atomicOr(&g_checks, bit);
+        return I(0);
+    }
+#endif
+    return idx;
+}
+
+// Host: OR this translation unit's check word into *out and clear it (after
+// the device has finished the work that may set it).
+#if VCT_DEVICE_CHECKS
+#define VCT_CHECKS_TU(NAME)                                                                \
+    int NAME(uint32_t* out) {                                                              \
+        unsigned int v = 0, z = 0;                                                         \
+        VCT_HIP_CHECK(hipMemcpyFromSymbol(&v, HIP_SYMBOL(g_checks), sizeof v, 0,          \
+                                          hipMemcpyDeviceToHost));                         \
+        VCT_HIP_CHECK(hipMemcpyToSymbol(HIP_SYMBOL(g_checks), &z, sizeof z, 0,            \
+                                        hipMemcpyHostToDevice));                           \
+        *out |= v;                                                                         \
+        return VCT_OK;                                                                     \
+    }
+#else
+#define VCT_CHECKS_TU(NAME) \
+    int NAME(uint32_t*) { return VCT_OK; }
+#endif
+
 // ------------------------------------------------------------------ launch timing
 
 // While launch timing is on (vct_timing_enable), every launch is bracketed by

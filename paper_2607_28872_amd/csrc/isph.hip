@@ -127,7 +127,7 @@ __global__ __launch_bounds__(kZThreads, 4) void k_ops0(ZeroArgs A, MapParams mp)
 #pragma unroll
         for (int p = 0; p < m; ++p) S[p] = 0.0;
         for (int64_t e = rb + lane; e < re; e += kZLanes) {
-            const int t = A.col16[e];
+            const int t = dcheck((int)A.col16[e], W, kChkWindow);
             int64_t j = 0;
             const double4 q = window_record<D>(A, w, sd, in_lds, t, j);
             const double fj = in_lds ? sf[t] : F[j];
@@ -212,7 +212,7 @@ __global__ __launch_bounds__(kZThreads, 4) void k_grad_sum(ZeroArgs A, MapParams
     for (int a = 0; a < D; ++a) acc[a] = 0.0;
     const int64_t rb = valid ? A.row_ptr[ii] : 0, re = valid ? A.row_ptr[ii + 1] : 0;
     for (int64_t e = rb + lane; e < re; e += kZLanes) {
-        const int t = A.col16[e];
+        const int t = dcheck((int)A.col16[e], W, kChkWindow);
         int64_t j = 0;
         const double4 q = window_record<D>(A, w, sd, in_lds, t, j);
         double2 pr;
@@ -277,6 +277,8 @@ static int64_t zero_cap(const vct_nlist* nl, const Grid& g) {
     const int64_t ncols = nl->dim == 3 ? g.nc[0] * g.nc[1] : g.nc[0];
     return ncols + nl->n / kChunk + 1;
 }
+
+VCT_CHECKS_TU(checks_isph)
 
 }  // namespace vct
 

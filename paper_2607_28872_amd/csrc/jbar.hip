@@ -126,7 +126,7 @@ __device__ __forceinline__ void row_geometry(const JbarArgs& A, const WindowT<D>
         c[s] = 0.0;
         jj[s] = -1;
         if (e < re) {
-            const int t = A.col16[e];
+            const int t = dcheck((int)A.col16[e], cw.off[cw.nr], kChkWindow);
             int r = 0;
 #pragma unroll
             for (int k = 1; k < kMaxRanges; ++k)
@@ -290,6 +290,7 @@ __device__ __forceinline__ void jbar_cell_pipelined(const JbarArgs& A, int64_t p
     // range's two shifts are looked up in LDS
     auto decode = [&](int k, int t, int64_t& j, int64_t& jl) {
         const WindowT<D>& w = cwa[k];
+        t = dcheck(t, w.off[w.nr], kChkWindow);
         int r = 0;
 #pragma unroll
         for (int q = 1; q < kMaxRanges; ++q) r += (q < w.nr && t >= w.off[q]) ? 1 : 0;
@@ -508,6 +509,8 @@ __global__ __launch_bounds__(256) void k_map_project(int dim, int64_t n, const d
     for (int a = 0; a < dim - 1; ++a) proj[(int64_t)a * n + i] = phys[(int64_t)a * n + i];
     proj[(int64_t)(dim - 1) * n + i] = c.alpha * (z + c.beta);
 }
+
+VCT_CHECKS_TU(checks_jbar)
 
 }  // namespace vct
 

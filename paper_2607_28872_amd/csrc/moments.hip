@@ -165,9 +165,9 @@ __global__ __launch_bounds__(kMThreads, VCT_SWEEP_WAVES) void k_moment_sweeps(Sw
             else cpk[s / 2] |= c << 16;
         }
     }
-    auto cols = [&](int s) -> int { return (int)((cpk[s / 2] >> (16 * (s % 2))) & 0xffffu); };
     __syncthreads();
     const int W = __builtin_amdgcn_readfirstlane(w.off[w.nr]);
+    auto cols = [&](int s) -> int { return dcheck((int)((cpk[s / 2] >> (16 * (s % 2))) & 0xffffu), W, kChkWindow); };
     const bool in_lds = W <= kMWin;
     if (in_lds) {
         // every load of a thread is issued before its first LDS store
@@ -189,6 +189,7 @@ __global__ __launch_bounds__(kMThreads, VCT_SWEEP_WAVES) void k_moment_sweeps(Sw
     }
     __syncthreads();
     auto fetch = [&](int t) -> double4 {
+        t = dcheck(t, W, kChkWindow);
         if (in_lds) return sd[t];
         const int64_t j = window_global<D>(w, t);
         return make_double4(A.pos[j], A.pos[n + j], D == 3 ? A.pos[2 * n + j] : 0.0, A.vol[j]);
@@ -574,6 +575,8 @@ static int launch_moments(const vct_nlist* nl, const Grid& g, const double* pos,
     VCT_LAUNCH_CHECK();
     return VCT_OK;
 }
+
+VCT_CHECKS_TU(checks_moments)
 
 }  // namespace vct
 

@@ -126,7 +126,7 @@ __global__ __launch_bounds__(kQThreads, 4) void k_ppe_first(PpeArgs A, MapParams
     double ksum = 0.0;
     const int64_t rb = valid ? A.row_ptr[ii] : 0, re = valid ? A.row_ptr[ii + 1] : 0;
     for (int64_t e = rb + lane; e < re; e += kQLanes) {
-        const int t = A.col16[e];
+        const int t = dcheck((int)A.col16[e], W, kChkWindow);
         double4 q;
         double fj[NC];
         if (in_lds) {
@@ -260,7 +260,7 @@ __global__ __launch_bounds__(kQThreads, 2) void k_ppe_diag(PpeArgs A) {
     double s = 0.0;
     const int64_t rb = valid ? A.row_ptr[ii] : 0, re = valid ? A.row_ptr[ii + 1] : 0;
     for (int64_t e = rb + lane; e < re; e += kQLanes) {
-        const int t = A.col16[e];
+        const int t = dcheck((int)A.col16[e], W, kChkWindow);
         double4 q;
         if (in_lds) {
             q = sd[t];
@@ -500,6 +500,8 @@ static int launch_first(int dim, int kernel, const PpeArgs& a, const MapParams& 
     VCT_LAUNCH_CHECK();
     return VCT_OK;
 }
+
+VCT_CHECKS_TU(checks_ppe)
 
 }  // namespace vct
 

@@ -147,6 +147,7 @@ __device__ __forceinline__ void window_load(const int32_t* __restrict__ tab, uin
 // global sorted index of window offset t
 template <int D>
 __device__ __forceinline__ int64_t window_global(const WindowT<D>& w, int t) {
+    t = dcheck(t, w.off[w.nr], kChkWindow);
     int r = 0;
 #pragma unroll
     for (int k = 1; k < kMaxRanges; ++k)

@@ -93,6 +93,8 @@ def lib():
         L.vct_chunk_capacity.argtypes = [C.c_int, _i64, _i64]
         L.vct_timing_enable.restype = C.c_int
         L.vct_timing_enable.argtypes = [C.c_int]
+        L.vct_device_checks.restype = C.c_int
+        L.vct_device_checks.argtypes = [C.POINTER(C.c_uint32)]
         L.vct_timing_reset.restype = None
         L.vct_timing_reset.argtypes = []
         L.vct_timing_count.restype = C.c_int
@@ -263,6 +265,20 @@ def make_nlist(dim, n, ncell, lo, hi, R, cell_start, chunk_off, chunk_start, chu
 
 def vct_timing_enable(on):
     return lib().vct_timing_enable(int(bool(on)))
+
+
+VCT_CHECK_WINDOW, VCT_CHECK_CAPACITY, VCT_CHECK_ACCUM = 1, 2, 4
+
+
+def vct_device_checks():
+    """(checked, bits): whether the loaded library is the debug build with
+    device bounds checks, and the check bits set since the previous call
+    (cleared by this call; waits for the device)."""
+    bits = C.c_uint32(0)
+    st = lib().vct_device_checks(C.byref(bits))
+    if st < 0:
+        _check("vct_device_checks", st)
+    return bool(st), int(bits.value)
 
 
 def vct_timing_reset():

@@ -31,6 +31,21 @@ def test_exports_every_declared_symbol(L):
         assert hasattr(L, s), s
 
 
+def test_checked_build_exports_the_same_symbols(L):
+    """The debug library with device bounds checks (built beside libvct.so)
+    has the same C ABI; the checks query rejects a NULL pointer on the host."""
+    from paper_2607_28872_amd import build
+    if not os.path.exists(build.CHECKED_LIB):
+        pytest.fail("libvct_checked.so is not built (run __graft_entry__.build())")
+    Lc = C.CDLL(build.CHECKED_LIB)
+    for s in _declared_symbols():
+        assert hasattr(Lc, s), s
+    for lib_ in (L, Lc):
+        lib_.vct_device_checks.restype = C.c_int
+        lib_.vct_device_checks.argtypes = [C.c_void_p]
+        assert lib_.vct_device_checks(None) == vct.VCT_E_ARG
+
+
 def test_status_strings(L):
     for st in (0, 1, -1, -2, -3, -4, -5, -6):
         assert vct.status_string(st).startswith("VCT_")
