@@ -377,8 +377,11 @@ def test_adjoint_with_pz_rows_gives_the_same_bits():
 
 
 @pytest.mark.parametrize("form", ["transposed", "push"])
-def test_adjoint_against_oracle(form):
+@pytest.mark.parametrize("kernel", [I.KERNEL_WENDLAND_C2, I.KERNEL_CUBIC_SPLINE])
+def test_adjoint_against_oracle(form, kernel):
     w = I.small("sigma3d-adj")
+    if kernel == I.KERNEL_CUBIC_SPLINE:   # the spline's support and its own term bound in the push form
+        w.kernel, w.R = kernel, 2.4 * w.dx
     mask = vct.VCT_OUT_LAP | vct.VCT_OUT_PGRAD | vct.VCT_OUT_PHESS
     g = vct.Geometry(w.pos, w.vol, w.lo, w.hi, w.R, w.kernel, device=DEV, keep_col=(form == "transposed"))
     g.moments(w.mapspec, mask)
