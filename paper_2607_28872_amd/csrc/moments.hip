@@ -194,12 +194,17 @@ __global__ __launch_bounds__(kMThreads, VCT_SWEEP_WAVES) void k_moment_sweeps(Sw
         const int64_t j = window_global<D>(w, t);
         return make_double4(A.pos[j], A.pos[n + j], D == 3 ? A.pos[2 * n + j] : 0.0, A.vol[j]);
     };
-    // r~ and its pair products q~ (q~ holds the squares first, so |r~|^2 is
-    // their sum)
+    // The offsets r = r^_j - r^_i and their pair products q, unscaled (q
+    // holds the squares first, so |r|^2 is their sum): every sum below is a
+    // homogeneous polynomial in r, so the scaling by 1/R of the moment
+    // formulation (r~ = r / R) is applied once to each total instead of to
+    // every offset -- A~ = A / R^2, B~ = B / R^3, C~ = C / R, E~ = E / R^2 (in
+    // sweep 2 the weight V F~ = V c~ (r~' L~ r~) / |r~|^4 equals R^2 times
+    // V c~ (r' L~ r) / |r|^4).
     auto geom = [&](const double4& q, double (&r)[D], double (&qv)[Dm::m], double& q2) {
-        r[0] = (q.x - xi[0]) * A.invR;
-        r[1] = (q.y - xi[1]) * A.invR;
-        if (D == 3) r[D - 1] = (q.z - xi[2]) * A.invR;
+        r[0] = q.x - xi[0];
+        r[1] = q.y - xi[1];
+        if (D == 3) r[D - 1] = q.z - xi[2];
 #pragma unroll
         for (int p = 0; p < Dm::m; ++p) qv[p] = r[pair_a<D>(p)] * r[pair_b<D>(p)];
         q2 = qv[0];
@@ -246,11 +251,12 @@ __global__ __launch_bounds__(kMThreads, VCT_SWEEP_WAVES) void k_moment_sweeps(Sw
     // The weighted offsets wr = wgt r~ are formed once per pair; the pair and
     // cubic sums are then one multiply-add each (wr times r~ or q~), not a
     // monomial product followed by a weighted multiply-add.
+    double q2min = 1.0;   // a zero offset marks a duplicate (tested after the sweep)
     sweep([&](const double4& q) {
         double r[D], q2, qv[Dm::m], wr[D];
         geom(q, r, qv, q2);
-        if (q2 == 0.0) fl |= VCT_FLAG_DUPLICATE;
-        const double wgt = q.w * kernel_shape<KERNEL>(vsqrt(q2));
+        q2min = fmin(q2min, q2);
+        const double wgt = q.w * kernel_shape<KERNEL>(vsqrt(q2) * A.invR);
 #pragma unroll
         for (int a = 0; a < D; ++a) wr[a] = wgt * r[a];
 #pragma unroll
@@ -259,10 +265,12 @@ __global__ __launch_bounds__(kMThreads, VCT_SWEEP_WAVES) void k_moment_sweeps(Sw
         for (int t = 0; t < Dm::n3; ++t)
             B[t] += wr[mono_comp<D, 3>(t, 0)] * qv[sym_index<D>(mono_comp<D, 3>(t, 1), mono_comp<D, 3>(t, 2))];
     }, std::true_type{});
+    if (q2min == 0.0) fl |= VCT_FLAG_DUPLICATE;
+    const double invR2 = A.invR * A.invR;
 #pragma unroll
-    for (int p = 0; p < Dm::nL; ++p) Am[p] = group_sum(Am[p], kMLanes);
+    for (int p = 0; p < Dm::nL; ++p) Am[p] = group_sum(Am[p], kMLanes) * invR2;
 #pragma unroll
-    for (int t = 0; t < Dm::n3; ++t) B[t] = group_sum(B[t], kMLanes);
+    for (int t = 0; t < Dm::n3; ++t) B[t] = group_sum(B[t], kMLanes) * (invR2 * A.invR);
     // a non-finite neighbour position or volume makes some sum non-finite
     // (every weight is positive), which is cheaper to test once than per pair
     {
@@ -298,9 +306,9 @@ __global__ __launch_bounds__(kMThreads, VCT_SWEEP_WAVES) void k_moment_sweeps(Sw
         double rLr = 0.0;
 #pragma unroll
         for (int p = 0; p < Dm::nL; ++p) rLr += L2[p] * qv[p];
-        // q = q2 / sqrt(q2) and 1/q^4 = (1/sqrt(q2))^4 from one refined reciprocal square root
+        // |r| = q2 / sqrt(q2) and 1/|r|^4 = (1/sqrt(q2))^4 from one refined reciprocal square root
         const double y = vrsq(q2), y2 = y * y;
-        const double wgt = live ? q.w * kernel_shape<KERNEL>(q2 * y) * rLr * (y2 * y2) : 0.0;
+        const double wgt = live ? q.w * kernel_shape<KERNEL>(q2 * y * A.invR) * rLr * (y2 * y2) : 0.0;
 #pragma unroll
         for (int p = 0; p < Dm::m; ++p) wq[p] = wgt * qv[p];
 #pragma unroll
@@ -312,9 +320,9 @@ __global__ __launch_bounds__(kMThreads, VCT_SWEEP_WAVES) void k_moment_sweeps(Sw
                     qv[sym_index<D>(mono_comp<D, 4>(t, 2), mono_comp<D, 4>(t, 3))];
     }, std::integral_constant<bool, VCT_SWEEP2_AHEAD>{});
 #pragma unroll
-    for (int t = 0; t < Dm::n3; ++t) Cm[t] = group_sum(Cm[t], kMLanes);
+    for (int t = 0; t < Dm::n3; ++t) Cm[t] = group_sum(Cm[t], kMLanes) * A.invR;
 #pragma unroll
-    for (int t = 0; t < Dm::n4; ++t) E[t] = group_sum(E[t], kMLanes);
+    for (int t = 0; t < Dm::n4; ++t) E[t] = group_sum(E[t], kMLanes) * invR2;
 
     // the sums through LDS (the window is no longer needed), then unit-stride
     // stores: thread t writes entries (v, q) with q = t % kChunk
