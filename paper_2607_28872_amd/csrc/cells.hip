@@ -262,12 +262,14 @@ __device__ __forceinline__ bool within_exact(double dx, double dy, double dz, do
     return d2 < R2;
 }
 
-// d2 - lim for an FP32 window record q and the particle's FP32 offsets, the
-// threshold folded into the first multiply-add: each of the three roundings
-// is relative to a partial result no larger than max(d2, lim).
-__device__ __forceinline__ float d2_minus(const float4& q, float f0, float f1, float f2, float lim) {
-    const float ex = q.x - f0, ey = q.y - f1, ez = q.z - f2;
-    return fmaf(ez, ez, fmaf(ey, ey, fmaf(ex, ex, -lim)));
+// d2 - lim for an FP32 window record q (offset from the chunk origin, with
+// |q|^2 in q.w) and the particle's FP32 offset f, expanded as
+// |q|^2 + (|f|^2 - lim) - 2 q . f: c = |f|^2 - lim and m = -2 f per
+// particle, so a candidate costs one add and three multiply-adds.  The
+// expansion's rounding grows with the offsets' size M instead of with d2
+// (bound below, where the band is set).
+__device__ __forceinline__ float d2_minus(const float4& q, float m0, float m1, float m2, float c) {
+    return fmaf(q.x, m0, fmaf(q.y, m1, fmaf(q.z, m2, q.w + c)));
 }
 
 constexpr int kNbWaves = 4;                    // waves per work-group
@@ -320,12 +322,16 @@ __global__ __launch_bounds__(kNbThreads) void k_nb_chunk(int64_t n, const double
     const int64_t i = p0 + pl;
     const bool valid = pl < np;
     const int64_t ii = valid ? i : p0;
-    const double o0 = pos[p0], o1 = pos[n + p0], o2 = (D == 3) ? pos[2 * n + p0] : 0.0;
+    // the chunk origin: its middle particle, which keeps the offsets (and the
+    // rounding of the expanded distance) small
+    const int64_t pm = p0 + (np - 1) / 2;
+    const double o0 = pos[pm], o1 = pos[n + pm], o2 = (D == 3) ? pos[2 * n + pm] : 0.0;
     const double xi0 = pos[ii], xi1 = pos[n + ii], xi2 = (D == 3) ? pos[2 * n + ii] : 0.0;
     // offsets from the chunk origin in FP32 (the same rounding as the records)
     const float f0 = (float)(xi0 - o0), f1 = (float)(xi1 - o1), f2 = (float)(xi2 - o2);
     const float fmax_own = fmaxf(fabsf(f0), fmaxf(fabsf(f1), fabsf(f2)));
-    const double R = sqrt(R2);
+    const float m0 = -2.0f * f0, m1 = -2.0f * f1, m2 = -2.0f * f2;   // exact
+    const float ff = fmaf(f2, f2, fmaf(f1, f1, f0 * f0));
     const int64_t rlo = FILL ? row_ptr[ii] : 0, rlen = FILL ? row_ptr[ii + 1] - rlo : 0;
     __syncthreads();
     const int W = w.off[w.nr];
@@ -360,8 +366,9 @@ __global__ __launch_bounds__(kNbThreads) void k_nb_chunk(int64_t n, const double
             for (int k = 0; k < kRep; ++k) {
                 const int t = threadIdx.x + k * kNbThreads;
                 if (t < sW) {
-                    const float4 q = make_float4((float)(px[k] - o0), (float)(py[k] - o1),
-                                                 D == 3 ? (float)(pz[k] - o2) : 0.0f, 0.0f);
+                    float4 q = make_float4((float)(px[k] - o0), (float)(py[k] - o1),
+                                           D == 3 ? (float)(pz[k] - o2) : 0.0f, 0.0f);
+                    q.w = fmaf(q.z, q.z, fmaf(q.y, q.y, q.x * q.x));
                     win[t] = q;
                     mo = fmaxf(mo, fmaxf(fabsf(q.x), fmaxf(fabsf(q.y), fabsf(q.z))));
                 }
@@ -371,19 +378,27 @@ __global__ __launch_bounds__(kNbThreads) void k_nb_chunk(int64_t n, const double
             if (pl == 0) wmax[wv] = mo;
         }
         __syncthreads();
-        // Absolute bound on the FP32 error of d2: the rounded offsets of each
-        // component (magnitude at most the largest staged or own offset), the
-        // rounding of R^2, and of the FP32 products and sums.
+        // Absolute bound on the FP32 error of t against the exact d2 - R^2,
+        // with M the largest offset component (staged or own) and u = 2^-24:
+        // the rounded offsets, |d2(q, f) - d2| <= 4 sqrt(3) u M |q - f| <=
+        // 24 u M^2; the three roundings of each of |q|^2 and |f|^2 (3 u
+        // 3M^2 each), the rounding of |f|^2 - lim, of the add and of the three
+        // multiply-adds, each relative to a partial result below 12 M^2 + R^2
+        // (57 u M^2 + 5 u R^2 in all); and the rounding of lim to FP32 (u R^2).
+        // 96 u M^2 + 8 u R^2 covers the sum.
         const float mseg = fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3]));
         const double maxoff = (double)fmaxf(mseg, fmax_own);
-        const double margin = 4.0 * (2.0 * R) * (maxoff * 0x1p-23) + R2 * 0x1p-19;
+        const double margin = (96.0 * maxoff * maxoff + 8.0 * R2) * 0x1p-24;
         const float in_lim = (float)(R2 - margin), out_lim = (float)(R2 + margin);
+        const float cf = ff - in_lim;
         // t = d2 - in_lim: t < 0 is a certain hit, 0 <= t <= band is the
         // uncertain band (as unsigned integers, exactly the non-negative t up
         // to band: a negative t has its sign bit set), t > band certainly
-        // lies outside.  band is exact (in_lim and out_lim are within a factor
-        // of two of each other).
-        const float band = out_lim - in_lim;
+        // lies outside.  band = out_lim - in_lim, rounded up if the FP32
+        // difference is inexact (offsets beyond about 240 R).
+        const double band_d = (double)out_lim - (double)in_lim;   // exact in FP64
+        float band = (float)band_d;
+        if ((double)band < band_d) band = nextafterf(band, INFINITY);
         const uint32_t band_u = __float_as_uint(band);
         const int nw = (sW + 31) / 32;
         const int k0 = wv * nw / kNbWaves, k1 = (wv + 1) * nw / kNbWaves;
@@ -397,7 +412,7 @@ __global__ __launch_bounds__(kNbThreads) void k_nb_chunk(int64_t n, const double
             const float4* wp = win + 32 * k;
 #pragma unroll
             for (int u = 0; u < 32; ++u) {
-                const uint32_t t = __float_as_uint(d2_minus(wp[u], f0, f1, f2, in_lim));   // same record, every lane
+                const uint32_t t = __float_as_uint(d2_minus(wp[u], m0, m1, m2, cf));   // same record, every lane
                 bits = __builtin_amdgcn_alignbit(bits, t, 31);
                 amb_any = amb_any || t <= band_u;
             }
@@ -412,12 +427,12 @@ __global__ __launch_bounds__(kNbThreads) void k_nb_chunk(int64_t n, const double
                 // the word's candidates in the band, from the same arithmetic
                 // (the empty asm keeps the compiler from carrying the t of the
                 // loop above over to here), then the exact FP64 predicate
-                float g0 = f0, g1 = f1, g2 = f2;
-                asm volatile("" : "+v"(g0), "+v"(g1), "+v"(g2));
+                float g0 = m0, g1 = m1, g2 = m2, gc = cf;
+                asm volatile("" : "+v"(g0), "+v"(g1), "+v"(g2), "+v"(gc));
                 uint32_t amb = 0u;
 #pragma unroll 1
                 for (int u = 0; u < 32; ++u)
-                    if (__float_as_uint(d2_minus(wp[u], g0, g1, g2, in_lim)) <= band_u) amb |= 1u << u;
+                    if (__float_as_uint(d2_minus(wp[u], g0, g1, g2, gc)) <= band_u) amb |= 1u << u;
                 amb &= keep;
                 while (amb) {
                     const int u = __builtin_ctz(amb);
