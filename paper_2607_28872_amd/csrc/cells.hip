@@ -410,11 +410,25 @@ __global__ __launch_bounds__(kNbThreads) void k_nb_chunk(int64_t n, const double
             uint32_t bits = 0u;
             bool amb_any = false;
             const float4* wp = win + 32 * k;
+            // records read eight at a time, the next eight while the current
+            // ones are tested
+            float4 rec[8], nxt[8];
 #pragma unroll
-            for (int u = 0; u < 32; ++u) {
-                const uint32_t t = __float_as_uint(d2_minus(wp[u], m0, m1, m2, cf));   // same record, every lane
-                bits = __builtin_amdgcn_alignbit(bits, t, 31);
-                amb_any = amb_any || t <= band_u;
+            for (int u = 0; u < 8; ++u) rec[u] = wp[u];   // same record, every lane
+#pragma unroll
+            for (int u0 = 0; u0 < 32; u0 += 8) {
+                if (u0 + 8 < 32) {
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) nxt[u] = wp[u0 + 8 + u];
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const uint32_t t = __float_as_uint(d2_minus(rec[u], m0, m1, m2, cf));
+                    bits = __builtin_amdgcn_alignbit(bits, t, 31);
+                    amb_any = amb_any || t <= band_u;
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) rec[u] = nxt[u];
             }
             bits = __builtin_bitreverse32(bits);
             // drop the tail beyond the segment, the particle itself, idle lanes
