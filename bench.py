@@ -183,7 +183,7 @@ def main():
     nl0 = vct.make_nlist(dim, n, ncell, w.lo, w.hi, w.R, cell_start, chunk_off, chunk_start, chunk_info, row_ptr)
     _, nnz = vct.vct_neighbors(nl0, pos_s, 0, 0, ws_nb)
     col16 = torch.empty(max(nnz, 8), dtype=torch.uint16, device=dev)
-    # the adjoint takes its gather form (no int32 columns, no transposed-entry
+    # the adjoint takes its push form (no int32 columns, no transposed-entry
     # map): the geometry is rebuilt every step, and building the map costs more
     # than it saves in a single adjoint call
     nl = vct.make_nlist(dim, n, ncell, w.lo, w.hi, w.R, cell_start, chunk_off, chunk_start, chunk_info, row_ptr,
