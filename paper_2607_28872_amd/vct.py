@@ -558,7 +558,7 @@ class Geometry:
     def adjoint(self, u_sorted, proj=None, want_dtheta=True):
         """dphi (sorted) and dtheta for the cotangent u of the Laplacian; `proj`
         is the FP64 apply output (1, n, n_out) of the field, needed for dtheta.
-        With keep_col the transposed-map form runs, else the gather form."""
+        With keep_col the transposed-map form runs, else the push form."""
         import torch
         nt = self.cmap.nterms
         dphi = torch.empty(max(self.n, 1), dtype=torch.float64, device=self.device)
