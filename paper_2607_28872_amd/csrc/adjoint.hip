@@ -352,7 +352,8 @@ __device__ __forceinline__ double r2_term(const R2Row<D>& w, const double4& qr, 
 // First sweep per particle (one chunk per work-group, kALanes lanes per
 // particle, window records and field values in LDS):
 //   G_i and H_i = L~ G_i L~, written as r2h[pairs][n];
-//   r2b[i], a bound on |term| / V_j of the row's terms and on nothing else:
+//   r2b[i], a bound on |term| / V_j over the row's terms (the push pass
+//   multiplies the largest of its column by the window's largest volume):
 //   with q >= q_min over the row, |r~| < 1, cmax >= c~, dcmax >= |dc~/dq|,
 //   L1 = sum |L2|, Pa1 = sum |P_a|, Ps1 = sum |P_s| (|P_s . q~| <= Ps1 q^2):
 //     |W| / V    <= cmax (Pa1 + L1 Ps1)
