@@ -155,12 +155,40 @@ __global__ void k_cell_scatter(int64_t n, const int32_t* __restrict__ keys,
 }
 
 // The scatter leaves each cell's particles in arbitrary order; sorting every
-// cell's slice by original index makes the result deterministic.
+// cell's slice by original index makes the result deterministic.  A slice of
+// at most kSortReg entries is sorted in registers by a bitonic network (the
+// slots past its end hold INT_MAX and stay at the end); a longer one by
+// insertion in place.
+constexpr int kSortReg = 64;
 __global__ void k_cell_sort(int64_t ncell, const int64_t* __restrict__ cell_start,
                             int32_t* __restrict__ perm) {
     int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= ncell) return;
     int64_t b = cell_start[c], e = cell_start[c + 1];
+    if (e - b <= kSortReg) {
+        const int len = (int)(e - b);
+        int v[kSortReg];
+#pragma unroll
+        for (int k = 0; k < kSortReg; ++k) v[k] = k < len ? perm[b + k] : INT_MAX;
+#pragma unroll
+        for (int size = 2; size <= kSortReg; size <<= 1)
+#pragma unroll
+            for (int stride = size >> 1; stride > 0; stride >>= 1)
+#pragma unroll
+                for (int k = 0; k < kSortReg; ++k) {
+                    const int l = k ^ stride;
+                    if (l > k) {
+                        const bool up = (k & size) == 0;   // ascending half
+                        const int lo = v[k] < v[l] ? v[k] : v[l], hi = v[k] < v[l] ? v[l] : v[k];
+                        v[k] = up ? lo : hi;
+                        v[l] = up ? hi : lo;
+                    }
+                }
+#pragma unroll
+        for (int k = 0; k < kSortReg; ++k)
+            if (k < len) perm[b + k] = v[k];
+        return;
+    }
     for (int64_t i = b + 1; i < e; ++i) {
         int32_t v = perm[i];
         int64_t j = i - 1;
