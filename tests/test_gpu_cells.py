@@ -4,8 +4,9 @@ per axis nc = max(1, floor((hi - lo) / (R (1 + 2^-20)))) cells, the cell
 coordinate floor((x - lo) nc / (hi - lo)) clamped to [0, nc - 1], the key in
 column-major order with z fastest, the particles sorted by (key, original
 index), cell_start from the per-cell counts, and the positions gathered in
-that order.  Bit-exact: shuffled inputs, 2-D and 3-D, and particles outside
-the box (clamped into the boundary cells).
+that order.  Bit-exact: shuffled inputs, 2-D and 3-D, particles outside the
+box (clamped into the boundary cells), and a cell holding more particles than
+the in-register sort of a cell's slice takes.
 """
 import numpy as np
 import pytest
@@ -54,6 +55,12 @@ def _sets():
     pos[0, k[:20]] += rng.choice([-1.0, 1.0], 20) * 0.5   # outside the box in x
     pos[2, k[20:]] -= 1.0                                   # below the box in z
     out.append(("sigma3d-outside", pos, w.vol, w.lo, w.hi, w.R, w.kernel))
+    # 100 extra particles below the box's lower corner: all clamped into the
+    # corner cell, whose slice then exceeds the register sort (64 entries)
+    extra = np.random.default_rng(8).uniform(-0.5, -0.4, (3, 100))
+    pos = np.concatenate([w.pos, extra], axis=1)
+    vol = np.concatenate([w.vol, np.full(100, w.vol[0])])
+    out.append(("sigma3d-crowded-corner", pos, vol, w.lo, w.hi, w.R, w.kernel))
     w = I.config("c0")
     out.append(("c0", w.pos, w.vol, w.lo, w.hi, w.R, w.kernel))
     return out
