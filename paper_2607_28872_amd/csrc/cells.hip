@@ -126,9 +126,12 @@ static int exclusive_scan(const int32_t* in, int64_t n, int64_t* out, int64_t* t
 
 // ------------------------------------------------------------------ cell sort
 
+// The key of every particle, and its slot in its cell (the count the atomic
+// increment returns; the slots of a cell are a permutation of 0..count-1 in
+// an order that varies from run to run, which the per-cell sort removes).
 __global__ void k_cell_keys(int dim, int64_t n, const double* __restrict__ pos, Grid g,
-                            int32_t* __restrict__ keys, int32_t* __restrict__ counts,
-                            int32_t* __restrict__ bad) {
+                            int32_t* __restrict__ keys, int32_t* __restrict__ slots,
+                            int32_t* __restrict__ counts, int32_t* __restrict__ bad) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     int64_t c[3] = {0, 0, 0};
@@ -141,17 +144,14 @@ __global__ void k_cell_keys(int dim, int64_t n, const double* __restrict__ pos, 
     if (!finite) atomicAdd(bad, 1);
     int32_t k = (int32_t)cell_key(c[0], c[1], c[2], g);
     keys[i] = k;
-    atomicAdd(&counts[k], 1);
+    slots[i] = atomicAdd(&counts[k], 1);
 }
 
-__global__ void k_cell_scatter(int64_t n, const int32_t* __restrict__ keys,
-                               const int64_t* __restrict__ cell_start, int32_t* __restrict__ fill,
-                               int32_t* __restrict__ perm) {
+__global__ void k_cell_scatter(int64_t n, const int32_t* __restrict__ keys, const int32_t* __restrict__ slots,
+                               const int64_t* __restrict__ cell_start, int32_t* __restrict__ perm) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    int32_t k = keys[i];
-    int32_t slot = atomicAdd(&fill[k], 1);
-    perm[cell_start[k] + slot] = (int32_t)i;
+    perm[cell_start[keys[i]] + slots[i]] = (int32_t)i;
 }
 
 // The scatter leaves each cell's particles in arbitrary order; sorting every
@@ -599,7 +599,7 @@ extern "C" int64_t vct_grid_dims(int dim, const double* lo, const double* hi, do
 extern "C" size_t vct_build_cells_workspace_size(int dim, int64_t n, int64_t ncell) {
     (void)dim;
     if (n < 0 || ncell < 1) return 0;
-    return aligned_sum({(size_t)n * 4, (size_t)ncell * 4, scan_ws_bytes(ncell), 64});
+    return aligned_sum({(size_t)n * 4, (size_t)n * 4, (size_t)ncell * 4, scan_ws_bytes(ncell), 64});
 }
 
 extern "C" int vct_build_cells(int dim, int64_t n, const double* pos, const double* lo, const double* hi,
@@ -617,6 +617,7 @@ extern "C" int vct_build_cells(int dim, int64_t n, const double* pos, const doub
     hipStream_t s = as_stream(stream);
     Carver cv(ws, ws_bytes);
     int32_t* keys = cv.take<int32_t>((size_t)n);
+    int32_t* slots = cv.take<int32_t>((size_t)n);
     int32_t* counts = cv.take<int32_t>((size_t)ncell);
     int64_t* tiles = cv.take<int64_t>(scan_ws_bytes(ncell) / 8);
     int32_t* bad = cv.take<int32_t>(16);
@@ -625,14 +626,13 @@ extern "C" int vct_build_cells(int dim, int64_t n, const double* pos, const doub
     if ((st = fill_i32(bad, 1, 0, s))) return st;
     if (n > 0) {
         VCT_LAUNCH("k_cell_keys", k_cell_keys, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, dim, n, pos, g,
-                   keys, counts, bad);
+                   keys, slots, counts, bad);
         VCT_LAUNCH_CHECK();
     }
     if ((st = exclusive_scan(counts, ncell, cell_start, tiles, s))) return st;
     if (n > 0) {
-        if ((st = fill_i32(counts, ncell, 0, s))) return st;
         VCT_LAUNCH("k_cell_scatter", k_cell_scatter, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, keys,
-                   cell_start, counts, perm);
+                   slots, cell_start, perm);
         VCT_LAUNCH_CHECK();
         VCT_LAUNCH("k_cell_sort", k_cell_sort, dim3((unsigned)((ncell + 255) / 256)), dim3(256), 0, s, ncell,
                    cell_start, perm);
