@@ -66,6 +66,9 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--adjoint-state", choices=["resolve", "recompute"], default="resolve",
                    help="backward state: solved from the forward's kept moment sums, or sweeps + solve again")
+    p.add_argument("--no-grad-hint", action="store_true",
+                   help="the backward's FP64 apply computes its own first-pass gradient instead of reading the "
+                        "forward's")
     p.add_argument("--ppe-iters", type=int, default=100, help="BiCGSTAB iterations of the pressure-step measurement")
     p.add_argument("--skip", default="",
                    help="comma-separated side measurements to leave out (outside the timed steps): "
@@ -174,6 +177,9 @@ def main():
     flags = torch.empty(n, dtype=torch.uint8, device=dev)
     out = torch.empty((nf, n, n_out), dtype=torch.float64, device=dev)
     proj = torch.empty((1, n, vct.vct_n_out(dim, adj_mask)), dtype=torch.float64, device=dev)
+    # the forward's first-pass gradient of each field, read back by the
+    # backward's FP64 apply of field 0 (same field, geometry and neighbours)
+    ghint = None if args.no_grad_hint else torch.empty((nf, dim, n), dtype=torch.float32, device=dev)
     u = torch.empty(n, dtype=torch.float64, device=dev)
     dphi = torch.empty(n, dtype=torch.float64, device=dev)
     dth = torch.empty(nterms, dtype=torch.float64, device=dev)
@@ -214,7 +220,7 @@ def main():
         # the forward only runs the mixed apply: the FP32 state is all it reads
         vct.vct_moments(nl, pos_s, vol_s, w.kernel, cmap, fwd_mask, None, st32, flags, False, ws_mom)
         mark()
-        vct.vct_apply_ops(nl, nf, phi_s, pos_s, vol_s, w.kernel, st32, fwd_mask, vct.VCT_MIXED, out)
+        vct.vct_apply_ops_ex(nl, nf, phi_s, pos_s, vol_s, w.kernel, st32, fwd_mask, vct.VCT_MIXED, out, g_out=ghint)
         mark()
         # backward of loss = sum (lap f - g)^2: the FP64 state of its rows,
         # from the moment sums the forward left in ws_mom (or recomputed)
@@ -223,7 +229,8 @@ def main():
         else:
             vct.vct_moments(nl, pos_s, vol_s, w.kernel, cmap, adj_mask, sta, None, flags, False, ws_mom)
         mark()
-        vct.vct_apply_ops(nl, 1, phi_s, pos_s, vol_s, w.kernel, sta, adj_mask, vct.VCT_FP64, proj)
+        vct.vct_apply_ops_ex(nl, 1, phi_s, pos_s, vol_s, w.kernel, sta, adj_mask, vct.VCT_FP64, proj,
+                             g_in=None if ghint is None else ghint[0])
         torch.sub(proj[0, :, 0], g_s, out=u)
         u.mul_(2.0)
         vct.vct_apply_ops_adjoint(nl, pos_s, vol_s, w.kernel, sta, adj_mask, cmap, proj, u, dphi, dth, ws_adj)
@@ -279,6 +286,10 @@ def main():
         return per_particle * n
 
     b_mixed, b_fp64 = apply_bytes(4), apply_bytes(8)
+    # the step's forward also writes the first-pass gradient (FP32, d per
+    # field) that the backward's FP64 apply reads instead of its first pass
+    b_hint = 0 if args.no_grad_hint else 4 * dim * n
+    b_mixed_step = b_mixed + b_hint * nf
     # per-kernel launch times over the timed steps, and the roofline of the
     # kernel that takes the most time per step
     n_out_a = vct.vct_n_out(dim, adj_mask)
@@ -286,8 +297,9 @@ def main():
     b_fp64_adj = n * (8 + 2 * deg + (dim * 8 + 8 + 8) + stride_a * 8 + 8 * n_out_a)
     candidates = n * 27.0 * (n / ncell)
     models = {   # kernel -> (bound, algorithmic bytes or flops per launch, peak)
-        "k_apply (mixed)": ("hbm", b_mixed, HBM_PEAK_GBS),
+        "k_apply (mixed)": ("hbm", b_mixed_step, HBM_PEAK_GBS),
         "k_apply (fp64)": ("hbm", b_fp64_adj, HBM_PEAK_GBS),
+        "k_apply (fp64, given G)": ("hbm", b_fp64_adj + b_hint, HBM_PEAK_GBS),
         "k_moment_sweeps": ("alu", pairs * MOMENT_FLOP_PER_PAIR_3D, FP64_PEAK_TFLOPS),
         "k_moment_solve": ("alu", n * MOMENT_FLOP_SOLVE_3D, FP64_PEAK_TFLOPS),
         "k_adjoint_push": ("alu", pairs * ADJOINT_DPHI_FLOP_PER_ENTRY_3D, FP64_PEAK_TFLOPS),
@@ -349,7 +361,8 @@ def main():
         "config": {"workload": f"3-D sigma-SPH sloped beach {w.counts[0]}x{w.counts[1]}x{w.counts[2]} "
                                f"({n} particles), Wendland C2 R=3dx, 5% jitter, {nf} field(s), mixed apply, "
                                + ("adjoint state solved from the forward's moment sums"
-                                  if args.adjoint_state == "resolve" else "adjoint with recomputed moments"),
+                                  if args.adjoint_state == "resolve" else "adjoint with recomputed moments")
+                               + ("" if args.no_grad_hint else ", backward reads the forward's first-pass gradient"),
                    "particles": n, "fields": nf, "neighbours_per_particle": round(deg, 2),
                    "parallelism": "single GPU"},
         "stage_ms": {k: round(v, 4) for k, v in stage.items()},

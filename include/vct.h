@@ -380,6 +380,23 @@ int vct_apply_ops(const vct_nlist* nl, int nf, const double* phi_sorted, const d
                   const double* vol_sorted, int kernel, const void* state, uint32_t out_mask, int precision,
                   double* out, void* stream);
 
+/* vct_apply_ops with the first-order gradient of the first pass exposed
+ * (Eq. gra_1st).  G~_i = L_i a_i is that gradient in projected coordinates and
+ * in units of 1/R (the gradient times R).  g_out [nf][d][n] FP32 (device, may
+ * be NULL) receives G~ as the call computed it, in any precision.  g_in
+ * [nf][d][n] FP32 (device, may be NULL) is read by VCT_FP64 only: it replaces
+ * the call's own first pass, which is then skipped (chunks whose neighbour
+ * windows exceed the LDS staging still run theirs).  Because
+ * out_i = P_i [a_i(psi); s_i(psi)] + W_i G_i holds for any G_i, a G~ from a
+ * mixed call on the same fields, positions, volumes and neighbour list (the
+ * FP32 rounding of the same gradient) gives the FP64 result up to rounding;
+ * a G~ of anything else gives a wrong result that the library cannot detect.
+ * The other precisions ignore g_in.  Passing both is VCT_E_ARG.  Other
+ * arguments, layout and errors as in vct_apply_ops.                         */
+int vct_apply_ops_ex(const vct_nlist* nl, int nf, const double* phi_sorted, const double* pos_sorted,
+                     const double* vol_sorted, int kernel, const void* state, uint32_t out_mask, int precision,
+                     double* out, float* g_out, const float* g_in, void* stream);
+
 /* ---------------------------------------------------------------- adjoint */
 
 size_t vct_adjoint_workspace_size(int dim, int64_t n, int64_t nnz, int nterms);

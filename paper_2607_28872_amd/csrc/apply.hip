@@ -108,6 +108,8 @@ template <class S> struct ApplyArgs {
     const int64_t* nchunks;
     const S* state;
     double* out;
+    float* g_out;        // [nf][D][n] or NULL: the first pass's G~, written
+    const float* g_in;   // [nf][D][n] or NULL: G~ given to the FP64 form (first pass skipped)
 };
 
 // The mixed form keeps positions in units of R (x / R, in FP64): the FP64
@@ -252,6 +254,10 @@ __device__ __forceinline__ void apply_chunk_global(const ApplyArgs<S>& A, const 
             for (int a = 0; a < D; ++a) a1[a] += wgt * r[a];
         }
         group_gradient<D, T>(L2, a1, Gt);
+        if (A.g_out && lane == 0) {
+#pragma unroll
+            for (int a = 0; a < D; ++a) A.g_out[((int64_t)f * D + a) * n + i] = (float)Gt[a];
+        }
         double Gp[D];
 #pragma unroll
         for (int a = 0; a < D; ++a) Gp[a] = Scaled<T>::value ? (double)Gt[a] : (double)Gt[a] * A.invR;
@@ -277,8 +283,11 @@ __device__ __forceinline__ void apply_chunk_global(const ApplyArgs<S>& A, const 
     }
 }
 
-template <int D, int KERNEL, class T, class S>
+// GIN: the FP64 form reads G~ from A.g_in instead of running the first pass
+// (a separate instantiation, so the other forms keep their registers).
+template <int D, int KERNEL, class T, class S, bool GIN>
 __global__ __launch_bounds__(ApplyCfg<T>::threads, ApplyCfg<T>::waves) void k_apply(ApplyArgs<S> A) {
+    static_assert(!GIN || !Scaled<T>::value, "only the FP64 form takes a given gradient");
     using Dm = Dims<D>;
     constexpr int nk = Dm::nk, kS = ApplyCfg<T>::slots, kW = ApplyCfg<T>::win;
     constexpr int kLanes = ApplyCfg<T>::lanes, kThreads = ApplyCfg<T>::threads;
@@ -449,39 +458,47 @@ __global__ __launch_bounds__(ApplyCfg<T>::threads, ApplyCfg<T>::waves) void k_ap
                 return 0.0f;
             }
         };
-        // software pipeline: the record of slot s + 1 is read while slot s is
-        // summed (the scheduling barriers keep the compiler from hoisting
-        // every slot's read, which would exhaust the registers)
-        double4 qn = sd[cols(0)];
-        T vn = sv[cols(0)];
+        // The FP64 form given G~ (a mixed call's first pass on the same field
+        // and geometry) skips its own: any G gives the same result up to the
+        // rounding of psi.
+        if constexpr (GIN) {
 #pragma unroll
-        for (int s = 0; s < kS; ++s) {
-            const double4 q = qn;
-            const T vj = vn;
-            if (s + 1 < kS) {
-                qn = sd[cols(s + 1)];
-                vn = sv[cols(s + 1)];
+            for (int a = 0; a < D; ++a) Gt[a] = T(A.g_in[((int64_t)f * D + a) * n + ii]);
+        } else {
+            // software pipeline: the record of slot s + 1 is read while slot s
+            // is summed (the scheduling barriers keep the compiler from
+            // hoisting every slot's read, which would exhaust the registers)
+            double4 qn = sd[cols(0)];
+            T vn = sv[cols(0)];
+#pragma unroll
+            for (int s = 0; s < kS; ++s) {
+                const double4 q = qn;
+                const T vj = vn;
+                if (s + 1 < kS) {
+                    qn = sd[cols(s + 1)];
+                    vn = sv[cols(s + 1)];
+                }
+                __builtin_amdgcn_sched_barrier(0);
+                vcs[s] = term1(q, vj, s < nslot, vqs[s]);
+                __builtin_amdgcn_sched_barrier(0);
             }
-            __builtin_amdgcn_sched_barrier(0);
-            vcs[s] = term1(q, vj, s < nslot, vqs[s]);
-            __builtin_amdgcn_sched_barrier(0);
-        }
-        for (int64_t e = tail + lane; e < re; e += kLanes) {
-            const int t = col_at(e);
-            float vq_;
-            term1(sd[t], sv[t], true, vq_);
-        }
-#pragma unroll
-        for (int a = 0; a < D; ++a) a1[a] = group_sum(a1[a], kLanes);
-#pragma unroll
-        for (int a = 0; a < D; ++a) {
-            T t = T(0);
-#pragma unroll
-            for (int c = 0; c < D; ++c) {
-                const int p = sym_index<D>(a, c);
-                t += (a == c ? L2[p] : T(0.5) * L2[p]) * T(a1[c]);
+            for (int64_t e = tail + lane; e < re; e += kLanes) {
+                const int t = col_at(e);
+                float vq_;
+                term1(sd[t], sv[t], true, vq_);
             }
-            Gt[a] = t;
+#pragma unroll
+            for (int a = 0; a < D; ++a) a1[a] = group_sum(a1[a], kLanes);
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                T t = T(0);
+#pragma unroll
+                for (int c = 0; c < D; ++c) {
+                    const int p = sym_index<D>(a, c);
+                    t += (a == c ? L2[p] : T(0.5) * L2[p]) * T(a1[c]);
+                }
+                Gt[a] = t;
+            }
         }
         double Gp[D];
 #pragma unroll
@@ -518,8 +535,8 @@ __global__ __launch_bounds__(ApplyCfg<T>::threads, ApplyCfg<T>::waves) void k_ap
             for (int a = 0; a < D; ++a) psi -= dx[a] * Gp[a];
             pair_sums<D, T>(r, vc * iq4, vc, T(psi), L2, acc);
         };
-        qn = sd[cols(0)];
-        vn = sv[cols(0)];
+        double4 qn = sd[cols(0)];
+        T vn = sv[cols(0)];
 #pragma unroll
         for (int s = 0; s < kS; ++s) {
             const double4 q = qn;
@@ -549,18 +566,30 @@ __global__ __launch_bounds__(ApplyCfg<T>::threads, ApplyCfg<T>::waves) void k_ap
         {
             const int q = threadIdx.x % kChunk;
             const int64_t iq = p0 + q;
-            if (iq < p1)
+            if (iq < p1) {
                 for (int o = threadIdx.x / kChunk; o < A.nrows; o += kThreads / kChunk)
                     A.out[((int64_t)f * n + iq) * A.nrows + o] =
                         out_row<D, T, S>(A, iq, o, &sacc[q][0], &sacc[q][nk]);
+                if (A.g_out && threadIdx.x < kChunk)
+#pragma unroll
+                    for (int a = 0; a < D; ++a) A.g_out[((int64_t)f * D + a) * n + iq] = (float)sacc[q][nk + a];
+            }
         }
     }
 }
 
 template <int D, int KERNEL, class T, class S>
 static int launch_apply(const ApplyArgs<S>& a, int64_t cap, hipStream_t s) {
+    if constexpr (!Scaled<T>::value) {
+        if (a.g_in) {
+            VCT_LAUNCH("k_apply (fp64, given G)", (k_apply<D, KERNEL, T, S, true>), dim3((unsigned)cap),
+                       dim3(ApplyCfg<T>::threads), 0, s, a);
+            VCT_LAUNCH_CHECK();
+            return VCT_OK;
+        }
+    }
     const char* name = sizeof(T) == 4 ? "k_apply (mixed)" : "k_apply (fp64)";
-    VCT_LAUNCH(name, (k_apply<D, KERNEL, T, S>), dim3((unsigned)cap), dim3(ApplyCfg<T>::threads), 0, s, a);
+    VCT_LAUNCH(name, (k_apply<D, KERNEL, T, S, false>), dim3((unsigned)cap), dim3(ApplyCfg<T>::threads), 0, s, a);
     VCT_LAUNCH_CHECK();
     return VCT_OK;
 }
@@ -596,6 +625,8 @@ static ApplyArgs<S> make_args(const vct_nlist* nl, const Grid& g, int nf, const 
     a.nchunks = nl->chunk_off + ncols;
     a.state = state;
     a.out = out;
+    a.g_out = nullptr;
+    a.g_in = nullptr;
     return a;
 }
 
@@ -605,10 +636,9 @@ VCT_CHECKS_TU(checks_apply)
 
 using namespace vct;
 
-extern "C" int vct_apply_ops(const vct_nlist* nl, int nf, const double* phi_sorted, const double* pos_sorted,
-                             const double* vol_sorted, int kernel, const void* state, uint32_t out_mask,
-                             int precision, double* out, void* stream) {
-    VCT_API_RANGE("vct_apply_ops");
+static int apply_ops(const vct_nlist* nl, int nf, const double* phi_sorted, const double* pos_sorted,
+                     const double* vol_sorted, int kernel, const void* state, uint32_t out_mask, int precision,
+                     double* out, float* g_out, const float* g_in, void* stream) {
     Grid g;
     int st = nlist_check(nl, g);
     if (st) return st;
@@ -624,20 +654,41 @@ extern "C" int vct_apply_ops(const vct_nlist* nl, int nf, const double* phi_sort
     const int64_t cap = ncols + n / kChunk + 1;   // upper bound of the chunk count
     hipStream_t s = as_stream(stream);
     switch (precision) {
-    case VCT_FP64:
-        return dispatch<double, double>(
-            dim, kernel,
-            make_args(nl, g, nf, phi_sorted, pos_sorted, vol_sorted, static_cast<const double*>(state), out_mask, out),
-            cap, s);
-    case VCT_MIXED:
-        return dispatch<float, float>(
-            dim, kernel,
-            make_args(nl, g, nf, phi_sorted, pos_sorted, vol_sorted, static_cast<const float*>(state), out_mask, out),
-            cap, s);
-    default:
-        return dispatch<float, double>(
-            dim, kernel,
-            make_args(nl, g, nf, phi_sorted, pos_sorted, vol_sorted, static_cast<const double*>(state), out_mask, out),
-            cap, s);
+    case VCT_FP64: {
+        auto a = make_args(nl, g, nf, phi_sorted, pos_sorted, vol_sorted, static_cast<const double*>(state), out_mask,
+                           out);
+        a.g_out = g_out;
+        a.g_in = g_in;
+        return dispatch<double, double>(dim, kernel, a, cap, s);
     }
+    case VCT_MIXED: {
+        auto a = make_args(nl, g, nf, phi_sorted, pos_sorted, vol_sorted, static_cast<const float*>(state), out_mask,
+                           out);
+        a.g_out = g_out;
+        return dispatch<float, float>(dim, kernel, a, cap, s);
+    }
+    default: {
+        auto a = make_args(nl, g, nf, phi_sorted, pos_sorted, vol_sorted, static_cast<const double*>(state), out_mask,
+                           out);
+        a.g_out = g_out;
+        return dispatch<float, double>(dim, kernel, a, cap, s);
+    }
+    }
+}
+
+extern "C" int vct_apply_ops(const vct_nlist* nl, int nf, const double* phi_sorted, const double* pos_sorted,
+                             const double* vol_sorted, int kernel, const void* state, uint32_t out_mask,
+                             int precision, double* out, void* stream) {
+    VCT_API_RANGE("vct_apply_ops");
+    return apply_ops(nl, nf, phi_sorted, pos_sorted, vol_sorted, kernel, state, out_mask, precision, out, nullptr,
+                     nullptr, stream);
+}
+
+extern "C" int vct_apply_ops_ex(const vct_nlist* nl, int nf, const double* phi_sorted, const double* pos_sorted,
+                                const double* vol_sorted, int kernel, const void* state, uint32_t out_mask,
+                                int precision, double* out, float* g_out, const float* g_in, void* stream) {
+    VCT_API_RANGE("vct_apply_ops_ex");
+    if (g_out && g_in) return VCT_E_ARG;   // distinct roles: one call writes G~, a later one reads it
+    return apply_ops(nl, nf, phi_sorted, pos_sorted, vol_sorted, kernel, state, out_mask, precision, out, g_out,
+                     g_in, stream);
 }

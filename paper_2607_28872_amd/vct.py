@@ -115,6 +115,9 @@ def lib():
                                           C.POINTER(_i64), _vp, _sz, _vp]
         L.vct_apply_ops.restype = C.c_int
         L.vct_apply_ops.argtypes = [_nlp, C.c_int, _vp, _vp, _vp, C.c_int, _vp, C.c_uint32, C.c_int, _vp, _vp]
+        L.vct_apply_ops_ex.restype = C.c_int
+        L.vct_apply_ops_ex.argtypes = [_nlp, C.c_int, _vp, _vp, _vp, C.c_int, _vp, C.c_uint32, C.c_int, _vp, _vp, _vp,
+                                       _vp]
         L.vct_adjoint_workspace_size.restype = _sz
         L.vct_adjoint_workspace_size.argtypes = [C.c_int, _i64, _i64, C.c_int]
         L.vct_apply_ops_adjoint.restype = C.c_int
@@ -329,6 +332,15 @@ def vct_apply_ops(nl, nf, phi_sorted, pos_sorted, vol_sorted, kernel, state, mas
     return _check("vct_apply_ops", lib().vct_apply_ops(
         C.byref(nl), nf, _p(phi_sorted), _p(pos_sorted), _p(vol_sorted), kernel, _p(state), mask, precision, _p(out),
         _stream(stream)))
+
+
+def vct_apply_ops_ex(nl, nf, phi_sorted, pos_sorted, vol_sorted, kernel, state, mask, precision, out, g_out=None,
+                     g_in=None, stream=None):
+    """vct_apply_ops with the first pass's gradient G~ [nf][d][n] FP32 written
+    to g_out, or (FP64 only) taken from g_in instead of computed."""
+    return _check("vct_apply_ops_ex", lib().vct_apply_ops_ex(
+        C.byref(nl), nf, _p(phi_sorted), _p(pos_sorted), _p(vol_sorted), kernel, _p(state), mask, precision, _p(out),
+        _p(g_out), _p(g_in), _stream(stream)))
 
 
 def vct_apply_ops_adjoint(nl, pos_sorted, vol_sorted, kernel, state64, mask, cmap, proj, u, dphi, dtheta, ws,

@@ -204,6 +204,50 @@ def test_dry_sigma_column_is_flagged():
     assert np.isnan(out[:, bad]).all() and np.isfinite(out[:, ~bad]).all()
 
 
+def _apply_ex(g, phi, precision, g_out=None, g_in=None):
+    nf = int(phi.shape[0])
+    out = torch.empty((nf, g.n, vct.vct_n_out(g.dim, g.mask)), dtype=torch.float64, device=DEV)
+    state = g.state32 if precision == vct.VCT_MIXED else g.state64
+    vct.vct_apply_ops_ex(g.nl, nf, phi, g.pos, g.vol, g.kernel, state, g.mask, precision, out, g_out, g_in)
+    return out
+
+
+@pytest.mark.parametrize("family,Rs", [("bf2d", 1.0), ("bfe2d", 1.0), ("sigma3d", 1.0), ("sigma3d", 1.4)])
+def test_fp64_apply_from_a_given_gradient(family, Rs):
+    """The FP64 apply given the first-pass gradient of a mixed call skips its
+    own first pass; since out = P [a(psi); s(psi)] + W G holds for any G, the
+    result stays at the FP64 bar against the oracle and within rounding of
+    the plain FP64 call.  Rs = 1.4 puts windows beyond the LDS staging, where
+    the chunk path reading records from memory writes the gradient."""
+    w = I.small(family)
+    R = Rs * w.R
+    g = _geom(w, R=R)
+    g.moments(w.mapspec, ALL_OUT, fp32_copy=True)
+    phi = g.sorted_field(w.phi)
+    nf, n, d = int(phi.shape[0]), g.n, w.dim
+    g32 = torch.full((nf, d, n), float("nan"), dtype=torch.float32, device=DEV)
+    g64 = torch.full((nf, d, n), float("nan"), dtype=torch.float32, device=DEV)
+    mixed = _apply_ex(g, phi, vct.VCT_MIXED, g_out=g32)
+    plain = _apply_ex(g, phi, vct.VCT_FP64, g_out=g64)
+    assert torch.equal(mixed, g.apply(phi, vct.VCT_MIXED)) and torch.equal(plain, g.apply(phi, vct.VCT_FP64))
+    assert torch.isfinite(g32).all() and torch.isfinite(g64).all()
+    dg = ((g32 - g64).abs().amax(dim=2) / g64.abs().amax(dim=2)).max().item()
+    assert dg <= 1e-5
+    hinted = _apply_ex(g, phi, vct.VCT_FP64, g_in=g32)
+    rec, _ = O.sph2(w.pos, w.vol, w.phi, w.kernel, R, w.mapspec)
+    ref = oracle_rows(rec, w.dim, ALL_OUT)
+    got = g.unsort(hinted).cpu().numpy()
+    e_plain = normwise(got, g.unsort(plain).cpu().numpy()).max()
+    print(f"\n{family} R={Rs}R0: mixed vs FP64 gradient {dg:.2e}; hinted vs plain FP64 {e_plain:.2e}")
+    assert e_plain <= 1e-12
+    if Rs == 1.0:
+        fp64_check(w, w.kernel, R, got, ref, ALL_OUT, label=f"{family} hinted")
+    else:
+        assert normwise(got, ref).max() <= 1e-11
+    with pytest.raises(vct.VctError):
+        _apply_ex(g, phi, vct.VCT_FP64, g_out=g64, g_in=g32)
+
+
 @pytest.mark.parametrize("family", FAMILIES)
 def test_first_order_gradient_option(family):
     w = I.small(family)
