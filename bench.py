@@ -64,8 +64,9 @@ def parse():
     p.add_argument("--nf", type=int, default=1)
     p.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--adjoint-state", choices=["resolve", "recompute"], default="resolve",
-                   help="backward state: solved from the forward's kept moment sums, or sweeps + solve again")
+    p.add_argument("--adjoint-state", choices=["forward", "resolve", "recompute"], default="forward",
+                   help="backward state: folded by the forward's solve beside its own, solved again from the "
+                        "forward's kept moment sums, or sweeps + solve again")
     p.add_argument("--no-grad-hint", action="store_true",
                    help="the backward's FP64 apply computes its own first-pass gradient instead of reading the "
                         "forward's")
@@ -218,7 +219,12 @@ def main():
         vct.vct_neighbors(nl, pos_s, nnz, 0, ws_nb)
         mark()
         # the forward only runs the mixed apply: the FP32 state is all it reads
-        vct.vct_moments(nl, pos_s, vol_s, w.kernel, cmap, fwd_mask, None, st32, flags, False, ws_mom)
+        # (its solve also folds the backward's FP64 rows from the same inverse)
+        if args.adjoint_state == "forward":
+            vct.vct_moments_ex(nl, pos_s, vol_s, w.kernel, cmap, fwd_mask, None, st32, adj_mask, sta, None, flags,
+                               False, ws_mom)
+        else:
+            vct.vct_moments(nl, pos_s, vol_s, w.kernel, cmap, fwd_mask, None, st32, flags, False, ws_mom)
         mark()
         vct.vct_apply_ops_ex(nl, nf, phi_s, pos_s, vol_s, w.kernel, st32, fwd_mask, vct.VCT_MIXED, out, g_out=ghint)
         mark()
@@ -226,7 +232,7 @@ def main():
         # from the moment sums the forward left in ws_mom (or recomputed)
         if args.adjoint_state == "resolve":
             vct.vct_moments_resolve(nl, pos_s, cmap, adj_mask, sta, None, flags, False, ws_mom)
-        else:
+        elif args.adjoint_state == "recompute":
             vct.vct_moments(nl, pos_s, vol_s, w.kernel, cmap, adj_mask, sta, None, flags, False, ws_mom)
         mark()
         vct.vct_apply_ops_ex(nl, 1, phi_s, pos_s, vol_s, w.kernel, sta, adj_mask, vct.VCT_FP64, proj,
@@ -360,8 +366,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"3-D sigma-SPH sloped beach {w.counts[0]}x{w.counts[1]}x{w.counts[2]} "
                                f"({n} particles), Wendland C2 R=3dx, 5% jitter, {nf} field(s), mixed apply, "
-                               + ("adjoint state solved from the forward's moment sums"
-                                  if args.adjoint_state == "resolve" else "adjoint with recomputed moments")
+                               + {"forward": "adjoint state folded by the forward's solve",
+                                  "resolve": "adjoint state solved from the forward's moment sums",
+                                  "recompute": "adjoint with recomputed moments"}[args.adjoint_state]
                                + ("" if args.no_grad_hint else ", backward reads the forward's first-pass gradient"),
                    "particles": n, "fields": nf, "neighbours_per_particle": round(deg, 2),
                    "parallelism": "single GPU"},

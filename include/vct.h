@@ -345,6 +345,22 @@ int vct_moments(const vct_nlist* nl, const double* pos_sorted, const double* vol
 
 size_t vct_moments_workspace_size(int dim, int64_t n);
 
+/* vct_moments with a second state from the same solve (Eqs. gra_1st and
+ * sec_SPH2; Sec. 2.1 for the fold): the inverse of each particle's moment
+ * system is folded twice, with out_mask into state64 / state32 and with
+ * out_mask2 into state64_2 / state32_2 (layout of each as in vct_moments,
+ * its stride from its own mask), so a caller that needs two row sets (the
+ * FP32 state of a mixed forward and the FP64 LAP + PZ state of its adjoint,
+ * say) reads the sums and inverts once.  The map, the flags and the
+ * VCT_OPT_GRAD1 choice are shared: masks that differ in VCT_OPT_GRAD1 are
+ * VCT_E_ARG.  With state64_2 and state32_2 both NULL this is vct_moments.
+ * Each state is bitwise the one a vct_moments call with its mask writes.
+ * Other arguments and errors as in vct_moments.                             */
+int vct_moments_ex(const vct_nlist* nl, const double* pos_sorted, const double* vol_sorted, int kernel,
+                   const vct_map* map /* host */, uint32_t out_mask, double* state64, float* state32,
+                   uint32_t out_mask2, double* state64_2, float* state32_2, uint8_t* flags, int64_t* n_flagged,
+                   void* ws, size_t ws_bytes, void* stream);
+
 /* The solve and fold of vct_moments alone, from the moment sums that the last
  * vct_moments call left in `ws`.  The sums depend only on the neighbour list,
  * positions, volumes, kernel and R, not on `map` or `out_mask`, so a second

@@ -406,12 +406,21 @@ __device__ __forceinline__ bool gj_invert(double (&A)[M][M]) {
 #ifndef VCT_SOLVE_WAVES
 #define VCT_SOLVE_WAVES 2
 #endif
-template <int D>
+// One folded state: its output rows and where it goes (either array may be null).
+struct SolveOut {
+    uint32_t mask;
+    int nrows;
+    double* s64;
+    float* s32;
+};
+
+// TWO: a second state with other output rows folded from the same inverse
+// (the map and the VCT_OPT_GRAD1 choice are shared).
+template <int D, bool TWO>
 __global__ __launch_bounds__(128, VCT_SOLVE_WAVES) void k_moment_solve(int64_t n, const double* __restrict__ pos,
                                                       const double* __restrict__ mom,
                                                       const uint8_t* __restrict__ mflags, double invR,
-                                                      MapParams mp, uint32_t mask, int nrows,
-                                                      double* __restrict__ state64, float* __restrict__ state32,
+                                                      MapParams mp, SolveOut o1, SolveOut o2,
                                                       uint8_t* __restrict__ flags_out,
                                                       unsigned long long* __restrict__ nflag) {
     using Dm = Dims<D>;
@@ -487,9 +496,20 @@ __global__ __launch_bounds__(128, VCT_SOLVE_WAVES) void k_moment_solve(int64_t n
     // Sec. 2.1 requires alpha > 0 (a dry sigma column without the limiter
     // gives alpha <= 0 or infinite); such a particle is flagged
     if (!(mc.alpha > 0.0) || !isfinite(mc.alpha + mc.gx + mc.gy + mc.c0 + mc.zxy)) fl |= VCT_FLAG_MAP;
-    const bool grad1 = (mask & VCT_OPT_GRAD1) != 0;
+    const bool grad1 = (o1.mask & VCT_OPT_GRAD1) != 0;
     const double invR2 = invR * invR;
     const double nanv = __builtin_nan("");
+    // one state's rows of output group k (or of W when w is set)
+    auto put = [&](const SolveOut& so, int k, bool w, const double* pg, const double* ph) {
+        const int base = w ? nL + so.nrows * nk : nL;
+        const int stride = w ? d : nk;
+        emit_rows<D>(so.mask, mc, pg, ph, [&](int o, double v) {
+            v = fl ? nanv : v;
+            const int64_t idx = (int64_t)(base + o * stride + k) * n + i;
+            if (so.s64) so.s64[idx] = v;
+            if (so.s32) so.s32[idx] = (float)v;
+        });
+    };
 
 #pragma unroll
     for (int k = 0; k < nk; ++k) {
@@ -526,17 +546,12 @@ __global__ __launch_bounds__(128, VCT_SOLVE_WAVES) void k_moment_solve(int64_t n
             const double hv = (k < d) ? -z[p] : z[p];
             ph[p] = hv * ((p < d) ? 2.0 * invR2 : invR2);
         }
-        emit_rows<D>(mask, mc, pg, ph, [&](int o, double v) {
-            v = fl ? nanv : v;
-            const int64_t idx = (int64_t)(nL + o * nk + k) * n + i;
-            if (state64) state64[idx] = v;
-            if (state32) state32[idx] = (float)v;
-        });
+        put(o1, k, false, pg, ph);
+        if constexpr (TWO) put(o2, k, false, pg, ph);
     }
     // W: response of every output row to a unit projected gradient (a linear
     // field), used by the apply kernels to add back the linear part removed
     // from the field before the neighbour sums
-    const int wbase = nL + nrows * nk;
 #pragma unroll
     for (int a = 0; a < d; ++a) {
         double pg[d], ph[m];
@@ -544,18 +559,18 @@ __global__ __launch_bounds__(128, VCT_SOLVE_WAVES) void k_moment_solve(int64_t n
         for (int b = 0; b < d; ++b) pg[b] = (a == b) ? 1.0 : 0.0;
 #pragma unroll
         for (int p = 0; p < m; ++p) ph[p] = 0.0;
-        emit_rows<D>(mask, mc, pg, ph, [&](int o, double v) {
-            v = fl ? nanv : v;
-            const int64_t idx = (int64_t)(wbase + o * d + a) * n + i;
-            if (state64) state64[idx] = v;
-            if (state32) state32[idx] = (float)v;
-        });
+        put(o1, a, true, pg, ph);
+        if constexpr (TWO) put(o2, a, true, pg, ph);
     }
 #pragma unroll
     for (int p = 0; p < nL; ++p) {
         const double v = fl ? nanv : L[p];
-        if (state64) state64[(int64_t)p * n + i] = v;
-        if (state32) state32[(int64_t)p * n + i] = (float)v;
+        if (o1.s64) o1.s64[(int64_t)p * n + i] = v;
+        if (o1.s32) o1.s32[(int64_t)p * n + i] = (float)v;
+        if constexpr (TWO) {
+            if (o2.s64) o2.s64[(int64_t)p * n + i] = v;
+            if (o2.s32) o2.s32[(int64_t)p * n + i] = (float)v;
+        }
     }
     if (flags_out) flags_out[i] = (uint8_t)fl;
     if (fl && nflag) atomicAdd(nflag, 1ull);
@@ -563,10 +578,25 @@ __global__ __launch_bounds__(128, VCT_SOLVE_WAVES) void k_moment_solve(int64_t n
 
 int nlist_check(const vct_nlist* nl, Grid& g);
 
+template <int D>
+static int launch_solve(int64_t n, const double* pos, const double* mom, const uint8_t* mflags, double invR,
+                        const MapParams& mp, const SolveOut& o1, const SolveOut& o2, uint8_t* flags,
+                        unsigned long long* nflag, hipStream_t s) {
+    const int64_t nb2 = (n + 127) / 128;
+    if (o2.s64 || o2.s32)
+        VCT_LAUNCH("k_moment_solve (two states)", (k_moment_solve<D, true>), dim3((unsigned)nb2), dim3(128), 0, s,
+                   n, pos, mom, mflags, invR, mp, o1, o2, flags, nflag);
+    else
+        VCT_LAUNCH("k_moment_solve", (k_moment_solve<D, false>), dim3((unsigned)nb2), dim3(128), 0, s, n, pos,
+                   mom, mflags, invR, mp, o1, o2, flags, nflag);
+    VCT_LAUNCH_CHECK();
+    return VCT_OK;
+}
+
 template <int D, int KERNEL>
 static int launch_moments(const vct_nlist* nl, const Grid& g, const double* pos, const double* vol, double invR,
-                          const MapParams& mp, uint32_t mask, int nrows, double* mom, uint8_t* mflags, double* s64,
-                          float* s32, uint8_t* flags, unsigned long long* nflag, hipStream_t s) {
+                          const MapParams& mp, const SolveOut& o1, const SolveOut& o2, double* mom, uint8_t* mflags,
+                          uint8_t* flags, unsigned long long* nflag, hipStream_t s) {
     const int64_t n = nl->n;
     const int64_t ncols = D == 3 ? g.nc[0] * g.nc[1] : g.nc[0];
     SweepArgs a;
@@ -577,11 +607,7 @@ static int launch_moments(const vct_nlist* nl, const Grid& g, const double* pos,
     const int64_t cap = ncols + n / kChunk + 1;
     VCT_LAUNCH("k_moment_sweeps", (k_moment_sweeps<D, KERNEL>), dim3((unsigned)cap), dim3(kMThreads), 0, s, a);
     VCT_LAUNCH_CHECK();
-    int64_t nb2 = (n + 127) / 128;
-    VCT_LAUNCH("k_moment_solve", (k_moment_solve<D>), dim3((unsigned)nb2), dim3(128), 0, s, n, pos, mom, mflags,
-               invR, mp, mask, nrows, s64, s32, flags, nflag);
-    VCT_LAUNCH_CHECK();
-    return VCT_OK;
+    return launch_solve<D>(n, pos, mom, mflags, invR, mp, o1, o2, flags, nflag, s);
 }
 
 VCT_CHECKS_TU(checks_moments)
@@ -598,10 +624,10 @@ extern "C" size_t vct_moments_workspace_size(int dim, int64_t n) {
 
 __global__ void k_zero_u64(unsigned long long* p) { *p = 0ull; }
 
-extern "C" int vct_moments(const vct_nlist* nl, const double* pos_sorted, const double* vol_sorted, int kernel,
-                           const vct_map* map, uint32_t out_mask, double* state64, float* state32, uint8_t* flags,
-                           int64_t* n_flagged, void* ws, size_t ws_bytes, void* stream) {
-    VCT_API_RANGE("vct_moments");
+static int moments_impl(const vct_nlist* nl, const double* pos_sorted, const double* vol_sorted, int kernel,
+                        const vct_map* map, uint32_t out_mask, double* state64, float* state32, uint32_t out_mask2,
+                        double* state64_2, float* state32_2, uint8_t* flags, int64_t* n_flagged, void* ws,
+                        size_t ws_bytes, void* stream) {
     Grid g;
     int st = nlist_check(nl, g);
     if (st) return st;
@@ -609,6 +635,8 @@ extern "C" int vct_moments(const vct_nlist* nl, const double* pos_sorted, const 
     const int64_t n = nl->n;
     if (!map || !mask_valid(out_mask) || (kernel != VCT_KERNEL_WENDLAND_C2 && kernel != VCT_KERNEL_CUBIC_SPLINE))
         return VCT_E_ARG;
+    const bool two = state64_2 || state32_2;
+    if (two && (!mask_valid(out_mask2) || ((out_mask ^ out_mask2) & VCT_OPT_GRAD1))) return VCT_E_ARG;
     MapParams mp;
     st = map_params_from(map, dim, n, mp);
     if (st) return st;
@@ -624,19 +652,20 @@ extern "C" int vct_moments(const vct_nlist* nl, const double* pos_sorted, const 
     VCT_LAUNCH_CHECK();
     if (n > 0) {
         const double invR = 1.0 / nl->R;
-        const int nrows = n_out_rows(dim, out_mask);
+        const SolveOut o1{out_mask, n_out_rows(dim, out_mask), state64, state32};
+        const SolveOut o2{two ? out_mask2 : 0u, two ? n_out_rows(dim, out_mask2) : 0, state64_2, state32_2};
         if (dim == 2)
             st = (kernel == VCT_KERNEL_WENDLAND_C2)
-                     ? launch_moments<2, VCT_KERNEL_WENDLAND_C2>(nl, g, pos_sorted, vol_sorted, invR, mp, out_mask,
-                                                                 nrows, mom, mflags, state64, state32, flags, cnt, s)
-                     : launch_moments<2, VCT_KERNEL_CUBIC_SPLINE>(nl, g, pos_sorted, vol_sorted, invR, mp, out_mask,
-                                                                  nrows, mom, mflags, state64, state32, flags, cnt, s);
+                     ? launch_moments<2, VCT_KERNEL_WENDLAND_C2>(nl, g, pos_sorted, vol_sorted, invR, mp, o1, o2, mom,
+                                                                 mflags, flags, cnt, s)
+                     : launch_moments<2, VCT_KERNEL_CUBIC_SPLINE>(nl, g, pos_sorted, vol_sorted, invR, mp, o1, o2,
+                                                                  mom, mflags, flags, cnt, s);
         else
             st = (kernel == VCT_KERNEL_WENDLAND_C2)
-                     ? launch_moments<3, VCT_KERNEL_WENDLAND_C2>(nl, g, pos_sorted, vol_sorted, invR, mp, out_mask,
-                                                                 nrows, mom, mflags, state64, state32, flags, cnt, s)
-                     : launch_moments<3, VCT_KERNEL_CUBIC_SPLINE>(nl, g, pos_sorted, vol_sorted, invR, mp, out_mask,
-                                                                  nrows, mom, mflags, state64, state32, flags, cnt, s);
+                     ? launch_moments<3, VCT_KERNEL_WENDLAND_C2>(nl, g, pos_sorted, vol_sorted, invR, mp, o1, o2, mom,
+                                                                 mflags, flags, cnt, s)
+                     : launch_moments<3, VCT_KERNEL_CUBIC_SPLINE>(nl, g, pos_sorted, vol_sorted, invR, mp, o1, o2,
+                                                                  mom, mflags, flags, cnt, s);
         if (st) return st;
     }
     if (n_flagged) {
@@ -647,6 +676,23 @@ extern "C" int vct_moments(const vct_nlist* nl, const double* pos_sorted, const 
         return h ? VCT_W_FLAGGED : VCT_OK;
     }
     return VCT_OK;
+}
+
+extern "C" int vct_moments(const vct_nlist* nl, const double* pos_sorted, const double* vol_sorted, int kernel,
+                           const vct_map* map, uint32_t out_mask, double* state64, float* state32, uint8_t* flags,
+                           int64_t* n_flagged, void* ws, size_t ws_bytes, void* stream) {
+    VCT_API_RANGE("vct_moments");
+    return moments_impl(nl, pos_sorted, vol_sorted, kernel, map, out_mask, state64, state32, 0u, nullptr, nullptr,
+                        flags, n_flagged, ws, ws_bytes, stream);
+}
+
+extern "C" int vct_moments_ex(const vct_nlist* nl, const double* pos_sorted, const double* vol_sorted, int kernel,
+                              const vct_map* map, uint32_t out_mask, double* state64, float* state32,
+                              uint32_t out_mask2, double* state64_2, float* state32_2, uint8_t* flags,
+                              int64_t* n_flagged, void* ws, size_t ws_bytes, void* stream) {
+    VCT_API_RANGE("vct_moments_ex");
+    return moments_impl(nl, pos_sorted, vol_sorted, kernel, map, out_mask, state64, state32, out_mask2, state64_2,
+                        state32_2, flags, n_flagged, ws, ws_bytes, stream);
 }
 
 extern "C" int vct_moments_resolve(const vct_nlist* nl, const double* pos_sorted, const vct_map* map,
@@ -675,16 +721,11 @@ extern "C" int vct_moments_resolve(const vct_nlist* nl, const double* pos_sorted
     VCT_LAUNCH_CHECK();
     if (n > 0) {
         const double invR = 1.0 / nl->R;
-        const int nrows = n_out_rows(dim, out_mask);
-        const int64_t nb2 = (n + 127) / 128;
-        if (dim == 2) {
-            VCT_LAUNCH("k_moment_solve", (k_moment_solve<2>), dim3((unsigned)nb2), dim3(128), 0, s, n, pos_sorted,
-                       mom, mflags, invR, mp, out_mask, nrows, state64, state32, flags, cnt);
-        } else {
-            VCT_LAUNCH("k_moment_solve", (k_moment_solve<3>), dim3((unsigned)nb2), dim3(128), 0, s, n, pos_sorted,
-                       mom, mflags, invR, mp, out_mask, nrows, state64, state32, flags, cnt);
-        }
-        VCT_LAUNCH_CHECK();
+        const SolveOut o1{out_mask, n_out_rows(dim, out_mask), state64, state32};
+        const SolveOut o2{0u, 0, nullptr, nullptr};
+        st = dim == 2 ? launch_solve<2>(n, pos_sorted, mom, mflags, invR, mp, o1, o2, flags, cnt, s)
+                      : launch_solve<3>(n, pos_sorted, mom, mflags, invR, mp, o1, o2, flags, cnt, s);
+        if (st) return st;
     }
     if (n_flagged) {
         unsigned long long h = 0;

@@ -110,6 +110,9 @@ def lib():
         L.vct_moments.restype = C.c_int
         L.vct_moments.argtypes = [_nlp, _vp, _vp, C.c_int, C.POINTER(vct_map), C.c_uint32, _vp, _vp, _vp,
                                   C.POINTER(_i64), _vp, _sz, _vp]
+        L.vct_moments_ex.restype = C.c_int
+        L.vct_moments_ex.argtypes = [_nlp, _vp, _vp, C.c_int, C.POINTER(vct_map), C.c_uint32, _vp, _vp, C.c_uint32,
+                                     _vp, _vp, _vp, C.POINTER(_i64), _vp, _sz, _vp]
         L.vct_moments_resolve.restype = C.c_int
         L.vct_moments_resolve.argtypes = [_nlp, _vp, C.POINTER(vct_map), C.c_uint32, _vp, _vp, _vp,
                                           C.POINTER(_i64), _vp, _sz, _vp]
@@ -316,6 +319,17 @@ def vct_moments(nl, pos_sorted, vol_sorted, kernel, cmap, mask, state64, state32
                            _p(state32), _p(flags), C.byref(cnt) if count_flagged else None, _p(ws), _nbytes(ws),
                            _stream(stream))
     _check("vct_moments", st)
+    return st, cnt.value
+
+
+def vct_moments_ex(nl, pos_sorted, vol_sorted, kernel, cmap, mask, state64, state32, mask2, state64_2, state32_2,
+                   flags, count_flagged, ws, stream=None):
+    """vct_moments folding the same inverse into a second state (mask2)."""
+    cnt = _i64(0)
+    st = lib().vct_moments_ex(C.byref(nl), _p(pos_sorted), _p(vol_sorted), kernel, C.byref(cmap), mask, _p(state64),
+                              _p(state32), mask2, _p(state64_2), _p(state32_2), _p(flags),
+                              C.byref(cnt) if count_flagged else None, _p(ws), _nbytes(ws), _stream(stream))
+    _check("vct_moments_ex", st)
     return st, cnt.value
 
 

@@ -365,6 +365,43 @@ def test_fp32_only_state_matches_the_rounded_fp64_state():
 
 
 @pytest.mark.parametrize("family", ["sigma3d-adj", "bf2d-degenerate"])
+def test_two_states_from_one_solve_give_the_same_bits(family):
+    """vct_moments_ex folds one inverse into two states (the mixed forward's
+    FP32 default rows and the adjoint's FP64 LAP + PZ rows, say): each is
+    bitwise the state of a vct_moments call with its mask, flags included."""
+    if family == "bf2d-degenerate":
+        w = I.small("bf2d")
+        pos = np.concatenate([w.pos, [[0.5], [10.0]], w.pos[:, :1]], axis=1)
+        vol = np.concatenate([w.vol, [w.vol[0], w.vol[0]]])
+        g = vct.Geometry(pos, vol, w.lo, w.hi, w.R, w.kernel, device=DEV)
+    else:
+        w = I.small(family)
+        g = _geom(w)
+    m1 = vct.VCT_OUT_DEFAULT
+    m2 = vct.VCT_OUT_LAP | vct.VCT_OUT_PZ
+    ref = {}
+    for m in (m1, m2):
+        st_ref = g.moments(w.mapspec, m, fp32_copy=True)
+        ref[m] = (g.state64.clone(), g.state32.clone(), g.flags.clone())
+    n, dim = g.n, g.dim
+    cm = g.map_for(w.mapspec)
+    s32 = torch.empty((vct.vct_state_stride(dim, m1), n), dtype=torch.float32, device=DEV)
+    s64b = torch.empty((vct.vct_state_stride(dim, m2), n), dtype=torch.float64, device=DEV)
+    s32b = torch.empty_like(s64b, dtype=torch.float32)
+    flags = torch.empty(n, dtype=torch.uint8, device=DEV)
+    ws = torch.empty(vct.lib().vct_moments_workspace_size(dim, n), dtype=torch.uint8, device=DEV)
+    st, _ = vct.vct_moments_ex(g.nl, g.pos, g.vol, g.kernel, cm, m1, None, s32, m2, s64b, s32b, flags, True, ws)
+    assert st == st_ref
+    assert torch.equal(flags[:n], ref[m2][2][:n])
+    assert torch.equal(s32.view(torch.int32), ref[m1][1][:, :n].view(torch.int32))
+    assert torch.equal(s64b.view(torch.int64), ref[m2][0][:, :n].view(torch.int64))
+    assert torch.equal(s32b.view(torch.int32), ref[m2][1][:, :n].view(torch.int32))
+    with pytest.raises(vct.VctError):
+        vct.vct_moments_ex(g.nl, g.pos, g.vol, g.kernel, cm, m1, None, s32, m2 | vct.VCT_OPT_GRAD1, s64b, None,
+                           flags, False, ws)
+
+
+@pytest.mark.parametrize("family", ["sigma3d-adj", "bf2d-degenerate"])
 def test_resolve_from_kept_sums_gives_the_same_bits(family):
     """A state solved from the sums an earlier call with another mask and map
     kept equals, bit for bit, the state of a full call (flags included)."""
