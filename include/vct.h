@@ -205,7 +205,8 @@ int vct_timing_get(int idx, const char** name, int64_t* launches, double* total_
 /* A debug build of the library (compiled with VCT_DEVICE_CHECKS=1) checks on
  * the device the indices its kernels derive from the neighbour data: window
  * offsets against their window (col16 of every entry point that reads it),
- * staged neighbour offsets against the staging capacity, and the push form's
+ * the neighbour search's staged hit words and expanded rows against their
+ * buffers, and the push form's
  * accumulator indices against the column window.  A failed check sets its bit
  * (below) and the index is replaced by 0, which stays in bounds, so every
  * kernel still runs to its end; the outputs are then meaningless.
@@ -307,9 +308,11 @@ size_t vct_neighbors_workspace_size(int64_t n, int64_t ncell);
  * Otherwise the columns are written (ascending within a row), and col_t when
  * it is given (it needs col; the neighbour relation is symmetric, so every
  * entry has its transpose).  With columns requested and reuse_row_ptr == 0 the
- * search runs once: every row is staged in the workspace while it is counted,
- * then compacted behind row_ptr; when some row is longer than 128 entries the
- * search is repeated to write the columns in place.  With reuse_row_ptr != 0
+ * search runs once: the hits of every chunk's candidate window are staged in
+ * the workspace as bit words while the rows are counted, then expanded into
+ * the rows behind row_ptr; when some chunk's window is wider than 2048
+ * particles (more words than its share of the workspace holds) the search is
+ * repeated to write the columns in place.  With reuse_row_ptr != 0
  * the chunk table and row_ptr are not recomputed (they must hold the result of
  * an earlier call on the same inputs) and the search writes the columns in
  * place.  Returns VCT_E_WINDOW if some window exceeds 65535 particles (col16

@@ -304,8 +304,8 @@ constexpr int kNbWaves = 4;                    // waves per work-group
 constexpr int kNbThreads = kNbWaves * kWave;   // one chunk per work-group, lane = particle
 constexpr int kNbSeg = 1536;                   // window records per LDS segment (24 KB)
 constexpr int kNbWords = kNbSeg / 32;          // 32-candidate words per segment
-constexpr int kStage = 128;                    // staged row entries per particle
-constexpr int kRowPad = kStage + 2;            // LDS row stride of the staged rows (bank spread)
+constexpr int kStage = 128;                    // 16-bit staging slots per particle in the workspace
+constexpr int kBmWords = kStage / 2;           // hit words per particle slot: windows up to 2048 candidates
 
 // One chunk per work-group; every wave holds the whole chunk, lane = particle,
 // and takes a quarter of the window's candidates.  The window is staged in
@@ -315,13 +315,16 @@ constexpr int kRowPad = kStage + 2;            // LDS row stride of the staged r
 // inside or outside R^2 by more than a bound on its rounding error is decided
 // by it; the few near the support edge are re-tested with the exact FP64
 // predicate on the stored positions.  Hits are collected as one bit per
-// candidate (32-candidate words in LDS, [word][particle]); a per-particle
-// prefix over the waves' hit counts then places every wave's hits, in
-// ascending window order, in the particle's row.
-// MODE 0 writes the counts; MODE 1 writes the columns at row_ptr (sorted
-// indices and/or 16-bit window offsets); MODE 2 writes the counts and stages
-// the first kStage window offsets of every row at i * kStage, flagging rows
-// that do not fit (overflow[2]).  overflow[0] flags windows beyond 65535.
+// candidate (32-candidate words).
+// MODE 0 writes the counts.  MODE 1 writes the columns at row_ptr (sorted
+// indices and/or 16-bit window offsets): the words go to LDS ([word][particle])
+// and a per-particle prefix over the waves' hit counts places every wave's
+// hits, in ascending window order, in the particle's row.  MODE 2 writes the
+// counts and the chunk's hit words, [word][particle] with the chunk's np
+// particles per word, at word p0 * kBmWords of `col16` (the staging buffer),
+// for k_nb_expand to turn into rows; a window wider than kBmWords * 32
+// candidates does not fit there and is flagged (overflow[2]).  overflow[0]
+// flags windows beyond 65535.
 template <int D, int MODE>
 __global__ __launch_bounds__(kNbThreads) void k_nb_chunk(int64_t n, const double* __restrict__ pos, Grid g,
                                                          double R2, const int64_t* __restrict__ cs,
@@ -335,9 +338,9 @@ __global__ __launch_bounds__(kNbThreads) void k_nb_chunk(int64_t n, const double
                                                          int32_t* __restrict__ win_tab) {
     constexpr bool FILL = MODE == 1, STAGE = MODE == 2;
     static_assert(kChunk == kWave, "lane = particle");
-    static_assert(kChunk * kRowPad * 2 <= kNbSeg * 16, "staged rows must fit in the window buffer");
+    static_assert(kNbSeg % 32 == 0, "segments hold whole words");
     __shared__ float4 win[kNbSeg];
-    __shared__ uint32_t bm[kNbWords][kChunk];
+    __shared__ uint32_t bm[FILL ? kNbWords : 1][kChunk];
     __shared__ int32_t wcnt[kNbWaves][kChunk];
     __shared__ float wmax[kNbWaves];
     __shared__ WindowT<D> w;
@@ -371,9 +374,13 @@ __global__ __launch_bounds__(kNbThreads) void k_nb_chunk(int64_t n, const double
         const int64_t d = i - w.gstart[r];
         if (d >= 0 && d < w.off[r + 1] - w.off[r]) self_t = w.off[r] + (int)d;
     }
-    const bool single = W <= kNbSeg;   // staged rows are built in LDS only then
-    uint16_t* srow = reinterpret_cast<uint16_t*>(win);
-    int rowpos = 0;                     // entries of the row found so far
+    // the chunk's hit words (MODE 2), np per word; only when they fit its
+    // share of the staging buffer (np * kBmWords words)
+    const bool bm_fit = W <= kBmWords * 32;
+    if (STAGE && threadIdx.x == 0 && !bm_fit) atomicOr(overflow + 2, 1);
+    uint32_t* bmg = STAGE && bm_fit ? reinterpret_cast<uint32_t*>(col16) + p0 * kBmWords : nullptr;
+    int rowpos = 0;                     // entries of the row found so far (MODE 1)
+    int mycnt = 0;                      // hits of this wave's candidates (MODES 0, 2)
     for (int s0 = 0; s0 < W; s0 += kNbSeg) {
         const int sW = W - s0 < kNbSeg ? W - s0 : kNbSeg;
         if (s0 > 0) __syncthreads();   // the previous segment is consumed
@@ -430,7 +437,7 @@ __global__ __launch_bounds__(kNbThreads) void k_nb_chunk(int64_t n, const double
         const uint32_t band_u = __float_as_uint(band);
         const int nw = (sW + 31) / 32;
         const int k0 = wv * nw / kNbWaves, k1 = (wv + 1) * nw / kNbWaves;
-        int cnt = 0;
+        [[maybe_unused]] int cnt = 0;   // this segment's hits of this wave (MODE 1)
         for (int k = k0; k < k1; ++k) {
             // Hits shift in as the sign bits of t (the first candidate ends in
             // bit 31, reversed below); whether any candidate of the word lies
@@ -484,98 +491,171 @@ __global__ __launch_bounds__(kNbThreads) void k_nb_chunk(int64_t n, const double
                         bits |= 1u << u;
                 }
             }
-            bm[k][pl] = bits;
-            cnt += __popc(bits);
-        }
-        wcnt[wv][pl] = cnt;
-        __syncthreads();
-        // place this wave's hits after those of the earlier waves
-        int pos0 = rowpos, total = 0;
-#pragma unroll
-        for (int v = 0; v < kNbWaves; ++v) {
-            const int c = wcnt[v][pl];
-            if (v < wv) pos0 += c;
-            total += c;
-        }
-        if (MODE != 0 && valid) {
-            int at = pos0;
-            for (int k = k0; k < k1; ++k) {
-                uint32_t bits = bm[k][pl];
-                while (bits) {
-                    const int t = s0 + 32 * k + __builtin_ctz(bits);
-                    bits &= bits - 1u;
-                    if (STAGE && at < kStage) {
-                        if (single) srow[pl * kRowPad + at] = (uint16_t)t;
-                        else col16[i * kStage + at] = (uint16_t)t;
-                    }
-                    if (FILL && at < rlen) {
-                        if (col) col[rlo + at] = (int32_t)window_global<D>(w, t);
-                        if (col16) col16[rlo + at] = (uint16_t)t;
-                    }
-                    ++at;
-                }
+            if constexpr (FILL) {
+                bm[k][pl] = bits;
+                cnt += __popc(bits);
+            } else {
+                if (STAGE && bmg && valid)
+                    bmg[dcheck((s0 / 32 + k) * np + pl, np * kBmWords, kChkCapacity)] = bits;
+                mycnt += __popc(bits);
             }
         }
-        rowpos += total;
+        // MODES 0 and 2 sum the counts once, after the last segment
+        if constexpr (FILL) {
+            wcnt[wv][pl] = cnt;
+            __syncthreads();
+            // place this wave's hits after those of the earlier waves
+            int pos0 = rowpos, total = 0;
+#pragma unroll
+            for (int v = 0; v < kNbWaves; ++v) {
+                const int c = wcnt[v][pl];
+                if (v < wv) pos0 += c;
+                total += c;
+            }
+            if (valid) {
+                int at = pos0;
+                for (int k = k0; k < k1; ++k) {
+                    uint32_t bits = bm[k][pl];
+                    while (bits) {
+                        const int t = s0 + 32 * k + __builtin_ctz(bits);
+                        bits &= bits - 1u;
+                        if (at < rlen) {
+                            if (col) col[rlo + at] = (int32_t)window_global<D>(w, t);
+                            if (col16) col16[rlo + at] = (uint16_t)t;
+                        }
+                        ++at;
+                    }
+                }
+            }
+            rowpos += total;
+        }
     }
-    if (!FILL && wv == 0 && valid) {
-        counts[i] = rowpos;
-        if (STAGE && rowpos > kStage) atomicOr(overflow + 2, 1);
-    }
-    if (STAGE && single) {   // the chunk's staged rows, contiguous at p0 * kStage
+    if constexpr (!FILL) {
+        wcnt[wv][pl] = mycnt;
         __syncthreads();
-        const uint32_t* src = reinterpret_cast<const uint32_t*>(srow);
-        uint32_t* dst = reinterpret_cast<uint32_t*>(col16 + p0 * kStage);
-        for (int k = threadIdx.x; k < np * (kStage / 2); k += kNbThreads) {
-            const int r = k / (kStage / 2), c = k % (kStage / 2);
-            dst[k] = src[r * (kRowPad / 2) + c];
+        if (wv == 0 && valid) {
+            int c = 0;
+#pragma unroll
+            for (int v = 0; v < kNbWaves; ++v) c += wcnt[v][pl];
+            counts[i] = c;
         }
     }
 }
 
-// Copy every staged row to its place in the column arrays (offsets, and
-// sorted indices through the chunk window when col is wanted).  The chunk's
-// staged rows are one contiguous block, read into LDS with 16-byte loads;
-// a row map in LDS gives each output entry its row, and the work-group walks
-// the chunk's contiguous output range one entry per thread.  Every row of
-// the chunk holds at most kStage entries (the caller checks the flag first).
+// Turn every chunk's hit words (written by k_nb_chunk in MODE 2) into its
+// rows behind row_ptr: 16-bit window offsets, and sorted indices through the
+// chunk window when col is wanted.  The words are [word][particle], np
+// particles per word.  Lane = particle, and the eight waves take an eighth of
+// the words each: every non-empty (word, particle) gets its first output
+// position (the row's start, the earlier waves' share of the row, the hits
+// before the word) and goes into a list ordered by its number of hits (a
+// counting sort in LDS).  Taken in that order, the lanes of a wave expand
+// words with about the same number of hits, so the loop over a word's bits
+// does not wait for the fullest word of 64.  The positions are fixed before
+// the expansion, so its order does not matter.  The entries go to the chunk's
+// block in LDS, which the work-group stores with unit stride; a chunk whose
+// block exceeds the LDS buffer writes its entries to memory directly.
+constexpr int kExT = 512;                     // threads of k_nb_expand
+constexpr int kExOut = 8192;                  // entries of a chunk's block in LDS (16 KB)
 template <int D>
-__global__ __launch_bounds__(512) void k_nb_compact(Grid g, const int64_t* __restrict__ cs,
+__global__ __launch_bounds__(kExT) void k_nb_expand(Grid g, const int64_t* __restrict__ cs,
                                                     const int32_t* __restrict__ cstart,
                                                     const int4* __restrict__ cinfo,
                                                     const int64_t* __restrict__ nchunks,
                                                     const int64_t* __restrict__ row_ptr,
-                                                    const uint16_t* __restrict__ staged,
+                                                    const uint32_t* __restrict__ words,
+                                                    const int32_t* __restrict__ win_tab,
                                                     int32_t* __restrict__ col, uint16_t* __restrict__ col16) {
-    constexpr int kT = 512, kRowLanes = kT / kChunk;
+    constexpr int kWaves = kExT / kWave;
+    constexpr int kPer = kBmWords / kWaves;   // words of one wave's share
+    static_assert(kBmWords % kWaves == 0 && kChunk == kWave, "shares of whole words, lane = particle");
     __shared__ WindowT<D> w;
     __shared__ int64_t rp[kChunk + 1];
-    __shared__ uint4 srow4[kChunk * kStage / 8];
-    __shared__ uint8_t rowof[kChunk * kStage];
-    const uint16_t* srow = reinterpret_cast<const uint16_t*>(srow4);
+    __shared__ int32_t part[kWaves][kChunk];      // each wave's share of every row
+    __shared__ uint32_t bucket[33];               // words per hit count (32 - count), then offsets
+    __shared__ uint2 list[kBmWords * kChunk];     // (bits, position | word << 24)
+    __shared__ uint16_t sout[kExOut];
     const uint32_t b = xcd_tile(blockIdx.x, gridDim.x);
     if (b >= *nchunks) return;   // uniform over the work-group
     const int64_t p0 = cstart[b];
     const int np = (int)(cstart[b + 1] - p0);
-    if (col && threadIdx.x < kWave) chunk_window_wave<D>(g, cs, cinfo[b], w);
+    const int wv = threadIdx.x / kWave, pl = threadIdx.x % kWave;
+    if (wv == 0) {
+        if (win_tab) window_load<D>(win_tab, b, w);
+        else chunk_window_wave<D>(g, cs, cinfo[b], w);
+    }
     if (threadIdx.x <= (unsigned)np) rp[threadIdx.x] = row_ptr[p0 + threadIdx.x];
-    const uint4* src = reinterpret_cast<const uint4*>(staged + p0 * kStage);
-    for (int k = threadIdx.x; k < np * (kStage / 8); k += kT) srow4[k] = src[k];
+    if (threadIdx.x < 33) bucket[threadIdx.x] = 0u;
     __syncthreads();
+    // at most kBmWords words: the search flags wider windows, and the host
+    // then runs the fill pass instead
+    const int nw = dcheck((w.off[w.nr] + 31) / 32, kBmWords + 1, kChkCapacity);
+    const uint32_t* src = words + p0 * kBmWords;
+    const int k0 = wv * kPer;
+    const bool lane_on = pl < np;
     const int64_t e0 = rp[0], e1 = rp[np];
+    uint32_t v[kPer];
+    int before[kPer];   // hits of the row in this wave's share before each word
     {
-        const int r = threadIdx.x / kRowLanes;
-        if (r < np) {
-            const int a0 = (int)(rp[r] - e0), a1 = (int)(rp[r + 1] - e0);
-            for (int k = a0 + (int)(threadIdx.x % kRowLanes); k < a1; k += kRowLanes) rowof[k] = (uint8_t)r;
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) v[u] = (lane_on && k0 + u < nw) ? src[(k0 + u) * np + pl] : 0u;
+        int c = 0;
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            before[u] = c;
+            c += __popc(v[u]);
+        }
+        part[wv][pl] = c;
+    }
+    __syncthreads();
+    int start = lane_on ? (int)(rp[pl] - e0) : 0;
+    for (int x = 0; x < wv; ++x) start += part[x][pl];
+    uint32_t slot[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) slot[u] = v[u] ? atomicAdd(&bucket[32 - __popc(v[u])], 1u) : 0u;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t acc = 0;
+        for (int c = 0; c < 33; ++c) {
+            const uint32_t t = bucket[c];
+            bucket[c] = acc;
+            acc += t;
         }
     }
     __syncthreads();
-    for (int64_t e = e0 + threadIdx.x; e < e1; e += kT) {
-        const int r = rowof[dcheck((int)(e - e0), kChunk * kStage, kChkCapacity)];
-        const uint16_t t = srow[r * kStage + dcheck((int)(e - rp[r]), kStage, kChkCapacity)];
-        if (col16) col16[e] = t;
-        if (col) col[e] = (int32_t)window_global<D>(w, t);
+#pragma unroll
+    for (int u = 0; u < kPer; ++u)
+        if (v[u]) {
+            const uint32_t at = (uint32_t)(start + before[u]);
+            list[dcheck((int)(bucket[32 - __popc(v[u])] + slot[u]), kBmWords * kChunk, kChkCapacity)] =
+                make_uint2(v[u], at | ((uint32_t)(k0 + u) << 24));
+        }
+    __syncthreads();
+    const bool in_lds = e1 - e0 <= kExOut;
+    const int nlist = (int)bucket[32];   // every listed word (words without hits are not listed)
+    for (int li = threadIdx.x; li < nlist; li += kExT) {
+        const uint2 ent = list[li];
+        uint32_t bits = ent.x;
+        int at = (int)(ent.y & 0xffffffu);
+        const int wd = (int)(ent.y >> 24);
+        while (bits) {
+            const uint16_t t = (uint16_t)(32 * wd + __builtin_ctz(bits));
+            bits &= bits - 1u;
+            if (in_lds) {
+                sout[dcheck(at, kExOut, kChkCapacity)] = t;
+            } else {
+                if (col16) col16[e0 + at] = t;
+                if (col) col[e0 + at] = (int32_t)window_global<D>(w, t);
+            }
+            ++at;
+        }
+    }
+    if (!in_lds) return;   // uniform over the work-group
+    __syncthreads();
+    for (int e = threadIdx.x; e < (int)(e1 - e0); e += kExT) {
+        const uint16_t t = sout[e];
+        if (col16) col16[e0 + e] = t;
+        if (col) col[e0 + e] = (int32_t)window_global<D>(w, t);
     }
 }
 
@@ -789,12 +869,12 @@ static int launch_nb(const vct_nlist* nl, const double* pos, const Grid& g, int3
 }
 
 template <int D>
-static int launch_compact(const vct_nlist* nl, const Grid& g, const uint16_t* staged, hipStream_t s) {
+static int launch_expand(const vct_nlist* nl, const Grid& g, const uint16_t* staged, hipStream_t s) {
     const int64_t ncols = D == 3 ? g.nc[0] * g.nc[1] : g.nc[0];
     const int64_t cap = ncols + nl->n / kChunk + 1;
-    VCT_LAUNCH("k_nb_compact", (k_nb_compact<D>), dim3((unsigned)cap), dim3(512), 0, s, g, nl->cell_start,
+    VCT_LAUNCH("k_nb_expand", (k_nb_expand<D>), dim3((unsigned)cap), dim3(kExT), 0, s, g, nl->cell_start,
                nl->chunk_start, reinterpret_cast<const int4*>(nl->chunk_info), nl->chunk_off + ncols,
-               nl->row_ptr, staged, nl->col, nl->col16);
+               nl->row_ptr, reinterpret_cast<const uint32_t*>(staged), nl->chunk_win, nl->col, nl->col16);
     VCT_LAUNCH_CHECK();
     return VCT_OK;
 }
@@ -818,7 +898,7 @@ extern "C" int vct_neighbors(vct_nlist* nl, const double* pos_sorted, int64_t co
     const int D = nl->dim;
     const bool want_cols = nl->col || nl->col16;
     // flag[0]: window wider than 16-bit offsets; flag[1]: transpose miss;
-    // flag[2]: a row longer than the staging capacity
+    // flag[2]: a window whose hit words exceed the staging capacity
     if ((st = fill_i32(flag, 3, 0, s))) return st;
     bool staged_ok = false;
     if (!reuse_row_ptr) {
@@ -849,8 +929,8 @@ extern "C" int vct_neighbors(vct_nlist* nl, const double* pos_sorted, int64_t co
     if (hflag[0]) return VCT_E_WINDOW;
     if (n > 0) {
         if (staged_ok && !hflag[2])
-            st = (D == 2) ? launch_compact<2>(nl, g, staged, s) : launch_compact<3>(nl, g, staged, s);
-        else   // rows too long for the staging buffer, or row_ptr given: the fill pass
+            st = (D == 2) ? launch_expand<2>(nl, g, staged, s) : launch_expand<3>(nl, g, staged, s);
+        else   // a window too wide for the staged hit words, or row_ptr given: the fill pass
             st = (D == 2) ? launch_nb<2, 1>(nl, pos_sorted, g, nullptr, flag, nullptr, s)
                           : launch_nb<3, 1>(nl, pos_sorted, g, nullptr, flag, nullptr, s);
         if (st) return st;

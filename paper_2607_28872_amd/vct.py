@@ -476,8 +476,9 @@ class Geometry:
         self.nl = make_nlist(self.dim, n, self.ncell, lo, hi, R, self.cell_start, self.chunk_off, self.chunk_start,
                              self.chunk_info, self.row_ptr, self.col, self.col16, chunk_cap=cap, col_t=self.col_t,
                              chunk_win=self.chunk_win)
-        # one search that stages the rows and compacts them (falling back to
-        # the fill pass by itself when a row is longer than the staging rows)
+        # one search that stages the hit words and expands them into rows
+        # (falling back to the fill pass by itself when a window is wider than
+        # the staged words can describe)
         _, nnz2 = vct_neighbors(self.nl, self.pos, max(nnz, 1), 0, self._nws)
         if nnz2 != nnz:
             raise VctError("vct_neighbors", VCT_E_HIP)

@@ -78,7 +78,7 @@ def test_neighbor_lists_on_an_unjittered_lattice(dim):
 
 @pytest.mark.parametrize("family", FAMILIES)
 def test_staged_search_equals_fill_pass(family):
-    """The one-search path (rows staged, then compacted) writes the same
+    """The one-search path (hit words staged, then expanded) writes the same
     columns, offsets and transposed-entry map as the count + fill passes."""
     w = I.small(family)
     g = _geom(w)
@@ -117,6 +117,63 @@ def test_long_rows_fall_back_to_the_fill_pass():
     orp, ocol = O.neighbors(w.pos, R)
     assert np.array_equal(rp, orp)
     assert np.array_equal(col, ocol)
+
+
+def _col16_through_windows(g):
+    """Sorted indices of the 16-bit window offsets, through each chunk's
+    stored window (nr, then nine int64 range starts, then the ten range
+    offsets, as int32 words)."""
+    win = g.chunk_win.cpu().numpy()
+    nch = int(g.chunk_off[-1].item())
+    cs = g.chunk_start[: nch + 1].cpu().numpy().astype(np.int64)
+    rp = g.row_ptr.cpu().numpy()
+    t = g.col16[: g.nnz].cpu().numpy().astype(np.int64)
+    chunk = np.searchsorted(cs, np.arange(g.n), side="right") - 1
+    be = np.repeat(chunk, np.diff(rp))
+    gstart = np.ascontiguousarray(win[:nch, 2:20]).view(np.int64)
+    off = win[:nch, 20:30].astype(np.int64)
+    r = np.zeros_like(t)
+    for k in range(1, 9):
+        r = np.where((k < win[be, 0]) & (t >= off[be, k]), k, r)
+    return gstart[be, r] + (t - off[be, r])
+
+
+def test_hit_words_and_fill_pass_give_the_oracle_lists():
+    """The single search writes each chunk's hit words and expands them into
+    rows; a window wider than the words' capacity (2048 candidates) makes the
+    search run again to fill the rows in place.  Both routes, with windows over
+    several LDS segments and rows beyond 128 entries on the first, give the
+    oracle's lists bit for bit (sorted indices and 16-bit window offsets)."""
+    w = I.small("sigma3d")
+    seen = {}
+    for Rs in (1.0, 1.15, 1.3, 1.45, 1.6):
+        R = Rs * w.R
+        vct.vct_timing_reset()
+        vct.vct_timing_enable(True)
+        try:
+            g = _geom(w, R=R)
+            torch.cuda.synchronize()
+        finally:
+            vct.vct_timing_enable(False)
+        t = vct.vct_timing_read()
+        vct.vct_timing_reset()
+        win = g.chunk_win.cpu().numpy()
+        nch = int(g.chunk_off[-1].item())
+        widest = int(win[np.arange(nch), 20 + win[:nch, 0]].max())
+        rp, col = g.csr_original()
+        longest = int(np.diff(rp).max())
+        route = "fill" if "k_nb_chunk (fill)" in t else "words"
+        print(f"\nR = {Rs} R0: widest window {widest}, longest row {longest}, route {route}")
+        assert ("k_nb_expand" in t) == (route == "words")
+        assert (route == "fill") == (widest > 2048)
+        orp, ocol = O.neighbors(w.pos, R)
+        assert np.array_equal(rp, orp)
+        assert np.array_equal(col, ocol)
+        # the 16-bit offsets address the same particles through each chunk's window
+        assert np.array_equal(_col16_through_windows(g), g.col[: g.nnz].cpu().numpy())
+        seen.setdefault(route, []).append((widest, longest))
+    assert set(seen) == {"words", "fill"}
+    assert max(wd for wd, _ in seen["words"]) > 1536 and max(ln for _, ln in seen["words"]) > 128
 
 
 def test_windows_beyond_the_lds_capacity():
@@ -584,6 +641,6 @@ def test_launch_timing_records_each_kernel():
     t = vct.vct_timing_read()
     vct.vct_timing_reset()
     assert t["k_apply (fp64)"][0] == 2 and t["k_apply (fp64)"][1] > 0.0
-    for k in ("k_cell_keys", "k_nb_chunk (count)", "k_nb_chunk (stage)", "k_nb_compact", "k_moment_sweeps",
+    for k in ("k_cell_keys", "k_nb_chunk (count)", "k_nb_chunk (stage)", "k_nb_expand", "k_moment_sweeps",
               "k_moment_solve"):
         assert t[k][0] >= 1, k
