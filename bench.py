@@ -200,6 +200,11 @@ def main():
 
     stream = torch.cuda.current_stream()
     stage_names = ["cells", "nb", "moments", "apply", "moments_adj", "adjoint"]
+    # the sorted copies of the volumes and fields are gathered on a second
+    # stream (default priority) while the neighbour search, which reads only
+    # the sorted positions, runs on the first
+    side = torch.cuda.Stream(device=dev)
+    ev_perm, ev_fields = torch.cuda.Event(), torch.cuda.Event()
 
     def ev():
         e = torch.cuda.Event(enable_timing=True)
@@ -214,9 +219,13 @@ def main():
                 marks.append(ev())
 
         vct.vct_build_cells(dim, n, pos, w.lo, w.hi, w.R, perm, pos_s, cell_start, ncell, ws_cells)
-        vct.vct_gather_sorted(n, 2 + nf, perm, fields_in, fields_s)
+        ev_perm.record(stream)
+        side.wait_event(ev_perm)
+        vct.vct_gather_sorted(n, 2 + nf, perm, fields_in, fields_s, stream=side)
+        ev_fields.record(side)
         mark()
         vct.vct_neighbors(nl, pos_s, nnz, 0, ws_nb)
+        stream.wait_event(ev_fields)
         mark()
         # the forward only runs the mixed apply: the FP32 state is all it reads
         # (its solve also folds the backward's FP64 rows from the same inverse)

@@ -452,7 +452,12 @@ size_t vct_adjoint_workspace_size(int dim, int64_t n, int64_t nnz, int nterms);
  * dtheta [map->nterms] are device outputs; either may be NULL.  A term that
  * is not finite makes the outputs it reaches NaN.  The workspace holds
  * nnz + (1 + 3^(d-1)) n doubles and the reduction partials
- * (vct_adjoint_workspace_size, with nnz = nl->nnz).                            */
+ * (vct_adjoint_workspace_size, with nnz = nl->nnz).  When both dphi and
+ * dtheta are wanted, dtheta is computed on a second stream of the calling
+ * host thread (created on its first such call on the device, default
+ * priority, kept until the process ends), forked from `stream` and joined
+ * back into it by events: the outputs are complete in `stream` order as for
+ * one stream.                                                                  */
 int vct_apply_ops_adjoint(const vct_nlist* nl, const double* pos_sorted, const double* vol_sorted, int kernel,
                           const double* state64, uint32_t out_mask, const vct_map* map /* host */,
                           const double* proj, const double* u, double* dphi, double* dtheta, void* ws,

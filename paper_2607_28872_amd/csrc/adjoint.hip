@@ -1033,10 +1033,61 @@ __global__ __launch_bounds__(kRedThreads) void k_dtheta_final(int64_t nblocks, i
     if (threadIdx.x == 0) dtheta[t] = red[0];
 }
 
+// A second stream of the calling thread on the current device (default
+// priority), with the two events of a fork and join, made on first use and
+// kept until the process ends: the d/dtheta reduction, which only reads the
+// inputs, runs there beside the d/dphi kernels.  Per thread, so calls from
+// several host threads do not share the events.
+struct SideStream {
+    hipStream_t s = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+};
+static int side_stream(SideStream** out) {
+    constexpr int kDev = 64;
+    thread_local SideStream side[kDev];
+    int dev = -1;
+    VCT_HIP_CHECK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kDev) return VCT_E_ARG;
+    SideStream& ss = side[dev];
+    if (!ss.s) {
+        VCT_HIP_CHECK(hipEventCreateWithFlags(&ss.fork, hipEventDisableTiming));
+        VCT_HIP_CHECK(hipEventCreateWithFlags(&ss.join, hipEventDisableTiming));
+        VCT_HIP_CHECK(hipStreamCreateWithFlags(&ss.s, hipStreamNonBlocking));
+    }
+    *out = &ss;
+    return VCT_OK;
+}
+
+template <int D>
+static int launch_dtheta(const AdjArgs& a, const MapParams& mp, double* dtheta, double* partials, hipStream_t s) {
+    const int64_t nred = (a.n + kRedThreads - 1) / kRedThreads;
+    VCT_LAUNCH("k_dtheta_partials", (k_dtheta_partials<D>), dim3((unsigned)nred), dim3(kRedThreads), 0, s, a, mp,
+               partials);
+    VCT_LAUNCH_CHECK();
+    VCT_LAUNCH("k_dtheta_final", k_dtheta_final, dim3((unsigned)mp.nterms), dim3(kRedThreads), 0, s, nred,
+               mp.nterms, partials, dtheta);
+    VCT_LAUNCH_CHECK();
+    return VCT_OK;
+}
+
+// overlap: run d/dtheta on the calling thread's second stream, forked from
+// and joined back into s (not for the allocation-free entry point, whose
+// first call must not create streams)
 template <int D, int KERNEL>
 static int launch_adjoint(AdjArgs a, int64_t cap, const MapParams& mp, double* dtheta, double* partials,
-                          hipStream_t s) {
+                          bool overlap, hipStream_t s) {
     const int64_t n = a.n;
+    const bool want_dtheta = dtheta && mp.nterms > 0;
+    SideStream* side = nullptr;
+    if (overlap && want_dtheta && a.dphi) {
+        int st = side_stream(&side);
+        if (st) return st;
+        VCT_HIP_CHECK(hipEventRecord(side->fork, s));
+        VCT_HIP_CHECK(hipStreamWaitEvent(side->s, side->fork, 0));
+        st = launch_dtheta<D>(a, mp, dtheta, partials, side->s);
+        if (st) return st;
+        VCT_HIP_CHECK(hipEventRecord(side->join, side->s));
+    }
     if (a.dphi && a.col_t) {
         VCT_LAUNCH("k_adjoint_weights", (k_adjoint_weights<D, KERNEL>), dim3((unsigned)cap), dim3(kAThreads), 0, s, a);
         VCT_LAUNCH_CHECK();
@@ -1059,14 +1110,11 @@ static int launch_adjoint(AdjArgs a, int64_t cap, const MapParams& mp, double* d
                    n, a.g, a.pos, a.partial, a.dphi);
         VCT_LAUNCH_CHECK();
     }
-    if (dtheta && mp.nterms > 0) {
-        const int64_t nred = (n + kRedThreads - 1) / kRedThreads;
-        VCT_LAUNCH("k_dtheta_partials", (k_dtheta_partials<D>), dim3((unsigned)nred), dim3(kRedThreads), 0, s, a,
-                   mp, partials);
-        VCT_LAUNCH_CHECK();
-        VCT_LAUNCH("k_dtheta_final", k_dtheta_final, dim3((unsigned)mp.nterms), dim3(kRedThreads), 0, s, nred,
-                   mp.nterms, partials, dtheta);
-        VCT_LAUNCH_CHECK();
+    if (side) {
+        VCT_HIP_CHECK(hipStreamWaitEvent(s, side->join, 0));
+    } else if (want_dtheta) {
+        const int st = launch_dtheta<D>(a, mp, dtheta, partials, s);
+        if (st) return st;
     }
     return VCT_OK;
 }
@@ -1195,14 +1243,15 @@ static int adjoint_run(const vct_nlist* nl, const double* pos_sorted, const doub
     a.nrows = n_out_rows(dim, out_mask);
     a.wbuf = wbuf; a.rowsum = rowsum; a.partial = partial; a.wide = wide; a.dphi = dphi;
     const int64_t cap = ncols + n / kChunk + 1;
+    const bool overlap = !push_only;   // the allocation-free entry point makes no stream
     if (dim == 2)
         st = (kernel == VCT_KERNEL_WENDLAND_C2)
-                 ? launch_adjoint<2, VCT_KERNEL_WENDLAND_C2>(a, cap, mp, dtheta, partials, s)
-                 : launch_adjoint<2, VCT_KERNEL_CUBIC_SPLINE>(a, cap, mp, dtheta, partials, s);
+                 ? launch_adjoint<2, VCT_KERNEL_WENDLAND_C2>(a, cap, mp, dtheta, partials, overlap, s)
+                 : launch_adjoint<2, VCT_KERNEL_CUBIC_SPLINE>(a, cap, mp, dtheta, partials, overlap, s);
     else
         st = (kernel == VCT_KERNEL_WENDLAND_C2)
-                 ? launch_adjoint<3, VCT_KERNEL_WENDLAND_C2>(a, cap, mp, dtheta, partials, s)
-                 : launch_adjoint<3, VCT_KERNEL_CUBIC_SPLINE>(a, cap, mp, dtheta, partials, s);
+                 ? launch_adjoint<3, VCT_KERNEL_WENDLAND_C2>(a, cap, mp, dtheta, partials, overlap, s)
+                 : launch_adjoint<3, VCT_KERNEL_CUBIC_SPLINE>(a, cap, mp, dtheta, partials, overlap, s);
     return st;
 }
 
