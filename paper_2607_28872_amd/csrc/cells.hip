@@ -552,11 +552,15 @@ __global__ __launch_bounds__(kNbThreads) void k_nb_chunk(int64_t n, const double
 // counting sort in LDS).  Taken in that order, the lanes of a wave expand
 // words with about the same number of hits, so the loop over a word's bits
 // does not wait for the fullest word of 64.  The positions are fixed before
-// the expansion, so its order does not matter.  The entries go to the chunk's
-// block in LDS, which the work-group stores with unit stride; a chunk whose
-// block exceeds the LDS buffer writes its entries to memory directly.
+// the expansion, so its order does not matter.  A list entry is 4 bytes (the
+// particle, the word and the hits of the row before it; the word's bits are
+// read again from the L2), which keeps the LDS at four work-groups per CU.
+// The entries go to the chunk's block in LDS, which the work-group stores
+// with unit stride; a chunk whose block exceeds the LDS buffer writes its
+// entries to memory directly.
 constexpr int kExT = 512;                     // threads of k_nb_expand
 constexpr int kExOut = 8192;                  // entries of a chunk's block in LDS (16 KB)
+constexpr int kExList = kBmWords * kChunk;    // every (word, particle) of a chunk can be listed (16 KB)
 template <int D>
 __global__ __launch_bounds__(kExT) void k_nb_expand(Grid g, const int64_t* __restrict__ cs,
                                                     const int32_t* __restrict__ cstart,
@@ -573,7 +577,7 @@ __global__ __launch_bounds__(kExT) void k_nb_expand(Grid g, const int64_t* __res
     __shared__ int64_t rp[kChunk + 1];
     __shared__ int32_t part[kWaves][kChunk];      // each wave's share of every row
     __shared__ uint32_t bucket[33];               // words per hit count (32 - count), then offsets
-    __shared__ uint2 list[kBmWords * kChunk];     // (bits, position | word << 24)
+    __shared__ uint32_t list[kExList];            // particle | word << 6 | hits of the row before it << 12
     __shared__ uint16_t sout[kExOut];
     const uint32_t b = xcd_tile(blockIdx.x, gridDim.x);
     if (b >= *nchunks) return;   // uniform over the work-group
@@ -608,36 +612,32 @@ __global__ __launch_bounds__(kExT) void k_nb_expand(Grid g, const int64_t* __res
         part[wv][pl] = c;
     }
     __syncthreads();
-    int start = lane_on ? (int)(rp[pl] - e0) : 0;
+    int start = 0;   // hits of the row in the earlier waves' shares
     for (int x = 0; x < wv; ++x) start += part[x][pl];
     uint32_t slot[kPer];
 #pragma unroll
     for (int u = 0; u < kPer; ++u) slot[u] = v[u] ? atomicAdd(&bucket[32 - __popc(v[u])], 1u) : 0u;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t acc = 0;
-        for (int c = 0; c < 33; ++c) {
-            const uint32_t t = bucket[c];
-            bucket[c] = acc;
-            acc += t;
+    if (wv == 0) {   // exclusive prefix of the 32 bucket sizes; bucket[32] = the total
+        const uint32_t t = pl < 32 ? bucket[pl] : 0u;
+        uint32_t incl = t;
+#pragma unroll
+        for (int m = 1; m < 64; m <<= 1) {
+            const uint32_t o = __shfl_up(incl, m, kWave);
+            if (pl >= m) incl += o;
         }
+        if (pl <= 32) bucket[pl] = incl - t;
     }
     __syncthreads();
+    const int nlist = (int)bucket[32];   // the non-empty words (words without hits are not listed)
 #pragma unroll
     for (int u = 0; u < kPer; ++u)
-        if (v[u]) {
-            const uint32_t at = (uint32_t)(start + before[u]);
-            list[dcheck((int)(bucket[32 - __popc(v[u])] + slot[u]), kBmWords * kChunk, kChkCapacity)] =
-                make_uint2(v[u], at | ((uint32_t)(k0 + u) << 24));
-        }
+        if (v[u])
+            list[dcheck((int)(bucket[32 - __popc(v[u])] + slot[u]), kExList, kChkCapacity)] =
+                (uint32_t)pl | ((uint32_t)(k0 + u) << 6) | ((uint32_t)(start + before[u]) << 12);
     __syncthreads();
     const bool in_lds = e1 - e0 <= kExOut;
-    const int nlist = (int)bucket[32];   // every listed word (words without hits are not listed)
-    for (int li = threadIdx.x; li < nlist; li += kExT) {
-        const uint2 ent = list[li];
-        uint32_t bits = ent.x;
-        int at = (int)(ent.y & 0xffffffu);
-        const int wd = (int)(ent.y >> 24);
+    auto expand = [&](uint32_t bits, int at, int wd) {
         while (bits) {
             const uint16_t t = (uint16_t)(32 * wd + __builtin_ctz(bits));
             bits &= bits - 1u;
@@ -649,6 +649,11 @@ __global__ __launch_bounds__(kExT) void k_nb_expand(Grid g, const int64_t* __res
             }
             ++at;
         }
+    };
+    for (int li = threadIdx.x; li < nlist; li += kExT) {
+        const uint32_t ent = list[li];
+        const int q = (int)(ent & 63u), wd = (int)((ent >> 6) & 63u);
+        expand(src[wd * np + q], (int)(rp[q] - e0) + (int)(ent >> 12), wd);
     }
     if (!in_lds) return;   // uniform over the work-group
     __syncthreads();

@@ -163,7 +163,14 @@ def test_hit_words_and_fill_pass_give_the_oracle_lists():
         rp, col = g.csr_original()
         longest = int(np.diff(rp).max())
         route = "fill" if "k_nb_chunk (fill)" in t else "words"
-        print(f"\nR = {Rs} R0: widest window {widest}, longest row {longest}, route {route}")
+        # non-empty (word, particle) pairs of every chunk, from the 16-bit offsets
+        srp = g.row_ptr.cpu().numpy()
+        cs = g.chunk_start[: nch + 1].cpu().numpy().astype(np.int64)
+        part_of = np.repeat(np.arange(g.n), np.diff(srp))
+        words = np.unique(part_of * 64 + g.col16[: g.nnz].cpu().numpy().astype(np.int64) // 32)
+        nonempty = np.bincount(np.searchsorted(cs, words // 64, side="right") - 1, minlength=nch)
+        print(f"\nR = {Rs} R0: widest window {widest}, longest row {longest}, route {route}, "
+              f"most non-empty words in a chunk {nonempty.max()}")
         assert ("k_nb_expand" in t) == (route == "words")
         assert (route == "fill") == (widest > 2048)
         orp, ocol = O.neighbors(w.pos, R)
