@@ -503,6 +503,11 @@ __global__ __launch_bounds__(ApplyCfg<T>::threads, ApplyCfg<T>::waves) void k_ap
         double Gp[D];
 #pragma unroll
         for (int a = 0; a < D; ++a) Gp[a] = Scaled<T>::value ? (double)Gt[a] : (double)Gt[a] * A.invR;
+        // G~ waits for the epilogue in LDS, not in registers
+        if (lane == 0) {
+#pragma unroll
+            for (int a = 0; a < D; ++a) sacc[pl][nk + a] = Gt[a];
+        }
         // pass 2: sums of the residual psi_ij = phi_ij - (x_j - x_i) . G.
         // The empty asm makes the packed offsets opaque, so the record
         // addresses are recomputed here instead of being kept live from pass 1.
@@ -559,8 +564,6 @@ __global__ __launch_bounds__(ApplyCfg<T>::threads, ApplyCfg<T>::waves) void k_ap
         if (lane == 0) {
 #pragma unroll
             for (int c = 0; c < nk; ++c) sacc[pl][c] = acc[c];
-#pragma unroll
-            for (int a = 0; a < D; ++a) sacc[pl][nk + a] = Gt[a];
         }
         __syncthreads();
         {
@@ -570,7 +573,7 @@ __global__ __launch_bounds__(ApplyCfg<T>::threads, ApplyCfg<T>::waves) void k_ap
                 for (int o = threadIdx.x / kChunk; o < A.nrows; o += kThreads / kChunk)
                     A.out[((int64_t)f * n + iq) * A.nrows + o] =
                         out_row<D, T, S>(A, iq, o, &sacc[q][0], &sacc[q][nk]);
-                if (A.g_out && threadIdx.x < kChunk)
+                if (!GIN && A.g_out && threadIdx.x < kChunk)   // the given-G form writes no G~
 #pragma unroll
                     for (int a = 0; a < D; ++a) A.g_out[((int64_t)f * D + a) * n + iq] = (float)sacc[q][nk + a];
             }
