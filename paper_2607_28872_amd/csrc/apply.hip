@@ -214,9 +214,14 @@ __device__ __forceinline__ double out_row(const ApplyArgs<S>& A, int64_t i, int 
     return (double)v + (double)lin * A.invR;
 }
 
+// What a launch does with the first-pass gradient G~: nothing, read it
+// (FP64 form: the first pass is skipped) or write it.  Separate
+// instantiations, so that a form without the gradient pays no registers for it.
+enum { kGNone = 0, kGIn = 1, kGOut = 2 };
+
 // A chunk whose window exceeds the LDS capacity: the same two passes with
 // every record read from the memory hierarchy.
-template <int D, int KERNEL, class T, class S>
+template <int D, int KERNEL, class T, class S, bool GOUT>
 __device__ __forceinline__ void apply_chunk_global(const ApplyArgs<S>& A, const WindowT<D>& w, int64_t p0,
                                                 int64_t p1) {
     constexpr int nk = Dims<D>::nk, kLanes = ApplyCfg<T>::lanes;
@@ -254,7 +259,7 @@ __device__ __forceinline__ void apply_chunk_global(const ApplyArgs<S>& A, const 
             for (int a = 0; a < D; ++a) a1[a] += wgt * r[a];
         }
         group_gradient<D, T>(L2, a1, Gt);
-        if (A.g_out && lane == 0) {
+        if (GOUT && lane == 0) {
 #pragma unroll
             for (int a = 0; a < D; ++a) A.g_out[((int64_t)f * D + a) * n + i] = (float)Gt[a];
         }
@@ -283,10 +288,10 @@ __device__ __forceinline__ void apply_chunk_global(const ApplyArgs<S>& A, const 
     }
 }
 
-// GIN: the FP64 form reads G~ from A.g_in instead of running the first pass
-// (a separate instantiation, so the other forms keep their registers).
-template <int D, int KERNEL, class T, class S, bool GIN>
+// GM (kGNone, kGIn, kGOut): what the launch does with G~.
+template <int D, int KERNEL, class T, class S, int GM>
 __global__ __launch_bounds__(ApplyCfg<T>::threads, ApplyCfg<T>::waves) void k_apply(ApplyArgs<S> A) {
+    constexpr bool GIN = GM == kGIn, GOUT = GM == kGOut;
     static_assert(!GIN || !Scaled<T>::value, "only the FP64 form takes a given gradient");
     using Dm = Dims<D>;
     constexpr int nk = Dm::nk, kS = ApplyCfg<T>::slots, kW = ApplyCfg<T>::win;
@@ -325,7 +330,7 @@ __global__ __launch_bounds__(ApplyCfg<T>::threads, ApplyCfg<T>::waves) void k_ap
     __syncthreads();
     const int W = __builtin_amdgcn_readfirstlane(w.off[w.nr]);
     if (W > kW) {
-        apply_chunk_global<D, KERNEL, T, S>(A, w, p0, p1);
+        apply_chunk_global<D, KERNEL, T, S, GOUT>(A, w, p0, p1);
         return;
     }
     // stage the window records and the chunk's row entries, in batches of
@@ -569,11 +574,16 @@ __global__ __launch_bounds__(ApplyCfg<T>::threads, ApplyCfg<T>::waves) void k_ap
         {
             const int q = threadIdx.x % kChunk;
             const int64_t iq = p0 + q;
+            // the row index made opaque here, so that the state addresses are
+            // formed now rather than kept in registers (or spilled) from the
+            // start of the kernel
+            int o0 = threadIdx.x / kChunk;
+            asm volatile("" : "+v"(o0));
             if (iq < p1) {
-                for (int o = threadIdx.x / kChunk; o < A.nrows; o += kThreads / kChunk)
+                for (int o = o0; o < A.nrows; o += kThreads / kChunk)
                     A.out[((int64_t)f * n + iq) * A.nrows + o] =
                         out_row<D, T, S>(A, iq, o, &sacc[q][0], &sacc[q][nk]);
-                if (!GIN && A.g_out && threadIdx.x < kChunk)   // the given-G form writes no G~
+                if (GOUT && threadIdx.x < kChunk)
 #pragma unroll
                     for (int a = 0; a < D; ++a) A.g_out[((int64_t)f * D + a) * n + iq] = (float)sacc[q][nk + a];
             }
@@ -583,16 +593,19 @@ __global__ __launch_bounds__(ApplyCfg<T>::threads, ApplyCfg<T>::waves) void k_ap
 
 template <int D, int KERNEL, class T, class S>
 static int launch_apply(const ApplyArgs<S>& a, int64_t cap, hipStream_t s) {
+    const dim3 grid((unsigned)cap), block(ApplyCfg<T>::threads);
+    const char* name = sizeof(T) == 4 ? "k_apply (mixed)" : "k_apply (fp64)";
     if constexpr (!Scaled<T>::value) {
         if (a.g_in) {
-            VCT_LAUNCH("k_apply (fp64, given G)", (k_apply<D, KERNEL, T, S, true>), dim3((unsigned)cap),
-                       dim3(ApplyCfg<T>::threads), 0, s, a);
+            VCT_LAUNCH("k_apply (fp64, given G)", (k_apply<D, KERNEL, T, S, kGIn>), grid, block, 0, s, a);
             VCT_LAUNCH_CHECK();
             return VCT_OK;
         }
     }
-    const char* name = sizeof(T) == 4 ? "k_apply (mixed)" : "k_apply (fp64)";
-    VCT_LAUNCH(name, (k_apply<D, KERNEL, T, S, false>), dim3((unsigned)cap), dim3(ApplyCfg<T>::threads), 0, s, a);
+    if (a.g_out)
+        VCT_LAUNCH(name, (k_apply<D, KERNEL, T, S, kGOut>), grid, block, 0, s, a);
+    else
+        VCT_LAUNCH(name, (k_apply<D, KERNEL, T, S, kGNone>), grid, block, 0, s, a);
     VCT_LAUNCH_CHECK();
     return VCT_OK;
 }
