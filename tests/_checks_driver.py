@@ -61,6 +61,13 @@ def main(out, mode):
         J = g.map_alpha(ms)
         jb = J * torch.as_tensor(I.volume_perturbation(g.n), device=DEV)
         res["jbar"] = g.jbar_smooth(J, jb, 1e-2).cpu().numpy()
+        # the neighbour search with windows over several LDS segments (hit
+        # words, then their expansion) and with windows wider than the hit
+        # words hold (the fill pass)
+        for name, Rs in (("multiseg", 1.3), ("fill", 1.6)):
+            gw = vct.Geometry(w.pos, w.vol, w.lo, w.hi, Rs * w.R, w.kernel, device=DEV, keep_col=False)
+            res[f"row_ptr_{name}"] = gw.row_ptr.cpu().numpy()
+            res[f"col16_{name}"] = gw.col16[: gw.nnz].cpu().numpy()
     checked, bits = vct.vct_device_checks()
     res["checked"], res["bits"] = np.array(int(checked)), np.array(bits)
     np.savez(out, **res)
