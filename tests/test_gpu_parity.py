@@ -297,6 +297,11 @@ def test_fp64_apply_from_a_given_gradient(family, Rs):
     assert torch.isfinite(g32).all() and torch.isfinite(g64).all()
     dg = ((g32 - g64).abs().amax(dim=2) / g64.abs().amax(dim=2)).max().item()
     assert dg <= 1e-5
+    # the mixed form over the FP64 state writes its gradient as well
+    gs = torch.full_like(g32, float("nan"))
+    s64 = _apply_ex(g, phi, vct.VCT_MIXED_S64, g_out=gs)
+    assert torch.equal(s64, g.apply(phi, vct.VCT_MIXED_S64)) and torch.isfinite(gs).all()
+    assert ((gs - g64).abs().amax(dim=2) / g64.abs().amax(dim=2)).max().item() <= 1e-5
     hinted = _apply_ex(g, phi, vct.VCT_FP64, g_in=g32)
     rec, _ = O.sph2(w.pos, w.vol, w.phi, w.kernel, R, w.mapspec)
     ref = oracle_rows(rec, w.dim, ALL_OUT)
