@@ -584,6 +584,16 @@ __global__ __launch_bounds__(kExT) void k_nb_expand(Grid g, const int64_t* __res
     const int64_t p0 = cstart[b];
     const int np = (int)(cstart[b + 1] - p0);
     const int wv = threadIdx.x / kWave, pl = threadIdx.x % kWave;
+    const uint32_t* src = words + p0 * kBmWords;
+    const int k0 = wv * kPer;
+    const bool lane_on = pl < np;
+    // this wave's share of the words, requested with the window and the row
+    // pointers: all kBmWords words of the chunk's share of the buffer (np x
+    // kBmWords), those past the window (not written by the search) masked
+    // once the window is known
+    uint32_t v[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) v[u] = lane_on ? src[(k0 + u) * np + pl] : 0u;
     if (wv == 0) {
         if (win_tab) window_load<D>(win_tab, b, w);
         else chunk_window_wave<D>(g, cs, cinfo[b], w);
@@ -594,15 +604,11 @@ __global__ __launch_bounds__(kExT) void k_nb_expand(Grid g, const int64_t* __res
     // at most kBmWords words: the search flags wider windows, and the host
     // then runs the fill pass instead
     const int nw = dcheck((w.off[w.nr] + 31) / 32, kBmWords + 1, kChkCapacity);
-    const uint32_t* src = words + p0 * kBmWords;
-    const int k0 = wv * kPer;
-    const bool lane_on = pl < np;
     const int64_t e0 = rp[0], e1 = rp[np];
-    uint32_t v[kPer];
     int before[kPer];   // hits of the row in this wave's share before each word
     {
 #pragma unroll
-        for (int u = 0; u < kPer; ++u) v[u] = (lane_on && k0 + u < nw) ? src[(k0 + u) * np + pl] : 0u;
+        for (int u = 0; u < kPer; ++u) v[u] = k0 + u < nw ? v[u] : 0u;
         int c = 0;
 #pragma unroll
         for (int u = 0; u < kPer; ++u) {
